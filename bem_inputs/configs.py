@@ -1,0 +1,121 @@
+"""Synthetic transmission problems (meshes + media) for tests and benchmarks.
+
+Lengths are in units of the exterior wavelength at the reference frequency
+(lambda_0 = 1), so the exterior wavenumber is k0 = 2*pi*f_rel.  A medium with
+speed ratio s = c_j/c_0 has k_j = k0/s.  Density ratios are rho_j/rho_0 with
+rho_0 = 1.  Media values follow the paper's table of tissue properties where
+a workload does not fix them.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import meshes
+
+
+@dataclass
+class Domain:
+    vertices: np.ndarray          # float64 [n_v, 3]
+    triangles: np.ndarray         # int32 [n_t, 3]
+    k: complex                    # wavenumber inside the domain
+    rho: float                    # density (exterior density is rho0)
+    name: str = ""
+
+    @property
+    def n_vertices(self) -> int:
+        return int(self.vertices.shape[0])
+
+    @property
+    def n_triangles(self) -> int:
+        return int(self.triangles.shape[0])
+
+
+@dataclass
+class Problem:
+    domains: list[Domain]
+    k0: complex
+    rho0: float = 1.0
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_unknowns(self) -> int:
+        return 2 * sum(d.n_vertices for d in self.domains)
+
+    @property
+    def n_points(self) -> int:
+        return 6 * sum(d.n_triangles for d in self.domains)
+
+
+def sphere_problem(level: int, k0: float, k1: float, rho_ratio: float, radius: float = 1.0,
+                   name: str = "") -> Problem:
+    v, t = meshes.icosphere(level, radius)
+    return Problem([Domain(v, t, complex(k1), float(rho_ratio), "sphere")], complex(k0), 1.0,
+                   name or f"sphere_l{level}")
+
+
+def config1() -> Problem:
+    """Unit sphere, 642 vertices / 1,280 triangles, k0 = 2, k1 = 2.2, density ratio 1."""
+    return sphere_problem(3, 2.0, 2.2, 1.0, name="sphere642_k2")
+
+
+def config2() -> Problem:
+    """Sphere, 10,242 vertices / 20,480 triangles, k0 = 10, k1 = 10.5, density ratio 1.05."""
+    return sphere_problem(5, 10.0, 10.5, 1.05, name="sphere10242_k10")
+
+
+def two_spheres(level: int = 2, k0: float = 3.0) -> Problem:
+    """Two disjoint penetrable spheres of different media (small multi-domain case)."""
+    v1, t1 = meshes.icosphere(level, 0.8, (-1.0, 0.0, 0.0))
+    v2, t2 = meshes.ellipsoid(level, (0.6, 0.7, 0.5), (1.0, 0.3, 0.2))
+    return Problem([Domain(v1, t1, complex(k0 / 1.2), 1.3, "a"),
+                    Domain(v2, t2, complex(k0 / 0.9), 0.8, "b")], complex(k0), 1.0, "two_spheres")
+
+
+def ribcage(h_scale: float = 1.0, f_rel: float = 1.0) -> Problem:
+    """Layered rib-cage stand-in: fat slab, five capsules and a liver box.
+
+    All domains are disjoint and border only the exterior (no triple points).
+    Fat slab x in [-6, 9], y in [-6.5, 6.5], z in [-8, -6] (speed ratio 0.96,
+    density 0.95); five capsules of radius 0.9 and length 12 along y at
+    x in {-4.5, -1.5, 1.5, 4.5, 7.5}, z = -4 (speed ratio 1.87, density 1.9);
+    liver box x in [-6, 9], y in [-6.5, 6.5], z in [-2, 1] (speed ratio 1.03,
+    density 1.07).  Element size h_j = min(1, s_j)/6 * h_scale.
+    """
+    k0 = 2.0 * np.pi * f_rel
+    doms = []
+    s_fat, s_rib, s_liv = 0.96, 1.87, 1.03
+    h_fat = min(1.0, s_fat) / 6.0 * h_scale / f_rel
+    h_rib = min(1.0, s_rib) / 6.0 * h_scale / f_rel
+    h_liv = min(1.0, s_liv) / 6.0 * h_scale / f_rel
+    v, t = meshes.box((-6.0, -6.5, -8.0), (9.0, 6.5, -6.0), h_fat)
+    doms.append(Domain(v, t, complex(k0 / s_fat), 0.95, "fat"))
+    for x in (-4.5, -1.5, 1.5, 4.5, 7.5):
+        v, t = meshes.capsule(0.9, 12.0, h_rib, axis=1, center=(x, 0.0, -4.0))
+        doms.append(Domain(v, t, complex(k0 / s_rib), 1.9, f"rib{x:+.1f}"))
+    v, t = meshes.box((-6.0, -6.5, -2.0), (9.0, 6.5, 1.0), h_liv)
+    doms.append(Domain(v, t, complex(k0 / s_liv), 1.07, "liver"))
+    return Problem(doms, complex(k0), 1.0, f"ribcage_h{h_scale:g}")
+
+
+def kidney(f_rel: float = 1.0, elements_per_wavelength: float = 6.0, level: int | None = None) -> Problem:
+    """Kidney ellipsoid (5, 3, 2.5) plus a perinephric fat shell with a 2/3 gap.
+
+    Kidney: speed ratio 1.04, density 1.066.  Fat shell: inner semi-axes
+    + 2/3, outer + 2/3 + 1, speed ratio 0.941, density 0.917.
+    """
+    k0 = 2.0 * np.pi * f_rel
+    s_k, s_f = 1.04, 0.941
+    axes = np.array([5.0, 3.0, 2.5])
+    g = 2.0 / 3.0
+    if level is None:
+        h = min(1.0, s_f) / f_rel / elements_per_wavelength
+        # icosphere mean edge ~ 1.05 * R * 2**-level; pick the level for the largest axis
+        level = int(np.clip(np.ceil(np.log2(1.05 * (axes[0] + g + 1.0) / h)), 1, 8))
+    vk, tk = meshes.ellipsoid(level, axes)
+    vs, ts = meshes.shell(level, axes + g, axes + g + 1.0)
+    return Problem([Domain(vk, tk, complex(k0 / s_k), 1.066, "kidney"),
+                    Domain(vs, ts, complex(k0 / s_f), 0.917, "fat_shell")], complex(k0), 1.0,
+                   f"kidney_l{level}")

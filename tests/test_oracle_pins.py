@@ -1,0 +1,388 @@
+"""Pins of the FP64 oracle against facts the mathematics fixes.
+
+Each test checks the oracle against something other than itself: exact
+moments of polynomials, closed-form integrals, sphere eigenvalues, Gauss's
+law, the Calderon projector identities, the series solution of a penetrable
+sphere, and dense LU.  A dropped term, a wrong sign, a transposed operand or a
+wrong Jacobian in the oracle fails at least one of them.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+import pytest
+from scipy import special
+
+import oracle
+from oracle import series
+from bem_inputs import configs, meshes
+
+from laplace_ref import laplace_pair
+
+pytestmark = pytest.mark.cpu
+
+
+# ---------------------------------------------------------------------------
+# quadrature rules
+# ---------------------------------------------------------------------------
+
+def test_far_rule_degree_four_exact():
+    """The 6-point rule integrates x1^p x2^q exactly for p+q <= 4 and not for 5."""
+    x1, x2, w = oracle.far_rule()
+    assert abs(w.sum() - 1.0) < 1e-15
+    for deg in range(6):
+        worst = 0.0
+        for p in range(deg + 1):
+            q = deg - p
+            exact = 2.0 * math.factorial(p) * math.factorial(q) / math.factorial(p + q + 2)
+            worst = max(worst, abs(np.sum(w * x1 ** p * x2 ** q) - exact) / exact)
+        if deg <= 4:
+            assert worst < 1e-14, (deg, worst)
+        else:
+            assert worst > 1e-3, (deg, worst)
+    # all points strictly inside the reference triangle
+    assert np.all(x1 > 0) and np.all(x2 > 0) and np.all(x1 + x2 < 1)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 6, 12])
+def test_gauss_legendre_matches_numpy(n):
+    x, w = oracle.gauss_legendre01(n)
+    z, wz = np.polynomial.legendre.leggauss(n)
+    np.testing.assert_allclose(np.sort(x), (z + 1) / 2, atol=1e-15)
+    np.testing.assert_allclose(w[np.argsort(x)], wz / 2, rtol=1e-13)
+
+
+def _tri_moment(p, q):
+    """int over {0 <= s2 <= s1 <= 1} of s1^p s2^q."""
+    return 1.0 / ((q + 1) * (p + q + 2))
+
+
+@pytest.mark.parametrize("cls", [oracle.COINCIDENT, oracle.EDGE, oracle.VERTEX])
+def test_sauter_schwab_rule_tiles_the_product_domain(cls):
+    """Every class's rule integrates smooth polynomials over T x T exactly.
+
+    This fixes the maps and their Jacobians: a missing piece, a wrong power
+    of xi or eta, or a map outside T breaks the moments.
+    """
+    xh, yh, w = oracle.ss_rule(cls, 6)
+    assert abs(w.sum() - 0.25) < 1e-14
+    assert np.all(xh[:, 1] <= xh[:, 0] + 1e-15) and np.all(yh[:, 1] <= yh[:, 0] + 1e-15)
+    assert np.all(xh >= 0) and np.all(yh >= 0) and np.all(xh <= 1) and np.all(yh <= 1)
+    worst = 0.0
+    for a, b, c, d in itertools.product(range(4), repeat=4):
+        if a + b + c + d > 5:
+            continue
+        v = np.sum(w * xh[:, 0] ** a * xh[:, 1] ** b * yh[:, 0] ** c * yh[:, 1] ** d)
+        ex = _tri_moment(a, b) * _tri_moment(c, d)
+        worst = max(worst, abs(v - ex) / ex)
+    assert worst < 1e-13
+
+
+_P = np.array([[0.0, 0.0, 0.0], [1.0, 0.1, 0.0], [0.2, 0.9, 0.1]])
+_Q3 = np.array([0.5, -0.7, 0.4])
+_Q4 = np.array([-0.6, 0.2, 0.5])
+PAIRS = {
+    "coincident": (_P, [0, 1, 2], _P, [0, 1, 2]),
+    "edge": (_P, [0, 1, 2], np.array([_P[1], _P[0], _Q3]), [1, 0, 3]),
+    "vertex": (_P, [0, 1, 2], np.array([_P[0], _Q3, _Q4]), [0, 3, 4]),
+}
+
+
+@pytest.mark.parametrize("name", list(PAIRS))
+def test_singular_laplace_matches_semi_analytic(name):
+    """sum_ab V_ab at k = 0 equals int int 1/(4 pi r), computed independently
+    with the closed-form inner potential of a triangle (Wilton et al.)."""
+    Pt, lt, Ps, ls = PAIRS[name]
+    ref = laplace_pair(Pt, Ps, 60) / (4.0 * np.pi)
+    cls, E = oracle.element_pair(Pt, lt, Ps, ls, 0.0, ss_n=14)
+    assert cls == {"coincident": 3, "edge": 2, "vertex": 1}[name]
+    assert abs(E[0].sum().real - ref) / ref < 1e-10
+    # the production order n = 6 is within the rule's accuracy
+    _, E6 = oracle.element_pair(Pt, lt, Ps, ls, 0.0, ss_n=6)
+    assert abs(E6[0].sum().real - ref) / ref < 5e-6
+
+
+@pytest.mark.parametrize("name", list(PAIRS))
+def test_singular_rule_converges_for_all_operators(name):
+    """Element matrices of V, K, K', W at a complex wavenumber converge in n."""
+    Pt, lt, Ps, ls = PAIRS[name]
+    k = 3.0 + 0.5j
+    Es = [oracle.element_pair(Pt, lt, Ps, ls, k, ss_n=n)[1] for n in (6, 10, 14)]
+    # K and K' vanish on a coincident flat pair: measure against the V scale
+    for op in range(4):
+        scale = max(np.abs(Es[2][op]).max(), np.abs(Es[2][0]).max())
+        d1 = np.abs(Es[0][op] - Es[2][op]).max() / scale
+        d2 = np.abs(Es[1][op] - Es[2][op]).max() / scale
+        # geometric convergence: n = 10 is far closer to n = 14 than n = 6 is
+        assert d2 < 1e-6, (op, d1, d2)
+        assert d1 < 2e-4, (op, d1, d2)
+        assert d2 < max(d1 / 20.0, 1e-12), (op, d1, d2)
+
+
+def test_far_rule_element_matches_refined_rule_for_separated_pair():
+    """For well separated triangles the 6-point element equals a fine reference."""
+    Pt = _P
+    Ps = _P + np.array([0.3, 0.2, 4.0])
+    _, E = oracle.element_pair(Pt, [0, 1, 2], Ps, [3, 4, 5], 2.0 + 0.0j)
+    # reference: Sauter-Schwab-free brute force with a 4-level subdivision of both triangles
+    x1, x2, w = oracle.far_rule()
+
+    def subdivide(T, levels):
+        tris = [T]
+        for _ in range(levels):
+            nt = []
+            for a, b, c in tris:
+                ab, bc, ca = (a + b) / 2, (b + c) / 2, (c + a) / 2
+                nt += [np.array([a, ab, ca]), np.array([ab, b, bc]), np.array([ca, bc, c]), np.array([ab, bc, ca])]
+            tris = nt
+        return tris
+
+    def points(T, levels):
+        X, L, W = [], [], []
+        M = np.array([[1, 1, 1], T[:, 0], T[:, 1], T[:, 2]])  # barycentric solve
+        for S in subdivide(T, levels):
+            ar = 0.5 * np.linalg.norm(np.cross(S[1] - S[0], S[2] - S[0]))
+            for q in range(6):
+                l = np.array([1 - x1[q] - x2[q], x1[q], x2[q]])
+                x = l @ S
+                lam = np.linalg.lstsq(M, np.r_[1.0, x], rcond=None)[0]
+                X.append(x); L.append(lam); W.append(ar * w[q])
+        return np.array(X), np.array(L), np.array(W)
+
+    X, LX, WX = points(Pt, 3)
+    Y, LY, WY = points(Ps, 3)
+    d = X[:, None, :] - Y[None, :, :]
+    r = np.linalg.norm(d, axis=-1)
+    G = np.exp(2j * r) / (4 * np.pi * r)
+    ref = np.einsum("p,pa,pq,q,qb->ab", WX, LX, G, WY, LY)
+    # degree-4 rule error at a separation of ~4 triangle sizes is ~2e-5
+    assert np.abs(E[0] - ref).max() / np.abs(ref).max() < 1e-4
+
+
+# ---------------------------------------------------------------------------
+# P1 mass / stiffness and geometry
+# ---------------------------------------------------------------------------
+
+def test_mass_and_stiffness_closed_forms():
+    v, t = meshes.icosphere(2)
+    M = oracle.mass_matrix(v, t)
+    S = oracle.stiffness_matrix(v, t)
+    area = 0.5 * np.linalg.norm(np.cross(v[t[:, 1]] - v[t[:, 0]], v[t[:, 2]] - v[t[:, 0]]), axis=1).sum()
+    assert abs(M.sum() - area) < 1e-13 * area
+    assert np.abs(S @ np.ones(v.shape[0])).max() < 1e-12
+    # linear function x on a flat patch: S x = 0 at interior vertices of a planar grid
+    vb, tb = meshes.box((0, 0, 0), (1, 1, 1), 0.25)
+    Sb = oracle.stiffness_matrix(vb, tb)
+    f = vb[:, 0]
+    interior = (vb[:, 2] == 0.0) & (vb[:, 0] > 0) & (vb[:, 0] < 1) & (vb[:, 1] > 0) & (vb[:, 1] < 1)
+    assert np.abs((Sb @ f)[interior]).max() < 1e-12
+
+
+def test_winding_number_inside_outside():
+    v, t = meshes.capsule(0.9, 4.0, 0.5)
+    pts = np.array([[0, 0, 0], [0, 1.5, 0.2], [2.0, 0, 0], [0, 2.5, 0], [0.5, 0.5, 0.5]])
+    wn = oracle.winding((v, t), pts)
+    np.testing.assert_allclose(wn, [1, 1, 0, 0, 1], atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# operators: identities and closed forms
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", ["tetrahedron", "bipyramid"])
+def test_gauss_law_on_polyhedra_with_only_touching_pairs(shape):
+    """k = 0: K_h 1 = -1/2 M 1 and 1^T K'_h = -1/2 1^T M on a closed polyhedron.
+
+    On these polyhedra every pair of faces touches, so only the singular rules
+    are exercised; the polyhedron is the exact surface.
+    """
+    v, t = getattr(meshes, shape)()
+    V, K, Kp, W = oracle.operators((v, t), 0.0, ss_n=10)
+    M = oracle.mass_matrix(v, t)
+    one = np.ones(v.shape[0])
+    np.testing.assert_allclose((K @ one).real, -0.5 * M @ one, atol=1e-9)
+    np.testing.assert_allclose((one @ Kp).real, -0.5 * one @ M, atol=1e-9)
+    assert np.abs((K @ one).imag).max() < 1e-15
+
+
+def test_operator_symmetries():
+    """V = V^T, W = W^T and K' = K^T (complex symmetric, not Hermitian)."""
+    v, t = meshes.icosphere(1)
+    # the edge rule is not swap-symmetric itself; at order 14 its error is negligible
+    V, K, Kp, W = oracle.operators((v, t), 2.5 + 0.3j, ss_n=14)
+    for A, B in ((V, V.T), (W, W.T), (Kp, K.T)):
+        assert np.abs(A - B).max() / np.abs(A).max() < 1e-12
+    assert np.abs(V - V.conj().T).max() / np.abs(V).max() > 1e-3
+
+
+def test_series_eigenvalues_satisfy_calderon_identity():
+    for k in (0.5, 2.0, 7.3):
+        for l in range(6):
+            lv, lk, lkp, lw = series.sphere_eigenvalues(l, k, 1.3)
+            assert abs(lk * lk + lv * lw - 0.25) < 1e-10
+    for l in range(4):
+        got = series.sphere_eigenvalues(l, 1e-5, 1.3)
+        ref = series.laplace_sphere_eigenvalues(l, 1.3)
+        np.testing.assert_allclose(np.real(got), ref, rtol=1e-4, atol=1e-8)
+
+
+@pytest.fixture(scope="module")
+def sphere_ops():
+    out = {}
+    for level in (2, 3):
+        v, t = meshes.icosphere(level)
+        out[level] = (v, t, oracle.operators((v, t), 2.0), oracle.mass_matrix(v, t))
+    return out
+
+
+def test_sphere_eigenvalues_converge(sphere_ops):
+    """Rayleigh quotients y^T A_h y / y^T M y of zonal harmonics vs closed forms.
+
+    Level 3 (642 vertices) within 1 % of the largest eigenvalue scale and an
+    O(h^2) error decrease (ratio near 4) from level 2 to 3.
+    """
+    errs = {}
+    for level, (v, t, ops, M) in sphere_ops.items():
+        for l in range(5):
+            y = special.eval_legendre(l, v[:, 2])
+            den = y @ M @ y
+            ex = series.sphere_eigenvalues(l, 2.0)
+            for o, A in enumerate(ops):
+                errs[(level, l, o)] = abs(y @ A @ y / den - ex[o])
+    for l in range(5):
+        ex = series.sphere_eigenvalues(l, 2.0)
+        for o in range(4):
+            assert errs[(3, l, o)] < 0.01 * max(1.0, abs(ex[o])), (l, o, errs[(3, l, o)])
+            ratio = errs[(2, l, o)] / errs[(3, l, o)]
+            assert ratio > 2.5, (l, o, ratio)
+
+
+def _traces_interpolant(v, t, p_fn, dpdn_fn):
+    """Nodal values of (p, dp/dn) with vertex normals of the sphere/ellipsoid."""
+    nrm = np.zeros_like(v)
+    P = [v[t[:, a]] for a in range(3)]
+    fn = np.cross(P[1] - P[0], P[2] - P[0])
+    for a in range(3):
+        np.add.at(nrm, t[:, a], fn)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    return p_fn(v), dpdn_fn(v, nrm)
+
+
+@pytest.mark.parametrize("which", ["interior", "radiating"])
+def test_calderon_projector_identity(which):
+    """A_h g = +1/2 M2 g for traces of an interior solution (plane wave) and
+    -1/2 M2 g for a radiating solution (monopole inside); A = [[-K, V], [W, K']].
+    The residual decreases at O(h^2) under refinement."""
+    res = []
+    for level in (2, 3):
+        v, t = meshes.ellipsoid(level, (1.0, 0.8, 0.7))
+        k = 2.0
+        if which == "interior":
+            p, dp = oracle.plane_wave(k, (0.3, 0.4, 0.86))
+            sign = 0.5
+        else:
+            p, dp = oracle.point_sources(k, [[0.1, -0.1, 0.05]], [1.0])
+            sign = -0.5
+        gD, gN = _traces_interpolant(v, t, p, dp)
+        V, K, Kp, W = oracle.operators((v, t), k)
+        M = oracle.mass_matrix(v, t)
+        lhsD = -K @ gD + V @ gN
+        lhsN = W @ gD + Kp @ gN
+        rD, rN = sign * M @ gD, sign * M @ gN
+        res.append(max(np.linalg.norm(lhsD - rD) / np.linalg.norm(rD),
+                       np.linalg.norm(lhsN - rN) / np.linalg.norm(rN)))
+    assert res[1] < 0.05, res
+    assert res[0] / res[1] > 2.5, res
+
+
+@pytest.fixture(scope="module")
+def config1_solution():
+    prob = configs.config1()
+    A = oracle.pmchwt_matrix(prob)
+    p, dp = oracle.plane_wave(prob.k0)
+    b = oracle.rhs(prob, p, dp)
+    u = oracle.solve_lu(A, b)
+    return prob, A, b, u
+
+
+def test_config1_matches_penetrable_sphere_series(config1_solution):
+    """PMCHWT solution on the 642-vertex sphere vs the series traces: < 2 %."""
+    prob, A, b, u = config1_solution
+    d = prob.domains[0]
+    nv = d.n_vertices
+    gD, gN = series.sphere_traces(d.vertices, 1.0, 2.0, 2.2, 1.0, 1.0)
+    M = oracle.mass_matrix(d.vertices, d.triangles)
+
+    def mnorm(x):
+        return np.sqrt(np.real(np.conj(x) @ M @ x))
+
+    eD = mnorm(u[:nv] - gD) / mnorm(gD)
+    eN = mnorm(u[nv:] - gN) / mnorm(gN)
+    assert eD < 0.02 and eN < 0.02, (eD, eN)
+
+
+def test_config1_field_matches_series(config1_solution):
+    """Total pressure on a coarse grid in the plane y = 0 (|x| != 1 band excluded)."""
+    prob, A, b, u = config1_solution
+    g = np.linspace(-3.0, 3.0, 13)
+    X, Z = np.meshgrid(g, g, indexing="ij")
+    pts = np.stack([X.ravel(), np.zeros(X.size), Z.ravel()], axis=1)
+    r = np.linalg.norm(pts, axis=1)
+    pts = pts[np.abs(r - 1.0) > 0.2]
+    p_inc, _ = oracle.plane_wave(prob.k0)
+    p, region = oracle.field(prob, u, pts, p_inc)
+    ref = series.sphere_field(pts, 1.0, 2.0, 2.2, 1.0, 1.0)
+    assert np.array_equal(region, (np.linalg.norm(pts, axis=1) < 1.0).astype(np.int32))
+    err = np.linalg.norm(p - ref) / np.linalg.norm(ref)
+    assert err < 0.02, err
+
+
+def test_gmres_matches_lu(config1_solution):
+    prob, A, b, u = config1_solution
+    x, it, hist = oracle.gmres(lambda z: A @ z, b, restart=100, tol=1e-12, maxiter=2000)
+    assert hist[-1] <= 1e-12
+    assert np.linalg.norm(x - u) / np.linalg.norm(u) < 1e-10
+    # the recursive residual estimate agrees with the true residual
+    assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) < 1e-11
+
+
+def test_pmchwt_rows_match_dense_two_domains():
+    prob = configs.two_spheres(level=1)
+    A = oracle.pmchwt_matrix(prob)
+    rows = np.array([0, 5, 41, 42, 43, prob.n_unknowns - 1])
+    R = oracle.pmchwt_rows(prob, rows)
+    np.testing.assert_allclose(R, A[rows], rtol=0, atol=1e-14 * np.abs(A).max())
+
+
+def test_two_domain_union_operator_projector():
+    """The exterior-k0 union operator of two disjoint surfaces applied to the
+    traces of a monopole placed inside domain 1 gives -1/2 M2 g on both
+    surfaces (radiating from outside the other one, still radiating overall)."""
+    res = []
+    for level in (1, 2):
+        prob = configs.two_spheres(level=level)
+        k0 = prob.k0
+        p, dp = oracle.point_sources(k0, [[-1.0, 0.05, 0.0]], [1.0])
+        gs = []
+        for d in prob.domains:
+            gs += list(_traces_interpolant(d.vertices, d.triangles, p, dp))
+        g = np.concatenate(gs)
+        off = oracle.offsets(prob)
+        A = np.zeros((off[-1], off[-1]), dtype=np.complex128)
+        M2 = np.zeros_like(A)
+        for j, dj in enumerate(prob.domains):
+            for i, di in enumerate(prob.domains):
+                V, K, Kp, W = oracle.operator_rows((dj.vertices, dj.triangles), (di.vertices, di.triangles), i == j, k0)
+                nj, ni = dj.n_vertices, di.n_vertices
+                A[off[j]:off[j] + nj, off[i]:off[i] + ni] = -K
+                A[off[j]:off[j] + nj, off[i] + ni:off[i + 1]] = V
+                A[off[j] + nj:off[j + 1], off[i]:off[i] + ni] = W
+                A[off[j] + nj:off[j + 1], off[i] + ni:off[i + 1]] = Kp
+            M = oracle.mass_matrix(dj.vertices, dj.triangles)
+            M2[off[j]:off[j] + dj.n_vertices, off[j]:off[j] + dj.n_vertices] = M
+            M2[off[j] + dj.n_vertices:off[j + 1], off[j] + dj.n_vertices:off[j + 1]] = M
+        r = A @ g + 0.5 * M2 @ g
+        res.append(np.linalg.norm(r) / np.linalg.norm(0.5 * M2 @ g))
+    assert res[1] < 0.1 and res[0] / res[1] > 2.5, res
