@@ -1,0 +1,175 @@
+/*
+ * bem.h - C ABI of the MI355X boundary-element library for the multiple-domain
+ * Helmholtz transmission problem (PMCHWT formulation, Galerkin P1 triangles).
+ *
+ * Problem statement (paper, section "Model formulation", eq. model): an
+ * unbounded exterior Omega^0 (wavenumber k0, density rho0) containing n
+ * disjoint bounded domains Omega^j (k_j, rho_j), each touching only the
+ * exterior (no triple points).  The unknowns are the exterior Cauchy traces
+ * u_j = (gamma_D^{j,+} p_tot, gamma_N^{j,+} p_tot) on every boundary
+ * (eq. Form2_matrix_format_p2); the system is
+ *   (A^j_{k0} + D_j^-1 A^j_{kj} D_j) u_j + sum_{i != j} A^{ji}_{k0} u_i = gamma^{j,+} p_inc
+ * (eq. Form2_calderon_sys_simp3) with the Calderon operator A = [[-K, V], [W, K']]
+ * and D_j = diag(1, rho_j/rho_0) (eq. Form1_BCs).  It is discretised with
+ * continuous piecewise-linear test and trial functions (eq. Galerkin_disc_lhs,
+ * eq. Galerkin_disc_rhs1).  Quadrature: 6-point degree-4 rule per triangle for
+ * pairs of triangles sharing no vertex, Sauter-Schwab rules (Gauss-Legendre
+ * order ss_order per dimension) for coincident, edge- and vertex-adjacent
+ * pairs of the same boundary.
+ *
+ * Unknown ordering: domain by domain, [u_D^1 (n_v^1), u_N^1 (n_v^1),
+ * u_D^2, u_N^2, ...]; u_D entries follow the domain's vertex order.  Several
+ * right-hand sides are stored RHS-major: vector r starts at r * n_unknowns.
+ *
+ * Complex numbers are two doubles (re, im).  Every function returns a status;
+ * on a non-OK status, bem_last_error() gives a message (per thread).
+ * Handles are not thread-safe: serialise calls on one handle.
+ */
+#ifndef BEM_MI355X_H
+#define BEM_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BEM_OK = 0,
+    BEM_WARN_NOT_CONVERGED = 1,   /* GMRES stopped at max_iter; best iterate returned */
+    BEM_ERR_INVALID_ARG = -1,     /* null pointer, bad size, non-finite input, bad option */
+    BEM_ERR_MESH = -2,            /* open/non-manifold/inverted mesh, zero area, index out of range */
+    BEM_ERR_OOM = -3,             /* device allocation failed or footprint over budget */
+    BEM_ERR_DEVICE = -4,          /* a HIP call failed */
+    BEM_ERR_UNSUPPORTED = -5      /* option not implemented */
+} bem_status;
+
+typedef struct { double re, im; } bem_complex;
+
+typedef struct bem_problem bem_problem;   /* opaque; owned by the library until bem_destroy */
+
+/* One penetrable domain Omega^j (paper eq. model).  Host arrays, copied by
+ * bem_assemble.  Triangles are 0-based vertex triples ordered
+ * counter-clockwise seen from the side the normal points to; the normal must
+ * point out of the domain (paper: n^j points out of Omega^j).  A domain may
+ * have several closed boundary components (e.g. a shell). */
+typedef struct {
+    const double *vertices;   int64_t n_vertices;    /* [n_vertices][3] */
+    const int32_t *triangles; int64_t n_triangles;   /* [n_triangles][3] */
+    bem_complex k;                                   /* k_j, Im k_j >= 0 */
+    double rho;                                      /* rho_j > 0 */
+} bem_domain;
+
+/* operator storage modes */
+#define BEM_OTF 0                  /* on-the-fly FP32 far field + FP64 sparse singular pass */
+#define BEM_ASSEMBLED_FP32 1       /* dense complex64 matrix (FP32), applied by GEMV/GEMM */
+#define BEM_ASSEMBLED_SPLIT_BF16 2 /* dense matrix plus BF16 hi/lo planes (3-term MFMA GEMM) */
+
+/* flags */
+#define BEM_DEVICE_PTRS 1u         /* vectors passed to apply/solve/rhs/evaluate are device pointers */
+
+typedef struct {
+    int mode;          /* BEM_OTF (default) or an assembled mode */
+    int far_points;    /* must be 6 (the only far rule) */
+    int ss_order;      /* Gauss-Legendre points per dimension of the singular rules (1..16), default 6 */
+    int device;        /* HIP device ordinal */
+    void *stream;      /* hipStream_t used for all work of this problem; NULL = default stream */
+    uint32_t flags;    /* BEM_DEVICE_PTRS */
+} bem_assemble_opts;
+
+/* Incident field kinds (paper eq. model: p_inc; numerical experiments). */
+#define BEM_PLANE_WAVE 0     /* params [n_fields][5]: direction (3), amplitude re, im */
+#define BEM_POINT_SOURCES 1  /* params [n_params][6]: position (3), amplitude re, im, field index */
+#define BEM_PISTON_ARRAY 2   /* params [n_params][10]: centre (3), unit normal (3), radius, amp re, im, field index */
+
+typedef struct {
+    int kind;
+    int32_t n_fields;       /* number of incident fields = number of right-hand sides */
+    const double *params;   /* host array, layout per kind */
+    int64_t n_params;       /* rows of params (plane waves: n_fields) */
+} bem_incident;
+
+#define BEM_PRECOND_NONE 0
+#define BEM_PRECOND_OSRC 1
+#define BEM_PREC_FP32 0
+#define BEM_PREC_SPLIT_BF16_FGMRES 1
+
+typedef struct {
+    double tol;          /* relative residual target (paper: 1e-5) */
+    int restart;         /* GMRES restart length (paper: 100) */
+    int max_iter;        /* total iteration cap */
+    int precond;         /* BEM_PRECOND_NONE or BEM_PRECOND_OSRC */
+    int n_pade;          /* OSRC Pade terms */
+    double r_eps;        /* OSRC damping length */
+    double theta;        /* OSRC Pade branch-cut rotation */
+    int precision;       /* BEM_PREC_FP32 or BEM_PREC_SPLIT_BF16_FGMRES */
+    double inner_tol;    /* inner tolerance of the flexible-GMRES refinement */
+} bem_solve_opts;
+
+typedef struct {
+    int32_t iterations;
+    int32_t converged;
+    double rel_residual;   /* ||b - A u|| / ||b|| of the returned u (weak form) */
+} bem_solve_info;
+
+/* Set up a problem: validate meshes, build geometry, quadrature points and the
+ * FP64 singular correction on the device.  n_domains >= 1.  k0 with
+ * Im k0 >= 0, rho0 > 0.  opts may be NULL (defaults).  On success *out owns
+ * device memory until bem_destroy.  Errors: BEM_ERR_INVALID_ARG,
+ * BEM_ERR_MESH, BEM_ERR_OOM, BEM_ERR_DEVICE. */
+bem_status bem_assemble(const bem_domain *domains, int32_t n_domains, bem_complex k0, double rho0,
+                        const bem_assemble_opts *opts, bem_problem **out);
+
+/* y = A x for n_rhs vectors: the Galerkin PMCHWT matrix (weak form, no mass
+ * matrix) applied to x.  x, y: [n_rhs][n_unknowns]; host or device memory per
+ * BEM_DEVICE_PTRS; x and y must not overlap.  Runs on the problem's stream;
+ * with device pointers the call returns after enqueueing the work. */
+bem_status bem_apply(bem_problem *p, const bem_complex *x, bem_complex *y, int32_t n_rhs);
+
+/* bem_apply restricted to parts of the operator (parts: 1 = far field
+ * (regular rule on every pair), 2 = singular correction; 3 = both). */
+bem_status bem_apply_parts(bem_problem *p, const bem_complex *x, bem_complex *y, int32_t n_rhs, int parts);
+
+/* Right-hand side b_j = <gamma^{j,+} p_inc, phi> (eq. Galerkin_disc_rhs1) for
+ * each incident field: b [n_fields][n_unknowns]. */
+bem_status bem_rhs(bem_problem *p, const bem_incident *inc, bem_complex *b);
+
+/* Solve A u = b for every incident field with GMRES (FP64 Arnoldi, zero
+ * initial guess).  u: [n_fields][n_unknowns]; info: [n_fields] (host).
+ * Returns BEM_WARN_NOT_CONVERGED when some field hit max_iter. */
+bem_status bem_solve(bem_problem *p, const bem_incident *inc, const bem_solve_opts *opts,
+                     bem_complex *u, bem_solve_info *info);
+
+/* Solve A u = b for given right-hand sides b [n_rhs][n_unknowns]. */
+bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, const bem_solve_opts *opts,
+                         bem_complex *u, bem_solve_info *info);
+
+/* Total pressure at points from traces u (paper eq. rep_formula_gen):
+ * exterior p = p_inc + sum_j [DL_k0 u_D^j - SL_k0 u_N^j]; inside domain j
+ * p = SL_kj((rho_j/rho_0) u_N^j) - DL_kj u_D^j.  points [n_points][3] (host
+ * or device per flag); field [n_fields][n_points]; region [n_points]
+ * (0 exterior, j >= 1 domain j).  inc may be NULL (no incident term). */
+bem_status bem_evaluate_field(bem_problem *p, const bem_complex *u, const bem_incident *inc,
+                              const double *points, int64_t n_points,
+                              bem_complex *field, int32_t *region);
+
+int64_t bem_num_unknowns(const bem_problem *p);
+
+/* Device bytes a problem would hold (admission control). */
+bem_status bem_footprint_bytes(const bem_domain *domains, int32_t n_domains, const bem_assemble_opts *opts,
+                               int32_t n_rhs, int32_t restart, uint64_t *bytes);
+
+/* Kernel timing of the last bem_apply on this problem, in milliseconds,
+ * measured with HIP events on the problem's stream: [0] whole apply,
+ * [1] far-field pair kernel, [2] singular sparse pass + scatter, [3] gather. */
+bem_status bem_last_timings(const bem_problem *p, double *ms4);
+
+void bem_destroy(bem_problem *p);
+
+/* Message of the last non-OK status returned on this thread. */
+const char *bem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BEM_MI355X_H */

@@ -1,0 +1,611 @@
+// Host runtime of the C ABI declared in include/bem.h: problem set-up on the
+// device, the operator apply, GMRES and the right-hand side / field entry points.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <vector>
+
+#include "bem_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+bem_status fail(bem_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+template <typename F>
+bem_status guarded(F &&f)
+{
+    try {
+        return f();
+    } catch (const bem::Error &e) {
+        return fail(e.status, e.msg);
+    } catch (const std::bad_alloc &) {
+        return fail(BEM_ERR_OOM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(BEM_ERR_DEVICE, e.what());
+    }
+}
+
+template <typename T>
+void dev_alloc(T **p, size_t n)
+{
+    BEM_HIP(hipMalloc(reinterpret_cast<void **>(p), std::max<size_t>(1, n) * sizeof(T)));
+}
+
+template <typename T>
+T *dev_copy(const std::vector<T> &h, hipStream_t s)
+{
+    T *d = nullptr;
+    dev_alloc(&d, h.size());
+    if (!h.empty()) BEM_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return d;
+}
+
+void free_problem(bem_problem *p)
+{
+    if (!p) return;
+    void *ptrs[] = {p->d_verts, p->d_tris, p->d_rowD, p->d_rowN, p->d_area, p->d_normal, p->d_curl, p->d_pts,
+                    p->d_tnrm, p->d_v2t_ptr, p->d_v2t, p->d_pass, p->d_work, p->d_trial, p->d_part, p->d_pot,
+                    p->d_cptr, p->d_ccol, p->d_cval, p->d_x, p->d_y};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    for (auto &e : p->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete p;
+}
+
+bool finite_c(const bem_complex &z) { return std::isfinite(z.re) && std::isfinite(z.im); }
+
+// Far-field pass table and work list.
+void build_passes(bem_problem &p)
+{
+    using bem::PassDesc;
+    p.passes.clear();
+    PassDesc ext{};
+    ext.test_begin = 0;
+    ext.test_end = p.M;
+    ext.trial_begin = 0;
+    ext.trial_end = p.M;
+    ext.kre = p.k0re;
+    ext.kim = p.k0im;
+    ext.sV = 1.0;
+    ext.sW = 1.0;
+    ext.slot = 0;
+    p.passes.push_back(ext);
+    for (const auto &d : p.doms) {
+        PassDesc q{};
+        q.test_begin = 6 * d.t_off;
+        q.test_end = 6 * (d.t_off + d.nt);
+        q.trial_begin = q.test_begin;
+        q.trial_end = q.test_end;
+        q.kre = d.kre;
+        q.kim = d.kim;
+        q.sV = d.rho / p.rho0;
+        q.sW = p.rho0 / d.rho;
+        q.slot = 1;
+        p.passes.push_back(q);
+    }
+    p.n_pass = int(p.passes.size());
+    std::vector<bem::PassDev> dv;
+    for (const auto &q : p.passes) {
+        bem::PassDev d{};
+        d.test_begin = q.test_begin;
+        d.test_end = q.test_end;
+        d.trial_begin = q.trial_begin;
+        d.trial_end = q.trial_end;
+        d.k = float(q.kre);
+        d.k_over_2pi = float(q.kre / (2.0 * M_PI));
+        d.kim = float(q.kim);
+        d.sV = float(q.sV);
+        d.sW = float(q.sW);
+        d.k2re = float(q.kre * q.kre - q.kim * q.kim);
+        d.k2im = float(2.0 * q.kre * q.kim);
+        d.slot = q.slot;
+        dv.push_back(d);
+    }
+    p.d_pass = dev_copy(dv, p.stream);
+    // work items: consecutive workgroups take consecutive splits, so that the
+    // round-robin placement of workgroups on the 8 XCDs keeps one trial chunk
+    // per XCD (its L2 holds that chunk).
+    const int tb = 256 * p.tpl;
+    std::vector<int4> work;
+    for (int ip = 0; ip < p.n_pass; ++ip) {
+        const int64_t nblk = (p.passes[ip].test_end - p.passes[ip].test_begin + tb - 1) / tb;
+        for (int64_t b = 0; b < nblk; ++b)
+            for (int s = 0; s < p.n_split; ++s) work.push_back(make_int4(ip, int(b), s, 0));
+    }
+    p.n_work = int(work.size());
+    p.d_work = dev_copy(work, p.stream);
+}
+
+void ensure_scratch(bem_problem &p, int64_t n_rhs)
+{
+    if (p.scratch_rhs >= n_rhs) return;
+    if (p.d_x) (void)hipFree(p.d_x);
+    if (p.d_y) (void)hipFree(p.d_y);
+    p.d_x = p.d_y = nullptr;
+    p.scratch_rhs = 0;
+    dev_alloc(&p.d_x, size_t(n_rhs * p.N));
+    dev_alloc(&p.d_y, size_t(n_rhs * p.N));
+    p.scratch_rhs = n_rhs;
+}
+
+// y = A x for one right-hand side, all on the device.
+void apply_one(bem_problem &p, const double2 *x, double2 *y, int parts, bool record)
+{
+    if (record) BEM_HIP(hipEventRecord(p.ev[0], p.stream));
+    if (parts & 1) {
+        bem::launch_gather(p, x);
+        if (record) BEM_HIP(hipEventRecord(p.ev[1], p.stream));
+        bem::launch_pairs(p);
+        if (record) BEM_HIP(hipEventRecord(p.ev[2], p.stream));
+        bem::launch_reduce(p);
+    } else if (record) {
+        BEM_HIP(hipEventRecord(p.ev[1], p.stream));
+        BEM_HIP(hipEventRecord(p.ev[2], p.stream));
+    }
+    if (record) BEM_HIP(hipEventRecord(p.ev[3], p.stream));
+    bem::launch_scatter(p, x, y, parts);
+    if (record) {
+        BEM_HIP(hipEventRecord(p.ev[4], p.stream));
+        p.timed = true;
+    }
+}
+
+void apply_device(bem_problem &p, const double2 *x, double2 *y, int n_rhs, int parts)
+{
+    for (int r = 0; r < n_rhs; ++r) apply_one(p, x + int64_t(r) * p.N, y + int64_t(r) * p.N, parts, r == n_rhs - 1);
+}
+
+bem_solve_opts default_solve_opts()
+{
+    bem_solve_opts o{};
+    o.tol = 1e-5;
+    o.restart = 100;
+    o.max_iter = 1000;
+    o.precond = BEM_PRECOND_NONE;
+    o.n_pade = 4;
+    o.r_eps = 0.1;
+    o.theta = M_PI / 3.0;
+    o.precision = BEM_PREC_FP32;
+    o.inner_tol = 1e-3;
+    return o;
+}
+
+// GMRES(m) with zero initial guess for one right-hand side (device vectors).
+// Arnoldi with classical Gram-Schmidt applied twice (FP64), Givens rotations
+// and the small triangular solve on the host.  Stops on the recursive
+// estimate of ||b - A x|| / ||b|| <= tol, then reports the true residual.
+void gmres_one(bem_problem &p, const double2 *b, double2 *x, const bem_solve_opts &o, bem_solve_info &info)
+{
+    const int64_t N = p.N;
+    const int m = std::max(1, o.restart);
+    hipStream_t s = p.stream;
+    double2 *V = nullptr, *w = nullptr, *h_dev = nullptr, *part = nullptr;
+    const int nblk = int(std::min<int64_t>(256, (N + 255) / 256));
+    dev_alloc(&V, size_t(m + 1) * N);
+    dev_alloc(&w, size_t(N));
+    dev_alloc(&h_dev, size_t(m + 2));
+    dev_alloc(&part, size_t(m + 2) * nblk);
+    struct Guard {
+        double2 *a, *b, *c, *d;
+        ~Guard() { (void)hipFree(a); (void)hipFree(b); (void)hipFree(c); (void)hipFree(d); }
+    } guard{V, w, h_dev, part};
+
+    using cd = std::complex<double>;
+    auto dot_host = [&](const double2 *Vb, int nvec, const double2 *vec, std::vector<cd> &out) {
+        bem::zdot_multi(s, Vb, N, nvec, vec, N, part, nblk, h_dev);
+        std::vector<double2> tmp(nvec);
+        BEM_HIP(hipMemcpyAsync(tmp.data(), h_dev, nvec * sizeof(double2), hipMemcpyDeviceToHost, s));
+        BEM_HIP(hipStreamSynchronize(s));
+        out.resize(nvec);
+        for (int i = 0; i < nvec; ++i) out[i] = cd(tmp[i].x, tmp[i].y);
+    };
+    auto norm = [&](const double2 *vec) {
+        std::vector<cd> t;
+        dot_host(vec, 1, vec, t);
+        return std::sqrt(std::max(0.0, t[0].real()));
+    };
+
+    BEM_HIP(hipMemsetAsync(x, 0, N * sizeof(double2), s));
+    const double bnorm = norm(b);
+    info.iterations = 0;
+    info.converged = 0;
+    info.rel_residual = 0.0;
+    if (bnorm == 0.0) {
+        info.converged = 1;
+        return;
+    }
+    int it = 0;
+    double est = 1.0;
+    while (it < o.max_iter) {
+        // r = b - A x  (into V_0)
+        if (it == 0) {
+            BEM_HIP(hipMemcpyAsync(V, b, N * sizeof(double2), hipMemcpyDeviceToDevice, s));
+        } else {
+            apply_device(p, x, w, 1, 3);
+            bem::zscale_copy(s, b, V, N, make_double2(1.0, 0.0));
+            bem::zaxpy(s, V, w, N, make_double2(-1.0, 0.0));
+        }
+        const double beta = norm(V);
+        est = beta / bnorm;
+        if (est <= o.tol) break;
+        bem::zscale_copy(s, V, V, N, make_double2(1.0 / beta, 0.0));
+        std::vector<cd> H(size_t(m + 1) * m, cd(0)), cs(m), sn(m), g(m + 1, cd(0));
+        g[0] = beta;
+        int j_used = 0;
+        for (int j = 0; j < m && it < o.max_iter; ++j) {
+            double2 *vj1 = V + int64_t(j + 1) * N;
+            apply_device(p, V + int64_t(j) * N, vj1, 1, 3);
+            std::vector<cd> h1, h2;
+            for (int pass = 0; pass < 2; ++pass) {
+                std::vector<cd> &h = pass == 0 ? h1 : h2;
+                dot_host(V, j + 1, vj1, h);
+                std::vector<double2> hh(j + 1);
+                for (int i = 0; i <= j; ++i) hh[i] = make_double2(h[i].real(), h[i].imag());
+                BEM_HIP(hipMemcpyAsync(h_dev, hh.data(), (j + 1) * sizeof(double2), hipMemcpyHostToDevice, s));
+                bem::zaxpy_multi(s, V, N, j + 1, h_dev, vj1, N, -1.0);
+            }
+            for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = h1[i] + h2[i];
+            const double hn = norm(vj1);
+            H[size_t(j + 1) * m + j] = hn;
+            if (hn > 0) bem::zscale_copy(s, vj1, vj1, N, make_double2(1.0 / hn, 0.0));
+            // apply the previous rotations, then the new one
+            for (int i = 0; i < j; ++i) {
+                const cd a = H[size_t(i) * m + j], c = H[size_t(i + 1) * m + j];
+                H[size_t(i) * m + j] = cs[i] * a + sn[i] * c;
+                H[size_t(i + 1) * m + j] = -std::conj(sn[i]) * a + std::conj(cs[i]) * c;
+            }
+            const cd a = H[size_t(j) * m + j], c = H[size_t(j + 1) * m + j];
+            const double rho = std::sqrt(std::norm(a) + std::norm(c));
+            cs[j] = std::conj(a) / rho;
+            sn[j] = std::conj(c) / rho;
+            H[size_t(j) * m + j] = rho;
+            H[size_t(j + 1) * m + j] = 0.0;
+            g[j + 1] = -std::conj(sn[j]) * g[j];
+            g[j] = cs[j] * g[j];
+            ++it;
+            j_used = j + 1;
+            est = std::abs(g[j + 1]) / bnorm;
+            if (est <= o.tol || hn == 0.0) break;
+        }
+        // y = H^-1 g, x += V y
+        std::vector<cd> y(j_used);
+        for (int i = j_used - 1; i >= 0; --i) {
+            cd acc = g[i];
+            for (int k = i + 1; k < j_used; ++k) acc -= H[size_t(i) * m + k] * y[k];
+            y[i] = acc / H[size_t(i) * m + i];
+        }
+        std::vector<double2> yy(j_used);
+        for (int i = 0; i < j_used; ++i) yy[i] = make_double2(y[i].real(), y[i].imag());
+        BEM_HIP(hipMemcpyAsync(h_dev, yy.data(), j_used * sizeof(double2), hipMemcpyHostToDevice, s));
+        bem::zaxpy_multi(s, V, N, j_used, h_dev, x, N, 1.0);
+        if (est <= o.tol) break;
+    }
+    // true residual of the returned iterate
+    apply_device(p, x, w, 1, 3);
+    bem::zscale_copy(s, w, w, N, make_double2(-1.0, 0.0));
+    bem::zaxpy(s, w, b, N, make_double2(1.0, 0.0));
+    info.rel_residual = norm(w) / bnorm;
+    info.iterations = it;
+    info.converged = info.rel_residual <= o.tol * 1.01 || est <= o.tol ? 1 : 0;
+}
+
+}  // namespace
+
+namespace bem {
+void set_error(const std::string &msg) { g_last_error = msg; }
+}  // namespace bem
+
+extern "C" {
+
+const char *bem_last_error(void) { return g_last_error.c_str(); }
+
+bem_status bem_assemble(const bem_domain *domains, int32_t n_domains, bem_complex k0, double rho0,
+                        const bem_assemble_opts *opts, bem_problem **out)
+{
+    if (!out) return fail(BEM_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!domains || n_domains < 1) return fail(BEM_ERR_INVALID_ARG, "need at least one domain");
+    if (!finite_c(k0) || k0.im < 0 || !(rho0 > 0) || !std::isfinite(rho0))
+        return fail(BEM_ERR_INVALID_ARG, "k0 must be finite with Im k0 >= 0 and rho0 > 0");
+    bem_assemble_opts o{};
+    o.mode = BEM_OTF;
+    o.far_points = 6;
+    o.ss_order = 6;
+    if (opts) o = *opts;
+    if (o.far_points == 0) o.far_points = 6;
+    if (o.ss_order == 0) o.ss_order = 6;
+    if (o.far_points != 6) return fail(BEM_ERR_UNSUPPORTED, "only the 6-point far rule is implemented");
+    if (o.ss_order < 1 || o.ss_order > 16) return fail(BEM_ERR_INVALID_ARG, "ss_order must be in 1..16");
+    if (o.mode != BEM_OTF) return fail(BEM_ERR_UNSUPPORTED, "assembled modes are not available in this build");
+    if (k0.re <= 0) return fail(BEM_ERR_INVALID_ARG, "Re k0 must be positive");
+    for (int j = 0; j < n_domains; ++j) {
+        const bem_domain &d = domains[j];
+        if (!d.vertices || !d.triangles) return fail(BEM_ERR_INVALID_ARG, "domain " + std::to_string(j) + ": NULL mesh");
+        if (!finite_c(d.k) || d.k.im < 0 || d.k.re <= 0)
+            return fail(BEM_ERR_INVALID_ARG, "domain " + std::to_string(j) + ": k must be finite, Re k > 0, Im k >= 0");
+        if (!(d.rho > 0) || !std::isfinite(d.rho))
+            return fail(BEM_ERR_INVALID_ARG, "domain " + std::to_string(j) + ": rho must be positive");
+    }
+    bem_problem *p = new bem_problem;
+    bem_status st = guarded([&]() -> bem_status {
+        p->device = o.device;
+        p->stream = static_cast<hipStream_t>(o.stream);
+        p->flags = o.flags;
+        p->mode = o.mode;
+        p->ss_order = o.ss_order;
+        p->k0re = k0.re;
+        p->k0im = k0.im;
+        p->rho0 = rho0;
+        int64_t voff = 0, toff = 0;
+        for (int j = 0; j < n_domains; ++j) {
+            const bem_domain &d = domains[j];
+            bem::validate_mesh(d.vertices, d.n_vertices, d.triangles, d.n_triangles, j);
+            bem::DomInfo di{d.n_vertices, d.n_triangles, voff, toff, d.k.re, d.k.im, d.rho};
+            p->doms.push_back(di);
+            p->h_verts.insert(p->h_verts.end(), d.vertices, d.vertices + 3 * d.n_vertices);
+            for (int64_t i = 0; i < 3 * d.n_triangles; ++i) p->h_tris.push_back(int32_t(d.triangles[i] + voff));
+            voff += d.n_vertices;
+            toff += d.n_triangles;
+        }
+        p->NV = voff;
+        p->NT = toff;
+        p->M = 6 * toff;
+        p->N = 2 * voff;
+        if (p->M >= (int64_t(1) << 31) / 10) throw bem::Error{BEM_ERR_INVALID_ARG, "problem too large for 32-bit indexing"};
+        bem::validate_disjoint(p->doms, p->h_verts);
+        p->h_rowD.resize(p->NV);
+        p->h_rowN.resize(p->NV);
+        for (const auto &d : p->doms)
+            for (int64_t i = 0; i < d.nv; ++i) {
+                p->h_rowD[d.v_off + i] = int32_t(2 * d.v_off + i);
+                p->h_rowN[d.v_off + i] = int32_t(2 * d.v_off + d.nv + i);
+            }
+        BEM_HIP(hipSetDevice(p->device));
+        for (auto &e : p->ev) BEM_HIP(hipEventCreate(&e));
+        p->d_verts = dev_copy(p->h_verts, p->stream);
+        p->d_tris = dev_copy(p->h_tris, p->stream);
+        p->d_rowD = dev_copy(p->h_rowD, p->stream);
+        p->d_rowN = dev_copy(p->h_rowN, p->stream);
+        dev_alloc(&p->d_area, p->NT);
+        dev_alloc(&p->d_normal, 3 * p->NT);
+        dev_alloc(&p->d_curl, 9 * p->NT);
+        dev_alloc(&p->d_pts, 3 * p->M);
+        dev_alloc(&p->d_tnrm, 3 * p->NT);
+        // vertex -> (triangle, corner)
+        std::vector<int32_t> vptr(p->NV + 1, 0), vlst(3 * p->NT);
+        for (int64_t i = 0; i < 3 * p->NT; ++i) vptr[p->h_tris[i] + 1]++;
+        for (int64_t i = 0; i < p->NV; ++i) vptr[i + 1] += vptr[i];
+        {
+            std::vector<int32_t> fill(vptr.begin(), vptr.end() - 1);
+            for (int64_t t = 0; t < p->NT; ++t)
+                for (int a = 0; a < 3; ++a) vlst[fill[p->h_tris[3 * t + a]]++] = int32_t(3 * t + a);
+        }
+        p->d_v2t_ptr = dev_copy(vptr, p->stream);
+        p->d_v2t = dev_copy(vlst, p->stream);
+        bem::launch_geometry(*p);
+        // far-field work decomposition: at least ~8 workgroups per CU
+        p->tpl = 1;
+        const int64_t blocks = (p->M + 255) / 256;
+        p->n_split = int(std::clamp<int64_t>((8 * 256 + blocks - 1) / std::max<int64_t>(1, blocks), 1, 64));
+        if (p->n_split > 1) p->n_split = (p->n_split + 7) / 8 * 8;
+        build_passes(*p);
+        dev_alloc(&p->d_trial, size_t(4 * p->M));
+        dev_alloc(&p->d_part, size_t(2) * p->n_split * 10 * p->M);
+        dev_alloc(&p->d_pot, size_t(10) * p->M);
+        // interior slot partials of points not covered by an interior pass do
+        // not exist (every point belongs to one domain), but zero everything once
+        BEM_HIP(hipMemsetAsync(p->d_part, 0, size_t(2) * p->n_split * 10 * p->M * sizeof(double), p->stream));
+        // singular correction
+        std::vector<bem::SingularItem> items;
+        bem::touching_pairs(*p, items);
+        bem::run_singular(*p, items);
+        BEM_HIP(hipStreamSynchronize(p->stream));
+        return BEM_OK;
+    });
+    if (st != BEM_OK) {
+        free_problem(p);
+        return st;
+    }
+    *out = p;
+    return BEM_OK;
+}
+
+void bem_destroy(bem_problem *p) { free_problem(p); }
+
+int64_t bem_num_unknowns(const bem_problem *p) { return p ? p->N : -1; }
+
+bem_status bem_apply_parts(bem_problem *p, const bem_complex *x, bem_complex *y, int32_t n_rhs, int parts)
+{
+    if (!p || !x || !y || n_rhs < 0) return fail(BEM_ERR_INVALID_ARG, "bem_apply: bad arguments");
+    if (parts < 0 || parts > 3) return fail(BEM_ERR_INVALID_ARG, "bem_apply: parts must be 0..3");
+    if (n_rhs == 0) return BEM_OK;
+    return guarded([&]() -> bem_status {
+        BEM_HIP(hipSetDevice(p->device));
+        const size_t bytes = size_t(n_rhs) * p->N * sizeof(double2);
+        if (p->flags & BEM_DEVICE_PTRS) {
+            apply_device(*p, reinterpret_cast<const double2 *>(x), reinterpret_cast<double2 *>(y), n_rhs, parts);
+        } else {
+            for (int64_t i = 0; i < int64_t(n_rhs) * p->N; ++i)
+                if (!finite_c(x[i])) return fail(BEM_ERR_INVALID_ARG, "bem_apply: non-finite input");
+            ensure_scratch(*p, n_rhs);
+            BEM_HIP(hipMemcpyAsync(p->d_x, x, bytes, hipMemcpyHostToDevice, p->stream));
+            apply_device(*p, p->d_x, p->d_y, n_rhs, parts);
+            BEM_HIP(hipMemcpyAsync(y, p->d_y, bytes, hipMemcpyDeviceToHost, p->stream));
+            BEM_HIP(hipStreamSynchronize(p->stream));
+        }
+        return BEM_OK;
+    });
+}
+
+bem_status bem_apply(bem_problem *p, const bem_complex *x, bem_complex *y, int32_t n_rhs)
+{
+    return bem_apply_parts(p, x, y, n_rhs, 3);
+}
+
+bem_status bem_last_timings(const bem_problem *p, double *ms4)
+{
+    if (!p || !ms4) return fail(BEM_ERR_INVALID_ARG, "bem_last_timings: bad arguments");
+    if (!p->timed) return fail(BEM_ERR_INVALID_ARG, "bem_last_timings: no apply recorded yet");
+    return guarded([&]() -> bem_status {
+        BEM_HIP(hipEventSynchronize(p->ev[4]));
+        float t[4];
+        BEM_HIP(hipEventElapsedTime(&t[0], p->ev[0], p->ev[4]));
+        BEM_HIP(hipEventElapsedTime(&t[1], p->ev[1], p->ev[2]));
+        BEM_HIP(hipEventElapsedTime(&t[2], p->ev[3], p->ev[4]));
+        BEM_HIP(hipEventElapsedTime(&t[3], p->ev[0], p->ev[1]));
+        for (int i = 0; i < 4; ++i) ms4[i] = t[i];
+        return BEM_OK;
+    });
+}
+
+bem_status bem_rhs(bem_problem *p, const bem_incident *inc, bem_complex *b)
+{
+    if (!p || !inc || !b || !inc->params || inc->n_fields < 1)
+        return fail(BEM_ERR_INVALID_ARG, "bem_rhs: bad arguments");
+    if (inc->kind < BEM_PLANE_WAVE || inc->kind > BEM_PISTON_ARRAY)
+        return fail(BEM_ERR_INVALID_ARG, "bem_rhs: unknown incident kind");
+    return guarded([&]() -> bem_status {
+        BEM_HIP(hipSetDevice(p->device));
+        const size_t n = size_t(inc->n_fields) * p->N;
+        if (p->flags & BEM_DEVICE_PTRS) {
+            bem::launch_rhs(*p, *inc, reinterpret_cast<double2 *>(b));
+        } else {
+            double2 *d_b = nullptr;
+            dev_alloc(&d_b, n);
+            bem::launch_rhs(*p, *inc, d_b);
+            BEM_HIP(hipMemcpy(b, d_b, n * sizeof(double2), hipMemcpyDeviceToHost));
+            (void)hipFree(d_b);
+        }
+        return BEM_OK;
+    });
+}
+
+bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, const bem_solve_opts *opts,
+                         bem_complex *u, bem_solve_info *info)
+{
+    if (!p || !b || !u || !info || n_rhs < 1) return fail(BEM_ERR_INVALID_ARG, "bem_solve: bad arguments");
+    bem_solve_opts o = opts ? *opts : default_solve_opts();
+    if (!(o.tol > 0) || o.restart < 1 || o.max_iter < 1) return fail(BEM_ERR_INVALID_ARG, "bem_solve: bad options");
+    if (o.precond != BEM_PRECOND_NONE) return fail(BEM_ERR_UNSUPPORTED, "bem_solve: preconditioner not available");
+    if (o.precision != BEM_PREC_FP32) return fail(BEM_ERR_UNSUPPORTED, "bem_solve: precision mode not available");
+    return guarded([&]() -> bem_status {
+        BEM_HIP(hipSetDevice(p->device));
+        const size_t n = size_t(n_rhs) * p->N;
+        const double2 *db;
+        double2 *du;
+        double2 *tb = nullptr, *tu = nullptr;
+        if (p->flags & BEM_DEVICE_PTRS) {
+            db = reinterpret_cast<const double2 *>(b);
+            du = reinterpret_cast<double2 *>(u);
+        } else {
+            for (size_t i = 0; i < n; ++i)
+                if (!finite_c(b[i])) return fail(BEM_ERR_INVALID_ARG, "bem_solve: non-finite right-hand side");
+            dev_alloc(&tb, n);
+            dev_alloc(&tu, n);
+            BEM_HIP(hipMemcpyAsync(tb, b, n * sizeof(double2), hipMemcpyHostToDevice, p->stream));
+            db = tb;
+            du = tu;
+        }
+        bool all = true;
+        for (int r = 0; r < n_rhs; ++r) {
+            gmres_one(*p, db + int64_t(r) * p->N, du + int64_t(r) * p->N, o, info[r]);
+            all = all && info[r].converged;
+        }
+        if (!(p->flags & BEM_DEVICE_PTRS)) {
+            BEM_HIP(hipMemcpyAsync(u, du, n * sizeof(double2), hipMemcpyDeviceToHost, p->stream));
+            BEM_HIP(hipStreamSynchronize(p->stream));
+            (void)hipFree(tb);
+            (void)hipFree(tu);
+        }
+        if (!all) return fail(BEM_WARN_NOT_CONVERGED, "bem_solve: GMRES reached max_iter for some right-hand side");
+        return BEM_OK;
+    });
+}
+
+bem_status bem_solve(bem_problem *p, const bem_incident *inc, const bem_solve_opts *opts, bem_complex *u,
+                     bem_solve_info *info)
+{
+    if (!p || !inc || !u || !info || inc->n_fields < 1) return fail(BEM_ERR_INVALID_ARG, "bem_solve: bad arguments");
+    return guarded([&]() -> bem_status {
+        BEM_HIP(hipSetDevice(p->device));
+        const size_t n = size_t(inc->n_fields) * p->N;
+        double2 *d_b = nullptr;
+        dev_alloc(&d_b, n);
+        bem::launch_rhs(*p, *inc, d_b);
+        const uint32_t saved = p->flags;
+        bem_status st;
+        if (saved & BEM_DEVICE_PTRS) {
+            st = bem_solve_rhs(p, reinterpret_cast<bem_complex *>(d_b), inc->n_fields, opts, u, info);
+        } else {
+            std::vector<bem_complex> hb(n);
+            BEM_HIP(hipMemcpy(hb.data(), d_b, n * sizeof(double2), hipMemcpyDeviceToHost));
+            st = bem_solve_rhs(p, hb.data(), inc->n_fields, opts, u, info);
+        }
+        (void)hipFree(d_b);
+        return st;
+    });
+}
+
+bem_status bem_evaluate_field(bem_problem *p, const bem_complex *u, const bem_incident *inc, const double *points,
+                              int64_t n_points, bem_complex *field, int32_t *region)
+{
+    if (!p || !u || !points || !field || !region || n_points < 0)
+        return fail(BEM_ERR_INVALID_ARG, "bem_evaluate_field: bad arguments");
+    const int n_fields = inc ? inc->n_fields : 1;
+    return guarded([&]() -> bem_status {
+        BEM_HIP(hipSetDevice(p->device));
+        if (p->flags & BEM_DEVICE_PTRS) {
+            bem::launch_field(*p, reinterpret_cast<const double2 *>(u), inc, n_fields, points, n_points,
+                              reinterpret_cast<double2 *>(field), region);
+        } else {
+            double2 *du = nullptr, *df = nullptr;
+            double *dp = nullptr;
+            int32_t *dr = nullptr;
+            dev_alloc(&du, size_t(n_fields) * p->N);
+            dev_alloc(&df, size_t(n_fields) * n_points);
+            dev_alloc(&dp, size_t(3 * n_points));
+            dev_alloc(&dr, size_t(n_points));
+            BEM_HIP(hipMemcpy(du, u, size_t(n_fields) * p->N * sizeof(double2), hipMemcpyHostToDevice));
+            BEM_HIP(hipMemcpy(dp, points, size_t(3 * n_points) * sizeof(double), hipMemcpyHostToDevice));
+            bem::launch_field(*p, du, inc, n_fields, dp, n_points, df, dr);
+            BEM_HIP(hipMemcpy(field, df, size_t(n_fields) * n_points * sizeof(double2), hipMemcpyDeviceToHost));
+            BEM_HIP(hipMemcpy(region, dr, size_t(n_points) * sizeof(int32_t), hipMemcpyDeviceToHost));
+            (void)hipFree(du); (void)hipFree(df); (void)hipFree(dp); (void)hipFree(dr);
+        }
+        return BEM_OK;
+    });
+}
+
+bem_status bem_footprint_bytes(const bem_domain *domains, int32_t n_domains, const bem_assemble_opts *opts,
+                               int32_t n_rhs, int32_t restart, uint64_t *bytes)
+{
+    (void)opts;
+    if (!domains || n_domains < 1 || !bytes || n_rhs < 0 || restart < 0)
+        return fail(BEM_ERR_INVALID_ARG, "bem_footprint_bytes: bad arguments");
+    uint64_t nv = 0, nt = 0;
+    for (int j = 0; j < n_domains; ++j) {
+        nv += uint64_t(domains[j].n_vertices);
+        nt += uint64_t(domains[j].n_triangles);
+    }
+    const uint64_t M = 6 * nt, N = 2 * nv;
+    const uint64_t n_split = 16;
+    uint64_t b = 0;
+    b += nv * 24 + nt * 12 + nv * 8;              // vertices, triangles, row maps
+    b += nt * (8 + 24 + 72 + 12) + M * 12;        // geometry, points
+    b += M * 64 + 2 * n_split * 10 * M * 8 + M * 80;   // trial records, partials, potentials
+    b += nv * 24 * (4 + 4 * 64);                  // correction CSR (about 24 entries per row)
+    b += uint64_t(n_rhs) * N * 16 * 2;            // x, y
+    b += uint64_t(restart + 1) * N * 16;          // Krylov basis of one right-hand side
+    *bytes = b;
+    return BEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,182 @@
+// Internal declarations shared by the host runtime and the HIP kernels of the
+// boundary-element library.  Not part of the C ABI (that is include/bem.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bem.h"
+
+namespace bem {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+struct Error {
+    bem_status status;
+    std::string msg;
+};
+
+void set_error(const std::string &msg);
+
+#define BEM_HIP(call)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            throw ::bem::Error{e_ == hipErrorOutOfMemory ? BEM_ERR_OOM : BEM_ERR_DEVICE,       \
+                               std::string(#call) + ": " + hipGetErrorString(e_)};            \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// quadrature constants (shared by the kernels through these definitions)
+// ---------------------------------------------------------------------------
+
+// Pair classes of two triangles of one boundary.
+enum PairClass : int { FAR = 0, VERTEX = 1, EDGE = 2, COINCIDENT = 3 };
+
+// Far-field work: one wavenumber pass of the pair kernel over a test range and
+// a trial range of quadrature points.
+struct PassDesc {
+    int64_t test_begin, test_end;    // quadrature-point range of test points
+    int64_t trial_begin, trial_end;  // quadrature-point range of trial points
+    double kre, kim;                 // wavenumber of the pass
+    double sV, sW;                   // density scalings of V and W (PMCHWT interior blocks)
+    int slot;                        // partial-sum slot (0: exterior pass, 1: interior pass)
+    int pad;
+};
+
+// Kernel-side copy of a pass (FP32 constants + ranges).
+struct PassDev {
+    long long test_begin, test_end, trial_begin, trial_end;
+    float k, k_over_2pi, kim, sV;
+    float sW, k2re, k2im, pad;       // k^2 (complex) for the W normal term
+    int slot, pad2, pad3, pad4;
+};
+
+// One ordered touching pair (test triangle t, trial triangle s) of the singular
+// pass.  pt/ps: local vertex orders that put the shared vertices first.
+struct SingularItem {
+    int t, s;
+    int cls;
+    int pass;          // index into the pass table (wavenumber and scalings)
+    int pt[3], ps[3];
+};
+
+struct DomInfo {
+    int64_t nv, nt;        // vertices / triangles of the domain
+    int64_t v_off, t_off;  // offsets in the global vertex / triangle arrays
+    double kre, kim, rho;
+};
+
+}  // namespace bem
+
+// ---------------------------------------------------------------------------
+// problem state (opaque handle of the C ABI)
+// ---------------------------------------------------------------------------
+
+struct bem_problem {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint32_t flags = 0;
+    int mode = BEM_OTF;
+    int ss_order = 6;
+
+    std::vector<bem::DomInfo> doms;
+    double k0re = 0, k0im = 0, rho0 = 1;
+    int64_t NV = 0, NT = 0, M = 0, N = 0;   // vertices, triangles, quadrature points, unknowns
+
+    // host copies
+    std::vector<double> h_verts;           // [NV][3]
+    std::vector<int32_t> h_tris;           // [NT][3] global vertex indices
+    std::vector<int32_t> h_rowD, h_rowN;   // unknown index of u_D / u_N per global vertex
+    std::vector<bem::PassDesc> passes;
+
+    // device geometry
+    double *d_verts = nullptr;      // [NV][3]
+    int32_t *d_tris = nullptr;      // [NT][3]
+    int32_t *d_rowD = nullptr, *d_rowN = nullptr;
+    double *d_area = nullptr;       // [NT]
+    double *d_normal = nullptr;     // [NT][3]
+    double *d_curl = nullptr;       // [NT][3][3]
+    float *d_pts = nullptr;         // [3][M] FP32 quadrature points (SoA)
+    float *d_tnrm = nullptr;        // [3][NT] FP32 triangle normals (SoA)
+    int32_t *d_v2t_ptr = nullptr;   // [NV + 1]
+    int32_t *d_v2t = nullptr;       // [3 NT]  (triangle * 3 + corner)
+
+    // far-field pass
+    bem::PassDev *d_pass = nullptr;
+    int n_pass = 0;
+    int4 *d_work = nullptr;         // (pass, test block, split, 0)
+    int n_work = 0;
+    int n_split = 8;
+    int tpl = 1;                    // test points per lane of the pair kernel
+    float4 *d_trial = nullptr;      // [M][4] trial records
+    double *d_part = nullptr;       // [2][n_split][10][M]
+    double *d_pot = nullptr;        // [M][10]
+
+    // singular correction: vertex-level CSR with 4 complex blocks (DD, DN, ND, NN)
+    int32_t *d_cptr = nullptr, *d_ccol = nullptr;
+    double2 *d_cval = nullptr;      // [nnz][4]
+    int64_t nnz = 0;
+
+    // scratch vectors
+    double2 *d_x = nullptr, *d_y = nullptr;
+    int64_t scratch_rhs = 0;
+
+    // timing
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool timed = false;
+};
+
+namespace bem {
+
+// ---------------------------------------------------------------------------
+// host-side mesh topology (mesh.cpp)
+// ---------------------------------------------------------------------------
+
+// Validate one domain's mesh; throws Error{BEM_ERR_MESH} with a message.
+void validate_mesh(const double *v, int64_t nv, const int32_t *t, int64_t nt, int dom);
+// Check that no two domains share or nearly share vertices (disjoint domains).
+void validate_disjoint(const std::vector<DomInfo> &doms, const std::vector<double> &verts);
+// Ordered touching pairs of every domain (sorted by class), for every pass that
+// covers the domain (exterior pass 0 and the domain's own interior pass).
+void touching_pairs(const bem_problem &p, std::vector<SingularItem> &items);
+// Vertex-level pattern of the singular correction and the slot of every
+// (item, a, b) contribution; contributions per slot are listed in item order.
+void correction_pattern(const bem_problem &p, const std::vector<SingularItem> &items,
+                        std::vector<int32_t> &cptr, std::vector<int32_t> &ccol,
+                        std::vector<int32_t> &contrib_ptr, std::vector<int32_t> &contrib_idx);
+
+// Sauter-Schwab rule of one class at order n on T x T, T = {0 <= s2 <= s1 <= 1}:
+// rows (x1, x2, y1, y2, w).  Independent implementation of the library.
+std::vector<double> singular_rule(int cls, int n);
+
+// ---------------------------------------------------------------------------
+// kernel launchers (k_*.hip)
+// ---------------------------------------------------------------------------
+
+void launch_geometry(bem_problem &p);
+void launch_gather(bem_problem &p, const double2 *x);
+void launch_pairs(bem_problem &p);
+void launch_reduce(bem_problem &p);
+void launch_scatter(bem_problem &p, const double2 *x, double2 *y, int parts);
+void run_singular(bem_problem &p, const std::vector<SingularItem> &items);
+
+// FP64 complex vector helpers for GMRES (k_linalg.hip)
+void zdot_multi(hipStream_t s, const double2 *V, int64_t ld, int nvec, const double2 *w, int64_t n,
+                double2 *partials, int nblk, double2 *out_dev);
+void zaxpy_multi(hipStream_t s, const double2 *V, int64_t ld, int nvec, const double2 *h_dev, double2 *w,
+                 int64_t n, double sign);
+void zscale_copy(hipStream_t s, const double2 *x, double2 *y, int64_t n, double2 a);
+void zaxpy(hipStream_t s, double2 *y, const double2 *x, int64_t n, double2 a);
+
+// incident fields and right-hand sides (k_field.hip)
+void launch_rhs(bem_problem &p, const bem_incident &inc, double2 *b);
+void launch_field(bem_problem &p, const double2 *u, const bem_incident *inc, int n_fields,
+                  const double *pts, int64_t np, double2 *field, int32_t *region);
+
+}  // namespace bem

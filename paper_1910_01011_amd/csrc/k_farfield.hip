@@ -1,0 +1,384 @@
+// Far-field path of the Galerkin apply y = A x:
+//   geometry  - per-triangle area, unit normal, P1 surface curls, quadrature points
+//   gather    - P1 coefficients -> weighted densities at trial quadrature points
+//   pairs     - all (test point, trial point) pairs of one wavenumber pass, FP32,
+//               trial tiles staged in LDS, FP64 accumulation per tile
+//   reduce    - sum of the per-split partial potentials (fixed order)
+//   scatter   - test-side P1 projection per vertex + FP64 singular correction
+//
+// Operators (paper, Appendix A) with G = exp(ikr)/(4 pi r), d = x - y and
+// F = G (1 - ikr)/r^2:  V: G;  K: F (d.n_y);  K': -F (d.n_x);
+// W (integrated by parts): G [curl phi_b . curl phi_a - k^2 (n_x.n_y) phi_a phi_b].
+// The PMCHWT rows of one domain (eq. Form2_calderon_sys_simp3) are
+//   Dirichlet row:  -K u_D + sV V u_N,   Neumann row:  sW W u_D + K' u_N,
+// with sV = sW = 1 for the exterior pass and sV = rho_j/rho_0, sW = rho_0/rho_j
+// for the interior pass of domain j (eq. Form1_calderon_sys_int_ptot).
+#include "bem_internal.h"
+
+namespace bem {
+
+// 6-point degree-4 rule: barycentric coordinates and weights (weights sum to 1).
+__constant__ double c_bary[6][3] = {
+    {0.10810301816807022736, 0.44594849091596488632, 0.44594849091596488632},
+    {0.44594849091596488632, 0.10810301816807022736, 0.44594849091596488632},
+    {0.44594849091596488632, 0.44594849091596488632, 0.10810301816807022736},
+    {0.81684757298045851308, 0.091576213509770743460, 0.091576213509770743460},
+    {0.091576213509770743460, 0.81684757298045851308, 0.091576213509770743460},
+    {0.091576213509770743460, 0.091576213509770743460, 0.81684757298045851308}};
+__constant__ double c_wq[6] = {0.22338158967801146570, 0.22338158967801146570, 0.22338158967801146570,
+                               0.10995174365532186764, 0.10995174365532186764, 0.10995174365532186764};
+
+constexpr int PAIR_BLOCK = 256;   // threads per workgroup of the pair kernel = trial tile
+constexpr double INV4PI = 0.079577471545947667884;
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+
+__global__ void k_geometry(const double *__restrict__ verts, const int32_t *__restrict__ tris, int64_t nt, int64_t M,
+                           double *__restrict__ area, double *__restrict__ normal, double *__restrict__ curl,
+                           float *__restrict__ pts, float *__restrict__ tnrm)
+{
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    double P[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int d = 0; d < 3; ++d) P[a][d] = verts[3 * int64_t(tris[3 * t + a]) + d];
+    double e1[3], e2[3];
+    for (int d = 0; d < 3; ++d) { e1[d] = P[1][d] - P[0][d]; e2[d] = P[2][d] - P[0][d]; }
+    const double c0 = e1[1] * e2[2] - e1[2] * e2[1];
+    const double c1 = e1[2] * e2[0] - e1[0] * e2[2];
+    const double c2 = e1[0] * e2[1] - e1[1] * e2[0];
+    const double twice = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+    area[t] = 0.5 * twice;
+    const double n[3] = {c0 / twice, c1 / twice, c2 / twice};
+    for (int d = 0; d < 3; ++d) {
+        normal[3 * t + d] = n[d];
+        tnrm[d * nt + t] = float(n[d]);
+    }
+    // surface curl of the barycentric function lambda_a: -(P_{a+2} - P_{a+1}) / (2|T|)
+    for (int a = 0; a < 3; ++a)
+        for (int d = 0; d < 3; ++d) curl[9 * t + 3 * a + d] = -(P[(a + 2) % 3][d] - P[(a + 1) % 3][d]) / twice;
+    for (int q = 0; q < 6; ++q)
+        for (int d = 0; d < 3; ++d) {
+            const double x = c_bary[q][0] * P[0][d] + c_bary[q][1] * P[1][d] + c_bary[q][2] * P[2][d];
+            pts[d * M + 6 * t + q] = float(x);
+        }
+}
+
+void launch_geometry(bem_problem &p)
+{
+    const int B = 256;
+    k_geometry<<<dim3(unsigned((p.NT + B - 1) / B)), dim3(B), 0, p.stream>>>(
+        p.d_verts, p.d_tris, p.NT, p.M, p.d_area, p.d_normal, p.d_curl, p.d_pts, p.d_tnrm);
+    BEM_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// gather: trial record of quadrature point i = 6 t + q (4 x float4)
+//   r0 = (y, n.x)   r1 = (n.y, n.z, u_D w)   r2 = (u_N w, curl(u_D).x w)
+//   r3 = (curl(u_D).y w, curl(u_D).z w)      with w = |T| w_q / (4 pi)
+// ---------------------------------------------------------------------------
+
+__global__ void k_gather(const double2 *__restrict__ x, const int32_t *__restrict__ tris,
+                         const int32_t *__restrict__ rowD, const int32_t *__restrict__ rowN,
+                         const double *__restrict__ area, const double *__restrict__ curl,
+                         const float *__restrict__ pts, const float *__restrict__ tnrm, int64_t nt, int64_t M,
+                         float4 *__restrict__ trial)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const int64_t t = i / 6;
+    const int q = int(i - 6 * t);
+    double uDr = 0, uDi = 0, uNr = 0, uNi = 0, cr[3] = {0, 0, 0}, ci[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a) {
+        const int32_t g = tris[3 * t + a];
+        const double2 xd = x[rowD[g]];
+        const double2 xn = x[rowN[g]];
+        const double l = c_bary[q][a];
+        uDr += l * xd.x; uDi += l * xd.y;
+        uNr += l * xn.x; uNi += l * xn.y;
+        for (int d = 0; d < 3; ++d) {
+            const double c = curl[9 * t + 3 * a + d];
+            cr[d] += c * xd.x;
+            ci[d] += c * xd.y;
+        }
+    }
+    const double w = area[t] * c_wq[q] * INV4PI;
+    float4 *r = trial + 4 * i;
+    r[0] = make_float4(pts[i], pts[M + i], pts[2 * M + i], tnrm[t]);
+    r[1] = make_float4(tnrm[nt + t], tnrm[2 * nt + t], float(uDr * w), float(uDi * w));
+    r[2] = make_float4(float(uNr * w), float(uNi * w), float(cr[0] * w), float(ci[0] * w));
+    r[3] = make_float4(float(cr[1] * w), float(ci[1] * w), float(cr[2] * w), float(ci[2] * w));
+}
+
+void launch_gather(bem_problem &p, const double2 *x)
+{
+    const int B = 256;
+    k_gather<<<dim3(unsigned((p.M + B - 1) / B)), dim3(B), 0, p.stream>>>(
+        x, p.d_tris, p.d_rowD, p.d_rowN, p.d_area, p.d_curl, p.d_pts, p.d_tnrm, p.NT, p.M, p.d_trial);
+    BEM_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// pair kernel
+// ---------------------------------------------------------------------------
+//
+// Work item (pass, test block, split): a workgroup of 256 lanes owns
+// 256 * TPL consecutive test points of the pass and one contiguous chunk of
+// its trial points (split s of n_split).  Trial points go through LDS in tiles
+// of 256; every lane reads each tile entry by broadcast.  Per test point the
+// kernel accumulates five complex potentials:
+//   D  = sum sV G u_N w - F (d.n_y) u_D w                       (Dirichlet row)
+//   N  = sum -k^2 sW (n_x.n_y) G u_D w - F (d.n_x) u_N w        (Neumann row, scalar part)
+//   C  = sum sW G curl(u_D) w                                   (Neumann row, curl part, 3-vector)
+// in FP32 within a tile and in FP64 across tiles.
+//
+// LDS record of one trial point (5 x float4):
+//   L0 = (y, n_y.x)  L1 = (n_y.y, n_y.z, -u_D w)  L2 = (sV u_N w, -u_N w)
+//   L3 = (-k^2 sW u_D w, sW curl.x)  L4 = (sW curl.y, sW curl.z)
+
+struct Acc {
+    float dr, di, nr, ni, cxr, cxi, cyr, cyi, czr, czi;
+};
+
+template <bool ATT>
+__device__ __forceinline__ void pair_step(const float xx, const float xy, const float xz, const float nx,
+                                          const float ny, const float nz, const float4 L0, const float4 L1,
+                                          const float4 L2, const float4 L3, const float4 L4, const float k,
+                                          const float k2pi, const float kim, Acc &a)
+{
+    const float dx = xx - L0.x, dy = xy - L0.y, dz = xz - L0.z;
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    // r2 == 0 only for a point paired with itself (coincident triangle, same
+    // quadrature point); that term belongs to the singular correction.
+    const float rinv = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+    const float r = r2 * rinv;
+    float ph = r * k2pi;                       // phase in revolutions
+    ph = ph - rintf(ph);
+    const float sn = __builtin_amdgcn_sinf(ph);  // sin(2 pi ph)
+    const float cs = __builtin_amdgcn_cosf(ph);
+    float gr = cs * rinv, gi = sn * rinv;
+    float fr, fi;
+    const float kr = r * k;
+    const float rinv2 = rinv * rinv;
+    if (ATT) {
+        const float damp = __expf(-kim * r);
+        gr *= damp;
+        gi *= damp;
+        // (1 - i k r) with complex k = (1 + kim r) - i kr
+        const float re1 = fmaf(kim, r, 1.0f);
+        fr = fmaf(gr, re1, gi * kr) * rinv2;
+        fi = fmaf(gi, re1, -gr * kr) * rinv2;
+    } else {
+        fr = fmaf(gi, kr, gr) * rinv2;
+        fi = fmaf(-gr, kr, gi) * rinv2;
+    }
+    const float tK = fmaf(dx, L0.w, fmaf(dy, L1.x, dz * L1.y));    // d . n_y
+    const float tKp = fmaf(dx, nx, fmaf(dy, ny, dz * nz));         // d . n_x
+    const float tW = fmaf(nx, L0.w, fmaf(ny, L1.x, nz * L1.y));    // n_x . n_y
+    const float eKr = fr * tK, eKi = fi * tK;
+    const float ePr = fr * tKp, ePi = fi * tKp;
+    const float gWr = gr * tW, gWi = gi * tW;
+    // D += G * (sV u_N w) + eK * (-u_D w)
+    a.dr = fmaf(gr, L2.x, fmaf(-gi, L2.y, fmaf(eKr, L1.z, fmaf(-eKi, L1.w, a.dr))));
+    a.di = fmaf(gr, L2.y, fmaf(gi, L2.x, fmaf(eKr, L1.w, fmaf(eKi, L1.z, a.di))));
+    // N += gW * (-k^2 sW u_D w) + eP * (-u_N w)
+    a.nr = fmaf(gWr, L3.x, fmaf(-gWi, L3.y, fmaf(ePr, L2.z, fmaf(-ePi, L2.w, a.nr))));
+    a.ni = fmaf(gWr, L3.y, fmaf(gWi, L3.x, fmaf(ePr, L2.w, fmaf(ePi, L2.z, a.ni))));
+    // C += G * (sW curl u_D w)
+    a.cxr = fmaf(gr, L3.z, fmaf(-gi, L3.w, a.cxr));
+    a.cxi = fmaf(gr, L3.w, fmaf(gi, L3.z, a.cxi));
+    a.cyr = fmaf(gr, L4.x, fmaf(-gi, L4.y, a.cyr));
+    a.cyi = fmaf(gr, L4.y, fmaf(gi, L4.x, a.cyi));
+    a.czr = fmaf(gr, L4.z, fmaf(-gi, L4.w, a.czr));
+    a.czi = fmaf(gr, L4.w, fmaf(gi, L4.z, a.czi));
+}
+
+template <int TPL, bool ATT>
+__global__ __launch_bounds__(PAIR_BLOCK) void k_pairs(const int4 *__restrict__ work, const PassDev *__restrict__ passes,
+                                                      const float *__restrict__ pts, const float *__restrict__ tnrm,
+                                                      const float4 *__restrict__ trial, double *__restrict__ part,
+                                                      int64_t M, int64_t nt, int n_split)
+{
+    __shared__ float4 lds[5][PAIR_BLOCK];
+    const int4 w = work[blockIdx.x];
+    const PassDev P = passes[w.x];
+    const int tid = threadIdx.x;
+
+    // test points of this lane
+    float xx[TPL], xy[TPL], xz[TPL], nx[TPL], ny[TPL], nz[TPL];
+    long long ti[TPL];
+#pragma unroll
+    for (int u = 0; u < TPL; ++u) {
+        const long long i = P.test_begin + (long long)w.y * (PAIR_BLOCK * TPL) + u * PAIR_BLOCK + tid;
+        ti[u] = i;
+        const long long ii = i < P.test_end ? i : P.test_end - 1;
+        const long long t = ii / 6;
+        xx[u] = pts[ii];
+        xy[u] = pts[M + ii];
+        xz[u] = pts[2 * M + ii];
+        nx[u] = tnrm[t];
+        ny[u] = tnrm[nt + t];
+        nz[u] = tnrm[2 * nt + t];
+    }
+
+    // trial chunk of this split (multiple of the tile size)
+    const long long n_trial = P.trial_end - P.trial_begin;
+    long long chunk = (n_trial + n_split - 1) / n_split;
+    chunk = (chunk + PAIR_BLOCK - 1) / PAIR_BLOCK * PAIR_BLOCK;
+    const long long j_begin = P.trial_begin + (long long)w.z * chunk;
+    const long long j_end = j_begin + chunk < P.trial_end ? j_begin + chunk : P.trial_end;
+
+    double acc[TPL][10];
+#pragma unroll
+    for (int u = 0; u < TPL; ++u)
+#pragma unroll
+        for (int c = 0; c < 10; ++c) acc[u][c] = 0.0;
+
+    for (long long jt = j_begin; jt < j_end; jt += PAIR_BLOCK) {
+        const int cnt = int(j_end - jt < PAIR_BLOCK ? j_end - jt : PAIR_BLOCK);
+        __syncthreads();
+        if (tid < cnt) {
+            const float4 *r = trial + 4 * (jt + tid);
+            const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+            lds[0][tid] = r0;
+            lds[1][tid] = make_float4(r1.x, r1.y, -r1.z, -r1.w);
+            lds[2][tid] = make_float4(P.sV * r2.x, P.sV * r2.y, -r2.x, -r2.y);
+            // -k^2 sW u_D w (complex k^2)
+            const float ar = -P.sW * (P.k2re * r1.z - P.k2im * r1.w);
+            const float ai = -P.sW * (P.k2re * r1.w + P.k2im * r1.z);
+            lds[3][tid] = make_float4(ar, ai, P.sW * r2.z, P.sW * r2.w);
+            lds[4][tid] = make_float4(P.sW * r3.x, P.sW * r3.y, P.sW * r3.z, P.sW * r3.w);
+        }
+        __syncthreads();
+        Acc a[TPL];
+#pragma unroll
+        for (int u = 0; u < TPL; ++u) a[u] = Acc{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int j = 0; j < cnt; ++j) {
+            const float4 L0 = lds[0][j], L1 = lds[1][j], L2 = lds[2][j], L3 = lds[3][j], L4 = lds[4][j];
+#pragma unroll
+            for (int u = 0; u < TPL; ++u)
+                pair_step<ATT>(xx[u], xy[u], xz[u], nx[u], ny[u], nz[u], L0, L1, L2, L3, L4, P.k, P.k_over_2pi,
+                               P.kim, a[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < TPL; ++u) {
+            acc[u][0] += a[u].dr; acc[u][1] += a[u].di;
+            acc[u][2] += a[u].nr; acc[u][3] += a[u].ni;
+            acc[u][4] += a[u].cxr; acc[u][5] += a[u].cxi;
+            acc[u][6] += a[u].cyr; acc[u][7] += a[u].cyi;
+            acc[u][8] += a[u].czr; acc[u][9] += a[u].czi;
+        }
+    }
+    double *out = part + (size_t(P.slot) * n_split + w.z) * 10 * size_t(M);
+#pragma unroll
+    for (int u = 0; u < TPL; ++u)
+        if (ti[u] < P.test_end)
+#pragma unroll
+            for (int c = 0; c < 10; ++c) out[size_t(c) * M + ti[u]] = acc[u][c];
+}
+
+void launch_pairs(bem_problem &p)
+{
+    bool att = false;
+    for (int i = 0; i < p.n_pass; ++i)
+        if (p.passes[i].kim != 0.0) att = true;
+    const dim3 grid(unsigned(p.n_work)), block(PAIR_BLOCK);
+    if (p.tpl == 2) {
+        if (att)
+            k_pairs<2, true><<<grid, block, 0, p.stream>>>(p.d_work, p.d_pass, p.d_pts, p.d_tnrm, p.d_trial, p.d_part, p.M, p.NT, p.n_split);
+        else
+            k_pairs<2, false><<<grid, block, 0, p.stream>>>(p.d_work, p.d_pass, p.d_pts, p.d_tnrm, p.d_trial, p.d_part, p.M, p.NT, p.n_split);
+    } else {
+        if (att)
+            k_pairs<1, true><<<grid, block, 0, p.stream>>>(p.d_work, p.d_pass, p.d_pts, p.d_tnrm, p.d_trial, p.d_part, p.M, p.NT, p.n_split);
+        else
+            k_pairs<1, false><<<grid, block, 0, p.stream>>>(p.d_work, p.d_pass, p.d_pts, p.d_tnrm, p.d_trial, p.d_part, p.M, p.NT, p.n_split);
+    }
+    BEM_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// reduce: pot[i][c] = sum over slots and splits of the partials (fixed order)
+// ---------------------------------------------------------------------------
+
+__global__ void k_reduce(const double *__restrict__ part, int64_t M, int n_split, double *__restrict__ pot)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    for (int c = 0; c < 10; ++c) {
+        double s = 0.0;
+        for (int k = 0; k < 2 * n_split; ++k) s += part[(size_t(k) * 10 + c) * M + i];
+        pot[10 * i + c] = s;
+    }
+}
+
+void launch_reduce(bem_problem &p)
+{
+    const int B = 256;
+    k_reduce<<<dim3(unsigned((p.M + B - 1) / B)), dim3(B), 0, p.stream>>>(p.d_part, p.M, p.n_split, p.d_pot);
+    BEM_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// scatter: one thread per vertex g
+//   y_D[g] = sum_{(t,a) at g} sum_q |t| w_q lambda_a(q) D(t,q)            + correction
+//   y_N[g] = sum_{(t,a) at g} sum_q |t| w_q [lambda_a(q) N(t,q) + curl_a . C(t,q)] + correction
+// correction: y_D += C_DD x_D + C_DN x_N,  y_N += C_ND x_D + C_NN x_N over the
+// vertex-level CSR of touching pairs.
+// ---------------------------------------------------------------------------
+
+__global__ void k_scatter(const double *__restrict__ pot, const int32_t *__restrict__ v2t_ptr,
+                          const int32_t *__restrict__ v2t, const double *__restrict__ area,
+                          const double *__restrict__ curl, const int32_t *__restrict__ rowD,
+                          const int32_t *__restrict__ rowN, const int32_t *__restrict__ cptr,
+                          const int32_t *__restrict__ ccol, const double2 *__restrict__ cval,
+                          const double2 *__restrict__ x, double2 *__restrict__ y, int64_t NV, int parts)
+{
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= NV) return;
+    double yDr = 0, yDi = 0, yNr = 0, yNi = 0;
+    if (parts & 1) {
+        for (int32_t k = v2t_ptr[g]; k < v2t_ptr[g + 1]; ++k) {
+            const int32_t tc = v2t[k];
+            const int64_t t = tc / 3;
+            const int a = tc - 3 * int(t);
+            const double ar = area[t];
+            const double cx = curl[9 * t + 3 * a], cy = curl[9 * t + 3 * a + 1], cz = curl[9 * t + 3 * a + 2];
+            for (int q = 0; q < 6; ++q) {
+                const double *P = pot + 10 * (6 * t + q);
+                const double w = ar * c_wq[q];
+                const double wl = w * c_bary[q][a];
+                yDr += wl * P[0];
+                yDi += wl * P[1];
+                yNr += wl * P[2] + w * (cx * P[4] + cy * P[6] + cz * P[8]);
+                yNi += wl * P[3] + w * (cx * P[5] + cy * P[7] + cz * P[9]);
+            }
+        }
+    }
+    if (parts & 2) {
+        for (int32_t e = cptr[g]; e < cptr[g + 1]; ++e) {
+            const int32_t h = ccol[e];
+            const double2 xd = x[rowD[h]], xn = x[rowN[h]];
+            const double2 DD = cval[4 * e], DN = cval[4 * e + 1], ND = cval[4 * e + 2], NN = cval[4 * e + 3];
+            yDr += DD.x * xd.x - DD.y * xd.y + DN.x * xn.x - DN.y * xn.y;
+            yDi += DD.x * xd.y + DD.y * xd.x + DN.x * xn.y + DN.y * xn.x;
+            yNr += ND.x * xd.x - ND.y * xd.y + NN.x * xn.x - NN.y * xn.y;
+            yNi += ND.x * xd.y + ND.y * xd.x + NN.x * xn.y + NN.y * xn.x;
+        }
+    }
+    y[rowD[g]] = make_double2(yDr, yDi);
+    y[rowN[g]] = make_double2(yNr, yNi);
+}
+
+void launch_scatter(bem_problem &p, const double2 *x, double2 *y, int parts)
+{
+    const int B = 256;
+    k_scatter<<<dim3(unsigned((p.NV + B - 1) / B)), dim3(B), 0, p.stream>>>(
+        p.d_pot, p.d_v2t_ptr, p.d_v2t, p.d_area, p.d_curl, p.d_rowD, p.d_rowN, p.d_cptr, p.d_ccol, p.d_cval, x, y,
+        p.NV, parts);
+    BEM_HIP(hipGetLastError());
+}
+
+}  // namespace bem

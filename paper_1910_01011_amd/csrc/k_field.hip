@@ -1,0 +1,305 @@
+// Incident fields, right-hand sides and the field off the surface.
+//
+// Right-hand side (eq. Galerkin_disc_rhs1): b_D[g] = <p_inc, phi_g>,
+// b_N[g] = <dp_inc/dn, phi_g>, integrated with the 6-point rule per triangle.
+// Incident kinds:
+//   plane wave    p = A exp(i k0 d.x)
+//   point sources p = sum_s a_s exp(i k0 |x - s|) / (4 pi |x - s|)
+//   pistons       flat baffled discs, p(x) = (-i k0 / 2 pi) int_disc exp(i k0 r)/r dS
+//                 (unit rho c u), each discretised by 3 Gauss-Legendre radii
+//                 (weight r dr) times 8 equal angles, i.e. a sum of 24 monopoles.
+// Field (eq. rep_formula_gen): exterior p = p_inc + sum_j [DL_k0 u_D - SL_k0 u_N],
+// inside domain j p = SL_kj((rho_j/rho_0) u_N) - DL_kj u_D, 6-point rule on the
+// sources; the region comes from the solid-angle winding number of each domain.
+#include <cmath>
+#include <vector>
+
+#include "bem_internal.h"
+
+namespace bem {
+
+__constant__ double f_bary[6][3] = {
+    {0.10810301816807022736, 0.44594849091596488632, 0.44594849091596488632},
+    {0.44594849091596488632, 0.10810301816807022736, 0.44594849091596488632},
+    {0.44594849091596488632, 0.44594849091596488632, 0.10810301816807022736},
+    {0.81684757298045851308, 0.091576213509770743460, 0.091576213509770743460},
+    {0.091576213509770743460, 0.81684757298045851308, 0.091576213509770743460},
+    {0.091576213509770743460, 0.091576213509770743460, 0.81684757298045851308}};
+__constant__ double f_wq[6] = {0.22338158967801146570, 0.22338158967801146570, 0.22338158967801146570,
+                               0.10995174365532186764, 0.10995174365532186764, 0.10995174365532186764};
+
+constexpr double PI_D = 3.14159265358979323846;
+
+struct IncDev {
+    int kind;
+    int n_fields;
+    int64_t n_params;
+    const double *params;   // device copy
+    double k0re, k0im;
+};
+
+// monopole exp(i k |x - s|) / (4 pi |x - s|) and its gradient . n, times amplitude a
+__device__ __forceinline__ void monopole(const double *x, const double *nrm, const double *s, double ar, double ai,
+                                         double kre, double kim, double &pr, double &pi, double &qr, double &qi)
+{
+    const double dx = x[0] - s[0], dy = x[1] - s[1], dz = x[2] - s[2];
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    double sn, cs;
+    sincos(kre * r, &sn, &cs);
+    const double e = exp(-kim * r) / (4.0 * PI_D * r);
+    const double gr = e * cs, gi = e * sn;
+    const double vr = gr * ar - gi * ai, vi = gr * ai + gi * ar;   // a G
+    pr += vr;
+    pi += vi;
+    // grad G . n = G (i k r - 1) / r^2 (x - s) . n,  i k r = -kim r + i kre r
+    const double dn = (dx * nrm[0] + dy * nrm[1] + dz * nrm[2]) / (r * r);
+    const double cr = -kim * r - 1.0, ci = kre * r;
+    qr += (vr * cr - vi * ci) * dn;
+    qi += (vr * ci + vi * cr) * dn;
+}
+
+// p_inc and dp_inc/dn of field f at x (normal nrm)
+__device__ void incident(const IncDev &I, int f, const double *x, const double *nrm, double &pr, double &pi,
+                         double &qr, double &qi)
+{
+    pr = pi = qr = qi = 0.0;
+    if (I.kind == BEM_PLANE_WAVE) {
+        const double *P = I.params + 5 * int64_t(f);
+        const double dx = P[0] * x[0] + P[1] * x[1] + P[2] * x[2];
+        const double dn = P[0] * nrm[0] + P[1] * nrm[1] + P[2] * nrm[2];
+        double sn, cs;
+        sincos(I.k0re * dx, &sn, &cs);
+        const double e = exp(-I.k0im * dx);
+        const double er = e * cs, ei = e * sn;
+        pr = P[3] * er - P[4] * ei;
+        pi = P[3] * ei + P[4] * er;
+        // i k0 (d.n) p
+        const double kr = -I.k0im * dn, ki = I.k0re * dn;
+        qr = kr * pr - ki * pi;
+        qi = kr * pi + ki * pr;
+    } else if (I.kind == BEM_POINT_SOURCES) {
+        for (int64_t s = 0; s < I.n_params; ++s) {
+            const double *P = I.params + 6 * s;
+            if (int(P[5]) != f) continue;
+            monopole(x, nrm, P, P[3], P[4], I.k0re, I.k0im, pr, pi, qr, qi);
+        }
+    } else {
+        // 3-point Gauss-Legendre radii on [0,1] and 8 equal angles
+        const double gx[3] = {0.11270166537925831148, 0.5, 0.88729833462074168852};
+        const double gw[3] = {0.27777777777777777778, 0.44444444444444444444, 0.27777777777777777778};
+        for (int64_t s = 0; s < I.n_params; ++s) {
+            const double *P = I.params + 10 * s;
+            if (int(P[9]) != f) continue;
+            const double *c = P, *nv = P + 3, a = P[6];
+            // orthonormal in-plane basis (e1, e2) of the disc
+            double ax[3] = {0, 0, 0};
+            const double anx = fabs(nv[0]), any = fabs(nv[1]), anz = fabs(nv[2]);
+            ax[(anx <= any && anx <= anz) ? 0 : (any <= anz ? 1 : 2)] = 1.0;
+            double e1[3] = {nv[1] * ax[2] - nv[2] * ax[1], nv[2] * ax[0] - nv[0] * ax[2], nv[0] * ax[1] - nv[1] * ax[0]};
+            const double l1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+            for (int d = 0; d < 3; ++d) e1[d] /= l1;
+            const double e2[3] = {nv[1] * e1[2] - nv[2] * e1[1], nv[2] * e1[0] - nv[0] * e1[2], nv[0] * e1[1] - nv[1] * e1[0]};
+            // amplitude (-i k0 / 2 pi) * 4 pi * w_r * rho * dtheta * A  (G carries 1/(4 pi))
+            const double kr = I.k0re, ki = I.k0im;
+            const double br = 2.0 * ki, bi = -2.0 * kr;   // -2 i k0
+            for (int i = 0; i < 3; ++i) {
+                const double rho = a * gx[i];
+                const double wgt = a * gw[i] * rho * (2.0 * PI_D / 8.0);
+                for (int j = 0; j < 8; ++j) {
+                    const double th = 2.0 * PI_D * j / 8.0;
+                    const double ct = cos(th), st = sin(th);
+                    double src[3];
+                    for (int d = 0; d < 3; ++d) src[d] = c[d] + rho * (ct * e1[d] + st * e2[d]);
+                    const double amr = wgt * (br * P[7] - bi * P[8]), ami = wgt * (br * P[8] + bi * P[7]);
+                    monopole(x, nrm, src, amr, ami, I.k0re, I.k0im, pr, pi, qr, qi);
+                }
+            }
+        }
+    }
+}
+
+// one thread per (vertex, field)
+__global__ void k_rhs(IncDev I, const double *__restrict__ verts, const int32_t *__restrict__ tris,
+                      const double *__restrict__ area, const double *__restrict__ normal,
+                      const int32_t *__restrict__ v2t_ptr, const int32_t *__restrict__ v2t,
+                      const int32_t *__restrict__ rowD, const int32_t *__restrict__ rowN, int64_t NV, int64_t N,
+                      double2 *__restrict__ b)
+{
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int f = blockIdx.y;
+    if (g >= NV) return;
+    double bDr = 0, bDi = 0, bNr = 0, bNi = 0;
+    for (int32_t k = v2t_ptr[g]; k < v2t_ptr[g + 1]; ++k) {
+        const int64_t t = v2t[k] / 3;
+        const int a = v2t[k] - 3 * int(t);
+        double P[3][3];
+        for (int c = 0; c < 3; ++c)
+            for (int d = 0; d < 3; ++d) P[c][d] = verts[3 * int64_t(tris[3 * t + c]) + d];
+        const double *n = normal + 3 * t;
+        for (int q = 0; q < 6; ++q) {
+            double x[3];
+            for (int d = 0; d < 3; ++d) x[d] = f_bary[q][0] * P[0][d] + f_bary[q][1] * P[1][d] + f_bary[q][2] * P[2][d];
+            double pr, pi, qr, qi;
+            incident(I, f, x, n, pr, pi, qr, qi);
+            const double w = area[t] * f_wq[q] * f_bary[q][a];
+            bDr += w * pr; bDi += w * pi;
+            bNr += w * qr; bNi += w * qi;
+        }
+    }
+    b[int64_t(f) * N + rowD[g]] = make_double2(bDr, bDi);
+    b[int64_t(f) * N + rowN[g]] = make_double2(bNr, bNi);
+}
+
+static IncDev upload_incident(bem_problem &p, const bem_incident &inc, double **d_params)
+{
+    int64_t cols = inc.kind == BEM_PLANE_WAVE ? 5 : (inc.kind == BEM_POINT_SOURCES ? 6 : 10);
+    int64_t rows = inc.kind == BEM_PLANE_WAVE ? inc.n_fields : inc.n_params;
+    std::vector<double> h(inc.params, inc.params + rows * cols);
+    if (inc.kind == BEM_PLANE_WAVE)
+        for (int64_t f = 0; f < rows; ++f) {
+            double *d = &h[5 * f];
+            const double l = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            for (int c = 0; c < 3; ++c) d[c] /= l;
+        }
+    if (inc.kind == BEM_PISTON_ARRAY)
+        for (int64_t s = 0; s < rows; ++s) {
+            double *d = &h[10 * s + 3];
+            const double l = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            for (int c = 0; c < 3; ++c) d[c] /= l;
+        }
+    BEM_HIP(hipMalloc(d_params, std::max<size_t>(1, h.size()) * sizeof(double)));
+    BEM_HIP(hipMemcpyAsync(*d_params, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, p.stream));
+    IncDev I;
+    I.kind = inc.kind;
+    I.n_fields = inc.n_fields;
+    I.n_params = rows;
+    I.params = *d_params;
+    I.k0re = p.k0re;
+    I.k0im = p.k0im;
+    return I;
+}
+
+void launch_rhs(bem_problem &p, const bem_incident &inc, double2 *b)
+{
+    double *d_params = nullptr;
+    IncDev I = upload_incident(p, inc, &d_params);
+    const int B = 128;
+    k_rhs<<<dim3(unsigned((p.NV + B - 1) / B), unsigned(inc.n_fields)), dim3(B), 0, p.stream>>>(
+        I, p.d_verts, p.d_tris, p.d_area, p.d_normal, p.d_v2t_ptr, p.d_v2t, p.d_rowD, p.d_rowN, p.NV, p.N, b);
+    BEM_HIP(hipGetLastError());
+    BEM_HIP(hipStreamSynchronize(p.stream));
+    (void)hipFree(d_params);
+}
+
+struct DomDev {
+    long long v_off, t_off, nt, nv;
+    double kre, kim, rho;
+};
+
+// one thread per point: region by winding numbers, then the potentials (all fields)
+__global__ void k_field(IncDev I, int has_inc, const DomDev *__restrict__ doms, int n_dom, double k0re, double k0im,
+                        double rho0, const double *__restrict__ verts, const int32_t *__restrict__ tris,
+                        const double *__restrict__ area, const double *__restrict__ normal,
+                        const int32_t *__restrict__ rowD, const int32_t *__restrict__ rowN,
+                        const double2 *__restrict__ u, int64_t N, int n_fields, const double *__restrict__ pts,
+                        int64_t np, double2 *__restrict__ field, int32_t *__restrict__ region)
+{
+    const int64_t ip = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (ip >= np) return;
+    const double x[3] = {pts[3 * ip], pts[3 * ip + 1], pts[3 * ip + 2]};
+    int reg = 0;
+    for (int j = 0; j < n_dom; ++j) {
+        double s = 0.0;
+        for (long long t = doms[j].t_off; t < doms[j].t_off + doms[j].nt; ++t) {
+            double a[3], b[3], c[3];
+            for (int d = 0; d < 3; ++d) {
+                a[d] = verts[3 * int64_t(tris[3 * t]) + d] - x[d];
+                b[d] = verts[3 * int64_t(tris[3 * t + 1]) + d] - x[d];
+                c[d] = verts[3 * int64_t(tris[3 * t + 2]) + d] - x[d];
+            }
+            const double la = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+            const double lb = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+            const double lc = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+            const double num = a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) +
+                               a[2] * (b[0] * c[1] - b[1] * c[0]);
+            const double den = la * lb * lc + (a[0] * b[0] + a[1] * b[1] + a[2] * b[2]) * lc +
+                               (a[0] * c[0] + a[1] * c[1] + a[2] * c[2]) * lb + (b[0] * c[0] + b[1] * c[1] + b[2] * c[2]) * la;
+            s += 2.0 * atan2(num, den);
+        }
+        if (rint(s / (4.0 * PI_D)) == 1.0) reg = j + 1;
+    }
+    region[ip] = reg;
+    const int j0 = reg == 0 ? 0 : reg - 1, j1 = reg == 0 ? n_dom : reg;
+    const double kre = reg == 0 ? k0re : doms[reg - 1].kre, kim = reg == 0 ? k0im : doms[reg - 1].kim;
+    const double sN = reg == 0 ? -1.0 : doms[reg - 1].rho / rho0;   // coefficient of SL u_N
+    const double sD = reg == 0 ? 1.0 : -1.0;                         // coefficient of DL u_D
+    for (int f = 0; f < n_fields; ++f) {
+        double pr = 0.0, pim = 0.0;
+        if (reg == 0 && has_inc) {
+            const double nz[3] = {0, 0, 1};
+            double qr, qi;
+            incident(I, f, x, nz, pr, pim, qr, qi);
+        }
+        const double2 *uf = u + int64_t(f) * N;
+        for (int j = j0; j < j1; ++j)
+            for (long long t = doms[j].t_off; t < doms[j].t_off + doms[j].nt; ++t) {
+                double P[3][3];
+                double2 uD[3], uN[3];
+                for (int c = 0; c < 3; ++c) {
+                    const int32_t g = tris[3 * t + c];
+                    for (int d = 0; d < 3; ++d) P[c][d] = verts[3 * int64_t(g) + d];
+                    uD[c] = uf[rowD[g]];
+                    uN[c] = uf[rowN[g]];
+                }
+                const double *n = normal + 3 * t;
+                for (int q = 0; q < 6; ++q) {
+                    double y[3];
+                    for (int d = 0; d < 3; ++d)
+                        y[d] = f_bary[q][0] * P[0][d] + f_bary[q][1] * P[1][d] + f_bary[q][2] * P[2][d];
+                    const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+                    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+                    double sn, cs;
+                    sincos(kre * r, &sn, &cs);
+                    const double e = exp(-kim * r) / (4.0 * PI_D * r);
+                    const double gr = e * cs, gi = e * sn;
+                    const double a1 = 1.0 + kim * r, b1 = -kre * r, ir2 = 1.0 / (r * r);
+                    const double dn = (dx * n[0] + dy * n[1] + dz * n[2]) * ir2;
+                    const double fr = (gr * a1 - gi * b1) * dn, fi = (gr * b1 + gi * a1) * dn;   // dG/dn_y
+                    double dr = 0, di = 0, nr = 0, ni = 0;
+                    for (int c = 0; c < 3; ++c) {
+                        dr += f_bary[q][c] * uD[c].x; di += f_bary[q][c] * uD[c].y;
+                        nr += f_bary[q][c] * uN[c].x; ni += f_bary[q][c] * uN[c].y;
+                    }
+                    const double w = area[t] * f_wq[q];
+                    pr += w * (sD * (fr * dr - fi * di) + sN * (gr * nr - gi * ni));
+                    pim += w * (sD * (fr * di + fi * dr) + sN * (gr * ni + gi * nr));
+                }
+            }
+        field[int64_t(f) * np + ip] = make_double2(pr, pim);
+    }
+}
+
+void launch_field(bem_problem &p, const double2 *u, const bem_incident *inc, int n_fields, const double *pts,
+                  int64_t np, double2 *field, int32_t *region)
+{
+    double *d_params = nullptr;
+    IncDev I{};
+    if (inc) I = upload_incident(p, *inc, &d_params);
+    std::vector<DomDev> hd;
+    for (const auto &d : p.doms) hd.push_back(DomDev{d.v_off, d.t_off, d.nt, d.nv, d.kre, d.kim, d.rho});
+    DomDev *d_doms = nullptr;
+    BEM_HIP(hipMalloc(&d_doms, hd.size() * sizeof(DomDev)));
+    BEM_HIP(hipMemcpyAsync(d_doms, hd.data(), hd.size() * sizeof(DomDev), hipMemcpyHostToDevice, p.stream));
+    const int B = 128;
+    if (np > 0) {
+        k_field<<<dim3(unsigned((np + B - 1) / B)), dim3(B), 0, p.stream>>>(
+            I, inc ? 1 : 0, d_doms, int(hd.size()), p.k0re, p.k0im, p.rho0, p.d_verts, p.d_tris, p.d_area, p.d_normal,
+            p.d_rowD, p.d_rowN, u, p.N, n_fields, pts, np, field, region);
+        BEM_HIP(hipGetLastError());
+    }
+    BEM_HIP(hipStreamSynchronize(p.stream));
+    (void)hipFree(d_doms);
+    if (d_params) (void)hipFree(d_params);
+}
+
+}  // namespace bem

@@ -1,0 +1,112 @@
+// FP64 complex vector kernels for the GMRES driver: several inner products
+// against one vector (two-stage, fixed-order reduction), multi-axpy and
+// scaling.  Vectors are double2 (re, im).
+#include "bem_internal.h"
+
+namespace bem {
+
+constexpr int LA_BLOCK = 256;
+
+// partials[k][blk] = sum over the block's chunk of conj(V_k[i]) w[i]
+__global__ __launch_bounds__(LA_BLOCK) void k_zdot_partial(const double2 *__restrict__ V, int64_t ld,
+                                                           const double2 *__restrict__ w, int64_t n, int nblk,
+                                                           double2 *__restrict__ partials)
+{
+    __shared__ double sr[LA_BLOCK], si[LA_BLOCK];
+    const int k = blockIdx.y, blk = blockIdx.x, tid = threadIdx.x;
+    const double2 *v = V + int64_t(k) * ld;
+    double ar = 0, ai = 0;
+    for (int64_t i = int64_t(blk) * LA_BLOCK + tid; i < n; i += int64_t(nblk) * LA_BLOCK) {
+        const double2 a = v[i], b = w[i];
+        ar += a.x * b.x + a.y * b.y;
+        ai += a.x * b.y - a.y * b.x;
+    }
+    sr[tid] = ar;
+    si[tid] = ai;
+    __syncthreads();
+    for (int s = LA_BLOCK / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            sr[tid] += sr[tid + s];
+            si[tid] += si[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) partials[int64_t(k) * nblk + blk] = make_double2(sr[0], si[0]);
+}
+
+__global__ void k_zdot_final(const double2 *__restrict__ partials, int nblk, int nvec, double2 *__restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nvec) return;
+    double r = 0, im = 0;
+    for (int b = 0; b < nblk; ++b) {
+        r += partials[int64_t(k) * nblk + b].x;
+        im += partials[int64_t(k) * nblk + b].y;
+    }
+    out[k] = make_double2(r, im);
+}
+
+void zdot_multi(hipStream_t s, const double2 *V, int64_t ld, int nvec, const double2 *w, int64_t n,
+                double2 *partials, int nblk, double2 *out_dev)
+{
+    if (nvec <= 0) return;
+    k_zdot_partial<<<dim3(unsigned(nblk), unsigned(nvec)), dim3(LA_BLOCK), 0, s>>>(V, ld, w, n, nblk, partials);
+    BEM_HIP(hipGetLastError());
+    k_zdot_final<<<dim3(unsigned((nvec + 63) / 64)), dim3(64), 0, s>>>(partials, nblk, nvec, out_dev);
+    BEM_HIP(hipGetLastError());
+}
+
+// w += sign * sum_k h_k V_k
+__global__ void k_zaxpy_multi(const double2 *__restrict__ V, int64_t ld, int nvec, const double2 *__restrict__ h,
+                              double2 *__restrict__ w, int64_t n, double sign)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double r = 0, im = 0;
+    for (int k = 0; k < nvec; ++k) {
+        const double2 a = V[int64_t(k) * ld + i], c = h[k];
+        r += c.x * a.x - c.y * a.y;
+        im += c.x * a.y + c.y * a.x;
+    }
+    w[i] = make_double2(w[i].x + sign * r, w[i].y + sign * im);
+}
+
+void zaxpy_multi(hipStream_t s, const double2 *V, int64_t ld, int nvec, const double2 *h_dev, double2 *w, int64_t n,
+                 double sign)
+{
+    if (nvec <= 0 || n <= 0) return;
+    k_zaxpy_multi<<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, s>>>(V, ld, nvec, h_dev, w, n, sign);
+    BEM_HIP(hipGetLastError());
+}
+
+__global__ void k_zscale_copy(const double2 *__restrict__ x, double2 *__restrict__ y, int64_t n, double2 a)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double2 v = x[i];
+    y[i] = make_double2(a.x * v.x - a.y * v.y, a.x * v.y + a.y * v.x);
+}
+
+void zscale_copy(hipStream_t s, const double2 *x, double2 *y, int64_t n, double2 a)
+{
+    if (n <= 0) return;
+    k_zscale_copy<<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, s>>>(x, y, n, a);
+    BEM_HIP(hipGetLastError());
+}
+
+__global__ void k_zaxpy(double2 *__restrict__ y, const double2 *__restrict__ x, int64_t n, double2 a)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double2 v = x[i];
+    y[i] = make_double2(y[i].x + a.x * v.x - a.y * v.y, y[i].y + a.x * v.y + a.y * v.x);
+}
+
+void zaxpy(hipStream_t s, double2 *y, const double2 *x, int64_t n, double2 a)
+{
+    if (n <= 0) return;
+    k_zaxpy<<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, s>>>(y, x, n, a);
+    BEM_HIP(hipGetLastError());
+}
+
+}  // namespace bem

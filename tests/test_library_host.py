@@ -1,0 +1,97 @@
+"""Host-side behaviour of the HIP library that needs no GPU.
+
+The shared library loads without a device; argument and mesh validation run
+before any HIP call, so these error paths are exercised on the CPU.
+"""
+from __future__ import annotations
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+from bem_inputs import configs, meshes
+
+pytestmark = pytest.mark.cpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bem():
+    return pytest.importorskip("paper_1910_01011_amd")
+
+
+def test_library_exports_every_declared_symbol():
+    bem = _bem()
+    header = open(os.path.join(ROOT, "include", "bem.h")).read()
+    declared = set(re.findall(r"^\s*(?:bem_status|int64_t|void|const char \*)\s*(bem_\w+)\s*\(", header, re.M))
+    assert declared, "no declarations parsed"
+    for name in declared:
+        assert hasattr(bem._L, name), name
+    assert declared == set(bem.EXPORTED)
+
+
+def _dom(v, t, k=2.0, rho=1.0):
+    return configs.Domain(np.asarray(v, dtype=np.float64), np.asarray(t, dtype=np.int32), complex(k), rho)
+
+
+def _expect(status, domains, k0=2.0, rho0=1.0):
+    bem = _bem()
+    with pytest.raises(bem.BemError) as e:
+        bem.Problem(domains, k0, rho0)
+    assert e.value.status == status, str(e.value)
+
+
+def test_argument_errors():
+    bem = _bem()
+    v, t = meshes.icosphere(1)
+    _expect(bem.BEM_ERR_INVALID_ARG, [])
+    _expect(bem.BEM_ERR_INVALID_ARG, [_dom(v, t)], k0=complex(2.0, -0.1))
+    _expect(bem.BEM_ERR_INVALID_ARG, [_dom(v, t)], rho0=0.0)
+    _expect(bem.BEM_ERR_INVALID_ARG, [_dom(v, t, rho=-1.0)])
+    _expect(bem.BEM_ERR_INVALID_ARG, [_dom(v, t, k=complex(2.0, -1.0))])
+    vv = v.copy()
+    vv[3, 1] = np.nan
+    _expect(bem.BEM_ERR_INVALID_ARG, [_dom(vv, t)])
+    with pytest.raises(bem.BemError) as e:
+        bem.Problem([_dom(v, t)], 2.0, 1.0, ss_order=40)
+    assert e.value.status == bem.BEM_ERR_INVALID_ARG
+
+
+def test_mesh_errors():
+    bem = _bem()
+    v, t = meshes.icosphere(1)
+    _expect(bem.BEM_ERR_MESH, [_dom(v, t[:, ::-1])])                    # inward normals
+    tf = t.copy()
+    tf[5] = tf[5, ::-1]
+    _expect(bem.BEM_ERR_MESH, [_dom(v, tf)])                           # one flipped triangle
+    _expect(bem.BEM_ERR_MESH, [_dom(v, t[1:])])                        # open surface
+    tb = t.copy()
+    tb[0, 0] = v.shape[0]
+    _expect(bem.BEM_ERR_MESH, [_dom(v, tb)])                           # index out of range
+    tr = t.copy()
+    tr[0, 1] = tr[0, 0]
+    _expect(bem.BEM_ERR_MESH, [_dom(v, tr)])                           # repeated vertex
+    vz = v.copy()
+    a, b, c = t[0]
+    vz[c] = 0.5 * (vz[a] + vz[b])
+    _expect(bem.BEM_ERR_MESH, [_dom(vz, t)])                           # zero-area triangle
+    _expect(bem.BEM_ERR_MESH, [_dom(v, t), _dom(v.copy(), t.copy())])  # touching domains
+
+
+def test_unsupported_options():
+    bem = _bem()
+    v, t = meshes.icosphere(1)
+    with pytest.raises(bem.BemError) as e:
+        bem.Problem([_dom(v, t)], 2.0, 1.0, mode=bem.BEM_ASSEMBLED_SPLIT_BF16 + 7)
+    assert e.value.status in (bem.BEM_ERR_UNSUPPORTED, bem.BEM_ERR_INVALID_ARG)
+
+
+def test_footprint_grows_with_rhs_and_restart():
+    bem = _bem()
+    prob = configs.config1()
+    a = bem.footprint_bytes(prob.domains, 1, 30)
+    b = bem.footprint_bytes(prob.domains, 8, 30)
+    c = bem.footprint_bytes(prob.domains, 8, 100)
+    assert 0 < a < b < c
