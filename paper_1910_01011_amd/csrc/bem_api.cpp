@@ -52,7 +52,8 @@ void free_problem(bem_problem *p)
     if (!p) return;
     void *ptrs[] = {p->d_verts, p->d_tris, p->d_rowD, p->d_rowN, p->d_area, p->d_normal, p->d_curl, p->d_pts,
                     p->d_tnrm, p->d_v2t_ptr, p->d_v2t, p->d_pass, p->d_work, p->d_trial, p->d_part, p->d_pot,
-                    p->d_cptr, p->d_ccol, p->d_cval, p->d_x, p->d_y};
+                    p->d_cptr, p->d_ccol, p->d_cval, p->d_x, p->d_y, p->d_A, p->d_Ahi, p->d_Alo,
+                    p->d_gx, p->d_gc};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (auto &e : p->ev)
@@ -158,9 +159,60 @@ void apply_one(bem_problem &p, const double2 *x, double2 *y, int parts, bool rec
     }
 }
 
+// y = A x with the dense matrix (assembled modes); events as in apply_one.
+void apply_dense_one(bem_problem &p, const double2 *x, double2 *y, bool record)
+{
+    if (record) {
+        BEM_HIP(hipEventRecord(p.ev[0], p.stream));
+        BEM_HIP(hipEventRecord(p.ev[1], p.stream));
+    }
+    bem::launch_gemv(p, x, y);
+    if (record) {
+        BEM_HIP(hipEventRecord(p.ev[2], p.stream));
+        BEM_HIP(hipEventRecord(p.ev[3], p.stream));
+        BEM_HIP(hipEventRecord(p.ev[4], p.stream));
+        p.timed = true;
+    }
+}
+
+// Y = A X for several right-hand sides in one GEMM (assembled modes).
+void apply_dense_multi(bem_problem &p, const double2 *X, double2 *Y, int n_rhs, bool bf16)
+{
+    const bem::GemmPlan g = bem::gemm_plan(p, n_rhs, bf16);
+    if (p.gx_bytes < g.bytes_x) {
+        if (p.d_gx) (void)hipFree(p.d_gx);
+        p.d_gx = nullptr;
+        p.gx_bytes = 0;
+        BEM_HIP(hipMalloc(&p.d_gx, g.bytes_x));
+        p.gx_bytes = g.bytes_x;
+    }
+    if (p.gc_bytes < g.bytes_c) {
+        if (p.d_gc) (void)hipFree(p.d_gc);
+        p.d_gc = nullptr;
+        p.gc_bytes = 0;
+        BEM_HIP(hipMalloc(&p.d_gc, g.bytes_c));
+        p.gc_bytes = g.bytes_c;
+    }
+    BEM_HIP(hipEventRecord(p.ev[0], p.stream));
+    p.timed_gemm = true;
+    bem::launch_gemm(p, g, X, Y, p.d_gx, p.d_gc);
+    BEM_HIP(hipEventRecord(p.ev[3], p.stream));
+    BEM_HIP(hipEventRecord(p.ev[4], p.stream));
+    p.timed = true;
+}
+
 void apply_device(bem_problem &p, const double2 *x, double2 *y, int n_rhs, int parts)
 {
-    for (int r = 0; r < n_rhs; ++r) apply_one(p, x + int64_t(r) * p.N, y + int64_t(r) * p.N, parts, r == n_rhs - 1);
+    if (p.mode != BEM_OTF && n_rhs > 1) {
+        apply_dense_multi(p, x, y, n_rhs, p.mode == BEM_ASSEMBLED_SPLIT_BF16);
+        return;
+    }
+    for (int r = 0; r < n_rhs; ++r) {
+        if (p.mode != BEM_OTF)
+            apply_dense_one(p, x + int64_t(r) * p.N, y + int64_t(r) * p.N, r == n_rhs - 1);
+        else
+            apply_one(p, x + int64_t(r) * p.N, y + int64_t(r) * p.N, parts, r == n_rhs - 1);
+    }
 }
 
 bem_solve_opts default_solve_opts()
@@ -324,7 +376,8 @@ bem_status bem_assemble(const bem_domain *domains, int32_t n_domains, bem_comple
     if (o.ss_order == 0) o.ss_order = 6;
     if (o.far_points != 6) return fail(BEM_ERR_UNSUPPORTED, "only the 6-point far rule is implemented");
     if (o.ss_order < 1 || o.ss_order > 16) return fail(BEM_ERR_INVALID_ARG, "ss_order must be in 1..16");
-    if (o.mode != BEM_OTF) return fail(BEM_ERR_UNSUPPORTED, "assembled modes are not available in this build");
+    if (o.mode != BEM_OTF && o.mode != BEM_ASSEMBLED_FP32 && o.mode != BEM_ASSEMBLED_SPLIT_BF16)
+        return fail(BEM_ERR_INVALID_ARG, "unknown operator mode");
     if (k0.re <= 0) return fail(BEM_ERR_INVALID_ARG, "Re k0 must be positive");
     for (int j = 0; j < n_domains; ++j) {
         const bem_domain &d = domains[j];
@@ -407,6 +460,11 @@ bem_status bem_assemble(const bem_domain *domains, int32_t n_domains, bem_comple
         std::vector<bem::SingularItem> items;
         bem::touching_pairs(*p, items);
         bem::run_singular(*p, items);
+        if (p->mode != BEM_OTF) {
+            dev_alloc(&p->d_A, size_t(p->N) * size_t(p->N));
+            bem::launch_assemble_dense(*p);
+            if (p->mode == BEM_ASSEMBLED_SPLIT_BF16) bem::split_matrix_bf16(*p);
+        }
         BEM_HIP(hipStreamSynchronize(p->stream));
         return BEM_OK;
     });
@@ -426,6 +484,8 @@ bem_status bem_apply_parts(bem_problem *p, const bem_complex *x, bem_complex *y,
 {
     if (!p || !x || !y || n_rhs < 0) return fail(BEM_ERR_INVALID_ARG, "bem_apply: bad arguments");
     if (parts < 0 || parts > 3) return fail(BEM_ERR_INVALID_ARG, "bem_apply: parts must be 0..3");
+    if (p->mode != BEM_OTF && parts != 3)
+        return fail(BEM_ERR_UNSUPPORTED, "bem_apply: an assembled matrix holds both parts together");
     if (n_rhs == 0) return BEM_OK;
     return guarded([&]() -> bem_status {
         BEM_HIP(hipSetDevice(p->device));

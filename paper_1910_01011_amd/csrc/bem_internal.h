@@ -66,6 +66,17 @@ struct SingularItem {
     int pt[3], ps[3];
 };
 
+// Launch plan of the multi-right-hand-side GEMM (k_gemm.hip).
+struct GemmPlan {
+    int R;             // right-hand sides
+    bool bf16;         // split-BF16 3-term (true) or FP32 MFMA (false)
+    int64_t Kp, Np;    // padded K (= 2n) and N (= 2R)
+    int n_m, n_n, n_s; // m-tiles, n-tiles, K slices
+    int64_t kslice;
+    int n_wg;
+    size_t bytes_x, bytes_c;
+};
+
 struct DomInfo {
     int64_t nv, nt;        // vertices / triangles of the domain
     int64_t v_off, t_off;  // offsets in the global vertex / triangle arrays
@@ -123,6 +134,15 @@ struct bem_problem {
     double2 *d_cval = nullptr;      // [nnz][4]
     int64_t nnz = 0;
 
+    // assembled mode: dense complex64 matrix, row-major [N][N]; BF16 planes
+    // of its real view [N][2N] (hi and lo) for the split-BF16 GEMM
+    float2 *d_A = nullptr;
+    uint16_t *d_Ahi = nullptr, *d_Alo = nullptr;
+    void *d_gx = nullptr;           // packed right-hand sides of the GEMM
+    float *d_gc = nullptr;          // K-slice partial products of the GEMM
+    size_t gx_bytes = 0, gc_bytes = 0;
+    bool timed_gemm = false;
+
     // scratch vectors
     double2 *d_x = nullptr, *d_y = nullptr;
     int64_t scratch_rhs = 0;
@@ -164,6 +184,11 @@ void launch_gather(bem_problem &p, const double2 *x);
 void launch_pairs(bem_problem &p);
 void launch_reduce(bem_problem &p);
 void launch_scatter(bem_problem &p, const double2 *x, double2 *y, int parts);
+void launch_assemble_dense(bem_problem &p);
+void launch_gemv(bem_problem &p, const double2 *x, double2 *y);
+void split_matrix_bf16(bem_problem &p);
+GemmPlan gemm_plan(const bem_problem &p, int R, bool bf16);
+void launch_gemm(bem_problem &p, const GemmPlan &g, const double2 *X, double2 *Y, void *xbuf, float *cbuf);
 void run_singular(bem_problem &p, const std::vector<SingularItem> &items);
 
 // FP64 complex vector helpers for GMRES (k_linalg.hip)

@@ -1,0 +1,256 @@
+// Assembled mode: the dense complex64 PMCHWT matrix and its single-vector apply.
+//
+// Entry (row g, column h) of the four blocks (DD, DN, ND, NN) is the sum over
+// the quadrature points q of the triangles at vertex g and p of the triangles
+// at vertex h of the same pair integrands as the on-the-fly kernel, weighted by
+// w_q lambda_g(q) w_p lambda_h(p) (curl term: w_q w_p curl_g . curl_h), for the
+// exterior wavenumber and, when g and h lie on the same boundary, the interior
+// one (paper eqs. Form1_calderon_sys_int_ptot and Form2_calderon_sys_simp3).
+// Point-with-itself pairs are skipped (r = 0); the FP64 singular CSR is added
+// afterwards, as in the on-the-fly apply.  Row-major storage: A[r * n + c],
+// complex64 interleaved.
+#include <cmath>
+#include <vector>
+
+#include "bem_internal.h"
+
+namespace bem {
+
+__constant__ double d_bary[6][3] = {
+    {0.10810301816807022736, 0.44594849091596488632, 0.44594849091596488632},
+    {0.44594849091596488632, 0.10810301816807022736, 0.44594849091596488632},
+    {0.44594849091596488632, 0.44594849091596488632, 0.10810301816807022736},
+    {0.81684757298045851308, 0.091576213509770743460, 0.091576213509770743460},
+    {0.091576213509770743460, 0.81684757298045851308, 0.091576213509770743460},
+    {0.091576213509770743460, 0.091576213509770743460, 0.81684757298045851308}};
+__constant__ double d_wq[6] = {0.22338158967801146570, 0.22338158967801146570, 0.22338158967801146570,
+                               0.10995174365532186764, 0.10995174365532186764, 0.10995174365532186764};
+
+// Per (vertex, incident triangle corner, point) record, 3 x float4:
+//   r0 = (x, w lambda_a(x) / (4 pi))   r1 = (n, w / (4 pi))   r2 = (curl lambda_a, 0)
+// grouped by vertex: records [6 v2t_ptr[g], 6 v2t_ptr[g+1]).
+__global__ void k_vertex_points(const int32_t *__restrict__ v2t, int64_t n_corner, const double *__restrict__ area,
+                                const double *__restrict__ normal, const double *__restrict__ curl,
+                                const float *__restrict__ pts, int64_t M, float4 *__restrict__ rec)
+{
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= 6 * n_corner) return;
+    const int64_t c = k / 6;
+    const int q = int(k - 6 * c);
+    const int32_t tc = v2t[c];
+    const int64_t t = tc / 3;
+    const int a = tc - 3 * int(t);
+    const int64_t i = 6 * t + q;
+    const double w = area[t] * d_wq[q] * 0.079577471545947667884;
+    rec[3 * k] = make_float4(pts[i], pts[M + i], pts[2 * M + i], float(w * d_bary[q][a]));
+    rec[3 * k + 1] = make_float4(float(normal[3 * t]), float(normal[3 * t + 1]), float(normal[3 * t + 2]), float(w));
+    rec[3 * k + 2] = make_float4(float(curl[9 * t + 3 * a]), float(curl[9 * t + 3 * a + 1]),
+                                 float(curl[9 * t + 3 * a + 2]), 0.0f);
+}
+
+struct DenseDom {
+    float k, k2pi, kim, sV, sW, k2re, k2im, pad;
+};
+
+struct Acc4 {
+    float vr, vi, kr, ki, pr, pi, wr, wi;
+};
+
+template <bool ATT>
+__device__ __forceinline__ void dense_pair(float r, float rinv, float ww, float wcc, float tK, float tKp, float nn,
+                                           float k, float k2pi, float kim, float k2re, float k2im, Acc4 &A)
+{
+    float ph = r * k2pi;
+    ph = ph - rintf(ph);
+    float gr = __builtin_amdgcn_cosf(ph) * rinv, gi = __builtin_amdgcn_sinf(ph) * rinv;
+    const float kr = r * k, rinv2 = rinv * rinv;
+    float fr, fi;
+    if (ATT) {
+        const float damp = __expf(-kim * r);
+        gr *= damp;
+        gi *= damp;
+        const float re1 = fmaf(kim, r, 1.0f);
+        fr = fmaf(gr, re1, gi * kr) * rinv2;
+        fi = fmaf(gi, re1, -gr * kr) * rinv2;
+    } else {
+        fr = fmaf(gi, kr, gr) * rinv2;
+        fi = fmaf(-gr, kr, gi) * rinv2;
+    }
+    A.vr = fmaf(ww, gr, A.vr);
+    A.vi = fmaf(ww, gi, A.vi);
+    A.kr = fmaf(ww * tK, fr, A.kr);
+    A.ki = fmaf(ww * tK, fi, A.ki);
+    A.pr = fmaf(-ww * tKp, fr, A.pr);
+    A.pi = fmaf(-ww * tKp, fi, A.pi);
+    // W: G [w w' curl.curl' - k^2 (n.n') w lambda w' lambda']   (complex k^2)
+    const float cr = fmaf(-k2re * nn, ww, wcc), ci = -k2im * nn * ww;
+    A.wr = fmaf(gr, cr, fmaf(-gi, ci, A.wr));
+    A.wi = fmaf(gr, ci, fmaf(gi, cr, A.wi));
+}
+
+template <bool ATT>
+__global__ __launch_bounds__(256) void k_assemble_dense(const float4 *__restrict__ rec, const int32_t *__restrict__ v2t_ptr,
+                                                        const int32_t *__restrict__ vdom, const DenseDom *__restrict__ doms,
+                                                        DenseDom ext, const int32_t *__restrict__ rowD,
+                                                        const int32_t *__restrict__ rowN, int64_t NV, int64_t n,
+                                                        float2 *__restrict__ A)
+{
+    const int64_t g = int64_t(blockIdx.y) * 16 + threadIdx.y;
+    const int64_t h = int64_t(blockIdx.x) * 16 + threadIdx.x;
+    if (g >= NV || h >= NV) return;
+    const int dg = vdom[g];
+    const bool same = dg == vdom[h];
+    const DenseDom in = doms[dg];
+    Acc4 E = {0, 0, 0, 0, 0, 0, 0, 0}, I = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int32_t q0 = 6 * v2t_ptr[g], q1 = 6 * v2t_ptr[g + 1];
+    const int32_t p0 = 6 * v2t_ptr[h], p1 = 6 * v2t_ptr[h + 1];
+    for (int32_t kq = q0; kq < q1; ++kq) {
+        const float4 T0 = rec[3 * kq], T1 = rec[3 * kq + 1], T2 = rec[3 * kq + 2];
+        for (int32_t kp = p0; kp < p1; ++kp) {
+            const float4 S0 = rec[3 * kp], S1 = rec[3 * kp + 1], S2 = rec[3 * kp + 2];
+            const float dx = T0.x - S0.x, dy = T0.y - S0.y, dz = T0.z - S0.z;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            if (!(r2 > 0.0f)) continue;   // point with itself: singular correction
+            const float rinv = __builtin_amdgcn_rsqf(r2);
+            const float r = r2 * rinv;
+            // the factor 1/(4 pi) sits in the test weights only
+            const float ww = T0.w * S0.w * 12.566370614359172954f;
+            const float wcc = T1.w * S1.w * 12.566370614359172954f * fmaf(T2.x, S2.x, fmaf(T2.y, S2.y, T2.z * S2.z));
+            const float tK = fmaf(dx, S1.x, fmaf(dy, S1.y, dz * S1.z));
+            const float tKp = fmaf(dx, T1.x, fmaf(dy, T1.y, dz * T1.z));
+            const float nn = fmaf(T1.x, S1.x, fmaf(T1.y, S1.y, T1.z * S1.z));
+            dense_pair<ATT>(r, rinv, ww, wcc, tK, tKp, nn, ext.k, ext.k2pi, ext.kim, ext.k2re, ext.k2im, E);
+            if (same)
+                dense_pair<ATT>(r, rinv, ww, wcc, tK, tKp, nn, in.k, in.k2pi, in.kim, in.k2re, in.k2im, I);
+        }
+    }
+    const float sV = same ? in.sV : 0.0f, sW = same ? in.sW : 0.0f, s1 = same ? 1.0f : 0.0f;
+    const int64_t rD = rowD[g], rN = rowN[g], cD = rowD[h], cN = rowN[h];
+    A[rD * n + cD] = make_float2(-(E.kr + s1 * I.kr), -(E.ki + s1 * I.ki));
+    A[rD * n + cN] = make_float2(E.vr + sV * I.vr, E.vi + sV * I.vi);
+    A[rN * n + cD] = make_float2(E.wr + sW * I.wr, E.wi + sW * I.wi);
+    A[rN * n + cN] = make_float2(E.pr + s1 * I.pr, E.pi + s1 * I.pi);
+}
+
+// A += singular correction (one thread per CSR entry)
+__global__ void k_dense_correction(const int32_t *__restrict__ cptr, const int32_t *__restrict__ ccol,
+                                   const double2 *__restrict__ cval, const int32_t *__restrict__ rowD,
+                                   const int32_t *__restrict__ rowN, int64_t NV, int64_t n, float2 *__restrict__ A)
+{
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= NV) return;
+    const int64_t rD = rowD[g], rN = rowN[g];
+    for (int32_t e = cptr[g]; e < cptr[g + 1]; ++e) {
+        const int32_t h = ccol[e];
+        const int64_t cD = rowD[h], cN = rowN[h];
+        const int64_t idx[4] = {rD * n + cD, rD * n + cN, rN * n + cD, rN * n + cN};
+        for (int b = 0; b < 4; ++b) {
+            const float2 a = A[idx[b]];
+            const double2 c = cval[4 * e + b];
+            A[idx[b]] = make_float2(float(double(a.x) + c.x), float(double(a.y) + c.y));
+        }
+    }
+}
+
+void launch_assemble_dense(bem_problem &p)
+{
+    const int64_t n_corner = 3 * p.NT;
+    float4 *rec = nullptr;
+    BEM_HIP(hipMalloc(&rec, size_t(18 * n_corner) * sizeof(float4)));
+    k_vertex_points<<<dim3(unsigned((6 * n_corner + 255) / 256)), dim3(256), 0, p.stream>>>(
+        p.d_v2t, n_corner, p.d_area, p.d_normal, p.d_curl, p.d_pts, p.M, rec);
+    BEM_HIP(hipGetLastError());
+    std::vector<int32_t> vdom(p.NV);
+    std::vector<DenseDom> doms;
+    bool att = p.k0im != 0.0;
+    for (size_t j = 0; j < p.doms.size(); ++j) {
+        const auto &d = p.doms[j];
+        for (int64_t i = 0; i < d.nv; ++i) vdom[d.v_off + i] = int32_t(j);
+        doms.push_back(DenseDom{float(d.kre), float(d.kre / (2.0 * M_PI)), float(d.kim), float(d.rho / p.rho0),
+                                float(p.rho0 / d.rho), float(d.kre * d.kre - d.kim * d.kim), float(2.0 * d.kre * d.kim),
+                                0.0f});
+        att = att || d.kim != 0.0;
+    }
+    const DenseDom ext{float(p.k0re), float(p.k0re / (2.0 * M_PI)), float(p.k0im), 1.0f, 1.0f,
+                       float(p.k0re * p.k0re - p.k0im * p.k0im), float(2.0 * p.k0re * p.k0im), 0.0f};
+    int32_t *d_vdom = nullptr;
+    DenseDom *d_doms = nullptr;
+    BEM_HIP(hipMalloc(&d_vdom, vdom.size() * sizeof(int32_t)));
+    BEM_HIP(hipMalloc(&d_doms, doms.size() * sizeof(DenseDom)));
+    BEM_HIP(hipMemcpyAsync(d_vdom, vdom.data(), vdom.size() * sizeof(int32_t), hipMemcpyHostToDevice, p.stream));
+    BEM_HIP(hipMemcpyAsync(d_doms, doms.data(), doms.size() * sizeof(DenseDom), hipMemcpyHostToDevice, p.stream));
+    const dim3 grid(unsigned((p.NV + 15) / 16), unsigned((p.NV + 15) / 16)), block(16, 16);
+    if (att)
+        k_assemble_dense<true><<<grid, block, 0, p.stream>>>(rec, p.d_v2t_ptr, d_vdom, d_doms, ext, p.d_rowD, p.d_rowN,
+                                                           p.NV, p.N, p.d_A);
+    else
+        k_assemble_dense<false><<<grid, block, 0, p.stream>>>(rec, p.d_v2t_ptr, d_vdom, d_doms, ext, p.d_rowD, p.d_rowN,
+                                                            p.NV, p.N, p.d_A);
+    BEM_HIP(hipGetLastError());
+    k_dense_correction<<<dim3(unsigned((p.NV + 255) / 256)), dim3(256), 0, p.stream>>>(
+        p.d_cptr, p.d_ccol, p.d_cval, p.d_rowD, p.d_rowN, p.NV, p.N, p.d_A);
+    BEM_HIP(hipGetLastError());
+    BEM_HIP(hipStreamSynchronize(p.stream));
+    (void)hipFree(rec);
+    (void)hipFree(d_vdom);
+    (void)hipFree(d_doms);
+}
+
+// y = A x, complex64 matrix, FP64 vectors and FP64 accumulation.  One wave per
+// GEMV_ROWS rows; lanes stride over the columns two entries at a time (16-byte
+// loads of A), partial sums reduced across the wave in a fixed order.
+constexpr int GEMV_ROWS = 4;
+
+__global__ __launch_bounds__(256) void k_gemv(const float2 *__restrict__ A, const double2 *__restrict__ x, int64_t n,
+                                              double2 *__restrict__ y)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t r0 = wave * GEMV_ROWS;
+    if (r0 >= n) return;
+    double ar[GEMV_ROWS], ai[GEMV_ROWS];
+#pragma unroll
+    for (int k = 0; k < GEMV_ROWS; ++k) ar[k] = ai[k] = 0.0;
+    const int64_t npair = n / 2;
+    for (int64_t c2 = lane; c2 < npair; c2 += 64) {
+        const double2 x0 = x[2 * c2], x1 = x[2 * c2 + 1];
+#pragma unroll
+        for (int k = 0; k < GEMV_ROWS; ++k) {
+            const int64_t r = r0 + k < n ? r0 + k : n - 1;
+            const float4 a = *reinterpret_cast<const float4 *>(A + r * n + 2 * c2);
+            ar[k] += double(a.x) * x0.x - double(a.y) * x0.y + double(a.z) * x1.x - double(a.w) * x1.y;
+            ai[k] += double(a.x) * x0.y + double(a.y) * x0.x + double(a.z) * x1.y + double(a.w) * x1.x;
+        }
+    }
+    if ((n & 1) && lane == 0) {
+        const double2 xl = x[n - 1];
+#pragma unroll
+        for (int k = 0; k < GEMV_ROWS; ++k) {
+            const int64_t r = r0 + k < n ? r0 + k : n - 1;
+            const float2 a = A[r * n + n - 1];
+            ar[k] += double(a.x) * xl.x - double(a.y) * xl.y;
+            ai[k] += double(a.x) * xl.y + double(a.y) * xl.x;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < GEMV_ROWS; ++k) {
+        for (int off = 32; off > 0; off >>= 1) {
+            ar[k] += __shfl_xor(ar[k], off);
+            ai[k] += __shfl_xor(ai[k], off);
+        }
+    }
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < GEMV_ROWS; ++k)
+            if (r0 + k < n) y[r0 + k] = make_double2(ar[k], ai[k]);
+}
+
+void launch_gemv(bem_problem &p, const double2 *x, double2 *y)
+{
+    const int64_t waves = (p.N + GEMV_ROWS - 1) / GEMV_ROWS;
+    const int64_t threads = waves * 64;
+    k_gemv<<<dim3(unsigned((threads + 255) / 256)), dim3(256), 0, p.stream>>>(p.d_A, x, p.N, y);
+    BEM_HIP(hipGetLastError());
+}
+
+}  // namespace bem

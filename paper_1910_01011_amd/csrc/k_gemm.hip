@@ -1,0 +1,315 @@
+// Multi-right-hand-side apply of the assembled matrix: Y = A X as one real GEMM
+// on the matrix cores.
+//
+// The complex64 matrix A (row-major [n][n], interleaved) is read as a real
+// matrix A' [n][2n]; X (R right-hand sides) becomes X' [2n][2R] with
+//   X'[2c][j] = Re X_j[c],  X'[2c+1][j] = -Im X_j[c],
+//   X'[2c][R+j] = Im X_j[c], X'[2c+1][R+j] = Re X_j[c],
+// so that Y' = A' X' holds [Re Y | Im Y].  X' is stored transposed (row j =
+// column j of X', K contiguous) so both operands stream along K.
+//
+// Precisions:
+//   split BF16 (3 terms): A' = A_hi + A_lo, X' = X_hi + X_lo (BF16 each);
+//     Y' = A_hi X_hi + A_hi X_lo + A_lo X_hi with FP32 accumulation
+//     (v_mfma_f32_16x16x32_bf16).
+//   FP32: v_mfma_f32_16x16x4_f32 on A' and X' directly.
+// Split-K over S slices fills the chip when 2R is small; slices are summed in
+// a fixed order by the unpack kernel.
+#include <algorithm>
+#include <cmath>
+
+#include "bem_internal.h"
+
+namespace bem {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+constexpr int GBM = 128;    // rows of a workgroup tile
+constexpr int GBN = 128;    // columns of a workgroup tile
+constexpr int GBK = 32;     // K step (one bf16 MFMA)
+constexpr int GBKP = 40;    // padded LDS row, bf16 elements (80 B)
+constexpr int FBKP = 36;    // padded LDS row, fp32 elements (144 B)
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even
+    return uint16_t(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+// A' (n x 2n fp32 view of A) -> hi/lo BF16 planes [n][Kp], zero-padded columns
+__global__ void k_split_matrix(const float *__restrict__ A, int64_t n, int64_t Kp, uint16_t *__restrict__ hi,
+                               uint16_t *__restrict__ lo)
+{
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n * Kp) return;
+    const int64_t r = idx / Kp, k = idx - r * Kp;
+    const float a = k < 2 * n ? A[r * 2 * n + k] : 0.0f;
+    const uint16_t h = f32_to_bf16(a);
+    hi[idx] = h;
+    lo[idx] = f32_to_bf16(a - bf16_to_f32(h));
+}
+
+// X (R vectors, complex128, RHS-major) -> X'^T [Np][Kp] (fp32, or bf16 hi/lo)
+template <bool BF16>
+__global__ void k_pack_rhs(const double2 *__restrict__ X, int64_t n, int R, int64_t Np, int64_t Kp,
+                           float *__restrict__ f32, uint16_t *__restrict__ hi, uint16_t *__restrict__ lo)
+{
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= Np * Kp) return;
+    const int64_t j = idx / Kp, k = idx - j * Kp;
+    float v = 0.0f;
+    if (k < 2 * n && j < 2 * R) {
+        const int64_t c = k >> 1;
+        const bool odd = k & 1;
+        const double2 x = X[(j < R ? j : j - R) * n + c];
+        if (j < R) v = odd ? float(-x.y) : float(x.x);
+        else v = odd ? float(x.x) : float(x.y);
+    }
+    if (BF16) {
+        const uint16_t h = f32_to_bf16(v);
+        hi[idx] = h;
+        lo[idx] = f32_to_bf16(v - bf16_to_f32(h));
+    } else {
+        f32[idx] = v;
+    }
+}
+
+// Tile order: the n-tiles and K slices of one m-tile sit on one XCD (workgroup
+// ids differ by multiples of 8), so its A rows are shared through that L2.
+__device__ __forceinline__ void tile_of(int id, int n_m, int n_n, int n_s, int &mt, int &nt, int &ks)
+{
+    const int per_m = n_n * n_s;
+    const int xcd = id & 7, slot = id >> 3;
+    const int group = slot / per_m, inner = slot - group * per_m;
+    mt = group * 8 + xcd;
+    nt = inner / n_s;
+    ks = inner - nt * n_s;
+    (void)n_m;
+}
+
+__global__ __launch_bounds__(256) void k_gemm_bf16x3(const uint16_t *__restrict__ Ahi, const uint16_t *__restrict__ Alo,
+                                                     const uint16_t *__restrict__ Bhi, const uint16_t *__restrict__ Blo,
+                                                     int64_t M, int64_t Kp, int n_m, int n_n, int n_s, int64_t kslice,
+                                                     float *__restrict__ C, int64_t Np)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t sA[2][GBM * GBKP];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[2][GBN * GBKP];
+    int mt, nt, ks;
+    tile_of(blockIdx.x, n_m, n_n, n_s, mt, nt, ks);
+    if (mt >= n_m) return;   // padding ids of the XCD-grouped order
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t m0 = int64_t(mt) * GBM, n0 = int64_t(nt) * GBN;
+    const int64_t kb = int64_t(ks) * kslice, ke = std::min<int64_t>(Kp, kb + kslice);
+    const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+    const int frow = lane & 15, fk = 8 * (lane >> 4);
+    for (int64_t k0 = kb; k0 < ke; k0 += GBK) {
+        // 128 rows x 32 bf16 per plane = 512 chunks of 16 B; two per thread
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+            const int c = tid + 256 * it;
+            const int row = c >> 2, ch = c & 3;
+            const int64_t gr = m0 + row;
+            uint4 vh = make_uint4(0, 0, 0, 0), vl = make_uint4(0, 0, 0, 0);
+            if (gr < M) {
+                vh = *reinterpret_cast<const uint4 *>(Ahi + gr * Kp + k0 + 8 * ch);
+                vl = *reinterpret_cast<const uint4 *>(Alo + gr * Kp + k0 + 8 * ch);
+            }
+            *reinterpret_cast<uint4 *>(&sA[0][row * GBKP + 8 * ch]) = vh;
+            *reinterpret_cast<uint4 *>(&sA[1][row * GBKP + 8 * ch]) = vl;
+            const int64_t gn = n0 + row;   // always < Np (padded)
+            *reinterpret_cast<uint4 *>(&sB[0][row * GBKP + 8 * ch]) =
+                *reinterpret_cast<const uint4 *>(Bhi + gn * Kp + k0 + 8 * ch);
+            *reinterpret_cast<uint4 *>(&sB[1][row * GBKP + 8 * ch]) =
+                *reinterpret_cast<const uint4 *>(Blo + gn * Kp + k0 + 8 * ch);
+        }
+        __syncthreads();
+        bf16x8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            ah[i] = *reinterpret_cast<const bf16x8 *>(&sA[0][(wm + 16 * i + frow) * GBKP + fk]);
+            al[i] = *reinterpret_cast<const bf16x8 *>(&sA[1][(wm + 16 * i + frow) * GBKP + fk]);
+            bh[i] = *reinterpret_cast<const bf16x8 *>(&sB[0][(wn + 16 * i + frow) * GBKP + fk]);
+            bl[i] = *reinterpret_cast<const bf16x8 *>(&sB[1][(wn + 16 * i + frow) * GBKP + fk]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+            }
+        __syncthreads();
+    }
+    float *Cs = C + int64_t(ks) * M * Np;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t row = m0 + wm + 16 * i + 4 * (lane >> 4) + e;
+                const int64_t col = n0 + wn + 16 * j + frow;
+                if (row < M) Cs[row * Np + col] = acc[i][j][e];
+            }
+}
+
+__global__ __launch_bounds__(256) void k_gemm_f32(const float *__restrict__ A, int64_t lda,
+                                                  const float *__restrict__ B, int64_t M, int64_t K, int64_t Kp,
+                                                  int n_m, int n_n, int n_s, int64_t kslice, float *__restrict__ C,
+                                                  int64_t Np)
+{
+    __shared__ __attribute__((aligned(16))) float sA[GBM * FBKP];
+    __shared__ __attribute__((aligned(16))) float sB[GBN * FBKP];
+    int mt, nt, ks;
+    tile_of(blockIdx.x, n_m, n_n, n_s, mt, nt, ks);
+    if (mt >= n_m) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t m0 = int64_t(mt) * GBM, n0 = int64_t(nt) * GBN;
+    const int64_t kb = int64_t(ks) * kslice, ke = std::min<int64_t>(Kp, kb + kslice);
+    const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+    const int frow = lane & 15, fk = 8 * (lane >> 4);
+    for (int64_t k0 = kb; k0 < ke; k0 += GBK) {
+        // 128 rows x 32 floats = 1024 chunks of 16 B; four per thread
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int c = tid + 256 * it;
+            const int row = c >> 3, ch = c & 7;
+            const int64_t gr = m0 + row, kk = k0 + 4 * ch;
+            float4 va = make_float4(0, 0, 0, 0);
+            if (gr < M && kk < K) va = *reinterpret_cast<const float4 *>(A + gr * lda + kk);   // K is a multiple of 4
+            *reinterpret_cast<float4 *>(&sA[row * FBKP + 4 * ch]) = va;
+            *reinterpret_cast<float4 *>(&sB[row * FBKP + 4 * ch]) =
+                *reinterpret_cast<const float4 *>(B + (n0 + row) * Kp + kk);
+        }
+        __syncthreads();
+        // lane group g = lane/16 owns k = 8g .. 8g+7 of this step, in both operands
+        float4 a0[4], a1[4], b0[4], b1[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            a0[i] = *reinterpret_cast<const float4 *>(&sA[(wm + 16 * i + frow) * FBKP + fk]);
+            a1[i] = *reinterpret_cast<const float4 *>(&sA[(wm + 16 * i + frow) * FBKP + fk + 4]);
+            b0[i] = *reinterpret_cast<const float4 *>(&sB[(wn + 16 * i + frow) * FBKP + fk]);
+            b1[i] = *reinterpret_cast<const float4 *>(&sB[(wn + 16 * i + frow) * FBKP + fk + 4]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[i].x, b0[j].x, acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[i].y, b0[j].y, acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[i].z, b0[j].z, acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[i].w, b0[j].w, acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[i].x, b1[j].x, acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[i].y, b1[j].y, acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[i].z, b1[j].z, acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[i].w, b1[j].w, acc[i][j], 0, 0, 0);
+            }
+        __syncthreads();
+    }
+    float *Cs = C + int64_t(ks) * M * Np;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t row = m0 + wm + 16 * i + 4 * (lane >> 4) + e;
+                const int64_t col = n0 + wn + 16 * j + frow;
+                if (row < M) Cs[row * Np + col] = acc[i][j][e];
+            }
+}
+
+// Y_j[r] = (sum_s C_s[r][j], sum_s C_s[r][R + j])  (fixed slice order, FP64 sums)
+__global__ void k_unpack_y(const float *__restrict__ C, int64_t M, int64_t Np, int R, int n_s, double2 *__restrict__ Y)
+{
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= M * R) return;
+    const int64_t j = idx / M, r = idx - j * M;
+    double re = 0, im = 0;
+    for (int s = 0; s < n_s; ++s) {
+        re += C[(int64_t(s) * M + r) * Np + j];
+        im += C[(int64_t(s) * M + r) * Np + R + j];
+    }
+    Y[j * M + r] = make_double2(re, im);
+}
+
+static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+void split_matrix_bf16(bem_problem &p)
+{
+    const int64_t Kp = round_up(2 * p.N, GBK);
+    BEM_HIP(hipMalloc(&p.d_Ahi, size_t(p.N) * Kp * sizeof(uint16_t)));
+    BEM_HIP(hipMalloc(&p.d_Alo, size_t(p.N) * Kp * sizeof(uint16_t)));
+    const int64_t tot = p.N * Kp;
+    k_split_matrix<<<dim3(unsigned((tot + 255) / 256)), dim3(256), 0, p.stream>>>(
+        reinterpret_cast<const float *>(p.d_A), p.N, Kp, p.d_Ahi, p.d_Alo);
+    BEM_HIP(hipGetLastError());
+}
+
+GemmPlan gemm_plan(const bem_problem &p, int R, bool bf16)
+{
+    GemmPlan g{};
+    g.R = R;
+    g.bf16 = bf16;
+    g.Kp = round_up(2 * p.N, GBK);
+    g.Np = round_up(2 * int64_t(R), GBN);
+    g.n_m = int((p.N + GBM - 1) / GBM);
+    g.n_n = int(g.Np / GBN);
+    const int64_t ksteps = g.Kp / GBK;
+    // enough workgroups to cover every CU several times
+    int s = int(std::max<int64_t>(1, (2048 + int64_t(g.n_m) * g.n_n - 1) / (int64_t(g.n_m) * g.n_n)));
+    s = int(std::min<int64_t>(s, std::max<int64_t>(1, ksteps / 8)));
+    g.n_s = std::max(1, std::min(s, 64));
+    g.kslice = round_up((g.Kp + g.n_s - 1) / g.n_s, GBK);
+    g.n_s = int((g.Kp + g.kslice - 1) / g.kslice);
+    const int groups = (g.n_m + 7) / 8;
+    g.n_wg = groups * 8 * g.n_n * g.n_s;
+    g.bytes_x = size_t(g.Np) * g.Kp * (bf16 ? 2 * sizeof(uint16_t) : sizeof(float));
+    g.bytes_c = size_t(g.n_s) * p.N * g.Np * sizeof(float);
+    return g;
+}
+
+void launch_gemm(bem_problem &p, const GemmPlan &g, const double2 *X, double2 *Y, void *xbuf, float *cbuf)
+{
+    const int64_t tot = g.Np * g.Kp;
+    if (g.bf16) {
+        uint16_t *hi = static_cast<uint16_t *>(xbuf), *lo = hi + tot;
+        k_pack_rhs<true><<<dim3(unsigned((tot + 255) / 256)), dim3(256), 0, p.stream>>>(X, p.N, g.R, g.Np, g.Kp,
+                                                                                       nullptr, hi, lo);
+        BEM_HIP(hipGetLastError());
+        if (p.timed_gemm) BEM_HIP(hipEventRecord(p.ev[1], p.stream));
+        k_gemm_bf16x3<<<dim3(unsigned(g.n_wg)), dim3(256), 0, p.stream>>>(p.d_Ahi, p.d_Alo, hi, lo, p.N, g.Kp, g.n_m,
+                                                                         g.n_n, g.n_s, g.kslice, cbuf, g.Np);
+    } else {
+        float *xf = static_cast<float *>(xbuf);
+        k_pack_rhs<false><<<dim3(unsigned((tot + 255) / 256)), dim3(256), 0, p.stream>>>(X, p.N, g.R, g.Np, g.Kp, xf,
+                                                                                        nullptr, nullptr);
+        BEM_HIP(hipGetLastError());
+        if (p.timed_gemm) BEM_HIP(hipEventRecord(p.ev[1], p.stream));
+        k_gemm_f32<<<dim3(unsigned(g.n_wg)), dim3(256), 0, p.stream>>>(reinterpret_cast<const float *>(p.d_A), 2 * p.N,
+                                                                      xf, p.N, 2 * p.N, g.Kp, g.n_m, g.n_n, g.n_s,
+                                                                      g.kslice, cbuf, g.Np);
+    }
+    BEM_HIP(hipGetLastError());
+    if (p.timed_gemm) BEM_HIP(hipEventRecord(p.ev[2], p.stream));
+    const int64_t ny = p.N * g.R;
+    k_unpack_y<<<dim3(unsigned((ny + 255) / 256)), dim3(256), 0, p.stream>>>(cbuf, p.N, g.Np, g.R, g.n_s, Y);
+    BEM_HIP(hipGetLastError());
+}
+
+}  // namespace bem
