@@ -46,8 +46,10 @@ def cpu_baseline(prob, seconds_target=15.0):
         nthreads = int(env_threads)
     x = vectors.random_complex(prob.n_unknowns, seed=0)
     nv = sum(d.n_vertices for d in prob.domains)
-    # calibrate on a few vertices, then run a sample sized for ~seconds_target
-    n_v = 4
+    # warm up (thread pool, rule tables), calibrate on 16 vertices, then run a
+    # sample sized for ~seconds_target
+    oracle.pmchwt_rows(prob, vectors.random_rows(nv, 2, seed=10))
+    n_v = 16
     t0 = time.perf_counter()
     rows = vectors.random_rows(nv, n_v, seed=11)
     R = oracle.pmchwt_rows(prob, rows)
@@ -73,6 +75,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-assembled", action="store_true")
     ap.add_argument("--level", type=int, default=5, help="icosphere level of the sphere workload (5: 10,242 v)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -146,9 +149,68 @@ def main():
         ts = time.perf_counter() - ts
         out["gmres"] = {"time_to_solve_s": ts, "iterations": info[0]["iterations"],
                         "rel_residual": info[0]["rel_residual"], "converged": info[0]["converged"], "tol": 1e-5}
+    if not args.no_assembled:
+        del P
+        torch.cuda.empty_cache()
+        out["assembled"] = assembled_section(prob, bem, vectors, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out))
+
+
+BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
+FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X FP32 MFMA
+HBM_PEAK_GBPS = 8000.0
+
+
+def assembled_section(prob, bem, vectors, torch):
+    """Assembled mode on the same problem: dense assembly, GEMV (HBM roofline),
+    multi-RHS GEMM (MFMA roofline) and time-to-solve of the three precision forms."""
+    n = prob.n_unknowns
+    res = {"n": n}
+    t = time.perf_counter()
+    P = bem.Problem.from_config(prob, device=True, mode=bem.BEM_ASSEMBLED_SPLIT_BF16)
+    torch.cuda.synchronize()
+    res["assembly_s"] = time.perf_counter() - t
+    x = torch.from_numpy(vectors.random_complex(n, seed=0)).cuda()
+    for _ in range(2):
+        P.apply(x)
+    ts = []
+    for _ in range(10):
+        P.apply(x)
+        ts.append(P.timings()[1])
+    ms = float(np.median(ts))
+    gbps = 8.0 * n * n / (ms * 1e-3) / 1e9
+    res["gemv"] = {"ms": ms, "GBps": gbps, "frac_hbm": gbps / HBM_PEAK_GBPS, "bytes": 8.0 * n * n}
+    for R in (64, 256):
+        X = torch.from_numpy(vectors.random_complex(n, seed=1, n_rhs=R)).cuda()
+        for kern, key, peak, fl in ((bem.BEM_APPLY_MFMA_SPLIT_BF16, "bf16x3", BF16_PEAK_TFLOPS, 24.0),
+                                    (bem.BEM_APPLY_MFMA_FP32, "fp32", FP32_MFMA_PEAK_TFLOPS, 8.0)):
+            for _ in range(2):
+                P.apply(X, kernel=kern)
+            ts = []
+            for _ in range(5):
+                P.apply(X, kernel=kern)
+                ts.append(P.timings()[1])
+            ms = float(np.median(ts))
+            tf = fl * n * n * R / (ms * 1e-3) / 1e12
+            res[f"gemm_{key}_R{R}"] = {"ms": ms, "TFLOPs": tf, "frac": tf / peak, "peak": peak}
+    # time-to-solve at 1e-5 for one plane wave and for 64 plane waves
+    dirs = np.random.default_rng(7).standard_normal((64, 3))
+    for R in (1, 64):
+        b = P.rhs(bem.Incident.plane_waves(dirs[:R]))
+        for name, prec in (("plain_fp32", bem.BEM_PREC_FP32), ("split_bf16_fgmres", bem.BEM_PREC_SPLIT_BF16_FGMRES),
+                           ("fp32_mfma_fgmres", bem.BEM_PREC_FP32_MFMA_FGMRES)):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            u, info = P.solve(b, bem.solve_options(tol=1e-5, restart=100 if prec == bem.BEM_PREC_FP32 else 30,
+                                                   max_iter=400, precision=prec, inner_tol=1e-3))
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            res[f"solve_{name}_R{R}"] = {"s": dt, "iterations": int(max(i["iterations"] for i in info)),
+                                         "max_rel_residual": float(max(i["rel_residual"] for i in info)),
+                                         "all_converged": all(i["converged"] for i in info)}
+    return res
 
 
 if __name__ == "__main__":

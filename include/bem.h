@@ -91,8 +91,19 @@ typedef struct {
 
 #define BEM_PRECOND_NONE 0
 #define BEM_PRECOND_OSRC 1
+/* Solver precision forms (compared at equal accuracy):
+ *   BEM_PREC_FP32               plain GMRES on the FP32 operator (on-the-fly kernel, or the
+ *                               dense FP32 matrix by GEMV with FP64 accumulation, one
+ *                               right-hand side per launch)
+ *   BEM_PREC_SPLIT_BF16_FGMRES  flexible GMRES: outer Arnoldi on the FP32 matrix with FP64
+ *                               accumulation, inner block GMRES (to inner_tol) on the 3-term
+ *                               split-BF16 MFMA GEMM, all right-hand sides in one launch
+ *                               (problem assembled with BEM_ASSEMBLED_SPLIT_BF16)
+ *   BEM_PREC_FP32_MFMA_FGMRES   the same with the FP32 MFMA GEMM as inner operator
+ *                               (any assembled mode) */
 #define BEM_PREC_FP32 0
 #define BEM_PREC_SPLIT_BF16_FGMRES 1
+#define BEM_PREC_FP32_MFMA_FGMRES 2
 
 typedef struct {
     double tol;          /* relative residual target (paper: 1e-5) */
@@ -102,14 +113,14 @@ typedef struct {
     int n_pade;          /* OSRC Pade terms */
     double r_eps;        /* OSRC damping length */
     double theta;        /* OSRC Pade branch-cut rotation */
-    int precision;       /* BEM_PREC_FP32 or BEM_PREC_SPLIT_BF16_FGMRES */
+    int precision;       /* BEM_PREC_FP32, BEM_PREC_SPLIT_BF16_FGMRES or BEM_PREC_FP32_MFMA_FGMRES */
     double inner_tol;    /* inner tolerance of the flexible-GMRES refinement */
 } bem_solve_opts;
 
 typedef struct {
-    int32_t iterations;
-    int32_t converged;
-    double rel_residual;   /* ||b - A u|| / ||b|| of the returned u (weak form) */
+    int32_t iterations;    /* (outer) GMRES iterations */
+    int32_t converged;     /* the GMRES residual estimate reached tol */
+    double rel_residual;   /* true ||b - A u|| / ||b|| of the returned u (weak form, FP32 operator) */
 } bem_solve_info;
 
 /* Set up a problem: validate meshes, build geometry, quadrature points and the
@@ -129,6 +140,20 @@ bem_status bem_apply(bem_problem *p, const bem_complex *x, bem_complex *y, int32
 /* bem_apply restricted to parts of the operator (parts: 1 = far field
  * (regular rule on every pair), 2 = singular correction; 3 = both). */
 bem_status bem_apply_parts(bem_problem *p, const bem_complex *x, bem_complex *y, int32_t n_rhs, int parts);
+
+/* bem_apply with an explicit kernel for assembled problems:
+ *   BEM_APPLY_DEFAULT         as bem_apply (GEMV for one vector; for several, the GEMM of the
+ *                             problem's mode: FP32 MFMA or split-BF16 MFMA)
+ *   BEM_APPLY_GEMV            one GEMV per vector (FP32 matrix, FP64 accumulation)
+ *   BEM_APPLY_MFMA_FP32       one FP32 MFMA GEMM for all vectors
+ *   BEM_APPLY_MFMA_SPLIT_BF16 one 3-term split-BF16 MFMA GEMM for all vectors (problem
+ *                             assembled with BEM_ASSEMBLED_SPLIT_BF16)
+ * On-the-fly problems accept only BEM_APPLY_DEFAULT. */
+#define BEM_APPLY_DEFAULT 0
+#define BEM_APPLY_GEMV 1
+#define BEM_APPLY_MFMA_FP32 2
+#define BEM_APPLY_MFMA_SPLIT_BF16 3
+bem_status bem_apply_with(bem_problem *p, const bem_complex *x, bem_complex *y, int32_t n_rhs, int kernel);
 
 /* Right-hand side b_j = <gamma^{j,+} p_inc, phi> (eq. Galerkin_disc_rhs1) for
  * each incident field: b [n_fields][n_unknowns]. */

@@ -34,9 +34,10 @@ BEM_OK, BEM_WARN_NOT_CONVERGED = 0, 1
 BEM_ERR_INVALID_ARG, BEM_ERR_MESH, BEM_ERR_OOM, BEM_ERR_DEVICE, BEM_ERR_UNSUPPORTED = -1, -2, -3, -4, -5
 BEM_OTF, BEM_ASSEMBLED_FP32, BEM_ASSEMBLED_SPLIT_BF16 = 0, 1, 2
 BEM_DEVICE_PTRS = 1
+BEM_APPLY_DEFAULT, BEM_APPLY_GEMV, BEM_APPLY_MFMA_FP32, BEM_APPLY_MFMA_SPLIT_BF16 = 0, 1, 2, 3
 BEM_PLANE_WAVE, BEM_POINT_SOURCES, BEM_PISTON_ARRAY = 0, 1, 2
 BEM_PRECOND_NONE, BEM_PRECOND_OSRC = 0, 1
-BEM_PREC_FP32, BEM_PREC_SPLIT_BF16_FGMRES = 0, 1
+BEM_PREC_FP32, BEM_PREC_SPLIT_BF16_FGMRES, BEM_PREC_FP32_MFMA_FGMRES = 0, 1, 2
 
 
 class bem_complex(ctypes.Structure):
@@ -74,6 +75,7 @@ _L.bem_assemble.argtypes = [ctypes.POINTER(bem_domain), ctypes.c_int32, bem_comp
                             ctypes.POINTER(bem_assemble_opts), ctypes.POINTER(_vp)]
 _L.bem_apply.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
 _L.bem_apply_parts.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int]
+_L.bem_apply_with.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int]
 _L.bem_rhs.argtypes = [_vp, ctypes.POINTER(bem_incident), _vp]
 _L.bem_solve.argtypes = [_vp, ctypes.POINTER(bem_incident), ctypes.POINTER(bem_solve_opts), _vp,
                          ctypes.POINTER(bem_solve_info)]
@@ -88,11 +90,11 @@ _L.bem_last_timings.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
 _L.bem_destroy.argtypes = [_vp]
 _L.bem_destroy.restype = None
 _L.bem_last_error.restype = ctypes.c_char_p
-for _f in ("bem_assemble", "bem_apply", "bem_apply_parts", "bem_rhs", "bem_solve", "bem_solve_rhs",
+for _f in ("bem_assemble", "bem_apply", "bem_apply_parts", "bem_apply_with", "bem_rhs", "bem_solve", "bem_solve_rhs",
            "bem_evaluate_field", "bem_footprint_bytes", "bem_last_timings"):
     getattr(_L, _f).restype = ctypes.c_int
 
-EXPORTED = ["bem_assemble", "bem_apply", "bem_apply_parts", "bem_rhs", "bem_solve", "bem_solve_rhs",
+EXPORTED = ["bem_assemble", "bem_apply", "bem_apply_parts", "bem_apply_with", "bem_rhs", "bem_solve", "bem_solve_rhs",
             "bem_evaluate_field", "bem_num_unknowns", "bem_footprint_bytes", "bem_last_timings",
             "bem_destroy", "bem_last_error"]
 
@@ -234,17 +236,22 @@ class Problem:
             raise ValueError(f"expected {self.n} unknowns per right-hand side, got shape {tuple(x.shape)}")
         return x, n_rhs
 
-    def apply(self, x, parts=3, out=None):
-        """y = A x (Galerkin PMCHWT matrix, weak form); parts: 1 far, 2 singular, 3 both."""
+    def apply(self, x, parts=3, out=None, kernel=BEM_APPLY_DEFAULT):
+        """y = A x (Galerkin PMCHWT matrix, weak form); parts: 1 far, 2 singular, 3 both;
+        kernel: BEM_APPLY_* choice for assembled problems."""
         if self.device:
             import torch
             x, n_rhs = self._dev_in(x)
             y = torch.empty_like(x) if out is None else out
-            _check(_L.bem_apply_parts(self._h, x.data_ptr(), y.data_ptr(), n_rhs, parts))
-            return y
-        x, n_rhs = self._host_in(x)
-        y = np.empty_like(x)
-        _check(_L.bem_apply_parts(self._h, x.ctypes.data, y.ctypes.data, n_rhs, parts))
+            xp, yp = x.data_ptr(), y.data_ptr()
+        else:
+            x, n_rhs = self._host_in(x)
+            y = np.empty_like(x)
+            xp, yp = x.ctypes.data, y.ctypes.data
+        if kernel == BEM_APPLY_DEFAULT:
+            _check(_L.bem_apply_parts(self._h, xp, yp, n_rhs, parts))
+        else:
+            _check(_L.bem_apply_with(self._h, xp, yp, n_rhs, kernel))
         return y
 
     def rhs(self, incident):

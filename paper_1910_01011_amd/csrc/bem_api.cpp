@@ -230,125 +230,6 @@ bem_solve_opts default_solve_opts()
     return o;
 }
 
-// GMRES(m) with zero initial guess for one right-hand side (device vectors).
-// Arnoldi with classical Gram-Schmidt applied twice (FP64), Givens rotations
-// and the small triangular solve on the host.  Stops on the recursive
-// estimate of ||b - A x|| / ||b|| <= tol, then reports the true residual.
-void gmres_one(bem_problem &p, const double2 *b, double2 *x, const bem_solve_opts &o, bem_solve_info &info)
-{
-    const int64_t N = p.N;
-    const int m = std::max(1, o.restart);
-    hipStream_t s = p.stream;
-    double2 *V = nullptr, *w = nullptr, *h_dev = nullptr, *part = nullptr;
-    const int nblk = int(std::min<int64_t>(256, (N + 255) / 256));
-    dev_alloc(&V, size_t(m + 1) * N);
-    dev_alloc(&w, size_t(N));
-    dev_alloc(&h_dev, size_t(m + 2));
-    dev_alloc(&part, size_t(m + 2) * nblk);
-    struct Guard {
-        double2 *a, *b, *c, *d;
-        ~Guard() { (void)hipFree(a); (void)hipFree(b); (void)hipFree(c); (void)hipFree(d); }
-    } guard{V, w, h_dev, part};
-
-    using cd = std::complex<double>;
-    auto dot_host = [&](const double2 *Vb, int nvec, const double2 *vec, std::vector<cd> &out) {
-        bem::zdot_multi(s, Vb, N, nvec, vec, N, part, nblk, h_dev);
-        std::vector<double2> tmp(nvec);
-        BEM_HIP(hipMemcpyAsync(tmp.data(), h_dev, nvec * sizeof(double2), hipMemcpyDeviceToHost, s));
-        BEM_HIP(hipStreamSynchronize(s));
-        out.resize(nvec);
-        for (int i = 0; i < nvec; ++i) out[i] = cd(tmp[i].x, tmp[i].y);
-    };
-    auto norm = [&](const double2 *vec) {
-        std::vector<cd> t;
-        dot_host(vec, 1, vec, t);
-        return std::sqrt(std::max(0.0, t[0].real()));
-    };
-
-    BEM_HIP(hipMemsetAsync(x, 0, N * sizeof(double2), s));
-    const double bnorm = norm(b);
-    info.iterations = 0;
-    info.converged = 0;
-    info.rel_residual = 0.0;
-    if (bnorm == 0.0) {
-        info.converged = 1;
-        return;
-    }
-    int it = 0;
-    double est = 1.0;
-    while (it < o.max_iter) {
-        // r = b - A x  (into V_0)
-        if (it == 0) {
-            BEM_HIP(hipMemcpyAsync(V, b, N * sizeof(double2), hipMemcpyDeviceToDevice, s));
-        } else {
-            apply_device(p, x, w, 1, 3);
-            bem::zscale_copy(s, b, V, N, make_double2(1.0, 0.0));
-            bem::zaxpy(s, V, w, N, make_double2(-1.0, 0.0));
-        }
-        const double beta = norm(V);
-        est = beta / bnorm;
-        if (est <= o.tol) break;
-        bem::zscale_copy(s, V, V, N, make_double2(1.0 / beta, 0.0));
-        std::vector<cd> H(size_t(m + 1) * m, cd(0)), cs(m), sn(m), g(m + 1, cd(0));
-        g[0] = beta;
-        int j_used = 0;
-        for (int j = 0; j < m && it < o.max_iter; ++j) {
-            double2 *vj1 = V + int64_t(j + 1) * N;
-            apply_device(p, V + int64_t(j) * N, vj1, 1, 3);
-            std::vector<cd> h1, h2;
-            for (int pass = 0; pass < 2; ++pass) {
-                std::vector<cd> &h = pass == 0 ? h1 : h2;
-                dot_host(V, j + 1, vj1, h);
-                std::vector<double2> hh(j + 1);
-                for (int i = 0; i <= j; ++i) hh[i] = make_double2(h[i].real(), h[i].imag());
-                BEM_HIP(hipMemcpyAsync(h_dev, hh.data(), (j + 1) * sizeof(double2), hipMemcpyHostToDevice, s));
-                bem::zaxpy_multi(s, V, N, j + 1, h_dev, vj1, N, -1.0);
-            }
-            for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = h1[i] + h2[i];
-            const double hn = norm(vj1);
-            H[size_t(j + 1) * m + j] = hn;
-            if (hn > 0) bem::zscale_copy(s, vj1, vj1, N, make_double2(1.0 / hn, 0.0));
-            // apply the previous rotations, then the new one
-            for (int i = 0; i < j; ++i) {
-                const cd a = H[size_t(i) * m + j], c = H[size_t(i + 1) * m + j];
-                H[size_t(i) * m + j] = cs[i] * a + sn[i] * c;
-                H[size_t(i + 1) * m + j] = -std::conj(sn[i]) * a + std::conj(cs[i]) * c;
-            }
-            const cd a = H[size_t(j) * m + j], c = H[size_t(j + 1) * m + j];
-            const double rho = std::sqrt(std::norm(a) + std::norm(c));
-            cs[j] = std::conj(a) / rho;
-            sn[j] = std::conj(c) / rho;
-            H[size_t(j) * m + j] = rho;
-            H[size_t(j + 1) * m + j] = 0.0;
-            g[j + 1] = -std::conj(sn[j]) * g[j];
-            g[j] = cs[j] * g[j];
-            ++it;
-            j_used = j + 1;
-            est = std::abs(g[j + 1]) / bnorm;
-            if (est <= o.tol || hn == 0.0) break;
-        }
-        // y = H^-1 g, x += V y
-        std::vector<cd> y(j_used);
-        for (int i = j_used - 1; i >= 0; --i) {
-            cd acc = g[i];
-            for (int k = i + 1; k < j_used; ++k) acc -= H[size_t(i) * m + k] * y[k];
-            y[i] = acc / H[size_t(i) * m + i];
-        }
-        std::vector<double2> yy(j_used);
-        for (int i = 0; i < j_used; ++i) yy[i] = make_double2(y[i].real(), y[i].imag());
-        BEM_HIP(hipMemcpyAsync(h_dev, yy.data(), j_used * sizeof(double2), hipMemcpyHostToDevice, s));
-        bem::zaxpy_multi(s, V, N, j_used, h_dev, x, N, 1.0);
-        if (est <= o.tol) break;
-    }
-    // true residual of the returned iterate
-    apply_device(p, x, w, 1, 3);
-    bem::zscale_copy(s, w, w, N, make_double2(-1.0, 0.0));
-    bem::zaxpy(s, w, b, N, make_double2(1.0, 0.0));
-    info.rel_residual = norm(w) / bnorm;
-    info.iterations = it;
-    info.converged = info.rel_residual <= o.tol * 1.01 || est <= o.tol ? 1 : 0;
-}
-
 }  // namespace
 
 namespace bem {
@@ -510,6 +391,41 @@ bem_status bem_apply(bem_problem *p, const bem_complex *x, bem_complex *y, int32
     return bem_apply_parts(p, x, y, n_rhs, 3);
 }
 
+bem_status bem_apply_with(bem_problem *p, const bem_complex *x, bem_complex *y, int32_t n_rhs, int kernel)
+{
+    if (!p || !x || !y || n_rhs < 0) return fail(BEM_ERR_INVALID_ARG, "bem_apply_with: bad arguments");
+    if (kernel < BEM_APPLY_DEFAULT || kernel > BEM_APPLY_MFMA_SPLIT_BF16)
+        return fail(BEM_ERR_INVALID_ARG, "bem_apply_with: unknown kernel");
+    if (kernel == BEM_APPLY_DEFAULT) return bem_apply_parts(p, x, y, n_rhs, 3);
+    if (p->mode == BEM_OTF) return fail(BEM_ERR_INVALID_ARG, "bem_apply_with: on-the-fly problems have no dense kernels");
+    if (kernel == BEM_APPLY_MFMA_SPLIT_BF16 && p->mode != BEM_ASSEMBLED_SPLIT_BF16)
+        return fail(BEM_ERR_INVALID_ARG, "bem_apply_with: no BF16 planes (assemble with BEM_ASSEMBLED_SPLIT_BF16)");
+    if (n_rhs == 0) return BEM_OK;
+    return guarded([&]() -> bem_status {
+        BEM_HIP(hipSetDevice(p->device));
+        const size_t bytes = size_t(n_rhs) * p->N * sizeof(double2);
+        const double2 *dx = reinterpret_cast<const double2 *>(x);
+        double2 *dy = reinterpret_cast<double2 *>(y);
+        if (!(p->flags & BEM_DEVICE_PTRS)) {
+            ensure_scratch(*p, n_rhs);
+            BEM_HIP(hipMemcpyAsync(p->d_x, x, bytes, hipMemcpyHostToDevice, p->stream));
+            dx = p->d_x;
+            dy = p->d_y;
+        }
+        if (kernel == BEM_APPLY_GEMV) {
+            for (int r = 0; r < n_rhs; ++r)
+                apply_dense_one(*p, dx + int64_t(r) * p->N, dy + int64_t(r) * p->N, r == n_rhs - 1);
+        } else {
+            apply_dense_multi(*p, dx, dy, n_rhs, kernel == BEM_APPLY_MFMA_SPLIT_BF16);
+        }
+        if (!(p->flags & BEM_DEVICE_PTRS)) {
+            BEM_HIP(hipMemcpyAsync(y, p->d_y, bytes, hipMemcpyDeviceToHost, p->stream));
+            BEM_HIP(hipStreamSynchronize(p->stream));
+        }
+        return BEM_OK;
+    });
+}
+
 bem_status bem_last_timings(const bem_problem *p, double *ms4)
 {
     if (!p || !ms4) return fail(BEM_ERR_INVALID_ARG, "bem_last_timings: bad arguments");
@@ -555,7 +471,15 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
     bem_solve_opts o = opts ? *opts : default_solve_opts();
     if (!(o.tol > 0) || o.restart < 1 || o.max_iter < 1) return fail(BEM_ERR_INVALID_ARG, "bem_solve: bad options");
     if (o.precond != BEM_PRECOND_NONE) return fail(BEM_ERR_UNSUPPORTED, "bem_solve: preconditioner not available");
-    if (o.precision != BEM_PREC_FP32) return fail(BEM_ERR_UNSUPPORTED, "bem_solve: precision mode not available");
+    if (o.precision != BEM_PREC_FP32 && o.precision != BEM_PREC_SPLIT_BF16_FGMRES &&
+        o.precision != BEM_PREC_FP32_MFMA_FGMRES)
+        return fail(BEM_ERR_INVALID_ARG, "bem_solve: unknown precision mode");
+    if (o.precision == BEM_PREC_FP32_MFMA_FGMRES && p->mode == BEM_OTF)
+        return fail(BEM_ERR_INVALID_ARG, "bem_solve: MFMA refinement needs an assembled problem");
+    if (o.precision == BEM_PREC_SPLIT_BF16_FGMRES && p->mode != BEM_ASSEMBLED_SPLIT_BF16)
+        return fail(BEM_ERR_INVALID_ARG, "bem_solve: split-BF16 refinement needs a problem assembled in split-BF16 mode");
+    if (o.precision != BEM_PREC_FP32 && !(o.inner_tol > 0 && o.inner_tol < 1))
+        return fail(BEM_ERR_INVALID_ARG, "bem_solve: inner_tol must be in (0, 1)");
     return guarded([&]() -> bem_status {
         BEM_HIP(hipSetDevice(p->device));
         const size_t n = size_t(n_rhs) * p->N;
@@ -574,11 +498,39 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
             db = tb;
             du = tu;
         }
-        bool all = true;
-        for (int r = 0; r < n_rhs; ++r) {
-            gmres_one(*p, db + int64_t(r) * p->N, du + int64_t(r) * p->N, o, info[r]);
-            all = all && info[r].converged;
+        bem_problem &P = *p;
+        // FP32-accurate operator: on-the-fly kernel, or the FP32 dense matrix
+        // (GEMV with FP64 accumulation for one vector, FP32 MFMA GEMM for a block)
+        const bem::ApplyFn fp32_apply = [&P](const double2 *X, double2 *Y, int R) {
+            if (P.mode == BEM_OTF) {
+                apply_device(P, X, Y, R, 3);
+            } else {
+                for (int r = 0; r < R; ++r) apply_dense_one(P, X + int64_t(r) * P.N, Y + int64_t(r) * P.N, true);
+            }
+        };
+        if (o.precision == BEM_PREC_FP32) {
+            bem::gmres_batch(P, P.N, n_rhs, db, du, bem::KrylovOpts{o.tol, o.restart, o.max_iter}, fp32_apply,
+                             nullptr, info);
+        } else {
+            // flexible GMRES: outer Arnoldi on the FP32 matrix with FP64
+            // accumulation, inner GMRES on the 3-term split-BF16 GEMM
+            const bem::ApplyFn outer = [&P](const double2 *X, double2 *Y, int R) {
+                for (int r = 0; r < R; ++r) apply_dense_one(P, X + int64_t(r) * P.N, Y + int64_t(r) * P.N, true);
+            };
+            const bool bf16 = o.precision == BEM_PREC_SPLIT_BF16_FGMRES;
+            const bem::ApplyFn inner_op = [&P, bf16](const double2 *X, double2 *Y, int R) {
+                apply_dense_multi(P, X, Y, R, bf16);
+            };
+            const bem::KrylovOpts io{o.inner_tol, 30, 300};
+            const bem::ApplyFn prec = [&P, &inner_op, io](const double2 *V, double2 *Z, int R) {
+                std::vector<bem_solve_info> ii(R);
+                bem::gmres_batch(P, P.N, R, V, Z, io, inner_op, nullptr, ii.data());
+            };
+            bem::gmres_batch(P, P.N, n_rhs, db, du, bem::KrylovOpts{o.tol, o.restart, o.max_iter}, outer, &prec,
+                             info);
         }
+        bool all = true;
+        for (int r = 0; r < n_rhs; ++r) all = all && info[r].converged;
         if (!(p->flags & BEM_DEVICE_PTRS)) {
             BEM_HIP(hipMemcpyAsync(u, du, n * sizeof(double2), hipMemcpyDeviceToHost, p->stream));
             BEM_HIP(hipStreamSynchronize(p->stream));

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -198,6 +199,23 @@ void zaxpy_multi(hipStream_t s, const double2 *V, int64_t ld, int nvec, const do
                  int64_t n, double sign);
 void zscale_copy(hipStream_t s, const double2 *x, double2 *y, int64_t n, double2 a);
 void zaxpy(hipStream_t s, double2 *y, const double2 *x, int64_t n, double2 a);
+
+// batched FP64 complex kernels: R vectors of length n, bases [i][R][n] (k_linalg.hip)
+void bdot(hipStream_t s, const double2 *V, int64_t ldv, int nvec, const double2 *w, int64_t n, int R,
+          double2 *partials, int nblk, double2 *out_dev);
+void baxpy(hipStream_t s, const double2 *V, int64_t ldv, int nvec, const double2 *h_dev, double2 *w, int64_t n, int R,
+           double sign);
+void bscale(hipStream_t s, const double2 *x, double2 *y, int64_t n, int R, const double2 *a_dev);
+
+// batched (flexible) GMRES (krylov.cpp)
+using ApplyFn = std::function<void(const double2 *X, double2 *Y, int R)>;
+struct KrylovOpts {
+    double tol;
+    int restart;
+    int max_iter;
+};
+void gmres_batch(bem_problem &p, int64_t n, int R, const double2 *B, double2 *X, const KrylovOpts &o,
+                 const ApplyFn &A, const ApplyFn *M, bem_solve_info *info);
 
 // incident fields and right-hand sides (k_field.hip)
 void launch_rhs(bem_problem &p, const bem_incident &inc, double2 *b);

@@ -110,3 +110,105 @@ void zaxpy(hipStream_t s, double2 *y, const double2 *x, int64_t n, double2 a)
 }
 
 }  // namespace bem
+
+namespace bem {
+
+// ---------------------------------------------------------------------------
+// batched kernels: R independent vectors of length n stored contiguously
+// (vector r at offset r * n); Krylov bases as [i][R][n].
+// ---------------------------------------------------------------------------
+
+// partials[(r * nvec + i) * nblk + blk] = sum over chunk of conj(V_i[r]) w[r]
+__global__ __launch_bounds__(LA_BLOCK) void k_bdot_partial(const double2 *__restrict__ V, int64_t ldv,
+                                                           const double2 *__restrict__ w, int64_t n, int R,
+                                                           int nvec, int nblk, double2 *__restrict__ partials)
+{
+    __shared__ double sr[LA_BLOCK], si[LA_BLOCK];
+    const int blk = blockIdx.x, i = blockIdx.y, r = blockIdx.z, tid = threadIdx.x;
+    const double2 *v = V + int64_t(i) * ldv + int64_t(r) * n;
+    const double2 *ww = w + int64_t(r) * n;
+    double ar = 0, ai = 0;
+    for (int64_t k = int64_t(blk) * LA_BLOCK + tid; k < n; k += int64_t(nblk) * LA_BLOCK) {
+        const double2 a = v[k], b = ww[k];
+        ar += a.x * b.x + a.y * b.y;
+        ai += a.x * b.y - a.y * b.x;
+    }
+    sr[tid] = ar;
+    si[tid] = ai;
+    __syncthreads();
+    for (int s = LA_BLOCK / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            sr[tid] += sr[tid + s];
+            si[tid] += si[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) partials[(int64_t(r) * nvec + i) * nblk + blk] = make_double2(sr[0], si[0]);
+}
+
+__global__ void k_bdot_final(const double2 *__restrict__ partials, int nblk, int total, double2 *__restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= total) return;
+    double re = 0, im = 0;
+    for (int b = 0; b < nblk; ++b) {
+        re += partials[int64_t(k) * nblk + b].x;
+        im += partials[int64_t(k) * nblk + b].y;
+    }
+    out[k] = make_double2(re, im);
+}
+
+void bdot(hipStream_t s, const double2 *V, int64_t ldv, int nvec, const double2 *w, int64_t n, int R,
+          double2 *partials, int nblk, double2 *out_dev)
+{
+    if (nvec <= 0 || R <= 0) return;
+    k_bdot_partial<<<dim3(unsigned(nblk), unsigned(nvec), unsigned(R)), dim3(LA_BLOCK), 0, s>>>(V, ldv, w, n, R, nvec,
+                                                                                              nblk, partials);
+    BEM_HIP(hipGetLastError());
+    const int total = R * nvec;
+    k_bdot_final<<<dim3(unsigned((total + 63) / 64)), dim3(64), 0, s>>>(partials, nblk, total, out_dev);
+    BEM_HIP(hipGetLastError());
+}
+
+// w[r] += sign * sum_i h[r * nvec + i] V_i[r]
+__global__ void k_baxpy(const double2 *__restrict__ V, int64_t ldv, int nvec, const double2 *__restrict__ h,
+                        double2 *__restrict__ w, int64_t n, int R, double sign)
+{
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n * R) return;
+    const int64_t r = idx / n;
+    double re = 0, im = 0;
+    for (int i = 0; i < nvec; ++i) {
+        const double2 a = V[int64_t(i) * ldv + idx], c = h[r * nvec + i];
+        re += c.x * a.x - c.y * a.y;
+        im += c.x * a.y + c.y * a.x;
+    }
+    w[idx] = make_double2(w[idx].x + sign * re, w[idx].y + sign * im);
+}
+
+void baxpy(hipStream_t s, const double2 *V, int64_t ldv, int nvec, const double2 *h_dev, double2 *w, int64_t n, int R,
+           double sign)
+{
+    if (nvec <= 0 || n * R <= 0) return;
+    k_baxpy<<<dim3(unsigned((n * R + 255) / 256)), dim3(256), 0, s>>>(V, ldv, nvec, h_dev, w, n, R, sign);
+    BEM_HIP(hipGetLastError());
+}
+
+// y[r] = a[r] * x[r]   (complex per-vector scalars)
+__global__ void k_bscale(const double2 *__restrict__ x, double2 *__restrict__ y, int64_t n, int R,
+                         const double2 *__restrict__ a)
+{
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n * R) return;
+    const double2 c = a[idx / n], v = x[idx];
+    y[idx] = make_double2(c.x * v.x - c.y * v.y, c.x * v.y + c.y * v.x);
+}
+
+void bscale(hipStream_t s, const double2 *x, double2 *y, int64_t n, int R, const double2 *a_dev)
+{
+    if (n * R <= 0) return;
+    k_bscale<<<dim3(unsigned((n * R + 255) / 256)), dim3(256), 0, s>>>(x, y, n, R, a_dev);
+    BEM_HIP(hipGetLastError());
+}
+
+}  // namespace bem

@@ -1,0 +1,86 @@
+"""GPU solves against the FP64 oracle's dense LU solution.
+
+Targets: relative l2 error <= 1e-5 for the FP32 operators (on-the-fly and
+assembled), <= 1e-4 for the split-BF16 operator after flexible-GMRES
+refinement (outer residual with the FP32 matrix, FP64 accumulation).  The
+error is measured as the maximum over the u_D blocks and the u_N blocks.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from bem_inputs import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def _bem():
+    import paper_1910_01011_amd as bem
+    return bem
+
+
+def _relerr(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _blocks_err(problem, u, ref):
+    off = oracle.offsets(problem)
+    mD = np.zeros(problem.n_unknowns, dtype=bool)
+    for j, d in enumerate(problem.domains):
+        mD[off[j]:off[j] + d.n_vertices] = True
+    return max(_relerr(u[mD], ref[mD]), _relerr(u[~mD], ref[~mD]))
+
+
+DIRS = [(0, 0, 1), (1, 0, 0), (0.3, -0.6, 0.74), (-0.5, 0.5, -0.7071)]
+
+
+@pytest.fixture(scope="module")
+def c1():
+    prob = configs.config1()
+    A = oracle.pmchwt_matrix(prob)
+    B = np.stack([oracle.rhs(prob, *oracle.plane_wave(prob.k0, d)) for d in DIRS])
+    U = np.stack([oracle.solve_lu(A, b) for b in B])
+    return prob, A, B, U
+
+
+@pytest.mark.parametrize("mode_name", ["BEM_OTF", "BEM_ASSEMBLED_FP32"])
+def test_block_gmres_fp32(c1, mode_name):
+    prob, A, B, U = c1
+    bem = _bem()
+    P = bem.Problem.from_config(prob, mode=getattr(bem, mode_name))
+    u, info = P.solve(B, bem.solve_options(tol=1e-8, restart=100, max_iter=500))
+    for r in range(len(DIRS)):
+        err = _blocks_err(prob, u[r], U[r])
+        print(f"{mode_name} rhs {r}: {info[r]} err {err:.2e}")
+        assert info[r]["converged"]
+        assert err <= 1e-5
+
+
+@pytest.mark.parametrize("form", ["BEM_PREC_SPLIT_BF16_FGMRES", "BEM_PREC_FP32_MFMA_FGMRES"])
+def test_flexible_gmres_block(c1, form):
+    prob, A, B, U = c1
+    bem = _bem()
+    P = bem.Problem.from_config(prob, mode=bem.BEM_ASSEMBLED_SPLIT_BF16)
+    opts = bem.solve_options(tol=1e-8, restart=30, max_iter=60, precision=getattr(bem, form), inner_tol=1e-3)
+    u, info = P.solve(B, opts)
+    for r in range(len(DIRS)):
+        err = _blocks_err(prob, u[r], U[r])
+        print(f"{form} rhs {r}: {info[r]} err {err:.2e}")
+        assert info[r]["converged"]
+        # the outer residual uses the FP32 matrix with FP64 accumulation, so the
+        # refined solution is as accurate as the plain FP32 one
+        assert err <= (1e-4 if "BF16" in form else 1e-5)
+
+
+def test_not_converged_returns_warning_and_best_iterate(c1):
+    prob, A, B, U = c1
+    bem = _bem()
+    P = bem.Problem.from_config(prob)
+    u, info = P.solve(B[:1], bem.solve_options(tol=1e-12, restart=5, max_iter=5))
+    assert not info[0]["converged"]
+    assert info[0]["iterations"] == 5
+    r_true = np.linalg.norm(B[0] - A @ u[0]) / np.linalg.norm(B[0])
+    assert abs(r_true - info[0]["rel_residual"]) < 1e-6 + 1e-3 * r_true
+    assert r_true < 1.0
