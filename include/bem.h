@@ -169,6 +169,15 @@ bem_status bem_solve(bem_problem *p, const bem_incident *inc, const bem_solve_op
 bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, const bem_solve_opts *opts,
                          bem_complex *u, bem_solve_info *info);
 
+/* Out = P y for n_rhs residual vectors y [n_rhs][n_unknowns], P the OSRC
+ * block-diagonal preconditioner of opts (precond = BEM_PRECOND_OSRC, n_pade,
+ * r_eps, theta; paper eqs. OSRC_prec, OSRC_prec_blocks, OSRC_DtN_NtD_maps):
+ * per domain, Lambda_DtN M^-1 on the Dirichlet-equation rows and
+ * Lambda_NtD M^-1 on the Neumann-equation rows, k = k0.  Inner sparse solves
+ * by COCG in FP64 to 1e-10. */
+bem_status bem_apply_preconditioner(bem_problem *p, const bem_solve_opts *opts, const bem_complex *y,
+                                    bem_complex *out, int32_t n_rhs);
+
 /* Total pressure at points from traces u (paper eq. rep_formula_gen):
  * exterior p = p_inc + sum_j [DL_k0 u_D^j - SL_k0 u_N^j]; inside domain j
  * p = SL_kj((rho_j/rho_0) u_N^j) - DL_kj u_D^j.  points [n_points][3] (host

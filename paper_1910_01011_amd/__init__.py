@@ -81,6 +81,7 @@ _L.bem_solve.argtypes = [_vp, ctypes.POINTER(bem_incident), ctypes.POINTER(bem_s
                          ctypes.POINTER(bem_solve_info)]
 _L.bem_solve_rhs.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.POINTER(bem_solve_opts), _vp,
                              ctypes.POINTER(bem_solve_info)]
+_L.bem_apply_preconditioner.argtypes = [_vp, ctypes.POINTER(bem_solve_opts), _vp, _vp, ctypes.c_int32]
 _L.bem_evaluate_field.argtypes = [_vp, _vp, ctypes.POINTER(bem_incident), _vp, ctypes.c_int64, _vp, _vp]
 _L.bem_num_unknowns.argtypes = [_vp]
 _L.bem_num_unknowns.restype = ctypes.c_int64
@@ -91,10 +92,12 @@ _L.bem_destroy.argtypes = [_vp]
 _L.bem_destroy.restype = None
 _L.bem_last_error.restype = ctypes.c_char_p
 for _f in ("bem_assemble", "bem_apply", "bem_apply_parts", "bem_apply_with", "bem_rhs", "bem_solve", "bem_solve_rhs",
+           "bem_apply_preconditioner",
            "bem_evaluate_field", "bem_footprint_bytes", "bem_last_timings"):
     getattr(_L, _f).restype = ctypes.c_int
 
 EXPORTED = ["bem_assemble", "bem_apply", "bem_apply_parts", "bem_apply_with", "bem_rhs", "bem_solve", "bem_solve_rhs",
+            "bem_apply_preconditioner",
             "bem_evaluate_field", "bem_num_unknowns", "bem_footprint_bytes", "bem_last_timings",
             "bem_destroy", "bem_last_error"]
 
@@ -281,6 +284,19 @@ class Problem:
             _check(_L.bem_solve_rhs(self._h, b.ctypes.data, n_rhs, ctypes.byref(opts), u.ctypes.data, infos), True)
         return u, [dict(iterations=i.iterations, converged=bool(i.converged), rel_residual=i.rel_residual)
                    for i in infos]
+
+    def precondition(self, y, options):
+        """OSRC preconditioner applied to residual vectors y (rows = vectors)."""
+        if self.device:
+            import torch
+            y, n_rhs = self._dev_in(y)
+            out = torch.empty_like(y)
+            _check(_L.bem_apply_preconditioner(self._h, ctypes.byref(options), y.data_ptr(), out.data_ptr(), n_rhs))
+            return out
+        y, n_rhs = self._host_in(y)
+        out = np.empty_like(y)
+        _check(_L.bem_apply_preconditioner(self._h, ctypes.byref(options), y.ctypes.data, out.ctypes.data, n_rhs))
+        return out
 
     def evaluate_field(self, u, points, incident=None):
         inc = incident._c() if incident is not None else None

@@ -53,7 +53,7 @@ void free_problem(bem_problem *p)
     void *ptrs[] = {p->d_verts, p->d_tris, p->d_rowD, p->d_rowN, p->d_area, p->d_normal, p->d_curl, p->d_pts,
                     p->d_tnrm, p->d_v2t_ptr, p->d_v2t, p->d_pass, p->d_work, p->d_trial, p->d_part, p->d_pot,
                     p->d_cptr, p->d_ccol, p->d_cval, p->d_x, p->d_y, p->d_A, p->d_Ahi, p->d_Alo,
-                    p->d_gx, p->d_gc};
+                    p->d_gx, p->d_gc, p->d_aptr, p->d_acol, p->d_Mv, p->d_Sv};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (auto &e : p->ev)
@@ -228,6 +228,30 @@ bem_solve_opts default_solve_opts()
     o.precision = BEM_PREC_FP32;
     o.inner_tol = 1e-3;
     return o;
+}
+
+// ||b_r - (Ax)_r|| / ||b_r|| for R vectors (Ax is overwritten)
+std::vector<double> residual_norms(bem_problem &p, const double2 *B, double2 *AX, int R)
+{
+    const int64_t n = p.N;
+    const int nblk = int(std::min<int64_t>(128, (n + 255) / 256));
+    double2 *part = nullptr, *h = nullptr;
+    dev_alloc(&part, size_t(R) * nblk);
+    dev_alloc(&h, size_t(R));
+    std::vector<double2> ones(R, make_double2(1.0, 0.0)), out(R);
+    BEM_HIP(hipMemcpyAsync(h, ones.data(), R * sizeof(double2), hipMemcpyHostToDevice, p.stream));
+    bem::baxpy(p.stream, B, 0, 1, h, AX, n, R, -1.0);
+    bem::bdot(p.stream, AX, 0, 1, AX, n, R, part, nblk, h);
+    BEM_HIP(hipMemcpyAsync(out.data(), h, R * sizeof(double2), hipMemcpyDeviceToHost, p.stream));
+    std::vector<double2> bb(R);
+    bem::bdot(p.stream, B, 0, 1, B, n, R, part, nblk, h);
+    BEM_HIP(hipMemcpyAsync(bb.data(), h, R * sizeof(double2), hipMemcpyDeviceToHost, p.stream));
+    BEM_HIP(hipStreamSynchronize(p.stream));
+    (void)hipFree(part);
+    (void)hipFree(h);
+    std::vector<double> r(R);
+    for (int i = 0; i < R; ++i) r[i] = bb[i].x > 0 ? std::sqrt(std::max(0.0, out[i].x) / bb[i].x) : 0.0;
+    return r;
 }
 
 }  // namespace
@@ -470,7 +494,14 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
     if (!p || !b || !u || !info || n_rhs < 1) return fail(BEM_ERR_INVALID_ARG, "bem_solve: bad arguments");
     bem_solve_opts o = opts ? *opts : default_solve_opts();
     if (!(o.tol > 0) || o.restart < 1 || o.max_iter < 1) return fail(BEM_ERR_INVALID_ARG, "bem_solve: bad options");
-    if (o.precond != BEM_PRECOND_NONE) return fail(BEM_ERR_UNSUPPORTED, "bem_solve: preconditioner not available");
+    if (o.precond != BEM_PRECOND_NONE && o.precond != BEM_PRECOND_OSRC)
+        return fail(BEM_ERR_INVALID_ARG, "bem_solve: unknown preconditioner");
+    if (o.precond == BEM_PRECOND_OSRC) {
+        if (!(o.r_eps > 0) || !std::isfinite(o.r_eps) || o.n_pade < 0 || o.n_pade > 64 || !std::isfinite(o.theta))
+            return fail(BEM_ERR_INVALID_ARG, "bem_solve: OSRC needs r_eps > 0, 0 <= n_pade <= 64, finite theta");
+        if (o.precision != BEM_PREC_FP32)
+            return fail(BEM_ERR_UNSUPPORTED, "bem_solve: OSRC is available with BEM_PREC_FP32");
+    }
     if (o.precision != BEM_PREC_FP32 && o.precision != BEM_PREC_SPLIT_BF16_FGMRES &&
         o.precision != BEM_PREC_FP32_MFMA_FGMRES)
         return fail(BEM_ERR_INVALID_ARG, "bem_solve: unknown precision mode");
@@ -508,7 +539,29 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
                 for (int r = 0; r < R; ++r) apply_dense_one(P, X + int64_t(r) * P.N, Y + int64_t(r) * P.N, true);
             }
         };
-        if (o.precision == BEM_PREC_FP32) {
+        if (o.precision == BEM_PREC_FP32 && o.precond == BEM_PRECOND_OSRC) {
+            // left preconditioning: GMRES on P A u = P b (stops on the
+            // preconditioned residual); the unpreconditioned weak-form residual
+            // is reported afterwards
+            const bem::OsrcParams op{o.n_pade, o.r_eps, o.theta, 1e-10, 3000};
+            double2 *PB = nullptr, *tmp = nullptr;
+            dev_alloc(&PB, n);
+            dev_alloc(&tmp, n);
+            struct G2 {
+                double2 *a, *b;
+                ~G2() { (void)hipFree(a); (void)hipFree(b); }
+            } g2{PB, tmp};
+            bem::osrc_apply(P, op, db, PB, n_rhs);
+            const bem::ApplyFn prec_apply = [&P, &fp32_apply, op, tmp](const double2 *X, double2 *Y, int R) {
+                fp32_apply(X, tmp, R);
+                bem::osrc_apply(P, op, tmp, Y, R);
+            };
+            bem::gmres_batch(P, P.N, n_rhs, PB, du, bem::KrylovOpts{o.tol, o.restart, o.max_iter}, prec_apply,
+                             nullptr, info);
+            fp32_apply(du, tmp, n_rhs);
+            const std::vector<double> rr = residual_norms(P, db, tmp, n_rhs);
+            for (int r = 0; r < n_rhs; ++r) info[r].rel_residual = rr[r];
+        } else if (o.precision == BEM_PREC_FP32) {
             bem::gmres_batch(P, P.N, n_rhs, db, du, bem::KrylovOpts{o.tol, o.restart, o.max_iter}, fp32_apply,
                              nullptr, info);
         } else {
@@ -538,6 +591,34 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
             (void)hipFree(tu);
         }
         if (!all) return fail(BEM_WARN_NOT_CONVERGED, "bem_solve: GMRES reached max_iter for some right-hand side");
+        return BEM_OK;
+    });
+}
+
+bem_status bem_apply_preconditioner(bem_problem *p, const bem_solve_opts *opts, const bem_complex *y,
+                                    bem_complex *out, int32_t n_rhs)
+{
+    if (!p || !opts || !y || !out || n_rhs < 0) return fail(BEM_ERR_INVALID_ARG, "bem_apply_preconditioner: bad arguments");
+    if (opts->precond != BEM_PRECOND_OSRC) return fail(BEM_ERR_INVALID_ARG, "bem_apply_preconditioner: precond must be OSRC");
+    if (!(opts->r_eps > 0) || opts->n_pade < 0 || opts->n_pade > 64 || !std::isfinite(opts->theta))
+        return fail(BEM_ERR_INVALID_ARG, "bem_apply_preconditioner: need r_eps > 0, 0 <= n_pade <= 64");
+    if (n_rhs == 0) return BEM_OK;
+    return guarded([&]() -> bem_status {
+        BEM_HIP(hipSetDevice(p->device));
+        const bem::OsrcParams op{opts->n_pade, opts->r_eps, opts->theta, 1e-10, 3000};
+        const size_t n = size_t(n_rhs) * p->N;
+        if (p->flags & BEM_DEVICE_PTRS) {
+            bem::osrc_apply(*p, op, reinterpret_cast<const double2 *>(y), reinterpret_cast<double2 *>(out), n_rhs);
+        } else {
+            double2 *dy = nullptr, *dout = nullptr;
+            dev_alloc(&dy, n);
+            dev_alloc(&dout, n);
+            BEM_HIP(hipMemcpy(dy, y, n * sizeof(double2), hipMemcpyHostToDevice));
+            bem::osrc_apply(*p, op, dy, dout, n_rhs);
+            BEM_HIP(hipMemcpy(out, dout, n * sizeof(double2), hipMemcpyDeviceToHost));
+            (void)hipFree(dy);
+            (void)hipFree(dout);
+        }
         return BEM_OK;
     });
 }

@@ -78,6 +78,14 @@ struct GemmPlan {
     size_t bytes_x, bytes_c;
 };
 
+// OSRC preconditioner parameters (k_osrc.hip).
+struct OsrcParams {
+    int n_pade;
+    double r_eps, theta;
+    double cg_tol;     // relative tolerance of the inner COCG solves
+    int cg_maxit;
+};
+
 struct DomInfo {
     int64_t nv, nt;        // vertices / triangles of the domain
     int64_t v_off, t_off;  // offsets in the global vertex / triangle arrays
@@ -143,6 +151,11 @@ struct bem_problem {
     float *d_gc = nullptr;          // K-slice partial products of the GEMM
     size_t gx_bytes = 0, gc_bytes = 0;
     bool timed_gemm = false;
+
+    // OSRC: vertex adjacency CSR with P1 mass and stiffness values
+    int32_t *d_aptr = nullptr, *d_acol = nullptr;
+    double *d_Mv = nullptr, *d_Sv = nullptr;
+    int64_t a_nnz = 0;
 
     // scratch vectors
     double2 *d_x = nullptr, *d_y = nullptr;
@@ -216,6 +229,10 @@ struct KrylovOpts {
 };
 void gmres_batch(bem_problem &p, int64_t n, int R, const double2 *B, double2 *X, const KrylovOpts &o,
                  const ApplyFn &A, const ApplyFn *M, bem_solve_info *info);
+
+// OSRC preconditioner (k_osrc.hip): Out = P Y for R residual vectors
+void osrc_setup(bem_problem &p);
+void osrc_apply(bem_problem &p, const OsrcParams &o, const double2 *Y, double2 *Out, int R);
 
 // incident fields and right-hand sides (k_field.hip)
 void launch_rhs(bem_problem &p, const bem_incident &inc, double2 *b);

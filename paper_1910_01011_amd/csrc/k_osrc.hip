@@ -1,0 +1,402 @@
+// OSRC block-diagonal preconditioner (paper, operator preconditioning section:
+// eqs. OSRC_prec, OSRC_prec_blocks, OSRC_DtN_NtD_maps).
+//
+// For every domain the Galerkin residual rows are mapped to coefficients by the
+// P1 mass matrix (z = M^-1 r) and then
+//   Dirichlet-equation row:  Lambda_DtN z = i k sqrt(1 + X) z
+//   Neumann-equation row:    Lambda_NtD z = (i k)^-1 (M - S')^-1 M sqrt(1 + X) z
+// with X = -M^-1 S', S' = S / k_eps^2, k_eps = k + 0.4 i k^(1/3) R_eps^(-2/3),
+// k = k0, and the branch-rotated Pade form
+//   sqrt(1 + X) z = C0 z - sum_l A_l (M - B_l S')^-1 S' z.
+// M and S are assembled on the union of all boundaries (block diagonal by
+// domain).  All sparse solves of one application are done together by a batched
+// COCG (conjugate orthogonal CG for complex symmetric matrices) in FP64.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "bem_internal.h"
+
+namespace bem {
+
+using cd = std::complex<double>;
+
+// ---------------------------------------------------------------------------
+// mass and stiffness on the vertex adjacency pattern
+// ---------------------------------------------------------------------------
+
+// one thread per vertex row g: M_gh += |t| (1 + d_ab)/12, S_gh += e_a . e_b / (4 |t|)
+__global__ void k_mass_stiff(const double *__restrict__ verts, const int32_t *__restrict__ tris,
+                             const double *__restrict__ area, const int32_t *__restrict__ v2t_ptr,
+                             const int32_t *__restrict__ v2t, const int32_t *__restrict__ aptr,
+                             const int32_t *__restrict__ acol, int64_t NV, double *__restrict__ Mv,
+                             double *__restrict__ Sv)
+{
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= NV) return;
+    for (int32_t e = aptr[g]; e < aptr[g + 1]; ++e) {
+        Mv[e] = 0.0;
+        Sv[e] = 0.0;
+    }
+    for (int32_t k = v2t_ptr[g]; k < v2t_ptr[g + 1]; ++k) {
+        const int64_t t = v2t[k] / 3;
+        const int a = v2t[k] - 3 * int(t);
+        double P[3][3];
+        for (int c = 0; c < 3; ++c)
+            for (int d = 0; d < 3; ++d) P[c][d] = verts[3 * int64_t(tris[3 * t + c]) + d];
+        double ea[3];
+        for (int d = 0; d < 3; ++d) ea[d] = P[(a + 2) % 3][d] - P[(a + 1) % 3][d];
+        const double ar = area[t];
+        for (int b = 0; b < 3; ++b) {
+            double eb[3];
+            for (int d = 0; d < 3; ++d) eb[d] = P[(b + 2) % 3][d] - P[(b + 1) % 3][d];
+            const int32_t h = tris[3 * t + b];
+            int32_t e = aptr[g];
+            while (e < aptr[g + 1] - 1 && acol[e] != h) ++e;
+            Mv[e] += ar * (a == b ? 2.0 : 1.0) / 12.0;
+            Sv[e] += (ea[0] * eb[0] + ea[1] * eb[1] + ea[2] * eb[2]) / (4.0 * ar);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// batched COCG pieces: G systems (M - c_g S) x_g = b_g, vectors [G][n]
+// ---------------------------------------------------------------------------
+
+__global__ void k_spmv_shift(const int32_t *__restrict__ aptr, const int32_t *__restrict__ acol,
+                             const double *__restrict__ Mv, const double *__restrict__ Sv,
+                             const double2 *__restrict__ c, const double2 *__restrict__ P, int64_t n, int G,
+                             double2 *__restrict__ Q)
+{
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n * G) return;
+    const int64_t g = idx / n, i = idx - g * n;
+    const double2 *p = P + g * n;
+    double mr = 0, mi = 0, sr = 0, si = 0;
+    for (int32_t e = aptr[i]; e < aptr[i + 1]; ++e) {
+        const double2 v = p[acol[e]];
+        mr += Mv[e] * v.x;
+        mi += Mv[e] * v.y;
+        sr += Sv[e] * v.x;
+        si += Sv[e] * v.y;
+    }
+    const double2 cg = c[g];
+    Q[idx] = make_double2(mr - (cg.x * sr - cg.y * si), mi - (cg.x * si + cg.y * sr));
+}
+
+// out[g] = sum_i a_g[i] b_g[i] (no conjugation), two-stage fixed-order reduction
+__global__ __launch_bounds__(256) void k_dotu_partial(const double2 *__restrict__ A, const double2 *__restrict__ B,
+                                                      int64_t n, int nblk, double2 *__restrict__ part)
+{
+    __shared__ double sr[256], si[256];
+    const int blk = blockIdx.x, g = blockIdx.y, tid = threadIdx.x;
+    const double2 *a = A + int64_t(g) * n, *b = B + int64_t(g) * n;
+    double re = 0, im = 0;
+    for (int64_t k = int64_t(blk) * 256 + tid; k < n; k += int64_t(nblk) * 256) {
+        const double2 x = a[k], y = b[k];
+        re += x.x * y.x - x.y * y.y;
+        im += x.x * y.y + x.y * y.x;
+    }
+    sr[tid] = re;
+    si[tid] = im;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+            sr[tid] += sr[tid + s];
+            si[tid] += si[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) part[int64_t(g) * nblk + blk] = make_double2(sr[0], si[0]);
+}
+
+__global__ void k_part_final(const double2 *__restrict__ part, int nblk, int G, double2 *__restrict__ out)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    double re = 0, im = 0;
+    for (int b = 0; b < nblk; ++b) {
+        re += part[int64_t(g) * nblk + b].x;
+        im += part[int64_t(g) * nblk + b].y;
+    }
+    out[g] = make_double2(re, im);
+}
+
+// x += alpha p, r -= alpha q
+__global__ void k_cocg_xr(const double2 *__restrict__ alpha, const double2 *__restrict__ P,
+                          const double2 *__restrict__ Q, double2 *__restrict__ X, double2 *__restrict__ R, int64_t n,
+                          int G)
+{
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n * G) return;
+    const double2 a = alpha[idx / n], p = P[idx], q = Q[idx];
+    X[idx] = make_double2(X[idx].x + a.x * p.x - a.y * p.y, X[idx].y + a.x * p.y + a.y * p.x);
+    R[idx] = make_double2(R[idx].x - (a.x * q.x - a.y * q.y), R[idx].y - (a.x * q.y + a.y * q.x));
+}
+
+// p = r + beta p
+__global__ void k_cocg_p(const double2 *__restrict__ beta, const double2 *__restrict__ R, double2 *__restrict__ P,
+                         int64_t n, int G)
+{
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n * G) return;
+    const double2 b = beta[idx / n], p = P[idx], r = R[idx];
+    P[idx] = make_double2(r.x + b.x * p.x - b.y * p.y, r.y + b.x * p.y + b.y * p.x);
+}
+
+// ---------------------------------------------------------------------------
+// preconditioner pieces
+// ---------------------------------------------------------------------------
+
+// residual rows (R vectors in unknown order) -> [2R][NV]: D rows then N rows
+__global__ void k_osrc_split(const double2 *__restrict__ Y, const int32_t *__restrict__ rowD,
+                             const int32_t *__restrict__ rowN, int64_t NV, int64_t N, int R, double2 *__restrict__ U)
+{
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= NV * R) return;
+    const int64_t r = idx / NV, g = idx - r * NV;
+    U[(2 * r) * NV + g] = Y[r * N + rowD[g]];
+    U[(2 * r + 1) * NV + g] = Y[r * N + rowN[g]];
+}
+
+// out[(v * L + l)][i] = sum_e S[e] z_v[col] * s  for l < L   (S' z replicated per Pade term)
+__global__ void k_osrc_sprime(const int32_t *__restrict__ aptr, const int32_t *__restrict__ acol,
+                              const double *__restrict__ Sv, const double2 *__restrict__ Z, int64_t n, int V, int L,
+                              double2 s, double2 *__restrict__ out)
+{
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n * V) return;
+    const int64_t v = idx / n, i = idx - v * n;
+    double re = 0, im = 0;
+    for (int32_t e = aptr[i]; e < aptr[i + 1]; ++e) {
+        const double2 z = Z[v * n + acol[e]];
+        re += Sv[e] * z.x;
+        im += Sv[e] * z.y;
+    }
+    const double2 w = make_double2(re * s.x - im * s.y, re * s.y + im * s.x);
+    for (int l = 0; l < L; ++l) out[(v * L + l) * n + i] = w;
+}
+
+// root_v = C0 z_v - sum_l A_l t_(v,l);  D rows: result i k root; N rows: M root (input of the last solve)
+__global__ void k_osrc_combine(const int32_t *__restrict__ aptr, const int32_t *__restrict__ acol,
+                               const double *__restrict__ Mv, const double2 *__restrict__ Z,
+                               const double2 *__restrict__ T, const double2 *__restrict__ Al, int L, double2 C0,
+                               double2 ik, int64_t n, int R, double2 *__restrict__ rootD, double2 *__restrict__ rootN)
+{
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n * 2 * R) return;
+    const int64_t v = idx / n, i = idx - v * n;
+    const double2 z = Z[idx];
+    double re = C0.x * z.x - C0.y * z.y, im = C0.x * z.y + C0.y * z.x;
+    for (int l = 0; l < L; ++l) {
+        const double2 t = T[(v * L + l) * n + i], a = Al[l];
+        re -= a.x * t.x - a.y * t.y;
+        im -= a.x * t.y + a.y * t.x;
+    }
+    const int64_t r = v >> 1;
+    if ((v & 1) == 0) rootD[r * n + i] = make_double2(ik.x * re - ik.y * im, ik.x * im + ik.y * re);
+    else rootN[r * n + i] = make_double2(re, im);
+}
+
+// w = M x per vector
+__global__ void k_spmv_mass(const int32_t *__restrict__ aptr, const int32_t *__restrict__ acol,
+                            const double *__restrict__ Mv, const double2 *__restrict__ X, int64_t n, int V,
+                            double2 *__restrict__ W)
+{
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n * V) return;
+    const int64_t v = idx / n, i = idx - v * n;
+    double re = 0, im = 0;
+    for (int32_t e = aptr[i]; e < aptr[i + 1]; ++e) {
+        const double2 x = X[v * n + acol[e]];
+        re += Mv[e] * x.x;
+        im += Mv[e] * x.y;
+    }
+    W[idx] = make_double2(re, im);
+}
+
+// out (unknown order): D rows <- rootD, N rows <- s * wN
+__global__ void k_osrc_out(const double2 *__restrict__ rootD, const double2 *__restrict__ wN, double2 s,
+                           const int32_t *__restrict__ rowD, const int32_t *__restrict__ rowN, int64_t NV, int64_t N,
+                           int R, double2 *__restrict__ Y)
+{
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= NV * R) return;
+    const int64_t r = idx / NV, g = idx - r * NV;
+    Y[r * N + rowD[g]] = rootD[idx];
+    const double2 w = wN[idx];
+    Y[r * N + rowN[g]] = make_double2(s.x * w.x - s.y * w.y, s.x * w.y + s.y * w.x);
+}
+
+static unsigned nb(int64_t n) { return unsigned((n + 255) / 256); }
+
+struct OsrcBuf {
+    double2 *p = nullptr;
+    explicit OsrcBuf(size_t n) { BEM_HIP(hipMalloc(&p, std::max<size_t>(1, n) * sizeof(double2))); }
+    ~OsrcBuf() { (void)hipFree(p); }
+};
+
+void osrc_setup(bem_problem &p)
+{
+    if (p.d_aptr) return;
+    // vertex adjacency (vertices sharing a triangle), sorted, including the diagonal
+    std::vector<std::vector<int32_t>> adj(p.NV);
+    for (int64_t t = 0; t < p.NT; ++t)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) adj[p.h_tris[3 * t + a]].push_back(p.h_tris[3 * t + b]);
+    std::vector<int32_t> ptr(p.NV + 1, 0), col;
+    for (int64_t g = 0; g < p.NV; ++g) {
+        auto &r = adj[g];
+        std::sort(r.begin(), r.end());
+        r.erase(std::unique(r.begin(), r.end()), r.end());
+        ptr[g + 1] = ptr[g] + int32_t(r.size());
+        col.insert(col.end(), r.begin(), r.end());
+    }
+    p.a_nnz = ptr[p.NV];
+    BEM_HIP(hipMalloc(&p.d_aptr, ptr.size() * sizeof(int32_t)));
+    BEM_HIP(hipMalloc(&p.d_acol, col.size() * sizeof(int32_t)));
+    BEM_HIP(hipMalloc(&p.d_Mv, col.size() * sizeof(double)));
+    BEM_HIP(hipMalloc(&p.d_Sv, col.size() * sizeof(double)));
+    BEM_HIP(hipMemcpyAsync(p.d_aptr, ptr.data(), ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice, p.stream));
+    BEM_HIP(hipMemcpyAsync(p.d_acol, col.data(), col.size() * sizeof(int32_t), hipMemcpyHostToDevice, p.stream));
+    k_mass_stiff<<<dim3(nb(p.NV)), dim3(256), 0, p.stream>>>(p.d_verts, p.d_tris, p.d_area, p.d_v2t_ptr, p.d_v2t,
+                                                            p.d_aptr, p.d_acol, p.NV, p.d_Mv, p.d_Sv);
+    BEM_HIP(hipGetLastError());
+    BEM_HIP(hipStreamSynchronize(p.stream));
+}
+
+// Batched COCG: (M - c_g S) x_g = b_g, zero initial guess, stop per system at
+// ||r|| <= tol ||b||; returns the largest iteration count.
+static int cocg_batch(bem_problem &p, int G, const std::vector<cd> &c, const double2 *B, double2 *X, double tol,
+                      int maxit)
+{
+    const int64_t n = p.NV;
+    hipStream_t s = p.stream;
+    const size_t tot = size_t(G) * n;
+    OsrcBuf R(tot), Pp(tot), Q(tot), sc{size_t(G)}, cdev{size_t(G)};
+    const int nblk = int(std::min<int64_t>(64, (n + 255) / 256));
+    OsrcBuf part(size_t(G) * nblk);
+    auto up = [&](const std::vector<cd> &v, double2 *d) {
+        std::vector<double2> t(v.size());
+        for (size_t i = 0; i < v.size(); ++i) t[i] = make_double2(v[i].real(), v[i].imag());
+        BEM_HIP(hipMemcpyAsync(d, t.data(), t.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+        BEM_HIP(hipStreamSynchronize(s));
+    };
+    auto dotu = [&](const double2 *a, const double2 *b, std::vector<cd> &out) {
+        k_dotu_partial<<<dim3(unsigned(nblk), unsigned(G)), dim3(256), 0, s>>>(a, b, n, nblk, part.p);
+        BEM_HIP(hipGetLastError());
+        k_part_final<<<dim3(unsigned((G + 63) / 64)), dim3(64), 0, s>>>(part.p, nblk, G, sc.p);
+        BEM_HIP(hipGetLastError());
+        std::vector<double2> t(G);
+        BEM_HIP(hipMemcpyAsync(t.data(), sc.p, G * sizeof(double2), hipMemcpyDeviceToHost, s));
+        BEM_HIP(hipStreamSynchronize(s));
+        out.resize(G);
+        for (int g = 0; g < G; ++g) out[g] = cd(t[g].x, t[g].y);
+    };
+    auto norms = [&](const double2 *a, std::vector<double> &out) {
+        bdot(s, a, 0, 1, a, n, G, part.p, nblk, sc.p);
+        std::vector<double2> t(G);
+        BEM_HIP(hipMemcpyAsync(t.data(), sc.p, G * sizeof(double2), hipMemcpyDeviceToHost, s));
+        BEM_HIP(hipStreamSynchronize(s));
+        out.resize(G);
+        for (int g = 0; g < G; ++g) out[g] = std::sqrt(std::max(0.0, t[g].x));
+    };
+    up(c, cdev.p);
+    BEM_HIP(hipMemsetAsync(X, 0, tot * sizeof(double2), s));
+    BEM_HIP(hipMemcpyAsync(R.p, B, tot * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    BEM_HIP(hipMemcpyAsync(Pp.p, B, tot * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    std::vector<double> bn, rn;
+    norms(B, bn);
+    std::vector<cd> rho, pq, rho2;
+    dotu(R.p, R.p, rho);
+    std::vector<char> done(G, 0);
+    for (int g = 0; g < G; ++g) done[g] = bn[g] == 0.0;
+    int it = 0;
+    for (; it < maxit; ++it) {
+        if (std::all_of(done.begin(), done.end(), [](char d) { return d != 0; })) break;
+        k_spmv_shift<<<dim3(nb(int64_t(tot))), dim3(256), 0, s>>>(p.d_aptr, p.d_acol, p.d_Mv, p.d_Sv, cdev.p, Pp.p, n,
+                                                                  G, Q.p);
+        BEM_HIP(hipGetLastError());
+        dotu(Pp.p, Q.p, pq);
+        std::vector<cd> alpha(G);
+        for (int g = 0; g < G; ++g) alpha[g] = done[g] || pq[g] == cd(0) ? cd(0) : rho[g] / pq[g];
+        up(alpha, sc.p);
+        k_cocg_xr<<<dim3(nb(int64_t(tot))), dim3(256), 0, s>>>(sc.p, Pp.p, Q.p, X, R.p, n, G);
+        BEM_HIP(hipGetLastError());
+        norms(R.p, rn);
+        for (int g = 0; g < G; ++g)
+            if (rn[g] <= tol * bn[g]) done[g] = 1;
+        dotu(R.p, R.p, rho2);
+        std::vector<cd> beta(G);
+        for (int g = 0; g < G; ++g) beta[g] = done[g] || rho[g] == cd(0) ? cd(0) : rho2[g] / rho[g];
+        rho = rho2;
+        up(beta, sc.p);
+        k_cocg_p<<<dim3(nb(int64_t(tot))), dim3(256), 0, s>>>(sc.p, R.p, Pp.p, n, G);
+        BEM_HIP(hipGetLastError());
+    }
+    return it;
+}
+
+void osrc_apply(bem_problem &p, const OsrcParams &o, const double2 *Y, double2 *Out, int R)
+{
+    osrc_setup(p);
+    const int64_t n = p.NV;
+    hipStream_t s = p.stream;
+    const int L = o.n_pade;
+    // coefficients
+    const cd k(p.k0re, p.k0im);
+    const cd ke = k + cd(0.0, 0.4 * std::cbrt(p.k0re) * std::pow(o.r_eps, -2.0 / 3.0));
+    const cd ke2 = ke * ke;
+    std::vector<cd> A(L), B(L);
+    const cd e = std::exp(cd(0.0, -o.theta)), c = e - 1.0;
+    cd C0 = 1.0;
+    for (int l = 1; l <= L; ++l) {
+        const double a = 2.0 / (2 * L + 1) * std::pow(std::sin(l * M_PI / (2 * L + 1)), 2);
+        const double b = std::pow(std::cos(l * M_PI / (2 * L + 1)), 2);
+        const cd D = 1.0 + b * c;
+        C0 += a * c / D;
+        A[l - 1] = std::exp(cd(0.0, -o.theta / 2.0)) * a / (D * D);
+        B[l - 1] = e * b / D;
+    }
+    C0 *= std::exp(cd(0.0, o.theta / 2.0));
+    const cd ik = cd(0.0, 1.0) * k;
+    // z = M^-1 (D rows, N rows)
+    OsrcBuf U(size_t(2 * R) * n), Z(size_t(2 * R) * n);
+    k_osrc_split<<<dim3(nb(n * R)), dim3(256), 0, s>>>(Y, p.d_rowD, p.d_rowN, n, p.N, R, U.p);
+    BEM_HIP(hipGetLastError());
+    cocg_batch(p, 2 * R, std::vector<cd>(2 * R, cd(0.0)), U.p, Z.p, o.cg_tol, o.cg_maxit);
+    // t_(v,l) = (M - B_l S')^-1 S' z_v
+    OsrcBuf Bt(size_t(2 * R) * L * n), T(size_t(2 * R) * L * n);
+    const cd inv = 1.0 / ke2;
+    k_osrc_sprime<<<dim3(nb(n * 2 * R)), dim3(256), 0, s>>>(p.d_aptr, p.d_acol, p.d_Sv, Z.p, n, 2 * R, L,
+                                                            make_double2(inv.real(), inv.imag()), Bt.p);
+    BEM_HIP(hipGetLastError());
+    std::vector<cd> shifts(size_t(2 * R) * L);
+    for (int v = 0; v < 2 * R; ++v)
+        for (int l = 0; l < L; ++l) shifts[size_t(v) * L + l] = B[l] / ke2;
+    if (L > 0) cocg_batch(p, 2 * R * L, shifts, Bt.p, T.p, o.cg_tol, o.cg_maxit);
+    // roots; D rows finished (i k root), N rows need (M - S')^-1 M root
+    OsrcBuf Al(size_t(std::max(L, 1))), rootD(size_t(R) * n), rootN(size_t(R) * n), MN(size_t(R) * n),
+        WN(size_t(R) * n);
+    {
+        std::vector<double2> t(L);
+        for (int l = 0; l < L; ++l) t[l] = make_double2(A[l].real(), A[l].imag());
+        if (L > 0) BEM_HIP(hipMemcpyAsync(Al.p, t.data(), L * sizeof(double2), hipMemcpyHostToDevice, s));
+        BEM_HIP(hipStreamSynchronize(s));
+    }
+    k_osrc_combine<<<dim3(nb(n * 2 * R)), dim3(256), 0, s>>>(p.d_aptr, p.d_acol, p.d_Mv, Z.p, T.p, Al.p, L,
+                                                             make_double2(C0.real(), C0.imag()),
+                                                             make_double2(ik.real(), ik.imag()), n, R, rootD.p, rootN.p);
+    BEM_HIP(hipGetLastError());
+    k_spmv_mass<<<dim3(nb(n * R)), dim3(256), 0, s>>>(p.d_aptr, p.d_acol, p.d_Mv, rootN.p, n, R, MN.p);
+    BEM_HIP(hipGetLastError());
+    cocg_batch(p, R, std::vector<cd>(R, inv), MN.p, WN.p, o.cg_tol, o.cg_maxit);
+    const cd sN = 1.0 / ik;
+    k_osrc_out<<<dim3(nb(n * R)), dim3(256), 0, s>>>(rootD.p, WN.p, make_double2(sN.real(), sN.imag()), p.d_rowD,
+                                                     p.d_rowN, n, p.N, R, Out);
+    BEM_HIP(hipGetLastError());
+    BEM_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace bem
