@@ -119,3 +119,59 @@ def kidney(f_rel: float = 1.0, elements_per_wavelength: float = 6.0, level: int 
     return Problem([Domain(vk, tk, complex(k0 / s_k), 1.066, "kidney"),
                     Domain(vs, ts, complex(k0 / s_f), 0.917, "fat_shell")], complex(k0), 1.0,
                    f"kidney_l{level}")
+
+
+_MESH_CACHE: dict = {}
+
+
+def kidney_level(f_rel: float, elements_per_wavelength: float) -> int:
+    """Icosphere level giving element size h = min(1, s_fat)/f_rel/e on the largest surface."""
+    s_f = 0.941
+    h = min(1.0, s_f) / f_rel / elements_per_wavelength
+    return int(np.clip(np.ceil(np.log2(1.05 * (5.0 + 2.0 / 3.0 + 1.0) / h)), 1, 8))
+
+
+def kidney_vertices(level: int) -> int:
+    return 3 * (10 * 4 ** level + 2)
+
+
+def serving_stream(rate: float, n_requests: int, seed_arrivals: int, seed_params: int,
+                   vertex_range=(2000, 40000), rhs_range=(1, 64), f_range=(0.5, 1.5), epw=(4, 5, 6)):
+    """Poisson arrivals of kidney + fat-shell solve requests (serving workload).
+
+    Per request: f_rel ~ U[f_range], elements per wavelength e ~ U{epw}, mesh
+    level from h = min(lambda_0, lambda_j)/e, redrawn until the total vertex
+    count lies in vertex_range; R ~ U{rhs_range} transducer elements drawn from
+    a 256-element bowl (aperture 20, focal length 27) focused on the kidney
+    centre with axis along [1, -1, 0], one right-hand side per element.
+    Returns dicts with the problem, the element geometry and the arrival time.
+    """
+    from . import pistons
+
+    ra = np.random.default_rng(seed_arrivals)
+    rp = np.random.default_rng(seed_params)
+    arrivals = np.cumsum(ra.exponential(1.0 / rate, size=n_requests))
+    centres, normals, radius = pistons.bowl_array(256, 27.0, 20.0, axis=(1.0, -1.0, 0.0))
+    out = []
+    for i in range(n_requests):
+        for _ in range(1000):
+            f = rp.uniform(*f_range)
+            e = int(rp.choice(epw))
+            level = kidney_level(f, e)
+            if vertex_range[0] <= kidney_vertices(level) <= vertex_range[1]:
+                break
+        else:
+            raise RuntimeError("no mesh level inside the vertex range")
+        R = int(rp.integers(rhs_range[0], rhs_range[1] + 1))
+        sel = np.sort(rp.choice(256, size=R, replace=False))
+        key = level
+        if key not in _MESH_CACHE:
+            _MESH_CACHE[key] = kidney(1.0, level=level)
+        base = _MESH_CACHE[key]
+        k0 = 2.0 * np.pi * f
+        doms = [Domain(d.vertices, d.triangles, complex(k0 / s), d.rho, d.name)
+                for d, s in zip(base.domains, (1.04, 0.941))]
+        prob = Problem(doms, complex(k0), 1.0, f"kidney_l{level}_f{f:.2f}")
+        out.append({"problem": prob, "f_rel": f, "level": level, "arrival": float(arrivals[i]),
+                    "piston_centres": centres[sel], "piston_normals": normals[sel], "piston_radius": radius})
+    return out

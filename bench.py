@@ -139,16 +139,23 @@ def main():
                      "kernel": "k_pairs", "kernel_ms": pair_avg, "flop_per_pair": FLOP_PER_PAIR},
     }
     if not args.no_solve:
-        from bem_inputs import configs as _c  # noqa: F401
+        # GMRES(100) on the on-the-fly operator, plane wave along +z, without and
+        # with the OSRC preconditioner (N_Pade = 4, R_eps = 0.1 = radius / 10)
         inc = bem.Incident.plane_waves([[0.0, 0.0, 1.0]])
         b = P.rhs(inc)
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        u, info = P.solve(b, bem.solve_options(tol=1e-5, restart=100, max_iter=400))
-        torch.cuda.synchronize()
-        ts = time.perf_counter() - ts
-        out["gmres"] = {"time_to_solve_s": ts, "iterations": info[0]["iterations"],
-                        "rel_residual": info[0]["rel_residual"], "converged": info[0]["converged"], "tol": 1e-5}
+        g = {}
+        for pname, pc in (("plain", bem.BEM_PRECOND_NONE), ("osrc", bem.BEM_PRECOND_OSRC)):
+            for tol in (1e-5, 1e-6):
+                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                u, info = P.solve(b, bem.solve_options(tol=tol, restart=100, max_iter=400, precond=pc, n_pade=4,
+                                                       r_eps=0.1, theta=np.pi / 3))
+                torch.cuda.synchronize()
+                ts = time.perf_counter() - ts
+                g[f"{pname}_tol{tol:g}"] = {"time_to_solve_s": ts, "iterations": info[0]["iterations"],
+                                            "rel_residual": info[0]["rel_residual"],
+                                            "converged": info[0]["converged"]}
+        out["gmres"] = g
     if not args.no_assembled:
         del P
         torch.cuda.empty_cache()

@@ -172,9 +172,12 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
 /* Out = P y for n_rhs residual vectors y [n_rhs][n_unknowns], P the OSRC
  * block-diagonal preconditioner of opts (precond = BEM_PRECOND_OSRC, n_pade,
  * r_eps, theta; paper eqs. OSRC_prec, OSRC_prec_blocks, OSRC_DtN_NtD_maps):
- * per domain, Lambda_DtN M^-1 on the Dirichlet-equation rows and
- * Lambda_NtD M^-1 on the Neumann-equation rows, k = k0.  Inner sparse solves
- * by COCG in FP64 to 1e-10. */
+ * per domain, Lambda_DtN M^-1 applied to the Dirichlet-equation rows and
+ * Lambda_NtD M^-1 to the Neumann-equation rows, k = k0, with the paper's
+ * permutation of the unknowns to [u_N; u_D] folded in: the Lambda_DtN result
+ * is returned in the u_N positions and the Lambda_NtD result in the u_D
+ * positions (GMRES on P A u = P b).  Inner sparse solves by COCG in FP64 to
+ * 1e-10. */
 bem_status bem_apply_preconditioner(bem_problem *p, const bem_solve_opts *opts, const bem_complex *y,
                                     bem_complex *out, int32_t n_rhs);
 

@@ -459,3 +459,41 @@ def field(problem, u, points, p_inc=None):
             sl, dl = potentials(m, d.k, uD, (d.rho / problem.rho0) * uN, pts[inside])
             p[inside] += sl - dl
     return p, region
+
+
+def piston_sources(k0, centres, normals, radius, amplitudes):
+    """Monopoles equivalent to flat baffled pistons (test infrastructure).
+
+    Each piston of radius a radiates p(x) = (-i k0 / 2 pi) A int_disc e^{i k0 r}/r dS
+    (Rayleigh integral, unit rho c u).  The disc integral uses 3 Gauss-Legendre
+    radii on [0, a] with the weight r dr and 8 equally spaced angles, i.e. 24
+    monopoles a_s G(x, s) with a_s = (-i k0 / 2 pi) 4 pi A w_r r dtheta.
+    Returns (positions [S, 3], amplitudes [S], piston index [S]).
+    """
+    g, gw = np.polynomial.legendre.leggauss(3)
+    g, gw = (g + 1.0) / 2.0, gw / 2.0
+    k0 = complex(k0)
+    C = np.atleast_2d(np.asarray(centres, dtype=np.float64))
+    Nn = np.atleast_2d(np.asarray(normals, dtype=np.float64))
+    A = np.broadcast_to(np.asarray(amplitudes, dtype=np.complex128), (C.shape[0],))
+    pos, amp, idx = [], [], []
+    for e, (c, n, a_e) in enumerate(zip(C, Nn, A)):
+        n = n / np.linalg.norm(n)
+        helper = np.eye(3)[np.argmin(np.abs(n))]
+        e1 = np.cross(n, helper)
+        e1 /= np.linalg.norm(e1)
+        e2 = np.cross(n, e1)
+        for gi, wi in zip(g, gw):
+            r = radius * gi
+            for j in range(8):
+                th = 2.0 * np.pi * j / 8.0
+                pos.append(c + r * (np.cos(th) * e1 + np.sin(th) * e2))
+                amp.append((-1j * k0 / (2.0 * np.pi)) * 4.0 * np.pi * a_e * (radius * wi) * r * (2.0 * np.pi / 8.0))
+                idx.append(e)
+    return np.asarray(pos), np.asarray(amp), np.asarray(idx)
+
+
+def piston_field(k0, centres, normals, radius, amplitudes):
+    """(p_fn, dpdn_fn) of the summed pistons (see piston_sources)."""
+    pos, amp, _ = piston_sources(k0, centres, normals, radius, amplitudes)
+    return point_sources(k0, pos, amp)

@@ -77,8 +77,17 @@ def osrc_maps(v, t, k, r_eps, n_pade, theta):
 
 
 def preconditioner_matrix(problem, r_eps, n_pade=4, theta=np.pi / 3):
-    """Dense left preconditioner P = blockdiag_j(diag(Lambda_DtN M^-1, Lambda_NtD M^-1))
-    in the unknown order of the PMCHWT system (rows: [Dirichlet row; Neumann row] per domain)."""
+    """Dense left preconditioner in the unknown order of the PMCHWT system.
+
+    The paper permutes the unknowns of every domain to [u_N; u_D] so that V and
+    W sit on the diagonal of the Calderon blocks, and applies
+    C = diag(Lambda_DtN, Lambda_NtD) to the (unchanged) rows:
+    C A Pi y = C b with u = Pi y.  GMRES on that system is identical (up to the
+    same permutation of all vectors) to GMRES on (Pi C) A u = Pi C b, so the
+    returned matrix is P = Pi C: its u_D positions receive
+    Lambda_NtD M^-1 (Neumann-equation rows) and its u_N positions
+    Lambda_DtN M^-1 (Dirichlet-equation rows).
+    """
     off = offsets(problem)
     n = off[-1]
     P = np.zeros((n, n), dtype=np.complex128)
@@ -86,6 +95,6 @@ def preconditioner_matrix(problem, r_eps, n_pade=4, theta=np.pi / 3):
         dtn, ntd, M = osrc_maps(d.vertices, d.triangles, problem.k0, r_eps, n_pade, theta)
         Minv = np.linalg.inv(M)
         nv = d.n_vertices
-        P[off[j]:off[j] + nv, off[j]:off[j] + nv] = dtn @ Minv
-        P[off[j] + nv:off[j + 1], off[j] + nv:off[j + 1]] = ntd @ Minv
+        P[off[j] + nv:off[j + 1], off[j]:off[j] + nv] = dtn @ Minv
+        P[off[j]:off[j] + nv, off[j] + nv:off[j + 1]] = ntd @ Minv
     return P

@@ -680,7 +680,6 @@ bem_status bem_evaluate_field(bem_problem *p, const bem_complex *u, const bem_in
 bem_status bem_footprint_bytes(const bem_domain *domains, int32_t n_domains, const bem_assemble_opts *opts,
                                int32_t n_rhs, int32_t restart, uint64_t *bytes)
 {
-    (void)opts;
     if (!domains || n_domains < 1 || !bytes || n_rhs < 0 || restart < 0)
         return fail(BEM_ERR_INVALID_ARG, "bem_footprint_bytes: bad arguments");
     uint64_t nv = 0, nt = 0;
@@ -696,7 +695,14 @@ bem_status bem_footprint_bytes(const bem_domain *domains, int32_t n_domains, con
     b += M * 64 + 2 * n_split * 10 * M * 8 + M * 80;   // trial records, partials, potentials
     b += nv * 24 * (4 + 4 * 64);                  // correction CSR (about 24 entries per row)
     b += uint64_t(n_rhs) * N * 16 * 2;            // x, y
-    b += uint64_t(restart + 1) * N * 16;          // Krylov basis of one right-hand side
+    b += uint64_t(restart + 1) * N * 16 * uint64_t(n_rhs > 0 ? n_rhs : 1);   // Krylov bases
+    const int mode = opts ? opts->mode : BEM_OTF;
+    if (mode != BEM_OTF) {
+        b += 8 * N * N;                                               // complex64 matrix
+        if (mode == BEM_ASSEMBLED_SPLIT_BF16) b += 8 * N * N;        // BF16 hi/lo planes
+        const uint64_t Np = ((2 * uint64_t(n_rhs) + 127) / 128) * 128;
+        b += Np * 2 * N * 4 + 16 * N * Np * 4;                        // packed X, K-slice partials
+    }
     *bytes = b;
     return BEM_OK;
 }

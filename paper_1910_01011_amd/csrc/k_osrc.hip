@@ -2,7 +2,8 @@
 // eqs. OSRC_prec, OSRC_prec_blocks, OSRC_DtN_NtD_maps).
 //
 // For every domain the Galerkin residual rows are mapped to coefficients by the
-// P1 mass matrix (z = M^-1 r) and then
+// P1 mass matrix (z = M^-1 r) and then (the results land in the swapped
+// positions, see k_osrc_out)
 //   Dirichlet-equation row:  Lambda_DtN z = i k sqrt(1 + X) z
 //   Neumann-equation row:    Lambda_NtD z = (i k)^-1 (M - S')^-1 M sqrt(1 + X) z
 // with X = -M^-1 S', S' = S / k_eps^2, k_eps = k + 0.4 i k^(1/3) R_eps^(-2/3),
@@ -58,91 +59,6 @@ __global__ void k_mass_stiff(const double *__restrict__ verts, const int32_t *__
             Sv[e] += (ea[0] * eb[0] + ea[1] * eb[1] + ea[2] * eb[2]) / (4.0 * ar);
         }
     }
-}
-
-// ---------------------------------------------------------------------------
-// batched COCG pieces: G systems (M - c_g S) x_g = b_g, vectors [G][n]
-// ---------------------------------------------------------------------------
-
-__global__ void k_spmv_shift(const int32_t *__restrict__ aptr, const int32_t *__restrict__ acol,
-                             const double *__restrict__ Mv, const double *__restrict__ Sv,
-                             const double2 *__restrict__ c, const double2 *__restrict__ P, int64_t n, int G,
-                             double2 *__restrict__ Q)
-{
-    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= n * G) return;
-    const int64_t g = idx / n, i = idx - g * n;
-    const double2 *p = P + g * n;
-    double mr = 0, mi = 0, sr = 0, si = 0;
-    for (int32_t e = aptr[i]; e < aptr[i + 1]; ++e) {
-        const double2 v = p[acol[e]];
-        mr += Mv[e] * v.x;
-        mi += Mv[e] * v.y;
-        sr += Sv[e] * v.x;
-        si += Sv[e] * v.y;
-    }
-    const double2 cg = c[g];
-    Q[idx] = make_double2(mr - (cg.x * sr - cg.y * si), mi - (cg.x * si + cg.y * sr));
-}
-
-// out[g] = sum_i a_g[i] b_g[i] (no conjugation), two-stage fixed-order reduction
-__global__ __launch_bounds__(256) void k_dotu_partial(const double2 *__restrict__ A, const double2 *__restrict__ B,
-                                                      int64_t n, int nblk, double2 *__restrict__ part)
-{
-    __shared__ double sr[256], si[256];
-    const int blk = blockIdx.x, g = blockIdx.y, tid = threadIdx.x;
-    const double2 *a = A + int64_t(g) * n, *b = B + int64_t(g) * n;
-    double re = 0, im = 0;
-    for (int64_t k = int64_t(blk) * 256 + tid; k < n; k += int64_t(nblk) * 256) {
-        const double2 x = a[k], y = b[k];
-        re += x.x * y.x - x.y * y.y;
-        im += x.x * y.y + x.y * y.x;
-    }
-    sr[tid] = re;
-    si[tid] = im;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) {
-            sr[tid] += sr[tid + s];
-            si[tid] += si[tid + s];
-        }
-        __syncthreads();
-    }
-    if (tid == 0) part[int64_t(g) * nblk + blk] = make_double2(sr[0], si[0]);
-}
-
-__global__ void k_part_final(const double2 *__restrict__ part, int nblk, int G, double2 *__restrict__ out)
-{
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= G) return;
-    double re = 0, im = 0;
-    for (int b = 0; b < nblk; ++b) {
-        re += part[int64_t(g) * nblk + b].x;
-        im += part[int64_t(g) * nblk + b].y;
-    }
-    out[g] = make_double2(re, im);
-}
-
-// x += alpha p, r -= alpha q
-__global__ void k_cocg_xr(const double2 *__restrict__ alpha, const double2 *__restrict__ P,
-                          const double2 *__restrict__ Q, double2 *__restrict__ X, double2 *__restrict__ R, int64_t n,
-                          int G)
-{
-    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= n * G) return;
-    const double2 a = alpha[idx / n], p = P[idx], q = Q[idx];
-    X[idx] = make_double2(X[idx].x + a.x * p.x - a.y * p.y, X[idx].y + a.x * p.y + a.y * p.x);
-    R[idx] = make_double2(R[idx].x - (a.x * q.x - a.y * q.y), R[idx].y - (a.x * q.y + a.y * q.x));
-}
-
-// p = r + beta p
-__global__ void k_cocg_p(const double2 *__restrict__ beta, const double2 *__restrict__ R, double2 *__restrict__ P,
-                         int64_t n, int G)
-{
-    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= n * G) return;
-    const double2 b = beta[idx / n], p = P[idx], r = R[idx];
-    P[idx] = make_double2(r.x + b.x * p.x - b.y * p.y, r.y + b.x * p.y + b.y * p.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -216,7 +132,10 @@ __global__ void k_spmv_mass(const int32_t *__restrict__ aptr, const int32_t *__r
     W[idx] = make_double2(re, im);
 }
 
-// out (unknown order): D rows <- rootD, N rows <- s * wN
+// out (unknown order), with the paper's permutation of the unknowns of every
+// domain to [u_N; u_D] folded in (GMRES on C A Pi y = C b is GMRES on
+// (Pi C) A u = Pi C b): u_N positions <- Lambda_DtN result of the Dirichlet
+// rows (rootD), u_D positions <- Lambda_NtD result of the Neumann rows (s wN)
 __global__ void k_osrc_out(const double2 *__restrict__ rootD, const double2 *__restrict__ wN, double2 s,
                            const int32_t *__restrict__ rowD, const int32_t *__restrict__ rowN, int64_t NV, int64_t N,
                            int R, double2 *__restrict__ Y)
@@ -224,17 +143,24 @@ __global__ void k_osrc_out(const double2 *__restrict__ rootD, const double2 *__r
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= NV * R) return;
     const int64_t r = idx / NV, g = idx - r * NV;
-    Y[r * N + rowD[g]] = rootD[idx];
+    Y[r * N + rowN[g]] = rootD[idx];
     const double2 w = wN[idx];
-    Y[r * N + rowN[g]] = make_double2(s.x * w.x - s.y * w.y, s.x * w.y + s.y * w.x);
+    Y[r * N + rowD[g]] = make_double2(s.x * w.x - s.y * w.y, s.x * w.y + s.y * w.x);
 }
 
 static unsigned nb(int64_t n) { return unsigned((n + 255) / 256); }
 
+// stream-ordered scratch on the stream of the current problem
+thread_local hipStream_t t_osrc_stream = nullptr;
+
 struct OsrcBuf {
     double2 *p = nullptr;
-    explicit OsrcBuf(size_t n) { BEM_HIP(hipMalloc(&p, std::max<size_t>(1, n) * sizeof(double2))); }
-    ~OsrcBuf() { (void)hipFree(p); }
+    hipStream_t s;
+    explicit OsrcBuf(size_t n) : s(t_osrc_stream)
+    {
+        BEM_HIP(hipMallocAsync(reinterpret_cast<void **>(&p), std::max<size_t>(1, n) * sizeof(double2), s));
+    }
+    ~OsrcBuf() { (void)hipFreeAsync(p, s); }
 };
 
 void osrc_setup(bem_problem &p)
@@ -266,81 +192,131 @@ void osrc_setup(bem_problem &p)
     BEM_HIP(hipStreamSynchronize(p.stream));
 }
 
-// Batched COCG: (M - c_g S) x_g = b_g, zero initial guess, stop per system at
-// ||r|| <= tol ||b||; returns the largest iteration count.
-static int cocg_batch(bem_problem &p, int G, const std::vector<cd> &c, const double2 *B, double2 *X, double tol,
-                      int maxit)
+// Persistent COCG: one 1024-lane workgroup per system (M - c_g S) x_g = b_g,
+// zero initial guess, iterating on the device until ||r|| <= tol ||b|| or
+// maxit.  Every loop decision uses block-reduced values, so all waves of a
+// workgroup take the same path and the loop ends for all of them.
+constexpr int CG_BLOCK = 1024;
+
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c, double *red)
 {
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+        c += __shfl_xor(c, off);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        red[3 * w] = a;
+        red[3 * w + 1] = b;
+        red[3 * w + 2] = c;
+    }
+    __syncthreads();
+    a = b = c = 0.0;
+    for (int k = 0; k < CG_BLOCK / 64; ++k) {
+        a += red[3 * k];
+        b += red[3 * k + 1];
+        c += red[3 * k + 2];
+    }
+}
+
+__global__ __launch_bounds__(CG_BLOCK) void k_cocg_persistent(const int32_t *__restrict__ aptr,
+                                                              const int32_t *__restrict__ acol,
+                                                              const double *__restrict__ Mv,
+                                                              const double *__restrict__ Sv,
+                                                              const double2 *__restrict__ c,
+                                                              const double2 *__restrict__ B, double2 *__restrict__ X,
+                                                              double2 *__restrict__ Rw, double2 *__restrict__ Pw,
+                                                              double2 *__restrict__ Qw, int64_t n, double tol,
+                                                              int maxit)
+{
+    __shared__ double red[3 * (CG_BLOCK / 64)];
+    const int64_t g = blockIdx.x;
+    const int tid = threadIdx.x;
+    const double2 cg = c[g];
+    const double2 *b = B + g * n;
+    double2 *x = X + g * n, *r = Rw + g * n, *pv = Pw + g * n, *q = Qw + g * n;
+    double bn2 = 0, rr_ = 0, ri_ = 0;
+    for (int64_t i = tid; i < n; i += CG_BLOCK) {
+        const double2 v = b[i];
+        x[i] = make_double2(0.0, 0.0);
+        r[i] = v;
+        pv[i] = v;
+        bn2 += v.x * v.x + v.y * v.y;
+        rr_ += v.x * v.x - v.y * v.y;
+        ri_ += 2.0 * v.x * v.y;
+    }
+    block_sum3(bn2, rr_, ri_, red);
+    if (bn2 == 0.0) return;
+    double rho_r = rr_, rho_i = ri_;
+    for (int it = 0; it < maxit; ++it) {
+        __syncthreads();   // p complete before the product
+        double pqr = 0, pqi = 0, dummy = 0;
+        for (int64_t i = tid; i < n; i += CG_BLOCK) {
+            double mr = 0, mi = 0, sr = 0, si = 0;
+            for (int32_t e = aptr[i]; e < aptr[i + 1]; ++e) {
+                const double2 v = pv[acol[e]];
+                mr += Mv[e] * v.x;
+                mi += Mv[e] * v.y;
+                sr += Sv[e] * v.x;
+                si += Sv[e] * v.y;
+            }
+            const double qr = mr - (cg.x * sr - cg.y * si), qi = mi - (cg.x * si + cg.y * sr);
+            q[i] = make_double2(qr, qi);
+            const double2 pp = pv[i];
+            pqr += pp.x * qr - pp.y * qi;
+            pqi += pp.x * qi + pp.y * qr;
+        }
+        block_sum3(pqr, pqi, dummy, red);
+        const double den = pqr * pqr + pqi * pqi;
+        if (den == 0.0) break;
+        const double ar = (rho_r * pqr + rho_i * pqi) / den, ai = (rho_i * pqr - rho_r * pqi) / den;
+        double rn2 = 0, sr2 = 0, si2 = 0;
+        for (int64_t i = tid; i < n; i += CG_BLOCK) {
+            const double2 pp = pv[i], qq = q[i], xx = x[i], rv = r[i];
+            x[i] = make_double2(xx.x + ar * pp.x - ai * pp.y, xx.y + ar * pp.y + ai * pp.x);
+            const double nr = rv.x - (ar * qq.x - ai * qq.y), ni = rv.y - (ar * qq.y + ai * qq.x);
+            r[i] = make_double2(nr, ni);
+            rn2 += nr * nr + ni * ni;
+            sr2 += nr * nr - ni * ni;
+            si2 += 2.0 * nr * ni;
+        }
+        block_sum3(rn2, sr2, si2, red);
+        if (rn2 <= tol * tol * bn2) break;
+        const double d2 = rho_r * rho_r + rho_i * rho_i;
+        if (d2 == 0.0) break;
+        const double br = (sr2 * rho_r + si2 * rho_i) / d2, bi = (si2 * rho_r - sr2 * rho_i) / d2;
+        rho_r = sr2;
+        rho_i = si2;
+        for (int64_t i = tid; i < n; i += CG_BLOCK) {
+            const double2 pp = pv[i], rv = r[i];
+            pv[i] = make_double2(rv.x + br * pp.x - bi * pp.y, rv.y + br * pp.y + bi * pp.x);
+        }
+    }
+}
+
+static void cocg_batch(bem_problem &p, int G, const std::vector<cd> &c, const double2 *B, double2 *X, double tol,
+                       int maxit)
+{
+    t_osrc_stream = p.stream;
     const int64_t n = p.NV;
     hipStream_t s = p.stream;
     const size_t tot = size_t(G) * n;
-    OsrcBuf R(tot), Pp(tot), Q(tot), sc{size_t(G)}, cdev{size_t(G)};
-    const int nblk = int(std::min<int64_t>(64, (n + 255) / 256));
-    OsrcBuf part(size_t(G) * nblk);
-    auto up = [&](const std::vector<cd> &v, double2 *d) {
-        std::vector<double2> t(v.size());
-        for (size_t i = 0; i < v.size(); ++i) t[i] = make_double2(v[i].real(), v[i].imag());
-        BEM_HIP(hipMemcpyAsync(d, t.data(), t.size() * sizeof(double2), hipMemcpyHostToDevice, s));
-        BEM_HIP(hipStreamSynchronize(s));
-    };
-    auto dotu = [&](const double2 *a, const double2 *b, std::vector<cd> &out) {
-        k_dotu_partial<<<dim3(unsigned(nblk), unsigned(G)), dim3(256), 0, s>>>(a, b, n, nblk, part.p);
-        BEM_HIP(hipGetLastError());
-        k_part_final<<<dim3(unsigned((G + 63) / 64)), dim3(64), 0, s>>>(part.p, nblk, G, sc.p);
-        BEM_HIP(hipGetLastError());
-        std::vector<double2> t(G);
-        BEM_HIP(hipMemcpyAsync(t.data(), sc.p, G * sizeof(double2), hipMemcpyDeviceToHost, s));
-        BEM_HIP(hipStreamSynchronize(s));
-        out.resize(G);
-        for (int g = 0; g < G; ++g) out[g] = cd(t[g].x, t[g].y);
-    };
-    auto norms = [&](const double2 *a, std::vector<double> &out) {
-        bdot(s, a, 0, 1, a, n, G, part.p, nblk, sc.p);
-        std::vector<double2> t(G);
-        BEM_HIP(hipMemcpyAsync(t.data(), sc.p, G * sizeof(double2), hipMemcpyDeviceToHost, s));
-        BEM_HIP(hipStreamSynchronize(s));
-        out.resize(G);
-        for (int g = 0; g < G; ++g) out[g] = std::sqrt(std::max(0.0, t[g].x));
-    };
-    up(c, cdev.p);
-    BEM_HIP(hipMemsetAsync(X, 0, tot * sizeof(double2), s));
-    BEM_HIP(hipMemcpyAsync(R.p, B, tot * sizeof(double2), hipMemcpyDeviceToDevice, s));
-    BEM_HIP(hipMemcpyAsync(Pp.p, B, tot * sizeof(double2), hipMemcpyDeviceToDevice, s));
-    std::vector<double> bn, rn;
-    norms(B, bn);
-    std::vector<cd> rho, pq, rho2;
-    dotu(R.p, R.p, rho);
-    std::vector<char> done(G, 0);
-    for (int g = 0; g < G; ++g) done[g] = bn[g] == 0.0;
-    int it = 0;
-    for (; it < maxit; ++it) {
-        if (std::all_of(done.begin(), done.end(), [](char d) { return d != 0; })) break;
-        k_spmv_shift<<<dim3(nb(int64_t(tot))), dim3(256), 0, s>>>(p.d_aptr, p.d_acol, p.d_Mv, p.d_Sv, cdev.p, Pp.p, n,
-                                                                  G, Q.p);
-        BEM_HIP(hipGetLastError());
-        dotu(Pp.p, Q.p, pq);
-        std::vector<cd> alpha(G);
-        for (int g = 0; g < G; ++g) alpha[g] = done[g] || pq[g] == cd(0) ? cd(0) : rho[g] / pq[g];
-        up(alpha, sc.p);
-        k_cocg_xr<<<dim3(nb(int64_t(tot))), dim3(256), 0, s>>>(sc.p, Pp.p, Q.p, X, R.p, n, G);
-        BEM_HIP(hipGetLastError());
-        norms(R.p, rn);
-        for (int g = 0; g < G; ++g)
-            if (rn[g] <= tol * bn[g]) done[g] = 1;
-        dotu(R.p, R.p, rho2);
-        std::vector<cd> beta(G);
-        for (int g = 0; g < G; ++g) beta[g] = done[g] || rho[g] == cd(0) ? cd(0) : rho2[g] / rho[g];
-        rho = rho2;
-        up(beta, sc.p);
-        k_cocg_p<<<dim3(nb(int64_t(tot))), dim3(256), 0, s>>>(sc.p, R.p, Pp.p, n, G);
-        BEM_HIP(hipGetLastError());
-    }
-    return it;
+    OsrcBuf R(tot), Pp(tot), Q(tot), cdev{size_t(G)};
+    std::vector<double2> t(G);
+    for (int g = 0; g < G; ++g) t[g] = make_double2(c[g].real(), c[g].imag());
+    BEM_HIP(hipMemcpyAsync(cdev.p, t.data(), G * sizeof(double2), hipMemcpyHostToDevice, s));
+    BEM_HIP(hipStreamSynchronize(s));
+    k_cocg_persistent<<<dim3(unsigned(G)), dim3(CG_BLOCK), 0, s>>>(p.d_aptr, p.d_acol, p.d_Mv, p.d_Sv, cdev.p, B, X,
+                                                                  R.p, Pp.p, Q.p, n, tol, maxit);
+    BEM_HIP(hipGetLastError());
 }
 
 void osrc_apply(bem_problem &p, const OsrcParams &o, const double2 *Y, double2 *Out, int R)
 {
     osrc_setup(p);
+    t_osrc_stream = p.stream;
     const int64_t n = p.NV;
     hipStream_t s = p.stream;
     const int L = o.n_pade;

@@ -27,11 +27,17 @@ namespace {
 
 using cd = std::complex<double>;
 
+// Stream-ordered scratch (no device-wide synchronisation, so the solves of
+// several problems on their own streams overlap).
 template <typename T>
 struct DevBuf {
     T *p = nullptr;
-    explicit DevBuf(size_t n) { BEM_HIP(hipMalloc(reinterpret_cast<void **>(&p), std::max<size_t>(1, n) * sizeof(T))); }
-    ~DevBuf() { (void)hipFree(p); }
+    hipStream_t s;
+    DevBuf(size_t n, hipStream_t st) : s(st)
+    {
+        BEM_HIP(hipMallocAsync(reinterpret_cast<void **>(&p), std::max<size_t>(1, n) * sizeof(T), s));
+    }
+    ~DevBuf() { (void)hipFreeAsync(p, s); }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
 };
@@ -44,8 +50,9 @@ void gmres_batch(bem_problem &p, int64_t n, int R, const double2 *B, double2 *X,
     hipStream_t s = p.stream;
     const int m = std::max(1, o.restart);
     const int nblk = int(std::min<int64_t>(128, (n + 255) / 256));
-    DevBuf<double2> V(size_t(m + 1) * R * n), Z(M ? size_t(m) * R * n : 1), Xa(size_t(R) * n), Ba(size_t(R) * n);
-    DevBuf<double2> hdev(size_t(R) * (m + 2)), part(size_t(R) * (m + 2) * nblk);
+    DevBuf<double2> V(size_t(m + 1) * R * n, s), Z(M ? size_t(m) * R * n : 1, s), Xa(size_t(R) * n, s),
+        Ba(size_t(R) * n, s);
+    DevBuf<double2> hdev(size_t(R) * (m + 2), s), part(size_t(R) * (m + 2) * nblk, s);
     const int64_t ld = int64_t(R) * n;   // stride between basis vectors (packed to the active count)
 
     auto host_dots = [&](const double2 *Vb, int64_t ldv, int nvec, const double2 *w, int Ra, std::vector<cd> &out) {

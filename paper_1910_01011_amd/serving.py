@@ -1,0 +1,161 @@
+"""Serving loop: continuous admission of solve requests on one GPU.
+
+Requests (a transmission problem, an incident field with one or more right-
+hand sides, solver options) arrive over time.  The dispatcher admits a waiting
+request as soon as a slot is free and its device footprint
+(``bem_footprint_bytes``: geometry, singular correction, dense matrix in the
+assembled modes, Krylov bases) fits in the HBM budget next to the requests
+already running.  Every admitted request runs on its own HIP stream in a
+worker thread: set-up, right-hand side and GMRES stay on the device (operators
+and Krylov state are device resident; the C calls release the Python lock),
+so the device work of concurrent requests overlaps.  Finished requests free
+their memory, which admits the next ones.
+
+Each request's computation is independent of the others (own problem handle,
+own stream, deterministic kernels, no reductions across requests), so its
+result is bitwise the same alone and in a mix.
+"""
+from __future__ import annotations
+
+import threading
+import time
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import (BEM_OTF, BEM_PREC_FP32, Incident, Problem, bem_assemble_opts, _L, _domains, _check, solve_options)
+import ctypes
+
+
+@dataclass
+class Request:
+    rid: int
+    domains: list
+    k0: complex
+    incident: Incident
+    rho0: float = 1.0
+    mode: int = BEM_OTF
+    precision: int = BEM_PREC_FP32
+    tol: float = 1e-5
+    restart: int = 100
+    max_iter: int = 400
+    arrival: float = 0.0        # seconds after the start of the stream
+
+
+@dataclass
+class Result:
+    rid: int
+    u: np.ndarray
+    info: list
+    arrival: float
+    admitted: float
+    finished: float
+    footprint: int
+    n_rhs: int
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+def footprint(req: Request) -> int:
+    arr, keep = _domains(req.domains)
+    opts = bem_assemble_opts()
+    opts.mode = req.mode
+    out = ctypes.c_uint64(0)
+    _check(_L.bem_footprint_bytes(arr, len(req.domains), ctypes.byref(opts), req.incident.n_fields,
+                                  req.restart, ctypes.byref(out)))
+    return int(out.value)
+
+
+def run_request(req: Request, t0: float, admitted: float, fp: int) -> Result:
+    """Set up, build the right-hand sides and solve one request on its own stream."""
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        P = Problem(req.domains, req.k0, req.rho0, device=True, mode=req.mode, stream=stream.cuda_stream)
+        b = P.rhs(req.incident)
+        u, info = P.solve(b, solve_options(tol=req.tol, restart=req.restart, max_iter=req.max_iter,
+                                           precision=req.precision))
+        u_host = u.cpu().numpy()
+        stream.synchronize()
+        P.close()
+    return Result(req.rid, u_host, info, req.arrival, admitted, time.perf_counter() - t0, fp,
+                  req.incident.n_fields)
+
+
+class Server:
+    """Admission by HBM footprint, bounded concurrency, one stream per request."""
+
+    def __init__(self, hbm_budget_bytes: int | None = None, max_inflight: int = 4, headroom_bytes: int = 16 << 30):
+        if hbm_budget_bytes is None:
+            free, _total = torch.cuda.mem_get_info()
+            hbm_budget_bytes = max(0, free - headroom_bytes)
+        self.budget = int(hbm_budget_bytes)
+        self.max_inflight = int(max_inflight)
+
+    def run(self, requests: list[Request]) -> list[Result]:
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        fps = {r.rid: footprint(r) for r in reqs}
+        for r in reqs:
+            if fps[r.rid] > self.budget:
+                raise MemoryError(f"request {r.rid} needs {fps[r.rid]} bytes, over the budget {self.budget}")
+        results: list[Result] = []
+        lock = threading.Lock()
+        done_evt = threading.Event()
+        inflight: dict[int, int] = {}
+        used = [0]
+
+        errors: list[BaseException] = []
+
+        def finished(fut, rid):
+            with lock:
+                used[0] -= inflight.pop(rid)
+                exc = fut.exception()
+                if exc is not None:
+                    errors.append(exc)
+                else:
+                    results.append(fut.result())
+            done_evt.set()
+
+        t0 = time.perf_counter()
+        pending: list[Request] = []
+        nxt = 0
+        with ThreadPoolExecutor(max_workers=self.max_inflight) as pool:
+            while nxt < len(reqs) or pending or inflight:
+                now = time.perf_counter() - t0
+                while nxt < len(reqs) and reqs[nxt].arrival <= now:
+                    pending.append(reqs[nxt])
+                    nxt += 1
+                # first-come first-served admission while slots and memory allow
+                with lock:
+                    while pending and len(inflight) < self.max_inflight and used[0] + fps[pending[0].rid] <= self.budget:
+                        r = pending.pop(0)
+                        inflight[r.rid] = fps[r.rid]
+                        used[0] += fps[r.rid]
+                        fut = pool.submit(run_request, r, t0, time.perf_counter() - t0, fps[r.rid])
+                        fut.add_done_callback(lambda f, rid=r.rid: finished(f, rid))
+                # sleep until the next arrival or a completion
+                wait = 0.05
+                if nxt < len(reqs):
+                    wait = max(0.0, min(wait, reqs[nxt].arrival - (time.perf_counter() - t0)))
+                done_evt.wait(timeout=wait)
+                done_evt.clear()
+                if errors:
+                    break
+        if errors:
+            raise errors[0]
+        return sorted(results, key=lambda r: r.rid)
+
+
+def summarize(results: list[Result]) -> dict:
+    lat = np.array([r.latency for r in results])
+    makespan = max(r.finished for r in results) - min(r.arrival for r in results)
+    n_rhs = sum(r.n_rhs for r in results)
+    return {"requests": len(results), "rhs": n_rhs, "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)), "mean_latency_s": float(lat.mean()),
+            "makespan_s": float(makespan), "requests_per_s": len(results) / makespan,
+            "solves_per_s": n_rhs / makespan,
+            "all_converged": all(all(i["converged"] for i in r.info) for r in results)}
