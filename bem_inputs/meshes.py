@@ -161,7 +161,7 @@ def capsule(radius: float, length: float, h: float, axis: int = 1, center=(0.0, 
     n_cyl = max(1, int(np.ceil(cyl / h - 1e-9)))
     n_cap = max(2, int(np.ceil(0.5 * np.pi * radius / h - 1e-9)))
     rings = []  # (axial coordinate, ring radius, angular offset)
-    for k in range(n_cap, 0, -1):  # bottom cap, from near the pole to the equator
+    for k in range(n_cap - 1, 0, -1):  # bottom cap, from near the pole to the equator
         phi = 0.5 * np.pi * k / n_cap
         rings.append((-0.5 * cyl - radius * np.sin(phi), radius * np.cos(phi)))
     for k in range(n_cyl + 1):

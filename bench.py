@@ -76,6 +76,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-assembled", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the heuristic launch shapes")
     ap.add_argument("--level", type=int, default=5, help="icosphere level of the sphere workload (5: 10,242 v)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -91,7 +92,7 @@ def main():
     torch.cuda.set_device(0)
     prob = configs.config2() if args.level == 5 else configs.sphere_problem(args.level, 10.0, 10.5, 1.05)
     t_setup = time.perf_counter()
-    P = bem.Problem.from_config(prob, device=True)
+    P = bem.Problem.from_config(prob, device=True, autotune=not args.no_autotune)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     x = torch.from_numpy(vectors.random_complex(prob.n_unknowns, seed=0)).cuda()
@@ -132,6 +133,7 @@ def main():
                                f"{prob.domains[0].n_triangles} t, k0=10, k1=10.5, rho1/rho0=1.05, 6-pt far rule, "
                                f"Sauter-Schwab order 6 singular pass",
                    "pairs_per_apply": pairs, "unknowns": prob.n_unknowns, "setup_s": t_setup,
+                   "autotune": not args.no_autotune, "pair_launch_shape": list(P.pair_launch_shape()),
                    "apply_ms_p50": float(np.percentile(step_ms, 50)),
                    "apply_ms_p99": float(np.percentile(step_ms, 99))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -159,7 +161,7 @@ def main():
     if not args.no_assembled:
         del P
         torch.cuda.empty_cache()
-        out["assembled"] = assembled_section(prob, bem, vectors, torch)
+        out["assembled"] = assembled_section(prob, bem, vectors, torch, autotune=not args.no_autotune)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out))
@@ -170,13 +172,13 @@ FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X FP32 MFMA
 HBM_PEAK_GBPS = 8000.0
 
 
-def assembled_section(prob, bem, vectors, torch):
+def assembled_section(prob, bem, vectors, torch, autotune=True):
     """Assembled mode on the same problem: dense assembly, GEMV (HBM roofline),
     multi-RHS GEMM (MFMA roofline) and time-to-solve of the three precision forms."""
     n = prob.n_unknowns
     res = {"n": n}
     t = time.perf_counter()
-    P = bem.Problem.from_config(prob, device=True, mode=bem.BEM_ASSEMBLED_SPLIT_BF16)
+    P = bem.Problem.from_config(prob, device=True, mode=bem.BEM_ASSEMBLED_SPLIT_BF16, autotune=autotune)
     torch.cuda.synchronize()
     res["assembly_s"] = time.perf_counter() - t
     x = torch.from_numpy(vectors.random_complex(n, seed=0)).cuda()

@@ -67,6 +67,8 @@ typedef struct {
 
 /* flags */
 #define BEM_DEVICE_PTRS 1u         /* vectors passed to apply/solve/rhs/evaluate are device pointers */
+#define BEM_AUTOTUNE 2u            /* time candidate launch shapes of the pair kernel at set-up and of the
+                                      GEMM at first use per right-hand-side bucket; cache the choice */
 
 typedef struct {
     int mode;          /* BEM_OTF (default) or an assembled mode */
@@ -74,7 +76,7 @@ typedef struct {
     int ss_order;      /* Gauss-Legendre points per dimension of the singular rules (1..16), default 6 */
     int device;        /* HIP device ordinal */
     void *stream;      /* hipStream_t used for all work of this problem; NULL = default stream */
-    uint32_t flags;    /* BEM_DEVICE_PTRS */
+    uint32_t flags;    /* BEM_DEVICE_PTRS | BEM_AUTOTUNE */
 } bem_assemble_opts;
 
 /* Incident field kinds (paper eq. model: p_inc; numerical experiments). */
@@ -195,6 +197,10 @@ int64_t bem_num_unknowns(const bem_problem *p);
 /* Device bytes a problem would hold (admission control). */
 bem_status bem_footprint_bytes(const bem_domain *domains, int32_t n_domains, const bem_assemble_opts *opts,
                                int32_t n_rhs, int32_t restart, uint64_t *bytes);
+
+/* Launch shape chosen for the pair kernel: test points per lane and trial
+ * splits (out[0], out[1]). */
+bem_status bem_pair_launch_shape(const bem_problem *p, int32_t *out2);
 
 /* Kernel timing of the last bem_apply on this problem, in milliseconds,
  * measured with HIP events on the problem's stream: [0] whole apply,

@@ -34,6 +34,7 @@ BEM_OK, BEM_WARN_NOT_CONVERGED = 0, 1
 BEM_ERR_INVALID_ARG, BEM_ERR_MESH, BEM_ERR_OOM, BEM_ERR_DEVICE, BEM_ERR_UNSUPPORTED = -1, -2, -3, -4, -5
 BEM_OTF, BEM_ASSEMBLED_FP32, BEM_ASSEMBLED_SPLIT_BF16 = 0, 1, 2
 BEM_DEVICE_PTRS = 1
+BEM_AUTOTUNE = 2
 BEM_APPLY_DEFAULT, BEM_APPLY_GEMV, BEM_APPLY_MFMA_FP32, BEM_APPLY_MFMA_SPLIT_BF16 = 0, 1, 2, 3
 BEM_PLANE_WAVE, BEM_POINT_SOURCES, BEM_PISTON_ARRAY = 0, 1, 2
 BEM_PRECOND_NONE, BEM_PRECOND_OSRC = 0, 1
@@ -88,16 +89,17 @@ _L.bem_num_unknowns.restype = ctypes.c_int64
 _L.bem_footprint_bytes.argtypes = [ctypes.POINTER(bem_domain), ctypes.c_int32, ctypes.POINTER(bem_assemble_opts),
                                    ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
 _L.bem_last_timings.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
+_L.bem_pair_launch_shape.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32)]
 _L.bem_destroy.argtypes = [_vp]
 _L.bem_destroy.restype = None
 _L.bem_last_error.restype = ctypes.c_char_p
 for _f in ("bem_assemble", "bem_apply", "bem_apply_parts", "bem_apply_with", "bem_rhs", "bem_solve", "bem_solve_rhs",
-           "bem_apply_preconditioner",
+           "bem_apply_preconditioner", "bem_pair_launch_shape",
            "bem_evaluate_field", "bem_footprint_bytes", "bem_last_timings"):
     getattr(_L, _f).restype = ctypes.c_int
 
 EXPORTED = ["bem_assemble", "bem_apply", "bem_apply_parts", "bem_apply_with", "bem_rhs", "bem_solve", "bem_solve_rhs",
-            "bem_apply_preconditioner",
+            "bem_apply_preconditioner", "bem_pair_launch_shape",
             "bem_evaluate_field", "bem_num_unknowns", "bem_footprint_bytes", "bem_last_timings",
             "bem_destroy", "bem_last_error"]
 
@@ -188,7 +190,8 @@ def footprint_bytes(domains, n_rhs=1, restart=100):
 class Problem:
     """A set-up transmission problem on one GPU (wraps ``bem_problem``)."""
 
-    def __init__(self, domains, k0, rho0=1.0, device=False, ss_order=6, mode=BEM_OTF, stream=None, gpu=0):
+    def __init__(self, domains, k0, rho0=1.0, device=False, ss_order=6, mode=BEM_OTF, stream=None, gpu=0,
+                 autotune=False):
         self._h = _vp()
         self.device = bool(device)
         arr, keep = _domains(domains)
@@ -201,7 +204,7 @@ class Problem:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
         opts.stream = stream or 0
-        opts.flags = BEM_DEVICE_PTRS if self.device else 0
+        opts.flags = (BEM_DEVICE_PTRS if self.device else 0) | (BEM_AUTOTUNE if autotune else 0)
         k0 = complex(k0)
         _check(_L.bem_assemble(arr, len(domains), bem_complex(k0.real, k0.imag), float(rho0), ctypes.byref(opts),
                                ctypes.byref(self._h)))
@@ -317,6 +320,12 @@ class Problem:
         _check(_L.bem_evaluate_field(self._h, u.ctypes.data, ctypes.byref(inc) if inc else None, pts.ctypes.data,
                                      pts.shape[0], field.ctypes.data, region.ctypes.data))
         return field, region
+
+    def pair_launch_shape(self):
+        """(test points per lane, trial splits) of the pair kernel."""
+        out = (ctypes.c_int32 * 2)()
+        _check(_L.bem_pair_launch_shape(self._h, out))
+        return int(out[0]), int(out[1])
 
     def timings(self):
         """(apply, pair kernel, scatter + singular pass, gather) in ms of the last apply."""

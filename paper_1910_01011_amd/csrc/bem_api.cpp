@@ -63,6 +63,8 @@ void free_problem(bem_problem *p)
 
 bool finite_c(const bem_complex &z) { return std::isfinite(z.re) && std::isfinite(z.im); }
 
+void build_work(bem_problem &p);
+
 // Far-field pass table and work list.
 void build_passes(bem_problem &p)
 {
@@ -111,6 +113,17 @@ void build_passes(bem_problem &p)
         dv.push_back(d);
     }
     p.d_pass = dev_copy(dv, p.stream);
+    build_work(p);
+}
+
+// Work list of the pair kernel for the current (tpl, n_split).
+void build_work(bem_problem &p)
+{
+    if (p.d_work) {
+        BEM_HIP(hipStreamSynchronize(p.stream));
+        (void)hipFree(p.d_work);
+        p.d_work = nullptr;
+    }
     // work items: consecutive workgroups take consecutive splits, so that the
     // round-robin placement of workgroups on the 8 XCDs keeps one trial chunk
     // per XCD (its L2 holds that chunk).
@@ -176,9 +189,38 @@ void apply_dense_one(bem_problem &p, const double2 *x, double2 *y, bool record)
 }
 
 // Y = A X for several right-hand sides in one GEMM (assembled modes).
-void apply_dense_multi(bem_problem &p, const double2 *X, double2 *Y, int n_rhs, bool bf16)
+void grow(void **ptr, size_t &have, size_t need)
 {
-    const bem::GemmPlan g = bem::gemm_plan(p, n_rhs, bf16);
+    if (have >= need) return;
+    if (*ptr) (void)hipFree(*ptr);
+    *ptr = nullptr;
+    have = 0;
+    BEM_HIP(hipMalloc(ptr, need));
+    have = need;
+}
+
+// search: allow the K-slice search for an untuned bucket (the solvers pass
+// false: they take a cached choice, else the heuristic, so that no timing runs
+// inside a solve).
+void apply_dense_multi(bem_problem &p, const double2 *X, double2 *Y, int n_rhs, bool bf16, bool search = true)
+{
+    int slices = 0;
+    if ((p.flags & BEM_AUTOTUNE) && !search) {
+        slices = bem::cached_gemm_slices(p, n_rhs, bf16);
+    } else if (p.flags & BEM_AUTOTUNE) {
+        // scratch for every candidate (K-slice partials capped at 4 GB), then tune once per bucket
+        size_t cmax = 0;
+        for (int s : {1, 2, 4, 8, 16, 32, 64}) {
+            const bem::GemmPlan c = bem::gemm_plan(p, n_rhs, bf16, s);
+            if (c.bytes_c <= (size_t(4) << 30)) cmax = std::max(cmax, c.bytes_c);
+        }
+        const bem::GemmPlan g0 = bem::gemm_plan(p, n_rhs, bf16, 1);
+        BEM_HIP(hipStreamSynchronize(p.stream));
+        grow(&p.d_gx, p.gx_bytes, g0.bytes_x);
+        grow(reinterpret_cast<void **>(&p.d_gc), p.gc_bytes, cmax);
+        slices = bem::tune_gemm_slices(p, n_rhs, bf16, p.d_gx, p.d_gc);
+    }
+    const bem::GemmPlan g = bem::gemm_plan(p, n_rhs, bf16, slices);
     if (p.gx_bytes < g.bytes_x) {
         if (p.d_gx) (void)hipFree(p.d_gx);
         p.d_gx = nullptr;
@@ -201,10 +243,10 @@ void apply_dense_multi(bem_problem &p, const double2 *X, double2 *Y, int n_rhs, 
     p.timed = true;
 }
 
-void apply_device(bem_problem &p, const double2 *x, double2 *y, int n_rhs, int parts)
+void apply_device(bem_problem &p, const double2 *x, double2 *y, int n_rhs, int parts, bool search = true)
 {
     if (p.mode != BEM_OTF && n_rhs > 1) {
-        apply_dense_multi(p, x, y, n_rhs, p.mode == BEM_ASSEMBLED_SPLIT_BF16);
+        apply_dense_multi(p, x, y, n_rhs, p.mode == BEM_ASSEMBLED_SPLIT_BF16, search);
         return;
     }
     for (int r = 0; r < n_rhs; ++r) {
@@ -353,13 +395,23 @@ bem_status bem_assemble(const bem_domain *domains, int32_t n_domains, bem_comple
         p->tpl = 1;
         const int64_t blocks = (p->M + 255) / 256;
         p->n_split = int(std::clamp<int64_t>((8 * 256 + blocks - 1) / std::max<int64_t>(1, blocks), 1, 64));
-        if (p->n_split > 1) p->n_split = (p->n_split + 7) / 8 * 8;
+        if (p->n_split > 1) p->n_split = std::min(64, (p->n_split + 7) / 8 * 8);
         build_passes(*p);
         dev_alloc(&p->d_trial, size_t(4 * p->M));
-        dev_alloc(&p->d_part, size_t(2) * p->n_split * 10 * p->M);
         dev_alloc(&p->d_pot, size_t(10) * p->M);
-        // interior slot partials of points not covered by an interior pass do
-        // not exist (every point belongs to one domain), but zero everything once
+        if ((o.flags & BEM_AUTOTUNE) && o.mode == BEM_OTF) {
+            // partial sums for the largest candidate (at most 2 GB), then the choice
+            int max_split = 64;
+            while (max_split > 1 && size_t(2) * max_split * 10 * p->M * sizeof(double) > (size_t(2) << 30)) max_split /= 2;
+            dev_alloc(&p->d_part, size_t(2) * max_split * 10 * p->M);
+            bem::tune_pairs(*p, &build_work, max_split);
+            BEM_HIP(hipStreamSynchronize(p->stream));
+            (void)hipFree(p->d_part);
+            p->d_part = nullptr;
+        }
+        dev_alloc(&p->d_part, size_t(2) * p->n_split * 10 * p->M);
+        // every (slot, split, point) partial is written by one work item on each
+        // apply; zero once anyway so a pass with an empty range cannot leave garbage
         BEM_HIP(hipMemsetAsync(p->d_part, 0, size_t(2) * p->n_split * 10 * p->M * sizeof(double), p->stream));
         // singular correction
         std::vector<bem::SingularItem> items;
@@ -450,6 +502,14 @@ bem_status bem_apply_with(bem_problem *p, const bem_complex *x, bem_complex *y, 
     });
 }
 
+bem_status bem_pair_launch_shape(const bem_problem *p, int32_t *out2)
+{
+    if (!p || !out2) return fail(BEM_ERR_INVALID_ARG, "bem_pair_launch_shape: bad arguments");
+    out2[0] = p->tpl;
+    out2[1] = p->n_split;
+    return BEM_OK;
+}
+
 bem_status bem_last_timings(const bem_problem *p, double *ms4)
 {
     if (!p || !ms4) return fail(BEM_ERR_INVALID_ARG, "bem_last_timings: bad arguments");
@@ -534,7 +594,7 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
         // (GEMV with FP64 accumulation for one vector, FP32 MFMA GEMM for a block)
         const bem::ApplyFn fp32_apply = [&P](const double2 *X, double2 *Y, int R) {
             if (P.mode == BEM_OTF) {
-                apply_device(P, X, Y, R, 3);
+                apply_device(P, X, Y, R, 3, false);
             } else {
                 for (int r = 0; r < R; ++r) apply_dense_one(P, X + int64_t(r) * P.N, Y + int64_t(r) * P.N, true);
             }
@@ -572,7 +632,7 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
             };
             const bool bf16 = o.precision == BEM_PREC_SPLIT_BF16_FGMRES;
             const bem::ApplyFn inner_op = [&P, bf16](const double2 *X, double2 *Y, int R) {
-                apply_dense_multi(P, X, Y, R, bf16);
+                apply_dense_multi(P, X, Y, R, bf16, false);
             };
             const bem::KrylovOpts io{o.inner_tol, 30, 300};
             const bem::ApplyFn prec = [&P, &inner_op, io](const double2 *V, double2 *Z, int R) {

@@ -201,8 +201,14 @@ void launch_scatter(bem_problem &p, const double2 *x, double2 *y, int parts);
 void launch_assemble_dense(bem_problem &p);
 void launch_gemv(bem_problem &p, const double2 *x, double2 *y);
 void split_matrix_bf16(bem_problem &p);
-GemmPlan gemm_plan(const bem_problem &p, int R, bool bf16);
+GemmPlan gemm_plan(const bem_problem &p, int R, bool bf16, int force_slices);
 void launch_gemm(bem_problem &p, const GemmPlan &g, const double2 *X, double2 *Y, void *xbuf, float *cbuf);
+void launch_gemm_kernel(bem_problem &p, const GemmPlan &g, void *xbuf, float *cbuf);
+
+// autotuner (autotune.cpp)
+int tune_pairs(bem_problem &p, void (*rebuild)(bem_problem &), int max_split);
+int tune_gemm_slices(bem_problem &p, int R, bool bf16, void *xbuf, float *cbuf);
+int cached_gemm_slices(bem_problem &p, int R, bool bf16);   // 0 when the bucket is untuned
 void run_singular(bem_problem &p, const std::vector<SingularItem> &items);
 
 // FP64 complex vector helpers for GMRES (k_linalg.hip)

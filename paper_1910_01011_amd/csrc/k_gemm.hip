@@ -261,7 +261,7 @@ void split_matrix_bf16(bem_problem &p)
     BEM_HIP(hipGetLastError());
 }
 
-GemmPlan gemm_plan(const bem_problem &p, int R, bool bf16)
+GemmPlan gemm_plan(const bem_problem &p, int R, bool bf16, int force_slices)
 {
     GemmPlan g{};
     g.R = R;
@@ -275,6 +275,7 @@ GemmPlan gemm_plan(const bem_problem &p, int R, bool bf16)
     int s = int(std::max<int64_t>(1, (2048 + int64_t(g.n_m) * g.n_n - 1) / (int64_t(g.n_m) * g.n_n)));
     s = int(std::min<int64_t>(s, std::max<int64_t>(1, ksteps / 8)));
     g.n_s = std::max(1, std::min(s, 64));
+    if (force_slices > 0) g.n_s = int(std::min<int64_t>(force_slices, ksteps));
     g.kslice = round_up((g.Kp + g.n_s - 1) / g.n_s, GBK);
     g.n_s = int((g.Kp + g.kslice - 1) / g.kslice);
     const int groups = (g.n_m + 7) / 8;
@@ -282,6 +283,21 @@ GemmPlan gemm_plan(const bem_problem &p, int R, bool bf16)
     g.bytes_x = size_t(g.Np) * g.Kp * (bf16 ? 2 * sizeof(uint16_t) : sizeof(float));
     g.bytes_c = size_t(g.n_s) * p.N * g.Np * sizeof(float);
     return g;
+}
+
+void launch_gemm_kernel(bem_problem &p, const GemmPlan &g, void *xbuf, float *cbuf)
+{
+    const int64_t tot = g.Np * g.Kp;
+    if (g.bf16) {
+        uint16_t *hi = static_cast<uint16_t *>(xbuf), *lo = hi + tot;
+        k_gemm_bf16x3<<<dim3(unsigned(g.n_wg)), dim3(256), 0, p.stream>>>(p.d_Ahi, p.d_Alo, hi, lo, p.N, g.Kp, g.n_m,
+                                                                         g.n_n, g.n_s, g.kslice, cbuf, g.Np);
+    } else {
+        k_gemm_f32<<<dim3(unsigned(g.n_wg)), dim3(256), 0, p.stream>>>(reinterpret_cast<const float *>(p.d_A), 2 * p.N,
+                                                                      static_cast<float *>(xbuf), p.N, 2 * p.N, g.Kp,
+                                                                      g.n_m, g.n_n, g.n_s, g.kslice, cbuf, g.Np);
+    }
+    BEM_HIP(hipGetLastError());
 }
 
 void launch_gemm(bem_problem &p, const GemmPlan &g, const double2 *X, double2 *Y, void *xbuf, float *cbuf)
