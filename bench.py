@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-assembled", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the heuristic launch shapes")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run only a 1 GiB elementwise copy (the counter scale) and 3 applies, for HBM counters")
     ap.add_argument("--level", type=int, default=5, help="icosphere level of the sphere workload (5: 10,242 v)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -97,6 +99,9 @@ def main():
     t_setup = time.perf_counter() - t_setup
     x = torch.from_numpy(vectors.random_complex(prob.n_unknowns, seed=0)).cuda()
     y = torch.empty_like(x)
+    if args.traffic_probe:
+        traffic_probe(P, x, y, torch)
+        return
     for _ in range(args.warmup):
         P.apply(x, out=y)
     torch.cuda.synchronize()
@@ -137,7 +142,7 @@ def main():
                    "apply_ms_p50": float(np.percentile(step_ms, 50)),
                    "apply_ms_p99": float(np.percentile(step_ms, 99))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": recorded_traffic(),
                      "kernel": "k_pairs", "kernel_ms": pair_avg, "flop_per_pair": FLOP_PER_PAIR},
     }
     if not args.no_solve:
@@ -165,6 +170,45 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out))
+
+
+COPY_PROBE_BYTES = 1 << 30     # bytes read (and written) by the copy of the traffic probe
+
+
+def traffic_probe(P, x, y, torch):
+    """Kernels for the HBM-counter runs: a plain elementwise copy of known size
+    (1 GiB read, 1 GiB written; its FETCH_SIZE / WRITE_SIZE give the counter
+    scale) and three applies."""
+    a = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    del a, b
+    for _ in range(3):
+        P.apply(x, out=y)
+    torch.cuda.synchronize()
+    print("traffic probe done", flush=True)
+
+
+def recorded_traffic():
+    """HBM bytes per k_pairs launch from the committed counter summary, or None
+    when the pair kernel's source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_pairs_sphere10242_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_1910_01011_amd", "csrc", "k_farfield.hip")
+    try:
+        fields = {}
+        for line in open(path):
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                fields[k.strip()] = v.strip().strip("`")
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if fields.get("k_farfield.hip sha256") != digest:
+            return None
+        return float(fields["HBM bytes per launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 MFMA

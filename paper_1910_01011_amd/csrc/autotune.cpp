@@ -27,6 +27,8 @@ namespace {
 std::mutex g_mu;
 std::map<std::string, int> g_cache;
 std::string g_loaded;   // path the in-memory cache was read from
+// bumped whenever a tuned kernel changes, so that older choices are not reused
+constexpr const char *TUNE_VERSION = "v2";
 
 std::string cache_path()
 {
@@ -102,7 +104,7 @@ int tune_pairs(bem_problem &p, void (*rebuild)(bem_problem &), int max_split)
     std::lock_guard<std::mutex> lk(g_mu);
     load_cache();
     std::ostringstream key;
-    key << "pairs:" << arch_name(p.device) << ":M" << bucket(p.M) << ":P" << p.n_pass;
+    key << "pairs" << TUNE_VERSION << ":" << arch_name(p.device) << ":M" << bucket(p.M) << ":P" << p.n_pass;
     auto it = g_cache.find(key.str());
     const auto valid = [&](int code) {
         const int tpl = code / 100, ns = code % 100;
@@ -131,7 +133,8 @@ int tune_pairs(bem_problem &p, void (*rebuild)(bem_problem &), int max_split)
             p.n_split = ns;
             rebuild(p);
             const int reps = p.M > 200000 ? 1 : 3;
-            const float ms = time_ms(p, [&]() { launch_pairs(p); }, reps);
+            // the partial sums of every split are read back by the reduction: time both
+            const float ms = time_ms(p, [&]() { launch_pairs(p); launch_reduce(p); }, reps);
             if (ms < best_ms) {
                 best_ms = ms;
                 best = 100 * tpl + ns;
@@ -150,7 +153,7 @@ int tune_pairs(bem_problem &p, void (*rebuild)(bem_problem &), int max_split)
 std::string gemm_key(const bem_problem &p, int R, bool bf16)
 {
     std::ostringstream key;
-    key << "gemm:" << arch_name(p.device) << ":N" << bucket(p.N) << ":R" << bucket(R) << ":" << (bf16 ? "bf16x3" : "f32");
+    key << "gemm" << TUNE_VERSION << ":" << arch_name(p.device) << ":N" << bucket(p.N) << ":R" << bucket(R) << ":" << (bf16 ? "bf16x3" : "f32");
     return key.str();
 }
 

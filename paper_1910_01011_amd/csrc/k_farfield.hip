@@ -303,21 +303,32 @@ void launch_pairs(bem_problem &p)
 // reduce: pot[i][c] = sum over slots and splits of the partials (fixed order)
 // ---------------------------------------------------------------------------
 
+// One thread per (channel, point): 2 n_split coalesced loads, summed as four
+// interleaved partial sums combined in a fixed order (deterministic).
 __global__ void k_reduce(const double *__restrict__ part, int64_t M, int n_split, double *__restrict__ pot)
 {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= M) return;
-    for (int c = 0; c < 10; ++c) {
-        double s = 0.0;
-        for (int k = 0; k < 2 * n_split; ++k) s += part[(size_t(k) * 10 + c) * M + i];
-        pot[10 * i + c] = s;
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= 10 * M) return;
+    const int64_t c = idx / M, i = idx - c * M;
+    const size_t stride = size_t(10) * M;
+    const double *q = part + idx;
+    const int n = 2 * n_split;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int k = 0;
+    for (; k + 4 <= n; k += 4) {
+        s0 += q[size_t(k) * stride];
+        s1 += q[size_t(k + 1) * stride];
+        s2 += q[size_t(k + 2) * stride];
+        s3 += q[size_t(k + 3) * stride];
     }
+    for (; k < n; ++k) s0 += q[size_t(k) * stride];
+    pot[10 * i + c] = (s0 + s1) + (s2 + s3);
 }
 
 void launch_reduce(bem_problem &p)
 {
     const int B = 256;
-    k_reduce<<<dim3(unsigned((p.M + B - 1) / B)), dim3(B), 0, p.stream>>>(p.d_part, p.M, p.n_split, p.d_pot);
+    k_reduce<<<dim3(unsigned((10 * p.M + B - 1) / B)), dim3(B), 0, p.stream>>>(p.d_part, p.M, p.n_split, p.d_pot);
     BEM_HIP(hipGetLastError());
 }
 

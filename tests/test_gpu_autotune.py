@@ -45,7 +45,7 @@ def test_tuned_pair_shapes_keep_parity(c1, tmp_path, monkeypatch):
     err = _relerr(P.apply(x), ref)
     P.close()
     lines = cache.read_text().split()
-    assert len(lines) == 2 and lines[0].startswith("pairs:"), lines
+    assert len(lines) == 2 and lines[0].startswith("pairs"), lines
     assert int(lines[1]) == 100 * tpl + ns
     print(f"searched shape tpl={tpl} n_split={ns}: rel err {err:.3e}")
     assert err <= APPLY_TOL
