@@ -77,6 +77,11 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-assembled", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the heuristic launch shapes")
+    ap.add_argument("--extra", default="",
+                    help="comma list of extra workloads appended to the JSON line: ribcage (53.5k-vertex stack, "
+                         "on the fly, pistons, OSRC), ribcage_assembled (26.9k vertices, 256 right-hand sides), "
+                         "serving (kidney request stream)")
+    ap.add_argument("--serving-requests", type=int, default=8, help="requests per arrival rate in --extra serving")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only a 1 GiB elementwise copy (the counter scale) and 3 applies, for HBM counters")
     ap.add_argument("--level", type=int, default=5, help="icosphere level of the sphere workload (5: 10,242 v)")
@@ -167,9 +172,139 @@ def main():
         del P
         torch.cuda.empty_cache()
         out["assembled"] = assembled_section(prob, bem, vectors, torch, autotune=not args.no_autotune)
+    extras = [e for e in args.extra.split(",") if e]
+    if extras:
+        os.environ.setdefault("BEM_PROGRESS", "50")   # solver progress lines on stderr
+        del P
+        torch.cuda.empty_cache()
+    for e in extras:
+        log(f"extra workload {e}")
+        if e == "ribcage":
+            out["ribcage"] = ribcage_section(bem, torch, not args.no_autotune)
+        elif e == "ribcage_assembled":
+            out["ribcage_assembled"] = ribcage_assembled_section(bem, torch, not args.no_autotune)
+        elif e == "serving":
+            out["serving"] = serving_section(bem, torch, args.serving_requests)
+        else:
+            raise SystemExit(f"unknown extra workload {e}")
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out))
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t
+
+
+def ribcage_section(bem, torch, autotune):
+    """Rib-cage stack at h = lambda/6 (53,524 vertices, 7 domains): on-the-fly
+    apply rate and the OSRC-preconditioned GMRES(100) solve of the 256-piston
+    bowl as one field (N_Pade = 8, R_eps = 1.5) to 1e-5."""
+    from bem_inputs import configs, pistons
+    prob = configs.ribcage(1.0)
+    P, t_setup = _timed(torch, lambda: bem.Problem.from_config(prob, device=True, autotune=autotune))
+    pairs = pairs_per_apply(prob)
+    x = torch.from_numpy(np.random.default_rng(0).standard_normal(prob.n_unknowns) + 0j).cuda()
+    y = torch.empty_like(x)
+    P.apply(x, out=y)
+    ts = []
+    for _ in range(3):
+        P.apply(x, out=y)
+        ts.append(P.timings()[0])
+    ms = float(np.median(ts))
+    log(f"ribcage apply {ms:.1f} ms")
+    c, n, a = pistons.bowl_array()
+    inc = bem.Incident.pistons(c, n, a, 1.0, np.zeros(len(c), dtype=int))
+    b = P.rhs(inc)
+    (u, info), t_solve = _timed(torch, lambda: P.solve(b, bem.solve_options(
+        tol=1e-5, restart=100, max_iter=1000, precond=bem.BEM_PRECOND_OSRC, n_pade=8, r_eps=1.5, theta=np.pi / 3)))
+    log(f"ribcage OSRC solve {t_solve:.1f} s, {info[0]['iterations']} iterations")
+    res = {"vertices": sum(d.n_vertices for d in prob.domains), "unknowns": prob.n_unknowns,
+           "domains": len(prob.domains), "setup_s": t_setup, "pair_launch_shape": list(P.pair_launch_shape()),
+           "pairs_per_apply": pairs, "apply_ms": ms, "pairs_per_s": pairs / (ms * 1e-3),
+           "osrc_solve": {"time_to_solve_s": t_solve, "iterations": info[0]["iterations"],
+                          "rel_residual": info[0]["rel_residual"], "converged": info[0]["converged"],
+                          "s_per_iteration": t_solve / max(1, info[0]["iterations"])}}
+    P.close()
+    return res
+
+
+def ribcage_assembled_section(bem, torch, autotune):
+    """Rib-cage stack at h * sqrt(2) (26,924 vertices): assembled split-BF16,
+    one right-hand side per piston (R = 256): GEMM rates and time-to-solve of
+    split-BF16 FGMRES (to 1e-6), FP32-MFMA FGMRES and plain FP32 GMRES (GEMV)."""
+    from bem_inputs import configs, pistons
+    prob = configs.ribcage(2.0 ** 0.5)
+    n = prob.n_unknowns
+    P, t_asm = _timed(torch, lambda: bem.Problem.from_config(prob, device=True, mode=bem.BEM_ASSEMBLED_SPLIT_BF16,
+                                                             autotune=autotune))
+    log(f"ribcage assembled: n = {n}, assembly {t_asm:.1f} s")
+    res = {"vertices": sum(d.n_vertices for d in prob.domains), "unknowns": n, "assembly_s": t_asm}
+    X = torch.from_numpy(np.random.default_rng(1).standard_normal((256, n)) + 0j).cuda()
+    for kern, key, peak, fl in ((bem.BEM_APPLY_MFMA_SPLIT_BF16, "bf16x3", BF16_PEAK_TFLOPS, 24.0),
+                                (bem.BEM_APPLY_MFMA_FP32, "fp32", FP32_MFMA_PEAK_TFLOPS, 8.0)):
+        P.apply(X, kernel=kern)
+        ts = []
+        for _ in range(3):
+            P.apply(X, kernel=kern)
+            ts.append(P.timings()[1])
+        ms = float(np.median(ts))
+        tf = fl * n * n * 256 / (ms * 1e-3) / 1e12
+        res[f"gemm_{key}_R256"] = {"ms": ms, "TFLOPs": tf, "frac": tf / peak, "peak": peak}
+        log(f"GEMM {key} R=256 {ms:.2f} ms {tf:.0f} TF")
+    del X
+    c, nn, a = pistons.bowl_array()
+    b = P.rhs(bem.Incident.pistons(c, nn, a, 1.0, np.arange(len(c))))
+    # flexible forms: all 256 right-hand sides in one block, outer FP64 residual
+    # to 1e-6; inner cycles of 100 (the stack needs hundreds of Krylov steps)
+    for name, prec in (("split_bf16_fgmres", bem.BEM_PREC_SPLIT_BF16_FGMRES),
+                       ("fp32_mfma_fgmres", bem.BEM_PREC_FP32_MFMA_FGMRES)):
+        (u, info), t = _timed(torch, lambda: P.solve(b, bem.solve_options(
+            tol=1e-6, restart=10, max_iter=8, precision=prec, inner_tol=1e-3, inner_restart=100,
+            inner_max_iter=1500)))
+        res[f"solve_{name}_R256"] = {"tol": 1e-6, "s": t, "outer_iterations_max": int(max(i["iterations"] for i in info)),
+                                     "max_rel_residual": float(max(i["rel_residual"] for i in info)),
+                                     "all_converged": all(i["converged"] for i in info)}
+        log(f"solve {name}: {t:.2f} s")
+    # plain FP32 GMRES(100), one GEMV per right-hand side and step: a sample of
+    # 8 right-hand sides with a 1000-step budget (time per right-hand side)
+    (u, info), t = _timed(torch, lambda: P.solve(b[:8], bem.solve_options(tol=1e-6, restart=100, max_iter=1000,
+                                                                          precision=bem.BEM_PREC_FP32)))
+    res["solve_plain_fp32_gemv_sample8"] = {"tol": 1e-6, "s": t, "s_per_rhs": t / 8, "iterations_max": int(max(i["iterations"] for i in info)),
+                                            "max_rel_residual": float(max(i["rel_residual"] for i in info)),
+                                            "all_converged": all(i["converged"] for i in info)}
+    log(f"solve plain fp32 (8 rhs): {t:.2f} s")
+    P.close()
+    return res
+
+
+def serving_section(bem, torch, n_requests):
+    """Kidney + fat-shell request stream: Poisson arrivals at two rates, 2k-40k
+    vertices, 1-64 pistons per request; p50/p99 latency and solves/s."""
+    from bem_inputs import configs
+    from paper_1910_01011_amd import serving
+    free, _ = torch.cuda.mem_get_info()
+    out = {}
+    for rate in (2.0, 10.0):
+        items = configs.serving_stream(rate, n_requests, 5000 + int(rate), 6000 + int(rate))
+        reqs = serving.requests_from_stream(items, free)
+        res = serving.Server(max_inflight=4).run(reqs)
+        summ = serving.summarize(res)
+        summ["vertices"] = [int(sum(d.n_vertices for d in r.domains)) for r in reqs]
+        summ["modes"] = [int(r.mode) for r in reqs]
+        summ["rhs_per_request"] = [int(r.incident.n_fields) for r in reqs]
+        out[f"rate_{rate:g}_per_s"] = summ
+        log(f"serving rate {rate}: p50 {summ['p50_latency_s']:.2f} s p99 {summ['p99_latency_s']:.2f} s")
+    return out
 
 
 COPY_PROBE_BYTES = 1 << 30     # bytes read (and written) by the copy of the traffic probe

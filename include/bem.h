@@ -102,7 +102,13 @@ typedef struct {
  *                               split-BF16 MFMA GEMM, all right-hand sides in one launch
  *                               (problem assembled with BEM_ASSEMBLED_SPLIT_BF16)
  *   BEM_PREC_FP32_MFMA_FGMRES   the same with the FP32 MFMA GEMM as inner operator
- *                               (any assembled mode) */
+ *                               (any assembled mode)
+ * With BEM_PRECOND_OSRC, plain GMRES runs on the left-preconditioned system
+ * (stopping on the preconditioned residual); the flexible forms precondition
+ * their inner solves (inner GMRES on P A z = P v) and keep stopping on the
+ * unpreconditioned FP64 residual.
+ * Progress: with the environment variable BEM_PROGRESS=k (k > 0) the solvers
+ * print one line to stderr every k Arnoldi steps. */
 #define BEM_PREC_FP32 0
 #define BEM_PREC_SPLIT_BF16_FGMRES 1
 #define BEM_PREC_FP32_MFMA_FGMRES 2
@@ -117,6 +123,8 @@ typedef struct {
     double theta;        /* OSRC Pade branch-cut rotation */
     int precision;       /* BEM_PREC_FP32, BEM_PREC_SPLIT_BF16_FGMRES or BEM_PREC_FP32_MFMA_FGMRES */
     double inner_tol;    /* inner tolerance of the flexible-GMRES refinement */
+    int inner_restart;   /* inner GMRES restart length (0: 30) */
+    int inner_max_iter;  /* inner iteration cap per outer step (0: 300) */
 } bem_solve_opts;
 
 typedef struct {

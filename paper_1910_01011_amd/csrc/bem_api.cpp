@@ -1,6 +1,7 @@
 // Host runtime of the C ABI declared in include/bem.h: problem set-up on the
 // device, the operator apply, GMRES and the right-hand side / field entry points.
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -53,7 +54,7 @@ void free_problem(bem_problem *p)
     void *ptrs[] = {p->d_verts, p->d_tris, p->d_rowD, p->d_rowN, p->d_area, p->d_normal, p->d_curl, p->d_pts,
                     p->d_tnrm, p->d_v2t_ptr, p->d_v2t, p->d_pass, p->d_work, p->d_trial, p->d_part, p->d_pot,
                     p->d_cptr, p->d_ccol, p->d_cval, p->d_x, p->d_y, p->d_A, p->d_Ahi, p->d_Alo,
-                    p->d_gx, p->d_gc, p->d_aptr, p->d_acol, p->d_Mv, p->d_Sv};
+                    p->d_gx, p->d_gc, p->d_aptr, p->d_acol, p->d_Mv, p->d_Sv, p->d_adiag, p->d_drange};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (auto &e : p->ev)
@@ -268,6 +269,8 @@ bem_solve_opts default_solve_opts()
     o.r_eps = 0.1;
     o.theta = M_PI / 3.0;
     o.precision = BEM_PREC_FP32;
+    o.inner_restart = 30;
+    o.inner_max_iter = 300;
     o.inner_tol = 1e-3;
     return o;
 }
@@ -559,9 +562,11 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
     if (o.precond == BEM_PRECOND_OSRC) {
         if (!(o.r_eps > 0) || !std::isfinite(o.r_eps) || o.n_pade < 0 || o.n_pade > 64 || !std::isfinite(o.theta))
             return fail(BEM_ERR_INVALID_ARG, "bem_solve: OSRC needs r_eps > 0, 0 <= n_pade <= 64, finite theta");
-        if (o.precision != BEM_PREC_FP32)
-            return fail(BEM_ERR_UNSUPPORTED, "bem_solve: OSRC is available with BEM_PREC_FP32");
     }
+    if (o.inner_restart == 0) o.inner_restart = 30;
+    if (o.inner_max_iter == 0) o.inner_max_iter = 300;
+    if (o.inner_restart < 1 || o.inner_max_iter < 1)
+        return fail(BEM_ERR_INVALID_ARG, "bem_solve: inner_restart and inner_max_iter must be positive (0: default)");
     if (o.precision != BEM_PREC_FP32 && o.precision != BEM_PREC_SPLIT_BF16_FGMRES &&
         o.precision != BEM_PREC_FP32_MFMA_FGMRES)
         return fail(BEM_ERR_INVALID_ARG, "bem_solve: unknown precision mode");
@@ -590,6 +595,8 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
             du = tu;
         }
         bem_problem &P = *p;
+        const char *pe = std::getenv("BEM_PROGRESS");
+        const int progress = pe ? std::max(0, std::atoi(pe)) : 0;
         // FP32-accurate operator: on-the-fly kernel, or the FP32 dense matrix
         // (GEMV with FP64 accumulation for one vector, FP32 MFMA GEMM for a block)
         const bem::ApplyFn fp32_apply = [&P](const double2 *X, double2 *Y, int R) {
@@ -616,14 +623,14 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
                 fp32_apply(X, tmp, R);
                 bem::osrc_apply(P, op, tmp, Y, R);
             };
-            bem::gmres_batch(P, P.N, n_rhs, PB, du, bem::KrylovOpts{o.tol, o.restart, o.max_iter}, prec_apply,
-                             nullptr, info);
+            bem::gmres_batch(P, P.N, n_rhs, PB, du, bem::KrylovOpts{o.tol, o.restart, o.max_iter, progress},
+                             prec_apply, nullptr, info);
             fp32_apply(du, tmp, n_rhs);
             const std::vector<double> rr = residual_norms(P, db, tmp, n_rhs);
             for (int r = 0; r < n_rhs; ++r) info[r].rel_residual = rr[r];
         } else if (o.precision == BEM_PREC_FP32) {
-            bem::gmres_batch(P, P.N, n_rhs, db, du, bem::KrylovOpts{o.tol, o.restart, o.max_iter}, fp32_apply,
-                             nullptr, info);
+            bem::gmres_batch(P, P.N, n_rhs, db, du, bem::KrylovOpts{o.tol, o.restart, o.max_iter, progress},
+                             fp32_apply, nullptr, info);
         } else {
             // flexible GMRES: outer Arnoldi on the FP32 matrix with FP64
             // accumulation, inner GMRES on the 3-term split-BF16 GEMM
@@ -634,12 +641,37 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
             const bem::ApplyFn inner_op = [&P, bf16](const double2 *X, double2 *Y, int R) {
                 apply_dense_multi(P, X, Y, R, bf16, false);
             };
-            const bem::KrylovOpts io{o.inner_tol, 30, 300};
-            const bem::ApplyFn prec = [&P, &inner_op, io](const double2 *V, double2 *Z, int R) {
-                std::vector<bem_solve_info> ii(R);
-                bem::gmres_batch(P, P.N, R, V, Z, io, inner_op, nullptr, ii.data());
-            };
-            bem::gmres_batch(P, P.N, n_rhs, db, du, bem::KrylovOpts{o.tol, o.restart, o.max_iter}, outer, &prec,
+            const bem::KrylovOpts io{o.inner_tol, o.inner_restart, o.inner_max_iter, progress, "inner gmres"};
+            bem::ApplyFn prec;
+            double2 *PV = nullptr, *tmp = nullptr;
+            struct G2 {
+                double2 *a = nullptr, *b = nullptr;
+                ~G2() { (void)hipFree(a); (void)hipFree(b); }
+            } g2;
+            if (o.precond == BEM_PRECOND_OSRC) {
+                // inner GMRES on the left-preconditioned system P A z = P v
+                const bem::OsrcParams op{o.n_pade, o.r_eps, o.theta, 1e-10, 3000};
+                dev_alloc(&PV, n);
+                dev_alloc(&tmp, n);
+                g2.a = PV;
+                g2.b = tmp;
+                prec = [&P, &inner_op, io, op, PV, tmp](const double2 *V, double2 *Z, int R) {
+                    bem::osrc_apply(P, op, V, PV, R);
+                    const bem::ApplyFn pa = [&P, &inner_op, op, tmp](const double2 *X, double2 *Y, int Ri) {
+                        inner_op(X, tmp, Ri);
+                        bem::osrc_apply(P, op, tmp, Y, Ri);
+                    };
+                    std::vector<bem_solve_info> ii(R);
+                    bem::gmres_batch(P, P.N, R, PV, Z, io, pa, nullptr, ii.data());
+                };
+            } else {
+                prec = [&P, &inner_op, io](const double2 *V, double2 *Z, int R) {
+                    std::vector<bem_solve_info> ii(R);
+                    bem::gmres_batch(P, P.N, R, V, Z, io, inner_op, nullptr, ii.data());
+                };
+            }
+            bem::gmres_batch(P, P.N, n_rhs, db, du,
+                             bem::KrylovOpts{o.tol, o.restart, o.max_iter, progress, "outer fgmres"}, outer, &prec,
                              info);
         }
         bool all = true;

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <functional>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/bem.h"
@@ -154,6 +155,8 @@ struct bem_problem {
 
     // OSRC: vertex adjacency CSR with P1 mass and stiffness values
     int32_t *d_aptr = nullptr, *d_acol = nullptr;
+    int32_t *d_adiag = nullptr;     // position of the diagonal entry of every row
+    int2 *d_drange = nullptr;       // vertex range [begin, end) of every domain
     double *d_Mv = nullptr, *d_Sv = nullptr;
     int64_t a_nnz = 0;
 
@@ -205,6 +208,17 @@ GemmPlan gemm_plan(const bem_problem &p, int R, bool bf16, int force_slices);
 void launch_gemm(bem_problem &p, const GemmPlan &g, const double2 *X, double2 *Y, void *xbuf, float *cbuf);
 void launch_gemm_kernel(bem_problem &p, const GemmPlan &g, void *xbuf, float *cbuf);
 
+// Blocks of a 1-D launch over `items` work items.  A dispatch counts its work
+// items in 32 bits: kernels whose item count can exceed that loop over a capped
+// grid (grid-stride) and pass capped = true; every other launch is checked.
+inline unsigned blocks_1d(int64_t items, int block, bool capped = false)
+{
+    const int64_t b = (items + block - 1) / block;
+    if (capped) return unsigned(std::max<int64_t>(1, std::min<int64_t>(b, int64_t(1) << 20)));
+    if (b * block >= (int64_t(1) << 32)) throw Error{BEM_ERR_UNSUPPORTED, "launch exceeds 2^32 work items"};
+    return unsigned(std::max<int64_t>(1, b));
+}
+
 // autotuner (autotune.cpp)
 int tune_pairs(bem_problem &p, void (*rebuild)(bem_problem &), int max_split);
 int tune_gemm_slices(bem_problem &p, int R, bool bf16, void *xbuf, float *cbuf);
@@ -232,6 +246,8 @@ struct KrylovOpts {
     double tol;
     int restart;
     int max_iter;
+    int progress = 0;             // print a line every `progress` Arnoldi steps (0: silent)
+    const char *label = "gmres";
 };
 void gmres_batch(bem_problem &p, int64_t n, int R, const double2 *B, double2 *X, const KrylovOpts &o,
                  const ApplyFn &A, const ApplyFn *M, bem_solve_info *info);

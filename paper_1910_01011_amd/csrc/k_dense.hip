@@ -157,7 +157,7 @@ void launch_assemble_dense(bem_problem &p)
     const int64_t n_corner = 3 * p.NT;
     float4 *rec = nullptr;
     BEM_HIP(hipMalloc(&rec, size_t(18 * n_corner) * sizeof(float4)));
-    k_vertex_points<<<dim3(unsigned((6 * n_corner + 255) / 256)), dim3(256), 0, p.stream>>>(
+    k_vertex_points<<<dim3(blocks_1d(6 * n_corner, 256)), dim3(256), 0, p.stream>>>(
         p.d_v2t, n_corner, p.d_area, p.d_normal, p.d_curl, p.d_pts, p.M, rec);
     BEM_HIP(hipGetLastError());
     std::vector<int32_t> vdom(p.NV);
@@ -187,7 +187,7 @@ void launch_assemble_dense(bem_problem &p)
         k_assemble_dense<false><<<grid, block, 0, p.stream>>>(rec, p.d_v2t_ptr, d_vdom, d_doms, ext, p.d_rowD, p.d_rowN,
                                                             p.NV, p.N, p.d_A);
     BEM_HIP(hipGetLastError());
-    k_dense_correction<<<dim3(unsigned((p.NV + 255) / 256)), dim3(256), 0, p.stream>>>(
+    k_dense_correction<<<dim3(blocks_1d(p.NV, 256)), dim3(256), 0, p.stream>>>(
         p.d_cptr, p.d_ccol, p.d_cval, p.d_rowD, p.d_rowN, p.NV, p.N, p.d_A);
     BEM_HIP(hipGetLastError());
     BEM_HIP(hipStreamSynchronize(p.stream));
@@ -249,7 +249,7 @@ void launch_gemv(bem_problem &p, const double2 *x, double2 *y)
 {
     const int64_t waves = (p.N + GEMV_ROWS - 1) / GEMV_ROWS;
     const int64_t threads = waves * 64;
-    k_gemv<<<dim3(unsigned((threads + 255) / 256)), dim3(256), 0, p.stream>>>(p.d_A, x, p.N, y);
+    k_gemv<<<dim3(blocks_1d(threads, 256)), dim3(256), 0, p.stream>>>(p.d_A, x, p.N, y);
     BEM_HIP(hipGetLastError());
 }
 

@@ -69,7 +69,7 @@ __global__ void k_geometry(const double *__restrict__ verts, const int32_t *__re
 void launch_geometry(bem_problem &p)
 {
     const int B = 256;
-    k_geometry<<<dim3(unsigned((p.NT + B - 1) / B)), dim3(B), 0, p.stream>>>(
+    k_geometry<<<dim3(blocks_1d(p.NT, B)), dim3(B), 0, p.stream>>>(
         p.d_verts, p.d_tris, p.NT, p.M, p.d_area, p.d_normal, p.d_curl, p.d_pts, p.d_tnrm);
     BEM_HIP(hipGetLastError());
 }
@@ -115,7 +115,7 @@ __global__ void k_gather(const double2 *__restrict__ x, const int32_t *__restric
 void launch_gather(bem_problem &p, const double2 *x)
 {
     const int B = 256;
-    k_gather<<<dim3(unsigned((p.M + B - 1) / B)), dim3(B), 0, p.stream>>>(
+    k_gather<<<dim3(blocks_1d(p.M, B)), dim3(B), 0, p.stream>>>(
         x, p.d_tris, p.d_rowD, p.d_rowN, p.d_area, p.d_curl, p.d_pts, p.d_tnrm, p.NT, p.M, p.d_trial);
     BEM_HIP(hipGetLastError());
 }
@@ -328,7 +328,7 @@ __global__ void k_reduce(const double *__restrict__ part, int64_t M, int n_split
 void launch_reduce(bem_problem &p)
 {
     const int B = 256;
-    k_reduce<<<dim3(unsigned((10 * p.M + B - 1) / B)), dim3(B), 0, p.stream>>>(p.d_part, p.M, p.n_split, p.d_pot);
+    k_reduce<<<dim3(blocks_1d(10 * p.M, B)), dim3(B), 0, p.stream>>>(p.d_part, p.M, p.n_split, p.d_pot);
     BEM_HIP(hipGetLastError());
 }
 
@@ -386,7 +386,7 @@ __global__ void k_scatter(const double *__restrict__ pot, const int32_t *__restr
 void launch_scatter(bem_problem &p, const double2 *x, double2 *y, int parts)
 {
     const int B = 256;
-    k_scatter<<<dim3(unsigned((p.NV + B - 1) / B)), dim3(B), 0, p.stream>>>(
+    k_scatter<<<dim3(blocks_1d(p.NV, B)), dim3(B), 0, p.stream>>>(
         p.d_pot, p.d_v2t_ptr, p.d_v2t, p.d_area, p.d_curl, p.d_rowD, p.d_rowN, p.d_cptr, p.d_ccol, p.d_cval, x, y,
         p.NV, parts);
     BEM_HIP(hipGetLastError());

@@ -184,7 +184,7 @@ void launch_rhs(bem_problem &p, const bem_incident &inc, double2 *b)
     double *d_params = nullptr;
     IncDev I = upload_incident(p, inc, &d_params);
     const int B = 128;
-    k_rhs<<<dim3(unsigned((p.NV + B - 1) / B), unsigned(inc.n_fields)), dim3(B), 0, p.stream>>>(
+    k_rhs<<<dim3(blocks_1d(p.NV, B), unsigned(inc.n_fields)), dim3(B), 0, p.stream>>>(
         I, p.d_verts, p.d_tris, p.d_area, p.d_normal, p.d_v2t_ptr, p.d_v2t, p.d_rowD, p.d_rowN, p.NV, p.N, b);
     BEM_HIP(hipGetLastError());
     BEM_HIP(hipStreamSynchronize(p.stream));
@@ -292,7 +292,7 @@ void launch_field(bem_problem &p, const double2 *u, const bem_incident *inc, int
     BEM_HIP(hipMemcpyAsync(d_doms, hd.data(), hd.size() * sizeof(DomDev), hipMemcpyHostToDevice, p.stream));
     const int B = 128;
     if (np > 0) {
-        k_field<<<dim3(unsigned((np + B - 1) / B)), dim3(B), 0, p.stream>>>(
+        k_field<<<dim3(blocks_1d(np, B)), dim3(B), 0, p.stream>>>(
             I, inc ? 1 : 0, d_doms, int(hd.size()), p.k0re, p.k0im, p.rho0, p.d_verts, p.d_tris, p.d_area, p.d_normal,
             p.d_rowD, p.d_rowN, u, p.N, n_fields, pts, np, field, region);
         BEM_HIP(hipGetLastError());

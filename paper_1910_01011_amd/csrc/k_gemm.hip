@@ -41,16 +41,19 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f)
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 
 // A' (n x 2n fp32 view of A) -> hi/lo BF16 planes [n][Kp], zero-padded columns
+// (grid-stride: n Kp exceeds the 32-bit work-item count of one dispatch
+// beyond n ~ 46k)
 __global__ void k_split_matrix(const float *__restrict__ A, int64_t n, int64_t Kp, uint16_t *__restrict__ hi,
                                uint16_t *__restrict__ lo)
 {
-    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= n * Kp) return;
-    const int64_t r = idx / Kp, k = idx - r * Kp;
-    const float a = k < 2 * n ? A[r * 2 * n + k] : 0.0f;
-    const uint16_t h = f32_to_bf16(a);
-    hi[idx] = h;
-    lo[idx] = f32_to_bf16(a - bf16_to_f32(h));
+    const int64_t total = n * Kp, step = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < total; idx += step) {
+        const int64_t r = idx / Kp, k = idx - r * Kp;
+        const float a = k < 2 * n ? A[r * 2 * n + k] : 0.0f;
+        const uint16_t h = f32_to_bf16(a);
+        hi[idx] = h;
+        lo[idx] = f32_to_bf16(a - bf16_to_f32(h));
+    }
 }
 
 // X (R vectors, complex128, RHS-major) -> X'^T [Np][Kp] (fp32, or bf16 hi/lo)
@@ -58,23 +61,24 @@ template <bool BF16>
 __global__ void k_pack_rhs(const double2 *__restrict__ X, int64_t n, int R, int64_t Np, int64_t Kp,
                            float *__restrict__ f32, uint16_t *__restrict__ hi, uint16_t *__restrict__ lo)
 {
-    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= Np * Kp) return;
-    const int64_t j = idx / Kp, k = idx - j * Kp;
-    float v = 0.0f;
-    if (k < 2 * n && j < 2 * R) {
-        const int64_t c = k >> 1;
-        const bool odd = k & 1;
-        const double2 x = X[(j < R ? j : j - R) * n + c];
-        if (j < R) v = odd ? float(-x.y) : float(x.x);
-        else v = odd ? float(x.x) : float(x.y);
-    }
-    if (BF16) {
-        const uint16_t h = f32_to_bf16(v);
-        hi[idx] = h;
-        lo[idx] = f32_to_bf16(v - bf16_to_f32(h));
-    } else {
-        f32[idx] = v;
+    const int64_t total = Np * Kp, step = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < total; idx += step) {
+        const int64_t j = idx / Kp, k = idx - j * Kp;
+        float v = 0.0f;
+        if (k < 2 * n && j < 2 * R) {
+            const int64_t c = k >> 1;
+            const bool odd = k & 1;
+            const double2 x = X[(j < R ? j : j - R) * n + c];
+            if (j < R) v = odd ? float(-x.y) : float(x.x);
+            else v = odd ? float(x.x) : float(x.y);
+        }
+        if (BF16) {
+            const uint16_t h = f32_to_bf16(v);
+            hi[idx] = h;
+            lo[idx] = f32_to_bf16(v - bf16_to_f32(h));
+        } else {
+            f32[idx] = v;
+        }
     }
 }
 
@@ -256,7 +260,7 @@ void split_matrix_bf16(bem_problem &p)
     BEM_HIP(hipMalloc(&p.d_Ahi, size_t(p.N) * Kp * sizeof(uint16_t)));
     BEM_HIP(hipMalloc(&p.d_Alo, size_t(p.N) * Kp * sizeof(uint16_t)));
     const int64_t tot = p.N * Kp;
-    k_split_matrix<<<dim3(unsigned((tot + 255) / 256)), dim3(256), 0, p.stream>>>(
+    k_split_matrix<<<dim3(blocks_1d(tot, 256, true)), dim3(256), 0, p.stream>>>(
         reinterpret_cast<const float *>(p.d_A), p.N, Kp, p.d_Ahi, p.d_Alo);
     BEM_HIP(hipGetLastError());
 }
@@ -305,7 +309,7 @@ void launch_gemm(bem_problem &p, const GemmPlan &g, const double2 *X, double2 *Y
     const int64_t tot = g.Np * g.Kp;
     if (g.bf16) {
         uint16_t *hi = static_cast<uint16_t *>(xbuf), *lo = hi + tot;
-        k_pack_rhs<true><<<dim3(unsigned((tot + 255) / 256)), dim3(256), 0, p.stream>>>(X, p.N, g.R, g.Np, g.Kp,
+        k_pack_rhs<true><<<dim3(blocks_1d(tot, 256, true)), dim3(256), 0, p.stream>>>(X, p.N, g.R, g.Np, g.Kp,
                                                                                        nullptr, hi, lo);
         BEM_HIP(hipGetLastError());
         if (p.timed_gemm) BEM_HIP(hipEventRecord(p.ev[1], p.stream));
@@ -313,7 +317,7 @@ void launch_gemm(bem_problem &p, const GemmPlan &g, const double2 *X, double2 *Y
                                                                          g.n_n, g.n_s, g.kslice, cbuf, g.Np);
     } else {
         float *xf = static_cast<float *>(xbuf);
-        k_pack_rhs<false><<<dim3(unsigned((tot + 255) / 256)), dim3(256), 0, p.stream>>>(X, p.N, g.R, g.Np, g.Kp, xf,
+        k_pack_rhs<false><<<dim3(blocks_1d(tot, 256, true)), dim3(256), 0, p.stream>>>(X, p.N, g.R, g.Np, g.Kp, xf,
                                                                                         nullptr, nullptr);
         BEM_HIP(hipGetLastError());
         if (p.timed_gemm) BEM_HIP(hipEventRecord(p.ev[1], p.stream));
@@ -324,7 +328,7 @@ void launch_gemm(bem_problem &p, const GemmPlan &g, const double2 *X, double2 *Y
     BEM_HIP(hipGetLastError());
     if (p.timed_gemm) BEM_HIP(hipEventRecord(p.ev[2], p.stream));
     const int64_t ny = p.N * g.R;
-    k_unpack_y<<<dim3(unsigned((ny + 255) / 256)), dim3(256), 0, p.stream>>>(cbuf, p.N, g.Np, g.R, g.n_s, Y);
+    k_unpack_y<<<dim3(blocks_1d(ny, 256)), dim3(256), 0, p.stream>>>(cbuf, p.N, g.Np, g.R, g.n_s, Y);
     BEM_HIP(hipGetLastError());
 }
 

@@ -52,7 +52,7 @@ void zdot_multi(hipStream_t s, const double2 *V, int64_t ld, int nvec, const dou
     if (nvec <= 0) return;
     k_zdot_partial<<<dim3(unsigned(nblk), unsigned(nvec)), dim3(LA_BLOCK), 0, s>>>(V, ld, w, n, nblk, partials);
     BEM_HIP(hipGetLastError());
-    k_zdot_final<<<dim3(unsigned((nvec + 63) / 64)), dim3(64), 0, s>>>(partials, nblk, nvec, out_dev);
+    k_zdot_final<<<dim3(blocks_1d(nvec, 64)), dim3(64), 0, s>>>(partials, nblk, nvec, out_dev);
     BEM_HIP(hipGetLastError());
 }
 
@@ -75,7 +75,7 @@ void zaxpy_multi(hipStream_t s, const double2 *V, int64_t ld, int nvec, const do
                  double sign)
 {
     if (nvec <= 0 || n <= 0) return;
-    k_zaxpy_multi<<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, s>>>(V, ld, nvec, h_dev, w, n, sign);
+    k_zaxpy_multi<<<dim3(blocks_1d(n, 256)), dim3(256), 0, s>>>(V, ld, nvec, h_dev, w, n, sign);
     BEM_HIP(hipGetLastError());
 }
 
@@ -90,7 +90,7 @@ __global__ void k_zscale_copy(const double2 *__restrict__ x, double2 *__restrict
 void zscale_copy(hipStream_t s, const double2 *x, double2 *y, int64_t n, double2 a)
 {
     if (n <= 0) return;
-    k_zscale_copy<<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, s>>>(x, y, n, a);
+    k_zscale_copy<<<dim3(blocks_1d(n, 256)), dim3(256), 0, s>>>(x, y, n, a);
     BEM_HIP(hipGetLastError());
 }
 
@@ -105,7 +105,7 @@ __global__ void k_zaxpy(double2 *__restrict__ y, const double2 *__restrict__ x, 
 void zaxpy(hipStream_t s, double2 *y, const double2 *x, int64_t n, double2 a)
 {
     if (n <= 0) return;
-    k_zaxpy<<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, s>>>(y, x, n, a);
+    k_zaxpy<<<dim3(blocks_1d(n, 256)), dim3(256), 0, s>>>(y, x, n, a);
     BEM_HIP(hipGetLastError());
 }
 
@@ -166,7 +166,7 @@ void bdot(hipStream_t s, const double2 *V, int64_t ldv, int nvec, const double2 
                                                                                               nblk, partials);
     BEM_HIP(hipGetLastError());
     const int total = R * nvec;
-    k_bdot_final<<<dim3(unsigned((total + 63) / 64)), dim3(64), 0, s>>>(partials, nblk, total, out_dev);
+    k_bdot_final<<<dim3(blocks_1d(total, 64)), dim3(64), 0, s>>>(partials, nblk, total, out_dev);
     BEM_HIP(hipGetLastError());
 }
 
@@ -190,7 +190,7 @@ void baxpy(hipStream_t s, const double2 *V, int64_t ldv, int nvec, const double2
            double sign)
 {
     if (nvec <= 0 || n * R <= 0) return;
-    k_baxpy<<<dim3(unsigned((n * R + 255) / 256)), dim3(256), 0, s>>>(V, ldv, nvec, h_dev, w, n, R, sign);
+    k_baxpy<<<dim3(blocks_1d(n * R, 256)), dim3(256), 0, s>>>(V, ldv, nvec, h_dev, w, n, R, sign);
     BEM_HIP(hipGetLastError());
 }
 
@@ -207,7 +207,7 @@ __global__ void k_bscale(const double2 *__restrict__ x, double2 *__restrict__ y,
 void bscale(hipStream_t s, const double2 *x, double2 *y, int64_t n, int R, const double2 *a_dev)
 {
     if (n * R <= 0) return;
-    k_bscale<<<dim3(unsigned((n * R + 255) / 256)), dim3(256), 0, s>>>(x, y, n, R, a_dev);
+    k_bscale<<<dim3(blocks_1d(n * R, 256)), dim3(256), 0, s>>>(x, y, n, R, a_dev);
     BEM_HIP(hipGetLastError());
 }
 

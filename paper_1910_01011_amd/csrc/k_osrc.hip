@@ -11,7 +11,8 @@
 //   sqrt(1 + X) z = C0 z - sum_l A_l (M - B_l S')^-1 S' z.
 // M and S are assembled on the union of all boundaries (block diagonal by
 // domain).  All sparse solves of one application are done together by a batched
-// COCG (conjugate orthogonal CG for complex symmetric matrices) in FP64.
+// Jacobi-preconditioned COCG (conjugate orthogonal CG for complex symmetric
+// matrices) in FP64, one workgroup per (system, domain) block.
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -148,7 +149,7 @@ __global__ void k_osrc_out(const double2 *__restrict__ rootD, const double2 *__r
     Y[r * N + rowD[g]] = make_double2(s.x * w.x - s.y * w.y, s.x * w.y + s.y * w.x);
 }
 
-static unsigned nb(int64_t n) { return unsigned((n + 255) / 256); }
+static unsigned nb(int64_t n) { return blocks_1d(n, 256); }
 
 // stream-ordered scratch on the stream of the current problem
 thread_local hipStream_t t_osrc_stream = nullptr;
@@ -180,6 +181,15 @@ void osrc_setup(bem_problem &p)
         col.insert(col.end(), r.begin(), r.end());
     }
     p.a_nnz = ptr[p.NV];
+    std::vector<int32_t> dpos(p.NV);
+    for (int64_t g = 0; g < p.NV; ++g)
+        dpos[g] = int32_t(std::lower_bound(col.begin() + ptr[g], col.begin() + ptr[g + 1], int32_t(g)) - col.begin());
+    std::vector<int2> rng;
+    for (const auto &d : p.doms) rng.push_back(make_int2(int(d.v_off), int(d.v_off + d.nv)));
+    BEM_HIP(hipMalloc(&p.d_adiag, dpos.size() * sizeof(int32_t)));
+    BEM_HIP(hipMalloc(&p.d_drange, rng.size() * sizeof(int2)));
+    BEM_HIP(hipMemcpyAsync(p.d_adiag, dpos.data(), dpos.size() * sizeof(int32_t), hipMemcpyHostToDevice, p.stream));
+    BEM_HIP(hipMemcpyAsync(p.d_drange, rng.data(), rng.size() * sizeof(int2), hipMemcpyHostToDevice, p.stream));
     BEM_HIP(hipMalloc(&p.d_aptr, ptr.size() * sizeof(int32_t)));
     BEM_HIP(hipMalloc(&p.d_acol, col.size() * sizeof(int32_t)));
     BEM_HIP(hipMalloc(&p.d_Mv, col.size() * sizeof(double)));
@@ -192,10 +202,13 @@ void osrc_setup(bem_problem &p)
     BEM_HIP(hipStreamSynchronize(p.stream));
 }
 
-// Persistent COCG: one 1024-lane workgroup per system (M - c_g S) x_g = b_g,
-// zero initial guess, iterating on the device until ||r|| <= tol ||b|| or
-// maxit.  Every loop decision uses block-reduced values, so all waves of a
-// workgroup take the same path and the loop ends for all of them.
+// Persistent COCG: one 1024-lane workgroup per (system, domain) block of
+// (M - c_g S) x_g = b_g.  M and S couple only vertices of one boundary, so
+// the block of every domain is an independent system; each converges on its
+// own (||r_d|| <= tol ||b_d||) with a Jacobi preconditioner
+// (diag(M - c_g S)), zero initial guess, maxit iterations at most.  Every loop
+// decision uses block-reduced values, so all waves of a workgroup take the same
+// path and the loop ends for all of them.
 constexpr int CG_BLOCK = 1024;
 
 __device__ __forceinline__ void block_sum3(double &a, double &b, double &c, double *red)
@@ -221,10 +234,19 @@ __device__ __forceinline__ void block_sum3(double &a, double &b, double &c, doub
     }
 }
 
+// z = r / d (complex)
+__device__ __forceinline__ double2 cdiv(double2 r, double2 d)
+{
+    const double den = d.x * d.x + d.y * d.y;
+    return make_double2((r.x * d.x + r.y * d.y) / den, (r.y * d.x - r.x * d.y) / den);
+}
+
 __global__ __launch_bounds__(CG_BLOCK) void k_cocg_persistent(const int32_t *__restrict__ aptr,
                                                               const int32_t *__restrict__ acol,
+                                                              const int32_t *__restrict__ adiag,
                                                               const double *__restrict__ Mv,
                                                               const double *__restrict__ Sv,
+                                                              const int2 *__restrict__ drange, int n_dom,
                                                               const double2 *__restrict__ c,
                                                               const double2 *__restrict__ B, double2 *__restrict__ X,
                                                               double2 *__restrict__ Rw, double2 *__restrict__ Pw,
@@ -232,20 +254,26 @@ __global__ __launch_bounds__(CG_BLOCK) void k_cocg_persistent(const int32_t *__r
                                                               int maxit)
 {
     __shared__ double red[3 * (CG_BLOCK / 64)];
-    const int64_t g = blockIdx.x;
+    const int64_t g = blockIdx.x / n_dom;
+    const int2 rng = drange[blockIdx.x - g * n_dom];
     const int tid = threadIdx.x;
     const double2 cg = c[g];
     const double2 *b = B + g * n;
     double2 *x = X + g * n, *r = Rw + g * n, *pv = Pw + g * n, *q = Qw + g * n;
+    auto diag = [&](int64_t i) {
+        const int32_t e = adiag[i];
+        return make_double2(Mv[e] - cg.x * Sv[e], -cg.y * Sv[e]);
+    };
     double bn2 = 0, rr_ = 0, ri_ = 0;
-    for (int64_t i = tid; i < n; i += CG_BLOCK) {
+    for (int64_t i = rng.x + tid; i < rng.y; i += CG_BLOCK) {
         const double2 v = b[i];
+        const double2 z = cdiv(v, diag(i));
         x[i] = make_double2(0.0, 0.0);
         r[i] = v;
-        pv[i] = v;
+        pv[i] = z;
         bn2 += v.x * v.x + v.y * v.y;
-        rr_ += v.x * v.x - v.y * v.y;
-        ri_ += 2.0 * v.x * v.y;
+        rr_ += v.x * z.x - v.y * z.y;   // rho = r^T z (unconjugated)
+        ri_ += v.x * z.y + v.y * z.x;
     }
     block_sum3(bn2, rr_, ri_, red);
     if (bn2 == 0.0) return;
@@ -253,7 +281,7 @@ __global__ __launch_bounds__(CG_BLOCK) void k_cocg_persistent(const int32_t *__r
     for (int it = 0; it < maxit; ++it) {
         __syncthreads();   // p complete before the product
         double pqr = 0, pqi = 0, dummy = 0;
-        for (int64_t i = tid; i < n; i += CG_BLOCK) {
+        for (int64_t i = rng.x + tid; i < rng.y; i += CG_BLOCK) {
             double mr = 0, mi = 0, sr = 0, si = 0;
             for (int32_t e = aptr[i]; e < aptr[i + 1]; ++e) {
                 const double2 v = pv[acol[e]];
@@ -273,14 +301,15 @@ __global__ __launch_bounds__(CG_BLOCK) void k_cocg_persistent(const int32_t *__r
         if (den == 0.0) break;
         const double ar = (rho_r * pqr + rho_i * pqi) / den, ai = (rho_i * pqr - rho_r * pqi) / den;
         double rn2 = 0, sr2 = 0, si2 = 0;
-        for (int64_t i = tid; i < n; i += CG_BLOCK) {
+        for (int64_t i = rng.x + tid; i < rng.y; i += CG_BLOCK) {
             const double2 pp = pv[i], qq = q[i], xx = x[i], rv = r[i];
             x[i] = make_double2(xx.x + ar * pp.x - ai * pp.y, xx.y + ar * pp.y + ai * pp.x);
-            const double nr = rv.x - (ar * qq.x - ai * qq.y), ni = rv.y - (ar * qq.y + ai * qq.x);
-            r[i] = make_double2(nr, ni);
-            rn2 += nr * nr + ni * ni;
-            sr2 += nr * nr - ni * ni;
-            si2 += 2.0 * nr * ni;
+            const double2 nr = make_double2(rv.x - (ar * qq.x - ai * qq.y), rv.y - (ar * qq.y + ai * qq.x));
+            r[i] = nr;
+            const double2 z = cdiv(nr, diag(i));
+            rn2 += nr.x * nr.x + nr.y * nr.y;
+            sr2 += nr.x * z.x - nr.y * z.y;
+            si2 += nr.x * z.y + nr.y * z.x;
         }
         block_sum3(rn2, sr2, si2, red);
         if (rn2 <= tol * tol * bn2) break;
@@ -289,9 +318,9 @@ __global__ __launch_bounds__(CG_BLOCK) void k_cocg_persistent(const int32_t *__r
         const double br = (sr2 * rho_r + si2 * rho_i) / d2, bi = (si2 * rho_r - sr2 * rho_i) / d2;
         rho_r = sr2;
         rho_i = si2;
-        for (int64_t i = tid; i < n; i += CG_BLOCK) {
-            const double2 pp = pv[i], rv = r[i];
-            pv[i] = make_double2(rv.x + br * pp.x - bi * pp.y, rv.y + br * pp.y + bi * pp.x);
+        for (int64_t i = rng.x + tid; i < rng.y; i += CG_BLOCK) {
+            const double2 pp = pv[i], z = cdiv(r[i], diag(i));
+            pv[i] = make_double2(z.x + br * pp.x - bi * pp.y, z.y + br * pp.y + bi * pp.x);
         }
     }
 }
@@ -308,8 +337,12 @@ static void cocg_batch(bem_problem &p, int G, const std::vector<cd> &c, const do
     for (int g = 0; g < G; ++g) t[g] = make_double2(c[g].real(), c[g].imag());
     BEM_HIP(hipMemcpyAsync(cdev.p, t.data(), G * sizeof(double2), hipMemcpyHostToDevice, s));
     BEM_HIP(hipStreamSynchronize(s));
-    k_cocg_persistent<<<dim3(unsigned(G)), dim3(CG_BLOCK), 0, s>>>(p.d_aptr, p.d_acol, p.d_Mv, p.d_Sv, cdev.p, B, X,
-                                                                  R.p, Pp.p, Q.p, n, tol, maxit);
+    const int n_dom = int(p.doms.size());
+    const int64_t wgs = int64_t(G) * n_dom;
+    if (wgs >= (int64_t(1) << 31)) throw Error{BEM_ERR_UNSUPPORTED, "OSRC: too many systems in one batch"};
+    k_cocg_persistent<<<dim3(unsigned(wgs)), dim3(CG_BLOCK), 0, s>>>(p.d_aptr, p.d_acol, p.d_adiag, p.d_Mv, p.d_Sv,
+                                                                    p.d_drange, n_dom, cdev.p, B, X, R.p, Pp.p, Q.p,
+                                                                    n, tol, maxit);
     BEM_HIP(hipGetLastError());
 }
 

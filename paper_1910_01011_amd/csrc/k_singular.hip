@@ -203,14 +203,14 @@ void run_singular(bem_problem &p, const std::vector<SingularItem> &items)
     BEM_HIP(hipMalloc(&d_elem, std::max<int64_t>(1, 36 * n_items) * sizeof(double2)));
     if (n_items > 0) {
         const int B = 64;
-        k_singular<<<dim3(unsigned((n_items + B - 1) / B)), dim3(B), 0, p.stream>>>(
+        k_singular<<<dim3(blocks_1d(n_items, B)), dim3(B), 0, p.stream>>>(
             d_items, n_items, d_passes, d_rc, int(rc.size() / 5), d_re, int(re.size() / 5), d_rv, int(rv.size() / 5),
             p.d_verts, p.d_tris, p.d_area, p.d_normal, p.d_curl, d_elem);
         BEM_HIP(hipGetLastError());
     }
     if (p.nnz > 0) {
         const int B = 256;
-        k_correction_sum<<<dim3(unsigned((p.nnz + B - 1) / B)), dim3(B), 0, p.stream>>>(d_elem, d_cp, d_ci, p.nnz,
+        k_correction_sum<<<dim3(blocks_1d(p.nnz, B)), dim3(B), 0, p.stream>>>(d_elem, d_cp, d_ci, p.nnz,
                                                                                        p.d_cval);
         BEM_HIP(hipGetLastError());
     }

@@ -14,6 +14,7 @@
 // lower-precision operator), z_j = M(v_j) is stored and x is updated from the
 // z's (Saad's FGMRES), so M may change from one step to the next.
 #include <algorithm>
+#include <cstdio>
 #include <cmath>
 #include <complex>
 #include <functional>
@@ -84,6 +85,7 @@ void gmres_batch(bem_problem &p, int64_t n, int R, const double2 *B, double2 *X,
     for (int r = 0; r < R; ++r)
         if (bnorm[r] == 0.0) { conv[r] = 1; est[r] = 0.0; }
     bool first = true;
+    long steps = 0;   // Arnoldi steps of this call (for progress lines)
     for (;;) {
         std::vector<int> act;
         for (int r = 0; r < R; ++r)
@@ -190,6 +192,16 @@ void gmres_batch(bem_problem &p, int64_t n, int R, const double2 *B, double2 *X,
             }
             to_dev(sc);
             bscale(s, vj1, vj1, n, Ra, hdev.p);
+            ++steps;
+            if (o.progress > 0 && steps % o.progress == 0) {
+                double worst = 0.0;
+                int n_act = 0;
+                for (int a = 0; a < Ra; ++a)
+                    if (live[a]) { worst = std::max(worst, est[act[a]]); ++n_act; }
+                std::fprintf(stderr, "[bem] %s step %ld: %d of %d systems active, worst residual estimate %.3e\n",
+                             o.label, steps, n_act, R, worst);
+                std::fflush(stderr);
+            }
             if (!any) { ++j; break; }
         }
         // x_a += basis * y_a, y_a = H_a^{-1} g_a (upper triangular)

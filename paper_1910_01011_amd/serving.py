@@ -61,6 +61,35 @@ class Result:
         return self.finished - self.arrival
 
 
+def choose_mode(n_vertices: int, n_rhs: int, free_bytes: int):
+    """Operator mode and solver precision of a request.
+
+    On the fly (FP32 GMRES) when the dense complex64 matrix (8 (2 N_V)^2 bytes)
+    would take more than a quarter of the free HBM or when there are at most
+    two right-hand sides; otherwise assembled with split-BF16 block GMRES inside
+    FP64-residual FGMRES.
+    """
+    from . import BEM_ASSEMBLED_SPLIT_BF16, BEM_PREC_SPLIT_BF16_FGMRES
+    if 32 * n_vertices ** 2 > 0.25 * free_bytes or n_rhs <= 2:
+        return BEM_OTF, BEM_PREC_FP32
+    return BEM_ASSEMBLED_SPLIT_BF16, BEM_PREC_SPLIT_BF16_FGMRES
+
+
+def requests_from_stream(items, free_bytes: int, tol: float = 1e-5) -> list[Request]:
+    """Requests from generated stream items (problem, piston geometry, arrival):
+    one right-hand side per piston, mode from ``choose_mode``."""
+    out = []
+    for rid, it in enumerate(items):
+        prob = it["problem"]
+        c, n = it["piston_centres"], it["piston_normals"]
+        R = len(c)
+        inc = Incident.pistons(c, n, it["piston_radius"], 1.0, np.arange(R))
+        mode, prec = choose_mode(sum(d.n_vertices for d in prob.domains), R, free_bytes)
+        out.append(Request(rid, prob.domains, prob.k0, inc, rho0=prob.rho0, mode=mode, precision=prec, tol=tol,
+                           restart=100 if mode == BEM_OTF else 30, max_iter=400, arrival=it["arrival"]))
+    return out
+
+
 def footprint(req: Request) -> int:
     arr, keep = _domains(req.domains)
     opts = bem_assemble_opts()

@@ -1,0 +1,155 @@
+"""GPU parity at the rib-cage stack sizes: 53,524 vertices (on-the-fly, piston
+array, OSRC) and 26,924 vertices (assembled, 256 right-hand sides).
+
+The oracle cannot form these operators whole, so it computes sampled rows one
+by one: rows of the PMCHWT matrix, and right-hand-side entries projected over
+the triangles around each sampled vertex (the full projection restricted to
+those triangles gives exactly those entries).  The GPU runs in the launch
+shapes the benchmark uses (autotuned).  Solutions are certified by the
+oracle's residual b - A u on the sampled rows.
+
+Tolerances: apply as in the smaller parity tests (FP32 pair kernel, 1e-5);
+split-BF16 GEMM 5e-5 (each split product keeps ~16 mantissa bits, errors of
+~4e-6 per product accumulate in FP32 over up to 107k terms); residual
+certificates at 20x the solver tolerance plus the apply tolerance, since a
+sampled-row residual may sit above the global one.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from bem_inputs import configs, pistons, vectors
+
+pytestmark = pytest.mark.gpu
+
+
+def _relerr(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def rows_rhs(problem, rows, p_fn, dpdn_fn):
+    """Oracle right-hand-side entries at the selected unknowns."""
+    off = oracle.offsets(problem)
+    out = np.zeros(len(rows), dtype=np.complex128)
+    for j, d in enumerate(problem.domains):
+        sel = np.nonzero((rows >= off[j]) & (rows < off[j + 1]))[0]
+        if sel.size == 0:
+            continue
+        loc = rows[sel] - off[j]
+        is_n = loc >= d.n_vertices
+        vtx = np.where(is_n, loc - d.n_vertices, loc)
+        around = np.isin(d.triangles, vtx).any(axis=1)
+        bD, bN = oracle.project_rhs(d.vertices, d.triangles[around], p_fn, dpdn_fn)
+        out[sel] = np.where(is_n, bN[vtx], bD[vtx])
+    return out
+
+
+@pytest.fixture(scope="module")
+def bowl():
+    return pistons.bowl_array()      # 256 pistons, focal 27, aperture 20, focus at the origin
+
+
+@pytest.fixture(scope="module")
+def c3():
+    prob = configs.ribcage(1.0)
+    rows = vectors.random_rows(prob.n_unknowns, 16, seed=3)
+    print(f"ribcage h=1: {sum(d.n_vertices for d in prob.domains)} vertices; oracle rows ...", flush=True)
+    return prob, rows, oracle.pmchwt_rows(prob, rows)
+
+
+def test_config3_sampled_rows_apply_and_piston_rhs(c3, bowl):
+    import paper_1910_01011_amd as bem
+    prob, rows, R = c3
+    P = bem.Problem.from_config(prob, autotune=True)
+    x = vectors.random_complex(prob.n_unknowns, seed=0)
+    y = P.apply(x)
+    err = _relerr(y[rows], R @ x)
+    print(f"ribcage h=1 apply, shape {P.pair_launch_shape()}: sampled-row rel err {err:.3e}")
+    assert err <= 1e-5
+    centres, normals, radius = bowl
+    inc = bem.Incident.pistons(centres, normals, radius, 1.0, np.zeros(len(centres), dtype=int))
+    b = P.rhs(inc)[0]
+    ref = rows_rhs(prob, rows, *oracle.piston_field(prob.k0, centres, normals, radius, 1.0))
+    err_b = _relerr(b[rows], ref)
+    print(f"ribcage h=1 piston rhs: sampled rel err {err_b:.3e}")
+    assert err_b <= 1e-10
+    P.close()
+
+
+def test_config3_reduced_h_osrc_solve_certificate(bowl):
+    """Config 3's solver settings (256 pistons as one field, OSRC N_Pade = 8,
+    R_eps = 1.5, GMRES(100) to 1e-5) on the stack meshed at twice the element
+    size; residual certified by the oracle on sampled rows."""
+    import paper_1910_01011_amd as bem
+    prob = configs.ribcage(2.0)
+    P = bem.Problem.from_config(prob, autotune=True)
+    centres, normals, radius = bowl
+    inc = bem.Incident.pistons(centres, normals, radius, 1.0, np.zeros(len(centres), dtype=int))
+    b = P.rhs(inc)
+    u, info = P.solve(b, bem.solve_options(tol=1e-5, restart=100, max_iter=400, precond=bem.BEM_PRECOND_OSRC,
+                                           n_pade=8, r_eps=1.5, theta=np.pi / 3))
+    P.close()
+    u = u[0]
+    print(f"ribcage h=2 OSRC solve: {info[0]}", flush=True)
+    assert info[0]["converged"]
+    rows = vectors.random_rows(prob.n_unknowns, 24, seed=11)
+    A_rows = oracle.pmchwt_rows(prob, rows)
+    b_rows = rows_rhs(prob, rows, *oracle.piston_field(prob.k0, centres, normals, radius, 1.0))
+    cert = float(np.linalg.norm(b_rows - A_rows @ u) / np.linalg.norm(b_rows))
+    print(f"ribcage h=2 sampled-row residual certificate {cert:.3e} (solver reports {info[0]['rel_residual']:.3e})")
+    assert cert <= 20 * 1e-5 + 1e-5
+
+
+@pytest.fixture(scope="module")
+def c4():
+    import paper_1910_01011_amd as bem
+    prob = configs.ribcage(2.0 ** 0.5)
+    rows = vectors.random_rows(prob.n_unknowns, 16, seed=4)
+    print(f"ribcage h=sqrt2: {sum(d.n_vertices for d in prob.domains)} vertices; oracle rows ...", flush=True)
+    R = oracle.pmchwt_rows(prob, rows)
+    P = bem.Problem.from_config(prob, device=False, mode=bem.BEM_ASSEMBLED_SPLIT_BF16, autotune=True)
+    yield prob, rows, R, P
+    P.close()
+
+
+def test_config4_sampled_rows_gemm_r256(c4):
+    import paper_1910_01011_amd as bem
+    prob, rows, R, P = c4
+    X = vectors.random_complex(prob.n_unknowns, seed=1, n_rhs=256)
+    ref = X @ R.T                                   # [256, rows]
+    for kernel, tol in ((bem.BEM_APPLY_MFMA_SPLIT_BF16, 5e-5), (bem.BEM_APPLY_MFMA_FP32, 1e-5),
+                        (bem.BEM_APPLY_GEMV, 1e-5)):
+        Xk = X if kernel != bem.BEM_APPLY_GEMV else X[:4]
+        Y = P.apply(Xk, kernel=kernel)
+        err = _relerr(Y[:, rows], ref[:Xk.shape[0]])
+        print(f"ribcage h=sqrt2 kernel {kernel} R={Xk.shape[0]}: sampled-row rel err {err:.3e}")
+        assert err <= tol
+
+
+def test_config4_split_bf16_fgmres_pistons(c4, bowl, monkeypatch):
+    """Config 4's solver (split-BF16 inner block GMRES inside FP64-residual
+    FGMRES) on 32 of the 256 pistons, one right-hand side each, to 1e-5; the
+    oracle certifies 8 of them on the sampled rows.  The layered stack needs
+    hundreds of unpreconditioned Krylov steps, hence the long inner cycles."""
+    import paper_1910_01011_amd as bem
+    prob, rows, R, P = c4
+    monkeypatch.setenv("BEM_PROGRESS", "100")
+    centres, normals, radius = bowl
+    sel = np.arange(0, 256, 8)
+    inc = bem.Incident.pistons(centres[sel], normals[sel], radius, 1.0, np.arange(len(sel)))
+    b = P.rhs(inc)
+    u, info = P.solve(b, bem.solve_options(tol=1e-5, restart=10, max_iter=8,
+                                           precision=bem.BEM_PREC_SPLIT_BF16_FGMRES, inner_tol=1e-3,
+                                           inner_restart=100, inner_max_iter=1500))
+    its = [i["iterations"] for i in info]
+    worst = max(i["rel_residual"] for i in info)
+    print(f"ribcage h=sqrt2 FGMRES R={len(sel)}: outer iterations {min(its)}..{max(its)}, worst rel residual {worst:.3e}")
+    assert all(i["converged"] for i in info)
+    for f in range(0, len(sel), 4):
+        e = sel[f]
+        b_rows = rows_rhs(prob, rows, *oracle.piston_field(prob.k0, centres[e:e + 1], normals[e:e + 1], radius, 1.0))
+        cert = float(np.linalg.norm(b_rows - R @ u[f]) / np.linalg.norm(b_rows))
+        print(f"  piston {e}: sampled-row residual certificate {cert:.3e}")
+        assert cert <= 20 * 1e-5 + 1e-5

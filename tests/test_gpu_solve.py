@@ -74,6 +74,25 @@ def test_flexible_gmres_block(c1, form):
         assert err <= (1e-4 if "BF16" in form else 1e-5)
 
 
+def test_flexible_gmres_with_osrc_inner_preconditioning(c1):
+    """FGMRES whose inner block GMRES runs on the OSRC left-preconditioned
+    system; the outer FP64 residual decides convergence, so the solution matches
+    the dense LU one as in the unpreconditioned forms."""
+    prob, A, B, U = c1
+    bem = _bem()
+    P = bem.Problem.from_config(prob, mode=bem.BEM_ASSEMBLED_SPLIT_BF16)
+    opts = bem.solve_options(tol=1e-8, restart=30, max_iter=60, precision=bem.BEM_PREC_SPLIT_BF16_FGMRES,
+                             inner_tol=1e-3, precond=bem.BEM_PRECOND_OSRC, n_pade=4, r_eps=0.1,
+                             inner_restart=40, inner_max_iter=200)
+    u, info = P.solve(B, opts)
+    for r in range(len(DIRS)):
+        err = _blocks_err(prob, u[r], U[r])
+        print(f"FGMRES + OSRC rhs {r}: {info[r]} err {err:.2e}")
+        assert info[r]["converged"]
+        assert err <= 1e-4
+    P.close()
+
+
 def test_not_converged_returns_warning_and_best_iterate(c1):
     prob, A, B, U = c1
     bem = _bem()
