@@ -100,39 +100,50 @@ def ribcage(h_scale: float = 1.0, f_rel: float = 1.0) -> Problem:
     return Problem(doms, complex(k0), 1.0, f"ribcage_h{h_scale:g}")
 
 
-def kidney(f_rel: float = 1.0, elements_per_wavelength: float = 6.0, level: int | None = None) -> Problem:
+def kidney(f_rel: float = 1.0, elements_per_wavelength: float = 6.0, level: int | None = None,
+           freq: int | None = None) -> Problem:
     """Kidney ellipsoid (5, 3, 2.5) plus a perinephric fat shell with a 2/3 gap.
 
     Kidney: speed ratio 1.04, density 1.066.  Fat shell: inner semi-axes
-    + 2/3, outer + 2/3 + 1, speed ratio 0.941, density 0.917.
+    + 2/3, outer + 2/3 + 1, speed ratio 0.941, density 0.917.  The three
+    surfaces are icospheres of ``level`` when it is given, else geodesic
+    spheres of frequency ``freq`` (default: from the element size
+    h = min(1, s_fat)/f_rel/elements_per_wavelength on the largest surface).
     """
     k0 = 2.0 * np.pi * f_rel
     s_k, s_f = 1.04, 0.941
     axes = np.array([5.0, 3.0, 2.5])
     g = 2.0 / 3.0
-    if level is None:
-        h = min(1.0, s_f) / f_rel / elements_per_wavelength
-        # icosphere mean edge ~ 1.05 * R * 2**-level; pick the level for the largest axis
-        level = int(np.clip(np.ceil(np.log2(1.05 * (axes[0] + g + 1.0) / h)), 1, 8))
-    vk, tk = meshes.ellipsoid(level, axes)
-    vs, ts = meshes.shell(level, axes + g, axes + g + 1.0)
+    if level is not None:
+        vk, tk = meshes.ellipsoid(level, axes)
+        vs, ts = meshes.shell(level, axes + g, axes + g + 1.0)
+        tag = f"l{level}"
+    else:
+        if freq is None:
+            freq = kidney_freq(f_rel, elements_per_wavelength)
+        vk, tk = meshes.geodesic_ellipsoid(freq, axes)
+        vs, ts = meshes.geodesic_shell(freq, axes + g, axes + g + 1.0)
+        tag = f"g{freq}"
     return Problem([Domain(vk, tk, complex(k0 / s_k), 1.066, "kidney"),
                     Domain(vs, ts, complex(k0 / s_f), 0.917, "fat_shell")], complex(k0), 1.0,
-                   f"kidney_l{level}")
+                   f"kidney_{tag}")
 
 
 _MESH_CACHE: dict = {}
 
 
-def kidney_level(f_rel: float, elements_per_wavelength: float) -> int:
-    """Icosphere level giving element size h = min(1, s_fat)/f_rel/e on the largest surface."""
+def kidney_freq(f_rel: float, elements_per_wavelength: float) -> int:
+    """Geodesic frequency giving element size h = min(1, s_fat)/f_rel/e along
+    the longest semi-axis of the outer shell surface (mean edge of a geodesic
+    sphere of radius a and frequency n is about 1.2 a/n)."""
     s_f = 0.941
     h = min(1.0, s_f) / f_rel / elements_per_wavelength
-    return int(np.clip(np.ceil(np.log2(1.05 * (5.0 + 2.0 / 3.0 + 1.0) / h)), 1, 8))
+    return max(1, int(np.ceil(1.2 * (5.0 + 2.0 / 3.0 + 1.0) / h - 1e-9)))
 
 
-def kidney_vertices(level: int) -> int:
-    return 3 * (10 * 4 ** level + 2)
+def kidney_vertices(freq: int) -> int:
+    """Vertices of the kidney workload: three geodesic surfaces of frequency freq."""
+    return 3 * (10 * freq ** 2 + 2)
 
 
 def serving_stream(rate: float, n_requests: int, seed_arrivals: int, seed_params: int,
@@ -140,8 +151,9 @@ def serving_stream(rate: float, n_requests: int, seed_arrivals: int, seed_params
     """Poisson arrivals of kidney + fat-shell solve requests (serving workload).
 
     Per request: f_rel ~ U[f_range], elements per wavelength e ~ U{epw}, mesh
-    level from h = min(lambda_0, lambda_j)/e, redrawn until the total vertex
-    count lies in vertex_range; R ~ U{rhs_range} transducer elements drawn from
+    frequency from h = min(lambda_0, lambda_j)/e (geodesic surfaces, so the
+    size follows h continuously), redrawn until the total vertex count lies in
+    vertex_range; R ~ U{rhs_range} transducer elements drawn from
     a 256-element bowl (aperture 20, focal length 27) focused on the kidney
     centre with axis along [1, -1, 0], one right-hand side per element.
     Returns dicts with the problem, the element geometry and the arrival time.
@@ -157,21 +169,21 @@ def serving_stream(rate: float, n_requests: int, seed_arrivals: int, seed_params
         for _ in range(1000):
             f = rp.uniform(*f_range)
             e = int(rp.choice(epw))
-            level = kidney_level(f, e)
-            if vertex_range[0] <= kidney_vertices(level) <= vertex_range[1]:
+            nu = kidney_freq(f, e)
+            if vertex_range[0] <= kidney_vertices(nu) <= vertex_range[1]:
                 break
         else:
             raise RuntimeError("no mesh level inside the vertex range")
         R = int(rp.integers(rhs_range[0], rhs_range[1] + 1))
         sel = np.sort(rp.choice(256, size=R, replace=False))
-        key = level
+        key = nu
         if key not in _MESH_CACHE:
-            _MESH_CACHE[key] = kidney(1.0, level=level)
+            _MESH_CACHE[key] = kidney(1.0, freq=nu)
         base = _MESH_CACHE[key]
         k0 = 2.0 * np.pi * f
         doms = [Domain(d.vertices, d.triangles, complex(k0 / s), d.rho, d.name)
                 for d, s in zip(base.domains, (1.04, 0.941))]
-        prob = Problem(doms, complex(k0), 1.0, f"kidney_l{level}_f{f:.2f}")
-        out.append({"problem": prob, "f_rel": f, "level": level, "arrival": float(arrivals[i]),
+        prob = Problem(doms, complex(k0), 1.0, f"kidney_g{nu}_f{f:.2f}")
+        out.append({"problem": prob, "f_rel": f, "freq": nu, "arrival": float(arrivals[i]),
                     "piston_centres": centres[sel], "piston_normals": normals[sel], "piston_radius": radius})
     return out

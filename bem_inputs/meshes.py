@@ -226,6 +226,64 @@ def shell(level: int, inner_axes, outer_axes, center=(0.0, 0.0, 0.0)):
     return v, np.ascontiguousarray(t)
 
 
+def geodesic_sphere(freq: int, radius: float = 1.0, center=(0.0, 0.0, 0.0)):
+    """Class-I geodesic sphere: every icosahedron face split into freq**2
+    triangles on a barycentric grid, grid points projected onto the sphere.
+
+    Sizes: 10*freq**2 + 2 vertices and 20*freq**2 triangles, for any
+    freq >= 1 (freq = 2**level gives the icosphere's counts), so the element
+    size can follow a target h continuously.  Grid points on shared edges and
+    corners are merged through their integer barycentric weights on the
+    icosahedron's vertex ids.
+    """
+    if freq < 1:
+        raise ValueError("freq must be >= 1")
+    v0, t0 = icosahedron()
+    index: dict[tuple, int] = {}
+    verts: list[np.ndarray] = []
+
+    def vid(ids, wts):
+        key = tuple(sorted((int(i), int(w)) for i, w in zip(ids, wts) if w > 0))
+        k = index.get(key)
+        if k is None:
+            k = len(verts)
+            index[key] = k
+            p = sum(w * v0[i] for i, w in key) / float(freq)
+            verts.append(p / np.linalg.norm(p))
+        return k
+
+    tris = []
+    for a, b, c in t0:
+        g = {}
+        for i in range(freq + 1):
+            for j in range(freq + 1 - i):
+                g[i, j] = vid((a, b, c), (freq - i - j, i, j))
+        for i in range(freq):
+            for j in range(freq - i):
+                tris.append([g[i, j], g[i + 1, j], g[i, j + 1]])
+                if i + j <= freq - 2:
+                    tris.append([g[i + 1, j], g[i + 1, j + 1], g[i, j + 1]])
+    v = np.asarray(verts, dtype=np.float64) * radius + np.asarray(center, dtype=np.float64)
+    return v, _orient_outward(v, np.asarray(tris, dtype=np.int32))
+
+
+def geodesic_ellipsoid(freq: int, semi_axes=(1.0, 1.0, 1.0), center=(0.0, 0.0, 0.0)):
+    """Geodesic sphere of frequency ``freq`` scaled along the coordinate axes."""
+    v, t = geodesic_sphere(freq)
+    v = v * np.asarray(semi_axes, dtype=np.float64) + np.asarray(center, dtype=np.float64)
+    return v, _orient_outward(v, t)
+
+
+def geodesic_shell(freq: int, inner_axes, outer_axes, center=(0.0, 0.0, 0.0)):
+    """Thick shell between two geodesic ellipsoids (inner surface reversed)."""
+    vo, to = geodesic_ellipsoid(freq, outer_axes, center)
+    vi, ti = geodesic_ellipsoid(freq, inner_axes, center)
+    ti = ti[:, [0, 2, 1]]
+    v = np.concatenate([vo, vi])
+    t = np.concatenate([to, ti + len(vo)]).astype(np.int32)
+    return v, np.ascontiguousarray(t)
+
+
 def mesh_size(v: np.ndarray, t: np.ndarray) -> float:
     """Mean edge length (used only to report h for a generated mesh)."""
     e = np.concatenate([v[t[:, 1]] - v[t[:, 0]], v[t[:, 2]] - v[t[:, 1]], v[t[:, 0]] - v[t[:, 2]]])

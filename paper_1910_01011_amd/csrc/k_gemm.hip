@@ -95,74 +95,147 @@ __device__ __forceinline__ void tile_of(int id, int n_m, int n_n, int n_s, int &
     (void)n_m;
 }
 
-__global__ __launch_bounds__(256) void k_gemm_bf16x3(const uint16_t *__restrict__ Ahi, const uint16_t *__restrict__ Alo,
-                                                     const uint16_t *__restrict__ Bhi, const uint16_t *__restrict__ Blo,
-                                                     int64_t M, int64_t Kp, int n_m, int n_n, int n_s, int64_t kslice,
-                                                     float *__restrict__ C, int64_t Np)
+// Tile order of the split-BF16 GEMM: on each XCD the K slice varies slowest,
+// then the XCD's m-tiles, then the n-tiles, so the workgroups resident at one
+// time on an XCD read the same K range of X' and share A rows across n-tiles
+// in that XCD's L2.
+__device__ __forceinline__ void tile_of_kouter(int id, int n_m, int n_n, int &mt, int &nt, int &ks)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t sA[2][GBM * GBKP];
-    __shared__ __attribute__((aligned(16))) uint16_t sB[2][GBN * GBKP];
+    const int per_x = (n_m + 7) / 8;
+    const int xcd = id & 7, slot = id >> 3;
+    ks = slot / (per_x * n_n);
+    const int rem = slot - ks * per_x * n_n;
+    const int loc = rem / n_n;
+    nt = rem - loc * n_n;
+    mt = loc * 8 + xcd;
+}
+
+// Split-BF16 GEMM.  Workgroup tile XBM x GBN (256 x 128): four waves stacked
+// along M, each owning 64 rows x 128 columns (4 x 8 MFMA tiles of 16 x 16,
+// 128 FP32 accumulators per lane).  A fragments are loaded from global memory
+// straight into registers in the MFMA operand layout (each row block is read
+// by exactly one wave, so staging it through LDS would only add LDS traffic);
+// two register sets alternate so the loads of step t + 2 are in flight during
+// step t + 1.  The X' tile (shared by the four waves) goes through a
+// double-buffered LDS tile, one barrier per K step of 32.  K slices are
+// multiples of 64, so every slice has an even number of steps.
+constexpr int XBM = 256;    // rows of a split-BF16 workgroup tile
+constexpr int XWB = 4;      // 16-row blocks per wave
+constexpr int GKA = 64;     // alignment of Kp and of the K slices
+
+__device__ __forceinline__ void load_a_frags(const uint16_t *const *pah, const uint16_t *const *pal, int64_t k,
+                                             bf16x8 (&ah)[XWB], bf16x8 (&al)[XWB])
+{
+#pragma unroll
+    for (int i = 0; i < XWB; ++i) {
+        ah[i] = *reinterpret_cast<const bf16x8 *>(pah[i] + k);
+        al[i] = *reinterpret_cast<const bf16x8 *>(pal[i] + k);
+    }
+}
+
+// one K step of 32: 8 column blocks x (hi hi, hi lo, lo hi) x 4 row blocks
+__device__ __forceinline__ void mfma_step(const uint16_t *sBh, const uint16_t *sBl, int frow, int fk,
+                                          const bf16x8 (&ah)[XWB], const bf16x8 (&al)[XWB], f32x4 (&acc)[XWB][8])
+{
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&sBh[(16 * j + frow) * GBKP + fk]);
+        const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(&sBl[(16 * j + frow) * GBKP + fk]);
+#pragma unroll
+        for (int i = 0; i < XWB; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < XWB; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < XWB; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+    }
+}
+
+__global__ __launch_bounds__(256, 2) void k_gemm_bf16x3(const uint16_t *__restrict__ Ahi,
+                                                        const uint16_t *__restrict__ Alo,
+                                                        const uint16_t *__restrict__ Bhi,
+                                                        const uint16_t *__restrict__ Blo, int64_t M, int64_t Kp,
+                                                        int n_m, int n_n, int64_t kslice, float *__restrict__ C,
+                                                        int64_t Np)
+{
+    constexpr int WM = 16 * XWB;
+    __shared__ __attribute__((aligned(16))) uint16_t sB[2][2][GBN * GBKP];   // [buffer][hi, lo]
     int mt, nt, ks;
-    tile_of(blockIdx.x, n_m, n_n, n_s, mt, nt, ks);
+    tile_of_kouter(blockIdx.x, n_m, n_n, mt, nt, ks);
     if (mt >= n_m) return;   // padding ids of the XCD-grouped order
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int64_t m0 = int64_t(mt) * GBM, n0 = int64_t(nt) * GBN;
+    const int64_t m0 = int64_t(mt) * XBM, n0 = int64_t(nt) * GBN;
     const int64_t kb = int64_t(ks) * kslice, ke = std::min<int64_t>(Kp, kb + kslice);
-    const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
-    f32x4 acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+    const int nk = int((ke - kb) / GBK);   // even, >= 2
+    const int64_t klast = int64_t(nk - 1) * GBK;
     const int frow = lane & 15, fk = 8 * (lane >> 4);
-    for (int64_t k0 = kb; k0 < ke; k0 += GBK) {
-        // 128 rows x 32 bf16 per plane = 512 chunks of 16 B; two per thread
+    // A operand rows of this lane (rows past M read row M - 1; never stored)
+    const uint16_t *pah[XWB], *pal[XWB];
 #pragma unroll
-        for (int it = 0; it < 2; ++it) {
-            const int c = tid + 256 * it;
-            const int row = c >> 2, ch = c & 3;
-            const int64_t gr = m0 + row;
-            uint4 vh = make_uint4(0, 0, 0, 0), vl = make_uint4(0, 0, 0, 0);
-            if (gr < M) {
-                vh = *reinterpret_cast<const uint4 *>(Ahi + gr * Kp + k0 + 8 * ch);
-                vl = *reinterpret_cast<const uint4 *>(Alo + gr * Kp + k0 + 8 * ch);
-            }
-            *reinterpret_cast<uint4 *>(&sA[0][row * GBKP + 8 * ch]) = vh;
-            *reinterpret_cast<uint4 *>(&sA[1][row * GBKP + 8 * ch]) = vl;
-            const int64_t gn = n0 + row;   // always < Np (padded)
-            *reinterpret_cast<uint4 *>(&sB[0][row * GBKP + 8 * ch]) =
-                *reinterpret_cast<const uint4 *>(Bhi + gn * Kp + k0 + 8 * ch);
-            *reinterpret_cast<uint4 *>(&sB[1][row * GBKP + 8 * ch]) =
-                *reinterpret_cast<const uint4 *>(Blo + gn * Kp + k0 + 8 * ch);
-        }
+    for (int i = 0; i < XWB; ++i) {
+        const int64_t r = std::min<int64_t>(M - 1, m0 + WM * w + 16 * i + frow);
+        pah[i] = Ahi + r * Kp + kb + fk;
+        pal[i] = Alo + r * Kp + kb + fk;
+    }
+    // X' tile staging: 128 rows x 4 chunks of 16 B per plane, two chunks per
+    // thread and plane; loads past the slice are clamped to its last step
+    // (valid memory, value unused)
+    const uint16_t *pbh[2], *pbl[2];
+    int soff[2];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const int c = tid + 256 * it, row = c >> 2, ch = c & 3;
+        pbh[it] = Bhi + (n0 + row) * Kp + kb + 8 * ch;   // n0 + row < Np (padded)
+        pbl[it] = Blo + (n0 + row) * Kp + kb + 8 * ch;
+        soff[it] = row * GBKP + 8 * ch;
+    }
+    uint4 b0h, b0l, b1h, b1l;
+    auto load_b = [&](int64_t k) {
+        k = std::min<int64_t>(k, klast);
+        b0h = *reinterpret_cast<const uint4 *>(pbh[0] + k);
+        b0l = *reinterpret_cast<const uint4 *>(pbl[0] + k);
+        b1h = *reinterpret_cast<const uint4 *>(pbh[1] + k);
+        b1l = *reinterpret_cast<const uint4 *>(pbl[1] + k);
+    };
+    auto store_b = [&](int buf) {
+        *reinterpret_cast<uint4 *>(&sB[buf][0][soff[0]]) = b0h;
+        *reinterpret_cast<uint4 *>(&sB[buf][1][soff[0]]) = b0l;
+        *reinterpret_cast<uint4 *>(&sB[buf][0][soff[1]]) = b1h;
+        *reinterpret_cast<uint4 *>(&sB[buf][1][soff[1]]) = b1l;
+    };
+    f32x4 acc[XWB][8];
+#pragma unroll
+    for (int i = 0; i < XWB; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+    bf16x8 xh[XWB], xl[XWB], yh[XWB], yl[XWB];
+    load_b(0);
+    load_a_frags(pah, pal, 0, xh, xl);
+    load_a_frags(pah, pal, GBK, yh, yl);
+    store_b(0);
+    __syncthreads();
+    for (int t = 0; t < nk; t += 2) {
+        // even step: LDS buffer 0, registers x
+        load_b(int64_t(t + 1) * GBK);
+        mfma_step(sB[0][0], sB[0][1], frow, fk, xh, xl, acc);
+        load_a_frags(pah, pal, std::min<int64_t>(int64_t(t + 2) * GBK, klast), xh, xl);
+        store_b(1);
         __syncthreads();
-        bf16x8 ah[4], al[4], bh[4], bl[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            ah[i] = *reinterpret_cast<const bf16x8 *>(&sA[0][(wm + 16 * i + frow) * GBKP + fk]);
-            al[i] = *reinterpret_cast<const bf16x8 *>(&sA[1][(wm + 16 * i + frow) * GBKP + fk]);
-            bh[i] = *reinterpret_cast<const bf16x8 *>(&sB[0][(wn + 16 * i + frow) * GBKP + fk]);
-            bl[i] = *reinterpret_cast<const bf16x8 *>(&sB[1][(wn + 16 * i + frow) * GBKP + fk]);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-            }
+        // odd step: LDS buffer 1, registers y
+        load_b(int64_t(t + 2) * GBK);
+        mfma_step(sB[1][0], sB[1][1], frow, fk, yh, yl, acc);
+        load_a_frags(pah, pal, std::min<int64_t>(int64_t(t + 3) * GBK, klast), yh, yl);
+        store_b(0);
         __syncthreads();
     }
     float *Cs = C + int64_t(ks) * M * Np;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < XWB; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 8; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int64_t row = m0 + wm + 16 * i + 4 * (lane >> 4) + e;
-                const int64_t col = n0 + wn + 16 * j + frow;
+                const int64_t row = m0 + WM * w + 16 * i + 4 * (lane >> 4) + e;
+                const int64_t col = n0 + 16 * j + frow;
                 if (row < M) Cs[row * Np + col] = acc[i][j][e];
             }
 }
@@ -238,25 +311,48 @@ __global__ __launch_bounds__(256) void k_gemm_f32(const float *__restrict__ A, i
             }
 }
 
-// Y_j[r] = (sum_s C_s[r][j], sum_s C_s[r][R + j])  (fixed slice order, FP64 sums)
-__global__ void k_unpack_y(const float *__restrict__ C, int64_t M, int64_t Np, int R, int n_s, double2 *__restrict__ Y)
+// Y_j[r] = (sum_s C_s[r][j], sum_s C_s[r][R + j])  (fixed slice order, FP64
+// sums).  One workgroup per 32 x 32 tile of (r, j): the partials are read
+// along j (rows of C are contiguous in j) and the sums written along r through
+// an LDS transpose, so both sides are coalesced.
+constexpr int UT = 32;
+__global__ __launch_bounds__(256) void k_unpack_y(const float *__restrict__ C, int64_t M, int64_t Np, int R, int n_s,
+                                                  double2 *__restrict__ Y)
 {
-    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= M * R) return;
-    const int64_t j = idx / M, r = idx - j * M;
-    double re = 0, im = 0;
-    for (int s = 0; s < n_s; ++s) {
-        re += C[(int64_t(s) * M + r) * Np + j];
-        im += C[(int64_t(s) * M + r) * Np + R + j];
+    __shared__ double2 tile[UT][UT + 1];
+    const int64_t r0 = int64_t(blockIdx.x) * UT;
+    const int j0 = blockIdx.y * UT;
+    const int t = threadIdx.x;
+    {
+        const int jj = t & (UT - 1);
+        for (int rr = t / UT; rr < UT; rr += 256 / UT) {
+            const int64_t r = r0 + rr;
+            const int j = j0 + jj;
+            double re = 0, im = 0;
+            if (r < M && j < R) {
+                for (int s = 0; s < n_s; ++s) {
+                    const float *row = C + (int64_t(s) * M + r) * Np;
+                    re += row[j];
+                    im += row[R + j];
+                }
+            }
+            tile[rr][jj] = make_double2(re, im);
+        }
     }
-    Y[j * M + r] = make_double2(re, im);
+    __syncthreads();
+    const int rr = t & (UT - 1);
+    for (int jj = t / UT; jj < UT; jj += 256 / UT) {
+        const int64_t r = r0 + rr;
+        const int j = j0 + jj;
+        if (r < M && j < R) Y[int64_t(j) * M + r] = tile[rr][jj];
+    }
 }
 
 static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 void split_matrix_bf16(bem_problem &p)
 {
-    const int64_t Kp = round_up(2 * p.N, GBK);
+    const int64_t Kp = round_up(2 * p.N, GKA);
     BEM_HIP(hipMalloc(&p.d_Ahi, size_t(p.N) * Kp * sizeof(uint16_t)));
     BEM_HIP(hipMalloc(&p.d_Alo, size_t(p.N) * Kp * sizeof(uint16_t)));
     const int64_t tot = p.N * Kp;
@@ -270,9 +366,9 @@ GemmPlan gemm_plan(const bem_problem &p, int R, bool bf16, int force_slices)
     GemmPlan g{};
     g.R = R;
     g.bf16 = bf16;
-    g.Kp = round_up(2 * p.N, GBK);
+    g.Kp = round_up(2 * p.N, GKA);
     g.Np = round_up(2 * int64_t(R), GBN);
-    g.n_m = int((p.N + GBM - 1) / GBM);
+    g.n_m = int((p.N + (bf16 ? XBM : GBM) - 1) / (bf16 ? XBM : GBM));
     g.n_n = int(g.Np / GBN);
     const int64_t ksteps = g.Kp / GBK;
     // enough workgroups to cover every CU several times
@@ -280,7 +376,7 @@ GemmPlan gemm_plan(const bem_problem &p, int R, bool bf16, int force_slices)
     s = int(std::min<int64_t>(s, std::max<int64_t>(1, ksteps / 8)));
     g.n_s = std::max(1, std::min(s, 64));
     if (force_slices > 0) g.n_s = int(std::min<int64_t>(force_slices, ksteps));
-    g.kslice = round_up((g.Kp + g.n_s - 1) / g.n_s, GBK);
+    g.kslice = round_up((g.Kp + g.n_s - 1) / g.n_s, GKA);
     g.n_s = int((g.Kp + g.kslice - 1) / g.kslice);
     const int groups = (g.n_m + 7) / 8;
     g.n_wg = groups * 8 * g.n_n * g.n_s;
@@ -295,7 +391,7 @@ void launch_gemm_kernel(bem_problem &p, const GemmPlan &g, void *xbuf, float *cb
     if (g.bf16) {
         uint16_t *hi = static_cast<uint16_t *>(xbuf), *lo = hi + tot;
         k_gemm_bf16x3<<<dim3(unsigned(g.n_wg)), dim3(256), 0, p.stream>>>(p.d_Ahi, p.d_Alo, hi, lo, p.N, g.Kp, g.n_m,
-                                                                         g.n_n, g.n_s, g.kslice, cbuf, g.Np);
+                                                                         g.n_n, g.kslice, cbuf, g.Np);
     } else {
         k_gemm_f32<<<dim3(unsigned(g.n_wg)), dim3(256), 0, p.stream>>>(reinterpret_cast<const float *>(p.d_A), 2 * p.N,
                                                                       static_cast<float *>(xbuf), p.N, 2 * p.N, g.Kp,
@@ -314,7 +410,7 @@ void launch_gemm(bem_problem &p, const GemmPlan &g, const double2 *X, double2 *Y
         BEM_HIP(hipGetLastError());
         if (p.timed_gemm) BEM_HIP(hipEventRecord(p.ev[1], p.stream));
         k_gemm_bf16x3<<<dim3(unsigned(g.n_wg)), dim3(256), 0, p.stream>>>(p.d_Ahi, p.d_Alo, hi, lo, p.N, g.Kp, g.n_m,
-                                                                         g.n_n, g.n_s, g.kslice, cbuf, g.Np);
+                                                                         g.n_n, g.kslice, cbuf, g.Np);
     } else {
         float *xf = static_cast<float *>(xbuf);
         k_pack_rhs<false><<<dim3(blocks_1d(tot, 256, true)), dim3(256), 0, p.stream>>>(X, p.N, g.R, g.Np, g.Kp, xf,
@@ -327,8 +423,8 @@ void launch_gemm(bem_problem &p, const GemmPlan &g, const double2 *X, double2 *Y
     }
     BEM_HIP(hipGetLastError());
     if (p.timed_gemm) BEM_HIP(hipEventRecord(p.ev[2], p.stream));
-    const int64_t ny = p.N * g.R;
-    k_unpack_y<<<dim3(blocks_1d(ny, 256)), dim3(256), 0, p.stream>>>(cbuf, p.N, g.Np, g.R, g.n_s, Y);
+    const dim3 ugrid(unsigned((p.N + UT - 1) / UT), unsigned((g.R + UT - 1) / UT));
+    k_unpack_y<<<ugrid, dim3(256), 0, p.stream>>>(cbuf, p.N, g.Np, g.R, g.n_s, Y);
     BEM_HIP(hipGetLastError());
 }
 
