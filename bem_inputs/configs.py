@@ -187,3 +187,55 @@ def serving_stream(rate: float, n_requests: int, seed_arrivals: int, seed_params
         out.append({"problem": prob, "f_rel": f, "freq": nu, "arrival": float(arrivals[i]),
                     "piston_centres": centres[sel], "piston_normals": normals[sel], "piston_radius": radius})
     return out
+
+
+# Media of the paper's table of physical properties (density kg/m^3, speed of
+# sound m/s, attenuation Np/m at 1 MHz, power law exponent); water is the
+# exterior of every workload.
+TABLE_MEDIA = {
+    "ribs": (1178.0, 2117.5, 47.0, 1.0),
+    "fat": (917.0, 1412.0, 9.3, 1.0),
+    "kidney": (1066.0, 1554.3, 2.8067, 1.0),
+    "liver": (1070.0, 1640.0, 7.0, 1.30),
+    "water": (1000.0, 1500.0, 0.015, 2.0),
+}
+
+
+def medium_wavenumber(name: str, f_mhz: float, wavelength_m: float) -> complex:
+    """k = omega/c + i alpha0 (f / 1 MHz)^b in units of 1/wavelength_m."""
+    rho, c, a0, b = TABLE_MEDIA[name]
+    k = 2.0 * np.pi * f_mhz * 1e6 / c + 1j * a0 * f_mhz ** b
+    return complex(k * wavelength_m)
+
+
+def paper_sphere(material: str = "fat", elements_per_wavelength: float = 6.0, f_mhz: float = 1.0,
+                 diameter_m: float = 0.01, freq: int | None = None) -> Problem:
+    """The single-sphere model problem of the paper's numerical experiments.
+
+    A sphere of diameter 1 cm in water at 1 MHz, filled with fat or with the
+    table's rib material, attenuating wavenumbers from the table.  Lengths are
+    in water wavelengths (1.5 mm at 1 MHz).  The mesh is a geodesic sphere
+    whose mean edge is h = lambda_min / e, lambda_min the shorter of the two
+    wavelengths (the paper's elements-per-wavelength rule).
+    """
+    lam0 = TABLE_MEDIA["water"][1] / (f_mhz * 1e6)
+    a = 0.5 * diameter_m / lam0
+    k0 = medium_wavenumber("water", f_mhz, lam0)
+    k1 = medium_wavenumber(material, f_mhz, lam0)
+    rho_ratio = TABLE_MEDIA[material][0] / TABLE_MEDIA["water"][0]
+    lam_min = min(1.0, TABLE_MEDIA[material][1] / TABLE_MEDIA["water"][1])
+    if freq is None:
+        freq = max(1, int(np.ceil(1.2 * a * elements_per_wavelength / lam_min - 1e-9)))
+    v, t = meshes.geodesic_sphere(freq, a)
+    return Problem([Domain(v, t, k1, rho_ratio, material)], k0, 1.0,
+                   f"paper_sphere_{material}_e{elements_per_wavelength:g}",
+                   meta={"radius": a, "wavelength_m": lam0, "freq": freq, "elements_per_wavelength": elements_per_wavelength,
+                         "r_eps": 5e-4 / lam0})
+
+
+def grid_plane_y0(radius: float, n: int = 200, extent: float = 3.0) -> np.ndarray:
+    """n x n points over [-extent R, extent R]^2 in the plane y = 0 (x, z),
+    which contains the propagation axis +z."""
+    g = np.linspace(-extent * radius, extent * radius, n)
+    X, Z = np.meshgrid(g, g, indexing="ij")
+    return np.stack([X.ravel(), np.zeros(X.size), Z.ravel()], axis=1)

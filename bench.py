@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only a 1 GiB elementwise copy (the counter scale) and 3 applies, for HBM counters")
     ap.add_argument("--level", type=int, default=5, help="icosphere level of the sphere workload (5: 10,242 v)")
+    ap.add_argument("--assembled-kernels-only", action="store_true",
+                    help="assembled section without its solves (GEMV and GEMM launches only, for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -171,7 +173,8 @@ def main():
     if not args.no_assembled:
         del P
         torch.cuda.empty_cache()
-        out["assembled"] = assembled_section(prob, bem, vectors, torch, autotune=not args.no_autotune)
+        out["assembled"] = assembled_section(prob, bem, vectors, torch, autotune=not args.no_autotune,
+                                             solves=not args.assembled_kernels_only)
     extras = [e for e in args.extra.split(",") if e]
     if extras:
         os.environ.setdefault("BEM_PROGRESS", "50")   # solver progress lines on stderr
@@ -351,7 +354,7 @@ FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X FP32 MFMA
 HBM_PEAK_GBPS = 8000.0
 
 
-def assembled_section(prob, bem, vectors, torch, autotune=True):
+def assembled_section(prob, bem, vectors, torch, autotune=True, solves=True):
     """Assembled mode on the same problem: dense assembly, GEMV (HBM roofline),
     multi-RHS GEMM (MFMA roofline) and time-to-solve of the three precision forms."""
     n = prob.n_unknowns
@@ -383,6 +386,8 @@ def assembled_section(prob, bem, vectors, torch, autotune=True):
             ms = float(np.median(ts))
             tf = fl * n * n * R / (ms * 1e-3) / 1e12
             res[f"gemm_{key}_R{R}"] = {"ms": ms, "TFLOPs": tf, "frac": tf / peak, "peak": peak}
+    if not solves:
+        return res
     # time-to-solve at 1e-5 for one plane wave and for 64 plane waves
     dirs = np.random.default_rng(7).standard_normal((64, 3))
     for R in (1, 64):

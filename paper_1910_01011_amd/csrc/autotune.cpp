@@ -121,23 +121,45 @@ int tune_pairs(bem_problem &p, void (*rebuild)(bem_problem &), int max_split)
     BEM_HIP(hipMallocAsync(reinterpret_cast<void **>(&x), size_t(p.N) * sizeof(double2), p.stream));
     BEM_HIP(hipMemsetAsync(x, 0, size_t(p.N) * sizeof(double2), p.stream));
     launch_gather(p, x);
-    int best = 0;
-    float best_ms = 1e30f;
     const int64_t blocks = (p.M + 255) / 256;
+    std::vector<std::pair<float, int>> timed;   // (ms, code)
+    const auto run = [&](int code, int reps) {
+        p.tpl = code / 100;
+        p.n_split = code % 100;
+        rebuild(p);
+        // the partial sums of every split are read back by the reduction: time both
+        return time_ms(p, [&]() { launch_pairs(p); launch_reduce(p); }, reps);
+    };
+    bool warmed = false;
     for (int tpl : {1, 2}) {
         for (int ns : {1, 2, 4, 8, 16, 32, 64}) {
             const int64_t wgs = int64_t(p.n_pass) * ((blocks + tpl - 1) / tpl) * ns;
             if (wgs < 256 || wgs > (int64_t(1) << 22)) continue;   // too few to fill 256 CUs / absurdly many
             if (int64_t(ns) * 256 > p.M || ns > max_split) continue;
-            p.tpl = tpl;
-            p.n_split = ns;
-            rebuild(p);
-            const int reps = p.M > 200000 ? 1 : 3;
-            // the partial sums of every split are read back by the reduction: time both
-            const float ms = time_ms(p, [&]() { launch_pairs(p); launch_reduce(p); }, reps);
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = 100 * tpl + ns;
+            const int code = 100 * tpl + ns;
+            if (!warmed) {
+                // bring the clocks to their loaded state before the first timing
+                for (int w = 0; w < 4; ++w) (void)run(code, 1);
+                warmed = true;
+            }
+            timed.emplace_back(run(code, p.M > 200000 ? 1 : 3), code);
+        }
+    }
+    // second pass: the three fastest candidates again, interleaved, so that a
+    // drift of the clock during the sweep does not decide between near-equal shapes
+    std::sort(timed.begin(), timed.end());
+    int best = 0;
+    if (!timed.empty()) {
+        const size_t nb = std::min<size_t>(3, timed.size());
+        std::vector<std::vector<float>> again(nb);
+        for (int round = 0; round < 3; ++round)
+            for (size_t c = 0; c < nb; ++c) again[c].push_back(run(timed[c].second, 1));
+        float best_ms = 1e30f;
+        for (size_t c = 0; c < nb; ++c) {
+            std::sort(again[c].begin(), again[c].end());
+            if (again[c][1] < best_ms) {
+                best_ms = again[c][1];
+                best = timed[c].second;
             }
         }
     }
@@ -153,7 +175,7 @@ int tune_pairs(bem_problem &p, void (*rebuild)(bem_problem &), int max_split)
 std::string gemm_key(const bem_problem &p, int R, bool bf16)
 {
     std::ostringstream key;
-    key << "gemm" << TUNE_VERSION << ":" << arch_name(p.device) << ":N" << bucket(p.N) << ":R" << bucket(R) << ":" << (bf16 ? "bf16x3a" : "f32");
+    key << "gemm" << TUNE_VERSION << ":" << arch_name(p.device) << ":N" << bucket(p.N) << ":R" << bucket(R) << ":" << (bf16 ? "bf16x3b" : "f32b");
     return key.str();
 }
 
@@ -166,7 +188,7 @@ int cached_gemm_slices(bem_problem &p, int R, bool bf16)
 }
 
 // Number of K slices of the GEMM for R right-hand sides (tuned once per bucket).
-int tune_gemm_slices(bem_problem &p, int R, bool bf16, void *xbuf, float *cbuf)
+int tune_gemm_slices(bem_problem &p, int R, bool bf16, void *xbuf, float *cbuf, double2 *Y)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     load_cache();
@@ -180,7 +202,11 @@ int tune_gemm_slices(bem_problem &p, int R, bool bf16, void *xbuf, float *cbuf)
     for (int s : {1, 2, 4, 8, 16, 32, 64}) {
         const GemmPlan g = gemm_plan(p, R, bf16, s);
         if (g.bytes_c > p.gc_bytes || g.bytes_x > p.gx_bytes) continue;
-        const float ms = time_ms(p, [&]() { launch_gemm_kernel(p, g, xbuf, cbuf); }, 2);
+        // the slice count trades GEMM occupancy against partials to sum: time both
+        const float ms = time_ms(p, [&]() {
+            launch_gemm_kernel(p, g, xbuf, cbuf);
+            launch_unpack(p, g, cbuf, Y);
+        }, 2);
         if (ms < best_ms) {
             best_ms = ms;
             best = g.n_s;

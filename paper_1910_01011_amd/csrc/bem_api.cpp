@@ -219,7 +219,7 @@ void apply_dense_multi(bem_problem &p, const double2 *X, double2 *Y, int n_rhs, 
         BEM_HIP(hipStreamSynchronize(p.stream));
         grow(&p.d_gx, p.gx_bytes, g0.bytes_x);
         grow(reinterpret_cast<void **>(&p.d_gc), p.gc_bytes, cmax);
-        slices = bem::tune_gemm_slices(p, n_rhs, bf16, p.d_gx, p.d_gc);
+        slices = bem::tune_gemm_slices(p, n_rhs, bf16, p.d_gx, p.d_gc, Y);
     }
     const bem::GemmPlan g = bem::gemm_plan(p, n_rhs, bf16, slices);
     if (p.gx_bytes < g.bytes_x) {
@@ -279,7 +279,7 @@ bem_solve_opts default_solve_opts()
 std::vector<double> residual_norms(bem_problem &p, const double2 *B, double2 *AX, int R)
 {
     const int64_t n = p.N;
-    const int nblk = int(std::min<int64_t>(128, (n + 255) / 256));
+    const int nblk = bem::bdot_chunks(n);
     double2 *part = nullptr, *h = nullptr;
     dev_alloc(&part, size_t(R) * nblk);
     dev_alloc(&h, size_t(R));

@@ -207,6 +207,7 @@ void split_matrix_bf16(bem_problem &p);
 GemmPlan gemm_plan(const bem_problem &p, int R, bool bf16, int force_slices);
 void launch_gemm(bem_problem &p, const GemmPlan &g, const double2 *X, double2 *Y, void *xbuf, float *cbuf);
 void launch_gemm_kernel(bem_problem &p, const GemmPlan &g, void *xbuf, float *cbuf);
+void launch_unpack(bem_problem &p, const GemmPlan &g, const float *cbuf, double2 *Y);
 
 // Blocks of a 1-D launch over `items` work items.  A dispatch counts its work
 // items in 32 bits: kernels whose item count can exceed that loop over a capped
@@ -221,7 +222,7 @@ inline unsigned blocks_1d(int64_t items, int block, bool capped = false)
 
 // autotuner (autotune.cpp)
 int tune_pairs(bem_problem &p, void (*rebuild)(bem_problem &), int max_split);
-int tune_gemm_slices(bem_problem &p, int R, bool bf16, void *xbuf, float *cbuf);
+int tune_gemm_slices(bem_problem &p, int R, bool bf16, void *xbuf, float *cbuf, double2 *Y);
 int cached_gemm_slices(bem_problem &p, int R, bool bf16);   // 0 when the bucket is untuned
 void run_singular(bem_problem &p, const std::vector<SingularItem> &items);
 
@@ -234,6 +235,9 @@ void zscale_copy(hipStream_t s, const double2 *x, double2 *y, int64_t n, double2
 void zaxpy(hipStream_t s, double2 *y, const double2 *x, int64_t n, double2 a);
 
 // batched FP64 complex kernels: R vectors of length n, bases [i][R][n] (k_linalg.hip)
+// chunks of the batched dot products: partial buffers hold R * nvec * bdot_chunks(n) entries
+constexpr int BD_CHUNK = 2048;
+inline int bdot_chunks(int64_t n) { return int(std::max<int64_t>(1, (n + BD_CHUNK - 1) / BD_CHUNK)); }
 void bdot(hipStream_t s, const double2 *V, int64_t ldv, int nvec, const double2 *w, int64_t n, int R,
           double2 *partials, int nblk, double2 *out_dev);
 void baxpy(hipStream_t s, const double2 *V, int64_t ldv, int nvec, const double2 *h_dev, double2 *w, int64_t n, int R,

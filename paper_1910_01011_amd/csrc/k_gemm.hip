@@ -330,10 +330,23 @@ __global__ __launch_bounds__(256) void k_unpack_y(const float *__restrict__ C, i
             const int j = j0 + jj;
             double re = 0, im = 0;
             if (r < M && j < R) {
-                for (int s = 0; s < n_s; ++s) {
-                    const float *row = C + (int64_t(s) * M + r) * Np;
-                    re += row[j];
-                    im += row[R + j];
+                // loads of 8 slices are issued together, then added in slice order
+                const int64_t sstride = M * Np;
+                const float *row = C + r * Np;
+                for (int s0 = 0; s0 < n_s; s0 += 8) {
+                    float vr[8], vi[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int s = std::min(s0 + q, n_s - 1);
+                        vr[q] = row[int64_t(s) * sstride + j];
+                        vi[q] = row[int64_t(s) * sstride + R + j];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (s0 + q < n_s) {
+                            re += vr[q];
+                            im += vi[q];
+                        }
                 }
             }
             tile[rr][jj] = make_double2(re, im);
@@ -423,6 +436,11 @@ void launch_gemm(bem_problem &p, const GemmPlan &g, const double2 *X, double2 *Y
     }
     BEM_HIP(hipGetLastError());
     if (p.timed_gemm) BEM_HIP(hipEventRecord(p.ev[2], p.stream));
+    launch_unpack(p, g, cbuf, Y);
+}
+
+void launch_unpack(bem_problem &p, const GemmPlan &g, const float *cbuf, double2 *Y)
+{
     const dim3 ugrid(unsigned((p.N + UT - 1) / UT), unsigned((g.R + UT - 1) / UT));
     k_unpack_y<<<ugrid, dim3(256), 0, p.stream>>>(cbuf, p.N, g.Np, g.R, g.n_s, Y);
     BEM_HIP(hipGetLastError());

@@ -118,32 +118,65 @@ namespace bem {
 // (vector r at offset r * n); Krylov bases as [i][R][n].
 // ---------------------------------------------------------------------------
 
-// partials[(r * nvec + i) * nblk + blk] = sum over chunk of conj(V_i[r]) w[r]
+// partials[(r * nvec + i) * nchunk + c] = sum over chunk c of conj(V_i[r]) w[r].
+// One workgroup per (chunk of BD_CHUNK elements, right-hand side): the chunk of
+// w stays in registers while the basis vectors are streamed in groups of
+// BD_G; each sum is reduced across the wave by shuffles and across the four
+// waves through LDS, always in the same order (deterministic).
+constexpr int BD_T = BD_CHUNK / LA_BLOCK;   // elements per thread
+constexpr int BD_G = 8;                     // basis vectors per pass
 __global__ __launch_bounds__(LA_BLOCK) void k_bdot_partial(const double2 *__restrict__ V, int64_t ldv,
                                                            const double2 *__restrict__ w, int64_t n, int R,
-                                                           int nvec, int nblk, double2 *__restrict__ partials)
+                                                           int nvec, int nchunk, double2 *__restrict__ partials)
 {
-    __shared__ double sr[LA_BLOCK], si[LA_BLOCK];
-    const int blk = blockIdx.x, i = blockIdx.y, r = blockIdx.z, tid = threadIdx.x;
-    const double2 *v = V + int64_t(i) * ldv + int64_t(r) * n;
+    __shared__ double2 red[LA_BLOCK / 64][BD_G];
+    const int c = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t base = int64_t(c) * BD_CHUNK + tid;
     const double2 *ww = w + int64_t(r) * n;
-    double ar = 0, ai = 0;
-    for (int64_t k = int64_t(blk) * LA_BLOCK + tid; k < n; k += int64_t(nblk) * LA_BLOCK) {
-        const double2 a = v[k], b = ww[k];
-        ar += a.x * b.x + a.y * b.y;
-        ai += a.x * b.y - a.y * b.x;
+    double2 wl[BD_T];
+#pragma unroll
+    for (int t = 0; t < BD_T; ++t) {
+        const int64_t k = base + int64_t(LA_BLOCK) * t;
+        wl[t] = k < n ? ww[k] : make_double2(0.0, 0.0);
     }
-    sr[tid] = ar;
-    si[tid] = ai;
-    __syncthreads();
-    for (int s = LA_BLOCK / 2; s > 0; s >>= 1) {
-        if (tid < s) {
-            sr[tid] += sr[tid + s];
-            si[tid] += si[tid + s];
+    for (int i0 = 0; i0 < nvec; i0 += BD_G) {
+        double ar[BD_G], ai[BD_G];
+#pragma unroll
+        for (int g = 0; g < BD_G; ++g) {
+            ar[g] = 0.0;
+            ai[g] = 0.0;
+            if (i0 + g < nvec) {
+                const double2 *v = V + int64_t(i0 + g) * ldv + int64_t(r) * n;
+#pragma unroll
+                for (int t = 0; t < BD_T; ++t) {
+                    const int64_t k = base + int64_t(LA_BLOCK) * t;
+                    const double2 a = k < n ? v[k] : make_double2(0.0, 0.0);
+                    ar[g] += a.x * wl[t].x + a.y * wl[t].y;
+                    ai[g] += a.x * wl[t].y - a.y * wl[t].x;
+                }
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < BD_G; ++g)
+            for (int off = 32; off > 0; off >>= 1) {
+                ar[g] += __shfl_down(ar[g], off);
+                ai[g] += __shfl_down(ai[g], off);
+            }
+        if (lane == 0)
+#pragma unroll
+            for (int g = 0; g < BD_G; ++g) red[wv][g] = make_double2(ar[g], ai[g]);
+        __syncthreads();
+        if (tid < BD_G && i0 + tid < nvec) {
+            double sr = 0.0, si = 0.0;
+#pragma unroll
+            for (int q = 0; q < LA_BLOCK / 64; ++q) {
+                sr += red[q][tid].x;
+                si += red[q][tid].y;
+            }
+            partials[(int64_t(r) * nvec + i0 + tid) * nchunk + c] = make_double2(sr, si);
         }
         __syncthreads();
     }
-    if (tid == 0) partials[(int64_t(r) * nvec + i) * nblk + blk] = make_double2(sr[0], si[0]);
 }
 
 __global__ void k_bdot_final(const double2 *__restrict__ partials, int nblk, int total, double2 *__restrict__ out)
@@ -162,8 +195,8 @@ void bdot(hipStream_t s, const double2 *V, int64_t ldv, int nvec, const double2 
           double2 *partials, int nblk, double2 *out_dev)
 {
     if (nvec <= 0 || R <= 0) return;
-    k_bdot_partial<<<dim3(unsigned(nblk), unsigned(nvec), unsigned(R)), dim3(LA_BLOCK), 0, s>>>(V, ldv, w, n, R, nvec,
-                                                                                              nblk, partials);
+    if (nblk != bdot_chunks(n)) throw Error{BEM_ERR_INVALID_ARG, "bdot: partial buffer sized for another length"};
+    k_bdot_partial<<<dim3(unsigned(nblk), unsigned(R)), dim3(LA_BLOCK), 0, s>>>(V, ldv, w, n, R, nvec, nblk, partials);
     BEM_HIP(hipGetLastError());
     const int total = R * nvec;
     k_bdot_final<<<dim3(blocks_1d(total, 64)), dim3(64), 0, s>>>(partials, nblk, total, out_dev);
@@ -178,6 +211,7 @@ __global__ void k_baxpy(const double2 *__restrict__ V, int64_t ldv, int nvec, co
     if (idx >= n * R) return;
     const int64_t r = idx / n;
     double re = 0, im = 0;
+#pragma unroll 4
     for (int i = 0; i < nvec; ++i) {
         const double2 a = V[int64_t(i) * ldv + idx], c = h[r * nvec + i];
         re += c.x * a.x - c.y * a.y;

@@ -50,7 +50,7 @@ void gmres_batch(bem_problem &p, int64_t n, int R, const double2 *B, double2 *X,
 {
     hipStream_t s = p.stream;
     const int m = std::max(1, o.restart);
-    const int nblk = int(std::min<int64_t>(128, (n + 255) / 256));
+    const int nblk = bdot_chunks(n);
     DevBuf<double2> V(size_t(m + 1) * R * n, s), Z(M ? size_t(m) * R * n : 1, s), Xa(size_t(R) * n, s),
         Ba(size_t(R) * n, s);
     DevBuf<double2> hdev(size_t(R) * (m + 2), s), part(size_t(R) * (m + 2) * nblk, s);

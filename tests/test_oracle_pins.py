@@ -386,3 +386,34 @@ def test_two_domain_union_operator_projector():
         r = A @ g + 0.5 * M2 @ g
         res.append(np.linalg.norm(r) / np.linalg.norm(0.5 * M2 @ g))
     assert res[1] < 0.1 and res[0] / res[1] > 2.5, res
+
+
+def test_series_transmission_conditions_with_attenuating_media():
+    """The penetrable-sphere series with complex wavenumbers (the paper's
+    attenuating media) satisfies the model's transmission conditions at r = a:
+    p continuous and (1/rho) dp/dr continuous; far from the sphere the
+    scattered part decays like an outgoing spherical wave."""
+    from bem_inputs import configs
+    prob = configs.paper_sphere("fat", 4)
+    a, k0 = prob.meta["radius"], prob.k0
+    d = prob.domains[0]
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal((40, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    eps = 1e-6 * a
+    p_out = series.sphere_field(u * (a + eps), a, k0, d.k, 1.0, d.rho)
+    p_in = series.sphere_field(u * (a - eps), a, k0, d.k, 1.0, d.rho)
+    assert np.max(np.abs(p_out - p_in)) < 1e-4 * np.max(np.abs(p_out))
+    h = 1e-4 * a
+
+    def f(r):
+        return series.sphere_field(u * r, a, k0, d.k, 1.0, d.rho)
+    # second-order one-sided differences from each side of the interface
+    dout = (-3.0 * f(a + eps) + 4.0 * f(a + h) - f(a + 2 * h)) / (2 * h)
+    din = (3.0 * f(a - eps) - 4.0 * f(a - h) + f(a - 2 * h)) / (2 * h)
+    assert np.max(np.abs(dout / 1.0 - din / d.rho)) < 1e-4 * np.max(np.abs(dout))
+    # the scattered field at large r: |r p_s| tends to a constant along a ray
+    z = np.array([[0.0, 0.0, 1.0]])
+    ps = [series.sphere_field(z * r, a, k0, d.k, 1.0, d.rho)[0] - np.exp(1j * k0 * r) for r in (400.0, 800.0)]
+    ratio = abs(ps[1] * 800.0 * np.exp(-1j * k0 * 800.0)) / abs(ps[0] * 400.0 * np.exp(-1j * k0 * 400.0))
+    assert abs(ratio - 1.0) < 1e-2
