@@ -80,7 +80,8 @@ def main():
     ap.add_argument("--extra", default="",
                     help="comma list of extra workloads appended to the JSON line: ribcage (53.5k-vertex stack, "
                          "on the fly, pistons, OSRC), ribcage_assembled (26.9k vertices, 256 right-hand sides), "
-                         "serving (kidney request stream)")
+                         "serving (kidney request stream), paper_sphere (the paper's 1 cm sphere at 1 MHz, fat and "
+                         "rib material, 4-10 elements per wavelength, OSRC GMRES)")
     ap.add_argument("--serving-requests", type=int, default=8, help="requests per arrival rate in --extra serving")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only a 1 GiB elementwise copy (the counter scale) and 3 applies, for HBM counters")
@@ -188,6 +189,8 @@ def main():
             out["ribcage_assembled"] = ribcage_assembled_section(bem, torch, not args.no_autotune)
         elif e == "serving":
             out["serving"] = serving_section(bem, torch, args.serving_requests)
+        elif e == "paper_sphere":
+            out["paper_sphere"] = paper_sphere_section(bem, torch)
         else:
             raise SystemExit(f"unknown extra workload {e}")
         torch.cuda.empty_cache()
@@ -309,6 +312,32 @@ def serving_section(bem, torch, n_requests):
         log(f"serving rate {rate}: p50 {summ['p50_latency_s']:.2f} s p99 {summ['p99_latency_s']:.2f} s")
     return out
 
+
+
+def paper_sphere_section(bem, torch):
+    """The paper's single-sphere model problem: 1 cm sphere at 1 MHz in water,
+    fat or the table's rib material (attenuating media), plane wave, OSRC
+    (N_Pade = 4, R_eps = 5e-4 m) GMRES(100) to 1e-5; iterations and time per
+    iteration against mesh density (the field error against the series
+    solution is checked in the GPU tests)."""
+    from bem_inputs import configs
+    out = {}
+    for material in ("fat", "ribs"):
+        for epw in (4, 6, 8, 10):
+            prob = configs.paper_sphere(material, epw)
+            (P, t_setup) = _timed(torch, lambda: bem.Problem.from_config(prob, device=True))
+            b = P.rhs(bem.Incident.plane_waves([[0.0, 0.0, 1.0]]))
+            (u, info), t = _timed(torch, lambda: P.solve(b, bem.solve_options(
+                tol=1e-5, restart=100, max_iter=400, precond=bem.BEM_PRECOND_OSRC, n_pade=4,
+                r_eps=prob.meta["r_eps"], theta=np.pi / 3)))
+            it = info[0]["iterations"]
+            out[f"{material}_e{epw}"] = {"vertices": prob.domains[0].n_vertices, "setup_s": t_setup,
+                                         "iterations": it, "time_to_solve_s": t,
+                                         "s_per_iteration": t / max(1, it), "rel_residual": info[0]["rel_residual"],
+                                         "converged": info[0]["converged"]}
+            log(f"paper sphere {material} e={epw}: {prob.domains[0].n_vertices} v, {it} it, {t:.2f} s")
+            P.close()
+    return out
 
 COPY_PROBE_BYTES = 1 << 30     # bytes read (and written) by the copy of the traffic probe
 

@@ -64,14 +64,19 @@ class Result:
 def choose_mode(n_vertices: int, n_rhs: int, free_bytes: int):
     """Operator mode and solver precision of a request.
 
-    On the fly (FP32 GMRES) when the dense complex64 matrix (8 (2 N_V)^2 bytes)
-    would take more than a quarter of the free HBM or when there are at most
-    two right-hand sides; otherwise assembled with split-BF16 block GMRES inside
-    FP64-residual FGMRES.
+    On the fly (FP32 GMRES) only when the dense complex64 matrix (8 (2 N_V)^2
+    bytes) would take more than a quarter of the free HBM: an on-the-fly apply
+    re-evaluates every quadrature pair, which costs far more than reading the
+    dense matrix once the matrix is built.  Otherwise assembled: FP32 GMRES with
+    one GEMV per right-hand side for one or two right-hand sides, else
+    split-BF16 block GMRES inside FP64-residual FGMRES (one GEMM per step for
+    the whole block).
     """
-    from . import BEM_ASSEMBLED_SPLIT_BF16, BEM_PREC_SPLIT_BF16_FGMRES
-    if 32 * n_vertices ** 2 > 0.25 * free_bytes or n_rhs <= 2:
+    from . import BEM_ASSEMBLED_FP32, BEM_ASSEMBLED_SPLIT_BF16, BEM_PREC_SPLIT_BF16_FGMRES
+    if 32 * n_vertices ** 2 > 0.25 * free_bytes:
         return BEM_OTF, BEM_PREC_FP32
+    if n_rhs <= 2:
+        return BEM_ASSEMBLED_FP32, BEM_PREC_FP32
     return BEM_ASSEMBLED_SPLIT_BF16, BEM_PREC_SPLIT_BF16_FGMRES
 
 
@@ -85,8 +90,9 @@ def requests_from_stream(items, free_bytes: int, tol: float = 1e-5) -> list[Requ
         R = len(c)
         inc = Incident.pistons(c, n, it["piston_radius"], 1.0, np.arange(R))
         mode, prec = choose_mode(sum(d.n_vertices for d in prob.domains), R, free_bytes)
+        flexible = prec != BEM_PREC_FP32
         out.append(Request(rid, prob.domains, prob.k0, inc, rho0=prob.rho0, mode=mode, precision=prec, tol=tol,
-                           restart=100 if mode == BEM_OTF else 30, max_iter=400, arrival=it["arrival"]))
+                           restart=30 if flexible else 100, max_iter=400, arrival=it["arrival"]))
     return out
 
 
@@ -104,15 +110,20 @@ def run_request(req: Request, t0: float, admitted: float, fp: int) -> Result:
     """Set up, build the right-hand sides and solve one request on its own stream."""
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
+        ta = time.perf_counter()
         P = Problem(req.domains, req.k0, req.rho0, device=True, mode=req.mode, stream=stream.cuda_stream)
         b = P.rhs(req.incident)
+        stream.synchronize()
+        tb = time.perf_counter()
         u, info = P.solve(b, solve_options(tol=req.tol, restart=req.restart, max_iter=req.max_iter,
                                            precision=req.precision))
         u_host = u.cpu().numpy()
         stream.synchronize()
+        tc = time.perf_counter()
         P.close()
+    extra = {"setup_s": tb - ta, "solve_s": tc - tb, "iterations": int(max(i["iterations"] for i in info))}
     return Result(req.rid, u_host, info, req.arrival, admitted, time.perf_counter() - t0, fp,
-                  req.incident.n_fields)
+                  req.incident.n_fields, extra)
 
 
 class Server:
@@ -187,4 +198,8 @@ def summarize(results: list[Result]) -> dict:
             "p99_latency_s": float(np.percentile(lat, 99)), "mean_latency_s": float(lat.mean()),
             "makespan_s": float(makespan), "requests_per_s": len(results) / makespan,
             "solves_per_s": n_rhs / makespan,
-            "all_converged": all(all(i["converged"] for i in r.info) for r in results)}
+            "all_converged": all(all(i["converged"] for i in r.info) for r in results),
+            "setup_s": [round(r.extra.get("setup_s", 0.0), 3) for r in results],
+            "solve_s": [round(r.extra.get("solve_s", 0.0), 3) for r in results],
+            "iterations": [r.extra.get("iterations", 0) for r in results],
+            "queue_s": [round(r.admitted - r.arrival, 3) for r in results]}
