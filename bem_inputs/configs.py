@@ -49,6 +49,13 @@ class Problem:
         return 6 * sum(d.n_triangles for d in self.domains)
 
 
+def _attenuation(name: str, f_rel: float, wavelength_m: float = 1.5e-3) -> float:
+    """Im k = alpha0 (f / 1 MHz)^b of a table medium, per exterior wavelength
+    (f_rel = 1 is 1 MHz, where the water wavelength is 1.5 mm)."""
+    rho, c, a0, b = TABLE_MEDIA[name]
+    return float(a0 * f_rel ** b * wavelength_m)
+
+
 def sphere_problem(level: int, k0: float, k1: float, rho_ratio: float, radius: float = 1.0,
                    name: str = "") -> Problem:
     v, t = meshes.icosphere(level, radius)
@@ -74,7 +81,7 @@ def two_spheres(level: int = 2, k0: float = 3.0) -> Problem:
                     Domain(v2, t2, complex(k0 / 0.9), 0.8, "b")], complex(k0), 1.0, "two_spheres")
 
 
-def ribcage(h_scale: float = 1.0, f_rel: float = 1.0) -> Problem:
+def ribcage(h_scale: float = 1.0, f_rel: float = 1.0, attenuating: bool = False) -> Problem:
     """Layered rib-cage stand-in: fat slab, five capsules and a liver box.
 
     All domains are disjoint and border only the exterior (no triple points).
@@ -82,26 +89,29 @@ def ribcage(h_scale: float = 1.0, f_rel: float = 1.0) -> Problem:
     density 0.95); five capsules of radius 0.9 and length 12 along y at
     x in {-4.5, -1.5, 1.5, 4.5, 7.5}, z = -4 (speed ratio 1.87, density 1.9);
     liver box x in [-6, 9], y in [-6.5, 6.5], z in [-2, 1] (speed ratio 1.03,
-    density 1.07).  Element size h_j = min(1, s_j)/6 * h_scale.
+    density 1.07).  Element size h_j = min(1, s_j)/6 * h_scale.  With
+    ``attenuating`` the wavenumbers gain the imaginary parts of the table's fat,
+    rib, liver and water attenuation at f_rel MHz (lambda_0 = 1.5 mm).
     """
     k0 = 2.0 * np.pi * f_rel
     doms = []
     s_fat, s_rib, s_liv = 0.96, 1.87, 1.03
+    att = (lambda name: _attenuation(name, f_rel)) if attenuating else (lambda name: 0.0)
     h_fat = min(1.0, s_fat) / 6.0 * h_scale / f_rel
     h_rib = min(1.0, s_rib) / 6.0 * h_scale / f_rel
     h_liv = min(1.0, s_liv) / 6.0 * h_scale / f_rel
     v, t = meshes.box((-6.0, -6.5, -8.0), (9.0, 6.5, -6.0), h_fat)
-    doms.append(Domain(v, t, complex(k0 / s_fat), 0.95, "fat"))
+    doms.append(Domain(v, t, complex(k0 / s_fat, att("fat")), 0.95, "fat"))
     for x in (-4.5, -1.5, 1.5, 4.5, 7.5):
         v, t = meshes.capsule(0.9, 12.0, h_rib, axis=1, center=(x, 0.0, -4.0))
-        doms.append(Domain(v, t, complex(k0 / s_rib), 1.9, f"rib{x:+.1f}"))
+        doms.append(Domain(v, t, complex(k0 / s_rib, att("ribs")), 1.9, f"rib{x:+.1f}"))
     v, t = meshes.box((-6.0, -6.5, -2.0), (9.0, 6.5, 1.0), h_liv)
-    doms.append(Domain(v, t, complex(k0 / s_liv), 1.07, "liver"))
-    return Problem(doms, complex(k0), 1.0, f"ribcage_h{h_scale:g}")
+    doms.append(Domain(v, t, complex(k0 / s_liv, att("liver")), 1.07, "liver"))
+    return Problem(doms, complex(k0, att("water")), 1.0, f"ribcage_h{h_scale:g}" + ("_att" if attenuating else ""))
 
 
 def kidney(f_rel: float = 1.0, elements_per_wavelength: float = 6.0, level: int | None = None,
-           freq: int | None = None) -> Problem:
+           freq: int | None = None, attenuating: bool = False) -> Problem:
     """Kidney ellipsoid (5, 3, 2.5) plus a perinephric fat shell with a 2/3 gap.
 
     Kidney: speed ratio 1.04, density 1.066.  Fat shell: inner semi-axes
@@ -109,6 +119,8 @@ def kidney(f_rel: float = 1.0, elements_per_wavelength: float = 6.0, level: int 
     surfaces are icospheres of ``level`` when it is given, else geodesic
     spheres of frequency ``freq`` (default: from the element size
     h = min(1, s_fat)/f_rel/elements_per_wavelength on the largest surface).
+    With ``attenuating`` the table's kidney, fat and water attenuation at
+    f_rel MHz is added (lambda_0 = 1.5 mm).
     """
     k0 = 2.0 * np.pi * f_rel
     s_k, s_f = 1.04, 0.941
@@ -124,9 +136,10 @@ def kidney(f_rel: float = 1.0, elements_per_wavelength: float = 6.0, level: int 
         vk, tk = meshes.geodesic_ellipsoid(freq, axes)
         vs, ts = meshes.geodesic_shell(freq, axes + g, axes + g + 1.0)
         tag = f"g{freq}"
-    return Problem([Domain(vk, tk, complex(k0 / s_k), 1.066, "kidney"),
-                    Domain(vs, ts, complex(k0 / s_f), 0.917, "fat_shell")], complex(k0), 1.0,
-                   f"kidney_{tag}")
+    att = (lambda name: _attenuation(name, f_rel)) if attenuating else (lambda name: 0.0)
+    return Problem([Domain(vk, tk, complex(k0 / s_k, att("kidney")), 1.066, "kidney"),
+                    Domain(vs, ts, complex(k0 / s_f, att("fat")), 0.917, "fat_shell")], complex(k0, att("water")),
+                   1.0, f"kidney_{tag}" + ("_att" if attenuating else ""))
 
 
 _MESH_CACHE: dict = {}

@@ -60,3 +60,18 @@ def test_ribcage_fat_slab_follows_the_table():
     # the stated values are the table's fat ratios to two digits (0.917, 0.941)
     assert abs(fat.rho - t["fat"]["rho"] / w["rho"]) < 0.035
     assert abs(prob.k0.real / fat.k.real - t["fat"]["c"] / w["c"]) < 0.02
+
+
+def test_attenuating_workloads_take_the_table_attenuation():
+    t = _table()
+    lam0 = 1.5e-3                       # water wavelength at 1 MHz
+    prob = configs.ribcage(4.0, attenuating=True)
+    fat, rib, liver = prob.domains[0], prob.domains[1], prob.domains[-1]
+    assert fat.k.imag == pytest.approx(t["fat"]["alpha0"] * lam0, rel=1e-12)
+    assert rib.k.imag == pytest.approx(t["ribs"]["alpha0"] * lam0, rel=1e-12)
+    assert liver.k.imag == pytest.approx(t["liver"]["alpha0"] * lam0, rel=1e-12)
+    assert prob.k0.imag == pytest.approx(t["water"]["alpha0"] * lam0, rel=1e-12)
+    # power law in frequency: kidney at 0.8 MHz equivalents
+    kid = configs.kidney(0.8, freq=6, attenuating=True)
+    assert kid.domains[0].k.imag == pytest.approx(t["kidney"]["alpha0"] * 0.8 ** t["kidney"]["b"] * lam0, rel=1e-12)
+    assert kid.k0.imag == pytest.approx(t["water"]["alpha0"] * 0.8 ** t["water"]["b"] * lam0, rel=1e-12)

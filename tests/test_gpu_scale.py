@@ -153,3 +153,20 @@ def test_config4_split_bf16_fgmres_pistons(c4, bowl, monkeypatch):
         cert = float(np.linalg.norm(b_rows - R @ u[f]) / np.linalg.norm(b_rows))
         print(f"  piston {e}: sampled-row residual certificate {cert:.3e}")
         assert cert <= 20 * 1e-5 + 1e-5
+
+
+def test_attenuating_ribcage_sampled_rows():
+    """Attenuating media of the table in the rib-cage stack (complex wavenumbers
+    in every pass, the exp(-Im k r) branch of the pair kernel) at twice the
+    element size: sampled rows against the oracle."""
+    import paper_1910_01011_amd as bem
+    prob = configs.ribcage(2.0, attenuating=True)
+    rows = vectors.random_rows(prob.n_unknowns, 16, seed=21)
+    R = oracle.pmchwt_rows(prob, rows)
+    P = bem.Problem.from_config(prob, autotune=True)
+    x = vectors.random_complex(prob.n_unknowns, seed=22)
+    y = P.apply(x)
+    P.close()
+    err = _relerr(y[rows], R @ x)
+    print(f"attenuating ribcage h=2 ({sum(d.n_vertices for d in prob.domains)} v): sampled-row rel err {err:.3e}")
+    assert err <= 1e-5
