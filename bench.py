@@ -257,6 +257,8 @@ def ribcage_assembled_section(bem, torch, autotune):
     res = {"vertices": sum(d.n_vertices for d in prob.domains), "unknowns": n, "assembly_s": t_asm}
     X = torch.from_numpy(np.random.default_rng(1).standard_normal((256, n)) + 0j).cuda()
     for kern, key, peak, fl in ((bem.BEM_APPLY_MFMA_SPLIT_BF16, "bf16x3", BF16_PEAK_TFLOPS, 24.0),
+                                (bem.BEM_APPLY_MFMA_SPLIT_BF16_W4, "bf16x3_w4", BF16_PEAK_TFLOPS, 24.0),
+                                (bem.BEM_APPLY_MFMA_SPLIT_BF16_W8, "bf16x3_w8", BF16_PEAK_TFLOPS, 24.0),
                                 (bem.BEM_APPLY_MFMA_FP32, "fp32", FP32_MFMA_PEAK_TFLOPS, 8.0)):
         P.apply(X, kernel=kern)
         ts = []
@@ -405,6 +407,8 @@ def assembled_section(prob, bem, vectors, torch, autotune=True, solves=True):
     for R in (64, 256):
         X = torch.from_numpy(vectors.random_complex(n, seed=1, n_rhs=R)).cuda()
         for kern, key, peak, fl in ((bem.BEM_APPLY_MFMA_SPLIT_BF16, "bf16x3", BF16_PEAK_TFLOPS, 24.0),
+                                    (bem.BEM_APPLY_MFMA_SPLIT_BF16_W4, "bf16x3_w4", BF16_PEAK_TFLOPS, 24.0),
+                                    (bem.BEM_APPLY_MFMA_SPLIT_BF16_W8, "bf16x3_w8", BF16_PEAK_TFLOPS, 24.0),
                                     (bem.BEM_APPLY_MFMA_FP32, "fp32", FP32_MFMA_PEAK_TFLOPS, 8.0)):
             for _ in range(2):
                 P.apply(X, kernel=kern)

@@ -157,12 +157,18 @@ bem_status bem_apply_parts(bem_problem *p, const bem_complex *x, bem_complex *y,
  *   BEM_APPLY_GEMV            one GEMV per vector (FP32 matrix, FP64 accumulation)
  *   BEM_APPLY_MFMA_FP32       one FP32 MFMA GEMM for all vectors
  *   BEM_APPLY_MFMA_SPLIT_BF16 one 3-term split-BF16 MFMA GEMM for all vectors (problem
- *                             assembled with BEM_ASSEMBLED_SPLIT_BF16)
+ *                             assembled with BEM_ASSEMBLED_SPLIT_BF16), tile shape and K
+ *                             slices from the autotuner (BEM_AUTOTUNE) or the heuristic
+ *   BEM_APPLY_MFMA_SPLIT_BF16_W4  the same GEMM forced to its 256 x 128 four-wave tile
+ *   BEM_APPLY_MFMA_SPLIT_BF16_W8  the same GEMM forced to its 384 x 128 eight-wave tile
+ *                             (both with heuristic K slices; for tests and measurements)
  * On-the-fly problems accept only BEM_APPLY_DEFAULT. */
 #define BEM_APPLY_DEFAULT 0
 #define BEM_APPLY_GEMV 1
 #define BEM_APPLY_MFMA_FP32 2
 #define BEM_APPLY_MFMA_SPLIT_BF16 3
+#define BEM_APPLY_MFMA_SPLIT_BF16_W4 4
+#define BEM_APPLY_MFMA_SPLIT_BF16_W8 5
 bem_status bem_apply_with(bem_problem *p, const bem_complex *x, bem_complex *y, int32_t n_rhs, int kernel);
 
 /* Right-hand side b_j = <gamma^{j,+} p_inc, phi> (eq. Galerkin_disc_rhs1) for

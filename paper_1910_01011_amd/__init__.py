@@ -36,6 +36,7 @@ BEM_OTF, BEM_ASSEMBLED_FP32, BEM_ASSEMBLED_SPLIT_BF16 = 0, 1, 2
 BEM_DEVICE_PTRS = 1
 BEM_AUTOTUNE = 2
 BEM_APPLY_DEFAULT, BEM_APPLY_GEMV, BEM_APPLY_MFMA_FP32, BEM_APPLY_MFMA_SPLIT_BF16 = 0, 1, 2, 3
+BEM_APPLY_MFMA_SPLIT_BF16_W4, BEM_APPLY_MFMA_SPLIT_BF16_W8 = 4, 5
 BEM_PLANE_WAVE, BEM_POINT_SOURCES, BEM_PISTON_ARRAY = 0, 1, 2
 BEM_PRECOND_NONE, BEM_PRECOND_OSRC = 0, 1
 BEM_PREC_FP32, BEM_PREC_SPLIT_BF16_FGMRES, BEM_PREC_FP32_MFMA_FGMRES = 0, 1, 2

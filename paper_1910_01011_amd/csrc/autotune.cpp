@@ -175,8 +175,15 @@ int tune_pairs(bem_problem &p, void (*rebuild)(bem_problem &), int max_split)
 std::string gemm_key(const bem_problem &p, int R, bool bf16)
 {
     std::ostringstream key;
-    key << "gemm" << TUNE_VERSION << ":" << arch_name(p.device) << ":N" << bucket(p.N) << ":R" << bucket(R) << ":" << (bf16 ? "bf16x3b" : "f32b");
+    key << "gemm" << TUNE_VERSION << ":" << arch_name(p.device) << ":N" << bucket(p.N) << ":R" << bucket(R) << ":" << (bf16 ? "bf16x3c" : "f32c");
     return key.str();
+}
+
+// Codes of the GEMM choice: 100 * tile shape + K slices.
+static bool valid_gemm_code(int code, bool bf16)
+{
+    const int shape = code / 100, ns = code % 100;
+    return ns >= 1 && ns <= 64 && (shape == 0 || (bf16 && shape == 1));
 }
 
 int cached_gemm_slices(bem_problem &p, int R, bool bf16)
@@ -184,32 +191,35 @@ int cached_gemm_slices(bem_problem &p, int R, bool bf16)
     std::lock_guard<std::mutex> lk(g_mu);
     load_cache();
     auto it = g_cache.find(gemm_key(p, R, bf16));
-    return it != g_cache.end() && it->second >= 1 && it->second <= 64 ? it->second : 0;
+    return it != g_cache.end() && valid_gemm_code(it->second, bf16) ? it->second : 0;
 }
 
-// Number of K slices of the GEMM for R right-hand sides (tuned once per bucket).
+// Tile shape and number of K slices of the GEMM for R right-hand sides, tuned
+// once per bucket; returns the code 100 * shape + slices.
 int tune_gemm_slices(bem_problem &p, int R, bool bf16, void *xbuf, float *cbuf, double2 *Y)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     load_cache();
     const std::string key = gemm_key(p, R, bf16);
     auto it = g_cache.find(key);
-    if (it != g_cache.end() && it->second >= 1 && it->second <= 64 &&
-        gemm_plan(p, R, bf16, it->second).bytes_c <= p.gc_bytes)
+    if (it != g_cache.end() && valid_gemm_code(it->second, bf16) &&
+        gemm_plan(p, R, bf16, it->second % 100, it->second / 100).bytes_c <= p.gc_bytes)
         return it->second;
     int best = gemm_plan(p, R, bf16, 0).n_s;
     float best_ms = 1e30f;
-    for (int s : {1, 2, 4, 8, 16, 32, 64}) {
-        const GemmPlan g = gemm_plan(p, R, bf16, s);
-        if (g.bytes_c > p.gc_bytes || g.bytes_x > p.gx_bytes) continue;
-        // the slice count trades GEMM occupancy against partials to sum: time both
-        const float ms = time_ms(p, [&]() {
-            launch_gemm_kernel(p, g, xbuf, cbuf);
-            launch_unpack(p, g, cbuf, Y);
-        }, 2);
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = g.n_s;
+    for (int shape = 0; shape < (bf16 ? 2 : 1); ++shape) {
+        for (int s : {1, 2, 4, 8, 16, 32, 64}) {
+            const GemmPlan g = gemm_plan(p, R, bf16, s, shape);
+            if (g.bytes_c > p.gc_bytes || g.bytes_x > p.gx_bytes) continue;
+            // the slice count trades GEMM occupancy against partials to sum: time both
+            const float ms = time_ms(p, [&]() {
+                launch_gemm_kernel(p, g, xbuf, cbuf);
+                launch_unpack(p, g, cbuf, Y);
+            }, 2);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = 100 * shape + g.n_s;
+            }
         }
     }
     store(key, best);

@@ -203,25 +203,30 @@ void grow(void **ptr, size_t &have, size_t need)
 // search: allow the K-slice search for an untuned bucket (the solvers pass
 // false: they take a cached choice, else the heuristic, so that no timing runs
 // inside a solve).
-void apply_dense_multi(bem_problem &p, const double2 *X, double2 *Y, int n_rhs, bool bf16, bool search = true)
+// force_shape >= 0: that split-BF16 tile shape with heuristic K slices (no tuning).
+void apply_dense_multi(bem_problem &p, const double2 *X, double2 *Y, int n_rhs, bool bf16, bool search = true,
+                       int force_shape = -1)
 {
-    int slices = 0;
-    if ((p.flags & BEM_AUTOTUNE) && !search) {
-        slices = bem::cached_gemm_slices(p, n_rhs, bf16);
+    int code = 0;   // 100 * tile shape + K slices (0: heuristic)
+    if (force_shape >= 0) {
+        code = 100 * force_shape;
+    } else if ((p.flags & BEM_AUTOTUNE) && !search) {
+        code = bem::cached_gemm_slices(p, n_rhs, bf16);
     } else if (p.flags & BEM_AUTOTUNE) {
         // scratch for every candidate (K-slice partials capped at 4 GB), then tune once per bucket
         size_t cmax = 0;
-        for (int s : {1, 2, 4, 8, 16, 32, 64}) {
-            const bem::GemmPlan c = bem::gemm_plan(p, n_rhs, bf16, s);
-            if (c.bytes_c <= (size_t(4) << 30)) cmax = std::max(cmax, c.bytes_c);
-        }
+        for (int shape = 0; shape < 2; ++shape)
+            for (int s : {1, 2, 4, 8, 16, 32, 64}) {
+                const bem::GemmPlan c = bem::gemm_plan(p, n_rhs, bf16, s, shape);
+                if (c.bytes_c <= (size_t(4) << 30)) cmax = std::max(cmax, c.bytes_c);
+            }
         const bem::GemmPlan g0 = bem::gemm_plan(p, n_rhs, bf16, 1);
         BEM_HIP(hipStreamSynchronize(p.stream));
         grow(&p.d_gx, p.gx_bytes, g0.bytes_x);
         grow(reinterpret_cast<void **>(&p.d_gc), p.gc_bytes, cmax);
-        slices = bem::tune_gemm_slices(p, n_rhs, bf16, p.d_gx, p.d_gc, Y);
+        code = bem::tune_gemm_slices(p, n_rhs, bf16, p.d_gx, p.d_gc, Y);
     }
-    const bem::GemmPlan g = bem::gemm_plan(p, n_rhs, bf16, slices);
+    const bem::GemmPlan g = bem::gemm_plan(p, n_rhs, bf16, code % 100, code / 100);
     if (p.gx_bytes < g.bytes_x) {
         if (p.d_gx) (void)hipFree(p.d_gx);
         p.d_gx = nullptr;
@@ -473,11 +478,12 @@ bem_status bem_apply(bem_problem *p, const bem_complex *x, bem_complex *y, int32
 bem_status bem_apply_with(bem_problem *p, const bem_complex *x, bem_complex *y, int32_t n_rhs, int kernel)
 {
     if (!p || !x || !y || n_rhs < 0) return fail(BEM_ERR_INVALID_ARG, "bem_apply_with: bad arguments");
-    if (kernel < BEM_APPLY_DEFAULT || kernel > BEM_APPLY_MFMA_SPLIT_BF16)
+    if (kernel < BEM_APPLY_DEFAULT || kernel > BEM_APPLY_MFMA_SPLIT_BF16_W8)
         return fail(BEM_ERR_INVALID_ARG, "bem_apply_with: unknown kernel");
     if (kernel == BEM_APPLY_DEFAULT) return bem_apply_parts(p, x, y, n_rhs, 3);
     if (p->mode == BEM_OTF) return fail(BEM_ERR_INVALID_ARG, "bem_apply_with: on-the-fly problems have no dense kernels");
-    if (kernel == BEM_APPLY_MFMA_SPLIT_BF16 && p->mode != BEM_ASSEMBLED_SPLIT_BF16)
+    const bool split = kernel >= BEM_APPLY_MFMA_SPLIT_BF16;
+    if (split && p->mode != BEM_ASSEMBLED_SPLIT_BF16)
         return fail(BEM_ERR_INVALID_ARG, "bem_apply_with: no BF16 planes (assemble with BEM_ASSEMBLED_SPLIT_BF16)");
     if (n_rhs == 0) return BEM_OK;
     return guarded([&]() -> bem_status {
@@ -495,7 +501,8 @@ bem_status bem_apply_with(bem_problem *p, const bem_complex *x, bem_complex *y, 
             for (int r = 0; r < n_rhs; ++r)
                 apply_dense_one(*p, dx + int64_t(r) * p->N, dy + int64_t(r) * p->N, r == n_rhs - 1);
         } else {
-            apply_dense_multi(*p, dx, dy, n_rhs, kernel == BEM_APPLY_MFMA_SPLIT_BF16);
+            const int shape = kernel == BEM_APPLY_MFMA_SPLIT_BF16_W4 ? 0 : kernel == BEM_APPLY_MFMA_SPLIT_BF16_W8 ? 1 : -1;
+            apply_dense_multi(*p, dx, dy, n_rhs, split, true, shape);
         }
         if (!(p->flags & BEM_DEVICE_PTRS)) {
             BEM_HIP(hipMemcpyAsync(y, p->d_y, bytes, hipMemcpyDeviceToHost, p->stream));

@@ -72,6 +72,8 @@ struct SingularItem {
 struct GemmPlan {
     int R;             // right-hand sides
     bool bf16;         // split-BF16 3-term (true) or FP32 MFMA (false)
+    int shape;         // split-BF16 tile: 0 = 256 x 128 (4 waves), 1 = 384 x 128 (8 waves)
+    int block;         // threads per workgroup
     int64_t Kp, Np;    // padded K (= 2n) and N (= 2R)
     int n_m, n_n, n_s; // m-tiles, n-tiles, K slices
     int64_t kslice;
@@ -204,7 +206,7 @@ void launch_scatter(bem_problem &p, const double2 *x, double2 *y, int parts);
 void launch_assemble_dense(bem_problem &p);
 void launch_gemv(bem_problem &p, const double2 *x, double2 *y);
 void split_matrix_bf16(bem_problem &p);
-GemmPlan gemm_plan(const bem_problem &p, int R, bool bf16, int force_slices);
+GemmPlan gemm_plan(const bem_problem &p, int R, bool bf16, int force_slices, int shape = 0);
 void launch_gemm(bem_problem &p, const GemmPlan &g, const double2 *X, double2 *Y, void *xbuf, float *cbuf);
 void launch_gemm_kernel(bem_problem &p, const GemmPlan &g, void *xbuf, float *cbuf);
 void launch_unpack(bem_problem &p, const GemmPlan &g, const float *cbuf, double2 *Y);

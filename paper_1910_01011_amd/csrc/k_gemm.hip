@@ -121,32 +121,34 @@ __device__ __forceinline__ void tile_of_kouter(int id, int n_m, int n_n, int &mt
 // multiples of 64, so every slice has an even number of steps.
 constexpr int XBM = 256;    // rows of a split-BF16 workgroup tile
 constexpr int XWB = 4;      // 16-row blocks per wave
-constexpr int GKA = 64;     // alignment of Kp and of the K slices
+constexpr int GKA = 192;    // alignment of Kp: K slices are multiples of 64 (4-wave shape) or 96 (8-wave shape)
 
+template <int WB>
 __device__ __forceinline__ void load_a_frags(const uint16_t *const *pah, const uint16_t *const *pal, int64_t k,
-                                             bf16x8 (&ah)[XWB], bf16x8 (&al)[XWB])
+                                             bf16x8 (&ah)[WB], bf16x8 (&al)[WB])
 {
 #pragma unroll
-    for (int i = 0; i < XWB; ++i) {
+    for (int i = 0; i < WB; ++i) {
         ah[i] = *reinterpret_cast<const bf16x8 *>(pah[i] + k);
         al[i] = *reinterpret_cast<const bf16x8 *>(pal[i] + k);
     }
 }
 
-// one K step of 32: 8 column blocks x (hi hi, hi lo, lo hi) x 4 row blocks
+// one K step of 32: 8 column blocks x (hi hi, hi lo, lo hi) x WB row blocks
+template <int WB>
 __device__ __forceinline__ void mfma_step(const uint16_t *sBh, const uint16_t *sBl, int frow, int fk,
-                                          const bf16x8 (&ah)[XWB], const bf16x8 (&al)[XWB], f32x4 (&acc)[XWB][8])
+                                          const bf16x8 (&ah)[WB], const bf16x8 (&al)[WB], f32x4 (&acc)[WB][8])
 {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&sBh[(16 * j + frow) * GBKP + fk]);
         const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(&sBl[(16 * j + frow) * GBKP + fk]);
 #pragma unroll
-        for (int i = 0; i < XWB; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+        for (int i = 0; i < WB; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
 #pragma unroll
-        for (int i = 0; i < XWB; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+        for (int i = 0; i < WB; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
 #pragma unroll
-        for (int i = 0; i < XWB; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+        for (int i = 0; i < WB; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
     }
 }
 
@@ -209,27 +211,116 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16x3(const uint16_t *__restri
         for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
     bf16x8 xh[XWB], xl[XWB], yh[XWB], yl[XWB];
     load_b(0);
-    load_a_frags(pah, pal, 0, xh, xl);
-    load_a_frags(pah, pal, GBK, yh, yl);
+    load_a_frags<XWB>(pah, pal, 0, xh, xl);
+    load_a_frags<XWB>(pah, pal, GBK, yh, yl);
     store_b(0);
     __syncthreads();
     for (int t = 0; t < nk; t += 2) {
         // even step: LDS buffer 0, registers x
         load_b(int64_t(t + 1) * GBK);
-        mfma_step(sB[0][0], sB[0][1], frow, fk, xh, xl, acc);
-        load_a_frags(pah, pal, std::min<int64_t>(int64_t(t + 2) * GBK, klast), xh, xl);
+        mfma_step<XWB>(sB[0][0], sB[0][1], frow, fk, xh, xl, acc);
+        load_a_frags<XWB>(pah, pal, std::min<int64_t>(int64_t(t + 2) * GBK, klast), xh, xl);
         store_b(1);
         __syncthreads();
         // odd step: LDS buffer 1, registers y
         load_b(int64_t(t + 2) * GBK);
-        mfma_step(sB[1][0], sB[1][1], frow, fk, yh, yl, acc);
-        load_a_frags(pah, pal, std::min<int64_t>(int64_t(t + 3) * GBK, klast), yh, yl);
+        mfma_step<XWB>(sB[1][0], sB[1][1], frow, fk, yh, yl, acc);
+        load_a_frags<XWB>(pah, pal, std::min<int64_t>(int64_t(t + 3) * GBK, klast), yh, yl);
         store_b(0);
         __syncthreads();
     }
     float *Cs = C + int64_t(ks) * M * Np;
 #pragma unroll
     for (int i = 0; i < XWB; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t row = m0 + WM * w + 16 * i + 4 * (lane >> 4) + e;
+                const int64_t col = n0 + 16 * j + frow;
+                if (row < M) Cs[row * Np + col] = acc[i][j][e];
+            }
+}
+
+// Split-BF16 GEMM, second tile shape: eight waves of 48 rows (3 x 8 MFMA tiles,
+// 96 accumulators per lane) share one 384 x 128 workgroup tile, so the X' tile
+// in LDS serves twice as many rows per byte staged, and the smaller per-wave
+// A fragment set leaves registers for three sets: the loads of step t + 3 are
+// issued as soon as step t has consumed its set.  K slices are multiples of 96
+// (step count divisible by three).  The autotuner picks this shape or the
+// four-wave one per problem size and right-hand-side bucket.
+constexpr int YBM = 384;    // rows of the eight-wave tile
+constexpr int YWB = 3;      // 16-row blocks per wave
+constexpr int YNS = 3;      // A register sets in flight
+
+__global__ __launch_bounds__(512, 1) void k_gemm_bf16x3_w8(const uint16_t *__restrict__ Ahi,
+                                                           const uint16_t *__restrict__ Alo,
+                                                           const uint16_t *__restrict__ Bhi,
+                                                           const uint16_t *__restrict__ Blo, int64_t M, int64_t Kp,
+                                                           int n_m, int n_n, int64_t kslice, float *__restrict__ C,
+                                                           int64_t Np)
+{
+    constexpr int WM = 16 * YWB;
+    __shared__ __attribute__((aligned(16))) uint16_t sB[2][2][GBN * GBKP];   // [buffer][hi, lo]
+    int mt, nt, ks;
+    tile_of_kouter(blockIdx.x, n_m, n_n, mt, nt, ks);
+    if (mt >= n_m) return;   // padding ids of the XCD-grouped order
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t m0 = int64_t(mt) * YBM, n0 = int64_t(nt) * GBN;
+    const int64_t kb = int64_t(ks) * kslice, ke = std::min<int64_t>(Kp, kb + kslice);
+    const int nk = int((ke - kb) / GBK);   // multiple of YNS
+    const int64_t klast = int64_t(nk - 1) * GBK;
+    const int frow = lane & 15, fk = 8 * (lane >> 4);
+    const uint16_t *pah[YWB], *pal[YWB];
+#pragma unroll
+    for (int i = 0; i < YWB; ++i) {
+        const int64_t r = std::min<int64_t>(M - 1, m0 + WM * w + 16 * i + frow);   // rows past M: never stored
+        pah[i] = Ahi + r * Kp + kb + fk;
+        pal[i] = Alo + r * Kp + kb + fk;
+    }
+    // X' tile staging: 512 threads, one plane per half, two rows (64 apart) of
+    // one 16-byte chunk each; loads past the slice are clamped to its last step
+    const int plane = tid >> 8, brow = (tid & 255) >> 2, bch = tid & 3;
+    const uint16_t *pb0 = (plane ? Blo : Bhi) + (n0 + brow) * Kp + kb + 8 * bch;   // n0 + brow + 64 < Np
+    const uint16_t *pb1 = pb0 + 64 * Kp;
+    const int soff0 = brow * GBKP + 8 * bch, soff1 = (brow + 64) * GBKP + 8 * bch;
+    uint4 b0, b1;
+    auto load_b = [&](int64_t k) {
+        k = std::min<int64_t>(k, klast);
+        b0 = *reinterpret_cast<const uint4 *>(pb0 + k);
+        b1 = *reinterpret_cast<const uint4 *>(pb1 + k);
+    };
+    auto store_b = [&](int buf) {
+        *reinterpret_cast<uint4 *>(&sB[buf][plane][soff0]) = b0;
+        *reinterpret_cast<uint4 *>(&sB[buf][plane][soff1]) = b1;
+    };
+    f32x4 acc[YWB][8];
+#pragma unroll
+    for (int i = 0; i < YWB; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+    bf16x8 ah[YNS][YWB], al[YNS][YWB];
+    load_b(0);
+#pragma unroll
+    for (int u = 0; u < YNS; ++u) load_a_frags<YWB>(pah, pal, int64_t(u) * GBK, ah[u], al[u]);
+    store_b(0);
+    __syncthreads();
+    int buf = 0;
+    for (int t = 0; t < nk; t += YNS) {
+#pragma unroll
+        for (int u = 0; u < YNS; ++u) {
+            load_b(int64_t(t + u + 1) * GBK);
+            mfma_step<YWB>(sB[buf][0], sB[buf][1], frow, fk, ah[u], al[u], acc);
+            load_a_frags<YWB>(pah, pal, std::min<int64_t>(int64_t(t + u + YNS) * GBK, klast), ah[u], al[u]);
+            // buffer buf ^ 1 was last read in the previous step, before the barrier
+            store_b(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
+    }
+    float *Cs = C + int64_t(ks) * M * Np;
+#pragma unroll
+    for (int i = 0; i < YWB; ++i)
 #pragma unroll
         for (int j = 0; j < 8; ++j)
 #pragma unroll
@@ -374,14 +465,18 @@ void split_matrix_bf16(bem_problem &p)
     BEM_HIP(hipGetLastError());
 }
 
-GemmPlan gemm_plan(const bem_problem &p, int R, bool bf16, int force_slices)
+GemmPlan gemm_plan(const bem_problem &p, int R, bool bf16, int force_slices, int shape)
 {
     GemmPlan g{};
     g.R = R;
     g.bf16 = bf16;
+    g.shape = bf16 ? std::max(0, std::min(shape, 1)) : 0;
+    const int tile_m = !bf16 ? GBM : (g.shape == 1 ? YBM : XBM);
+    const int64_t kalign = !bf16 ? 64 : (g.shape == 1 ? 96 : 64);   // divides GKA
+    g.block = g.shape == 1 ? 512 : 256;
     g.Kp = round_up(2 * p.N, GKA);
     g.Np = round_up(2 * int64_t(R), GBN);
-    g.n_m = int((p.N + (bf16 ? XBM : GBM) - 1) / (bf16 ? XBM : GBM));
+    g.n_m = int((p.N + tile_m - 1) / tile_m);
     g.n_n = int(g.Np / GBN);
     const int64_t ksteps = g.Kp / GBK;
     // enough workgroups to cover every CU several times
@@ -389,7 +484,7 @@ GemmPlan gemm_plan(const bem_problem &p, int R, bool bf16, int force_slices)
     s = int(std::min<int64_t>(s, std::max<int64_t>(1, ksteps / 8)));
     g.n_s = std::max(1, std::min(s, 64));
     if (force_slices > 0) g.n_s = int(std::min<int64_t>(force_slices, ksteps));
-    g.kslice = round_up((g.Kp + g.n_s - 1) / g.n_s, GKA);
+    g.kslice = round_up((g.Kp + g.n_s - 1) / g.n_s, kalign);
     g.n_s = int((g.Kp + g.kslice - 1) / g.kslice);
     const int groups = (g.n_m + 7) / 8;
     g.n_wg = groups * 8 * g.n_n * g.n_s;
@@ -403,8 +498,12 @@ void launch_gemm_kernel(bem_problem &p, const GemmPlan &g, void *xbuf, float *cb
     const int64_t tot = g.Np * g.Kp;
     if (g.bf16) {
         uint16_t *hi = static_cast<uint16_t *>(xbuf), *lo = hi + tot;
-        k_gemm_bf16x3<<<dim3(unsigned(g.n_wg)), dim3(256), 0, p.stream>>>(p.d_Ahi, p.d_Alo, hi, lo, p.N, g.Kp, g.n_m,
-                                                                         g.n_n, g.kslice, cbuf, g.Np);
+        if (g.shape == 1)
+            k_gemm_bf16x3_w8<<<dim3(unsigned(g.n_wg)), dim3(512), 0, p.stream>>>(p.d_Ahi, p.d_Alo, hi, lo, p.N, g.Kp,
+                                                                                g.n_m, g.n_n, g.kslice, cbuf, g.Np);
+        else
+            k_gemm_bf16x3<<<dim3(unsigned(g.n_wg)), dim3(256), 0, p.stream>>>(p.d_Ahi, p.d_Alo, hi, lo, p.N, g.Kp,
+                                                                             g.n_m, g.n_n, g.kslice, cbuf, g.Np);
     } else {
         k_gemm_f32<<<dim3(unsigned(g.n_wg)), dim3(256), 0, p.stream>>>(reinterpret_cast<const float *>(p.d_A), 2 * p.N,
                                                                       static_cast<float *>(xbuf), p.N, 2 * p.N, g.Kp,
@@ -422,8 +521,12 @@ void launch_gemm(bem_problem &p, const GemmPlan &g, const double2 *X, double2 *Y
                                                                                        nullptr, hi, lo);
         BEM_HIP(hipGetLastError());
         if (p.timed_gemm) BEM_HIP(hipEventRecord(p.ev[1], p.stream));
-        k_gemm_bf16x3<<<dim3(unsigned(g.n_wg)), dim3(256), 0, p.stream>>>(p.d_Ahi, p.d_Alo, hi, lo, p.N, g.Kp, g.n_m,
-                                                                         g.n_n, g.kslice, cbuf, g.Np);
+        if (g.shape == 1)
+            k_gemm_bf16x3_w8<<<dim3(unsigned(g.n_wg)), dim3(512), 0, p.stream>>>(p.d_Ahi, p.d_Alo, hi, lo, p.N, g.Kp,
+                                                                                g.n_m, g.n_n, g.kslice, cbuf, g.Np);
+        else
+            k_gemm_bf16x3<<<dim3(unsigned(g.n_wg)), dim3(256), 0, p.stream>>>(p.d_Ahi, p.d_Alo, hi, lo, p.N, g.Kp,
+                                                                             g.n_m, g.n_n, g.kslice, cbuf, g.Np);
     } else {
         float *xf = static_cast<float *>(xbuf);
         k_pack_rhs<false><<<dim3(blocks_1d(tot, 256, true)), dim3(256), 0, p.stream>>>(X, p.N, g.R, g.Np, g.Kp, xf,

@@ -68,6 +68,24 @@ def test_assembled_split_bf16_gemm_multi_rhs(c1):
     assert max(errs) <= 1e-4
 
 
+@pytest.mark.parametrize("kernel_name", ["BEM_APPLY_MFMA_SPLIT_BF16_W4", "BEM_APPLY_MFMA_SPLIT_BF16_W8"])
+def test_split_bf16_tile_shapes(c1, kernel_name):
+    """Both split-BF16 tile shapes (256 x 128 four-wave, 384 x 128 eight-wave;
+    n = 1,284 leaves a ragged last m-tile for both) against the oracle, at R = 70
+    (two n-tiles, the second ragged)."""
+    prob, A = c1
+    bem = _bem()
+    P = bem.Problem.from_config(prob, mode=bem.BEM_ASSEMBLED_SPLIT_BF16)
+    X = vectors.random_complex(prob.n_unknowns, seed=6, n_rhs=70)
+    Y = P.apply(X, kernel=getattr(bem, kernel_name))
+    errs = [_relerr(Y[r], A @ X[r]) for r in range(70)]
+    print(f"{kernel_name} rel err max {max(errs):.2e}")
+    assert max(errs) <= 1e-4
+    # the FP32 MFMA GEMM of the same matrix agrees to the split's precision
+    Yf = P.apply(X, kernel=bem.BEM_APPLY_MFMA_FP32)
+    assert max(_relerr(Y[r], Yf[r]) for r in range(70)) <= 1e-4
+
+
 def test_assembled_two_domains_matches_oracle():
     prob = configs.two_spheres(level=2)
     A = oracle.pmchwt_matrix(prob)

@@ -119,7 +119,8 @@ def test_config4_sampled_rows_gemm_r256(c4):
     prob, rows, R, P = c4
     X = vectors.random_complex(prob.n_unknowns, seed=1, n_rhs=256)
     ref = X @ R.T                                   # [256, rows]
-    for kernel, tol in ((bem.BEM_APPLY_MFMA_SPLIT_BF16, 5e-5), (bem.BEM_APPLY_MFMA_FP32, 1e-5),
+    for kernel, tol in ((bem.BEM_APPLY_MFMA_SPLIT_BF16, 5e-5), (bem.BEM_APPLY_MFMA_SPLIT_BF16_W4, 5e-5),
+                        (bem.BEM_APPLY_MFMA_SPLIT_BF16_W8, 5e-5), (bem.BEM_APPLY_MFMA_FP32, 1e-5),
                         (bem.BEM_APPLY_GEMV, 1e-5)):
         Xk = X if kernel != bem.BEM_APPLY_GEMV else X[:4]
         Y = P.apply(Xk, kernel=kernel)
