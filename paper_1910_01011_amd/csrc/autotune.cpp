@@ -175,7 +175,7 @@ int tune_pairs(bem_problem &p, void (*rebuild)(bem_problem &), int max_split)
 std::string gemm_key(const bem_problem &p, int R, bool bf16)
 {
     std::ostringstream key;
-    key << "gemm" << TUNE_VERSION << ":" << arch_name(p.device) << ":N" << bucket(p.N) << ":R" << bucket(R) << ":" << (bf16 ? "bf16x3c" : "f32c");
+    key << "gemm" << TUNE_VERSION << ":" << arch_name(p.device) << ":N" << bucket(p.N) << ":R" << bucket(R) << ":" << (bf16 ? "bf16x3d" : "f32c");
     return key.str();
 }
 

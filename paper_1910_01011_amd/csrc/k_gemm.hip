@@ -15,6 +15,13 @@
 //   FP32: v_mfma_f32_16x16x4_f32 on A' and X' directly.
 // Split-K over S slices fills the chip when 2R is small; slices are summed in
 // a fixed order by the unpack kernel.
+//
+// The BF16 planes of A' and of X'^T are stored blocked: 16 rows x 32 K values
+// per 1 KB block, blocks ordered (row block, K step), inside a block
+// (K chunk of 8, row, 8 values).  One MFMA operand fragment of a row block and
+// K step (lane l: row l % 16, K values 8 (l / 16) .. + 7) is then exactly the
+// block, lane l reading bytes 16 l .. 16 l + 15: every fragment load is one
+// contiguous 1 KB read of whole cache lines.
 #include <algorithm>
 #include <cmath>
 
@@ -40,23 +47,32 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f)
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 
-// A' (n x 2n fp32 view of A) -> hi/lo BF16 planes [n][Kp], zero-padded columns
-// (grid-stride: n Kp exceeds the 32-bit work-item count of one dispatch
-// beyond n ~ 46k)
-__global__ void k_split_matrix(const float *__restrict__ A, int64_t n, int64_t Kp, uint16_t *__restrict__ hi,
-                               uint16_t *__restrict__ lo)
+// element (r, k) of a blocked BF16 plane with Kp columns
+__device__ __forceinline__ int64_t blocked_offset(int64_t r, int64_t k, int64_t Kp)
 {
-    const int64_t total = n * Kp, step = int64_t(gridDim.x) * blockDim.x;
+    return ((r >> 4) * (Kp >> 5) + (k >> 5)) * 512 + ((k & 31) >> 3) * 128 + (r & 15) * 8 + (k & 7);
+}
+
+// A' (n x 2n fp32 view of A) -> blocked hi/lo BF16 planes of Mr = n rounded up
+// to 16 rows and Kp columns, zero-padded (grid-stride: Mr Kp exceeds the
+// 32-bit work-item count of one dispatch beyond n ~ 46k).  Reads are along
+// rows of A' (coalesced), writes are 16-byte runs inside the blocks.
+__global__ void k_split_matrix(const float *__restrict__ A, int64_t n, int64_t Mr, int64_t Kp,
+                               uint16_t *__restrict__ hi, uint16_t *__restrict__ lo)
+{
+    const int64_t total = Mr * Kp, step = int64_t(gridDim.x) * blockDim.x;
     for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < total; idx += step) {
         const int64_t r = idx / Kp, k = idx - r * Kp;
-        const float a = k < 2 * n ? A[r * 2 * n + k] : 0.0f;
+        const float a = (r < n && k < 2 * n) ? A[r * 2 * n + k] : 0.0f;
         const uint16_t h = f32_to_bf16(a);
-        hi[idx] = h;
-        lo[idx] = f32_to_bf16(a - bf16_to_f32(h));
+        const int64_t o = blocked_offset(r, k, Kp);
+        hi[o] = h;
+        lo[o] = f32_to_bf16(a - bf16_to_f32(h));
     }
 }
 
-// X (R vectors, complex128, RHS-major) -> X'^T [Np][Kp] (fp32, or bf16 hi/lo)
+// X (R vectors, complex128, RHS-major) -> X'^T [Np][Kp] (fp32 row-major, or
+// blocked bf16 hi/lo planes)
 template <bool BF16>
 __global__ void k_pack_rhs(const double2 *__restrict__ X, int64_t n, int R, int64_t Np, int64_t Kp,
                            float *__restrict__ f32, uint16_t *__restrict__ hi, uint16_t *__restrict__ lo)
@@ -74,8 +90,9 @@ __global__ void k_pack_rhs(const double2 *__restrict__ X, int64_t n, int R, int6
         }
         if (BF16) {
             const uint16_t h = f32_to_bf16(v);
-            hi[idx] = h;
-            lo[idx] = f32_to_bf16(v - bf16_to_f32(h));
+            const int64_t o = blocked_offset(j, k, Kp);
+            hi[o] = h;
+            lo[o] = f32_to_bf16(v - bf16_to_f32(h));
         } else {
             f32[idx] = v;
         }
@@ -123,14 +140,16 @@ constexpr int XBM = 256;    // rows of a split-BF16 workgroup tile
 constexpr int XWB = 4;      // 16-row blocks per wave
 constexpr int GKA = 192;    // alignment of Kp: K slices are multiples of 64 (4-wave shape) or 96 (8-wave shape)
 
+// fragments of K offset k (a multiple of 32 inside the slice) from the blocked planes
 template <int WB>
 __device__ __forceinline__ void load_a_frags(const uint16_t *const *pah, const uint16_t *const *pal, int64_t k,
                                              bf16x8 (&ah)[WB], bf16x8 (&al)[WB])
 {
+    const int64_t o = (k / GBK) * 512;
 #pragma unroll
     for (int i = 0; i < WB; ++i) {
-        ah[i] = *reinterpret_cast<const bf16x8 *>(pah[i] + k);
-        al[i] = *reinterpret_cast<const bf16x8 *>(pal[i] + k);
+        ah[i] = *reinterpret_cast<const bf16x8 *>(pah[i] + o);
+        al[i] = *reinterpret_cast<const bf16x8 *>(pal[i] + o);
     }
 }
 
@@ -170,33 +189,38 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16x3(const uint16_t *__restri
     const int nk = int((ke - kb) / GBK);   // even, >= 2
     const int64_t klast = int64_t(nk - 1) * GBK;
     const int frow = lane & 15, fk = 8 * (lane >> 4);
-    // A operand rows of this lane (rows past M read row M - 1; never stored)
+    // A fragments of this lane in the blocked planes: block (row block, K step)
+    // at ((row block) Kp / 32 + step) * 512, lane l at 8 l.  Row blocks past the
+    // last one read the last one (valid memory; those rows are never stored).
+    const int64_t ksteps = Kp / GBK, ks0 = kb / GBK, nrb = (M + 15) / 16;
     const uint16_t *pah[XWB], *pal[XWB];
 #pragma unroll
     for (int i = 0; i < XWB; ++i) {
-        const int64_t r = std::min<int64_t>(M - 1, m0 + WM * w + 16 * i + frow);
-        pah[i] = Ahi + r * Kp + kb + fk;
-        pal[i] = Alo + r * Kp + kb + fk;
+        const int64_t rb = std::min<int64_t>(nrb - 1, (m0 + WM * w + 16 * i) >> 4);
+        pah[i] = Ahi + (rb * ksteps + ks0) * 512 + 8 * lane;
+        pal[i] = Alo + (rb * ksteps + ks0) * 512 + 8 * lane;
     }
-    // X' tile staging: 128 rows x 4 chunks of 16 B per plane, two chunks per
-    // thread and plane; loads past the slice are clamped to its last step
-    // (valid memory, value unused)
+    // X' tile staging: 8 column blocks x 64 chunks of 16 B per plane and step,
+    // two chunks per thread and plane, each stored to its (column, K chunk)
+    // place of the padded LDS tile; loads past the slice are clamped to its
+    // last step (valid memory, value unused)
     const uint16_t *pbh[2], *pbl[2];
     int soff[2];
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
-        const int c = tid + 256 * it, row = c >> 2, ch = c & 3;
-        pbh[it] = Bhi + (n0 + row) * Kp + kb + 8 * ch;   // n0 + row < Np (padded)
-        pbl[it] = Blo + (n0 + row) * Kp + kb + 8 * ch;
-        soff[it] = row * GBKP + 8 * ch;
+        const int c = tid + 256 * it;
+        const int64_t cb = (n0 >> 4) + (c >> 6);   // column block, < Np / 16 (padded)
+        pbh[it] = Bhi + (cb * ksteps + ks0) * 512 + 8 * (c & 63);
+        pbl[it] = Blo + (cb * ksteps + ks0) * 512 + 8 * (c & 63);
+        soff[it] = ((c >> 6) * 16 + (c & 15)) * GBKP + 8 * ((c & 63) >> 4);
     }
     uint4 b0h, b0l, b1h, b1l;
     auto load_b = [&](int64_t k) {
-        k = std::min<int64_t>(k, klast);
-        b0h = *reinterpret_cast<const uint4 *>(pbh[0] + k);
-        b0l = *reinterpret_cast<const uint4 *>(pbl[0] + k);
-        b1h = *reinterpret_cast<const uint4 *>(pbh[1] + k);
-        b1l = *reinterpret_cast<const uint4 *>(pbl[1] + k);
+        const int64_t o = (std::min<int64_t>(k, klast) / GBK) * 512;
+        b0h = *reinterpret_cast<const uint4 *>(pbh[0] + o);
+        b0l = *reinterpret_cast<const uint4 *>(pbl[0] + o);
+        b1h = *reinterpret_cast<const uint4 *>(pbh[1] + o);
+        b1l = *reinterpret_cast<const uint4 *>(pbl[1] + o);
     };
     auto store_b = [&](int buf) {
         *reinterpret_cast<uint4 *>(&sB[buf][0][soff[0]]) = b0h;
@@ -271,28 +295,31 @@ __global__ __launch_bounds__(512, 1) void k_gemm_bf16x3_w8(const uint16_t *__res
     const int nk = int((ke - kb) / GBK);   // multiple of YNS
     const int64_t klast = int64_t(nk - 1) * GBK;
     const int frow = lane & 15, fk = 8 * (lane >> 4);
+    // blocked planes as in k_gemm_bf16x3 (row blocks past the last read the last)
+    const int64_t ksteps = Kp / GBK, ks0 = kb / GBK, nrb = (M + 15) / 16;
     const uint16_t *pah[YWB], *pal[YWB];
 #pragma unroll
     for (int i = 0; i < YWB; ++i) {
-        const int64_t r = std::min<int64_t>(M - 1, m0 + WM * w + 16 * i + frow);   // rows past M: never stored
-        pah[i] = Ahi + r * Kp + kb + fk;
-        pal[i] = Alo + r * Kp + kb + fk;
+        const int64_t rb = std::min<int64_t>(nrb - 1, (m0 + WM * w + 16 * i) >> 4);
+        pah[i] = Ahi + (rb * ksteps + ks0) * 512 + 8 * lane;
+        pal[i] = Alo + (rb * ksteps + ks0) * 512 + 8 * lane;
     }
-    // X' tile staging: 512 threads, one plane per half, two rows (64 apart) of
-    // one 16-byte chunk each; loads past the slice are clamped to its last step
-    const int plane = tid >> 8, brow = (tid & 255) >> 2, bch = tid & 3;
-    const uint16_t *pb0 = (plane ? Blo : Bhi) + (n0 + brow) * Kp + kb + 8 * bch;   // n0 + brow + 64 < Np
-    const uint16_t *pb1 = pb0 + 64 * Kp;
-    const int soff0 = brow * GBKP + 8 * bch, soff1 = (brow + 64) * GBKP + 8 * bch;
+    // X' tile staging: 512 threads, one 16-byte chunk per thread and plane;
+    // loads past the slice are clamped to its last step
+    const int c = tid;
+    const int64_t cb = (n0 >> 4) + (c >> 6);   // column block, < Np / 16 (padded)
+    const uint16_t *pbh = Bhi + (cb * ksteps + ks0) * 512 + 8 * (c & 63);
+    const uint16_t *pbl = Blo + (cb * ksteps + ks0) * 512 + 8 * (c & 63);
+    const int soff = ((c >> 6) * 16 + (c & 15)) * GBKP + 8 * ((c & 63) >> 4);
     uint4 b0, b1;
     auto load_b = [&](int64_t k) {
-        k = std::min<int64_t>(k, klast);
-        b0 = *reinterpret_cast<const uint4 *>(pb0 + k);
-        b1 = *reinterpret_cast<const uint4 *>(pb1 + k);
+        const int64_t o = (std::min<int64_t>(k, klast) / GBK) * 512;
+        b0 = *reinterpret_cast<const uint4 *>(pbh + o);
+        b1 = *reinterpret_cast<const uint4 *>(pbl + o);
     };
     auto store_b = [&](int buf) {
-        *reinterpret_cast<uint4 *>(&sB[buf][plane][soff0]) = b0;
-        *reinterpret_cast<uint4 *>(&sB[buf][plane][soff1]) = b1;
+        *reinterpret_cast<uint4 *>(&sB[buf][0][soff]) = b0;
+        *reinterpret_cast<uint4 *>(&sB[buf][1][soff]) = b1;
     };
     f32x4 acc[YWB][8];
 #pragma unroll
@@ -456,12 +483,12 @@ static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 void split_matrix_bf16(bem_problem &p)
 {
-    const int64_t Kp = round_up(2 * p.N, GKA);
-    BEM_HIP(hipMalloc(&p.d_Ahi, size_t(p.N) * Kp * sizeof(uint16_t)));
-    BEM_HIP(hipMalloc(&p.d_Alo, size_t(p.N) * Kp * sizeof(uint16_t)));
-    const int64_t tot = p.N * Kp;
+    const int64_t Kp = round_up(2 * p.N, GKA), Mr = round_up(p.N, 16);
+    BEM_HIP(hipMalloc(&p.d_Ahi, size_t(Mr) * Kp * sizeof(uint16_t)));
+    BEM_HIP(hipMalloc(&p.d_Alo, size_t(Mr) * Kp * sizeof(uint16_t)));
+    const int64_t tot = Mr * Kp;
     k_split_matrix<<<dim3(blocks_1d(tot, 256, true)), dim3(256), 0, p.stream>>>(
-        reinterpret_cast<const float *>(p.d_A), p.N, Kp, p.d_Ahi, p.d_Alo);
+        reinterpret_cast<const float *>(p.d_A), p.N, Mr, Kp, p.d_Ahi, p.d_Alo);
     BEM_HIP(hipGetLastError());
 }
 
