@@ -170,6 +170,17 @@ def main():
                 g[f"{pname}_tol{tol:g}"] = {"time_to_solve_s": ts, "iterations": info[0]["iterations"],
                                             "rel_residual": info[0]["rel_residual"],
                                             "converged": info[0]["converged"]}
+        # OSRC with its inner sparse solves to 1e-6 instead of 1e-10 (cheaper applies)
+        for otol in (1e-6, 1e-8):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            u, info = P.solve(b, bem.solve_options(tol=1e-5, restart=100, max_iter=400, precond=bem.BEM_PRECOND_OSRC,
+                                                   n_pade=4, r_eps=0.1, theta=np.pi / 3, osrc_tol=otol))
+            torch.cuda.synchronize()
+            ts = time.perf_counter() - ts
+            g[f"osrc_cocg{otol:g}_tol1e-05"] = {"time_to_solve_s": ts, "iterations": info[0]["iterations"],
+                                                "rel_residual": info[0]["rel_residual"],
+                                                "converged": info[0]["converged"]}
         out["gmres"] = g
     if not args.no_assembled:
         del P
@@ -273,11 +284,12 @@ def ribcage_assembled_section(bem, torch, autotune):
     c, nn, a = pistons.bowl_array()
     b = P.rhs(bem.Incident.pistons(c, nn, a, 1.0, np.arange(len(c))))
     # flexible forms: all 256 right-hand sides in one block, outer FP64 residual
-    # to 1e-6; inner cycles of 100 (the stack needs hundreds of Krylov steps)
+    # to 1e-6; inner cycles of 200 (the stack needs hundreds of Krylov steps;
+    # 200 saves about a tenth of the time against 100)
     for name, prec in (("split_bf16_fgmres", bem.BEM_PREC_SPLIT_BF16_FGMRES),
                        ("fp32_mfma_fgmres", bem.BEM_PREC_FP32_MFMA_FGMRES)):
         (u, info), t = _timed(torch, lambda: P.solve(b, bem.solve_options(
-            tol=1e-6, restart=10, max_iter=8, precision=prec, inner_tol=1e-3, inner_restart=100,
+            tol=1e-6, restart=10, max_iter=8, precision=prec, inner_tol=1e-3, inner_restart=200,
             inner_max_iter=1500)))
         res[f"solve_{name}_R256"] = {"tol": 1e-6, "s": t, "outer_iterations_max": int(max(i["iterations"] for i in info)),
                                      "max_rel_residual": float(max(i["rel_residual"] for i in info)),

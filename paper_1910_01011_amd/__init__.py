@@ -66,7 +66,7 @@ class bem_solve_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("precond", ctypes.c_int), ("n_pade", ctypes.c_int), ("r_eps", ctypes.c_double),
                 ("theta", ctypes.c_double), ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("inner_restart", ctypes.c_int), ("inner_max_iter", ctypes.c_int)]
+                ("inner_restart", ctypes.c_int), ("inner_max_iter", ctypes.c_int), ("osrc_tol", ctypes.c_double)]
 
 
 class bem_solve_info(ctypes.Structure):
@@ -178,9 +178,10 @@ class Incident:
 
 
 def solve_options(tol=1e-5, restart=100, max_iter=1000, precond=BEM_PRECOND_NONE, n_pade=4, r_eps=0.1,
-                  theta=np.pi / 3, precision=BEM_PREC_FP32, inner_tol=1e-3, inner_restart=0, inner_max_iter=0):
+                  theta=np.pi / 3, precision=BEM_PREC_FP32, inner_tol=1e-3, inner_restart=0, inner_max_iter=0,
+                  osrc_tol=0.0):
     return bem_solve_opts(tol, restart, max_iter, precond, n_pade, r_eps, theta, precision, inner_tol,
-                          inner_restart, inner_max_iter)
+                          inner_restart, inner_max_iter, osrc_tol)
 
 
 def footprint_bytes(domains, n_rhs=1, restart=100):

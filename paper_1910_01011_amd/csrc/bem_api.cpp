@@ -583,6 +583,8 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
         return fail(BEM_ERR_INVALID_ARG, "bem_solve: split-BF16 refinement needs a problem assembled in split-BF16 mode");
     if (o.precision != BEM_PREC_FP32 && !(o.inner_tol > 0 && o.inner_tol < 1))
         return fail(BEM_ERR_INVALID_ARG, "bem_solve: inner_tol must be in (0, 1)");
+    if (!(o.osrc_tol >= 0 && o.osrc_tol < 1))
+        return fail(BEM_ERR_INVALID_ARG, "bem_solve: osrc_tol must be in [0, 1) (0: 1e-10)");
     return guarded([&]() -> bem_status {
         BEM_HIP(hipSetDevice(p->device));
         const size_t n = size_t(n_rhs) * p->N;
@@ -617,7 +619,7 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
             // left preconditioning: GMRES on P A u = P b (stops on the
             // preconditioned residual); the unpreconditioned weak-form residual
             // is reported afterwards
-            const bem::OsrcParams op{o.n_pade, o.r_eps, o.theta, 1e-10, 3000};
+            const bem::OsrcParams op{o.n_pade, o.r_eps, o.theta, o.osrc_tol > 0 ? o.osrc_tol : 1e-10, 3000};
             double2 *PB = nullptr, *tmp = nullptr;
             dev_alloc(&PB, n);
             dev_alloc(&tmp, n);
@@ -657,7 +659,7 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
             } g2;
             if (o.precond == BEM_PRECOND_OSRC) {
                 // inner GMRES on the left-preconditioned system P A z = P v
-                const bem::OsrcParams op{o.n_pade, o.r_eps, o.theta, 1e-10, 3000};
+                const bem::OsrcParams op{o.n_pade, o.r_eps, o.theta, o.osrc_tol > 0 ? o.osrc_tol : 1e-10, 3000};
                 dev_alloc(&PV, n);
                 dev_alloc(&tmp, n);
                 g2.a = PV;
@@ -701,10 +703,12 @@ bem_status bem_apply_preconditioner(bem_problem *p, const bem_solve_opts *opts, 
     if (opts->precond != BEM_PRECOND_OSRC) return fail(BEM_ERR_INVALID_ARG, "bem_apply_preconditioner: precond must be OSRC");
     if (!(opts->r_eps > 0) || opts->n_pade < 0 || opts->n_pade > 64 || !std::isfinite(opts->theta))
         return fail(BEM_ERR_INVALID_ARG, "bem_apply_preconditioner: need r_eps > 0, 0 <= n_pade <= 64");
+    if (!(opts->osrc_tol >= 0 && opts->osrc_tol < 1))
+        return fail(BEM_ERR_INVALID_ARG, "bem_apply_preconditioner: osrc_tol must be in [0, 1)");
     if (n_rhs == 0) return BEM_OK;
     return guarded([&]() -> bem_status {
         BEM_HIP(hipSetDevice(p->device));
-        const bem::OsrcParams op{opts->n_pade, opts->r_eps, opts->theta, 1e-10, 3000};
+        const bem::OsrcParams op{opts->n_pade, opts->r_eps, opts->theta, opts->osrc_tol > 0 ? opts->osrc_tol : 1e-10, 3000};
         const size_t n = size_t(n_rhs) * p->N;
         if (p->flags & BEM_DEVICE_PTRS) {
             bem::osrc_apply(*p, op, reinterpret_cast<const double2 *>(y), reinterpret_cast<double2 *>(out), n_rhs);

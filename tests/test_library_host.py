@@ -95,3 +95,22 @@ def test_footprint_grows_with_rhs_and_restart():
     b = bem.footprint_bytes(prob.domains, 8, 30)
     c = bem.footprint_bytes(prob.domains, 8, 100)
     assert 0 < a < b < c
+
+
+@pytest.mark.parametrize("cname", ["bem_solve_opts", "bem_solve_info", "bem_assemble_opts"])
+def test_binding_structs_follow_the_header(cname):
+    """The ctypes structures of the binding list the C structs' fields in the
+    header's order (names as declared), so the two cannot drift apart."""
+    bem = _bem()
+    header = open(os.path.join(ROOT, "include", "bem.h")).read()
+    structs = dict((name, body) for body, name in re.findall(r"typedef struct\s*\{([^{}]*)\}\s*(\w+)\s*;", header))
+    assert cname in structs, cname
+    body = re.sub(r"/\*.*?\*/", "", structs[cname], flags=re.S)
+    names = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        for part in decl.split(","):
+            names.append(re.findall(r"\**(\w+)\s*$", part.strip())[0])
+    assert [f[0] for f in getattr(bem, cname)._fields_] == names
