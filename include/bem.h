@@ -125,9 +125,12 @@ typedef struct {
     double inner_tol;    /* inner tolerance of the flexible-GMRES refinement */
     int inner_restart;   /* inner GMRES restart length (0: 30) */
     int inner_max_iter;  /* inner iteration cap per outer step (0: 300) */
-    double osrc_tol;     /* relative residual of the OSRC inner sparse solves (COCG); 0: 1e-10.
-                            A looser value makes each preconditioner apply cheaper and slightly
-                            less exact (the solvers' stopping tests are unchanged) */
+    double osrc_tol;     /* relative residual of the OSRC inner sparse solves (COCG).  0: inside
+                            bem_solve one tenth of the tolerance GMRES works to (tol, or inner_tol
+                            for the flexible forms), within [1e-10, 1e-6]; in
+                            bem_apply_preconditioner 1e-10.  A looser value makes each
+                            preconditioner apply cheaper and slightly less exact; the solvers'
+                            stopping tests are unchanged */
 } bem_solve_opts;
 
 typedef struct {

@@ -263,6 +263,15 @@ void apply_device(bem_problem &p, const double2 *x, double2 *y, int n_rhs, int p
     }
 }
 
+// OSRC inner-solve tolerance inside a solve: the caller's osrc_tol, else ten
+// times tighter than the solver tolerance, within [1e-10, 1e-6]
+double osrc_inner_tol(const bem_solve_opts &o)
+{
+    if (o.osrc_tol > 0) return o.osrc_tol;
+    const double inner = o.precision == BEM_PREC_FP32 ? o.tol : std::min(o.tol, o.inner_tol);
+    return std::min(1e-6, std::max(1e-10, 0.1 * inner));
+}
+
 bem_solve_opts default_solve_opts()
 {
     bem_solve_opts o{};
@@ -619,7 +628,7 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
             // left preconditioning: GMRES on P A u = P b (stops on the
             // preconditioned residual); the unpreconditioned weak-form residual
             // is reported afterwards
-            const bem::OsrcParams op{o.n_pade, o.r_eps, o.theta, o.osrc_tol > 0 ? o.osrc_tol : 1e-10, 3000};
+            const bem::OsrcParams op{o.n_pade, o.r_eps, o.theta, osrc_inner_tol(o), 3000};
             double2 *PB = nullptr, *tmp = nullptr;
             dev_alloc(&PB, n);
             dev_alloc(&tmp, n);
@@ -659,7 +668,7 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
             } g2;
             if (o.precond == BEM_PRECOND_OSRC) {
                 // inner GMRES on the left-preconditioned system P A z = P v
-                const bem::OsrcParams op{o.n_pade, o.r_eps, o.theta, o.osrc_tol > 0 ? o.osrc_tol : 1e-10, 3000};
+                const bem::OsrcParams op{o.n_pade, o.r_eps, o.theta, osrc_inner_tol(o), 3000};
                 dev_alloc(&PV, n);
                 dev_alloc(&tmp, n);
                 g2.a = PV;
