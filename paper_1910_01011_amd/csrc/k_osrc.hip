@@ -9,8 +9,12 @@
 // with X = -M^-1 S', S' = S / k_eps^2, k_eps = k + 0.4 i k^(1/3) R_eps^(-2/3),
 // k = k0, and the branch-rotated Pade form
 //   sqrt(1 + X) z = C0 z - sum_l A_l (M - B_l S')^-1 S' z.
+// The Neumann rows are evaluated as C0 w0 - sum_l A_l (w0 - z - B_l t_l)/(1 - B_l)
+// with w0 = (M - S')^-1 M z and t_l the Pade solves (k_osrc_ntd): the same
+// operator, so that w0 is solved in the same batch as the t_l.
 // M and S are assembled on the union of all boundaries (block diagonal by
-// domain).  All sparse solves of one application are done together by a batched
+// domain).  The sparse solves of one application (two batches: the mass solve,
+// then every Pade and w0 system) are done by a batched
 // Jacobi-preconditioned COCG (conjugate orthogonal CG for complex symmetric
 // matrices) in FP64, one workgroup per (system, domain) block.
 #include <algorithm>
@@ -95,42 +99,68 @@ __global__ void k_osrc_sprime(const int32_t *__restrict__ aptr, const int32_t *_
     for (int l = 0; l < L; ++l) out[(v * L + l) * n + i] = w;
 }
 
-// root_v = C0 z_v - sum_l A_l t_(v,l);  D rows: result i k root; N rows: M root (input of the last solve)
-__global__ void k_osrc_combine(const int32_t *__restrict__ aptr, const int32_t *__restrict__ acol,
-                               const double *__restrict__ Mv, const double2 *__restrict__ Z,
-                               const double2 *__restrict__ T, const double2 *__restrict__ Al, int L, double2 C0,
-                               double2 ik, int64_t n, int R, double2 *__restrict__ rootD, double2 *__restrict__ rootN)
+// Dirichlet rows (v = 2 r): i k (C0 z_v - sum_l A_l t_(v,l)), the square-root
+// Pade approximant applied to z
+__global__ void k_osrc_combine(const double2 *__restrict__ Z, const double2 *__restrict__ T,
+                               const double2 *__restrict__ Al, int L, double2 C0, double2 ik, int64_t n, int R,
+                               double2 *__restrict__ rootD)
 {
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= n * 2 * R) return;
-    const int64_t v = idx / n, i = idx - v * n;
-    const double2 z = Z[idx];
+    if (idx >= n * R) return;
+    const int64_t r = idx / n, i = idx - r * n, v = 2 * r;
+    const double2 z = Z[v * n + i];
     double re = C0.x * z.x - C0.y * z.y, im = C0.x * z.y + C0.y * z.x;
     for (int l = 0; l < L; ++l) {
         const double2 t = T[(v * L + l) * n + i], a = Al[l];
         re -= a.x * t.x - a.y * t.y;
         im -= a.x * t.y + a.y * t.x;
     }
-    const int64_t r = v >> 1;
-    if ((v & 1) == 0) rootD[r * n + i] = make_double2(ik.x * re - ik.y * im, ik.x * im + ik.y * re);
-    else rootN[r * n + i] = make_double2(re, im);
+    rootD[idx] = make_double2(ik.x * re - ik.y * im, ik.x * im + ik.y * re);
 }
 
-// w = M x per vector
-__global__ void k_spmv_mass(const int32_t *__restrict__ aptr, const int32_t *__restrict__ acol,
-                            const double *__restrict__ Mv, const double2 *__restrict__ X, int64_t n, int V,
-                            double2 *__restrict__ W)
+// w = M x for the Neumann-row vectors (v = 2 r + 1) of Z: right-hand sides of
+// the (M - S')^-1 M z solves, appended after the Pade systems
+__global__ void k_mass_nrows(const int32_t *__restrict__ aptr, const int32_t *__restrict__ acol,
+                             const double *__restrict__ Mv, const double2 *__restrict__ Z, int64_t n, int R,
+                             double2 *__restrict__ W)
 {
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= n * V) return;
-    const int64_t v = idx / n, i = idx - v * n;
+    if (idx >= n * R) return;
+    const int64_t r = idx / n, i = idx - r * n;
+    const double2 *z = Z + (2 * r + 1) * n;
     double re = 0, im = 0;
     for (int32_t e = aptr[i]; e < aptr[i + 1]; ++e) {
-        const double2 x = X[v * n + acol[e]];
+        const double2 x = z[acol[e]];
         re += Mv[e] * x.x;
         im += Mv[e] * x.y;
     }
     W[idx] = make_double2(re, im);
+}
+
+// Neumann rows: wN = (M - S')^-1 M root with root = C0 z - sum_l A_l t_l and
+// t_l = (M - B_l S')^-1 S' z.  With T = M^-1 S' (all maps are functions of T),
+// (I - T)^-1 (I - B T)^-1 T = [(I - T)^-1 - (I - B T)^-1] / (1 - B) and
+// (I - B T)^-1 = I + B (I - B T)^-1 T, so
+//   wN = C0 w0 - sum_l A_l (w0 - z - B_l t_l) / (1 - B_l),  w0 = (M - S')^-1 M z,
+// the same discrete operator with w0 solved beside the t_l instead of after them.
+// coef[l] = (A_l / (1 - B_l), B_l)
+__global__ void k_osrc_ntd(const double2 *__restrict__ Z, const double2 *__restrict__ T,
+                           const double2 *__restrict__ W0, const double2 *__restrict__ coef, int L, double2 C0,
+                           int64_t n, int R, double2 *__restrict__ WN)
+{
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n * R) return;
+    const int64_t r = idx / n, i = idx - r * n, v = 2 * r + 1;
+    const double2 z = Z[v * n + i], w0 = W0[idx];
+    double re = C0.x * w0.x - C0.y * w0.y, im = C0.x * w0.y + C0.y * w0.x;
+    for (int l = 0; l < L; ++l) {
+        const double2 t = T[(v * L + l) * n + i], a = coef[2 * l], b = coef[2 * l + 1];
+        // d = w0 - z - B_l t
+        const double dr = w0.x - z.x - (b.x * t.x - b.y * t.y), di = w0.y - z.y - (b.x * t.y + b.y * t.x);
+        re -= a.x * dr - a.y * di;
+        im -= a.x * di + a.y * dr;
+    }
+    WN[idx] = make_double2(re, im);
 }
 
 // out (unknown order), with the paper's permutation of the unknowns of every
@@ -375,32 +405,46 @@ void osrc_apply(bem_problem &p, const OsrcParams &o, const double2 *Y, double2 *
     k_osrc_split<<<dim3(nb(n * R)), dim3(256), 0, s>>>(Y, p.d_rowD, p.d_rowN, n, p.N, R, U.p);
     BEM_HIP(hipGetLastError());
     cocg_batch(p, 2 * R, std::vector<cd>(2 * R, cd(0.0)), U.p, Z.p, o.cg_tol, o.cg_maxit);
-    // t_(v,l) = (M - B_l S')^-1 S' z_v
-    OsrcBuf Bt(size_t(2 * R) * L * n), T(size_t(2 * R) * L * n);
+    // one batch: t_(v,l) = (M - B_l S')^-1 S' z_v for both rows of every vector,
+    // and w0_r = (M - S')^-1 M z_(N rows) (see k_osrc_ntd)
+    const int64_t nt = int64_t(2 * R) * L;   // Pade systems
+    OsrcBuf Bt(size_t(nt + R) * n), T(size_t(nt + R) * n);
     const cd inv = 1.0 / ke2;
-    k_osrc_sprime<<<dim3(nb(n * 2 * R)), dim3(256), 0, s>>>(p.d_aptr, p.d_acol, p.d_Sv, Z.p, n, 2 * R, L,
-                                                            make_double2(inv.real(), inv.imag()), Bt.p);
+    if (L > 0) {
+        k_osrc_sprime<<<dim3(nb(n * 2 * R)), dim3(256), 0, s>>>(p.d_aptr, p.d_acol, p.d_Sv, Z.p, n, 2 * R, L,
+                                                                make_double2(inv.real(), inv.imag()), Bt.p);
+        BEM_HIP(hipGetLastError());
+    }
+    k_mass_nrows<<<dim3(nb(n * R)), dim3(256), 0, s>>>(p.d_aptr, p.d_acol, p.d_Mv, Z.p, n, R, Bt.p + nt * n);
     BEM_HIP(hipGetLastError());
-    std::vector<cd> shifts(size_t(2 * R) * L);
+    std::vector<cd> shifts(size_t(nt + R));
     for (int v = 0; v < 2 * R; ++v)
         for (int l = 0; l < L; ++l) shifts[size_t(v) * L + l] = B[l] / ke2;
-    if (L > 0) cocg_batch(p, 2 * R * L, shifts, Bt.p, T.p, o.cg_tol, o.cg_maxit);
-    // roots; D rows finished (i k root), N rows need (M - S')^-1 M root
-    OsrcBuf Al(size_t(std::max(L, 1))), rootD(size_t(R) * n), rootN(size_t(R) * n), MN(size_t(R) * n),
+    for (int r = 0; r < R; ++r) shifts[size_t(nt) + r] = inv;
+    cocg_batch(p, int(nt + R), shifts, Bt.p, T.p, o.cg_tol, o.cg_maxit);
+    // D rows: i k root; N rows: wN from w0 and the t_l
+    OsrcBuf Al(size_t(std::max(L, 1))), coef(size_t(2 * std::max(L, 1))), rootD(size_t(R) * n),
         WN(size_t(R) * n);
     {
-        std::vector<double2> t(L);
-        for (int l = 0; l < L; ++l) t[l] = make_double2(A[l].real(), A[l].imag());
-        if (L > 0) BEM_HIP(hipMemcpyAsync(Al.p, t.data(), L * sizeof(double2), hipMemcpyHostToDevice, s));
+        std::vector<double2> t(L), cf(2 * L);
+        for (int l = 0; l < L; ++l) {
+            t[l] = make_double2(A[l].real(), A[l].imag());
+            const cd q = A[l] / (1.0 - B[l]);
+            cf[2 * l] = make_double2(q.real(), q.imag());
+            cf[2 * l + 1] = make_double2(B[l].real(), B[l].imag());
+        }
+        if (L > 0) {
+            BEM_HIP(hipMemcpyAsync(Al.p, t.data(), L * sizeof(double2), hipMemcpyHostToDevice, s));
+            BEM_HIP(hipMemcpyAsync(coef.p, cf.data(), 2 * L * sizeof(double2), hipMemcpyHostToDevice, s));
+        }
         BEM_HIP(hipStreamSynchronize(s));
     }
-    k_osrc_combine<<<dim3(nb(n * 2 * R)), dim3(256), 0, s>>>(p.d_aptr, p.d_acol, p.d_Mv, Z.p, T.p, Al.p, L,
-                                                             make_double2(C0.real(), C0.imag()),
-                                                             make_double2(ik.real(), ik.imag()), n, R, rootD.p, rootN.p);
+    k_osrc_combine<<<dim3(nb(n * R)), dim3(256), 0, s>>>(Z.p, T.p, Al.p, L, make_double2(C0.real(), C0.imag()),
+                                                         make_double2(ik.real(), ik.imag()), n, R, rootD.p);
     BEM_HIP(hipGetLastError());
-    k_spmv_mass<<<dim3(nb(n * R)), dim3(256), 0, s>>>(p.d_aptr, p.d_acol, p.d_Mv, rootN.p, n, R, MN.p);
+    k_osrc_ntd<<<dim3(nb(n * R)), dim3(256), 0, s>>>(Z.p, T.p, T.p + nt * n, coef.p, L,
+                                                     make_double2(C0.real(), C0.imag()), n, R, WN.p);
     BEM_HIP(hipGetLastError());
-    cocg_batch(p, R, std::vector<cd>(R, inv), MN.p, WN.p, o.cg_tol, o.cg_maxit);
     const cd sN = 1.0 / ik;
     k_osrc_out<<<dim3(nb(n * R)), dim3(256), 0, s>>>(rootD.p, WN.p, make_double2(sN.real(), sN.imag()), p.d_rowD,
                                                      p.d_rowN, n, p.N, R, Out);
