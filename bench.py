@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "BEM apply G quad-pair interactions/s + GMRES time-to-solve at 1e-5; p50/p99 latency"
 FLOP_PER_PAIR = 140.0          # fused V, K, K', W multitrace pair (per-pair count of the design notes)
+FLOP_PER_PAIR_V = 21.0         # single-layer pair alone: difference, r^2, r, phase, G, one complex multiply-add
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector peak
 
 
@@ -153,6 +154,7 @@ def main():
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": recorded_traffic(),
                      "kernel": "k_pairs", "kernel_ms": pair_avg, "flop_per_pair": FLOP_PER_PAIR},
     }
+    out["single_layer"] = single_layer_section(P, prob, torch, args.steps, args.warmup)
     if not args.no_solve:
         # GMRES(100) on the on-the-fly operator, plane wave along +z, without and
         # with the OSRC preconditioner (N_Pade = 4, R_eps = 0.1 = radius / 10)
@@ -184,14 +186,14 @@ def main():
                                                 "converged": info[0]["converged"]}
         out["gmres"] = g
     if not args.no_assembled:
-        del P
+        P = None
         torch.cuda.empty_cache()
         out["assembled"] = assembled_section(prob, bem, vectors, torch, autotune=not args.no_autotune,
                                              solves=not args.assembled_kernels_only)
     extras = [e for e in args.extra.split(",") if e]
     if extras:
         os.environ.setdefault("BEM_PROGRESS", "50")   # solver progress lines on stderr
-        del P
+        P = None
         torch.cuda.empty_cache()
     for e in extras:
         log(f"extra workload {e}")
@@ -209,6 +211,36 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out))
+
+
+def single_layer_section(P, prob, torch, steps, warmup):
+    """The single-layer operator alone, y = V_k0 x on the sphere (exterior pass
+    only, M^2 pairs): the one-channel pair kernel, about 21 FLOP and three
+    transcendentals per pair, for comparison with the fused multitrace kernel."""
+    from bem_inputs import vectors
+    nv = sum(d.n_vertices for d in prob.domains)
+    x = torch.from_numpy(vectors.random_complex(nv, seed=3)).cuda()
+    y = torch.empty_like(x)
+    for _ in range(max(1, warmup)):
+        P.apply_single_layer(x, out=y)
+    torch.cuda.synchronize()
+    step_ms, pair_ms = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        P.apply_single_layer(x, out=y)
+        tm = P.timings()
+        step_ms.append(tm[0])
+        pair_ms.append(tm[1])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pairs = float(prob.n_points) ** 2
+    k_ms = float(np.mean(pair_ms))
+    achieved = FLOP_PER_PAIR_V * pairs / (k_ms * 1e-3) / 1e12
+    return {"pairs_per_apply": pairs, "value": pairs * steps / wall, "unit": "quad-pair interactions/s",
+            "apply_ms_p50": float(np.percentile(step_ms, 50)), "apply_ms_p99": float(np.percentile(step_ms, 99)),
+            "kernel": "k_pairs_v", "kernel_ms": k_ms, "kernel_pairs_per_s": pairs / (k_ms * 1e-3),
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / FP32_PEAK_TFLOPS, "flop_per_pair": FLOP_PER_PAIR_V}}
 
 
 def log(msg):

@@ -153,6 +153,17 @@ bem_status bem_assemble(const bem_domain *domains, int32_t n_domains, bem_comple
  * with device pointers the call returns after enqueueing the work. */
 bem_status bem_apply(bem_problem *p, const bem_complex *x, bem_complex *y, int32_t n_rhs);
 
+/* The single-layer operator alone (paper, Appendix A: V phi(x) = int G(x, y)
+ * phi(y) ds_y, G = exp(i k0 |x - y|)/(4 pi |x - y|)), Galerkin P1 on the union
+ * of all boundaries at the exterior wavenumber k0:
+ *   y_i = sum_j <phi_i, V_k0 phi_j> x_j,
+ * with the 6-point far rule on FP32 pairs plus the FP64 Sauter-Schwab
+ * correction of touching pairs (the exterior V_k0 blocks of the PMCHWT matrix).
+ * x, y: [n_rhs][total vertices], vertices in domain order (host or device per
+ * BEM_DEVICE_PTRS).  The V-only correction is computed on the first call.
+ * Available in every mode (it runs on the far-field pair path). */
+bem_status bem_apply_single_layer(bem_problem *p, const bem_complex *x, bem_complex *y, int32_t n_rhs);
+
 /* bem_apply restricted to parts of the operator (parts: 1 = far field
  * (regular rule on every pair), 2 = singular correction; 3 = both). */
 bem_status bem_apply_parts(bem_problem *p, const bem_complex *x, bem_complex *y, int32_t n_rhs, int parts);
@@ -199,7 +210,7 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
  * permutation of the unknowns to [u_N; u_D] folded in: the Lambda_DtN result
  * is returned in the u_N positions and the Lambda_NtD result in the u_D
  * positions (GMRES on P A u = P b).  Inner sparse solves by COCG in FP64 to
- * 1e-10. */
+ * the relative residual opts->osrc_tol, or 1e-10 when it is 0. */
 bem_status bem_apply_preconditioner(bem_problem *p, const bem_solve_opts *opts, const bem_complex *y,
                                     bem_complex *out, int32_t n_rhs);
 
@@ -207,7 +218,11 @@ bem_status bem_apply_preconditioner(bem_problem *p, const bem_solve_opts *opts, 
  * exterior p = p_inc + sum_j [DL_k0 u_D^j - SL_k0 u_N^j]; inside domain j
  * p = SL_kj((rho_j/rho_0) u_N^j) - DL_kj u_D^j.  points [n_points][3] (host
  * or device per flag); field [n_fields][n_points]; region [n_points]
- * (0 exterior, j >= 1 domain j).  inc may be NULL (no incident term). */
+ * (0 exterior, j >= 1 domain j from the solid-angle winding number, -1 for
+ * points closer than 2 h_j to the boundary of some domain j, h_j the mean edge
+ * length of its mesh: the 6-point rule is not accurate there; their field is
+ * still computed, in the region the winding number gives).  inc may be NULL
+ * (no incident term). */
 bem_status bem_evaluate_field(bem_problem *p, const bem_complex *u, const bem_incident *inc,
                               const double *points, int64_t n_points,
                               bem_complex *field, int32_t *region);

@@ -150,6 +150,21 @@ def operators(mesh, kappa, ss_n=6):
     return operator_rows(mesh, mesh, True, kappa, None, ss_n)
 
 
+def single_layer_matrix(problem, ss_n=6):
+    """Galerkin single-layer matrix at k0 on the union of all boundaries
+    (Appendix A, single-layer operator): block (i, j) is V_k0 with test
+    functions on boundary i and trial functions on boundary j (singular rules
+    only within one boundary).  Vertices in domain order."""
+    meshes = [(d.vertices, d.triangles) for d in problem.domains]
+    nv = [d.n_vertices for d in problem.domains]
+    off = np.concatenate([[0], np.cumsum(nv)])
+    V = np.zeros((off[-1], off[-1]), dtype=np.complex128)
+    for i, mi in enumerate(meshes):
+        for j, mj in enumerate(meshes):
+            V[off[i]:off[i + 1], off[j]:off[j + 1]] = operator_rows(mi, mj, i == j, problem.k0, None, ss_n)[0]
+    return V
+
+
 def mass_matrix(v, t):
     """P1 mass matrix: M^T_ab = |T| (1 + delta_ab) / 12 (dense)."""
     v = np.asarray(v, dtype=np.float64)
@@ -431,12 +446,61 @@ def winding(mesh, points):
     return out
 
 
+def mean_edge(v, t):
+    """Mean edge length h of a triangle mesh, every edge counted from both of its
+    triangles (each triangle's three sides averaged over the mesh)."""
+    v = np.asarray(v, dtype=np.float64)
+    t = np.asarray(t)
+    sides = [np.linalg.norm(v[t[:, (e + 1) % 3]] - v[t[:, e]], axis=1) for e in range(3)]
+    return float(np.mean(np.concatenate(sides)))
+
+
+def triangle_distance(v, t, x):
+    """Distance from the point x to each triangle of (v, t).
+
+    The nearest point of triangle (A, B, C) is A + s (B - A) + r (C - A) with
+    (s, r) minimising the squared distance over s, r >= 0, s + r <= 1: the free
+    minimiser (normal equations of the 2 x 2 least-squares problem) if it lies
+    in that set, else the best point of the three sides, each a clamped 1-D
+    minimisation.
+    """
+    v = np.asarray(v, dtype=np.float64)
+    A, B, C = v[t[:, 0]], v[t[:, 1]], v[t[:, 2]]
+    x = np.asarray(x, dtype=np.float64)
+    e1, e2, d = B - A, C - A, x - A
+    g11, g12, g22 = (e1 * e1).sum(1), (e1 * e2).sum(1), (e2 * e2).sum(1)
+    r1, r2 = (e1 * d).sum(1), (e2 * d).sum(1)
+    det = g11 * g22 - g12 * g12
+    s = (g22 * r1 - g12 * r2) / det
+    r = (g11 * r2 - g12 * r1) / det
+    free = (s >= 0) & (r >= 0) & (s + r <= 1)
+    p_free = A + s[:, None] * e1 + r[:, None] * e2
+
+    def side(P, Q):
+        u = Q - P
+        tt = np.clip(((x - P) * u).sum(1) / (u * u).sum(1), 0.0, 1.0)
+        return np.linalg.norm(P + tt[:, None] * u - x, axis=1)
+
+    best_side = np.minimum(np.minimum(side(A, B), side(B, C)), side(C, A))
+    return np.where(free, np.linalg.norm(p_free - x, axis=1), best_side)
+
+
+def near_surface(mesh, points, factor=2.0):
+    """True where a point is closer than factor * h to the surface (h = mean edge)."""
+    v, t = np.asarray(mesh[0], dtype=np.float64), np.asarray(mesh[1])
+    h = mean_edge(v, t)
+    pts = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    return np.array([triangle_distance(v, t, x).min() < factor * h for x in pts], dtype=bool)
+
+
 def field(problem, u, points, p_inc=None):
     """Total pressure at points from the boundary traces u = gamma^+ p_tot.
 
     Exterior: p = p_inc + sum_j [DL_k0 u_D^j - SL_k0 u_N^j]; inside domain j:
     p = SL_kj((rho_j/rho_0) u_N^j) - DL_kj u_D^j.  Region from the winding
-    number (0 = exterior, j = domain j).
+    number (0 = exterior, j = domain j); the returned code is -1 for points
+    closer than 2 h_j to boundary j (h_j its mean edge length), where the
+    6-point rule is inaccurate; their field still uses the winding region.
     """
     pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
     off = offsets(problem)
@@ -458,7 +522,10 @@ def field(problem, u, points, p_inc=None):
         if inside.any():
             sl, dl = potentials(m, d.k, uD, (d.rho / problem.rho0) * uN, pts[inside])
             p[inside] += sl - dl
-    return p, region
+    flagged = region.copy()
+    for d in problem.domains:
+        flagged[near_surface((d.vertices, d.triangles), pts)] = -1
+    return p, flagged
 
 
 def piston_sources(k0, centres, normals, radius, amplitudes):

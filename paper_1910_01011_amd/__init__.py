@@ -79,6 +79,7 @@ _L.bem_assemble.argtypes = [ctypes.POINTER(bem_domain), ctypes.c_int32, bem_comp
 _L.bem_apply.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
 _L.bem_apply_parts.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int]
 _L.bem_apply_with.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int]
+_L.bem_apply_single_layer.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
 _L.bem_rhs.argtypes = [_vp, ctypes.POINTER(bem_incident), _vp]
 _L.bem_solve.argtypes = [_vp, ctypes.POINTER(bem_incident), ctypes.POINTER(bem_solve_opts), _vp,
                          ctypes.POINTER(bem_solve_info)]
@@ -95,12 +96,12 @@ _L.bem_pair_launch_shape.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32)]
 _L.bem_destroy.argtypes = [_vp]
 _L.bem_destroy.restype = None
 _L.bem_last_error.restype = ctypes.c_char_p
-for _f in ("bem_assemble", "bem_apply", "bem_apply_parts", "bem_apply_with", "bem_rhs", "bem_solve", "bem_solve_rhs",
+for _f in ("bem_assemble", "bem_apply", "bem_apply_parts", "bem_apply_with", "bem_apply_single_layer", "bem_rhs", "bem_solve", "bem_solve_rhs",
            "bem_apply_preconditioner", "bem_pair_launch_shape",
            "bem_evaluate_field", "bem_footprint_bytes", "bem_last_timings"):
     getattr(_L, _f).restype = ctypes.c_int
 
-EXPORTED = ["bem_assemble", "bem_apply", "bem_apply_parts", "bem_apply_with", "bem_rhs", "bem_solve", "bem_solve_rhs",
+EXPORTED = ["bem_assemble", "bem_apply", "bem_apply_parts", "bem_apply_with", "bem_apply_single_layer", "bem_rhs", "bem_solve", "bem_solve_rhs",
             "bem_apply_preconditioner", "bem_pair_launch_shape",
             "bem_evaluate_field", "bem_num_unknowns", "bem_footprint_bytes", "bem_last_timings",
             "bem_destroy", "bem_last_error"]
@@ -262,6 +263,28 @@ class Problem:
             _check(_L.bem_apply_parts(self._h, xp, yp, n_rhs, parts))
         else:
             _check(_L.bem_apply_with(self._h, xp, yp, n_rhs, kernel))
+        return y
+
+    def apply_single_layer(self, x, out=None):
+        """y = V_k0 x (Galerkin single-layer matrix on the union of all boundaries);
+        x has one value per vertex (domain order), rows = right-hand sides."""
+        nv = self.n // 2
+        if self.device:
+            import torch
+            if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.complex128 and x.is_contiguous()):
+                raise TypeError("device problems take contiguous complex128 CUDA tensors")
+            n_rhs = 1 if x.dim() == 1 else x.shape[0]
+            if x.numel() != n_rhs * nv:
+                raise ValueError(f"expected {nv} vertex values per right-hand side, got shape {tuple(x.shape)}")
+            y = torch.empty_like(x) if out is None else out
+            _check(_L.bem_apply_single_layer(self._h, x.data_ptr(), y.data_ptr(), n_rhs))
+            return y
+        x = np.ascontiguousarray(x, dtype=np.complex128)
+        n_rhs = 1 if x.ndim == 1 else x.shape[0]
+        if x.size != n_rhs * nv:
+            raise ValueError(f"expected {nv} vertex values per right-hand side, got shape {x.shape}")
+        y = np.empty_like(x)
+        _check(_L.bem_apply_single_layer(self._h, x.ctypes.data, y.ctypes.data, n_rhs))
         return y
 
     def rhs(self, incident):

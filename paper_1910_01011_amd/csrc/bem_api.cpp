@@ -54,7 +54,8 @@ void free_problem(bem_problem *p)
     void *ptrs[] = {p->d_verts, p->d_tris, p->d_rowD, p->d_rowN, p->d_area, p->d_normal, p->d_curl, p->d_pts,
                     p->d_tnrm, p->d_v2t_ptr, p->d_v2t, p->d_pass, p->d_work, p->d_trial, p->d_part, p->d_pot,
                     p->d_cptr, p->d_ccol, p->d_cval, p->d_x, p->d_y, p->d_A, p->d_Ahi, p->d_Alo,
-                    p->d_gx, p->d_gc, p->d_aptr, p->d_acol, p->d_Mv, p->d_Sv, p->d_adiag, p->d_drange};
+                    p->d_gx, p->d_gc, p->d_aptr, p->d_acol, p->d_Mv, p->d_Sv, p->d_adiag, p->d_drange,
+                    p->d_sl_cptr, p->d_sl_ccol, p->d_sl_cval};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (auto &e : p->ev)
@@ -433,7 +434,7 @@ bem_status bem_assemble(const bem_domain *domains, int32_t n_domains, bem_comple
         // singular correction
         std::vector<bem::SingularItem> items;
         bem::touching_pairs(*p, items);
-        bem::run_singular(*p, items);
+        bem::run_singular(*p, items, &p->d_cptr, &p->d_ccol, &p->d_cval, &p->nnz);
         if (p->mode != BEM_OTF) {
             dev_alloc(&p->d_A, size_t(p->N) * size_t(p->N));
             bem::launch_assemble_dense(*p);
@@ -472,6 +473,43 @@ bem_status bem_apply_parts(bem_problem *p, const bem_complex *x, bem_complex *y,
             ensure_scratch(*p, n_rhs);
             BEM_HIP(hipMemcpyAsync(p->d_x, x, bytes, hipMemcpyHostToDevice, p->stream));
             apply_device(*p, p->d_x, p->d_y, n_rhs, parts);
+            BEM_HIP(hipMemcpyAsync(y, p->d_y, bytes, hipMemcpyDeviceToHost, p->stream));
+            BEM_HIP(hipStreamSynchronize(p->stream));
+        }
+        return BEM_OK;
+    });
+}
+
+bem_status bem_apply_single_layer(bem_problem *p, const bem_complex *x, bem_complex *y, int32_t n_rhs)
+{
+    if (!p || !x || !y || n_rhs < 0) return fail(BEM_ERR_INVALID_ARG, "bem_apply_single_layer: bad arguments");
+    if (n_rhs == 0) return BEM_OK;
+    return guarded([&]() -> bem_status {
+        BEM_HIP(hipSetDevice(p->device));
+        if (!p->sl_ready) {
+            // V correction of the exterior pass: its touching pairs, V block only
+            std::vector<bem::SingularItem> items, ext;
+            bem::touching_pairs(*p, items);
+            for (const auto &it : items)
+                if (it.pass == 0) ext.push_back(it);
+            bem::run_singular(*p, ext, &p->d_sl_cptr, &p->d_sl_ccol, &p->d_sl_cval, &p->sl_nnz);
+            p->sl_ready = true;
+        }
+        const int64_t nv = p->NV;
+        const size_t bytes = size_t(n_rhs) * nv * sizeof(double2);
+        const double2 *dx = reinterpret_cast<const double2 *>(x);
+        double2 *dy = reinterpret_cast<double2 *>(y);
+        if (!(p->flags & BEM_DEVICE_PTRS)) {
+            for (int64_t i = 0; i < int64_t(n_rhs) * nv; ++i)
+                if (!finite_c(x[i])) return fail(BEM_ERR_INVALID_ARG, "bem_apply_single_layer: non-finite input");
+            ensure_scratch(*p, n_rhs);   // N = 2 NV per right-hand side: room for NV
+            BEM_HIP(hipMemcpyAsync(p->d_x, x, bytes, hipMemcpyHostToDevice, p->stream));
+            dx = p->d_x;
+            dy = p->d_y;
+        }
+        for (int r = 0; r < n_rhs; ++r)
+            bem::launch_single_layer(*p, dx + int64_t(r) * nv, dy + int64_t(r) * nv, r == n_rhs - 1);
+        if (!(p->flags & BEM_DEVICE_PTRS)) {
             BEM_HIP(hipMemcpyAsync(y, p->d_y, bytes, hipMemcpyDeviceToHost, p->stream));
             BEM_HIP(hipStreamSynchronize(p->stream));
         }

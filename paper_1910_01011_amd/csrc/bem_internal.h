@@ -145,6 +145,11 @@ struct bem_problem {
     int32_t *d_cptr = nullptr, *d_ccol = nullptr;
     double2 *d_cval = nullptr;      // [nnz][4]
     int64_t nnz = 0;
+    // the same for the single-layer operator alone (pass 0 only; built on first use)
+    int32_t *d_sl_cptr = nullptr, *d_sl_ccol = nullptr;
+    double2 *d_sl_cval = nullptr;   // [nnz][4], block 1 = V
+    int64_t sl_nnz = 0;
+    bool sl_ready = false;
 
     // assembled mode: dense complex64 matrix, row-major [N][N]; BF16 planes
     // of its real view [N][2N] (hi and lo) for the split-BF16 GEMM
@@ -226,7 +231,12 @@ inline unsigned blocks_1d(int64_t items, int block, bool capped = false)
 int tune_pairs(bem_problem &p, void (*rebuild)(bem_problem &), int max_split);
 int tune_gemm_slices(bem_problem &p, int R, bool bf16, void *xbuf, float *cbuf, double2 *Y);
 int cached_gemm_slices(bem_problem &p, int R, bool bf16);   // 0 when the bucket is untuned
-void run_singular(bem_problem &p, const std::vector<SingularItem> &items);
+// Singular correction of the given touching pairs into a vertex-level CSR with
+// 4 complex blocks per entry (device arrays allocated here).
+void run_singular(bem_problem &p, const std::vector<SingularItem> &items, int32_t **cptr, int32_t **ccol,
+                  double2 **cval, int64_t *nnz);
+// y = V_k0 x on the union of all boundaries (k_single_layer.hip); events as in the apply
+void launch_single_layer(bem_problem &p, const double2 *x, double2 *y, bool record);
 
 // FP64 complex vector helpers for GMRES (k_linalg.hip)
 void zdot_multi(hipStream_t s, const double2 *V, int64_t ld, int nvec, const double2 *w, int64_t n,

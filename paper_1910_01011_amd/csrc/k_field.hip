@@ -11,6 +11,8 @@
 // Field (eq. rep_formula_gen): exterior p = p_inc + sum_j [DL_k0 u_D - SL_k0 u_N],
 // inside domain j p = SL_kj((rho_j/rho_0) u_N) - DL_kj u_D, 6-point rule on the
 // sources; the region comes from the solid-angle winding number of each domain.
+// Points closer than 2 h_j to boundary j (h_j its mean edge length) are flagged
+// with region -1; their field is still computed, with the winding-number region.
 #include <cmath>
 #include <vector>
 
@@ -194,7 +196,39 @@ void launch_rhs(bem_problem &p, const bem_incident &inc, double2 *b)
 struct DomDev {
     long long v_off, t_off, nt, nv;
     double kre, kim, rho;
+    double h;   // mean edge length of the boundary mesh
 };
+
+// squared distance from the origin to the triangle (a, b, c): the foot of the
+// perpendicular if it falls inside (same side of all three edges as the
+// normal), else the nearest point of the three edges
+__device__ double seg_dist2(const double *p, const double *q)
+{
+    const double d[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
+    const double dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    const double t = fmin(1.0, fmax(0.0, -(p[0] * d[0] + p[1] * d[1] + p[2] * d[2]) / dd));
+    const double v[3] = {p[0] + t * d[0], p[1] + t * d[1], p[2] + t * d[2]};
+    return v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+}
+
+__device__ double tri_dist2(const double *a, const double *b, const double *c)
+{
+    const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    const double nn = n[0] * n[0] + n[1] * n[1] + n[2] * n[2];
+    const double s = (n[0] * a[0] + n[1] * a[1] + n[2] * a[2]) / nn;
+    const double f[3] = {s * n[0], s * n[1], s * n[2]};   // foot of the perpendicular
+    const double *v[3] = {a, b, c};
+    bool inside = true;
+    for (int e = 0; e < 3; ++e) {
+        const double *p = v[e], *q = v[(e + 1) % 3];
+        const double u[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]}, w[3] = {f[0] - p[0], f[1] - p[1], f[2] - p[2]};
+        const double cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+        if (cr[0] * n[0] + cr[1] * n[1] + cr[2] * n[2] < 0.0) inside = false;
+    }
+    if (inside) return f[0] * f[0] + f[1] * f[1] + f[2] * f[2];
+    return fmin(seg_dist2(a, b), fmin(seg_dist2(b, c), seg_dist2(c, a)));
+}
 
 // one thread per point: region by winding numbers, then the potentials (all fields)
 __global__ void k_field(IncDev I, int has_inc, const DomDev *__restrict__ doms, int n_dom, double k0re, double k0im,
@@ -208,8 +242,10 @@ __global__ void k_field(IncDev I, int has_inc, const DomDev *__restrict__ doms, 
     if (ip >= np) return;
     const double x[3] = {pts[3 * ip], pts[3 * ip + 1], pts[3 * ip + 2]};
     int reg = 0;
+    bool near = false;
     for (int j = 0; j < n_dom; ++j) {
         double s = 0.0;
+        const double h2 = 2.0 * doms[j].h;
         for (long long t = doms[j].t_off; t < doms[j].t_off + doms[j].nt; ++t) {
             double a[3], b[3], c[3];
             for (int d = 0; d < 3; ++d) {
@@ -225,10 +261,20 @@ __global__ void k_field(IncDev I, int has_inc, const DomDev *__restrict__ doms, 
             const double den = la * lb * lc + (a[0] * b[0] + a[1] * b[1] + a[2] * b[2]) * lc +
                                (a[0] * c[0] + a[1] * c[1] + a[2] * c[2]) * lb + (b[0] * c[0] + b[1] * c[1] + b[2] * c[2]) * la;
             s += 2.0 * atan2(num, den);
+            // within 2 h: every point of the triangle is within its longest
+            // edge of each vertex, so the exact distance is needed only when
+            // the nearest vertex is closer than 2 h + that edge
+            if (!near) {
+                const double e0 = (b[0] - a[0]) * (b[0] - a[0]) + (b[1] - a[1]) * (b[1] - a[1]) + (b[2] - a[2]) * (b[2] - a[2]);
+                const double e1 = (c[0] - b[0]) * (c[0] - b[0]) + (c[1] - b[1]) * (c[1] - b[1]) + (c[2] - b[2]) * (c[2] - b[2]);
+                const double e2 = (a[0] - c[0]) * (a[0] - c[0]) + (a[1] - c[1]) * (a[1] - c[1]) + (a[2] - c[2]) * (a[2] - c[2]);
+                if (fmin(la, fmin(lb, lc)) < h2 + sqrt(fmax(e0, fmax(e1, e2))) && tri_dist2(a, b, c) < h2 * h2)
+                    near = true;
+            }
         }
         if (rint(s / (4.0 * PI_D)) == 1.0) reg = j + 1;
     }
-    region[ip] = reg;
+    region[ip] = near ? -1 : reg;
     const int j0 = reg == 0 ? 0 : reg - 1, j1 = reg == 0 ? n_dom : reg;
     const double kre = reg == 0 ? k0re : doms[reg - 1].kre, kim = reg == 0 ? k0im : doms[reg - 1].kim;
     const double sN = reg == 0 ? -1.0 : doms[reg - 1].rho / rho0;   // coefficient of SL u_N
@@ -286,7 +332,18 @@ void launch_field(bem_problem &p, const double2 *u, const bem_incident *inc, int
     IncDev I{};
     if (inc) I = upload_incident(p, *inc, &d_params);
     std::vector<DomDev> hd;
-    for (const auto &d : p.doms) hd.push_back(DomDev{d.v_off, d.t_off, d.nt, d.nv, d.kre, d.kim, d.rho});
+    for (const auto &d : p.doms) {
+        // mean edge length (every edge counted from both of its triangles)
+        double sum = 0.0;
+        for (int64_t t = d.t_off; t < d.t_off + d.nt; ++t)
+            for (int e = 0; e < 3; ++e) {
+                const double *P = &p.h_verts[3 * size_t(p.h_tris[3 * t + e])];
+                const double *Q = &p.h_verts[3 * size_t(p.h_tris[3 * t + (e + 1) % 3])];
+                sum += std::sqrt((P[0] - Q[0]) * (P[0] - Q[0]) + (P[1] - Q[1]) * (P[1] - Q[1]) +
+                                 (P[2] - Q[2]) * (P[2] - Q[2]));
+            }
+        hd.push_back(DomDev{d.v_off, d.t_off, d.nt, d.nv, d.kre, d.kim, d.rho, sum / double(3 * d.nt)});
+    }
     DomDev *d_doms = nullptr;
     BEM_HIP(hipMalloc(&d_doms, hd.size() * sizeof(DomDev)));
     BEM_HIP(hipMemcpyAsync(d_doms, hd.data(), hd.size() * sizeof(DomDev), hipMemcpyHostToDevice, p.stream));

@@ -182,14 +182,16 @@ static T *dev_upload(const std::vector<T> &h, hipStream_t s)
     return d;
 }
 
-void run_singular(bem_problem &p, const std::vector<SingularItem> &items)
+void run_singular(bem_problem &p, const std::vector<SingularItem> &items, int32_t **d_cptr, int32_t **d_ccol,
+                  double2 **d_cval, int64_t *nnz_out)
 {
     std::vector<int32_t> cptr, ccol, contrib_ptr, contrib_idx;
     correction_pattern(p, items, cptr, ccol, contrib_ptr, contrib_idx);
-    p.nnz = cptr[p.NV];
-    p.d_cptr = dev_upload(cptr, p.stream);
-    p.d_ccol = dev_upload(ccol, p.stream);
-    BEM_HIP(hipMalloc(&p.d_cval, std::max<int64_t>(1, 4 * p.nnz) * sizeof(double2)));
+    const int64_t nnz = cptr[p.NV];
+    *nnz_out = nnz;
+    *d_cptr = dev_upload(cptr, p.stream);
+    *d_ccol = dev_upload(ccol, p.stream);
+    BEM_HIP(hipMalloc(d_cval, std::max<int64_t>(1, 4 * nnz) * sizeof(double2)));
 
     const std::vector<double> rc = singular_rule(COINCIDENT, p.ss_order);
     const std::vector<double> re = singular_rule(EDGE, p.ss_order);
@@ -208,10 +210,9 @@ void run_singular(bem_problem &p, const std::vector<SingularItem> &items)
             p.d_verts, p.d_tris, p.d_area, p.d_normal, p.d_curl, d_elem);
         BEM_HIP(hipGetLastError());
     }
-    if (p.nnz > 0) {
+    if (nnz > 0) {
         const int B = 256;
-        k_correction_sum<<<dim3(blocks_1d(p.nnz, B)), dim3(B), 0, p.stream>>>(d_elem, d_cp, d_ci, p.nnz,
-                                                                                       p.d_cval);
+        k_correction_sum<<<dim3(blocks_1d(nnz, B)), dim3(B), 0, p.stream>>>(d_elem, d_cp, d_ci, nnz, *d_cval);
         BEM_HIP(hipGetLastError());
     }
     BEM_HIP(hipStreamSynchronize(p.stream));

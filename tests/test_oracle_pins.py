@@ -180,6 +180,48 @@ def test_mass_and_stiffness_closed_forms():
     assert np.abs((Sb @ f)[interior]).max() < 1e-12
 
 
+def test_triangle_distance_closed_forms():
+    """Foot of the perpendicular inside, vertex region, edge region."""
+    v = np.array([[0.0, 0.0, 0.0], [2.0, 0.0, 0.0], [0.0, 1.0, 0.0]])
+    t = np.array([[0, 1, 2]])
+    assert np.isclose(oracle.triangle_distance(v, t, [0.3, 0.2, -0.7])[0], 0.7, rtol=0, atol=1e-15)
+    # beyond vertex (2, 0, 0): nearest point is the vertex
+    assert np.isclose(oracle.triangle_distance(v, t, [3.0, -1.0, 0.5])[0], np.sqrt(1 + 1 + 0.25), atol=1e-15)
+    # beyond the hypotenuse x + 2y = 2 at its midpoint (1, 0.5): distance to that line
+    n = np.array([1.0, 2.0, 0.0]) / np.sqrt(5.0)
+    x = np.array([1.0, 0.5, 0.0]) + 0.4 * n + np.array([0, 0, 0.3])
+    assert np.isclose(oracle.triangle_distance(v, t, x)[0], 0.5, atol=1e-14)
+
+
+def test_triangle_distance_against_sampling():
+    """Brute force: the minimum over a dense barycentric grid is never below the
+    exact distance and exceeds it by at most the grid spacing."""
+    rng = np.random.default_rng(7)
+    for _ in range(5):
+        v = rng.standard_normal((3, 3))
+        t = np.array([[0, 1, 2]])
+        n = 300
+        a, b = np.meshgrid(np.linspace(0, 1, n + 1), np.linspace(0, 1, n + 1), indexing="ij")
+        keep = a + b <= 1 + 1e-12
+        P = v[0] + a[keep, None] * (v[1] - v[0]) + b[keep, None] * (v[2] - v[0])
+        step = max(np.linalg.norm(v[1] - v[0]), np.linalg.norm(v[2] - v[0])) / n
+        for x in rng.standard_normal((8, 3)) * 1.5:
+            d = oracle.triangle_distance(v, t, x)[0]
+            brute = np.linalg.norm(P - x, axis=1).min()
+            assert d <= brute + 1e-12
+            assert brute - d <= step
+
+
+def test_near_surface_band_on_a_sphere():
+    v, t = meshes.icosphere(3, 1.0)
+    h = oracle.mean_edge(v, t)
+    rng = np.random.default_rng(3)
+    d = rng.standard_normal((40, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    for r, flagged in ((1.0 - 3 * h, False), (1.0 - h, True), (1.0 + h, True), (1.0 + 3 * h, False)):
+        assert np.all(oracle.near_surface((v, t), r * d) == flagged), r
+
+
 def test_winding_number_inside_outside():
     v, t = meshes.capsule(0.9, 4.0, 0.5)
     pts = np.array([[0, 0, 0], [0, 1.5, 0.2], [2.0, 0, 0], [0, 2.5, 0], [0.5, 0.5, 0.5]])
@@ -334,7 +376,13 @@ def test_config1_field_matches_series(config1_solution):
     p_inc, _ = oracle.plane_wave(prob.k0)
     p, region = oracle.field(prob, u, pts, p_inc)
     ref = series.sphere_field(pts, 1.0, 2.0, 2.2, 1.0, 1.0)
-    assert np.array_equal(region, (np.linalg.norm(pts, axis=1) < 1.0).astype(np.int32))
+    # points within 2h of the polyhedron carry region -1 (h = 0.15 here)
+    r = np.linalg.norm(pts, axis=1)
+    h = oracle.mean_edge(prob.domains[0].vertices, prob.domains[0].triangles)
+    assert 0.14 < h < 0.16
+    clear = np.abs(r - 1.0) > 2 * h + 0.01
+    assert np.array_equal(region[clear], (r[clear] < 1.0).astype(np.int32))
+    assert np.all(region[np.abs(r - 1.0) < 2 * h - 0.01] == -1)
     err = np.linalg.norm(p - ref) / np.linalg.norm(ref)
     assert err < 0.02, err
 
@@ -346,6 +394,31 @@ def test_gmres_matches_lu(config1_solution):
     assert np.linalg.norm(x - u) / np.linalg.norm(u) < 1e-10
     # the recursive residual estimate agrees with the true residual
     assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) < 1e-11
+
+
+def test_union_single_layer_constant_density_closed_forms():
+    """1^T V 1 over one sphere of radius a is 4 pi a^3 j0(ka) e^{ika}, and over
+    two separated spheres (radii a, b, centres R apart) it is
+    (4 pi a^2)(4 pi b^2) j0(ka) j0(kb) e^{ikR} / (4 pi R) (the l = 0 term of
+    the addition theorem); the polyhedral meshes converge to both at O(h^2),
+    and the two cross blocks are transposes of each other."""
+    a, b, R, k = 0.5, 0.4, 3.0, 1.7
+    errs = []
+    for level in (1, 2):
+        v1, t1 = meshes.icosphere(level, a)
+        v2, t2 = meshes.icosphere(level, b, (R, 0.0, 0.0))
+        prob = configs.Problem([configs.Domain(v1, t1, 2.0 + 0j, 1.0), configs.Domain(v2, t2, 2.0 + 0j, 1.0)],
+                               complex(k), 1.0)
+        V = oracle.single_layer_matrix(prob)
+        n1 = v1.shape[0]
+        o1, o2 = np.ones(n1), np.ones(v2.shape[0])
+        j0a, j0b = np.sin(k * a) / (k * a), np.sin(k * b) / (k * b)
+        ref11 = 4 * np.pi * a ** 3 * j0a * np.exp(1j * k * a)
+        ref12 = (4 * np.pi * a * a) * (4 * np.pi * b * b) * j0a * j0b * np.exp(1j * k * R) / (4 * np.pi * R)
+        np.testing.assert_allclose(V[n1:, :n1], V[:n1, n1:].T, rtol=0, atol=1e-15)
+        errs.append((abs(o1 @ V[:n1, :n1] @ o1 / ref11 - 1), abs(o1 @ V[:n1, n1:] @ o2 / ref12 - 1)))
+    assert errs[1][0] < 0.04 and errs[1][1] < 0.04
+    assert errs[0][0] / errs[1][0] > 3 and errs[0][1] / errs[1][1] > 3
 
 
 def test_pmchwt_rows_match_dense_two_domains():
