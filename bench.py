@@ -82,7 +82,8 @@ def main():
                     help="comma list of extra workloads appended to the JSON line: ribcage (53.5k-vertex stack, "
                          "on the fly, pistons, OSRC), ribcage_assembled (26.9k vertices, 256 right-hand sides), "
                          "serving (kidney request stream), paper_sphere (the paper's 1 cm sphere at 1 MHz, fat and "
-                         "rib material, 4-10 elements per wavelength, OSRC GMRES)")
+                         "rib material, 4-10 elements per wavelength, OSRC GMRES), planning (full matrix capture "
+                         "of 256 pistons on the 13.5k-vertex stack, then phase conjugation and rib sparing)")
     ap.add_argument("--serving-requests", type=int, default=8, help="requests per arrival rate in --extra serving")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only a 1 GiB elementwise copy (the counter scale) and 3 applies, for HBM counters")
@@ -205,6 +206,8 @@ def main():
             out["serving"] = serving_section(bem, torch, args.serving_requests)
         elif e == "paper_sphere":
             out["paper_sphere"] = paper_sphere_section(bem, torch)
+        elif e == "planning":
+            out["planning"] = planning_section(bem, torch, not args.no_autotune)
         else:
             raise SystemExit(f"unknown extra workload {e}")
         torch.cuda.empty_cache()
@@ -338,6 +341,36 @@ def ribcage_assembled_section(bem, torch, autotune):
     log(f"solve plain fp32 (8 rhs): {t:.2f} s")
     P.close()
     return res
+
+
+def planning_section(bem, torch, autotune):
+    """Full matrix capture and excitation planning on the rib-cage stack at
+    h * 2 (13.5k vertices): 256 pistons solved as one block (assembled split
+    BF16, FGMRES to 1e-5), the total field of every element at the focus and at
+    20 points 0.5 below the four central ribs, then phase conjugation and the
+    sparing excitation (peak rib-side pressure at most 0.3 of the focal one)."""
+    from bem_inputs import configs, pistons
+    from paper_1910_01011_amd import planning
+    prob = configs.ribcage(2.0)
+    P, t_asm = _timed(torch, lambda: bem.Problem.from_config(prob, device=True, mode=bem.BEM_ASSEMBLED_SPLIT_BF16,
+                                                             autotune=autotune))
+    c, nn, a = pistons.bowl_array()
+    spare = np.array([[x, y, -5.4] for x in (-4.5, -1.5, 1.5, 4.5) for y in (-2.0, -1.0, 0.0, 1.0, 2.0)])
+    opts = bem.solve_options(tol=1e-5, restart=10, max_iter=8, precision=bem.BEM_PREC_SPLIT_BF16_FGMRES,
+                             inner_tol=1e-3, inner_restart=200, inner_max_iter=1500)
+    res = planning.plan(P, c, nn, a, np.zeros(3), spare, 0.3, opts)
+    P.close()
+    info = res["solve_info"]
+    out = {"vertices": sum(d.n_vertices for d in prob.domains), "unknowns": prob.n_unknowns, "elements": len(c),
+           "assembly_s": t_asm, "capture_s": res["capture_s"], "solve_s": res["solve_s"], "field_s": res["field_s"],
+           "optimise_s": res["optimise_s"],
+           "all_converged": all(i["converged"] for i in info),
+           "max_rel_residual": float(max(i["rel_residual"] for i in info)),
+           "phase_conjugation": {k: v for k, v in res["phase_conjugation"].items() if k != "a"},
+           "sparing": {k: v for k, v in res["sparing"].items() if k != "a"}}
+    log(f"planning: capture {res['capture_s']:.1f} s, ratio pc {out['phase_conjugation']['ratio']:.3f} "
+        f"sparing {out['sparing']['ratio']:.3f}")
+    return out
 
 
 def serving_section(bem, torch, n_requests):

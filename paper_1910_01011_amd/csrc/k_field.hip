@@ -13,6 +13,7 @@
 // sources; the region comes from the solid-angle winding number of each domain.
 // Points closer than 2 h_j to boundary j (h_j its mean edge length) are flagged
 // with region -1; their field is still computed, with the winding-number region.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -193,6 +194,9 @@ void launch_rhs(bem_problem &p, const bem_incident &inc, double2 *b)
     (void)hipFree(d_params);
 }
 
+constexpr int FIELD_DIRECT_MAX = 4;                   // more fields: rows + dense product
+constexpr int64_t FIELD_ROWS_BYTES = int64_t(512) << 20;   // row buffer of one chunk of points
+
 struct DomDev {
     long long v_off, t_off, nt, nv;
     double kre, kim, rho;
@@ -230,13 +234,11 @@ __device__ double tri_dist2(const double *a, const double *b, const double *c)
     return fmin(seg_dist2(a, b), fmin(seg_dist2(b, c), seg_dist2(c, a)));
 }
 
-// one thread per point: region by winding numbers, then the potentials (all fields)
-__global__ void k_field(IncDev I, int has_inc, const DomDev *__restrict__ doms, int n_dom, double k0re, double k0im,
-                        double rho0, const double *__restrict__ verts, const int32_t *__restrict__ tris,
-                        const double *__restrict__ area, const double *__restrict__ normal,
-                        const int32_t *__restrict__ rowD, const int32_t *__restrict__ rowN,
-                        const double2 *__restrict__ u, int64_t N, int n_fields, const double *__restrict__ pts,
-                        int64_t np, double2 *__restrict__ field, int32_t *__restrict__ region)
+// one thread per point: region by winding numbers (wreg) and the reported
+// region code (-1 within 2 h of a boundary)
+__global__ void k_region(const DomDev *__restrict__ doms, int n_dom, const double *__restrict__ verts,
+                         const int32_t *__restrict__ tris, const double *__restrict__ pts, int64_t np,
+                         int32_t *__restrict__ wreg, int32_t *__restrict__ region)
 {
     const int64_t ip = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (ip >= np) return;
@@ -274,7 +276,22 @@ __global__ void k_field(IncDev I, int has_inc, const DomDev *__restrict__ doms, 
         }
         if (rint(s / (4.0 * PI_D)) == 1.0) reg = j + 1;
     }
+    wreg[ip] = reg;
     region[ip] = near ? -1 : reg;
+}
+
+// one thread per point: the potentials of all fields in the winding region
+__global__ void k_field(IncDev I, int has_inc, const DomDev *__restrict__ doms, int n_dom, double k0re, double k0im,
+                        double rho0, const double *__restrict__ verts, const int32_t *__restrict__ tris,
+                        const double *__restrict__ area, const double *__restrict__ normal,
+                        const int32_t *__restrict__ rowD, const int32_t *__restrict__ rowN,
+                        const double2 *__restrict__ u, int64_t N, int n_fields, const double *__restrict__ pts,
+                        int64_t np, const int32_t *__restrict__ wreg, double2 *__restrict__ field)
+{
+    const int64_t ip = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (ip >= np) return;
+    const double x[3] = {pts[3 * ip], pts[3 * ip + 1], pts[3 * ip + 2]};
+    const int reg = wreg[ip];
     const int j0 = reg == 0 ? 0 : reg - 1, j1 = reg == 0 ? n_dom : reg;
     const double kre = reg == 0 ? k0re : doms[reg - 1].kre, kim = reg == 0 ? k0im : doms[reg - 1].kim;
     const double sN = reg == 0 ? -1.0 : doms[reg - 1].rho / rho0;   // coefficient of SL u_N
@@ -325,6 +342,110 @@ __global__ void k_field(IncDev I, int has_inc, const DomDev *__restrict__ doms, 
     }
 }
 
+// Many fields: the representation formula is linear in u, so for a chunk of
+// points the field of every field f is one row of a dense product,
+//   field[f][p] = sum_n R[p][n] u_f[n] (+ p_inc,f(x_p) outside),
+// R[p][rowD g] = sD sum_{(t,a) at g} sum_q |t| w_q lambda_a(q) dG/dn_y(x_p, y_q),
+// R[p][rowN g] = sN sum_{(t,a) at g} sum_q |t| w_q lambda_a(q) G(x_p, y_q),
+// with the wavenumber and signs of the point's winding region (zero for the
+// vertices of other domains when the point is inside a domain).  The kernel
+// values are then evaluated once per (point, source point) instead of once per
+// field.  One thread per (point, vertex).
+__global__ void k_field_rows(const DomDev *__restrict__ doms, int n_dom, double k0re, double k0im, double rho0,
+                             const double *__restrict__ verts, const int32_t *__restrict__ tris,
+                             const double *__restrict__ area, const double *__restrict__ normal,
+                             const int32_t *__restrict__ v2t_ptr, const int32_t *__restrict__ v2t,
+                             const int32_t *__restrict__ rowD, const int32_t *__restrict__ rowN, int64_t NV, int64_t N,
+                             const double *__restrict__ pts, const int32_t *__restrict__ wreg, int64_t p0, int64_t npc,
+                             double2 *__restrict__ R)
+{
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= npc * NV) return;
+    const int64_t pl = idx / NV, g = idx - pl * NV, ip = p0 + pl;
+    const int reg = wreg[ip];
+    int dom = 0;
+    for (int j = 0; j < n_dom; ++j)
+        if (g >= doms[j].v_off && g < doms[j].v_off + doms[j].nv) dom = j;
+    double2 *row = R + pl * N;
+    if (reg != 0 && dom != reg - 1) {
+        row[rowD[g]] = make_double2(0.0, 0.0);
+        row[rowN[g]] = make_double2(0.0, 0.0);
+        return;
+    }
+    const double kre = reg == 0 ? k0re : doms[reg - 1].kre, kim = reg == 0 ? k0im : doms[reg - 1].kim;
+    const double sN = reg == 0 ? -1.0 : doms[reg - 1].rho / rho0;
+    const double sD = reg == 0 ? 1.0 : -1.0;
+    const double x[3] = {pts[3 * ip], pts[3 * ip + 1], pts[3 * ip + 2]};
+    double dr = 0, di = 0, nr = 0, ni = 0;
+    for (int32_t k = v2t_ptr[g]; k < v2t_ptr[g + 1]; ++k) {
+        const int64_t t = v2t[k] / 3;
+        const int a = v2t[k] - 3 * int(t);
+        double P[3][3];
+        for (int c = 0; c < 3; ++c)
+            for (int d = 0; d < 3; ++d) P[c][d] = verts[3 * int64_t(tris[3 * t + c]) + d];
+        const double *n = normal + 3 * t;
+        for (int q = 0; q < 6; ++q) {
+            double y[3];
+            for (int d = 0; d < 3; ++d) y[d] = f_bary[q][0] * P[0][d] + f_bary[q][1] * P[1][d] + f_bary[q][2] * P[2][d];
+            const double ex = x[0] - y[0], ey = x[1] - y[1], ez = x[2] - y[2];
+            const double r = sqrt(ex * ex + ey * ey + ez * ez);
+            double sn, cs;
+            sincos(kre * r, &sn, &cs);
+            const double e = exp(-kim * r) / (4.0 * PI_D * r);
+            const double gr = e * cs, gi = e * sn;
+            const double a1 = 1.0 + kim * r, b1 = -kre * r, ir2 = 1.0 / (r * r);
+            const double dn = (ex * n[0] + ey * n[1] + ez * n[2]) * ir2;
+            const double fr = (gr * a1 - gi * b1) * dn, fi = (gr * b1 + gi * a1) * dn;   // dG/dn_y
+            const double w = area[t] * f_wq[q] * f_bary[q][a];
+            dr += w * fr; di += w * fi;
+            nr += w * gr; ni += w * gi;
+        }
+    }
+    row[rowD[g]] = make_double2(sD * dr, sD * di);
+    row[rowN[g]] = make_double2(sN * nr, sN * ni);
+}
+
+// field[f][p0 + pl] = sum_n u_f[n] R[pl][n] (+ incident outside): tiles of 16
+// fields x 16 points, K chunks of 32 through LDS, FP64 complex
+constexpr int FG_T = 16, FG_K = 32;
+__global__ __launch_bounds__(256) void k_field_gemm(const double2 *__restrict__ U, int64_t N, int n_fields,
+                                                    const double2 *__restrict__ R, int64_t p0, int64_t npc, int64_t np,
+                                                    const double *__restrict__ pts, const int32_t *__restrict__ wreg,
+                                                    IncDev I, int has_inc, double2 *__restrict__ field)
+{
+    __shared__ double2 sU[FG_T][FG_K + 1], sR[FG_T][FG_K + 1];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int64_t f0 = int64_t(blockIdx.y) * FG_T, l0 = int64_t(blockIdx.x) * FG_T;
+    double ar = 0, ai = 0;
+    for (int64_t k0 = 0; k0 < N; k0 += FG_K) {
+        for (int e = threadIdx.x; e < FG_T * FG_K; e += 256) {
+            const int r = e / FG_K, c = e - r * FG_K;
+            const int64_t n = k0 + c, f = f0 + r, l = l0 + r;
+            sU[r][c] = (f < n_fields && n < N) ? U[f * N + n] : make_double2(0.0, 0.0);
+            sR[r][c] = (l < npc && n < N) ? R[l * N + n] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int c = 0; c < FG_K; ++c) {
+            const double2 u = sU[ty][c], w = sR[tx][c];
+            ar += u.x * w.x - u.y * w.y;
+            ai += u.x * w.y + u.y * w.x;
+        }
+        __syncthreads();
+    }
+    const int64_t f = f0 + ty, l = l0 + tx;
+    if (f >= n_fields || l >= npc) return;
+    const int64_t ip = p0 + l;
+    if (has_inc && wreg[ip] == 0) {
+        const double x[3] = {pts[3 * ip], pts[3 * ip + 1], pts[3 * ip + 2]}, nz[3] = {0, 0, 1};
+        double pr, pim, qr, qi;
+        incident(I, int(f), x, nz, pr, pim, qr, qi);
+        ar += pr;
+        ai += pim;
+    }
+    field[f * np + ip] = make_double2(ar, ai);
+}
+
 void launch_field(bem_problem &p, const double2 *u, const bem_incident *inc, int n_fields, const double *pts,
                   int64_t np, double2 *field, int32_t *region)
 {
@@ -348,13 +469,38 @@ void launch_field(bem_problem &p, const double2 *u, const bem_incident *inc, int
     BEM_HIP(hipMalloc(&d_doms, hd.size() * sizeof(DomDev)));
     BEM_HIP(hipMemcpyAsync(d_doms, hd.data(), hd.size() * sizeof(DomDev), hipMemcpyHostToDevice, p.stream));
     const int B = 128;
+    int32_t *wreg = nullptr;
+    double2 *R = nullptr;
     if (np > 0) {
-        k_field<<<dim3(blocks_1d(np, B)), dim3(B), 0, p.stream>>>(
-            I, inc ? 1 : 0, d_doms, int(hd.size()), p.k0re, p.k0im, p.rho0, p.d_verts, p.d_tris, p.d_area, p.d_normal,
-            p.d_rowD, p.d_rowN, u, p.N, n_fields, pts, np, field, region);
+        BEM_HIP(hipMalloc(&wreg, size_t(np) * sizeof(int32_t)));
+        k_region<<<dim3(blocks_1d(np, B)), dim3(B), 0, p.stream>>>(d_doms, int(hd.size()), p.d_verts, p.d_tris, pts, np,
+                                                                   wreg, region);
         BEM_HIP(hipGetLastError());
+        if (n_fields <= FIELD_DIRECT_MAX) {
+            k_field<<<dim3(blocks_1d(np, B)), dim3(B), 0, p.stream>>>(
+                I, inc ? 1 : 0, d_doms, int(hd.size()), p.k0re, p.k0im, p.rho0, p.d_verts, p.d_tris, p.d_area,
+                p.d_normal, p.d_rowD, p.d_rowN, u, p.N, n_fields, pts, np, wreg, field);
+            BEM_HIP(hipGetLastError());
+        } else {
+            // points in chunks whose rows take at most FIELD_ROWS_BYTES
+            const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(np, FIELD_ROWS_BYTES / (16 * p.N)));
+            BEM_HIP(hipMalloc(&R, size_t(chunk) * p.N * sizeof(double2)));
+            for (int64_t p0 = 0; p0 < np; p0 += chunk) {
+                const int64_t npc = std::min(chunk, np - p0);
+                k_field_rows<<<dim3(blocks_1d(npc * p.NV, 256)), dim3(256), 0, p.stream>>>(
+                    d_doms, int(hd.size()), p.k0re, p.k0im, p.rho0, p.d_verts, p.d_tris, p.d_area, p.d_normal,
+                    p.d_v2t_ptr, p.d_v2t, p.d_rowD, p.d_rowN, p.NV, p.N, pts, wreg, p0, npc, R);
+                BEM_HIP(hipGetLastError());
+                const dim3 grid(unsigned((npc + FG_T - 1) / FG_T), unsigned((n_fields + FG_T - 1) / FG_T));
+                k_field_gemm<<<grid, dim3(256), 0, p.stream>>>(u, p.N, n_fields, R, p0, npc, np, pts, wreg, I,
+                                                               inc ? 1 : 0, field);
+                BEM_HIP(hipGetLastError());
+            }
+        }
     }
     BEM_HIP(hipStreamSynchronize(p.stream));
+    if (R) (void)hipFree(R);
+    if (wreg) (void)hipFree(wreg);
     (void)hipFree(d_doms);
     if (d_params) (void)hipFree(d_params);
 }
