@@ -530,6 +530,12 @@ def assembled_section(prob, bem, vectors, torch, autotune=True, solves=True):
             ms = float(np.median(ts))
             tf = fl * n * n * R / (ms * 1e-3) / 1e12
             res[f"gemm_{key}_R{R}"] = {"ms": ms, "TFLOPs": tf, "frac": tf / peak, "peak": peak}
+            if R == 64:
+                # one 128-column block of X': the matrix (BF16 hi/lo planes or the
+                # FP32 real view, 8 n^2 bytes either way) is streamed once, so
+                # this size is bound by HBM
+                gbs = 8.0 * n * n / (ms * 1e-3) / 1e9
+                res[f"gemm_{key}_R{R}"].update({"matrix_bytes": 8.0 * n * n, "GBps": gbs, "frac_hbm": gbs / HBM_PEAK_GBPS})
     if not solves:
         return res
     # time-to-solve at 1e-5 for one plane wave and for 64 plane waves

@@ -198,8 +198,11 @@ void launch_assemble_dense(bem_problem &p)
 
 // y = A x, complex64 matrix, FP64 vectors and FP64 accumulation.  One wave per
 // GEMV_ROWS rows; lanes stride over the columns two entries at a time (16-byte
-// loads of A), partial sums reduced across the wave in a fixed order.
-constexpr int GEMV_ROWS = 4;
+// loads of A), GEMV_UNROLL column strides loaded before they are used (16
+// loads of A in flight per lane), partial sums reduced across the wave in a
+// fixed order.  Eight rows per wave also halve the re-reads of x against four.
+constexpr int GEMV_ROWS = 8;
+constexpr int GEMV_UNROLL = 2;
 
 __global__ __launch_bounds__(256) void k_gemv(const float2 *__restrict__ A, const double2 *__restrict__ x, int64_t n,
                                               double2 *__restrict__ y)
@@ -209,27 +212,49 @@ __global__ __launch_bounds__(256) void k_gemv(const float2 *__restrict__ A, cons
     const int64_t r0 = wave * GEMV_ROWS;
     if (r0 >= n) return;
     double ar[GEMV_ROWS], ai[GEMV_ROWS];
+    const float2 *row[GEMV_ROWS];
 #pragma unroll
-    for (int k = 0; k < GEMV_ROWS; ++k) ar[k] = ai[k] = 0.0;
+    for (int k = 0; k < GEMV_ROWS; ++k) {
+        ar[k] = ai[k] = 0.0;
+        row[k] = A + (r0 + k < n ? r0 + k : n - 1) * n;   // rows past n repeat the last (not stored)
+    }
     const int64_t npair = n / 2;
-    for (int64_t c2 = lane; c2 < npair; c2 += 64) {
+    int64_t c2 = lane;
+    for (; c2 + 64 * (GEMV_UNROLL - 1) < npair; c2 += 64 * GEMV_UNROLL) {
+        float4 a[GEMV_UNROLL][GEMV_ROWS];
+        double2 x0[GEMV_UNROLL], x1[GEMV_UNROLL];
+#pragma unroll
+        for (int u = 0; u < GEMV_UNROLL; ++u) {
+#pragma unroll
+            for (int k = 0; k < GEMV_ROWS; ++k) a[u][k] = *reinterpret_cast<const float4 *>(row[k] + 2 * (c2 + 64 * u));
+            x0[u] = x[2 * (c2 + 64 * u)];
+            x1[u] = x[2 * (c2 + 64 * u) + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < GEMV_UNROLL; ++u)
+#pragma unroll
+            for (int k = 0; k < GEMV_ROWS; ++k) {
+                const float4 v = a[u][k];
+                ar[k] += double(v.x) * x0[u].x - double(v.y) * x0[u].y + double(v.z) * x1[u].x - double(v.w) * x1[u].y;
+                ai[k] += double(v.x) * x0[u].y + double(v.y) * x0[u].x + double(v.z) * x1[u].y + double(v.w) * x1[u].x;
+            }
+    }
+    for (; c2 < npair; c2 += 64) {
         const double2 x0 = x[2 * c2], x1 = x[2 * c2 + 1];
 #pragma unroll
         for (int k = 0; k < GEMV_ROWS; ++k) {
-            const int64_t r = r0 + k < n ? r0 + k : n - 1;
-            const float4 a = *reinterpret_cast<const float4 *>(A + r * n + 2 * c2);
-            ar[k] += double(a.x) * x0.x - double(a.y) * x0.y + double(a.z) * x1.x - double(a.w) * x1.y;
-            ai[k] += double(a.x) * x0.y + double(a.y) * x0.x + double(a.z) * x1.y + double(a.w) * x1.x;
+            const float4 v = *reinterpret_cast<const float4 *>(row[k] + 2 * c2);
+            ar[k] += double(v.x) * x0.x - double(v.y) * x0.y + double(v.z) * x1.x - double(v.w) * x1.y;
+            ai[k] += double(v.x) * x0.y + double(v.y) * x0.x + double(v.z) * x1.y + double(v.w) * x1.x;
         }
     }
     if ((n & 1) && lane == 0) {
         const double2 xl = x[n - 1];
 #pragma unroll
         for (int k = 0; k < GEMV_ROWS; ++k) {
-            const int64_t r = r0 + k < n ? r0 + k : n - 1;
-            const float2 a = A[r * n + n - 1];
-            ar[k] += double(a.x) * xl.x - double(a.y) * xl.y;
-            ai[k] += double(a.x) * xl.y + double(a.y) * xl.x;
+            const float2 v = row[k][n - 1];
+            ar[k] += double(v.x) * xl.x - double(v.y) * xl.y;
+            ai[k] += double(v.x) * xl.y + double(v.y) * xl.x;
         }
     }
 #pragma unroll
