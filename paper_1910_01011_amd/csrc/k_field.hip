@@ -15,6 +15,7 @@
 // with region -1; their field is still computed, with the winding-number region.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "bem_internal.h"
@@ -483,7 +484,12 @@ void launch_field(bem_problem &p, const double2 *u, const bem_incident *inc, int
             BEM_HIP(hipGetLastError());
         } else {
             // points in chunks whose rows take at most FIELD_ROWS_BYTES
-            const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(np, FIELD_ROWS_BYTES / (16 * p.N)));
+            // (BEM_FIELD_CHUNK_POINTS sets a smaller chunk, for tests of the chunk loop)
+            int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(np, FIELD_ROWS_BYTES / (16 * p.N)));
+            if (const char *e = std::getenv("BEM_FIELD_CHUNK_POINTS")) {
+                const long long c = std::atoll(e);
+                if (c > 0) chunk = std::min<int64_t>(chunk, c);
+            }
             BEM_HIP(hipMalloc(&R, size_t(chunk) * p.N * sizeof(double2)));
             for (int64_t p0 = 0; p0 < np; p0 += chunk) {
                 const int64_t npc = std::min(chunk, np - p0);

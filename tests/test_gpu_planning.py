@@ -85,3 +85,30 @@ def test_planning_transfer_matrix_matches_oracle():
     assert err <= 1e-6
     assert res["sparing"]["met"] and res["sparing"]["ratio"] <= 0.3 * (1 + 1e-9)
     assert np.isclose(np.max(np.abs(res["sparing"]["a"])), 1.0)
+
+
+def test_many_fields_in_point_chunks_and_empty_inputs(monkeypatch):
+    """The rows + product path over several ragged chunks of points (7 points
+    per chunk) gives the single-chunk result; zero points and zero right-hand
+    sides are accepted."""
+    import paper_1910_01011_amd as bem
+    prob = configs.two_spheres()
+    rng = np.random.default_rng(4)
+    U = rng.standard_normal((5, prob.n_unknowns)) + 1j * rng.standard_normal((5, prob.n_unknowns))
+    pts = _points() + np.array([0.2, 0.1, 0.0])
+    dirs = np.eye(3)[[0, 1, 2, 0, 1]]
+    P = bem.Problem.from_config(prob)
+    inc = bem.Incident.plane_waves(dirs)
+    f1, r1 = P.evaluate_field(U, pts, inc)
+    monkeypatch.setenv("BEM_FIELD_CHUNK_POINTS", "7")
+    f2, r2 = P.evaluate_field(U, pts, inc)
+    monkeypatch.delenv("BEM_FIELD_CHUNK_POINTS")
+    assert np.array_equal(r1, r2)
+    assert np.array_equal(f1, f2)
+    ref = np.array([oracle.field(prob, U[i], pts, oracle.plane_wave(prob.k0, dirs[i])[0])[0] for i in range(5)])
+    assert _relerr(f1, ref) <= 1e-10
+    f0, r0 = P.evaluate_field(U, np.zeros((0, 3)), inc)
+    assert f0.shape == (5, 0) and r0.shape == (0,)
+    y0 = P.apply_single_layer(np.zeros((0, prob.n_unknowns // 2), dtype=np.complex128))
+    assert y0.shape == (0, prob.n_unknowns // 2)
+    P.close()
