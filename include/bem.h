@@ -67,8 +67,9 @@ typedef struct {
 
 /* flags */
 #define BEM_DEVICE_PTRS 1u         /* vectors passed to apply/solve/rhs/evaluate are device pointers */
-#define BEM_AUTOTUNE 2u            /* time candidate launch shapes of the pair kernel at set-up and of the
-                                      GEMM at first use per right-hand-side bucket; cache the choice */
+#define BEM_AUTOTUNE 2u            /* time candidate launch shapes of the pair kernel at set-up, of the
+                                      single-layer pair kernel at its first use, and of the GEMM at first
+                                      use per right-hand-side bucket; cache the pair and GEMM choices */
 
 typedef struct {
     int mode;          /* BEM_OTF (default) or an assembled mode */

@@ -150,6 +150,7 @@ struct bem_problem {
     double2 *d_sl_cval = nullptr;   // [nnz][4], block 1 = V
     int64_t sl_nnz = 0;
     bool sl_ready = false;
+    int sl_tpl = 0, sl_split = 8;   // launch shape of the single-layer pair kernel (0: not chosen yet)
 
     // assembled mode: dense complex64 matrix, row-major [N][N]; BF16 planes
     // of its real view [N][2N] (hi and lo) for the split-BF16 GEMM

@@ -154,6 +154,18 @@ __global__ void k_rhs(IncDev I, const double *__restrict__ verts, const int32_t 
     b[int64_t(f) * N + rowN[g]] = make_double2(bNr, bNi);
 }
 
+// device scratch of one call, freed on every exit path (hipFree waits for the device)
+struct DevScratch {
+    void *p = nullptr;
+    DevScratch() = default;
+    DevScratch(const DevScratch &) = delete;
+    DevScratch &operator=(const DevScratch &) = delete;
+    ~DevScratch()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
 static IncDev upload_incident(bem_problem &p, const bem_incident &inc, double **d_params)
 {
     int64_t cols = inc.kind == BEM_PLANE_WAVE ? 5 : (inc.kind == BEM_POINT_SOURCES ? 6 : 10);
@@ -186,13 +198,14 @@ static IncDev upload_incident(bem_problem &p, const bem_incident &inc, double **
 void launch_rhs(bem_problem &p, const bem_incident &inc, double2 *b)
 {
     double *d_params = nullptr;
+    DevScratch params_mem;
     IncDev I = upload_incident(p, inc, &d_params);
+    params_mem.p = d_params;
     const int B = 128;
     k_rhs<<<dim3(blocks_1d(p.NV, B), unsigned(inc.n_fields)), dim3(B), 0, p.stream>>>(
         I, p.d_verts, p.d_tris, p.d_area, p.d_normal, p.d_v2t_ptr, p.d_v2t, p.d_rowD, p.d_rowN, p.NV, p.N, b);
     BEM_HIP(hipGetLastError());
     BEM_HIP(hipStreamSynchronize(p.stream));
-    (void)hipFree(d_params);
 }
 
 constexpr int FIELD_DIRECT_MAX = 4;                   // more fields: rows + dense product
@@ -451,8 +464,10 @@ void launch_field(bem_problem &p, const double2 *u, const bem_incident *inc, int
                   int64_t np, double2 *field, int32_t *region)
 {
     double *d_params = nullptr;
+    DevScratch params_mem, doms_mem, wreg_mem, rows_mem;
     IncDev I{};
     if (inc) I = upload_incident(p, *inc, &d_params);
+    params_mem.p = d_params;
     std::vector<DomDev> hd;
     for (const auto &d : p.doms) {
         // mean edge length (every edge counted from both of its triangles)
@@ -468,12 +483,14 @@ void launch_field(bem_problem &p, const double2 *u, const bem_incident *inc, int
     }
     DomDev *d_doms = nullptr;
     BEM_HIP(hipMalloc(&d_doms, hd.size() * sizeof(DomDev)));
+    doms_mem.p = d_doms;
     BEM_HIP(hipMemcpyAsync(d_doms, hd.data(), hd.size() * sizeof(DomDev), hipMemcpyHostToDevice, p.stream));
     const int B = 128;
     int32_t *wreg = nullptr;
     double2 *R = nullptr;
     if (np > 0) {
         BEM_HIP(hipMalloc(&wreg, size_t(np) * sizeof(int32_t)));
+        wreg_mem.p = wreg;
         k_region<<<dim3(blocks_1d(np, B)), dim3(B), 0, p.stream>>>(d_doms, int(hd.size()), p.d_verts, p.d_tris, pts, np,
                                                                    wreg, region);
         BEM_HIP(hipGetLastError());
@@ -491,6 +508,7 @@ void launch_field(bem_problem &p, const double2 *u, const bem_incident *inc, int
                 if (c > 0) chunk = std::min<int64_t>(chunk, c);
             }
             BEM_HIP(hipMalloc(&R, size_t(chunk) * p.N * sizeof(double2)));
+            rows_mem.p = R;
             for (int64_t p0 = 0; p0 < np; p0 += chunk) {
                 const int64_t npc = std::min(chunk, np - p0);
                 k_field_rows<<<dim3(blocks_1d(npc * p.NV, 256)), dim3(256), 0, p.stream>>>(
@@ -505,10 +523,6 @@ void launch_field(bem_problem &p, const double2 *u, const bem_incident *inc, int
         }
     }
     BEM_HIP(hipStreamSynchronize(p.stream));
-    if (R) (void)hipFree(R);
-    if (wreg) (void)hipFree(wreg);
-    (void)hipFree(d_doms);
-    if (d_params) (void)hipFree(d_params);
 }
 
 }  // namespace bem

@@ -10,8 +10,11 @@
 //              touching pairs (pass 0 of the singular pass, V block only)
 // Per pair: difference, r^2, 1/r, r, phase, sin, cos, G and one complex
 // multiply-add: about 21 FLOP and 3 transcendentals, against 140 FLOP of the
-// fused multitrace pair.  It shares the work list, launch shape and scratch
-// buffers of the fused path.
+// fused multitrace pair.  It shares the scratch buffers of the fused path; its
+// launch shape is timed on first use when the problem was set up with
+// autotuning, and is the fused kernel's otherwise.
+#include <algorithm>
+
 #include "bem_internal.h"
 
 namespace bem {
@@ -50,21 +53,21 @@ __global__ void k_gather_v(const double2 *__restrict__ x, const int32_t *__restr
     im[i] = float(pi * w);
 }
 
-// Work items (pass 0, test block, split) of the shared work list: a workgroup
-// owns SL_BLOCK * TPL test points and one trial chunk; trial tiles of SL_BLOCK
-// points go through LDS and are read by broadcast.  FP32 sums within a tile,
-// FP64 across tiles.  The point paired with itself (r = 0) is skipped: the
-// singular correction accounts for it.
+// Workgroup b * n_split + s owns test block b (SL_BLOCK * TPL points of the
+// exterior pass) and trial chunk s (consecutive workgroups take consecutive
+// chunks, so each XCD's L2 holds one chunk); trial tiles of SL_BLOCK points go
+// through LDS and are read by broadcast.  FP32 sums within a tile, FP64 across
+// tiles.  The point paired with itself (r = 0) is skipped: the singular
+// correction accounts for it.
 template <int TPL, bool ATT>
-__global__ __launch_bounds__(SL_BLOCK) void k_pairs_v(const int4 *__restrict__ work, const PassDev *__restrict__ passes,
-                                                      const float *__restrict__ pts, const float4 *__restrict__ rec,
-                                                      const float *__restrict__ rim, double *__restrict__ part, int64_t M,
-                                                      int n_split)
+__global__ __launch_bounds__(SL_BLOCK) void k_pairs_v(const PassDev *__restrict__ pass0, const float *__restrict__ pts,
+                                                      const float4 *__restrict__ rec, const float *__restrict__ rim,
+                                                      double *__restrict__ part, int64_t M, int n_split)
 {
     __shared__ float4 l0[SL_BLOCK];
     __shared__ float l1[SL_BLOCK];
-    const int4 w = work[blockIdx.x];
-    const PassDev P = passes[w.x];
+    const int4 w = make_int4(0, int(blockIdx.x) / n_split, int(blockIdx.x) % n_split, 0);
+    const PassDev P = *pass0;
     const int tid = threadIdx.x;
     float xx[TPL], xy[TPL], xz[TPL];
     long long ti[TPL];
@@ -179,31 +182,91 @@ __global__ void k_scatter_v(const double2 *__restrict__ pot, const int32_t *__re
     y[g] = make_double2(yr, yi);
 }
 
+static void launch_pairs_v(bem_problem &p, int tpl, int n_split, const float4 *rec, const float *rim)
+{
+    const bool att = p.passes[0].kim != 0.0;
+    const int64_t nblk = (p.passes[0].test_end - p.passes[0].test_begin + SL_BLOCK * tpl - 1) / (SL_BLOCK * tpl);
+    const dim3 grid(blocks_1d(nblk * n_split * SL_BLOCK, SL_BLOCK)), block(SL_BLOCK);
+#define SL_LAUNCH(T)                                                                                                  \
+    if (att) k_pairs_v<T, true><<<grid, block, 0, p.stream>>>(p.d_pass, p.d_pts, rec, rim, p.d_part, p.M, n_split);  \
+    else k_pairs_v<T, false><<<grid, block, 0, p.stream>>>(p.d_pass, p.d_pts, rec, rim, p.d_part, p.M, n_split);
+    if (tpl == 4) {
+        SL_LAUNCH(4)
+    } else if (tpl == 2) {
+        SL_LAUNCH(2)
+    } else {
+        SL_LAUNCH(1)
+    }
+#undef SL_LAUNCH
+    BEM_HIP(hipGetLastError());
+}
+
+// Launch shape of the single-layer pair kernel (test points per lane, trial
+// chunks): a short timing sweep on first use.  The partial sums (2 M doubles
+// per chunk) live in the fused path's buffer of 2 x n_split x 10 M doubles,
+// which bounds the chunks at 10 n_split.
+static void tune_single_layer(bem_problem &p, const float4 *rec, const float *rim)
+{
+    const int64_t cap = 10 * int64_t(p.n_split);
+    const int64_t m0 = p.passes[0].test_end - p.passes[0].test_begin;
+    hipEvent_t e0, e1;
+    BEM_HIP(hipEventCreate(&e0));
+    BEM_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_tpl = 1, best_split = int(std::min<int64_t>(cap, 8));
+    bool warmed = false;
+    for (int tpl : {1, 2, 4})
+        for (int ns : {4, 8, 16, 32, 64}) {
+            const int64_t wgs = (m0 + SL_BLOCK * tpl - 1) / (SL_BLOCK * tpl) * ns;
+            if (ns > cap || wgs < 256 || int64_t(ns) * SL_BLOCK > m0) continue;
+            if (!warmed) {
+                for (int w = 0; w < 3; ++w) launch_pairs_v(p, tpl, ns, rec, rim);
+                warmed = true;
+            }
+            float t = 1e30f;
+            for (int r = 0; r < 2; ++r) {
+                BEM_HIP(hipEventRecord(e0, p.stream));
+                launch_pairs_v(p, tpl, ns, rec, rim);
+                BEM_HIP(hipEventRecord(e1, p.stream));
+                BEM_HIP(hipEventSynchronize(e1));
+                float ms = 0;
+                BEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+                t = std::min(t, ms);
+            }
+            if (t < best) {
+                best = t;
+                best_tpl = tpl;
+                best_split = ns;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p.sl_tpl = best_tpl;
+    p.sl_split = best_split;
+}
+
 void launch_single_layer(bem_problem &p, const double2 *x, double2 *y, bool record)
 {
     const int B = 256;
     float4 *rec = p.d_trial;
     float *rim = reinterpret_cast<float *>(p.d_trial + p.M);   // d_trial holds 4 M float4
     double2 *pot = reinterpret_cast<double2 *>(p.d_pot);       // d_pot holds 10 M doubles
-    const bool att = p.passes[0].kim != 0.0;
-    // work items of pass 0 lead the shared work list
-    const int64_t nblk0 = (p.passes[0].test_end - p.passes[0].test_begin + 256 * p.tpl - 1) / (256 * p.tpl);
-    const unsigned n0 = unsigned(nblk0 * p.n_split);
     if (record) BEM_HIP(hipEventRecord(p.ev[0], p.stream));
     k_gather_v<<<dim3(blocks_1d(p.M, B)), dim3(B), 0, p.stream>>>(x, p.d_tris, p.d_area, p.d_pts, p.M, rec, rim);
     BEM_HIP(hipGetLastError());
-    if (record) BEM_HIP(hipEventRecord(p.ev[1], p.stream));
-    const dim3 grid(n0), block(SL_BLOCK);
-    if (p.tpl == 2) {
-        if (att) k_pairs_v<2, true><<<grid, block, 0, p.stream>>>(p.d_work, p.d_pass, p.d_pts, rec, rim, p.d_part, p.M, p.n_split);
-        else k_pairs_v<2, false><<<grid, block, 0, p.stream>>>(p.d_work, p.d_pass, p.d_pts, rec, rim, p.d_part, p.M, p.n_split);
-    } else {
-        if (att) k_pairs_v<1, true><<<grid, block, 0, p.stream>>>(p.d_work, p.d_pass, p.d_pts, rec, rim, p.d_part, p.M, p.n_split);
-        else k_pairs_v<1, false><<<grid, block, 0, p.stream>>>(p.d_work, p.d_pass, p.d_pts, rec, rim, p.d_part, p.M, p.n_split);
+    if (p.sl_tpl == 0) {
+        if (p.flags & BEM_AUTOTUNE) {
+            tune_single_layer(p, rec, rim);
+        } else {
+            // without tuning: the fused kernel's shape, bounded by the partial buffer
+            p.sl_tpl = std::min(p.tpl, 4);
+            p.sl_split = p.n_split;
+        }
     }
-    BEM_HIP(hipGetLastError());
+    if (record) BEM_HIP(hipEventRecord(p.ev[1], p.stream));
+    launch_pairs_v(p, p.sl_tpl, p.sl_split, rec, rim);
     if (record) BEM_HIP(hipEventRecord(p.ev[2], p.stream));
-    k_reduce_v<<<dim3(blocks_1d(p.M, B)), dim3(B), 0, p.stream>>>(p.d_part, p.M, p.n_split, pot);
+    k_reduce_v<<<dim3(blocks_1d(p.M, B)), dim3(B), 0, p.stream>>>(p.d_part, p.M, p.sl_split, pot);
     BEM_HIP(hipGetLastError());
     if (record) BEM_HIP(hipEventRecord(p.ev[3], p.stream));
     k_scatter_v<<<dim3(blocks_1d(p.NV, B)), dim3(B), 0, p.stream>>>(pot, p.d_v2t_ptr, p.d_v2t, p.d_area, p.d_sl_cptr,

@@ -81,3 +81,25 @@ def test_tuned_gemm_slices_keep_parity(c1, tmp_path, monkeypatch):
         assert np.array_equal(Y1, Y2)
     text = (tmp_path / "tune.txt").read_text()
     assert "bf16x3" in text and "f32" in text
+
+
+def test_tuned_single_layer_shape_keeps_parity(tmp_path, monkeypatch):
+    """The single-layer kernel's shape is timed on first use when autotuning is
+    on.  On the 2,562-vertex sphere (several candidate shapes) the tuned
+    operator equals the untuned one (the fused kernel's shape, parity-tested
+    against the oracle's V_k0) to two FP32 summation orders, and repeated calls
+    with the chosen shape are bitwise equal."""
+    import paper_1910_01011_amd as bem
+    monkeypatch.setenv("BEM_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    prob = configs.sphere_problem(4, 4.0, 4.4, 1.0)
+    nv = prob.domains[0].n_vertices
+    x = vectors.random_complex(nv, seed=9)
+    P = _problem(bem, prob, autotune=True)
+    y1 = P.apply_single_layer(x)
+    y2 = P.apply_single_layer(x)
+    P.close()
+    Q = _problem(bem, prob)
+    y0 = Q.apply_single_layer(x)
+    Q.close()
+    assert np.array_equal(y1, y2)
+    assert _relerr(y1, y0) <= 1e-6
