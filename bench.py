@@ -83,7 +83,8 @@ def main():
                          "on the fly, pistons, OSRC), ribcage_assembled (26.9k vertices, 256 right-hand sides), "
                          "serving (kidney request stream), paper_sphere (the paper's 1 cm sphere at 1 MHz, fat and "
                          "rib material, 4-10 elements per wavelength, OSRC GMRES), planning (full matrix capture "
-                         "of 256 pistons on the 13.5k-vertex stack, then phase conjugation and rib sparing)")
+                         "of 256 pistons on the 13.5k-vertex stack, then phase conjugation and rib sparing), hmatrix "
+                         "(ACA-compressed operator on the sphere and the 53.5k-vertex stack)")
     ap.add_argument("--serving-requests", type=int, default=8, help="requests per arrival rate in --extra serving")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only a 1 GiB elementwise copy (the counter scale) and 3 applies, for HBM counters")
@@ -208,6 +209,8 @@ def main():
             out["paper_sphere"] = paper_sphere_section(bem, torch)
         elif e == "planning":
             out["planning"] = planning_section(bem, torch, not args.no_autotune)
+        elif e == "hmatrix":
+            out["hmatrix"] = hmatrix_section(bem, torch, not args.no_autotune)
         else:
             raise SystemExit(f"unknown extra workload {e}")
         torch.cuda.empty_cache()
@@ -400,6 +403,66 @@ def planning_section(bem, torch, autotune):
            "sparing": {k: v for k, v in res["sparing"].items() if k != "a"}}
     log(f"planning: capture {res['capture_s']:.1f} s, ratio pc {out['phase_conjugation']['ratio']:.3f} "
         f"sparing {out['sparing']['ratio']:.3f}")
+    return out
+
+
+def hmatrix_section(bem, torch, autotune):
+    """Hierarchical matrix (ACA, eps 1e-4, leaves of 64 vertices, eta 2): on the
+    10,242-vertex sphere against the dense complex64 matrix (storage, apply
+    time, difference, GMRES to 1e-5), and on the 53.5k-vertex rib-cage stack
+    against the on-the-fly operator (OSRC GMRES to 1e-5 with the compressed
+    operator; the on-the-fly residual of its solution)."""
+    from bem_inputs import configs, pistons, vectors
+    out = {}
+    prob = configs.config2()
+    P = bem.Problem.from_config(prob, device=True, mode=bem.BEM_ASSEMBLED_FP32, autotune=autotune)
+    x = torch.from_numpy(vectors.random_complex(prob.n_unknowns, seed=0)).cuda()
+    yd = P.apply(x, kernel=bem.BEM_APPLY_GEMV)
+    info = P.hmatrix_build(eps=1e-4, leaf_vertices=64, eta=2.0)
+    yh = P.apply(x, kernel=bem.BEM_APPLY_HMATRIX)
+    ts_h, ts_d = [], []
+    for _ in range(10):
+        P.apply(x, out=yh, kernel=bem.BEM_APPLY_HMATRIX)
+        ts_h.append(P.timings()[0])
+        P.apply(x, out=yd, kernel=bem.BEM_APPLY_GEMV)
+        ts_d.append(P.timings()[0])
+    b = P.rhs(bem.Incident.plane_waves([[0.0, 0.0, 1.0]]))
+    (ud, i_d), t_d = _timed(torch, lambda: P.solve(b, bem.solve_options(tol=1e-5, restart=100, max_iter=400)))
+    (uh, i_h), t_h = _timed(torch, lambda: P.solve(b, bem.solve_options(tol=1e-5, restart=100, max_iter=400,
+                                                                        precision=bem.BEM_PREC_HMATRIX)))
+    r = P.apply(uh[0].contiguous(), kernel=bem.BEM_APPLY_GEMV) - b[0]
+    out["sphere10242"] = {"info": info, "apply_ms": float(np.median(ts_h)), "gemv_ms": float(np.median(ts_d)),
+                          "rel_diff_to_dense": float((yh - yd).norm() / yd.norm()),
+                          "gmres_dense_s": t_d, "gmres_hmatrix_s": t_h, "iterations": [i_d[0]["iterations"],
+                                                                                          i_h[0]["iterations"]],
+                          "dense_residual_of_h_solution": float(r.norm() / b[0].norm())}
+    log(f"hmatrix sphere: {info['bytes'] / 1e6:.0f} MB of {info['dense_bytes'] / 1e6:.0f} MB, "
+        f"apply {np.median(ts_h):.3f} ms vs GEMV {np.median(ts_d):.3f} ms")
+    P.close()
+    torch.cuda.empty_cache()
+    prob = configs.ribcage(1.0)
+    P, t_setup = _timed(torch, lambda: bem.Problem.from_config(prob, device=True, autotune=autotune))
+    x = torch.from_numpy(vectors.random_complex(prob.n_unknowns, seed=0)).cuda()
+    yo = P.apply(x)
+    info, t_build = _timed(torch, lambda: P.hmatrix_build(eps=1e-4, leaf_vertices=64, eta=2.0))
+    yh = P.apply(x, kernel=bem.BEM_APPLY_HMATRIX)
+    ts = []
+    for _ in range(5):
+        P.apply(x, out=yh, kernel=bem.BEM_APPLY_HMATRIX)
+        ts.append(P.timings()[0])
+    c, nn, a = pistons.bowl_array()
+    b = P.rhs(bem.Incident.pistons(c, nn, a, 1.0, np.zeros(len(c), dtype=int)))
+    opts = bem.solve_options(tol=1e-5, restart=100, max_iter=1000, precond=bem.BEM_PRECOND_OSRC, n_pade=8, r_eps=1.5,
+                             theta=np.pi / 3, precision=bem.BEM_PREC_HMATRIX)
+    (u, info_s), t_solve = _timed(torch, lambda: P.solve(b, opts))
+    r = P.apply(u[0].contiguous()) - b[0]
+    out["ribcage53524"] = {"info": info, "setup_s": t_setup, "build_s": t_build, "apply_ms": float(np.median(ts)),
+                           "rel_diff_to_on_the_fly": float((yh - yo).norm() / yo.norm()),
+                           "osrc_gmres_hmatrix": {"time_to_solve_s": t_solve, **info_s[0]},
+                           "on_the_fly_residual_of_solution": float(r.norm() / b[0].norm())}
+    log(f"hmatrix ribcage: {info['bytes'] / 1e9:.1f} GB of {info['dense_bytes'] / 1e9:.1f} GB, build {t_build:.1f} s, "
+        f"apply {np.median(ts):.2f} ms, OSRC GMRES {t_solve:.1f} s, {info_s[0]['iterations']} iterations")
+    P.close()
     return out
 
 

@@ -104,6 +104,8 @@ typedef struct {
  *                               (problem assembled with BEM_ASSEMBLED_SPLIT_BF16)
  *   BEM_PREC_FP32_MFMA_FGMRES   the same with the FP32 MFMA GEMM as inner operator
  *                               (any assembled mode)
+ *   BEM_PREC_HMATRIX            plain GMRES (or OSRC-preconditioned GMRES) on the
+ *                               hierarchical matrix of bem_hmatrix_build (any mode)
  * With BEM_PRECOND_OSRC, plain GMRES runs on the left-preconditioned system
  * (stopping on the preconditioned residual); the flexible forms precondition
  * their inner solves (inner GMRES on P A z = P v) and keep stopping on the
@@ -113,6 +115,7 @@ typedef struct {
 #define BEM_PREC_FP32 0
 #define BEM_PREC_SPLIT_BF16_FGMRES 1
 #define BEM_PREC_FP32_MFMA_FGMRES 2
+#define BEM_PREC_HMATRIX 3          /* GMRES on the hierarchical matrix of bem_hmatrix_build */
 
 typedef struct {
     double tol;          /* relative residual target (paper: 1e-5) */
@@ -122,7 +125,8 @@ typedef struct {
     int n_pade;          /* OSRC Pade terms */
     double r_eps;        /* OSRC damping length */
     double theta;        /* OSRC Pade branch-cut rotation */
-    int precision;       /* BEM_PREC_FP32, BEM_PREC_SPLIT_BF16_FGMRES or BEM_PREC_FP32_MFMA_FGMRES */
+    int precision;       /* BEM_PREC_FP32, BEM_PREC_SPLIT_BF16_FGMRES, BEM_PREC_FP32_MFMA_FGMRES or
+                            BEM_PREC_HMATRIX */
     double inner_tol;    /* inner tolerance of the flexible-GMRES refinement */
     int inner_restart;   /* inner GMRES restart length (0: 30) */
     int inner_max_iter;  /* inner iteration cap per outer step (0: 300) */
@@ -187,6 +191,7 @@ bem_status bem_apply_parts(bem_problem *p, const bem_complex *x, bem_complex *y,
 #define BEM_APPLY_MFMA_SPLIT_BF16 3
 #define BEM_APPLY_MFMA_SPLIT_BF16_W4 4
 #define BEM_APPLY_MFMA_SPLIT_BF16_W8 5
+#define BEM_APPLY_HMATRIX 6   /* the hierarchical matrix of bem_hmatrix_build (any mode) */
 bem_status bem_apply_with(bem_problem *p, const bem_complex *x, bem_complex *y, int32_t n_rhs, int kernel);
 
 /* Right-hand side b_j = <gamma^{j,+} p_inc, phi> (eq. Galerkin_disc_rhs1) for
@@ -227,6 +232,30 @@ bem_status bem_apply_preconditioner(bem_problem *p, const bem_solve_opts *opts, 
 bem_status bem_evaluate_field(bem_problem *p, const bem_complex *u, const bem_incident *inc,
                               const double *points, int64_t n_points,
                               bem_complex *field, int32_t *region);
+
+/* Hierarchical-matrix compression of the PMCHWT matrix, the paper's device
+ * for going beyond dense storage (its numerical experiments use H-matrices
+ * with adaptive cross approximation).  The vertices of all boundaries are
+ * clustered by recursive median bisection down to leaf_vertices per cluster; a
+ * pair of clusters with max(diam) <= eta dist (bounding boxes) becomes a
+ * low-rank block, built by adaptive cross approximation with complete pivoting
+ * to the relative tolerance eps of its largest entry (kept dense when the rank
+ * would not halve its storage); pairs of leaves are dense blocks with the FP64
+ * singular correction.  Entries are those of the assembled matrix (FP32 pairs,
+ * complex64 storage).  Replaces any previous hierarchical matrix of p; it is
+ * applied by bem_apply_with(BEM_APPLY_HMATRIX) and used by solves with
+ * precision BEM_PREC_HMATRIX.  eps in (0, 0.1], leaf_vertices in [8, 4096],
+ * eta > 0.  info may be NULL. */
+typedef struct {
+    int64_t n_blocks, n_lowrank, n_dense;
+    int64_t n_admissible;   /* blocks the tree made admissible (low rank, or dense when not compressible) */
+    int64_t bytes;          /* storage of all blocks */
+    int64_t dense_bytes;    /* the dense complex64 matrix, for comparison */
+    int32_t max_rank;
+    int32_t pad;
+    double build_s;
+} bem_hmatrix_info;
+bem_status bem_hmatrix_build(bem_problem *p, double eps, int32_t leaf_vertices, double eta, bem_hmatrix_info *info);
 
 int64_t bem_num_unknowns(const bem_problem *p);
 

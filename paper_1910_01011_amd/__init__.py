@@ -37,9 +37,11 @@ BEM_DEVICE_PTRS = 1
 BEM_AUTOTUNE = 2
 BEM_APPLY_DEFAULT, BEM_APPLY_GEMV, BEM_APPLY_MFMA_FP32, BEM_APPLY_MFMA_SPLIT_BF16 = 0, 1, 2, 3
 BEM_APPLY_MFMA_SPLIT_BF16_W4, BEM_APPLY_MFMA_SPLIT_BF16_W8 = 4, 5
+BEM_APPLY_HMATRIX = 6
 BEM_PLANE_WAVE, BEM_POINT_SOURCES, BEM_PISTON_ARRAY = 0, 1, 2
 BEM_PRECOND_NONE, BEM_PRECOND_OSRC = 0, 1
 BEM_PREC_FP32, BEM_PREC_SPLIT_BF16_FGMRES, BEM_PREC_FP32_MFMA_FGMRES = 0, 1, 2
+BEM_PREC_HMATRIX = 3
 
 
 class bem_complex(ctypes.Structure):
@@ -73,6 +75,13 @@ class bem_solve_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("rel_residual", ctypes.c_double)]
 
 
+class bem_hmatrix_info(ctypes.Structure):
+    _fields_ = [("n_blocks", ctypes.c_int64), ("n_lowrank", ctypes.c_int64), ("n_dense", ctypes.c_int64),
+                ("n_admissible", ctypes.c_int64),
+                ("bytes", ctypes.c_int64), ("dense_bytes", ctypes.c_int64), ("max_rank", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("build_s", ctypes.c_double)]
+
+
 _vp = ctypes.c_void_p
 _L.bem_assemble.argtypes = [ctypes.POINTER(bem_domain), ctypes.c_int32, bem_complex, ctypes.c_double,
                             ctypes.POINTER(bem_assemble_opts), ctypes.POINTER(_vp)]
@@ -80,6 +89,7 @@ _L.bem_apply.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
 _L.bem_apply_parts.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int]
 _L.bem_apply_with.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int]
 _L.bem_apply_single_layer.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
+_L.bem_hmatrix_build.argtypes = [_vp, ctypes.c_double, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(bem_hmatrix_info)]
 _L.bem_rhs.argtypes = [_vp, ctypes.POINTER(bem_incident), _vp]
 _L.bem_solve.argtypes = [_vp, ctypes.POINTER(bem_incident), ctypes.POINTER(bem_solve_opts), _vp,
                          ctypes.POINTER(bem_solve_info)]
@@ -96,12 +106,14 @@ _L.bem_pair_launch_shape.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32)]
 _L.bem_destroy.argtypes = [_vp]
 _L.bem_destroy.restype = None
 _L.bem_last_error.restype = ctypes.c_char_p
-for _f in ("bem_assemble", "bem_apply", "bem_apply_parts", "bem_apply_with", "bem_apply_single_layer", "bem_rhs", "bem_solve", "bem_solve_rhs",
+for _f in ("bem_assemble", "bem_apply", "bem_apply_parts", "bem_apply_with", "bem_apply_single_layer",
+           "bem_hmatrix_build", "bem_rhs", "bem_solve", "bem_solve_rhs",
            "bem_apply_preconditioner", "bem_pair_launch_shape",
            "bem_evaluate_field", "bem_footprint_bytes", "bem_last_timings"):
     getattr(_L, _f).restype = ctypes.c_int
 
-EXPORTED = ["bem_assemble", "bem_apply", "bem_apply_parts", "bem_apply_with", "bem_apply_single_layer", "bem_rhs", "bem_solve", "bem_solve_rhs",
+EXPORTED = ["bem_assemble", "bem_apply", "bem_apply_parts", "bem_apply_with", "bem_apply_single_layer",
+            "bem_hmatrix_build", "bem_rhs", "bem_solve", "bem_solve_rhs",
             "bem_apply_preconditioner", "bem_pair_launch_shape",
             "bem_evaluate_field", "bem_num_unknowns", "bem_footprint_bytes", "bem_last_timings",
             "bem_destroy", "bem_last_error"]
@@ -347,6 +359,13 @@ class Problem:
         _check(_L.bem_evaluate_field(self._h, u.ctypes.data, ctypes.byref(inc) if inc else None, pts.ctypes.data,
                                      pts.shape[0], field.ctypes.data, region.ctypes.data))
         return field, region
+
+    def hmatrix_build(self, eps=1e-6, leaf_vertices=64, eta=1.0):
+        """Hierarchical-matrix compression (ACA) of the operator; returns its statistics.
+        Applied with apply(..., kernel=BEM_APPLY_HMATRIX), solved with precision=BEM_PREC_HMATRIX."""
+        info = bem_hmatrix_info()
+        _check(_L.bem_hmatrix_build(self._h, float(eps), int(leaf_vertices), float(eta), ctypes.byref(info)))
+        return {f: getattr(info, f) for f, _ in bem_hmatrix_info._fields_ if f != "pad"}
 
     def pair_launch_shape(self):
         """(test points per lane, trial splits) of the pair kernel."""

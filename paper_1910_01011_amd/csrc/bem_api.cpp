@@ -58,6 +58,7 @@ void free_problem(bem_problem *p)
                     p->d_sl_cptr, p->d_sl_ccol, p->d_sl_cval};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
+    if (p->hm) bem::hmatrix_free(p->hm);
     for (auto &e : p->ev)
         if (e) (void)hipEventDestroy(e);
     delete p;
@@ -269,7 +270,7 @@ void apply_device(bem_problem &p, const double2 *x, double2 *y, int n_rhs, int p
 double osrc_inner_tol(const bem_solve_opts &o)
 {
     if (o.osrc_tol > 0) return o.osrc_tol;
-    const double inner = o.precision == BEM_PREC_FP32 ? o.tol : std::min(o.tol, o.inner_tol);
+    const double inner = (o.precision == BEM_PREC_FP32 || o.precision == BEM_PREC_HMATRIX) ? o.tol : std::min(o.tol, o.inner_tol);
     return std::min(1e-6, std::max(1e-10, 0.1 * inner));
 }
 
@@ -525,9 +526,27 @@ bem_status bem_apply(bem_problem *p, const bem_complex *x, bem_complex *y, int32
 bem_status bem_apply_with(bem_problem *p, const bem_complex *x, bem_complex *y, int32_t n_rhs, int kernel)
 {
     if (!p || !x || !y || n_rhs < 0) return fail(BEM_ERR_INVALID_ARG, "bem_apply_with: bad arguments");
-    if (kernel < BEM_APPLY_DEFAULT || kernel > BEM_APPLY_MFMA_SPLIT_BF16_W8)
+    if (kernel < BEM_APPLY_DEFAULT || kernel > BEM_APPLY_HMATRIX)
         return fail(BEM_ERR_INVALID_ARG, "bem_apply_with: unknown kernel");
     if (kernel == BEM_APPLY_DEFAULT) return bem_apply_parts(p, x, y, n_rhs, 3);
+    if (kernel == BEM_APPLY_HMATRIX) {
+        if (!p->hm) return fail(BEM_ERR_INVALID_ARG, "bem_apply_with: no hierarchical matrix (bem_hmatrix_build)");
+        if (n_rhs == 0) return BEM_OK;
+        return guarded([&]() -> bem_status {
+            BEM_HIP(hipSetDevice(p->device));
+            const size_t bytes = size_t(n_rhs) * p->N * sizeof(double2);
+            if (p->flags & BEM_DEVICE_PTRS) {
+                bem::hmatrix_apply(*p, reinterpret_cast<const double2 *>(x), reinterpret_cast<double2 *>(y), n_rhs, true);
+            } else {
+                ensure_scratch(*p, n_rhs);
+                BEM_HIP(hipMemcpyAsync(p->d_x, x, bytes, hipMemcpyHostToDevice, p->stream));
+                bem::hmatrix_apply(*p, p->d_x, p->d_y, n_rhs, true);
+                BEM_HIP(hipMemcpyAsync(y, p->d_y, bytes, hipMemcpyDeviceToHost, p->stream));
+                BEM_HIP(hipStreamSynchronize(p->stream));
+            }
+            return BEM_OK;
+        });
+    }
     if (p->mode == BEM_OTF) return fail(BEM_ERR_INVALID_ARG, "bem_apply_with: on-the-fly problems have no dense kernels");
     const bool split = kernel >= BEM_APPLY_MFMA_SPLIT_BF16;
     if (split && p->mode != BEM_ASSEMBLED_SPLIT_BF16)
@@ -555,6 +574,22 @@ bem_status bem_apply_with(bem_problem *p, const bem_complex *x, bem_complex *y, 
             BEM_HIP(hipMemcpyAsync(y, p->d_y, bytes, hipMemcpyDeviceToHost, p->stream));
             BEM_HIP(hipStreamSynchronize(p->stream));
         }
+        return BEM_OK;
+    });
+}
+
+bem_status bem_hmatrix_build(bem_problem *p, double eps, int32_t leaf_vertices, double eta, bem_hmatrix_info *info)
+{
+    if (!p) return fail(BEM_ERR_INVALID_ARG, "bem_hmatrix_build: bad arguments");
+    if (!(eps > 0 && eps <= 0.1) || leaf_vertices < 8 || leaf_vertices > 4096 || !(eta > 0) || !std::isfinite(eta))
+        return fail(BEM_ERR_INVALID_ARG, "bem_hmatrix_build: need 0 < eps <= 0.1, 8 <= leaf_vertices <= 4096, eta > 0");
+    return guarded([&]() -> bem_status {
+        BEM_HIP(hipSetDevice(p->device));
+        if (p->hm) {
+            bem::hmatrix_free(p->hm);
+            p->hm = nullptr;
+        }
+        p->hm = bem::hmatrix_build(*p, eps, leaf_vertices, eta, info);
         return BEM_OK;
     });
 }
@@ -622,13 +657,16 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
     if (o.inner_restart < 1 || o.inner_max_iter < 1)
         return fail(BEM_ERR_INVALID_ARG, "bem_solve: inner_restart and inner_max_iter must be positive (0: default)");
     if (o.precision != BEM_PREC_FP32 && o.precision != BEM_PREC_SPLIT_BF16_FGMRES &&
-        o.precision != BEM_PREC_FP32_MFMA_FGMRES)
+        o.precision != BEM_PREC_FP32_MFMA_FGMRES && o.precision != BEM_PREC_HMATRIX)
         return fail(BEM_ERR_INVALID_ARG, "bem_solve: unknown precision mode");
+    if (o.precision == BEM_PREC_HMATRIX && !p->hm)
+        return fail(BEM_ERR_INVALID_ARG, "bem_solve: no hierarchical matrix (bem_hmatrix_build)");
     if (o.precision == BEM_PREC_FP32_MFMA_FGMRES && p->mode == BEM_OTF)
         return fail(BEM_ERR_INVALID_ARG, "bem_solve: MFMA refinement needs an assembled problem");
     if (o.precision == BEM_PREC_SPLIT_BF16_FGMRES && p->mode != BEM_ASSEMBLED_SPLIT_BF16)
         return fail(BEM_ERR_INVALID_ARG, "bem_solve: split-BF16 refinement needs a problem assembled in split-BF16 mode");
-    if (o.precision != BEM_PREC_FP32 && !(o.inner_tol > 0 && o.inner_tol < 1))
+    const bool plain = o.precision == BEM_PREC_FP32 || o.precision == BEM_PREC_HMATRIX;
+    if (!plain && !(o.inner_tol > 0 && o.inner_tol < 1))
         return fail(BEM_ERR_INVALID_ARG, "bem_solve: inner_tol must be in (0, 1)");
     if (!(o.osrc_tol >= 0 && o.osrc_tol < 1))
         return fail(BEM_ERR_INVALID_ARG, "bem_solve: osrc_tol must be in [0, 1) (0: 1e-10)");
@@ -655,14 +693,17 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
         const int progress = pe ? std::max(0, std::atoi(pe)) : 0;
         // FP32-accurate operator: on-the-fly kernel, or the FP32 dense matrix
         // (GEMV with FP64 accumulation for one vector, FP32 MFMA GEMM for a block)
-        const bem::ApplyFn fp32_apply = [&P](const double2 *X, double2 *Y, int R) {
-            if (P.mode == BEM_OTF) {
+        const bool hmat = o.precision == BEM_PREC_HMATRIX;
+        const bem::ApplyFn fp32_apply = [&P, hmat](const double2 *X, double2 *Y, int R) {
+            if (hmat) {
+                bem::hmatrix_apply(P, X, Y, R, false);
+            } else if (P.mode == BEM_OTF) {
                 apply_device(P, X, Y, R, 3, false);
             } else {
                 for (int r = 0; r < R; ++r) apply_dense_one(P, X + int64_t(r) * P.N, Y + int64_t(r) * P.N, true);
             }
         };
-        if (o.precision == BEM_PREC_FP32 && o.precond == BEM_PRECOND_OSRC) {
+        if (plain && o.precond == BEM_PRECOND_OSRC) {
             // left preconditioning: GMRES on P A u = P b (stops on the
             // preconditioned residual); the unpreconditioned weak-form residual
             // is reported afterwards
@@ -684,7 +725,7 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
             fp32_apply(du, tmp, n_rhs);
             const std::vector<double> rr = residual_norms(P, db, tmp, n_rhs);
             for (int r = 0; r < n_rhs; ++r) info[r].rel_residual = rr[r];
-        } else if (o.precision == BEM_PREC_FP32) {
+        } else if (plain) {
             bem::gmres_batch(P, P.N, n_rhs, db, du, bem::KrylovOpts{o.tol, o.restart, o.max_iter, progress},
                              fp32_apply, nullptr, info);
         } else {

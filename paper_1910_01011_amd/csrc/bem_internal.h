@@ -89,6 +89,21 @@ struct OsrcParams {
     int cg_maxit;
 };
 
+// One block of the hierarchical matrix.  Vertices are reordered so that every
+// cluster is a contiguous range; a block couples row vertices [r0, r1) and
+// column vertices [c0, c1) of that order as a (2 m) x (2 n) complex matrix in
+// interleaved (vertex, D/N) order.
+struct HBlock {
+    int32_t r0, r1, c0, c1;
+    int32_t rank;      // -1: dense block D; else U V with this rank
+    int32_t pad;
+    float2 *U;         // (2 m) x rank, column-major
+    float2 *V;         // rank x (2 n), row-major
+    float2 *D;         // (2 m) x (2 n), column-major
+    int64_t zoff;      // offset of the block's 2 m products in the product buffer
+};
+struct HMatrix;
+
 struct DomInfo {
     int64_t nv, nt;        // vertices / triangles of the domain
     int64_t v_off, t_off;  // offsets in the global vertex / triangle arrays
@@ -168,6 +183,9 @@ struct bem_problem {
     double *d_Mv = nullptr, *d_Sv = nullptr;
     int64_t a_nnz = 0;
 
+    // hierarchical matrix (bem_hmatrix_build)
+    bem::HMatrix *hm = nullptr;
+
     // scratch vectors
     double2 *d_x = nullptr, *d_y = nullptr;
     int64_t scratch_rhs = 0;
@@ -236,6 +254,15 @@ int cached_gemm_slices(bem_problem &p, int R, bool bf16);   // 0 when the bucket
 // 4 complex blocks per entry (device arrays allocated here).
 void run_singular(bem_problem &p, const std::vector<SingularItem> &items, int32_t **cptr, int32_t **ccol,
                   double2 **cval, int64_t *nnz);
+// hierarchical matrix: block entries and the singular correction of near
+// blocks (k_dense.hip), build and apply (hmatrix.cpp, k_hmatrix.hip)
+void launch_hblock_entries(bem_problem &p, const int32_t *perm, const int4 *tiles, int64_t n_tiles,
+                           const HBlock *blocks, float2 *const *out);
+void launch_hblock_correction(bem_problem &p, const int2 *rows, int64_t n_rows, const HBlock *blocks,
+                              float2 *const *out, const int32_t *perm, const int32_t *iperm);
+void hmatrix_free(HMatrix *h);
+HMatrix *hmatrix_build(bem_problem &p, double eps, int leaf, double eta, bem_hmatrix_info *info);
+void hmatrix_apply(bem_problem &p, const double2 *x, double2 *y, int n_rhs, bool record);
 // y = V_k0 x on the union of all boundaries (k_single_layer.hip); events as in the apply
 void launch_single_layer(bem_problem &p, const double2 *x, double2 *y, bool record);
 

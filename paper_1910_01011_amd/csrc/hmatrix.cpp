@@ -1,0 +1,418 @@
+// Hierarchical matrix of the PMCHWT operator (the compression the paper uses
+// to go beyond dense storage, there with Bempp's H-matrices).
+//
+// Build:
+//  * cluster tree: the vertices of all boundaries are bisected recursively at
+//    the median of the longest axis of their bounding box, down to `leaf`
+//    vertices; the vertex order is permuted so that every cluster is a range;
+//  * block tree: a pair of clusters (s, t) is admissible when
+//    max(diam s, diam t) <= eta dist(s, t) (bounding boxes); admissible pairs
+//    become low-rank blocks, pairs of leaves dense blocks, others are split;
+//  * entries: every block's vertex-pair entries (the far-field sums of the
+//    dense assembly) are computed on the GPU; dense blocks get the FP64 singular
+//    correction (touching pairs never lie in admissible blocks);
+//  * low-rank blocks: adaptive cross approximation with complete pivoting to
+//    the relative tolerance eps, in batches; a block whose rank would not save
+//    storage is kept dense.
+// Apply: reorder x, one workgroup per block writes its products, each row sums
+// its blocks' products in a fixed order (no atomics; deterministic).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <memory>
+#include <numeric>
+#include <type_traits>
+#include <vector>
+
+#include "bem_internal.h"
+
+namespace bem {
+
+void launch_aca(hipStream_t s, const HBlock *blocks, const int32_t *ids, int n, float2 *const *R, float2 *const *U,
+                float2 *const *V, const int32_t *kmax, float eps, int32_t *rank);
+void launch_copy_list(hipStream_t s, const float2 *const *src, float2 *const *dst, const int64_t *count, int n);
+void launch_h_apply(hipStream_t s, const HBlock *blocks, int n_blocks, const int32_t *perm, const int32_t *rowD,
+                    const int32_t *rowN, const int32_t *rowptr, const int32_t *rowz, int64_t NV, const double2 *x,
+                    double2 *xp, double2 *z, double2 *y);
+
+namespace {
+
+constexpr int HK_CAP = 128;                       // largest rank kept (LDS of the apply kernel)
+constexpr int64_t ACA_BATCH_BYTES = int64_t(4) << 30;   // dense scratch of one batch of far blocks
+
+struct Cluster {
+    int32_t b, e;          // range in the permuted order
+    double lo[3], hi[3];   // bounding box
+    int32_t child[2];
+};
+
+struct DevMem {
+    void *p = nullptr;
+    DevMem() = default;
+    DevMem(const DevMem &) = delete;
+    DevMem &operator=(const DevMem &) = delete;
+    ~DevMem()
+    {
+        if (p) (void)hipFree(p);
+    }
+    template <typename T>
+    T *alloc(size_t n)
+    {
+        BEM_HIP(hipMalloc(&p, std::max<size_t>(1, n) * sizeof(T)));
+        return static_cast<T *>(p);
+    }
+};
+
+template <typename T>
+T *upload(const std::vector<T> &h, DevMem &m, hipStream_t s)
+{
+    T *d = m.alloc<T>(h.size());
+    if (!h.empty()) BEM_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return d;
+}
+
+double diam(const Cluster &c)
+{
+    double s = 0;
+    for (int d = 0; d < 3; ++d) s += (c.hi[d] - c.lo[d]) * (c.hi[d] - c.lo[d]);
+    return std::sqrt(s);
+}
+
+double dist(const Cluster &a, const Cluster &b)
+{
+    double s = 0;
+    for (int d = 0; d < 3; ++d) {
+        const double g = std::max({0.0, a.lo[d] - b.hi[d], b.lo[d] - a.hi[d]});
+        s += g * g;
+    }
+    return std::sqrt(s);
+}
+
+}  // namespace
+
+struct HMatrix {
+    std::vector<HBlock> blocks;
+    std::vector<void *> pools;   // device storage of the blocks
+    HBlock *d_blocks = nullptr;
+    int32_t *d_perm = nullptr, *d_rowptr = nullptr, *d_rowz = nullptr;
+    double2 *d_xp = nullptr, *d_z = nullptr;
+    int64_t z_len = 0;
+    bem_hmatrix_info info{};
+    ~HMatrix()
+    {
+        for (void *q : pools)
+            if (q) (void)hipFree(q);
+        void *ptrs[] = {d_blocks, d_perm, d_rowptr, d_rowz, d_xp, d_z};
+        for (void *q : ptrs)
+            if (q) (void)hipFree(q);
+    }
+};
+
+void hmatrix_free(HMatrix *h) { delete h; }
+
+static HMatrix *build(bem_problem &p, double eps, int leaf, double eta)
+{
+    const auto t_start = std::chrono::steady_clock::now();
+    const int64_t NV = p.NV;
+    hipStream_t s = p.stream;
+    // cluster tree
+    std::vector<int32_t> perm(NV);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::vector<Cluster> cl;
+    std::vector<int32_t> stack;
+    const auto make = [&](int32_t b, int32_t e) {
+        Cluster c{};
+        c.b = b;
+        c.e = e;
+        for (int d = 0; d < 3; ++d) {
+            c.lo[d] = 1e300;
+            c.hi[d] = -1e300;
+        }
+        for (int32_t i = b; i < e; ++i)
+            for (int d = 0; d < 3; ++d) {
+                const double x = p.h_verts[3 * size_t(perm[i]) + d];
+                c.lo[d] = std::min(c.lo[d], x);
+                c.hi[d] = std::max(c.hi[d], x);
+            }
+        c.child[0] = c.child[1] = -1;
+        cl.push_back(c);
+        return int32_t(cl.size() - 1);
+    };
+    stack.push_back(make(0, int32_t(NV)));
+    while (!stack.empty()) {
+        const int32_t ci = stack.back();
+        stack.pop_back();
+        const Cluster c = cl[ci];
+        if (c.e - c.b <= leaf) continue;
+        int ax = 0;
+        for (int d = 1; d < 3; ++d)
+            if (c.hi[d] - c.lo[d] > c.hi[ax] - c.lo[ax]) ax = d;
+        const int32_t mid = c.b + (c.e - c.b) / 2;
+        std::nth_element(perm.begin() + c.b, perm.begin() + mid, perm.begin() + c.e, [&](int32_t u, int32_t v) {
+            const double xu = p.h_verts[3 * size_t(u) + ax], xv = p.h_verts[3 * size_t(v) + ax];
+            return xu < xv || (xu == xv && u < v);
+        });
+        const int32_t c0 = make(c.b, mid), c1 = make(mid, c.e);
+        cl[ci].child[0] = c0;
+        cl[ci].child[1] = c1;
+        stack.push_back(c0);
+        stack.push_back(c1);
+    }
+    std::vector<int32_t> iperm(NV);
+    for (int64_t i = 0; i < NV; ++i) iperm[perm[i]] = int32_t(i);
+    // block tree
+    auto H = std::make_unique<HMatrix>();
+    std::vector<std::pair<int32_t, int32_t>> todo{{0, 0}};
+    std::vector<char> lowrank;
+    while (!todo.empty()) {
+        const auto [a, b] = todo.back();
+        todo.pop_back();
+        const Cluster &A = cl[a], &B = cl[b];
+        const bool adm = std::max(diam(A), diam(B)) <= eta * dist(A, B);
+        const bool la = A.child[0] < 0, lb = B.child[0] < 0;
+        if (adm || (la && lb)) {
+            HBlock hb{};
+            hb.r0 = A.b;
+            hb.r1 = A.e;
+            hb.c0 = B.b;
+            hb.c1 = B.e;
+            hb.rank = -1;
+            H->blocks.push_back(hb);
+            lowrank.push_back(adm ? 1 : 0);
+        } else if (la) {
+            todo.push_back({a, B.child[0]});
+            todo.push_back({a, B.child[1]});
+        } else if (lb) {
+            todo.push_back({A.child[0], b});
+            todo.push_back({A.child[1], b});
+        } else {
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j) todo.push_back({A.child[i], B.child[j]});
+        }
+    }
+    const int nb = int(H->blocks.size());
+    // product offsets and the per-row lists
+    int64_t zl = 0;
+    for (auto &hb : H->blocks) {
+        hb.zoff = zl;
+        zl += 2 * int64_t(hb.r1 - hb.r0);
+    }
+    if (zl >= (int64_t(1) << 31)) throw Error{BEM_ERR_UNSUPPORTED, "hierarchical matrix: too many block products"};
+    H->z_len = zl;
+    std::vector<int32_t> rowptr(2 * NV + 1, 0), rowz(zl);
+    for (const auto &hb : H->blocks)
+        for (int64_t r = 2 * int64_t(hb.r0); r < 2 * int64_t(hb.r1); ++r) rowptr[r + 1]++;
+    for (int64_t r = 0; r < 2 * NV; ++r) rowptr[r + 1] += rowptr[r];
+    {
+        std::vector<int32_t> fill(rowptr.begin(), rowptr.end() - 1);
+        for (const auto &hb : H->blocks)
+            for (int64_t a = 0; a < 2 * int64_t(hb.r1 - hb.r0); ++a)
+                rowz[fill[2 * int64_t(hb.r0) + a]++] = int32_t(hb.zoff + a);
+    }
+    // device copies that live with the matrix (owned by H)
+    const auto own = [&](auto &dst, const auto &h) {
+        using T = typename std::decay_t<decltype(h)>::value_type;
+        BEM_HIP(hipMalloc(&dst, std::max<size_t>(1, h.size()) * sizeof(T)));
+        if (!h.empty()) BEM_HIP(hipMemcpyAsync(dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    };
+    own(H->d_perm, perm);
+    own(H->d_rowptr, rowptr);
+    own(H->d_rowz, rowz);
+    BEM_HIP(hipMalloc(&H->d_xp, size_t(2 * NV) * sizeof(double2)));
+    BEM_HIP(hipMalloc(&H->d_z, size_t(std::max<int64_t>(1, zl)) * sizeof(double2)));
+    DevMem m_iperm;
+    int32_t *d_iperm = upload(iperm, m_iperm, s);
+
+    // dense storage size and low-rank rank caps
+    std::vector<int> far_ids, dense_ids;
+    for (int i = 0; i < nb; ++i) (lowrank[i] ? far_ids : dense_ids).push_back(i);
+    H->info.n_admissible = int64_t(far_ids.size());
+    const auto mn = [&](int i) {
+        const auto &hb = H->blocks[i];
+        return std::make_pair(2 * int64_t(hb.r1 - hb.r0), 2 * int64_t(hb.c1 - hb.c0));
+    };
+    const auto kcap = [&](int i) {
+        const auto [m2, n2] = mn(i);
+        // a rank-k block stores k (m2 + n2) values: keep it only if below m2 n2 / 2
+        return int(std::min<int64_t>(HK_CAP, std::max<int64_t>(1, m2 * n2 / (2 * (m2 + n2)))));
+    };
+    // far blocks: entries into scratch, ACA, compaction; batches by scratch size
+    std::sort(far_ids.begin(), far_ids.end(), [&](int u, int v) {
+        const auto a = mn(u), b = mn(v);
+        return a.first * a.second > b.first * b.second || (a.first * a.second == b.first * b.second && u < v);
+    });
+    BEM_HIP(hipMalloc(&H->d_blocks, std::max<size_t>(1, size_t(nb)) * sizeof(HBlock)));
+    const auto push_blocks = [&]() {
+        BEM_HIP(hipMemcpyAsync(H->d_blocks, H->blocks.data(), size_t(nb) * sizeof(HBlock), hipMemcpyHostToDevice, s));
+        BEM_HIP(hipStreamSynchronize(s));
+    };
+    const auto tiles_of = [&](const std::vector<int> &ids, std::vector<int4> &tiles) {
+        tiles.clear();
+        for (int i : ids) {
+            const auto &hb = H->blocks[i];
+            const int tm = (hb.r1 - hb.r0 + 15) / 16, tn = (hb.c1 - hb.c0 + 15) / 16;
+            for (int a = 0; a < tm; ++a)
+                for (int c = 0; c < tn; ++c) tiles.push_back(make_int4(i, a, c, 0));
+        }
+    };
+    std::vector<int> fallback;
+    push_blocks();
+    size_t fi = 0;
+    while (fi < far_ids.size()) {
+        std::vector<int> batch;
+        int64_t bytes = 0;
+        while (fi < far_ids.size()) {
+            const auto [m2, n2] = mn(far_ids[fi]);
+            const int64_t need = (m2 * n2 + int64_t(kcap(far_ids[fi])) * (m2 + n2)) * int64_t(sizeof(float2));
+            if (!batch.empty() && bytes + need > ACA_BATCH_BYTES) break;
+            batch.push_back(far_ids[fi++]);
+            bytes += need;
+        }
+        DevMem m_scr;
+        float2 *scr = m_scr.alloc<float2>(size_t(bytes / int64_t(sizeof(float2))));
+        std::vector<float2 *> Rp(nb, nullptr), Rb, Ub, Vb;
+        std::vector<int32_t> kb, ids32;
+        int64_t off = 0;
+        for (int i : batch) {
+            const auto [m2, n2] = mn(i);
+            const int k = kcap(i);
+            Rp[i] = scr + off;
+            Rb.push_back(scr + off);
+            off += m2 * n2;
+            Ub.push_back(scr + off);
+            off += int64_t(k) * m2;
+            Vb.push_back(scr + off);
+            off += int64_t(k) * n2;
+            kb.push_back(k);
+            ids32.push_back(i);
+        }
+        std::vector<int4> tiles;
+        tiles_of(batch, tiles);
+        DevMem m_rp, m_tiles, m_ids, m_R, m_U, m_V, m_k, m_rank;
+        float2 **d_rp = upload(Rp, m_rp, s);
+        int4 *d_tiles = upload(tiles, m_tiles, s);
+        launch_hblock_entries(p, H->d_perm, d_tiles, int64_t(tiles.size()), H->d_blocks, d_rp);
+        int32_t *d_ids = upload(ids32, m_ids, s);
+        float2 **d_R = upload(Rb, m_R, s), **d_U = upload(Ub, m_U, s), **d_V = upload(Vb, m_V, s);
+        int32_t *d_k = upload(kb, m_k, s);
+        int32_t *d_rank = m_rank.alloc<int32_t>(batch.size());
+        launch_aca(s, H->d_blocks, d_ids, int(batch.size()), d_R, d_U, d_V, d_k, float(eps), d_rank);
+        std::vector<int32_t> rank(batch.size());
+        BEM_HIP(hipMemcpyAsync(rank.data(), d_rank, rank.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        BEM_HIP(hipStreamSynchronize(s));
+        // compaction into storage of the exact size
+        int64_t keep = 0;
+        for (size_t j = 0; j < batch.size(); ++j)
+            if (rank[j] >= 0) {
+                const auto [m2, n2] = mn(batch[j]);
+                keep += int64_t(rank[j]) * (m2 + n2);
+            }
+        float2 *pool = nullptr;
+        BEM_HIP(hipMalloc(&pool, size_t(std::max<int64_t>(1, keep)) * sizeof(float2)));
+        H->pools.push_back(pool);
+        std::vector<const float2 *> src;
+        std::vector<float2 *> dst;
+        std::vector<int64_t> cnt;
+        int64_t po = 0;
+        for (size_t j = 0; j < batch.size(); ++j) {
+            HBlock &hb = H->blocks[batch[j]];
+            if (rank[j] < 0) {
+                fallback.push_back(batch[j]);
+                continue;
+            }
+            const auto [m2, n2] = mn(batch[j]);
+            hb.rank = rank[j];
+            hb.U = pool + po;
+            src.push_back(Ub[j]);
+            dst.push_back(hb.U);
+            cnt.push_back(int64_t(rank[j]) * m2);   // first rank columns (column-major)
+            po += int64_t(rank[j]) * m2;
+            hb.V = pool + po;
+            src.push_back(Vb[j]);
+            dst.push_back(hb.V);
+            cnt.push_back(int64_t(rank[j]) * n2);   // first rank rows (row-major)
+            po += int64_t(rank[j]) * n2;
+            H->info.max_rank = std::max(H->info.max_rank, rank[j]);
+            H->info.n_lowrank++;
+            H->info.bytes += (int64_t(rank[j]) * (m2 + n2)) * int64_t(sizeof(float2));
+        }
+        DevMem m_src, m_dst, m_cnt;
+        const float2 **d_src = upload(src, m_src, s);
+        float2 **d_dst = upload(dst, m_dst, s);
+        int64_t *d_cnt = upload(cnt, m_cnt, s);
+        launch_copy_list(s, d_src, d_dst, d_cnt, int(src.size()));
+        BEM_HIP(hipStreamSynchronize(s));
+    }
+    // dense blocks: near pairs of leaves, and far blocks the ACA did not compress
+    dense_ids.insert(dense_ids.end(), fallback.begin(), fallback.end());
+    int64_t dense_len = 0;
+    for (int i : dense_ids) {
+        const auto [m2, n2] = mn(i);
+        dense_len += m2 * n2;
+    }
+    float2 *dpool = nullptr;
+    BEM_HIP(hipMalloc(&dpool, size_t(std::max<int64_t>(1, dense_len)) * sizeof(float2)));
+    H->pools.push_back(dpool);
+    std::vector<float2 *> Dp(nb, nullptr);
+    {
+        int64_t off = 0;
+        for (int i : dense_ids) {
+            const auto [m2, n2] = mn(i);
+            HBlock &hb = H->blocks[i];
+            hb.rank = -1;
+            hb.D = dpool + off;
+            Dp[i] = hb.D;
+            off += m2 * n2;
+            H->info.n_dense++;
+        }
+        H->info.bytes += dense_len * int64_t(sizeof(float2));
+    }
+    push_blocks();
+    if (!dense_ids.empty()) {
+        std::vector<int4> tiles;
+        tiles_of(dense_ids, tiles);
+        std::vector<int2> rows;
+        for (int i : dense_ids) {
+            const auto &hb = H->blocks[i];
+            for (int a = 0; a < hb.r1 - hb.r0; ++a) rows.push_back(make_int2(i, a));
+        }
+        DevMem m_dp, m_tiles, m_rows;
+        float2 **d_dp = upload(Dp, m_dp, s);
+        int4 *d_tiles = upload(tiles, m_tiles, s);
+        int2 *d_rows = upload(rows, m_rows, s);
+        launch_hblock_entries(p, H->d_perm, d_tiles, int64_t(tiles.size()), H->d_blocks, d_dp);
+        launch_hblock_correction(p, d_rows, int64_t(rows.size()), H->d_blocks, d_dp, H->d_perm, d_iperm);
+    }
+    BEM_HIP(hipStreamSynchronize(s));
+    H->info.n_blocks = nb;
+    H->info.dense_bytes = 8 * int64_t(p.N) * int64_t(p.N);
+    H->info.build_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    return H.release();
+}
+
+void hmatrix_apply(bem_problem &p, const double2 *x, double2 *y, int n_rhs, bool record)
+{
+    HMatrix &H = *p.hm;
+    if (record) {
+        BEM_HIP(hipEventRecord(p.ev[0], p.stream));
+        BEM_HIP(hipEventRecord(p.ev[1], p.stream));
+    }
+    for (int r = 0; r < n_rhs; ++r)
+        launch_h_apply(p.stream, H.d_blocks, int(H.blocks.size()), H.d_perm, p.d_rowD, p.d_rowN, H.d_rowptr, H.d_rowz,
+                       p.NV, x + int64_t(r) * p.N, H.d_xp, H.d_z, y + int64_t(r) * p.N);
+    if (record) {
+        BEM_HIP(hipEventRecord(p.ev[2], p.stream));
+        BEM_HIP(hipEventRecord(p.ev[3], p.stream));
+        BEM_HIP(hipEventRecord(p.ev[4], p.stream));
+        p.timed = true;
+    }
+}
+
+HMatrix *hmatrix_build(bem_problem &p, double eps, int leaf, double eta, bem_hmatrix_info *info)
+{
+    HMatrix *h = build(p, eps, leaf, eta);
+    if (info) *info = h->info;
+    return h;
+}
+
+}  // namespace bem

@@ -9,6 +9,7 @@
 // Point-with-itself pairs are skipped (r = 0); the FP64 singular CSR is added
 // afterwards, as in the on-the-fly apply.  Row-major storage: A[r * n + c],
 // complex64 interleaved.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -152,48 +153,178 @@ __global__ void k_dense_correction(const int32_t *__restrict__ cptr, const int32
     }
 }
 
-void launch_assemble_dense(bem_problem &p)
+// Device inputs of the entry kernels: vertex records, domain of every vertex,
+// per-domain constants and the exterior ones.
+struct EntrySetup {
+    float4 *rec = nullptr;
+    int32_t *vdom = nullptr;
+    DenseDom *doms = nullptr;
+    DenseDom ext{};
+    bool att = false;
+    EntrySetup() = default;
+    EntrySetup(const EntrySetup &) = delete;
+    EntrySetup &operator=(const EntrySetup &) = delete;
+    ~EntrySetup()
+    {
+        if (rec) (void)hipFree(rec);
+        if (vdom) (void)hipFree(vdom);
+        if (doms) (void)hipFree(doms);
+    }
+};
+
+static void entry_setup(bem_problem &p, EntrySetup &E)
 {
     const int64_t n_corner = 3 * p.NT;
-    float4 *rec = nullptr;
-    BEM_HIP(hipMalloc(&rec, size_t(18 * n_corner) * sizeof(float4)));
+    BEM_HIP(hipMalloc(&E.rec, size_t(18 * n_corner) * sizeof(float4)));
     k_vertex_points<<<dim3(blocks_1d(6 * n_corner, 256)), dim3(256), 0, p.stream>>>(
-        p.d_v2t, n_corner, p.d_area, p.d_normal, p.d_curl, p.d_pts, p.M, rec);
+        p.d_v2t, n_corner, p.d_area, p.d_normal, p.d_curl, p.d_pts, p.M, E.rec);
     BEM_HIP(hipGetLastError());
     std::vector<int32_t> vdom(p.NV);
     std::vector<DenseDom> doms;
-    bool att = p.k0im != 0.0;
+    E.att = p.k0im != 0.0;
     for (size_t j = 0; j < p.doms.size(); ++j) {
         const auto &d = p.doms[j];
         for (int64_t i = 0; i < d.nv; ++i) vdom[d.v_off + i] = int32_t(j);
         doms.push_back(DenseDom{float(d.kre), float(d.kre / (2.0 * M_PI)), float(d.kim), float(d.rho / p.rho0),
                                 float(p.rho0 / d.rho), float(d.kre * d.kre - d.kim * d.kim), float(2.0 * d.kre * d.kim),
                                 0.0f});
-        att = att || d.kim != 0.0;
+        E.att = E.att || d.kim != 0.0;
     }
-    const DenseDom ext{float(p.k0re), float(p.k0re / (2.0 * M_PI)), float(p.k0im), 1.0f, 1.0f,
-                       float(p.k0re * p.k0re - p.k0im * p.k0im), float(2.0 * p.k0re * p.k0im), 0.0f};
-    int32_t *d_vdom = nullptr;
-    DenseDom *d_doms = nullptr;
-    BEM_HIP(hipMalloc(&d_vdom, vdom.size() * sizeof(int32_t)));
-    BEM_HIP(hipMalloc(&d_doms, doms.size() * sizeof(DenseDom)));
-    BEM_HIP(hipMemcpyAsync(d_vdom, vdom.data(), vdom.size() * sizeof(int32_t), hipMemcpyHostToDevice, p.stream));
-    BEM_HIP(hipMemcpyAsync(d_doms, doms.data(), doms.size() * sizeof(DenseDom), hipMemcpyHostToDevice, p.stream));
+    E.ext = DenseDom{float(p.k0re), float(p.k0re / (2.0 * M_PI)), float(p.k0im), 1.0f, 1.0f,
+                     float(p.k0re * p.k0re - p.k0im * p.k0im), float(2.0 * p.k0re * p.k0im), 0.0f};
+    BEM_HIP(hipMalloc(&E.vdom, vdom.size() * sizeof(int32_t)));
+    BEM_HIP(hipMalloc(&E.doms, doms.size() * sizeof(DenseDom)));
+    BEM_HIP(hipMemcpyAsync(E.vdom, vdom.data(), vdom.size() * sizeof(int32_t), hipMemcpyHostToDevice, p.stream));
+    BEM_HIP(hipMemcpyAsync(E.doms, doms.data(), doms.size() * sizeof(DenseDom), hipMemcpyHostToDevice, p.stream));
+    BEM_HIP(hipStreamSynchronize(p.stream));
+}
+
+void launch_assemble_dense(bem_problem &p)
+{
+    EntrySetup E;
+    entry_setup(p, E);
     const dim3 grid(unsigned((p.NV + 15) / 16), unsigned((p.NV + 15) / 16)), block(16, 16);
-    if (att)
-        k_assemble_dense<true><<<grid, block, 0, p.stream>>>(rec, p.d_v2t_ptr, d_vdom, d_doms, ext, p.d_rowD, p.d_rowN,
-                                                           p.NV, p.N, p.d_A);
+    if (E.att)
+        k_assemble_dense<true><<<grid, block, 0, p.stream>>>(E.rec, p.d_v2t_ptr, E.vdom, E.doms, E.ext, p.d_rowD,
+                                                           p.d_rowN, p.NV, p.N, p.d_A);
     else
-        k_assemble_dense<false><<<grid, block, 0, p.stream>>>(rec, p.d_v2t_ptr, d_vdom, d_doms, ext, p.d_rowD, p.d_rowN,
-                                                            p.NV, p.N, p.d_A);
+        k_assemble_dense<false><<<grid, block, 0, p.stream>>>(E.rec, p.d_v2t_ptr, E.vdom, E.doms, E.ext, p.d_rowD,
+                                                            p.d_rowN, p.NV, p.N, p.d_A);
     BEM_HIP(hipGetLastError());
     k_dense_correction<<<dim3(blocks_1d(p.NV, 256)), dim3(256), 0, p.stream>>>(
         p.d_cptr, p.d_ccol, p.d_cval, p.d_rowD, p.d_rowN, p.NV, p.N, p.d_A);
     BEM_HIP(hipGetLastError());
     BEM_HIP(hipStreamSynchronize(p.stream));
-    (void)hipFree(rec);
-    (void)hipFree(d_vdom);
-    (void)hipFree(d_doms);
+}
+
+// Entries of hierarchical-matrix blocks: tile (block, 16 row vertices, 16
+// column vertices) per workgroup; the 2 x 2 entries of a vertex pair (the same
+// sums as k_assemble_dense) go to a (2 m) x (2 n) column-major complex64 block
+// in interleaved (vertex, D/N) order: row 2 a + s, column 2 c + t.
+template <bool ATT>
+__global__ __launch_bounds__(256) void k_hblock_entries(const float4 *__restrict__ rec,
+                                                        const int32_t *__restrict__ v2t_ptr,
+                                                        const int32_t *__restrict__ vdom,
+                                                        const DenseDom *__restrict__ doms, DenseDom ext,
+                                                        const int32_t *__restrict__ perm, const int4 *__restrict__ tiles,
+                                                        const HBlock *__restrict__ blocks, float2 *const *__restrict__ out)
+{
+    const int4 tl = tiles[blockIdx.x];
+    const HBlock B = blocks[tl.x];
+    const int m = B.r1 - B.r0, n = B.c1 - B.c0;
+    const int a = tl.y * 16 + int(threadIdx.y), c = tl.z * 16 + int(threadIdx.x);
+    if (a >= m || c >= n) return;
+    const int64_t g = perm[B.r0 + a], h = perm[B.c0 + c];
+    const int dg = vdom[g];
+    const bool same = dg == vdom[h];
+    const DenseDom in = doms[dg];
+    Acc4 E = {0, 0, 0, 0, 0, 0, 0, 0}, I = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int32_t q0 = 6 * v2t_ptr[g], q1 = 6 * v2t_ptr[g + 1];
+    const int32_t p0 = 6 * v2t_ptr[h], p1 = 6 * v2t_ptr[h + 1];
+    for (int32_t kq = q0; kq < q1; ++kq) {
+        const float4 T0 = rec[3 * kq], T1 = rec[3 * kq + 1], T2 = rec[3 * kq + 2];
+        for (int32_t kp = p0; kp < p1; ++kp) {
+            const float4 S0 = rec[3 * kp], S1 = rec[3 * kp + 1], S2 = rec[3 * kp + 2];
+            const float dx = T0.x - S0.x, dy = T0.y - S0.y, dz = T0.z - S0.z;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            if (!(r2 > 0.0f)) continue;   // point with itself: singular correction
+            const float rinv = __builtin_amdgcn_rsqf(r2);
+            const float r = r2 * rinv;
+            const float ww = T0.w * S0.w * 12.566370614359172954f;
+            const float wcc = T1.w * S1.w * 12.566370614359172954f * fmaf(T2.x, S2.x, fmaf(T2.y, S2.y, T2.z * S2.z));
+            const float tK = fmaf(dx, S1.x, fmaf(dy, S1.y, dz * S1.z));
+            const float tKp = fmaf(dx, T1.x, fmaf(dy, T1.y, dz * T1.z));
+            const float nn = fmaf(T1.x, S1.x, fmaf(T1.y, S1.y, T1.z * S1.z));
+            dense_pair<ATT>(r, rinv, ww, wcc, tK, tKp, nn, ext.k, ext.k2pi, ext.kim, ext.k2re, ext.k2im, E);
+            if (same)
+                dense_pair<ATT>(r, rinv, ww, wcc, tK, tKp, nn, in.k, in.k2pi, in.kim, in.k2re, in.k2im, I);
+        }
+    }
+    const float sV = same ? in.sV : 0.0f, sW = same ? in.sW : 0.0f, s1 = same ? 1.0f : 0.0f;
+    float2 *D = out[tl.x];
+    const int64_t ld = 2 * int64_t(m);
+    D[(2 * int64_t(c)) * ld + 2 * a] = make_float2(-(E.kr + s1 * I.kr), -(E.ki + s1 * I.ki));        // DD
+    D[(2 * int64_t(c) + 1) * ld + 2 * a] = make_float2(E.vr + sV * I.vr, E.vi + sV * I.vi);           // DN
+    D[(2 * int64_t(c)) * ld + 2 * a + 1] = make_float2(E.wr + sW * I.wr, E.wi + sW * I.wi);           // ND
+    D[(2 * int64_t(c) + 1) * ld + 2 * a + 1] = make_float2(E.pr + s1 * I.pr, E.pi + s1 * I.pi);       // NN
+}
+
+// Block += singular correction: one thread per (listed block, row vertex); the
+// touching pairs of a row vertex whose column vertex lies in the block
+__global__ void k_hblock_correction(const int2 *__restrict__ rows, int64_t n_rows, const HBlock *__restrict__ blocks,
+                                    float2 *const *__restrict__ out, const int32_t *__restrict__ perm,
+                                    const int32_t *__restrict__ iperm, const int32_t *__restrict__ cptr,
+                                    const int32_t *__restrict__ ccol, const double2 *__restrict__ cval)
+{
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n_rows) return;
+    const int2 ra = rows[k];   // (block, local row vertex)
+    const HBlock B = blocks[ra.x];
+    const int64_t m = B.r1 - B.r0, ld = 2 * m;
+    const int32_t g = perm[B.r0 + ra.y];
+    float2 *D = out[ra.x];
+    for (int32_t e = cptr[g]; e < cptr[g + 1]; ++e) {
+        const int32_t hc = iperm[ccol[e]];
+        if (hc < B.c0 || hc >= B.c1) continue;
+        const int64_t c = hc - B.c0;
+        const int64_t idx[4] = {(2 * c) * ld + 2 * ra.y, (2 * c + 1) * ld + 2 * ra.y, (2 * c) * ld + 2 * ra.y + 1,
+                                (2 * c + 1) * ld + 2 * ra.y + 1};
+        for (int b = 0; b < 4; ++b) {
+            const float2 v = D[idx[b]];
+            const double2 cv = cval[4 * e + b];
+            D[idx[b]] = make_float2(float(double(v.x) + cv.x), float(double(v.y) + cv.y));
+        }
+    }
+}
+
+void launch_hblock_entries(bem_problem &p, const int32_t *perm, const int4 *tiles, int64_t n_tiles,
+                           const HBlock *blocks, float2 *const *out)
+{
+    if (n_tiles == 0) return;
+    EntrySetup E;
+    entry_setup(p, E);
+    const dim3 block(16, 16);
+    for (int64_t t0 = 0; t0 < n_tiles; t0 += (int64_t(1) << 30)) {
+        const unsigned nt = unsigned(std::min<int64_t>(n_tiles - t0, int64_t(1) << 30));
+        if (E.att)
+            k_hblock_entries<true><<<dim3(nt), block, 0, p.stream>>>(E.rec, p.d_v2t_ptr, E.vdom, E.doms, E.ext, perm,
+                                                                    tiles + t0, blocks, out);
+        else
+            k_hblock_entries<false><<<dim3(nt), block, 0, p.stream>>>(E.rec, p.d_v2t_ptr, E.vdom, E.doms, E.ext, perm,
+                                                                     tiles + t0, blocks, out);
+        BEM_HIP(hipGetLastError());
+    }
+    BEM_HIP(hipStreamSynchronize(p.stream));
+}
+
+void launch_hblock_correction(bem_problem &p, const int2 *rows, int64_t n_rows, const HBlock *blocks,
+                              float2 *const *out, const int32_t *perm, const int32_t *iperm)
+{
+    if (n_rows == 0) return;
+    k_hblock_correction<<<dim3(blocks_1d(n_rows, 256)), dim3(256), 0, p.stream>>>(rows, n_rows, blocks, out, perm, iperm,
+                                                                                 p.d_cptr, p.d_ccol, p.d_cval);
+    BEM_HIP(hipGetLastError());
+    BEM_HIP(hipStreamSynchronize(p.stream));
 }
 
 // y = A x, complex64 matrix, FP64 vectors and FP64 accumulation.  One wave per

@@ -97,7 +97,7 @@ def test_footprint_grows_with_rhs_and_restart():
     assert 0 < a < b < c
 
 
-@pytest.mark.parametrize("cname", ["bem_solve_opts", "bem_solve_info", "bem_assemble_opts"])
+@pytest.mark.parametrize("cname", ["bem_solve_opts", "bem_solve_info", "bem_assemble_opts", "bem_hmatrix_info"])
 def test_binding_structs_follow_the_header(cname):
     """The ctypes structures of the binding list the C structs' fields in the
     header's order (names as declared), so the two cannot drift apart."""
