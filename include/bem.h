@@ -105,7 +105,12 @@ typedef struct {
  *   BEM_PREC_FP32_MFMA_FGMRES   the same with the FP32 MFMA GEMM as inner operator
  *                               (any assembled mode)
  *   BEM_PREC_HMATRIX            plain GMRES (or OSRC-preconditioned GMRES) on the
- *                               hierarchical matrix of bem_hmatrix_build (any mode)
+ *                               hierarchical matrix of bem_hmatrix_build (any mode);
+ *                               the solution solves the compressed system
+ *   BEM_PREC_HMATRIX_FGMRES     flexible GMRES: outer Arnoldi on the FP32 operator of the
+ *                               problem's mode (on-the-fly kernel or dense GEMV) with its
+ *                               FP64 residual, inner GMRES on the hierarchical matrix to
+ *                               inner_tol (any mode)
  * With BEM_PRECOND_OSRC, plain GMRES runs on the left-preconditioned system
  * (stopping on the preconditioned residual); the flexible forms precondition
  * their inner solves (inner GMRES on P A z = P v) and keep stopping on the
@@ -116,6 +121,7 @@ typedef struct {
 #define BEM_PREC_SPLIT_BF16_FGMRES 1
 #define BEM_PREC_FP32_MFMA_FGMRES 2
 #define BEM_PREC_HMATRIX 3          /* GMRES on the hierarchical matrix of bem_hmatrix_build */
+#define BEM_PREC_HMATRIX_FGMRES 4   /* flexible GMRES, inner GMRES on the hierarchical matrix */
 
 typedef struct {
     double tol;          /* relative residual target (paper: 1e-5) */
@@ -125,8 +131,8 @@ typedef struct {
     int n_pade;          /* OSRC Pade terms */
     double r_eps;        /* OSRC damping length */
     double theta;        /* OSRC Pade branch-cut rotation */
-    int precision;       /* BEM_PREC_FP32, BEM_PREC_SPLIT_BF16_FGMRES, BEM_PREC_FP32_MFMA_FGMRES or
-                            BEM_PREC_HMATRIX */
+    int precision;       /* BEM_PREC_FP32, BEM_PREC_SPLIT_BF16_FGMRES, BEM_PREC_FP32_MFMA_FGMRES,
+                            BEM_PREC_HMATRIX or BEM_PREC_HMATRIX_FGMRES */
     double inner_tol;    /* inner tolerance of the flexible-GMRES refinement */
     int inner_restart;   /* inner GMRES restart length (0: 30) */
     int inner_max_iter;  /* inner iteration cap per outer step (0: 300) */

@@ -41,7 +41,7 @@ BEM_APPLY_HMATRIX = 6
 BEM_PLANE_WAVE, BEM_POINT_SOURCES, BEM_PISTON_ARRAY = 0, 1, 2
 BEM_PRECOND_NONE, BEM_PRECOND_OSRC = 0, 1
 BEM_PREC_FP32, BEM_PREC_SPLIT_BF16_FGMRES, BEM_PREC_FP32_MFMA_FGMRES = 0, 1, 2
-BEM_PREC_HMATRIX = 3
+BEM_PREC_HMATRIX, BEM_PREC_HMATRIX_FGMRES = 3, 4
 
 
 class bem_complex(ctypes.Structure):

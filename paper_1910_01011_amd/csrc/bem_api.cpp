@@ -657,9 +657,10 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
     if (o.inner_restart < 1 || o.inner_max_iter < 1)
         return fail(BEM_ERR_INVALID_ARG, "bem_solve: inner_restart and inner_max_iter must be positive (0: default)");
     if (o.precision != BEM_PREC_FP32 && o.precision != BEM_PREC_SPLIT_BF16_FGMRES &&
-        o.precision != BEM_PREC_FP32_MFMA_FGMRES && o.precision != BEM_PREC_HMATRIX)
+        o.precision != BEM_PREC_FP32_MFMA_FGMRES && o.precision != BEM_PREC_HMATRIX &&
+        o.precision != BEM_PREC_HMATRIX_FGMRES)
         return fail(BEM_ERR_INVALID_ARG, "bem_solve: unknown precision mode");
-    if (o.precision == BEM_PREC_HMATRIX && !p->hm)
+    if ((o.precision == BEM_PREC_HMATRIX || o.precision == BEM_PREC_HMATRIX_FGMRES) && !p->hm)
         return fail(BEM_ERR_INVALID_ARG, "bem_solve: no hierarchical matrix (bem_hmatrix_build)");
     if (o.precision == BEM_PREC_FP32_MFMA_FGMRES && p->mode == BEM_OTF)
         return fail(BEM_ERR_INVALID_ARG, "bem_solve: MFMA refinement needs an assembled problem");
@@ -731,12 +732,20 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
         } else {
             // flexible GMRES: outer Arnoldi on the FP32 matrix with FP64
             // accumulation, inner GMRES on the 3-term split-BF16 GEMM
-            const bem::ApplyFn outer = [&P](const double2 *X, double2 *Y, int R) {
+            // (for the hierarchical matrix: outer on the FP32 operator of the
+            // problem's mode, on the fly or dense; inner on the compressed one)
+            const bool hinner = o.precision == BEM_PREC_HMATRIX_FGMRES;
+            const bem::ApplyFn outer = [&P, &fp32_apply, hinner](const double2 *X, double2 *Y, int R) {
+                if (hinner) {
+                    fp32_apply(X, Y, R);
+                    return;
+                }
                 for (int r = 0; r < R; ++r) apply_dense_one(P, X + int64_t(r) * P.N, Y + int64_t(r) * P.N, true);
             };
             const bool bf16 = o.precision == BEM_PREC_SPLIT_BF16_FGMRES;
-            const bem::ApplyFn inner_op = [&P, bf16](const double2 *X, double2 *Y, int R) {
-                apply_dense_multi(P, X, Y, R, bf16, false);
+            const bem::ApplyFn inner_op = [&P, bf16, hinner](const double2 *X, double2 *Y, int R) {
+                if (hinner) bem::hmatrix_apply(P, X, Y, R, false);
+                else apply_dense_multi(P, X, Y, R, bf16, false);
             };
             const bem::KrylovOpts io{o.inner_tol, o.inner_restart, o.inner_max_iter, progress, "inner gmres"};
             bem::ApplyFn prec;

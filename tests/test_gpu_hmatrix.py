@@ -70,4 +70,12 @@ def test_hmatrix_against_dense_matrix_and_solve():
           f"dense-operator residual of the H solution {res:.2e}", flush=True)
     assert i_h[0]["converged"]
     assert res <= 2e-5
+    # flexible GMRES: outer residual on the dense FP32 matrix, inner on the
+    # compressed one; the solution meets the tolerance on the dense operator
+    uf, i_f = P.solve(b, bem.solve_options(tol=1e-7, restart=10, max_iter=20, precision=bem.BEM_PREC_HMATRIX_FGMRES,
+                                           inner_tol=1e-3, inner_restart=100, inner_max_iter=500))
+    res_f = _relerr(P.apply(uf[0], kernel=bem.BEM_APPLY_GEMV), b[0])
+    print(f"hmatrix FGMRES {i_f[0]}, dense-operator residual {res_f:.2e}, solution diff {_relerr(uf[0], ud[0]):.2e}",
+          flush=True)
+    assert i_f[0]["converged"] and res_f <= 1.5e-7
     P.close()
