@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <memory>
 #include <numeric>
 #include <type_traits>
@@ -38,6 +39,7 @@ void launch_h_apply(hipStream_t s, const HBlock *blocks, int n_blocks, const int
 namespace {
 
 constexpr int HK_CAP = 128;                       // largest rank kept (LDS of the apply kernel)
+constexpr int HBLOCK_MAX_SIDE = 512;              // vertices on a side of a low-rank block
 constexpr int64_t ACA_BATCH_BYTES = int64_t(4) << 30;   // dense scratch of one batch of far blocks
 
 struct Cluster {
@@ -110,7 +112,7 @@ struct HMatrix {
 
 void hmatrix_free(HMatrix *h) { delete h; }
 
-static HMatrix *build(bem_problem &p, double eps, int leaf, double eta)
+static HMatrix *build(bem_problem &p, double eps, int leaf, double eta, int max_side)
 {
     const auto t_start = std::chrono::steady_clock::now();
     const int64_t NV = p.NV;
@@ -168,7 +170,11 @@ static HMatrix *build(bem_problem &p, double eps, int leaf, double eta)
         const auto [a, b] = todo.back();
         todo.pop_back();
         const Cluster &A = cl[a], &B = cl[b];
-        const bool adm = std::max(diam(A), diam(B)) <= eta * dist(A, B);
+        // admissible pairs larger than max_side vertices on a side are split
+        // further: each block's cross approximation runs in one workgroup, so
+        // bounded blocks keep the whole chip busy
+        const bool adm = std::max(diam(A), diam(B)) <= eta * dist(A, B) && A.e - A.b <= max_side &&
+                         B.e - B.b <= max_side;
         const bool la = A.child[0] < 0, lb = B.child[0] < 0;
         if (adm || (la && lb)) {
             HBlock hb{};
@@ -410,7 +416,12 @@ void hmatrix_apply(bem_problem &p, const double2 *x, double2 *y, int n_rhs, bool
 
 HMatrix *hmatrix_build(bem_problem &p, double eps, int leaf, double eta, bem_hmatrix_info *info)
 {
-    HMatrix *h = build(p, eps, leaf, eta);
+    int max_side = HBLOCK_MAX_SIDE;
+    if (const char *e = std::getenv("BEM_HMATRIX_MAX_SIDE")) {   // for measurements of the split
+        const int v = std::atoi(e);
+        if (v >= leaf) max_side = v;
+    }
+    HMatrix *h = build(p, eps, leaf, eta, std::max(max_side, leaf));
     if (info) *info = h->info;
     return h;
 }
