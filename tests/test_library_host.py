@@ -59,6 +59,18 @@ def test_argument_errors():
     assert e.value.status == bem.BEM_ERR_INVALID_ARG
 
 
+def test_entry_points_reject_null_handles():
+    """Argument checks that run before any device call."""
+    import ctypes
+    bem = _bem()
+    L = bem._L
+    info = bem.bem_hmatrix_info()
+    assert L.bem_hmatrix_build(None, 1e-4, 64, 1.0, ctypes.byref(info)) == bem.BEM_ERR_INVALID_ARG
+    assert L.bem_apply_single_layer(None, None, None, 1) == bem.BEM_ERR_INVALID_ARG
+    assert L.bem_apply_with(None, None, None, 1, bem.BEM_APPLY_HMATRIX) == bem.BEM_ERR_INVALID_ARG
+    assert L.bem_evaluate_field(None, None, None, None, 0, None, None) == bem.BEM_ERR_INVALID_ARG
+
+
 def test_mesh_errors():
     bem = _bem()
     v, t = meshes.icosphere(1)
