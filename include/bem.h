@@ -190,7 +190,7 @@ bem_status bem_apply_parts(bem_problem *p, const bem_complex *x, bem_complex *y,
  *   BEM_APPLY_MFMA_SPLIT_BF16_W4  the same GEMM forced to its 256 x 128 four-wave tile
  *   BEM_APPLY_MFMA_SPLIT_BF16_W8  the same GEMM forced to its 384 x 128 eight-wave tile
  *                             (both with heuristic K slices; for tests and measurements)
- * On-the-fly problems accept only BEM_APPLY_DEFAULT. */
+ * On-the-fly problems accept BEM_APPLY_DEFAULT and BEM_APPLY_HMATRIX. */
 #define BEM_APPLY_DEFAULT 0
 #define BEM_APPLY_GEMV 1
 #define BEM_APPLY_MFMA_FP32 2
