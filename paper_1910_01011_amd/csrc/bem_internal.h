@@ -256,7 +256,10 @@ void run_singular(bem_problem &p, const std::vector<SingularItem> &items, int32_
                   double2 **cval, int64_t *nnz);
 // hierarchical matrix: block entries and the singular correction of near
 // blocks (k_dense.hip), build and apply (hmatrix.cpp, k_hmatrix.hip)
-void launch_hblock_entries(bem_problem &p, const int32_t *perm, const int4 *tiles, int64_t n_tiles,
+struct EntryCtx;   // device inputs of the entry kernel (vertex records, domain constants)
+EntryCtx *entry_ctx_create(bem_problem &p);
+void entry_ctx_free(EntryCtx *c);
+void launch_hblock_entries(bem_problem &p, EntryCtx *ctx, const int32_t *perm, const int4 *tiles, int64_t n_tiles,
                            const HBlock *blocks, float2 *const *out);
 void launch_hblock_correction(bem_problem &p, const int2 *rows, int64_t n_rows, const HBlock *blocks,
                               float2 *const *out, const int32_t *perm, const int32_t *iperm);

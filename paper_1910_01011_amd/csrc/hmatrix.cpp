@@ -4,7 +4,9 @@
 // Build:
 //  * cluster tree: the vertices of all boundaries are bisected recursively at
 //    the median of the longest axis of their bounding box, down to `leaf`
-//    vertices; the vertex order is permuted so that every cluster is a range;
+//    vertices; the vertex order is permuted so that every cluster is a range
+//    (complete pivoting copes with blocks that mix boundaries; splitting by
+//    boundary first was measured no better);
 //  * block tree: a pair of clusters (s, t) is admissible when
 //    max(diam s, diam t) <= eta dist(s, t) (bounding boxes); admissible pairs
 //    become low-rank blocks, pairs of leaves dense blocks, others are split;
@@ -263,50 +265,14 @@ static HMatrix *build(bem_problem &p, double eps, int leaf, double eta, int max_
     };
     std::vector<int> fallback;
     push_blocks();
-    size_t fi = 0;
-    while (fi < far_ids.size()) {
-        std::vector<int> batch;
-        int64_t bytes = 0;
-        while (fi < far_ids.size()) {
-            const auto [m2, n2] = mn(far_ids[fi]);
-            const int64_t need = (m2 * n2 + int64_t(kcap(far_ids[fi])) * (m2 + n2)) * int64_t(sizeof(float2));
-            if (!batch.empty() && bytes + need > ACA_BATCH_BYTES) break;
-            batch.push_back(far_ids[fi++]);
-            bytes += need;
-        }
-        DevMem m_scr;
-        float2 *scr = m_scr.alloc<float2>(size_t(bytes / int64_t(sizeof(float2))));
-        std::vector<float2 *> Rp(nb, nullptr), Rb, Ub, Vb;
-        std::vector<int32_t> kb, ids32;
-        int64_t off = 0;
-        for (int i : batch) {
-            const auto [m2, n2] = mn(i);
-            const int k = kcap(i);
-            Rp[i] = scr + off;
-            Rb.push_back(scr + off);
-            off += m2 * n2;
-            Ub.push_back(scr + off);
-            off += int64_t(k) * m2;
-            Vb.push_back(scr + off);
-            off += int64_t(k) * n2;
-            kb.push_back(k);
-            ids32.push_back(i);
-        }
-        std::vector<int4> tiles;
-        tiles_of(batch, tiles);
-        DevMem m_rp, m_tiles, m_ids, m_R, m_U, m_V, m_k, m_rank;
-        float2 **d_rp = upload(Rp, m_rp, s);
-        int4 *d_tiles = upload(tiles, m_tiles, s);
-        launch_hblock_entries(p, H->d_perm, d_tiles, int64_t(tiles.size()), H->d_blocks, d_rp);
-        int32_t *d_ids = upload(ids32, m_ids, s);
-        float2 **d_R = upload(Rb, m_R, s), **d_U = upload(Ub, m_U, s), **d_V = upload(Vb, m_V, s);
-        int32_t *d_k = upload(kb, m_k, s);
-        int32_t *d_rank = m_rank.alloc<int32_t>(batch.size());
-        launch_aca(s, H->d_blocks, d_ids, int(batch.size()), d_R, d_U, d_V, d_k, float(eps), d_rank);
-        std::vector<int32_t> rank(batch.size());
-        BEM_HIP(hipMemcpyAsync(rank.data(), d_rank, rank.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        BEM_HIP(hipStreamSynchronize(s));
-        // compaction into storage of the exact size
+    EntryCtx *ectx = entry_ctx_create(p);
+    struct CtxGuard {
+        EntryCtx *c;
+        ~CtxGuard() { entry_ctx_free(c); }
+    } ctx_guard{ectx};
+    // ranks -> storage of the exact size; blocks without a rank become dense
+    const auto compact = [&](const std::vector<int> &batch, const std::vector<int32_t> &rank,
+                             const std::vector<float2 *> &Ub, const std::vector<float2 *> &Vb) {
         int64_t keep = 0;
         for (size_t j = 0; j < batch.size(); ++j)
             if (rank[j] >= 0) {
@@ -348,6 +314,51 @@ static HMatrix *build(bem_problem &p, double eps, int leaf, double eta, int max_
         int64_t *d_cnt = upload(cnt, m_cnt, s);
         launch_copy_list(s, d_src, d_dst, d_cnt, int(src.size()));
         BEM_HIP(hipStreamSynchronize(s));
+    };
+    size_t fi = 0;
+    while (fi < far_ids.size()) {
+        std::vector<int> batch;
+        int64_t bytes = 0;
+        while (fi < far_ids.size()) {
+            const auto [m2, n2] = mn(far_ids[fi]);
+            const int64_t need = (m2 * n2 + int64_t(kcap(far_ids[fi])) * (m2 + n2)) * int64_t(sizeof(float2));
+            if (!batch.empty() && bytes + need > ACA_BATCH_BYTES) break;
+            batch.push_back(far_ids[fi++]);
+            bytes += need;
+        }
+        DevMem m_scr;
+        float2 *scr = m_scr.alloc<float2>(size_t(bytes / int64_t(sizeof(float2))));
+        std::vector<float2 *> Rp(nb, nullptr), Rb, Ub, Vb;
+        std::vector<int32_t> kb, ids32;
+        int64_t off = 0;
+        for (int i : batch) {
+            const auto [m2, n2] = mn(i);
+            const int k = kcap(i);
+            Rp[i] = scr + off;
+            Rb.push_back(scr + off);
+            off += m2 * n2;
+            Ub.push_back(scr + off);
+            off += int64_t(k) * m2;
+            Vb.push_back(scr + off);
+            off += int64_t(k) * n2;
+            kb.push_back(k);
+            ids32.push_back(i);
+        }
+        std::vector<int4> tiles;
+        tiles_of(batch, tiles);
+        DevMem m_rp, m_tiles, m_ids, m_R, m_U, m_V, m_k, m_rank;
+        float2 **d_rp = upload(Rp, m_rp, s);
+        int4 *d_tiles = upload(tiles, m_tiles, s);
+        launch_hblock_entries(p, ectx, H->d_perm, d_tiles, int64_t(tiles.size()), H->d_blocks, d_rp);
+        int32_t *d_ids = upload(ids32, m_ids, s);
+        float2 **d_R = upload(Rb, m_R, s), **d_U = upload(Ub, m_U, s), **d_V = upload(Vb, m_V, s);
+        int32_t *d_k = upload(kb, m_k, s);
+        int32_t *d_rank = m_rank.alloc<int32_t>(batch.size());
+        launch_aca(s, H->d_blocks, d_ids, int(batch.size()), d_R, d_U, d_V, d_k, float(eps), d_rank);
+        std::vector<int32_t> rank(batch.size());
+        BEM_HIP(hipMemcpyAsync(rank.data(), d_rank, rank.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        BEM_HIP(hipStreamSynchronize(s));
+        compact(batch, rank, Ub, Vb);
     }
     // dense blocks: near pairs of leaves, and far blocks the ACA did not compress
     dense_ids.insert(dense_ids.end(), fallback.begin(), fallback.end());
@@ -386,7 +397,7 @@ static HMatrix *build(bem_problem &p, double eps, int leaf, double eta, int max_
         float2 **d_dp = upload(Dp, m_dp, s);
         int4 *d_tiles = upload(tiles, m_tiles, s);
         int2 *d_rows = upload(rows, m_rows, s);
-        launch_hblock_entries(p, H->d_perm, d_tiles, int64_t(tiles.size()), H->d_blocks, d_dp);
+        launch_hblock_entries(p, ectx, H->d_perm, d_tiles, int64_t(tiles.size()), H->d_blocks, d_dp);
         launch_hblock_correction(p, d_rows, int64_t(rows.size()), H->d_blocks, d_dp, H->d_perm, d_iperm);
     }
     BEM_HIP(hipStreamSynchronize(s));

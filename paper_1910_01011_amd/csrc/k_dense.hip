@@ -297,12 +297,25 @@ __global__ void k_hblock_correction(const int2 *__restrict__ rows, int64_t n_row
     }
 }
 
-void launch_hblock_entries(bem_problem &p, const int32_t *perm, const int4 *tiles, int64_t n_tiles,
+EntryCtx *entry_ctx_create(bem_problem &p)
+{
+    auto *E = new EntrySetup;
+    try {
+        entry_setup(p, *E);
+    } catch (...) {
+        delete E;
+        throw;
+    }
+    return reinterpret_cast<EntryCtx *>(E);
+}
+
+void entry_ctx_free(EntryCtx *c) { delete reinterpret_cast<EntrySetup *>(c); }
+
+void launch_hblock_entries(bem_problem &p, EntryCtx *ctx, const int32_t *perm, const int4 *tiles, int64_t n_tiles,
                            const HBlock *blocks, float2 *const *out)
 {
     if (n_tiles == 0) return;
-    EntrySetup E;
-    entry_setup(p, E);
+    const EntrySetup &E = *reinterpret_cast<EntrySetup *>(ctx);
     const dim3 block(16, 16);
     for (int64_t t0 = 0; t0 < n_tiles; t0 += (int64_t(1) << 30)) {
         const unsigned nt = unsigned(std::min<int64_t>(n_tiles - t0, int64_t(1) << 30));
