@@ -27,7 +27,13 @@ def _relerr(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("prob", [configs.config1(), configs.two_spheres()], ids=lambda p: p.name)
+def _attenuating():
+    d = configs.config1().domains[0]
+    return configs.Problem([configs.Domain(d.vertices, d.triangles, complex(2.2, 0.15), 1.1, "sphere")],
+                           complex(2.0, 0.05), 1.0, "sphere642_attenuating")
+
+
+@pytest.mark.parametrize("prob", [configs.config1(), configs.two_spheres(), _attenuating()], ids=lambda p: p.name)
 def test_hmatrix_apply_matches_oracle(prob):
     import paper_1910_01011_amd as bem
     A = oracle.pmchwt_matrix(prob)
