@@ -98,6 +98,21 @@ void build_passes(bem_problem &p)
         p.passes.push_back(q);
     }
     p.n_pass = int(p.passes.size());
+    // largest phase of any pair: bounding-box diagonal of all vertices times
+    // the largest real wavenumber, in revolutions (the hardware sine and
+    // cosine reduce arguments below 256 revolutions themselves)
+    {
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int64_t i = 0; i < p.NV; ++i)
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = std::min(lo[d], p.h_verts[3 * size_t(i) + d]);
+                hi[d] = std::max(hi[d], p.h_verts[3 * size_t(i) + d]);
+            }
+        double diag = 0.0, kmax = 0.0;
+        for (int d = 0; d < 3; ++d) diag += (hi[d] - lo[d]) * (hi[d] - lo[d]);
+        for (const auto &q : p.passes) kmax = std::max(kmax, std::abs(q.kre));
+        p.wrap_phase = !(std::sqrt(diag) * kmax / (2.0 * M_PI) < 128.0);
+    }
     std::vector<bem::PassDev> dv;
     for (const auto &q : p.passes) {
         bem::PassDev d{};

@@ -152,6 +152,7 @@ struct bem_problem {
     int n_work = 0;
     int n_split = 8;
     int tpl = 1;                    // test points per lane of the pair kernel
+    bool wrap_phase = true;         // phases k r / 2 pi may reach 256 revolutions: reduce them in the kernel
     float4 *d_trial = nullptr;      // [M][4] trial records
     double *d_part = nullptr;       // [2][n_split][10][M]
     double *d_pot = nullptr;        // [M][10]

@@ -142,7 +142,7 @@ struct Acc {
     float dr, di, nr, ni, cxr, cxi, cyr, cyi, czr, czi;
 };
 
-template <bool ATT>
+template <bool ATT, bool WRAP>
 __device__ __forceinline__ void pair_step(const float xx, const float xy, const float xz, const float nx,
                                           const float ny, const float nz, const float4 L0, const float4 L1,
                                           const float4 L2, const float4 L3, const float4 L4, const float k,
@@ -155,7 +155,9 @@ __device__ __forceinline__ void pair_step(const float xx, const float xy, const 
     const float rinv = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
     const float r = r2 * rinv;
     float ph = r * k2pi;                       // phase in revolutions
-    ph = ph - rintf(ph);
+    // v_sin / v_cos take revolutions and reduce |ph| < 256 themselves; the
+    // explicit reduction is kept only when a pass's phases can exceed that
+    if (WRAP) ph = ph - rintf(ph);
     const float sn = __builtin_amdgcn_sinf(ph);  // sin(2 pi ph)
     const float cs = __builtin_amdgcn_cosf(ph);
     float gr = cs * rinv, gi = sn * rinv;
@@ -195,7 +197,7 @@ __device__ __forceinline__ void pair_step(const float xx, const float xy, const 
     a.czi = fmaf(gr, L4.w, fmaf(gi, L4.z, a.czi));
 }
 
-template <int TPL, bool ATT>
+template <int TPL, bool ATT, bool WRAP>
 __global__ __launch_bounds__(PAIR_BLOCK) void k_pairs(const int4 *__restrict__ work, const PassDev *__restrict__ passes,
                                                       const float *__restrict__ pts, const float *__restrict__ tnrm,
                                                       const float4 *__restrict__ trial, double *__restrict__ part,
@@ -259,7 +261,7 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pairs(const int4 *__restrict__ w
             const float4 L0 = lds[0][j], L1 = lds[1][j], L2 = lds[2][j], L3 = lds[3][j], L4 = lds[4][j];
 #pragma unroll
             for (int u = 0; u < TPL; ++u)
-                pair_step<ATT>(xx[u], xy[u], xz[u], nx[u], ny[u], nz[u], L0, L1, L2, L3, L4, P.k, P.k_over_2pi,
+                pair_step<ATT, WRAP>(xx[u], xy[u], xz[u], nx[u], ny[u], nz[u], L0, L1, L2, L3, L4, P.k, P.k_over_2pi,
                                P.kim, a[u]);
         }
 #pragma unroll
@@ -285,17 +287,24 @@ void launch_pairs(bem_problem &p)
     for (int i = 0; i < p.n_pass; ++i)
         if (p.passes[i].kim != 0.0) att = true;
     const dim3 grid(unsigned(p.n_work)), block(PAIR_BLOCK);
+#define PAIRS(T, A, W)                                                                                             \
+    k_pairs<T, A, W><<<grid, block, 0, p.stream>>>(p.d_work, p.d_pass, p.d_pts, p.d_tnrm, p.d_trial, p.d_part, p.M, \
+                                                   p.NT, p.n_split)
+    const bool w = p.wrap_phase;
     if (p.tpl == 2) {
-        if (att)
-            k_pairs<2, true><<<grid, block, 0, p.stream>>>(p.d_work, p.d_pass, p.d_pts, p.d_tnrm, p.d_trial, p.d_part, p.M, p.NT, p.n_split);
-        else
-            k_pairs<2, false><<<grid, block, 0, p.stream>>>(p.d_work, p.d_pass, p.d_pts, p.d_tnrm, p.d_trial, p.d_part, p.M, p.NT, p.n_split);
+        if (att) {
+            if (w) PAIRS(2, true, true); else PAIRS(2, true, false);
+        } else {
+            if (w) PAIRS(2, false, true); else PAIRS(2, false, false);
+        }
     } else {
-        if (att)
-            k_pairs<1, true><<<grid, block, 0, p.stream>>>(p.d_work, p.d_pass, p.d_pts, p.d_tnrm, p.d_trial, p.d_part, p.M, p.NT, p.n_split);
-        else
-            k_pairs<1, false><<<grid, block, 0, p.stream>>>(p.d_work, p.d_pass, p.d_pts, p.d_tnrm, p.d_trial, p.d_part, p.M, p.NT, p.n_split);
+        if (att) {
+            if (w) PAIRS(1, true, true); else PAIRS(1, true, false);
+        } else {
+            if (w) PAIRS(1, false, true); else PAIRS(1, false, false);
+        }
     }
+#undef PAIRS
     BEM_HIP(hipGetLastError());
 }
 

@@ -59,7 +59,7 @@ __global__ void k_gather_v(const double2 *__restrict__ x, const int32_t *__restr
 // through LDS and are read by broadcast.  FP32 sums within a tile, FP64 across
 // tiles.  The point paired with itself (r = 0) is skipped: the singular
 // correction accounts for it.
-template <int TPL, bool ATT>
+template <int TPL, bool ATT, bool WRAP>
 __global__ __launch_bounds__(SL_BLOCK) void k_pairs_v(const PassDev *__restrict__ pass0, const float *__restrict__ pts,
                                                       const float4 *__restrict__ rec, const float *__restrict__ rim,
                                                       double *__restrict__ part, int64_t M, int n_split)
@@ -109,8 +109,8 @@ __global__ __launch_bounds__(SL_BLOCK) void k_pairs_v(const PassDev *__restrict_
                 const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                 const float rinv = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
                 const float r = r2 * rinv;
-                float ph = r * k2pi;   // phase in revolutions
-                ph = ph - rintf(ph);
+                float ph = r * k2pi;   // phase in revolutions (v_sin / v_cos reduce |ph| < 256)
+                if (WRAP) ph = ph - rintf(ph);
                 float gr = __builtin_amdgcn_cosf(ph) * rinv, gi = __builtin_amdgcn_sinf(ph) * rinv;
                 if (ATT) {
                     const float damp = __expf(-kim * r);
@@ -187,9 +187,15 @@ static void launch_pairs_v(bem_problem &p, int tpl, int n_split, const float4 *r
     const bool att = p.passes[0].kim != 0.0;
     const int64_t nblk = (p.passes[0].test_end - p.passes[0].test_begin + SL_BLOCK * tpl - 1) / (SL_BLOCK * tpl);
     const dim3 grid(blocks_1d(nblk * n_split * SL_BLOCK, SL_BLOCK)), block(SL_BLOCK);
+#define SL_LAUNCH2(T, W)                                                                                              \
+    if (att) k_pairs_v<T, true, W><<<grid, block, 0, p.stream>>>(p.d_pass, p.d_pts, rec, rim, p.d_part, p.M, n_split); \
+    else k_pairs_v<T, false, W><<<grid, block, 0, p.stream>>>(p.d_pass, p.d_pts, rec, rim, p.d_part, p.M, n_split);
 #define SL_LAUNCH(T)                                                                                                  \
-    if (att) k_pairs_v<T, true><<<grid, block, 0, p.stream>>>(p.d_pass, p.d_pts, rec, rim, p.d_part, p.M, n_split);  \
-    else k_pairs_v<T, false><<<grid, block, 0, p.stream>>>(p.d_pass, p.d_pts, rec, rim, p.d_part, p.M, n_split);
+    if (p.wrap_phase) {                                                                                               \
+        SL_LAUNCH2(T, true)                                                                                           \
+    } else {                                                                                                          \
+        SL_LAUNCH2(T, false)                                                                                          \
+    }
     if (tpl == 4) {
         SL_LAUNCH(4)
     } else if (tpl == 2) {
@@ -198,6 +204,7 @@ static void launch_pairs_v(bem_problem &p, int tpl, int n_split, const float4 *r
         SL_LAUNCH(1)
     }
 #undef SL_LAUNCH
+#undef SL_LAUNCH2
     BEM_HIP(hipGetLastError());
 }
 
