@@ -57,12 +57,12 @@ struct Acc4 {
     float vr, vi, kr, ki, pr, pi, wr, wi;
 };
 
-template <bool ATT>
+template <bool ATT, bool WRAP>
 __device__ __forceinline__ void dense_pair(float r, float rinv, float ww, float wcc, float tK, float tKp, float nn,
                                            float k, float k2pi, float kim, float k2re, float k2im, Acc4 &A)
 {
     float ph = r * k2pi;
-    ph = ph - rintf(ph);
+    if (WRAP) ph = ph - rintf(ph);   // else the hardware sine and cosine reduce |ph| < 256 revolutions
     float gr = __builtin_amdgcn_cosf(ph) * rinv, gi = __builtin_amdgcn_sinf(ph) * rinv;
     const float kr = r * k, rinv2 = rinv * rinv;
     float fr, fi;
@@ -89,7 +89,7 @@ __device__ __forceinline__ void dense_pair(float r, float rinv, float ww, float 
     A.wi = fmaf(gr, ci, fmaf(gi, cr, A.wi));
 }
 
-template <bool ATT>
+template <bool ATT, bool WRAP>
 __global__ __launch_bounds__(256) void k_assemble_dense(const float4 *__restrict__ rec, const int32_t *__restrict__ v2t_ptr,
                                                         const int32_t *__restrict__ vdom, const DenseDom *__restrict__ doms,
                                                         DenseDom ext, const int32_t *__restrict__ rowD,
@@ -120,9 +120,9 @@ __global__ __launch_bounds__(256) void k_assemble_dense(const float4 *__restrict
             const float tK = fmaf(dx, S1.x, fmaf(dy, S1.y, dz * S1.z));
             const float tKp = fmaf(dx, T1.x, fmaf(dy, T1.y, dz * T1.z));
             const float nn = fmaf(T1.x, S1.x, fmaf(T1.y, S1.y, T1.z * S1.z));
-            dense_pair<ATT>(r, rinv, ww, wcc, tK, tKp, nn, ext.k, ext.k2pi, ext.kim, ext.k2re, ext.k2im, E);
+            dense_pair<ATT, WRAP>(r, rinv, ww, wcc, tK, tKp, nn, ext.k, ext.k2pi, ext.kim, ext.k2re, ext.k2im, E);
             if (same)
-                dense_pair<ATT>(r, rinv, ww, wcc, tK, tKp, nn, in.k, in.k2pi, in.kim, in.k2re, in.k2im, I);
+                dense_pair<ATT, WRAP>(r, rinv, ww, wcc, tK, tKp, nn, in.k, in.k2pi, in.kim, in.k2re, in.k2im, I);
         }
     }
     const float sV = same ? in.sV : 0.0f, sW = same ? in.sW : 0.0f, s1 = same ? 1.0f : 0.0f;
@@ -204,12 +204,15 @@ void launch_assemble_dense(bem_problem &p)
     EntrySetup E;
     entry_setup(p, E);
     const dim3 grid(unsigned((p.NV + 15) / 16), unsigned((p.NV + 15) / 16)), block(16, 16);
-    if (E.att)
-        k_assemble_dense<true><<<grid, block, 0, p.stream>>>(E.rec, p.d_v2t_ptr, E.vdom, E.doms, E.ext, p.d_rowD,
-                                                           p.d_rowN, p.NV, p.N, p.d_A);
-    else
-        k_assemble_dense<false><<<grid, block, 0, p.stream>>>(E.rec, p.d_v2t_ptr, E.vdom, E.doms, E.ext, p.d_rowD,
-                                                            p.d_rowN, p.NV, p.N, p.d_A);
+#define ASSEMBLE(A, W)                                                                                             \
+    k_assemble_dense<A, W><<<grid, block, 0, p.stream>>>(E.rec, p.d_v2t_ptr, E.vdom, E.doms, E.ext, p.d_rowD, p.d_rowN, \
+                                                         p.NV, p.N, p.d_A)
+    if (E.att) {
+        if (p.wrap_phase) ASSEMBLE(true, true); else ASSEMBLE(true, false);
+    } else {
+        if (p.wrap_phase) ASSEMBLE(false, true); else ASSEMBLE(false, false);
+    }
+#undef ASSEMBLE
     BEM_HIP(hipGetLastError());
     k_dense_correction<<<dim3(blocks_1d(p.NV, 256)), dim3(256), 0, p.stream>>>(
         p.d_cptr, p.d_ccol, p.d_cval, p.d_rowD, p.d_rowN, p.NV, p.N, p.d_A);
@@ -221,7 +224,7 @@ void launch_assemble_dense(bem_problem &p)
 // column vertices) per workgroup; the 2 x 2 entries of a vertex pair (the same
 // sums as k_assemble_dense) go to a (2 m) x (2 n) column-major complex64 block
 // in interleaved (vertex, D/N) order: row 2 a + s, column 2 c + t.
-template <bool ATT>
+template <bool ATT, bool WRAP>
 __global__ __launch_bounds__(256) void k_hblock_entries(const float4 *__restrict__ rec,
                                                         const int32_t *__restrict__ v2t_ptr,
                                                         const int32_t *__restrict__ vdom,
@@ -255,9 +258,9 @@ __global__ __launch_bounds__(256) void k_hblock_entries(const float4 *__restrict
             const float tK = fmaf(dx, S1.x, fmaf(dy, S1.y, dz * S1.z));
             const float tKp = fmaf(dx, T1.x, fmaf(dy, T1.y, dz * T1.z));
             const float nn = fmaf(T1.x, S1.x, fmaf(T1.y, S1.y, T1.z * S1.z));
-            dense_pair<ATT>(r, rinv, ww, wcc, tK, tKp, nn, ext.k, ext.k2pi, ext.kim, ext.k2re, ext.k2im, E);
+            dense_pair<ATT, WRAP>(r, rinv, ww, wcc, tK, tKp, nn, ext.k, ext.k2pi, ext.kim, ext.k2re, ext.k2im, E);
             if (same)
-                dense_pair<ATT>(r, rinv, ww, wcc, tK, tKp, nn, in.k, in.k2pi, in.kim, in.k2re, in.k2im, I);
+                dense_pair<ATT, WRAP>(r, rinv, ww, wcc, tK, tKp, nn, in.k, in.k2pi, in.kim, in.k2re, in.k2im, I);
         }
     }
     const float sV = same ? in.sV : 0.0f, sW = same ? in.sW : 0.0f, s1 = same ? 1.0f : 0.0f;
@@ -319,12 +322,15 @@ void launch_hblock_entries(bem_problem &p, EntryCtx *ctx, const int32_t *perm, c
     const dim3 block(16, 16);
     for (int64_t t0 = 0; t0 < n_tiles; t0 += (int64_t(1) << 30)) {
         const unsigned nt = unsigned(std::min<int64_t>(n_tiles - t0, int64_t(1) << 30));
-        if (E.att)
-            k_hblock_entries<true><<<dim3(nt), block, 0, p.stream>>>(E.rec, p.d_v2t_ptr, E.vdom, E.doms, E.ext, perm,
-                                                                    tiles + t0, blocks, out);
-        else
-            k_hblock_entries<false><<<dim3(nt), block, 0, p.stream>>>(E.rec, p.d_v2t_ptr, E.vdom, E.doms, E.ext, perm,
-                                                                     tiles + t0, blocks, out);
+#define ENTRIES(A, W)                                                                                              \
+    k_hblock_entries<A, W><<<dim3(nt), block, 0, p.stream>>>(E.rec, p.d_v2t_ptr, E.vdom, E.doms, E.ext, perm,          \
+                                                             tiles + t0, blocks, out)
+        if (E.att) {
+            if (p.wrap_phase) ENTRIES(true, true); else ENTRIES(true, false);
+        } else {
+            if (p.wrap_phase) ENTRIES(false, true); else ENTRIES(false, false);
+        }
+#undef ENTRIES
         BEM_HIP(hipGetLastError());
     }
     BEM_HIP(hipStreamSynchronize(p.stream));
