@@ -70,7 +70,10 @@ def sparing_excitation(h_focus, H_spare, ratio, mu_range=(1e-8, 1e8), steps=60):
     (scaled by the mean eigenvalue of H_s^H H_s).  Returns (a, info).
     """
     h = np.asarray(h_focus, dtype=np.complex128)
-    Hs = np.asarray(H_spare, dtype=np.complex128)
+    Hs = np.asarray(H_spare, dtype=np.complex128).reshape(-1, h.shape[0])
+    if Hs.shape[0] == 0:   # nothing to spare: the limit mu -> infinity
+        a = h.conj() / np.max(np.abs(h))
+        return a, {"mu": float("inf"), "exposure_ratio": 0.0, "met": True}
     G = Hs.conj().T @ Hs
     lam, Q = np.linalg.eigh(G)
     lam = np.maximum(lam, 0.0)

@@ -58,3 +58,11 @@ def test_loose_threshold_returns_near_conjugation():
     a, info = planning.sparing_excitation(h, Hs, ratio=0.5)
     cos = abs(np.vdot(a, h.conj())) / (np.linalg.norm(a) * np.linalg.norm(h))
     assert info["met"] and cos > 0.999
+
+
+def test_no_points_to_spare():
+    rng = np.random.default_rng(4)
+    h = _rand(rng, 8)
+    a, info = planning.sparing_excitation(h, np.zeros((0, 8)), ratio=0.1)
+    assert info["met"] and np.isclose(np.max(np.abs(a)), 1.0)
+    assert np.isclose(abs(h @ a), np.linalg.norm(h) ** 2 / np.max(np.abs(h)))
