@@ -89,26 +89,18 @@ __device__ __forceinline__ void dense_pair(float r, float rinv, float ww, float 
     A.wi = fmaf(gr, ci, fmaf(gi, cr, A.wi));
 }
 
+// Entry sums of vertex pair (g, h): the test records of g (global memory,
+// loaded once per test point) against the trial records of h (`trial`, in
+// LDS when staged), exterior pass and, on the same boundary, interior pass.
 template <bool ATT, bool WRAP>
-__global__ __launch_bounds__(256) void k_assemble_dense(const float4 *__restrict__ rec, const int32_t *__restrict__ v2t_ptr,
-                                                        const int32_t *__restrict__ vdom, const DenseDom *__restrict__ doms,
-                                                        DenseDom ext, const int32_t *__restrict__ rowD,
-                                                        const int32_t *__restrict__ rowN, int64_t NV, int64_t n,
-                                                        float2 *__restrict__ A)
+__device__ __forceinline__ void vertex_pair_sums(const float4 *__restrict__ rec, int32_t q0, int32_t q1,
+                                                 const float4 *trial, int cnt, const DenseDom &ext, const DenseDom &in,
+                                                 bool same, Acc4 &E, Acc4 &I)
 {
-    const int64_t g = int64_t(blockIdx.y) * 16 + threadIdx.y;
-    const int64_t h = int64_t(blockIdx.x) * 16 + threadIdx.x;
-    if (g >= NV || h >= NV) return;
-    const int dg = vdom[g];
-    const bool same = dg == vdom[h];
-    const DenseDom in = doms[dg];
-    Acc4 E = {0, 0, 0, 0, 0, 0, 0, 0}, I = {0, 0, 0, 0, 0, 0, 0, 0};
-    const int32_t q0 = 6 * v2t_ptr[g], q1 = 6 * v2t_ptr[g + 1];
-    const int32_t p0 = 6 * v2t_ptr[h], p1 = 6 * v2t_ptr[h + 1];
     for (int32_t kq = q0; kq < q1; ++kq) {
         const float4 T0 = rec[3 * kq], T1 = rec[3 * kq + 1], T2 = rec[3 * kq + 2];
-        for (int32_t kp = p0; kp < p1; ++kp) {
-            const float4 S0 = rec[3 * kp], S1 = rec[3 * kp + 1], S2 = rec[3 * kp + 2];
+        for (int kp = 0; kp < cnt; ++kp) {
+            const float4 S0 = trial[3 * kp], S1 = trial[3 * kp + 1], S2 = trial[3 * kp + 2];
             const float dx = T0.x - S0.x, dy = T0.y - S0.y, dz = T0.z - S0.z;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
             if (!(r2 > 0.0f)) continue;   // point with itself: singular correction
@@ -125,6 +117,63 @@ __global__ __launch_bounds__(256) void k_assemble_dense(const float4 *__restrict
                 dense_pair<ATT, WRAP>(r, rinv, ww, wcc, tK, tKp, nn, in.k, in.k2pi, in.kim, in.k2re, in.k2im, I);
         }
     }
+}
+
+constexpr int STAGE_MAX_DEGREE = 8;   // columns of higher degree: the tile reads global memory
+
+// Trial records of the tile's 16 column vertices (hv[c], -1 past the end) to
+// LDS, column c at float4 c * stride (stride = 18 D + 1 for the staged degree
+// D: odd, so the 16 columns start in different banks).  Returns false,
+// staging nothing, when a column has more than 6 D records; the tile then
+// reads them from global memory.  Every thread of the workgroup takes part.
+__device__ __forceinline__ bool stage_columns(const float4 *__restrict__ rec, const int32_t *__restrict__ v2t_ptr,
+                                              const int64_t *hv, int stride, float4 *srec, int *cnt)
+{
+    const int tid = threadIdx.y * 16 + threadIdx.x;
+    if (tid < 16) cnt[tid] = hv[tid] >= 0 ? 6 * (v2t_ptr[hv[tid] + 1] - v2t_ptr[hv[tid]]) : 0;
+    __syncthreads();
+    bool fits = true;
+    for (int c = 0; c < 16; ++c) fits = fits && 3 * cnt[c] < stride;
+    if (fits)
+        for (int c = 0; c < 16; ++c) {
+            if (hv[c] < 0) continue;
+            const int64_t p0 = 6 * int64_t(v2t_ptr[hv[c]]);
+            for (int e = tid; e < 3 * cnt[c]; e += 256) srec[c * stride + e] = rec[3 * p0 + e];
+        }
+    __syncthreads();
+    return fits;
+}
+
+// Dense matrix, one 16 x 16 tile of vertex pairs per workgroup; the trial
+// records of the tile's columns are read from LDS (every one is used by the 16
+// rows of the tile) unless one has more than the staged degree.
+template <bool ATT, bool WRAP>
+__global__ __launch_bounds__(256) void k_assemble_dense(const float4 *__restrict__ rec, const int32_t *__restrict__ v2t_ptr,
+                                                        const int32_t *__restrict__ vdom, const DenseDom *__restrict__ doms,
+                                                        DenseDom ext, const int32_t *__restrict__ rowD,
+                                                        const int32_t *__restrict__ rowN, int64_t NV, int64_t n,
+                                                        float2 *__restrict__ A, int stride)
+{
+    extern __shared__ float4 srec[];
+    __shared__ int cnt[16];
+    __shared__ int64_t hv[16];
+    const int64_t g = int64_t(blockIdx.y) * 16 + threadIdx.y;
+    const int64_t h = int64_t(blockIdx.x) * 16 + threadIdx.x;
+    const int tid = threadIdx.y * 16 + threadIdx.x;
+    if (tid < 16) hv[tid] = int64_t(blockIdx.x) * 16 + tid < NV ? int64_t(blockIdx.x) * 16 + tid : -1;
+    __syncthreads();
+    const bool staged = stage_columns(rec, v2t_ptr, hv, stride, srec, cnt);
+    if (g >= NV || h >= NV) return;
+    const int dg = vdom[g];
+    const bool same = dg == vdom[h];
+    const DenseDom in = doms[dg];
+    Acc4 E = {0, 0, 0, 0, 0, 0, 0, 0}, I = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int32_t q0 = 6 * v2t_ptr[g], q1 = 6 * v2t_ptr[g + 1];
+    if (staged)
+        vertex_pair_sums<ATT, WRAP>(rec, q0, q1, srec + threadIdx.x * stride, cnt[threadIdx.x], ext, in, same, E, I);
+    else
+        vertex_pair_sums<ATT, WRAP>(rec, q0, q1, rec + 3 * int64_t(6 * v2t_ptr[h]), 6 * (v2t_ptr[h + 1] - v2t_ptr[h]),
+                                    ext, in, same, E, I);
     const float sV = same ? in.sV : 0.0f, sW = same ? in.sW : 0.0f, s1 = same ? 1.0f : 0.0f;
     const int64_t rD = rowD[g], rN = rowN[g], cD = rowD[h], cN = rowN[h];
     A[rD * n + cD] = make_float2(-(E.kr + s1 * I.kr), -(E.ki + s1 * I.ki));
@@ -161,6 +210,8 @@ struct EntrySetup {
     DenseDom *doms = nullptr;
     DenseDom ext{};
     bool att = false;
+    int stride = 0;          // float4 per staged column (18 D + 1 for the staged degree D)
+    size_t lds_bytes = 0;    // 16 staged columns
     EntrySetup() = default;
     EntrySetup(const EntrySetup &) = delete;
     EntrySetup &operator=(const EntrySetup &) = delete;
@@ -196,6 +247,14 @@ static void entry_setup(bem_problem &p, EntrySetup &E)
     BEM_HIP(hipMalloc(&E.doms, doms.size() * sizeof(DenseDom)));
     BEM_HIP(hipMemcpyAsync(E.vdom, vdom.data(), vdom.size() * sizeof(int32_t), hipMemcpyHostToDevice, p.stream));
     BEM_HIP(hipMemcpyAsync(E.doms, doms.data(), doms.size() * sizeof(DenseDom), hipMemcpyHostToDevice, p.stream));
+    // staged degree: the mesh's largest, at most STAGE_MAX_DEGREE (LDS per
+    // workgroup 16 (18 D + 1) float4: 28 KB at D = 6)
+    std::vector<int32_t> deg(p.NV, 0);
+    for (int64_t i = 0; i < 3 * p.NT; ++i) deg[p.h_tris[i]]++;
+    const int maxdeg = p.NV > 0 ? *std::max_element(deg.begin(), deg.end()) : 1;
+    const int D = std::max(1, std::min(maxdeg, STAGE_MAX_DEGREE));
+    E.stride = 18 * D + 1;
+    E.lds_bytes = size_t(16) * E.stride * sizeof(float4);
     BEM_HIP(hipStreamSynchronize(p.stream));
 }
 
@@ -205,8 +264,8 @@ void launch_assemble_dense(bem_problem &p)
     entry_setup(p, E);
     const dim3 grid(unsigned((p.NV + 15) / 16), unsigned((p.NV + 15) / 16)), block(16, 16);
 #define ASSEMBLE(A, W)                                                                                             \
-    k_assemble_dense<A, W><<<grid, block, 0, p.stream>>>(E.rec, p.d_v2t_ptr, E.vdom, E.doms, E.ext, p.d_rowD, p.d_rowN, \
-                                                         p.NV, p.N, p.d_A)
+    k_assemble_dense<A, W><<<grid, block, E.lds_bytes, p.stream>>>(E.rec, p.d_v2t_ptr, E.vdom, E.doms, E.ext, p.d_rowD, \
+                                                                   p.d_rowN, p.NV, p.N, p.d_A, E.stride)
     if (E.att) {
         if (p.wrap_phase) ASSEMBLE(true, true); else ASSEMBLE(true, false);
     } else {
@@ -230,12 +289,20 @@ __global__ __launch_bounds__(256) void k_hblock_entries(const float4 *__restrict
                                                         const int32_t *__restrict__ vdom,
                                                         const DenseDom *__restrict__ doms, DenseDom ext,
                                                         const int32_t *__restrict__ perm, const int4 *__restrict__ tiles,
-                                                        const HBlock *__restrict__ blocks, float2 *const *__restrict__ out)
+                                                        const HBlock *__restrict__ blocks, float2 *const *__restrict__ out,
+                                                        int stride)
 {
+    extern __shared__ float4 srec[];
+    __shared__ int cnt[16];
+    __shared__ int64_t hv[16];
     const int4 tl = tiles[blockIdx.x];
     const HBlock B = blocks[tl.x];
     const int m = B.r1 - B.r0, n = B.c1 - B.c0;
     const int a = tl.y * 16 + int(threadIdx.y), c = tl.z * 16 + int(threadIdx.x);
+    const int tid = threadIdx.y * 16 + threadIdx.x;
+    if (tid < 16) hv[tid] = tl.z * 16 + tid < n ? int64_t(perm[B.c0 + tl.z * 16 + tid]) : -1;
+    __syncthreads();
+    const bool staged = stage_columns(rec, v2t_ptr, hv, stride, srec, cnt);
     if (a >= m || c >= n) return;
     const int64_t g = perm[B.r0 + a], h = perm[B.c0 + c];
     const int dg = vdom[g];
@@ -243,26 +310,11 @@ __global__ __launch_bounds__(256) void k_hblock_entries(const float4 *__restrict
     const DenseDom in = doms[dg];
     Acc4 E = {0, 0, 0, 0, 0, 0, 0, 0}, I = {0, 0, 0, 0, 0, 0, 0, 0};
     const int32_t q0 = 6 * v2t_ptr[g], q1 = 6 * v2t_ptr[g + 1];
-    const int32_t p0 = 6 * v2t_ptr[h], p1 = 6 * v2t_ptr[h + 1];
-    for (int32_t kq = q0; kq < q1; ++kq) {
-        const float4 T0 = rec[3 * kq], T1 = rec[3 * kq + 1], T2 = rec[3 * kq + 2];
-        for (int32_t kp = p0; kp < p1; ++kp) {
-            const float4 S0 = rec[3 * kp], S1 = rec[3 * kp + 1], S2 = rec[3 * kp + 2];
-            const float dx = T0.x - S0.x, dy = T0.y - S0.y, dz = T0.z - S0.z;
-            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            if (!(r2 > 0.0f)) continue;   // point with itself: singular correction
-            const float rinv = __builtin_amdgcn_rsqf(r2);
-            const float r = r2 * rinv;
-            const float ww = T0.w * S0.w * 12.566370614359172954f;
-            const float wcc = T1.w * S1.w * 12.566370614359172954f * fmaf(T2.x, S2.x, fmaf(T2.y, S2.y, T2.z * S2.z));
-            const float tK = fmaf(dx, S1.x, fmaf(dy, S1.y, dz * S1.z));
-            const float tKp = fmaf(dx, T1.x, fmaf(dy, T1.y, dz * T1.z));
-            const float nn = fmaf(T1.x, S1.x, fmaf(T1.y, S1.y, T1.z * S1.z));
-            dense_pair<ATT, WRAP>(r, rinv, ww, wcc, tK, tKp, nn, ext.k, ext.k2pi, ext.kim, ext.k2re, ext.k2im, E);
-            if (same)
-                dense_pair<ATT, WRAP>(r, rinv, ww, wcc, tK, tKp, nn, in.k, in.k2pi, in.kim, in.k2re, in.k2im, I);
-        }
-    }
+    if (staged)
+        vertex_pair_sums<ATT, WRAP>(rec, q0, q1, srec + threadIdx.x * stride, cnt[threadIdx.x], ext, in, same, E, I);
+    else
+        vertex_pair_sums<ATT, WRAP>(rec, q0, q1, rec + 3 * int64_t(6 * v2t_ptr[h]), 6 * (v2t_ptr[h + 1] - v2t_ptr[h]),
+                                    ext, in, same, E, I);
     const float sV = same ? in.sV : 0.0f, sW = same ? in.sW : 0.0f, s1 = same ? 1.0f : 0.0f;
     float2 *D = out[tl.x];
     const int64_t ld = 2 * int64_t(m);
@@ -323,8 +375,8 @@ void launch_hblock_entries(bem_problem &p, EntryCtx *ctx, const int32_t *perm, c
     for (int64_t t0 = 0; t0 < n_tiles; t0 += (int64_t(1) << 30)) {
         const unsigned nt = unsigned(std::min<int64_t>(n_tiles - t0, int64_t(1) << 30));
 #define ENTRIES(A, W)                                                                                              \
-    k_hblock_entries<A, W><<<dim3(nt), block, 0, p.stream>>>(E.rec, p.d_v2t_ptr, E.vdom, E.doms, E.ext, perm,          \
-                                                             tiles + t0, blocks, out)
+    k_hblock_entries<A, W><<<dim3(nt), block, E.lds_bytes, p.stream>>>(E.rec, p.d_v2t_ptr, E.vdom, E.doms, E.ext, perm, \
+                                                                       tiles + t0, blocks, out, E.stride)
         if (E.att) {
             if (p.wrap_phase) ENTRIES(true, true); else ENTRIES(true, false);
         } else {
