@@ -401,6 +401,17 @@ static HMatrix *build(bem_problem &p, double eps, int leaf, double eta, int max_
         launch_hblock_correction(p, d_rows, int64_t(rows.size()), H->d_blocks, d_dp, H->d_perm, d_iperm);
     }
     BEM_HIP(hipStreamSynchronize(s));
+    // the apply launches the blocks largest first (each carries its own
+    // product offset, so the order changes no sum) to shorten the tail
+    const auto stored = [&](const HBlock &hb) {
+        const int64_t m2 = 2 * int64_t(hb.r1 - hb.r0), n2 = 2 * int64_t(hb.c1 - hb.c0);
+        return hb.rank < 0 ? m2 * n2 : int64_t(hb.rank) * (m2 + n2);
+    };
+    std::sort(H->blocks.begin(), H->blocks.end(), [&](const HBlock &u, const HBlock &v) {
+        const int64_t a = stored(u), b = stored(v);
+        return a > b || (a == b && u.zoff < v.zoff);
+    });
+    push_blocks();
     H->info.n_blocks = nb;
     H->info.dense_bytes = 8 * int64_t(p.N) * int64_t(p.N);
     H->info.build_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();

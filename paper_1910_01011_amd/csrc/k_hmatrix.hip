@@ -153,75 +153,214 @@ __global__ void k_h_gather(const int32_t *__restrict__ perm, const int32_t *__re
     xp[r] = x[(r & 1) ? rowN[g] : rowD[g]];
 }
 
-// one workgroup per block: z[zoff + a] = (D x_J)[a], or (U (V x_J))[a] with the
-// r values V x_J reduced per wave and kept in LDS; FP64 sums
-__global__ __launch_bounds__(256) void k_h_blocks(const HBlock *__restrict__ blocks, const double2 *__restrict__ xp,
-                                                  double2 *__restrict__ z)
+constexpr int HB_THREADS = 256;
+constexpr int HB_XS_MAX = 1024;   // columns of x_J staged in LDS for V x_J
+
+__device__ __forceinline__ void cmac(double &sr, double &si, float dx, float dy, double2 v)
 {
-    __shared__ double2 t[HK_MAX];
-    const HBlock B = blocks[blockIdx.x];
-    const int64_t m2 = 2 * int64_t(B.r1 - B.r0), n2 = 2 * int64_t(B.c1 - B.c0);
-    const double2 *xj = xp + 2 * int64_t(B.c0);
-    double2 *zb = z + B.zoff;
-    if (B.rank < 0) {
-        for (int64_t a = threadIdx.x; a < m2; a += blockDim.x) {
-            double sr = 0.0, si = 0.0;
-            for (int64_t c = 0; c < n2; ++c) {
-                const float2 d = B.D[c * m2 + a];
-                const double2 v = xj[c];
-                sr += double(d.x) * v.x - double(d.y) * v.y;
-                si += double(d.x) * v.y + double(d.y) * v.x;
+    sr += double(dx) * v.x - double(dy) * v.y;
+    si += double(dx) * v.y + double(dy) * v.x;
+}
+
+// zb = A v for a column-major (2 m) x ncol complex64 matrix A, rows taken in
+// pairs (one 16-byte load holds rows 2 j and 2 j + 1 of a column).  With
+// m <= 128 the columns are split over G = 256 / m thread groups whose FP64
+// partial sums are added in group order through LDS; larger m loop over row
+// pairs with all columns per thread.  Every thread of the workgroup calls it.
+__device__ __forceinline__ void colmajor_apply(const float2 *__restrict__ A, int m, int64_t ncol, const double2 *vec,
+                               double2 *__restrict__ zb, double2 *part)
+{
+    const int tid = threadIdx.x;
+    const int P = min(m, HB_THREADS), G = HB_THREADS / P;
+    const int j0 = tid % P, g = tid / P;
+    const float4 *A4 = reinterpret_cast<const float4 *>(A);
+    if (G == 1) {
+        if (g != 0) return;
+        for (int j = j0; j < m; j += P) {
+            double ar = 0, ai = 0, br = 0, bi = 0;
+            int64_t c = 0;
+            for (; c + 4 <= ncol; c += 4) {
+                float4 d[4];
+                double2 v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    d[u] = A4[(c + u) * m + j];
+                    v[u] = vec[c + u];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    cmac(ar, ai, d[u].x, d[u].y, v[u]);
+                    cmac(br, bi, d[u].z, d[u].w, v[u]);
+                }
             }
-            zb[a] = make_double2(sr, si);
+            for (; c < ncol; ++c) {
+                const float4 d = A4[c * m + j];
+                const double2 v = vec[c];
+                cmac(ar, ai, d.x, d.y, v);
+                cmac(br, bi, d.z, d.w, v);
+            }
+            zb[2 * j] = make_double2(ar, ai);
+            zb[2 * j + 1] = make_double2(br, bi);
         }
         return;
     }
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int k = w; k < B.rank; k += nw) {
-        double sr = 0.0, si = 0.0;
-        const float2 *vk = B.V + int64_t(k) * n2;
-        for (int64_t c = lane; c < n2; c += 64) {
-            const float2 d = vk[c];
-            const double2 v = xj[c];
-            sr += double(d.x) * v.x - double(d.y) * v.y;
-            si += double(d.x) * v.y + double(d.y) * v.x;
+    // m <= 128: one row pair per thread, G >= 2 column groups
+    double ar = 0, ai = 0, br = 0, bi = 0;
+    if (g < G) {
+        int64_t c = g;
+        for (; c + 3 * G < ncol; c += 4 * G) {
+            float4 d[4];
+            double2 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                d[u] = A4[(c + u * G) * m + j0];
+                v[u] = vec[c + u * G];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                cmac(ar, ai, d[u].x, d[u].y, v[u]);
+                cmac(br, bi, d[u].z, d[u].w, v[u]);
+            }
         }
-        for (int off = 32; off > 0; off >>= 1) {
-            sr += __shfl_xor(sr, off);
-            si += __shfl_xor(si, off);
+        for (; c < ncol; c += G) {
+            const float4 d = A4[c * m + j0];
+            const double2 v = vec[c];
+            cmac(ar, ai, d.x, d.y, v);
+            cmac(br, bi, d.z, d.w, v);
         }
-        if (lane == 0) t[k] = make_double2(sr, si);
     }
+    part[2 * tid] = make_double2(ar, ai);
+    part[2 * tid + 1] = make_double2(br, bi);
     __syncthreads();
-    for (int64_t a = threadIdx.x; a < m2; a += blockDim.x) {
-        double sr = 0.0, si = 0.0;
-        for (int k = 0; k < B.rank; ++k) {
-            const float2 u = B.U[int64_t(k) * m2 + a];
-            const double2 v = t[k];
-            sr += double(u.x) * v.x - double(u.y) * v.y;
-            si += double(u.x) * v.y + double(u.y) * v.x;
+    if (g == 0) {
+        double sr0 = 0, si0 = 0, sr1 = 0, si1 = 0;
+        for (int q = 0; q < G; ++q) {
+            const double2 a = part[2 * (q * P + j0)], b = part[2 * (q * P + j0) + 1];
+            sr0 += a.x;
+            si0 += a.y;
+            sr1 += b.x;
+            si1 += b.y;
         }
-        zb[a] = make_double2(sr, si);
+        zb[2 * j0] = make_double2(sr0, si0);
+        zb[2 * j0 + 1] = make_double2(sr1, si1);
     }
 }
 
-// y[row_s(perm[i])] = sum of the block products of reordered row 2 i + s, in
-// the fixed order of the row's list
+// t[k + i dk] (+)= row k + i dk of V (columns c0 ... c0 + 2 np - 1) times the
+// staged x_J chunk, for i < NR rows at once so that the loads of one row are in
+// flight while another is reduced; whole-wave call, lane 0 writes
+template <int NR>
+__device__ __forceinline__ void v_rows(const float2 *__restrict__ V, int64_t n2, int64_t c0, int np, int k, int dk,
+                                       const double2 *xs, double2 *t)
+{
+    const int lane = threadIdx.x & 63;
+    double sr[NR], si[NR];
+    const float4 *vk[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        sr[i] = si[i] = 0.0;
+        vk[i] = reinterpret_cast<const float4 *>(V + int64_t(k + i * dk) * n2 + c0);
+    }
+    int cp = lane;
+    for (; cp + 64 < np; cp += 128) {
+        float4 d0[NR], d1[NR];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            d0[i] = vk[i][cp];
+            d1[i] = vk[i][cp + 64];
+        }
+        const double2 x0 = xs[2 * cp], x1 = xs[2 * cp + 1], x2 = xs[2 * cp + 128], x3 = xs[2 * cp + 129];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            cmac(sr[i], si[i], d0[i].x, d0[i].y, x0);
+            cmac(sr[i], si[i], d0[i].z, d0[i].w, x1);
+            cmac(sr[i], si[i], d1[i].x, d1[i].y, x2);
+            cmac(sr[i], si[i], d1[i].z, d1[i].w, x3);
+        }
+    }
+    for (; cp < np; cp += 64) {
+        const double2 x0 = xs[2 * cp], x1 = xs[2 * cp + 1];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const float4 d = vk[i][cp];
+            cmac(sr[i], si[i], d.x, d.y, x0);
+            cmac(sr[i], si[i], d.z, d.w, x1);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+        for (int off = 32; off > 0; off >>= 1) {
+            sr[i] += __shfl_xor(sr[i], off);
+            si[i] += __shfl_xor(si[i], off);
+        }
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            double2 &o = t[k + i * dk];
+            o = c0 == 0 ? make_double2(sr[i], si[i]) : make_double2(o.x + sr[i], o.y + si[i]);
+        }
+}
+
+// one workgroup per block: z[zoff + a] = (D x_J)[a], or (U (V x_J))[a] with
+// the r values V x_J (x_J staged in LDS, two columns per lane and load,
+// reduced per wave) kept in LDS, then U t; FP64 sums in a fixed order
+__global__ __launch_bounds__(HB_THREADS) void k_h_blocks(const HBlock *__restrict__ blocks,
+                                                         const double2 *__restrict__ xp, double2 *__restrict__ z)
+{
+    __shared__ double2 t[HK_MAX];
+    __shared__ double2 part[2 * HB_THREADS];
+    __shared__ double2 xs[HB_XS_MAX];
+    const HBlock B = blocks[blockIdx.x];
+    const int m = B.r1 - B.r0, nc = B.c1 - B.c0;   // vertices on each side
+    const int64_t n2 = 2 * int64_t(nc);
+    const double2 *xj = xp + 2 * int64_t(B.c0);
+    double2 *zb = z + B.zoff;
+    if (B.rank < 0) {
+        colmajor_apply(B.D, m, n2, xj, zb, part);
+        return;
+    }
+    // t = V x_J over chunks of HB_XS_MAX columns of x_J staged in LDS; lane 0
+    // of the wave that owns row k adds each chunk's sum to t[k] in chunk order
+    const int w = threadIdx.x >> 6;
+    for (int64_t c0 = 0; c0 < n2; c0 += HB_XS_MAX) {
+        const int cn = int(min(int64_t(HB_XS_MAX), n2 - c0)), np = cn / 2;
+        __syncthreads();
+        for (int c = threadIdx.x; c < cn; c += HB_THREADS) xs[c] = xj[c0 + c];
+        __syncthreads();
+        int k = w;
+        for (; k + HB_THREADS / 64 < B.rank; k += 2 * (HB_THREADS / 64))
+            v_rows<2>(B.V, n2, c0, np, k, HB_THREADS / 64, xs, t);
+        for (; k < B.rank; k += HB_THREADS / 64) v_rows<1>(B.V, n2, c0, np, k, HB_THREADS / 64, xs, t);
+    }
+    __syncthreads();
+    colmajor_apply(B.U, m, B.rank, t, zb, part);
+}
+
+// y[row_s(perm[i])] = sum of the block products of reordered row 2 i + s:
+// 16 lanes per row, each summing every 16th entry of the row's list, then a
+// fixed shuffle tree (deterministic, no atomics)
 __global__ void k_h_rows(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ rowz,
                          const double2 *__restrict__ z, const int32_t *__restrict__ perm,
                          const int32_t *__restrict__ rowD, const int32_t *__restrict__ rowN, int64_t NV,
                          double2 *__restrict__ y)
 {
-    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= 2 * NV) return;
+    const int64_t r = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 4;
+    const int sub = threadIdx.x & 15;
     double sr = 0.0, si = 0.0;
-    for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-        const double2 v = z[rowz[e]];
-        sr += v.x;
-        si += v.y;
+    if (r < 2 * NV)
+        for (int32_t e = rowptr[r] + sub; e < rowptr[r + 1]; e += 16) {
+            const double2 v = z[rowz[e]];
+            sr += v.x;
+            si += v.y;
+        }
+    for (int off = 8; off > 0; off >>= 1) {
+        sr += __shfl_xor(sr, off);
+        si += __shfl_xor(si, off);
     }
-    const int32_t g = perm[r >> 1];
-    y[(r & 1) ? rowN[g] : rowD[g]] = make_double2(sr, si);
+    if (sub == 0 && r < 2 * NV) {
+        const int32_t g = perm[r >> 1];
+        y[(r & 1) ? rowN[g] : rowD[g]] = make_double2(sr, si);
+    }
 }
 
 void launch_h_apply(hipStream_t s, const HBlock *blocks, int n_blocks, const int32_t *perm, const int32_t *rowD,
@@ -230,9 +369,9 @@ void launch_h_apply(hipStream_t s, const HBlock *blocks, int n_blocks, const int
 {
     k_h_gather<<<dim3(blocks_1d(2 * NV, 256)), dim3(256), 0, s>>>(perm, rowD, rowN, x, NV, xp);
     BEM_HIP(hipGetLastError());
-    k_h_blocks<<<dim3(unsigned(n_blocks)), dim3(256), 0, s>>>(blocks, xp, z);
+    k_h_blocks<<<dim3(unsigned(n_blocks)), dim3(HB_THREADS), 0, s>>>(blocks, xp, z);
     BEM_HIP(hipGetLastError());
-    k_h_rows<<<dim3(blocks_1d(2 * NV, 256)), dim3(256), 0, s>>>(rowptr, rowz, z, perm, rowD, rowN, NV, y);
+    k_h_rows<<<dim3(blocks_1d(2 * NV * 16, 256)), dim3(256), 0, s>>>(rowptr, rowz, z, perm, rowD, rowN, NV, y);
     BEM_HIP(hipGetLastError());
 }
 

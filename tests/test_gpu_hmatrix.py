@@ -85,3 +85,40 @@ def test_hmatrix_against_dense_matrix_and_solve():
           flush=True)
     assert i_f[0]["converged"] and res_f <= 1.5e-7
     P.close()
+
+
+def _far_spheres():
+    """Two 2,562-vertex spheres 8 radii apart: the root cluster splits into the
+    two spheres (then 1,281 and 640/641 vertices), and the clusters of one
+    sphere are admissible against those of the other at eta 1."""
+    from bem_inputs import meshes
+    v1, t1 = meshes.icosphere(4, 1.0, (-4.0, 0.0, 0.0))
+    v2, t2 = meshes.icosphere(4, 1.0, (4.0, 0.0, 0.0))
+    return configs.Problem([configs.Domain(v1, t1, complex(2.2), 1.1, "a"),
+                            configs.Domain(v2, t2, complex(1.8), 0.9, "b")], complex(2.0), 1.0, "far_spheres")
+
+
+@pytest.mark.parametrize("leaf,max_side", [(64, 700), (700, 700)], ids=["wide_lowrank", "large_dense"])
+def test_hmatrix_large_blocks(monkeypatch, leaf, max_side):
+    """Blocks beyond the default sizes: with blocks of up to 700 vertices a side
+    the far pairs of the two spheres are low-rank blocks of 640 vertices a side
+    (V x_J runs over x_J in two LDS chunks, U t over several row pairs per
+    thread); with 700-vertex leaves the dense blocks have 640 vertices a side as
+    well.  Both against the library's dense matrix of the same FP32 entries, and
+    bit-identical on repetition."""
+    import paper_1910_01011_amd as bem
+    monkeypatch.setenv("BEM_HMATRIX_MAX_SIDE", str(max_side))
+    prob = _far_spheres()
+    P = bem.Problem.from_config(prob, mode=bem.BEM_ASSEMBLED_FP32)
+    X = vectors.random_complex(prob.n_unknowns, seed=23, n_rhs=2)
+    Yd = P.apply(X, kernel=bem.BEM_APPLY_GEMV)
+    info = P.hmatrix_build(eps=1e-4, leaf_vertices=leaf, eta=1.0)
+    print(f"leaf {leaf}, max side {max_side}: {info}", flush=True)
+    assert info["n_lowrank"] > 0 and info["n_dense"] > 0
+    Yh = P.apply(X, kernel=bem.BEM_APPLY_HMATRIX)
+    for r in range(2):
+        err = _relerr(Yh[r], Yd[r])
+        print(f"rhs {r}: rel diff to the dense matrix {err:.2e}", flush=True)
+        assert err <= 1e-4
+    assert np.array_equal(P.apply(X, kernel=bem.BEM_APPLY_HMATRIX), Yh)
+    P.close()
