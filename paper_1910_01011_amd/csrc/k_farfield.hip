@@ -28,7 +28,7 @@ __constant__ double c_bary[6][3] = {
 __constant__ double c_wq[6] = {0.22338158967801146570, 0.22338158967801146570, 0.22338158967801146570,
                                0.10995174365532186764, 0.10995174365532186764, 0.10995174365532186764};
 
-constexpr int PAIR_BLOCK = 256;   // threads per workgroup of the pair kernel = trial tile
+constexpr int PAIR_BLOCK = 256;   // threads (test points per TPL) of a pair-kernel workgroup
 constexpr double INV4PI = 0.079577471545947667884;
 
 // ---------------------------------------------------------------------------
@@ -75,9 +75,13 @@ void launch_geometry(bem_problem &p)
 }
 
 // ---------------------------------------------------------------------------
-// gather: trial record of quadrature point i = 6 t + q (4 x float4)
-//   r0 = (y, n.x)   r1 = (n.y, n.z, u_D w)   r2 = (u_N w, curl(u_D).x w)
-//   r3 = (curl(u_D).y w, curl(u_D).z w)      with w = |T| w_q / (4 pi)
+// gather: trial records, grouped by triangle (float4)
+//   point i = 6 t + q, at 2 i:       P0 = (y, 0)   P1 = (u_D w, u_N w)
+//   triangle t, at 2 M + 3 t:        T0 = (n_y, 0)
+//                                    T1 = (curl(u_D).x, curl(u_D).y) |T| / (4 pi)
+//                                    T2 = (curl(u_D).z |T| / (4 pi), 0, 0)
+// with w = |T| w_q / (4 pi): the normal and the surface curl of u_D are
+// constant on a triangle, and the curl density of point q is w_q times T1, T2.
 // ---------------------------------------------------------------------------
 
 __global__ void k_gather(const double2 *__restrict__ x, const int32_t *__restrict__ tris,
@@ -98,18 +102,22 @@ __global__ void k_gather(const double2 *__restrict__ x, const int32_t *__restric
         const double l = c_bary[q][a];
         uDr += l * xd.x; uDi += l * xd.y;
         uNr += l * xn.x; uNi += l * xn.y;
-        for (int d = 0; d < 3; ++d) {
-            const double c = curl[9 * t + 3 * a + d];
-            cr[d] += c * xd.x;
-            ci[d] += c * xd.y;
-        }
+        if (q == 0)
+            for (int d = 0; d < 3; ++d) {
+                const double c = curl[9 * t + 3 * a + d];
+                cr[d] += c * xd.x;
+                ci[d] += c * xd.y;
+            }
     }
-    const double w = area[t] * c_wq[q] * INV4PI;
-    float4 *r = trial + 4 * i;
-    r[0] = make_float4(pts[i], pts[M + i], pts[2 * M + i], tnrm[t]);
-    r[1] = make_float4(tnrm[nt + t], tnrm[2 * nt + t], float(uDr * w), float(uDi * w));
-    r[2] = make_float4(float(uNr * w), float(uNi * w), float(cr[0] * w), float(ci[0] * w));
-    r[3] = make_float4(float(cr[1] * w), float(ci[1] * w), float(cr[2] * w), float(ci[2] * w));
+    const double A = area[t] * INV4PI, w = A * c_wq[q];
+    trial[2 * i] = make_float4(pts[i], pts[M + i], pts[2 * M + i], 0.0f);
+    trial[2 * i + 1] = make_float4(float(uDr * w), float(uDi * w), float(uNr * w), float(uNi * w));
+    if (q == 0) {
+        float4 *r = trial + 2 * M + 3 * t;
+        r[0] = make_float4(tnrm[t], tnrm[nt + t], tnrm[2 * nt + t], 0.0f);
+        r[1] = make_float4(float(cr[0] * A), float(ci[0] * A), float(cr[1] * A), float(ci[1] * A));
+        r[2] = make_float4(float(cr[2] * A), float(ci[2] * A), 0.0f, 0.0f);
+    }
 }
 
 void launch_gather(bem_problem &p, const double2 *x)
@@ -126,29 +134,48 @@ void launch_gather(bem_problem &p, const double2 *x)
 //
 // Work item (pass, test block, split): a workgroup of 256 lanes owns
 // 256 * TPL consecutive test points of the pass and one contiguous chunk of
-// its trial points (split s of n_split).  Trial points go through LDS in tiles
-// of 256; every lane reads each tile entry by broadcast.  Per test point the
-// kernel accumulates five complex potentials:
-//   D  = sum sV G u_N w - F (d.n_y) u_D w                       (Dirichlet row)
-//   N  = sum -k^2 sW (n_x.n_y) G u_D w - F (d.n_x) u_N w        (Neumann row, scalar part)
-//   C  = sum sW G curl(u_D) w                                   (Neumann row, curl part, 3-vector)
-// in FP32 within a tile and in FP64 across tiles.
-//
-// LDS record of one trial point (5 x float4):
-//   L0 = (y, n_y.x)  L1 = (n_y.y, n_y.z, -u_D w)  L2 = (sV u_N w, -u_N w)
-//   L3 = (-k^2 sW u_D w, sW curl.x)  L4 = (sW curl.y, sW curl.z)
+// its trial triangles (split s of n_split).  Trial records go through LDS in
+// tiles of 42 triangles (252 points); every lane reads each entry by
+// broadcast.  Per test point x (normal n_x) the kernel forms, in FP32 within a
+// tile and in FP64 across tiles,
+//   A1 = sum G u_N w              A2 = sum F (d.n_y) u_D w
+//   B1 = sum_T (n_x.n_y) sum_q G u_D w          B2 = sum F (d.n_x) u_N w
+//   Cc = sum_T curl_T(u_D) |T|/(4 pi) sum_q w_q G
+// over the trial points (d = x - y, F = G (1 - ikr)/r^2) and returns
+//   D = sV A1 - A2 (Dirichlet row),  N = -k^2 sW B1 - B2 and C = sW Cc
+// (Neumann row, scalar and curl parts).  The factors that are constant on a
+// trial triangle (n_x.n_y and the curl) multiply sums over its six points
+// once per triangle rather than once per pair.
+
+// a value of a uniform kernel argument in a VGPR: a VALU instruction that
+// reads an SGPR issues at half the rate of one whose operands are all VGPRs
+__device__ __forceinline__ float in_vgpr(float s)
+{
+    float v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+    return v;
+}
+
+constexpr int TILE_TRI = 42;               // trial triangles per LDS tile
+constexpr int TILE_PTS = 6 * TILE_TRI;     // their 252 quadrature points
 
 struct Acc {
-    float dr, di, nr, ni, cxr, cxi, cyr, cyi, czr, czi;
+    float a1r, a1i, a2r, a2i, b1r, b1i, b2r, b2i, xr, xi, yr, yi, zr, zi;
 };
 
+// per-triangle sums of one test point: T = sum G u_D w, S = sum w_q G
+struct TriSum {
+    float tr, ti, sr, si;
+};
+
+// one (test point, trial point) pair
 template <bool ATT, bool WRAP>
 __device__ __forceinline__ void pair_step(const float xx, const float xy, const float xz, const float nx,
-                                          const float ny, const float nz, const float4 L0, const float4 L1,
-                                          const float4 L2, const float4 L3, const float4 L4, const float k,
-                                          const float k2pi, const float kim, Acc &a)
+                                          const float ny, const float nz, const float4 P0, const float4 P1,
+                                          const float4 T0, const float cq, const float k, const float k2pi,
+                                          const float kim, Acc &a, TriSum &s)
 {
-    const float dx = xx - L0.x, dy = xy - L0.y, dz = xz - L0.z;
+    const float dx = xx - P0.x, dy = xy - P0.y, dz = xz - P0.z;
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     // r2 == 0 only for a point paired with itself (coincident triangle, same
     // quadrature point); that term belongs to the singular correction.
@@ -176,37 +203,58 @@ __device__ __forceinline__ void pair_step(const float xx, const float xy, const 
         fr = fmaf(gi, kr, gr) * rinv2;
         fi = fmaf(-gr, kr, gi) * rinv2;
     }
-    const float tK = fmaf(dx, L0.w, fmaf(dy, L1.x, dz * L1.y));    // d . n_y
+    const float tK = fmaf(dx, T0.x, fmaf(dy, T0.y, dz * T0.z));    // d . n_y
     const float tKp = fmaf(dx, nx, fmaf(dy, ny, dz * nz));         // d . n_x
-    const float tW = fmaf(nx, L0.w, fmaf(ny, L1.x, nz * L1.y));    // n_x . n_y
     const float eKr = fr * tK, eKi = fi * tK;
     const float ePr = fr * tKp, ePi = fi * tKp;
-    const float gWr = gr * tW, gWi = gi * tW;
-    // D += G * (sV u_N w) + eK * (-u_D w)
-    a.dr = fmaf(gr, L2.x, fmaf(-gi, L2.y, fmaf(eKr, L1.z, fmaf(-eKi, L1.w, a.dr))));
-    a.di = fmaf(gr, L2.y, fmaf(gi, L2.x, fmaf(eKr, L1.w, fmaf(eKi, L1.z, a.di))));
-    // N += gW * (-k^2 sW u_D w) + eP * (-u_N w)
-    a.nr = fmaf(gWr, L3.x, fmaf(-gWi, L3.y, fmaf(ePr, L2.z, fmaf(-ePi, L2.w, a.nr))));
-    a.ni = fmaf(gWr, L3.y, fmaf(gWi, L3.x, fmaf(ePr, L2.w, fmaf(ePi, L2.z, a.ni))));
-    // C += G * (sW curl u_D w)
-    a.cxr = fmaf(gr, L3.z, fmaf(-gi, L3.w, a.cxr));
-    a.cxi = fmaf(gr, L3.w, fmaf(gi, L3.z, a.cxi));
-    a.cyr = fmaf(gr, L4.x, fmaf(-gi, L4.y, a.cyr));
-    a.cyi = fmaf(gr, L4.y, fmaf(gi, L4.x, a.cyi));
-    a.czr = fmaf(gr, L4.z, fmaf(-gi, L4.w, a.czr));
-    a.czi = fmaf(gr, L4.w, fmaf(gi, L4.z, a.czi));
+    // A1 += G u_N w, A2 += eK u_D w, B2 += eP u_N w
+    a.a1r = fmaf(gr, P1.z, fmaf(-gi, P1.w, a.a1r));
+    a.a1i = fmaf(gr, P1.w, fmaf(gi, P1.z, a.a1i));
+    a.a2r = fmaf(eKr, P1.x, fmaf(-eKi, P1.y, a.a2r));
+    a.a2i = fmaf(eKr, P1.y, fmaf(eKi, P1.x, a.a2i));
+    a.b2r = fmaf(ePr, P1.z, fmaf(-ePi, P1.w, a.b2r));
+    a.b2i = fmaf(ePr, P1.w, fmaf(ePi, P1.z, a.b2i));
+    // T += G u_D w, S += w_q G
+    s.tr = fmaf(gr, P1.x, fmaf(-gi, P1.y, s.tr));
+    s.ti = fmaf(gr, P1.y, fmaf(gi, P1.x, s.ti));
+    s.sr = fmaf(cq, gr, s.sr);
+    s.si = fmaf(cq, gi, s.si);
 }
 
+// the per-triangle factors: B1 += (n_x.n_y) T, Cc += curl S
+__device__ __forceinline__ void triangle_step(const float nx, const float ny, const float nz, const float4 T0,
+                                              const float4 T1, const float4 T2, const TriSum &s, Acc &a)
+{
+    const float tW = fmaf(nx, T0.x, fmaf(ny, T0.y, nz * T0.z));    // n_x . n_y
+    a.b1r = fmaf(tW, s.tr, a.b1r);
+    a.b1i = fmaf(tW, s.ti, a.b1i);
+    a.xr = fmaf(s.sr, T1.x, fmaf(-s.si, T1.y, a.xr));
+    a.xi = fmaf(s.sr, T1.y, fmaf(s.si, T1.x, a.xi));
+    a.yr = fmaf(s.sr, T1.z, fmaf(-s.si, T1.w, a.yr));
+    a.yi = fmaf(s.sr, T1.w, fmaf(s.si, T1.z, a.yi));
+    a.zr = fmaf(s.sr, T2.x, fmaf(-s.si, T2.y, a.zr));
+    a.zi = fmaf(s.sr, T2.y, fmaf(s.si, T2.x, a.zi));
+}
+
+// Five waves per SIMD (one test point per lane): left to itself the compiler
+// hoists all twelve LDS reads of a triangle and needs 129 VGPRs (three
+// waves); bounded, it fits 93 without spills and runs 8 % faster.
 template <int TPL, bool ATT, bool WRAP>
-__global__ __launch_bounds__(PAIR_BLOCK) void k_pairs(const int4 *__restrict__ work, const PassDev *__restrict__ passes,
+__global__ __launch_bounds__(PAIR_BLOCK) __attribute__((amdgpu_waves_per_eu(TPL == 1 ? 5 : 3))) void k_pairs(const int4 *__restrict__ work, const PassDev *__restrict__ passes,
                                                       const float *__restrict__ pts, const float *__restrict__ tnrm,
                                                       const float4 *__restrict__ trial, double *__restrict__ part,
                                                       int64_t M, int64_t nt, int n_split)
 {
-    __shared__ float4 lds[5][PAIR_BLOCK];
+    __shared__ float4 lp[2][TILE_PTS];
+    __shared__ float4 lt[3][TILE_TRI];
     const int4 w = work[blockIdx.x];
     const PassDev P = passes[w.x];
     const int tid = threadIdx.x;
+    const float kv = in_vgpr(P.k), k2piv = in_vgpr(P.k_over_2pi), kimv = in_vgpr(P.kim);
+    // the two weights of the 6-point rule (points 0-2 and 3-5)
+    const float wqa = in_vgpr(float(c_wq[0])), wqb = in_vgpr(float(c_wq[3]));
+    // pass constants of the per-tile combination: sV, sW and -k^2 sW
+    const double sV = P.sV, sW = P.sW, cNr = -double(P.sW) * P.k2re, cNi = -double(P.sW) * P.k2im;
 
     // test points of this lane
     float xx[TPL], xy[TPL], xz[TPL], nx[TPL], ny[TPL], nz[TPL];
@@ -225,12 +273,14 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pairs(const int4 *__restrict__ w
         nz[u] = tnrm[2 * nt + t];
     }
 
-    // trial chunk of this split (multiple of the tile size)
+    // trial chunk of this split: whole tiles (the pass ranges hold whole
+    // triangles, so every chunk and tile does too)
     const long long n_trial = P.trial_end - P.trial_begin;
     long long chunk = (n_trial + n_split - 1) / n_split;
-    chunk = (chunk + PAIR_BLOCK - 1) / PAIR_BLOCK * PAIR_BLOCK;
+    chunk = (chunk + TILE_PTS - 1) / TILE_PTS * TILE_PTS;
     const long long j_begin = P.trial_begin + (long long)w.z * chunk;
     const long long j_end = j_begin + chunk < P.trial_end ? j_begin + chunk : P.trial_end;
+    const float4 *tri_rec = trial + 2 * M;
 
     double acc[TPL][10];
 #pragma unroll
@@ -238,39 +288,54 @@ __global__ __launch_bounds__(PAIR_BLOCK) void k_pairs(const int4 *__restrict__ w
 #pragma unroll
         for (int c = 0; c < 10; ++c) acc[u][c] = 0.0;
 
-    for (long long jt = j_begin; jt < j_end; jt += PAIR_BLOCK) {
-        const int cnt = int(j_end - jt < PAIR_BLOCK ? j_end - jt : PAIR_BLOCK);
+    for (long long jt = j_begin; jt < j_end; jt += TILE_PTS) {
+        const int cnt = int(j_end - jt < TILE_PTS ? j_end - jt : TILE_PTS);
+        const int ntri = cnt / 6;
         __syncthreads();
         if (tid < cnt) {
-            const float4 *r = trial + 4 * (jt + tid);
-            const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
-            lds[0][tid] = r0;
-            lds[1][tid] = make_float4(r1.x, r1.y, -r1.z, -r1.w);
-            lds[2][tid] = make_float4(P.sV * r2.x, P.sV * r2.y, -r2.x, -r2.y);
-            // -k^2 sW u_D w (complex k^2)
-            const float ar = -P.sW * (P.k2re * r1.z - P.k2im * r1.w);
-            const float ai = -P.sW * (P.k2re * r1.w + P.k2im * r1.z);
-            lds[3][tid] = make_float4(ar, ai, P.sW * r2.z, P.sW * r2.w);
-            lds[4][tid] = make_float4(P.sW * r3.x, P.sW * r3.y, P.sW * r3.z, P.sW * r3.w);
+            lp[0][tid] = trial[2 * (jt + tid)];
+            lp[1][tid] = trial[2 * (jt + tid) + 1];
+        }
+        if (tid < ntri) {
+            const float4 *r = tri_rec + 3 * (jt / 6 + tid);
+            lt[0][tid] = r[0];
+            lt[1][tid] = r[1];
+            lt[2][tid] = r[2];
         }
         __syncthreads();
         Acc a[TPL];
 #pragma unroll
-        for (int u = 0; u < TPL; ++u) a[u] = Acc{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-        for (int j = 0; j < cnt; ++j) {
-            const float4 L0 = lds[0][j], L1 = lds[1][j], L2 = lds[2][j], L3 = lds[3][j], L4 = lds[4][j];
+        for (int u = 0; u < TPL; ++u) a[u] = Acc{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int tr = 0; tr < ntri; ++tr) {
+            const float4 T0 = lt[0][tr];
+            TriSum s[TPL];
 #pragma unroll
-            for (int u = 0; u < TPL; ++u)
-                pair_step<ATT, WRAP>(xx[u], xy[u], xz[u], nx[u], ny[u], nz[u], L0, L1, L2, L3, L4, P.k, P.k_over_2pi,
-                               P.kim, a[u]);
+            for (int u = 0; u < TPL; ++u) s[u] = TriSum{0, 0, 0, 0};
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const float4 P0 = lp[0][6 * tr + q], P1 = lp[1][6 * tr + q];
+#pragma unroll
+                for (int u = 0; u < TPL; ++u)
+                    pair_step<ATT, WRAP>(xx[u], xy[u], xz[u], nx[u], ny[u], nz[u], P0, P1, T0, q < 3 ? wqa : wqb, kv,
+                                         k2piv, kimv, a[u], s[u]);
+            }
+            const float4 T1 = lt[1][tr], T2 = lt[2][tr];
+#pragma unroll
+            for (int u = 0; u < TPL; ++u) triangle_step(nx[u], ny[u], nz[u], T0, T1, T2, s[u], a[u]);
         }
 #pragma unroll
         for (int u = 0; u < TPL; ++u) {
-            acc[u][0] += a[u].dr; acc[u][1] += a[u].di;
-            acc[u][2] += a[u].nr; acc[u][3] += a[u].ni;
-            acc[u][4] += a[u].cxr; acc[u][5] += a[u].cxi;
-            acc[u][6] += a[u].cyr; acc[u][7] += a[u].cyi;
-            acc[u][8] += a[u].czr; acc[u][9] += a[u].czi;
+            const Acc &q = a[u];
+            acc[u][0] += sV * double(q.a1r) - double(q.a2r);
+            acc[u][1] += sV * double(q.a1i) - double(q.a2i);
+            acc[u][2] += cNr * double(q.b1r) - cNi * double(q.b1i) - double(q.b2r);
+            acc[u][3] += cNr * double(q.b1i) + cNi * double(q.b1r) - double(q.b2i);
+            acc[u][4] += sW * double(q.xr);
+            acc[u][5] += sW * double(q.xi);
+            acc[u][6] += sW * double(q.yr);
+            acc[u][7] += sW * double(q.yi);
+            acc[u][8] += sW * double(q.zr);
+            acc[u][9] += sW * double(q.zi);
         }
     }
     double *out = part + (size_t(P.slot) * n_split + w.z) * 10 * size_t(M);
