@@ -97,6 +97,12 @@ __device__ __forceinline__ void vertex_pair_sums(const float4 *__restrict__ rec,
                                                  const float4 *trial, int cnt, const DenseDom &ext, const DenseDom &in,
                                                  bool same, Acc4 &E, Acc4 &I)
 {
+    // the constants of the loop in VGPRs (an SGPR operand halves the issue rate)
+    const DenseDom e{in_vgpr(ext.k), in_vgpr(ext.k2pi), in_vgpr(ext.kim), 0.0f, 0.0f, in_vgpr(ext.k2re),
+                     in_vgpr(ext.k2im), 0.0f};
+    const DenseDom d{in_vgpr(in.k), in_vgpr(in.k2pi), in_vgpr(in.kim), 0.0f, 0.0f, in_vgpr(in.k2re), in_vgpr(in.k2im),
+                     0.0f};
+    const float four_pi = in_vgpr(12.566370614359172954f);
     for (int32_t kq = q0; kq < q1; ++kq) {
         const float4 T0 = rec[3 * kq], T1 = rec[3 * kq + 1], T2 = rec[3 * kq + 2];
         for (int kp = 0; kp < cnt; ++kp) {
@@ -107,14 +113,13 @@ __device__ __forceinline__ void vertex_pair_sums(const float4 *__restrict__ rec,
             const float rinv = __builtin_amdgcn_rsqf(r2);
             const float r = r2 * rinv;
             // the factor 1/(4 pi) sits in the test weights only
-            const float ww = T0.w * S0.w * 12.566370614359172954f;
-            const float wcc = T1.w * S1.w * 12.566370614359172954f * fmaf(T2.x, S2.x, fmaf(T2.y, S2.y, T2.z * S2.z));
+            const float ww = T0.w * S0.w * four_pi;
+            const float wcc = T1.w * S1.w * four_pi * fmaf(T2.x, S2.x, fmaf(T2.y, S2.y, T2.z * S2.z));
             const float tK = fmaf(dx, S1.x, fmaf(dy, S1.y, dz * S1.z));
             const float tKp = fmaf(dx, T1.x, fmaf(dy, T1.y, dz * T1.z));
             const float nn = fmaf(T1.x, S1.x, fmaf(T1.y, S1.y, T1.z * S1.z));
-            dense_pair<ATT, WRAP>(r, rinv, ww, wcc, tK, tKp, nn, ext.k, ext.k2pi, ext.kim, ext.k2re, ext.k2im, E);
-            if (same)
-                dense_pair<ATT, WRAP>(r, rinv, ww, wcc, tK, tKp, nn, in.k, in.k2pi, in.kim, in.k2re, in.k2im, I);
+            dense_pair<ATT, WRAP>(r, rinv, ww, wcc, tK, tKp, nn, e.k, e.k2pi, e.kim, e.k2re, e.k2im, E);
+            if (same) dense_pair<ATT, WRAP>(r, rinv, ww, wcc, tK, tKp, nn, d.k, d.k2pi, d.kim, d.k2re, d.k2im, I);
         }
     }
 }

@@ -147,15 +147,6 @@ void launch_gather(bem_problem &p, const double2 *x)
 // trial triangle (n_x.n_y and the curl) multiply sums over its six points
 // once per triangle rather than once per pair.
 
-// a value of a uniform kernel argument in a VGPR: a VALU instruction that
-// reads an SGPR issues at half the rate of one whose operands are all VGPRs
-__device__ __forceinline__ float in_vgpr(float s)
-{
-    float v;
-    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
-    return v;
-}
-
 constexpr int TILE_TRI = 42;               // trial triangles per LDS tile
 constexpr int TILE_PTS = 6 * TILE_TRI;     // their 252 quadrature points
 

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(SL_BLOCK) void k_pairs_v(const PassDev *__restrict_
     chunk = (chunk + SL_BLOCK - 1) / SL_BLOCK * SL_BLOCK;
     const long long j_begin = P.trial_begin + (long long)w.z * chunk;
     const long long j_end = j_begin + chunk < P.trial_end ? j_begin + chunk : P.trial_end;
-    const float k2pi = P.k_over_2pi, kim = P.kim;
+    const float k2pi = in_vgpr(P.k_over_2pi), kim = in_vgpr(P.kim);
     double acc[TPL][2];
 #pragma unroll
     for (int u = 0; u < TPL; ++u) acc[u][0] = acc[u][1] = 0.0;
