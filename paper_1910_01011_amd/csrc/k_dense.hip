@@ -57,9 +57,17 @@ struct Acc4 {
     float vr, vi, kr, ki, pr, pi, wr, wi;
 };
 
+// sums of one pass over the point pairs of a (test corner, trial corner) pair:
+// V = sum G (w lambda)(w lambda)',  Cc = sum G w w'
+struct Corner {
+    float vr, vi, cr, ci;
+};
+
+// one point pair of one pass: K and K' into the vertex-pair sums, V and the
+// curl-term sum into the corner-pair sums (weights without the 4 pi)
 template <bool ATT, bool WRAP>
-__device__ __forceinline__ void dense_pair(float r, float rinv, float ww, float wcc, float tK, float tKp, float nn,
-                                           float k, float k2pi, float kim, float k2re, float k2im, Acc4 &A)
+__device__ __forceinline__ void dense_pair(float r, float rinv, float ww, float ws, float tK, float tKp, float k,
+                                           float k2pi, float kim, Acc4 &A, Corner &C)
 {
     float ph = r * k2pi;
     if (WRAP) ph = ph - rintf(ph);   // else the hardware sine and cosine reduce |ph| < 256 revolutions
@@ -77,21 +85,34 @@ __device__ __forceinline__ void dense_pair(float r, float rinv, float ww, float 
         fr = fmaf(gi, kr, gr) * rinv2;
         fi = fmaf(-gr, kr, gi) * rinv2;
     }
-    A.vr = fmaf(ww, gr, A.vr);
-    A.vi = fmaf(ww, gi, A.vi);
-    A.kr = fmaf(ww * tK, fr, A.kr);
-    A.ki = fmaf(ww * tK, fi, A.ki);
-    A.pr = fmaf(-ww * tKp, fr, A.pr);
-    A.pi = fmaf(-ww * tKp, fi, A.pi);
-    // W: G [w w' curl.curl' - k^2 (n.n') w lambda w' lambda']   (complex k^2)
-    const float cr = fmaf(-k2re * nn, ww, wcc), ci = -k2im * nn * ww;
-    A.wr = fmaf(gr, cr, fmaf(-gi, ci, A.wr));
-    A.wi = fmaf(gr, ci, fmaf(gi, cr, A.wi));
+    C.vr = fmaf(ww, gr, C.vr);
+    C.vi = fmaf(ww, gi, C.vi);
+    C.cr = fmaf(ws, gr, C.cr);
+    C.ci = fmaf(ws, gi, C.ci);
+    const float wk = ww * tK, wp = ww * tKp;
+    A.kr = fmaf(wk, fr, A.kr);
+    A.ki = fmaf(wk, fi, A.ki);
+    A.pr = fmaf(-wp, fr, A.pr);
+    A.pi = fmaf(-wp, fi, A.pi);
+}
+
+// the factors constant on a corner pair: V += Vc and
+// W += (curl.curl') Cc - k^2 (n.n') Vc   (complex k^2)
+__device__ __forceinline__ void corner_done(const Corner &C, float cc, float nn, float k2re, float k2im, Acc4 &A)
+{
+    A.vr += C.vr;
+    A.vi += C.vi;
+    const float ar = k2re * nn, ai = k2im * nn;
+    A.wr = fmaf(cc, C.cr, A.wr) - fmaf(ar, C.vr, -ai * C.vi);
+    A.wi = fmaf(cc, C.ci, A.wi) - fmaf(ar, C.vi, ai * C.vr);
 }
 
 // Entry sums of vertex pair (g, h): the test records of g (global memory,
-// loaded once per test point) against the trial records of h (`trial`, in
-// LDS when staged), exterior pass and, on the same boundary, interior pass.
+// the six points of a test corner held in registers) against the trial
+// records of h (`trial`, in LDS when staged), exterior pass and, on the same
+// boundary, interior pass.  The records of a corner share its triangle's
+// normal and curl, so the curl.curl' and n.n' factors of the W entry multiply
+// sums over the corner pair's 36 point pairs.
 template <bool ATT, bool WRAP>
 __device__ __forceinline__ void vertex_pair_sums(const float4 *__restrict__ rec, int32_t q0, int32_t q1,
                                                  const float4 *trial, int cnt, const DenseDom &ext, const DenseDom &in,
@@ -102,25 +123,47 @@ __device__ __forceinline__ void vertex_pair_sums(const float4 *__restrict__ rec,
                      in_vgpr(ext.k2im), 0.0f};
     const DenseDom d{in_vgpr(in.k), in_vgpr(in.k2pi), in_vgpr(in.kim), 0.0f, 0.0f, in_vgpr(in.k2re), in_vgpr(in.k2im),
                      0.0f};
-    const float four_pi = in_vgpr(12.566370614359172954f);
-    for (int32_t kq = q0; kq < q1; ++kq) {
-        const float4 T0 = rec[3 * kq], T1 = rec[3 * kq + 1], T2 = rec[3 * kq + 2];
-        for (int kp = 0; kp < cnt; ++kp) {
-            const float4 S0 = trial[3 * kp], S1 = trial[3 * kp + 1], S2 = trial[3 * kp + 2];
-            const float dx = T0.x - S0.x, dy = T0.y - S0.y, dz = T0.z - S0.z;
-            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            if (!(r2 > 0.0f)) continue;   // point with itself: singular correction
-            const float rinv = __builtin_amdgcn_rsqf(r2);
-            const float r = r2 * rinv;
-            // the factor 1/(4 pi) sits in the test weights only
-            const float ww = T0.w * S0.w * four_pi;
-            const float wcc = T1.w * S1.w * four_pi * fmaf(T2.x, S2.x, fmaf(T2.y, S2.y, T2.z * S2.z));
-            const float tK = fmaf(dx, S1.x, fmaf(dy, S1.y, dz * S1.z));
-            const float tKp = fmaf(dx, T1.x, fmaf(dy, T1.y, dz * T1.z));
-            const float nn = fmaf(T1.x, S1.x, fmaf(T1.y, S1.y, T1.z * S1.z));
-            dense_pair<ATT, WRAP>(r, rinv, ww, wcc, tK, tKp, nn, e.k, e.k2pi, e.kim, e.k2re, e.k2im, E);
-            if (same) dense_pair<ATT, WRAP>(r, rinv, ww, wcc, tK, tKp, nn, d.k, d.k2pi, d.kim, d.k2re, d.k2im, I);
+    for (int32_t c0 = q0; c0 < q1; c0 += 6) {
+        const float4 Tn = rec[3 * c0 + 1], Tc = rec[3 * c0 + 2];   // test corner: normal, curl
+        float4 T0[6];
+        float tw[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            T0[q] = rec[3 * (c0 + q)];
+            tw[q] = rec[3 * (c0 + q) + 1].w;
         }
+        for (int p0 = 0; p0 < cnt; p0 += 6) {
+            const float4 Sn = trial[3 * p0 + 1], Sc = trial[3 * p0 + 2];   // trial corner: normal, curl
+            const float nn = fmaf(Tn.x, Sn.x, fmaf(Tn.y, Sn.y, Tn.z * Sn.z));
+            const float cc = fmaf(Tc.x, Sc.x, fmaf(Tc.y, Sc.y, Tc.z * Sc.z));
+            Corner ce{0, 0, 0, 0}, ci{0, 0, 0, 0};
+            for (int p = 0; p < 6; ++p) {
+                const float4 S0 = trial[3 * (p0 + p)];
+                const float sw = trial[3 * (p0 + p) + 1].w;
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    const float dx = T0[q].x - S0.x, dy = T0[q].y - S0.y, dz = T0[q].z - S0.z;
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    if (r2 > 0.0f) {   // else a point with itself: singular correction
+                        const float rinv = __builtin_amdgcn_rsqf(r2);
+                        const float r = r2 * rinv;
+                        const float ww = T0[q].w * S0.w, ws = tw[q] * sw;
+                        const float tK = fmaf(dx, Sn.x, fmaf(dy, Sn.y, dz * Sn.z));
+                        const float tKp = fmaf(dx, Tn.x, fmaf(dy, Tn.y, dz * Tn.z));
+                        dense_pair<ATT, WRAP>(r, rinv, ww, ws, tK, tKp, e.k, e.k2pi, e.kim, E, ce);
+                        if (same) dense_pair<ATT, WRAP>(r, rinv, ww, ws, tK, tKp, d.k, d.k2pi, d.kim, I, ci);
+                    }
+                }
+            }
+            corner_done(ce, cc, nn, e.k2re, e.k2im, E);
+            if (same) corner_done(ci, cc, nn, d.k2re, d.k2im, I);
+        }
+    }
+    // the records carry 1/(4 pi) on both sides; the kernel has it once
+    const float four_pi = 12.566370614359172954f;
+    for (Acc4 *A : {&E, &I}) {
+        A->vr *= four_pi; A->vi *= four_pi; A->kr *= four_pi; A->ki *= four_pi;
+        A->pr *= four_pi; A->pi *= four_pi; A->wr *= four_pi; A->wi *= four_pi;
     }
 }
 
