@@ -476,7 +476,7 @@ __global__ __launch_bounds__(256) void k_gemv(const float2 *__restrict__ A, cons
 #pragma unroll
         for (int u = 0; u < GEMV_UNROLL; ++u) {
 #pragma unroll
-            for (int k = 0; k < GEMV_ROWS; ++k) a[u][k] = *reinterpret_cast<const float4 *>(row[k] + 2 * (c2 + 64 * u));
+            for (int k = 0; k < GEMV_ROWS; ++k) a[u][k] = load_streamed(row[k] + 2 * (c2 + 64 * u));
             x0[u] = x[2 * (c2 + 64 * u)];
             x1[u] = x[2 * (c2 + 64 * u) + 1];
         }
@@ -493,7 +493,7 @@ __global__ __launch_bounds__(256) void k_gemv(const float2 *__restrict__ A, cons
         const double2 x0 = x[2 * c2], x1 = x[2 * c2 + 1];
 #pragma unroll
         for (int k = 0; k < GEMV_ROWS; ++k) {
-            const float4 v = *reinterpret_cast<const float4 *>(row[k] + 2 * c2);
+            const float4 v = load_streamed(row[k] + 2 * c2);
             ar[k] += double(v.x) * x0.x - double(v.y) * x0.y + double(v.z) * x1.x - double(v.w) * x1.y;
             ai[k] += double(v.x) * x0.y + double(v.y) * x0.x + double(v.z) * x1.y + double(v.w) * x1.x;
         }

@@ -173,7 +173,6 @@ __device__ __forceinline__ void colmajor_apply(const float2 *__restrict__ A, int
     const int tid = threadIdx.x;
     const int P = min(m, HB_THREADS), G = HB_THREADS / P;
     const int j0 = tid % P, g = tid / P;
-    const float4 *A4 = reinterpret_cast<const float4 *>(A);
     if (G == 1) {
         if (g != 0) return;
         for (int j = j0; j < m; j += P) {
@@ -184,7 +183,7 @@ __device__ __forceinline__ void colmajor_apply(const float2 *__restrict__ A, int
                 double2 v[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    d[u] = A4[(c + u) * m + j];
+                    d[u] = load_streamed(A + 2 * ((c + u) * m + j));
                     v[u] = vec[c + u];
                 }
 #pragma unroll
@@ -194,7 +193,7 @@ __device__ __forceinline__ void colmajor_apply(const float2 *__restrict__ A, int
                 }
             }
             for (; c < ncol; ++c) {
-                const float4 d = A4[c * m + j];
+                const float4 d = load_streamed(A + 2 * (c * m + j));
                 const double2 v = vec[c];
                 cmac(ar, ai, d.x, d.y, v);
                 cmac(br, bi, d.z, d.w, v);
@@ -213,7 +212,7 @@ __device__ __forceinline__ void colmajor_apply(const float2 *__restrict__ A, int
             double2 v[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                d[u] = A4[(c + u * G) * m + j0];
+                d[u] = load_streamed(A + 2 * ((c + u * G) * m + j0));
                 v[u] = vec[c + u * G];
             }
 #pragma unroll
@@ -223,7 +222,7 @@ __device__ __forceinline__ void colmajor_apply(const float2 *__restrict__ A, int
             }
         }
         for (; c < ncol; c += G) {
-            const float4 d = A4[c * m + j0];
+            const float4 d = load_streamed(A + 2 * (c * m + j0));
             const double2 v = vec[c];
             cmac(ar, ai, d.x, d.y, v);
             cmac(br, bi, d.z, d.w, v);
@@ -255,19 +254,19 @@ __device__ __forceinline__ void v_rows(const float2 *__restrict__ V, int64_t n2,
 {
     const int lane = threadIdx.x & 63;
     double sr[NR], si[NR];
-    const float4 *vk[NR];
+    const float2 *vr[NR];
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
         sr[i] = si[i] = 0.0;
-        vk[i] = reinterpret_cast<const float4 *>(V + int64_t(k + i * dk) * n2 + c0);
+        vr[i] = V + int64_t(k + i * dk) * n2 + c0;
     }
     int cp = lane;
     for (; cp + 64 < np; cp += 128) {
         float4 d0[NR], d1[NR];
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
-            d0[i] = vk[i][cp];
-            d1[i] = vk[i][cp + 64];
+            d0[i] = load_streamed(vr[i] + 2 * cp);
+            d1[i] = load_streamed(vr[i] + 2 * (cp + 64));
         }
         const double2 x0 = xs[2 * cp], x1 = xs[2 * cp + 1], x2 = xs[2 * cp + 128], x3 = xs[2 * cp + 129];
 #pragma unroll
@@ -282,7 +281,7 @@ __device__ __forceinline__ void v_rows(const float2 *__restrict__ V, int64_t n2,
         const double2 x0 = xs[2 * cp], x1 = xs[2 * cp + 1];
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
-            const float4 d = vk[i][cp];
+            const float4 d = load_streamed(vr[i] + 2 * cp);
             cmac(sr[i], si[i], d.x, d.y, x0);
             cmac(sr[i], si[i], d.z, d.w, x1);
         }
