@@ -86,6 +86,7 @@ void build_passes(bem_problem &p)
     p.passes.push_back(ext);
     for (const auto &d : p.doms) {
         PassDesc q{};
+        // whole triangles: the pair kernel's trial tiles and records are per triangle
         q.test_begin = 6 * d.t_off;
         q.test_end = 6 * (d.t_off + d.nt);
         q.trial_begin = q.test_begin;
@@ -431,7 +432,7 @@ bem_status bem_assemble(const bem_domain *domains, int32_t n_domains, bem_comple
         p->n_split = int(std::clamp<int64_t>((8 * 256 + blocks - 1) / std::max<int64_t>(1, blocks), 1, 64));
         if (p->n_split > 1) p->n_split = std::min(64, (p->n_split + 7) / 8 * 8);
         build_passes(*p);
-        dev_alloc(&p->d_trial, size_t(4 * p->M));
+        dev_alloc(&p->d_trial, size_t(2 * p->M + 3 * p->NT));   // point records, then triangle records
         dev_alloc(&p->d_pot, size_t(10) * p->M);
         if ((o.flags & BEM_AUTOTUNE) && o.mode == BEM_OTF) {
             // partial sums for the largest candidate (at most 2 GB), then the choice
@@ -907,7 +908,7 @@ bem_status bem_footprint_bytes(const bem_domain *domains, int32_t n_domains, con
     uint64_t b = 0;
     b += nv * 24 + nt * 12 + nv * 8;              // vertices, triangles, row maps
     b += nt * (8 + 24 + 72 + 12) + M * 12;        // geometry, points
-    b += M * 64 + 2 * n_split * 10 * M * 8 + M * 80;   // trial records, partials, potentials
+    b += M * 32 + nt * 48 + 2 * n_split * 10 * M * 8 + M * 80;   // trial records, partials, potentials
     b += nv * 24 * (4 + 4 * 64);                  // correction CSR (about 24 entries per row)
     b += uint64_t(n_rhs) * N * 16 * 2;            // x, y
     b += uint64_t(restart + 1) * N * 16 * uint64_t(n_rhs > 0 ? n_rhs : 1);   // Krylov bases

@@ -153,7 +153,7 @@ struct bem_problem {
     int n_split = 8;
     int tpl = 1;                    // test points per lane of the pair kernel
     bool wrap_phase = true;         // phases k r / 2 pi may reach 256 revolutions: reduce them in the kernel
-    float4 *d_trial = nullptr;      // [M][4] trial records
+    float4 *d_trial = nullptr;      // trial records: [M][2] per point, then [NT][3] per triangle
     double *d_part = nullptr;       // [2][n_split][10][M]
     double *d_pot = nullptr;        // [M][10]
 
