@@ -490,3 +490,80 @@ def test_series_transmission_conditions_with_attenuating_media():
     ps = [series.sphere_field(z * r, a, k0, d.k, 1.0, d.rho)[0] - np.exp(1j * k0 * r) for r in (400.0, 800.0)]
     ratio = abs(ps[1] * 800.0 * np.exp(-1j * k0 * 800.0)) / abs(ps[0] * 400.0 * np.exp(-1j * k0 * 400.0))
     assert abs(ratio - 1.0) < 1e-2
+
+
+def _sphere_solution(ratio):
+    """Oracle LU solution on the 642-vertex unit sphere, k0 = 2, k1 = 2.2, rho1/rho0 = ratio."""
+    v, t = meshes.icosphere(3)
+    prob = configs.Problem([configs.Domain(v, t, complex(2.2), float(ratio), "sphere")], complex(2.0), 1.0)
+    A = oracle.pmchwt_matrix(prob)
+    p, dp = oracle.plane_wave(prob.k0)
+    u = oracle.solve_lu(A, oracle.rhs(prob, p, dp))
+    return prob, u, p
+
+
+def _series_errors(prob, u, p_inc, ratio):
+    """Mass-norm trace errors and interior / exterior field errors (points more
+    than 2h from the sphere) against the series at density ratio ``ratio``."""
+    d = prob.domains[0]
+    v, t, nv = d.vertices, d.triangles, d.n_vertices
+    gD, gN = series.sphere_traces(v, 1.0, 2.0, 2.2, 1.0, ratio)
+    M = oracle.mass_matrix(v, t)
+
+    def mnorm(x):
+        return np.sqrt(np.real(np.conj(x) @ M @ x))
+
+    g = np.linspace(-3.0, 3.0, 25)
+    X, Z = np.meshgrid(g, g, indexing="ij")
+    pts = np.stack([X.ravel(), np.zeros(X.size), Z.ravel()], axis=1)
+    gi = np.linspace(-0.6, 0.6, 7)
+    Xi, Zi = np.meshgrid(gi, gi, indexing="ij")
+    pts = np.concatenate([pts, np.stack([Xi.ravel(), 0.1 + 0 * Xi.ravel(), Zi.ravel()], axis=1)])
+    h = oracle.mean_edge(v, t)
+    pts = pts[np.abs(np.linalg.norm(pts, axis=1) - 1.0) > 2 * h + 0.01]
+    p, region = oracle.field(prob, u, pts, p_inc)
+    ref = series.sphere_field(pts, 1.0, 2.0, 2.2, 1.0, ratio)
+    ins, ext = region == 1, region == 0
+    assert ins.sum() > 40 and ext.sum() > 400 and ins.sum() + ext.sum() == pts.shape[0]
+
+    def rel(m):
+        return float(np.linalg.norm(p[m] - ref[m]) / np.linalg.norm(ref[m]))
+
+    return (mnorm(u[:nv] - gD) / mnorm(gD), mnorm(u[nv:] - gN) / mnorm(gN), rel(ins), rel(ext))
+
+
+@pytest.mark.parametrize("ratio", [1.9, 0.5])
+def test_density_ratio_scaling_matches_series(ratio):
+    """The density scaling D_j = diag(1, rho_j/rho_0) of the interior operator
+    (eq. Form1_BCs, eq. Form1_calderon_sys_int_ptot: sV = rho_j/rho_0 on V,
+    sW = rho_0/rho_j on W) and the interior representation formula's
+    (rho_j/rho_0) u_N (eq. rep_formula_gen), pinned by the penetrable-sphere
+    series at a density contrast: traces (mass norm) and the interior and
+    exterior fields off the surface all within 2 % on the 642-vertex sphere."""
+    prob, u, p_inc = _sphere_solution(ratio)
+    eD, eN, e_in, e_out = _series_errors(prob, u, p_inc, ratio)
+    print(f"rho ratio {ratio}: traces {eD:.2e} {eN:.2e}, field inside {e_in:.2e}, outside {e_out:.2e}")
+    assert max(eD, eN, e_in, e_out) < 0.02, (eD, eN, e_in, e_out)
+
+
+def test_density_ratio_pin_rejects_an_inverted_scaling():
+    """The pin above is sensitive to the scaling's direction: the oracle run with
+    the ratio inverted (sV = rho_0/rho_j, sW = rho_j/rho_0, which is what a
+    swapped scaling computes) misses the series of the true ratio by far more
+    than 2 % on the traces, and an interior field formed with rho_0/rho_j
+    instead of rho_j/rho_0 misses it as well."""
+    ratio = 1.9
+    prob_inv, u_inv, p_inc = _sphere_solution(1.0 / ratio)
+    eD, eN, e_in, e_out = _series_errors(prob_inv, u_inv, p_inc, ratio)
+    print(f"inverted: traces {eD:.2e} {eN:.2e}, field inside {e_in:.2e}, outside {e_out:.2e}")
+    assert min(eD, eN) > 0.2 and e_in > 0.2
+    # interior field with the correct solution but the inverted factor on u_N
+    prob, u, _ = _sphere_solution(ratio)
+    d = prob.domains[0]
+    nv = d.n_vertices
+    pts = np.array([[0.1, 0.0, 0.2], [-0.3, 0.1, 0.4], [0.0, 0.0, -0.5], [0.4, -0.2, 0.0]])
+    sl, dl = oracle.potentials((d.vertices, d.triangles), d.k, u[:nv], (prob.rho0 / d.rho) * u[nv:], pts)
+    ref = series.sphere_field(pts, 1.0, 2.0, 2.2, 1.0, ratio)
+    assert np.linalg.norm(sl - dl - ref) / np.linalg.norm(ref) > 0.2
+    p_ok, _ = oracle.field(prob, u, pts)
+    assert np.linalg.norm(p_ok - ref) / np.linalg.norm(ref) < 0.02
