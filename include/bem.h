@@ -243,7 +243,8 @@ bem_status bem_evaluate_field(bem_problem *p, const bem_complex *u, const bem_in
  * for going beyond dense storage (its numerical experiments use H-matrices
  * with adaptive cross approximation).  The vertices of all boundaries are
  * clustered by recursive median bisection down to leaf_vertices per cluster; a
- * pair of clusters with max(diam) <= eta dist (bounding boxes) becomes a
+ * pair of clusters with max(diam) <= eta dist (bounding boxes of the supports
+ * of the clusters' basis functions; see bem_hmatrix_plan) becomes a
  * low-rank block, built by adaptive cross approximation with complete pivoting
  * to the relative tolerance eps of its largest entry (kept dense when the rank
  * would not halve its storage); pairs of leaves are dense blocks with the FP64
@@ -262,6 +263,20 @@ typedef struct {
     double build_s;
 } bem_hmatrix_info;
 bem_status bem_hmatrix_build(bem_problem *p, double eps, int32_t leaf_vertices, double eta, bem_hmatrix_info *info);
+
+/* The cluster and block trees bem_hmatrix_build would use for these domains,
+ * computed on the host alone (no device needed).  A cluster's box bounds the
+ * supports of its vertices' P1 functions (all triangles at each vertex), so
+ * two vertices whose functions meet on touching triangles (the pairs that
+ * get the Sauter-Schwab rules) lie in clusters at distance 0, which are never
+ * admissible.  out4 (host, 4 values): [0] blocks, [1] admissible blocks,
+ * [2] vertex pairs of the singular pattern (touching triangles within one
+ * boundary), [3] of those, the pairs that fall in an admissible block (0 by
+ * construction; bem_hmatrix_build fails with BEM_ERR_DEVICE otherwise).
+ * Errors: BEM_ERR_INVALID_ARG (null pointers, leaf_vertices outside
+ * [8, 4096], eta <= 0), BEM_ERR_MESH as in bem_assemble. */
+bem_status bem_hmatrix_plan(const bem_domain *domains, int32_t n_domains, int32_t leaf_vertices, double eta,
+                            int64_t *out4);
 
 int64_t bem_num_unknowns(const bem_problem *p);
 

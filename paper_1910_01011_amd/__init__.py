@@ -90,6 +90,8 @@ _L.bem_apply_parts.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int]
 _L.bem_apply_with.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int]
 _L.bem_apply_single_layer.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
 _L.bem_hmatrix_build.argtypes = [_vp, ctypes.c_double, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(bem_hmatrix_info)]
+_L.bem_hmatrix_plan.argtypes = [ctypes.POINTER(bem_domain), ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                ctypes.POINTER(ctypes.c_int64)]
 _L.bem_rhs.argtypes = [_vp, ctypes.POINTER(bem_incident), _vp]
 _L.bem_solve.argtypes = [_vp, ctypes.POINTER(bem_incident), ctypes.POINTER(bem_solve_opts), _vp,
                          ctypes.POINTER(bem_solve_info)]
@@ -107,13 +109,13 @@ _L.bem_destroy.argtypes = [_vp]
 _L.bem_destroy.restype = None
 _L.bem_last_error.restype = ctypes.c_char_p
 for _f in ("bem_assemble", "bem_apply", "bem_apply_parts", "bem_apply_with", "bem_apply_single_layer",
-           "bem_hmatrix_build", "bem_rhs", "bem_solve", "bem_solve_rhs",
+           "bem_hmatrix_build", "bem_hmatrix_plan", "bem_rhs", "bem_solve", "bem_solve_rhs",
            "bem_apply_preconditioner", "bem_pair_launch_shape",
            "bem_evaluate_field", "bem_footprint_bytes", "bem_last_timings"):
     getattr(_L, _f).restype = ctypes.c_int
 
 EXPORTED = ["bem_assemble", "bem_apply", "bem_apply_parts", "bem_apply_with", "bem_apply_single_layer",
-            "bem_hmatrix_build", "bem_rhs", "bem_solve", "bem_solve_rhs",
+            "bem_hmatrix_build", "bem_hmatrix_plan", "bem_rhs", "bem_solve", "bem_solve_rhs",
             "bem_apply_preconditioner", "bem_pair_launch_shape",
             "bem_evaluate_field", "bem_num_unknowns", "bem_footprint_bytes", "bem_last_timings",
             "bem_destroy", "bem_last_error"]
@@ -202,6 +204,15 @@ def footprint_bytes(domains, n_rhs=1, restart=100):
     out = ctypes.c_uint64(0)
     _check(_L.bem_footprint_bytes(arr, len(domains), None, n_rhs, restart, ctypes.byref(out)))
     return int(out.value)
+
+
+def hmatrix_plan(domains, leaf_vertices=64, eta=1.0):
+    """Host-only plan of the hierarchical matrix's trees (``bem_hmatrix_plan``)."""
+    arr, keep = _domains(domains)
+    out = (ctypes.c_int64 * 4)()
+    _check(_L.bem_hmatrix_plan(arr, len(domains), int(leaf_vertices), float(eta), out))
+    return {"n_blocks": int(out[0]), "n_admissible": int(out[1]), "n_touching": int(out[2]),
+            "n_touching_admissible": int(out[3])}
 
 
 class Problem:

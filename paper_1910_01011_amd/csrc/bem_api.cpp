@@ -64,6 +64,28 @@ void free_problem(bem_problem *p)
     delete p;
 }
 
+// Validated host copies of the domains' meshes and media (no device work).
+void load_domains(bem_problem &p, const bem_domain *domains, int32_t n_domains)
+{
+    int64_t voff = 0, toff = 0;
+    for (int j = 0; j < n_domains; ++j) {
+        const bem_domain &d = domains[j];
+        bem::validate_mesh(d.vertices, d.n_vertices, d.triangles, d.n_triangles, j);
+        bem::DomInfo di{d.n_vertices, d.n_triangles, voff, toff, d.k.re, d.k.im, d.rho};
+        p.doms.push_back(di);
+        p.h_verts.insert(p.h_verts.end(), d.vertices, d.vertices + 3 * d.n_vertices);
+        for (int64_t i = 0; i < 3 * d.n_triangles; ++i) p.h_tris.push_back(int32_t(d.triangles[i] + voff));
+        voff += d.n_vertices;
+        toff += d.n_triangles;
+    }
+    p.NV = voff;
+    p.NT = toff;
+    p.M = 6 * toff;
+    p.N = 2 * voff;
+    if (p.M >= (int64_t(1) << 31) / 10) throw bem::Error{BEM_ERR_INVALID_ARG, "problem too large for 32-bit indexing"};
+    bem::validate_disjoint(p.doms, p.h_verts);
+}
+
 bool finite_c(const bem_complex &z) { return std::isfinite(z.re) && std::isfinite(z.im); }
 
 void build_work(bem_problem &p);
@@ -379,23 +401,7 @@ bem_status bem_assemble(const bem_domain *domains, int32_t n_domains, bem_comple
         p->k0re = k0.re;
         p->k0im = k0.im;
         p->rho0 = rho0;
-        int64_t voff = 0, toff = 0;
-        for (int j = 0; j < n_domains; ++j) {
-            const bem_domain &d = domains[j];
-            bem::validate_mesh(d.vertices, d.n_vertices, d.triangles, d.n_triangles, j);
-            bem::DomInfo di{d.n_vertices, d.n_triangles, voff, toff, d.k.re, d.k.im, d.rho};
-            p->doms.push_back(di);
-            p->h_verts.insert(p->h_verts.end(), d.vertices, d.vertices + 3 * d.n_vertices);
-            for (int64_t i = 0; i < 3 * d.n_triangles; ++i) p->h_tris.push_back(int32_t(d.triangles[i] + voff));
-            voff += d.n_vertices;
-            toff += d.n_triangles;
-        }
-        p->NV = voff;
-        p->NT = toff;
-        p->M = 6 * toff;
-        p->N = 2 * voff;
-        if (p->M >= (int64_t(1) << 31) / 10) throw bem::Error{BEM_ERR_INVALID_ARG, "problem too large for 32-bit indexing"};
-        bem::validate_disjoint(p->doms, p->h_verts);
+        load_domains(*p, domains, n_domains);
         p->h_rowD.resize(p->NV);
         p->h_rowN.resize(p->NV);
         for (const auto &d : p->doms)
@@ -606,6 +612,23 @@ bem_status bem_hmatrix_build(bem_problem *p, double eps, int32_t leaf_vertices, 
             p->hm = nullptr;
         }
         p->hm = bem::hmatrix_build(*p, eps, leaf_vertices, eta, info);
+        return BEM_OK;
+    });
+}
+
+bem_status bem_hmatrix_plan(const bem_domain *domains, int32_t n_domains, int32_t leaf_vertices, double eta,
+                            int64_t *out4)
+{
+    if (!domains || n_domains < 1 || !out4) return fail(BEM_ERR_INVALID_ARG, "bem_hmatrix_plan: bad arguments");
+    if (leaf_vertices < 8 || leaf_vertices > 4096 || !(eta > 0) || !std::isfinite(eta))
+        return fail(BEM_ERR_INVALID_ARG, "bem_hmatrix_plan: need 8 <= leaf_vertices <= 4096, eta > 0");
+    for (int j = 0; j < n_domains; ++j)
+        if (!domains[j].vertices || !domains[j].triangles)
+            return fail(BEM_ERR_INVALID_ARG, "domain " + std::to_string(j) + ": NULL mesh");
+    return guarded([&]() -> bem_status {
+        bem_problem p;
+        load_domains(p, domains, n_domains);
+        bem::hmatrix_plan(p, leaf_vertices, eta, out4);
         return BEM_OK;
     });
 }

@@ -286,6 +286,9 @@ void launch_hblock_correction(bem_problem &p, const int2 *rows, int64_t n_rows, 
                               float2 *const *out, const int32_t *perm, const int32_t *iperm);
 void hmatrix_free(HMatrix *h);
 HMatrix *hmatrix_build(bem_problem &p, double eps, int leaf, double eta, bem_hmatrix_info *info);
+// Host-only plan of the hierarchical matrix's trees: out = {blocks, admissible
+// blocks, entries of the singular pattern, of those the ones in admissible blocks}.
+void hmatrix_plan(const bem_problem &p, int leaf, double eta, int64_t out[4]);
 void hmatrix_apply(bem_problem &p, const double2 *x, double2 *y, int n_rhs, bool record);
 // y = V_k0 x on the union of all boundaries (k_single_layer.hip); events as in the apply
 void launch_single_layer(bem_problem &p, const double2 *x, double2 *y, bool record);

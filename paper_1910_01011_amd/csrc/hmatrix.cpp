@@ -8,11 +8,16 @@
 //    (complete pivoting copes with blocks that mix boundaries; splitting by
 //    boundary first was measured no better);
 //  * block tree: a pair of clusters (s, t) is admissible when
-//    max(diam s, diam t) <= eta dist(s, t) (bounding boxes); admissible pairs
-//    become low-rank blocks, pairs of leaves dense blocks, others are split;
+//    max(diam s, diam t) <= eta dist(s, t); admissible pairs become low-rank
+//    blocks, pairs of leaves dense blocks, others are split.  A cluster's box
+//    bounds the supports of its vertices' P1 functions (every triangle at each
+//    vertex), not the vertices alone: two vertices whose functions meet on
+//    touching triangles then lie in clusters at distance 0, which are never
+//    admissible;
 //  * entries: every block's vertex-pair entries (the far-field sums of the
 //    dense assembly) are computed on the GPU; dense blocks get the FP64 singular
-//    correction (touching pairs never lie in admissible blocks);
+//    correction.  The build counts the entries of the singular pattern that fall
+//    in low-rank blocks and fails unless there are none;
 //  * low-rank blocks: adaptive cross approximation with complete pivoting to
 //    the relative tolerance eps, in batches; a block whose rank would not save
 //    storage is kept dense.
@@ -46,8 +51,17 @@ constexpr int64_t ACA_BATCH_BYTES = int64_t(4) << 30;   // dense scratch of one 
 
 struct Cluster {
     int32_t b, e;          // range in the permuted order
-    double lo[3], hi[3];   // bounding box
+    double lo[3], hi[3];   // bounding box of the supports of its vertices
     int32_t child[2];
+};
+
+// Cluster tree (vertex permutation and clusters) and block tree (blocks with
+// their row and column ranges, and which of them are admissible).
+struct HTree {
+    std::vector<int32_t> perm;
+    std::vector<Cluster> cl;
+    std::vector<HBlock> blocks;
+    std::vector<char> lowrank;
 };
 
 struct DevMem {
@@ -92,6 +106,128 @@ double dist(const Cluster &a, const Cluster &b)
     return std::sqrt(s);
 }
 
+// Bounding box of the support of every vertex's P1 function: the vertices of
+// all triangles at that vertex.  [NV][6] = (lo, hi).
+std::vector<double> support_boxes(const bem_problem &p)
+{
+    std::vector<double> box(6 * size_t(p.NV));
+    for (int64_t i = 0; i < p.NV; ++i)
+        for (int d = 0; d < 3; ++d) box[6 * i + d] = box[6 * i + 3 + d] = p.h_verts[3 * size_t(i) + d];
+    for (int64_t t = 0; t < p.NT; ++t)
+        for (int a = 0; a < 3; ++a) {
+            double *b = &box[6 * size_t(p.h_tris[3 * t + a])];
+            for (int c = 0; c < 3; ++c) {
+                const double *x = &p.h_verts[3 * size_t(p.h_tris[3 * t + c])];
+                for (int d = 0; d < 3; ++d) {
+                    b[d] = std::min(b[d], x[d]);
+                    b[3 + d] = std::max(b[3 + d], x[d]);
+                }
+            }
+        }
+    return box;
+}
+
+HTree plan_tree(const bem_problem &p, int leaf, double eta, int max_side)
+{
+    const int64_t NV = p.NV;
+    const std::vector<double> sbox = support_boxes(p);
+    HTree T;
+    std::vector<int32_t> &perm = T.perm;
+    std::vector<Cluster> &cl = T.cl;
+    perm.resize(NV);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::vector<int32_t> stack;
+    const auto make = [&](int32_t b, int32_t e) {
+        Cluster c{};
+        c.b = b;
+        c.e = e;
+        for (int d = 0; d < 3; ++d) {
+            c.lo[d] = 1e300;
+            c.hi[d] = -1e300;
+        }
+        for (int32_t i = b; i < e; ++i)
+            for (int d = 0; d < 3; ++d) {
+                c.lo[d] = std::min(c.lo[d], sbox[6 * size_t(perm[i]) + d]);
+                c.hi[d] = std::max(c.hi[d], sbox[6 * size_t(perm[i]) + 3 + d]);
+            }
+        c.child[0] = c.child[1] = -1;
+        cl.push_back(c);
+        return int32_t(cl.size() - 1);
+    };
+    stack.push_back(make(0, int32_t(NV)));
+    while (!stack.empty()) {
+        const int32_t ci = stack.back();
+        stack.pop_back();
+        const Cluster c = cl[ci];
+        if (c.e - c.b <= leaf) continue;
+        int ax = 0;
+        for (int d = 1; d < 3; ++d)
+            if (c.hi[d] - c.lo[d] > c.hi[ax] - c.lo[ax]) ax = d;
+        const int32_t mid = c.b + (c.e - c.b) / 2;
+        std::nth_element(perm.begin() + c.b, perm.begin() + mid, perm.begin() + c.e, [&](int32_t u, int32_t v) {
+            const double xu = p.h_verts[3 * size_t(u) + ax], xv = p.h_verts[3 * size_t(v) + ax];
+            return xu < xv || (xu == xv && u < v);
+        });
+        const int32_t c0 = make(c.b, mid), c1 = make(mid, c.e);
+        cl[ci].child[0] = c0;
+        cl[ci].child[1] = c1;
+        stack.push_back(c0);
+        stack.push_back(c1);
+    }
+    std::vector<std::pair<int32_t, int32_t>> todo{{0, 0}};
+    while (!todo.empty()) {
+        const auto [a, b] = todo.back();
+        todo.pop_back();
+        const Cluster &A = cl[a], &B = cl[b];
+        // admissible pairs larger than max_side vertices on a side are split
+        // further: each block's cross approximation runs in one workgroup, so
+        // bounded blocks keep the whole chip busy
+        const bool adm = std::max(diam(A), diam(B)) <= eta * dist(A, B) && A.e - A.b <= max_side &&
+                         B.e - B.b <= max_side;
+        const bool la = A.child[0] < 0, lb = B.child[0] < 0;
+        if (adm || (la && lb)) {
+            HBlock hb{};
+            hb.r0 = A.b;
+            hb.r1 = A.e;
+            hb.c0 = B.b;
+            hb.c1 = B.e;
+            hb.rank = -1;
+            T.blocks.push_back(hb);
+            T.lowrank.push_back(adm ? 1 : 0);
+        } else if (la) {
+            todo.push_back({a, B.child[0]});
+            todo.push_back({a, B.child[1]});
+        } else if (lb) {
+            todo.push_back({A.child[0], b});
+            todo.push_back({A.child[1], b});
+        } else {
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j) todo.push_back({A.child[i], B.child[j]});
+        }
+    }
+    return T;
+}
+
+int64_t touching_in_lowrank(const HTree &T, int64_t NV, const std::vector<int32_t> &cptr,
+                            const std::vector<int32_t> &ccol)
+{
+    std::vector<int32_t> iperm(NV);
+    for (int64_t i = 0; i < NV; ++i) iperm[T.perm[i]] = int32_t(i);
+    int64_t n = 0;
+    for (size_t i = 0; i < T.blocks.size(); ++i) {
+        if (!T.lowrank[i]) continue;
+        const HBlock &hb = T.blocks[i];
+        for (int32_t r = hb.r0; r < hb.r1; ++r) {
+            const int32_t g = T.perm[r];
+            for (int32_t k = cptr[g]; k < cptr[g + 1]; ++k) {
+                const int32_t c = iperm[ccol[k]];
+                n += (c >= hb.c0 && c < hb.c1) ? 1 : 0;
+            }
+        }
+    }
+    return n;
+}
+
 }  // namespace
 
 struct HMatrix {
@@ -119,85 +255,26 @@ static HMatrix *build(bem_problem &p, double eps, int leaf, double eta, int max_
     const auto t_start = std::chrono::steady_clock::now();
     const int64_t NV = p.NV;
     hipStream_t s = p.stream;
-    // cluster tree
-    std::vector<int32_t> perm(NV);
-    std::iota(perm.begin(), perm.end(), 0);
-    std::vector<Cluster> cl;
-    std::vector<int32_t> stack;
-    const auto make = [&](int32_t b, int32_t e) {
-        Cluster c{};
-        c.b = b;
-        c.e = e;
-        for (int d = 0; d < 3; ++d) {
-            c.lo[d] = 1e300;
-            c.hi[d] = -1e300;
-        }
-        for (int32_t i = b; i < e; ++i)
-            for (int d = 0; d < 3; ++d) {
-                const double x = p.h_verts[3 * size_t(perm[i]) + d];
-                c.lo[d] = std::min(c.lo[d], x);
-                c.hi[d] = std::max(c.hi[d], x);
-            }
-        c.child[0] = c.child[1] = -1;
-        cl.push_back(c);
-        return int32_t(cl.size() - 1);
-    };
-    stack.push_back(make(0, int32_t(NV)));
-    while (!stack.empty()) {
-        const int32_t ci = stack.back();
-        stack.pop_back();
-        const Cluster c = cl[ci];
-        if (c.e - c.b <= leaf) continue;
-        int ax = 0;
-        for (int d = 1; d < 3; ++d)
-            if (c.hi[d] - c.lo[d] > c.hi[ax] - c.lo[ax]) ax = d;
-        const int32_t mid = c.b + (c.e - c.b) / 2;
-        std::nth_element(perm.begin() + c.b, perm.begin() + mid, perm.begin() + c.e, [&](int32_t u, int32_t v) {
-            const double xu = p.h_verts[3 * size_t(u) + ax], xv = p.h_verts[3 * size_t(v) + ax];
-            return xu < xv || (xu == xv && u < v);
-        });
-        const int32_t c0 = make(c.b, mid), c1 = make(mid, c.e);
-        cl[ci].child[0] = c0;
-        cl[ci].child[1] = c1;
-        stack.push_back(c0);
-        stack.push_back(c1);
+    HTree T = plan_tree(p, leaf, eta, max_side);
+    std::vector<int32_t> &perm = T.perm;
+    {
+        // every entry of the singular pattern must lie in a dense block (that
+        // is where the FP64 correction is added)
+        std::vector<int32_t> cptr(NV + 1), ccol(std::max<int64_t>(1, p.nnz));
+        BEM_HIP(hipMemcpyAsync(cptr.data(), p.d_cptr, cptr.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        if (p.nnz > 0)
+            BEM_HIP(hipMemcpyAsync(ccol.data(), p.d_ccol, size_t(p.nnz) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        BEM_HIP(hipStreamSynchronize(s));
+        const int64_t bad = touching_in_lowrank(T, NV, cptr, ccol);
+        if (bad != 0)
+            throw Error{BEM_ERR_DEVICE, "hierarchical matrix: " + std::to_string(bad) +
+                                            " singular-pattern entries in low-rank blocks"};
     }
     std::vector<int32_t> iperm(NV);
     for (int64_t i = 0; i < NV; ++i) iperm[perm[i]] = int32_t(i);
-    // block tree
     auto H = std::make_unique<HMatrix>();
-    std::vector<std::pair<int32_t, int32_t>> todo{{0, 0}};
-    std::vector<char> lowrank;
-    while (!todo.empty()) {
-        const auto [a, b] = todo.back();
-        todo.pop_back();
-        const Cluster &A = cl[a], &B = cl[b];
-        // admissible pairs larger than max_side vertices on a side are split
-        // further: each block's cross approximation runs in one workgroup, so
-        // bounded blocks keep the whole chip busy
-        const bool adm = std::max(diam(A), diam(B)) <= eta * dist(A, B) && A.e - A.b <= max_side &&
-                         B.e - B.b <= max_side;
-        const bool la = A.child[0] < 0, lb = B.child[0] < 0;
-        if (adm || (la && lb)) {
-            HBlock hb{};
-            hb.r0 = A.b;
-            hb.r1 = A.e;
-            hb.c0 = B.b;
-            hb.c1 = B.e;
-            hb.rank = -1;
-            H->blocks.push_back(hb);
-            lowrank.push_back(adm ? 1 : 0);
-        } else if (la) {
-            todo.push_back({a, B.child[0]});
-            todo.push_back({a, B.child[1]});
-        } else if (lb) {
-            todo.push_back({A.child[0], b});
-            todo.push_back({A.child[1], b});
-        } else {
-            for (int i = 0; i < 2; ++i)
-                for (int j = 0; j < 2; ++j) todo.push_back({A.child[i], B.child[j]});
-        }
-    }
+    H->blocks = std::move(T.blocks);
+    std::vector<char> lowrank = std::move(T.lowrank);
     const int nb = int(H->blocks.size());
     // product offsets and the per-row lists
     int64_t zl = 0;
@@ -446,6 +523,21 @@ HMatrix *hmatrix_build(bem_problem &p, double eps, int leaf, double eta, bem_hma
     HMatrix *h = build(p, eps, leaf, eta, std::max(max_side, leaf));
     if (info) *info = h->info;
     return h;
+}
+
+void hmatrix_plan(const bem_problem &p, int leaf, double eta, int64_t out[4])
+{
+    const HTree T = plan_tree(p, leaf, eta, std::max(HBLOCK_MAX_SIDE, leaf));
+    std::vector<SingularItem> items;
+    touching_pairs(p, items);
+    std::vector<int32_t> cptr, ccol, cp, ci;
+    correction_pattern(p, items, cptr, ccol, cp, ci);
+    int64_t n_adm = 0;
+    for (char c : T.lowrank) n_adm += c;
+    out[0] = int64_t(T.blocks.size());
+    out[1] = n_adm;
+    out[2] = int64_t(ccol.size());
+    out[3] = touching_in_lowrank(T, p.NV, cptr, ccol);
 }
 
 }  // namespace bem

@@ -4,7 +4,8 @@
   the exact operator by the FP32 entries (~1e-7) plus the cross-approximation
   truncation, at most eps of each block's largest entry: with eps = 1e-4 (the
   blocks of these small meshes are too small to compress at tighter
-  tolerances) the relative error of a random apply stays below 1e-3;
+  tolerances) the relative error of a random apply stays below 1e-5, also on
+  the fine trees of 8-vertex leaves;
 * against the library's dense complex64 matrix (same FP32 entries): the
   difference is the truncation alone, and it falls with eps (1e-2, then 1e-4);
 * GMRES on the compressed operator (eps = 1e-5) converges, and its solution
@@ -33,20 +34,27 @@ def _attenuating():
                            complex(2.0, 0.05), 1.0, "sphere642_attenuating")
 
 
-@pytest.mark.parametrize("prob", [configs.config1(), configs.two_spheres(), _attenuating()], ids=lambda p: p.name)
-def test_hmatrix_apply_matches_oracle(prob):
+_CASES = [(configs.config1(), 16), (configs.config1(), 8), (configs.two_spheres(), 16), (configs.two_spheres(), 8),
+          (_attenuating(), 16)]
+
+
+@pytest.mark.parametrize("prob,leaf", _CASES, ids=[f"{p.name}-leaf{l}" for p, l in _CASES])
+def test_hmatrix_apply_matches_oracle(prob, leaf):
+    """The truncation at eps = 1e-4 of each block's largest entry leaves a few
+    1e-7 on a random apply; a touching pair placed in a low-rank block (its
+    FP64 singular correction dropped) costs far more than the 1e-5 allowed."""
     import paper_1910_01011_amd as bem
     A = oracle.pmchwt_matrix(prob)
     P = bem.Problem.from_config(prob)
-    info = P.hmatrix_build(eps=1e-4, leaf_vertices=16, eta=2.0)
-    print(f"{prob.name}: {info}", flush=True)
+    info = P.hmatrix_build(eps=1e-4, leaf_vertices=leaf, eta=2.0)
+    print(f"{prob.name} leaf {leaf}: {info}", flush=True)
     assert info["n_lowrank"] > 0 and info["n_dense"] > 0
     X = vectors.random_complex(prob.n_unknowns, seed=21, n_rhs=2)
     Y = P.apply(X, kernel=bem.BEM_APPLY_HMATRIX)
     for r in range(2):
         err = _relerr(Y[r], A @ X[r])
         print(f"{prob.name} H apply rhs {r}: rel err {err:.2e}", flush=True)
-        assert err <= 1e-3
+        assert err <= 1e-5
     assert np.array_equal(P.apply(X, kernel=bem.BEM_APPLY_HMATRIX), Y)
     P.close()
 

@@ -126,3 +126,30 @@ def test_binding_structs_follow_the_header(cname):
         for part in decl.split(","):
             names.append(re.findall(r"\**(\w+)\s*$", part.strip())[0])
     assert [f[0] for f in getattr(bem, cname)._fields_] == names
+
+
+@pytest.mark.parametrize("leaf,eta", [(8, 2.0), (8, 1.0), (16, 2.0), (16, 4.0)])
+def test_hmatrix_tree_keeps_touching_pairs_out_of_lowrank_blocks(leaf, eta):
+    """Every vertex pair that the singular pass corrects (touching triangles of
+    one boundary) lies in a dense block of the hierarchical matrix: the
+    clusters' boxes bound the supports of their basis functions, so such pairs
+    are at distance 0 and never admissible.  Checked on the host on the trees
+    the build uses, at leaf sizes and eta values that admit many blocks."""
+    bem = _bem()
+    for prob in (configs.config1(), configs.two_spheres()):
+        plan = bem.hmatrix_plan(prob.domains, leaf_vertices=leaf, eta=eta)
+        assert plan["n_admissible"] > 0 and plan["n_touching"] > 0, plan
+        assert plan["n_touching_admissible"] == 0, (prob.name, leaf, eta, plan)
+
+
+def test_hmatrix_plan_errors():
+    bem = _bem()
+    v, t = meshes.icosphere(1)
+    with pytest.raises(bem.BemError) as e:
+        bem.hmatrix_plan([_dom(v, t)], leaf_vertices=4)
+    assert e.value.status == bem.BEM_ERR_INVALID_ARG
+    tt = t.copy()
+    tt[0, 0] = v.shape[0] + 3
+    with pytest.raises(bem.BemError) as e:
+        bem.hmatrix_plan([_dom(v, tt)], leaf_vertices=8)
+    assert e.value.status == bem.BEM_ERR_MESH
