@@ -22,3 +22,21 @@ def random_rows(n: int, count: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     count = min(count, n)
     return np.sort(rng.choice(n, size=count, replace=False)).astype(np.int64)
+
+
+def stratified_rows(n_vertices, per_domain: int, seed: int) -> np.ndarray:
+    """Unknown indices sampled from every domain: for each domain (vertex
+    counts ``n_vertices``, unknowns laid out domain by domain as [u_D; u_N])
+    its first and last vertex plus ``per_domain - 2`` distinct random ones
+    (``default_rng(seed)``), each with both its u_D and u_N row.  Sorted."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    off = 0
+    for nv in n_vertices:
+        nv = int(nv)
+        k = max(0, min(per_domain, nv) - 2)
+        inner = rng.choice(np.arange(1, nv - 1), size=min(k, max(0, nv - 2)), replace=False) if nv > 2 else []
+        vtx = np.unique(np.concatenate([[0, nv - 1], np.asarray(inner, dtype=np.int64)]))
+        rows += list(off + vtx) + list(off + nv + vtx)
+        off += 2 * nv
+    return np.sort(np.asarray(rows, dtype=np.int64))

@@ -1,20 +1,27 @@
 """Benchmark: quadrature-pair interactions/s of the Galerkin PMCHWT apply.
 
-One step = one full operator apply y = A x on the sphere workload with 10,242
-vertices / 20,480 triangles (k0 = 10, k1 = 10.5, density ratio 1.05): gather,
-FP32 pair kernel for the exterior pass (union of boundaries, k0) and the
-interior pass (k1), reduction, test-side projection and the FP64 singular
-correction.  Inputs are resident in HBM before the timed region.
+One step = one full on-the-fly operator apply y = A x on the rib-cage stack
+(the paper's ribs + fat layer + liver model problem, synthetic stand-in): a fat
+slab, five capsule ribs and a liver box, 53,524 vertices / 107,048 unknowns
+meshed at lambda/6, exterior k0 = 2 pi plus one interior pass per domain.  The
+apply is gather, the FP32 pair kernel (exterior pass over the union of all
+boundaries, interior passes per domain), reduction, test-side projection and
+the FP64 singular correction.  Inputs are resident in HBM before the timed
+region.
 
-Also reported: GMRES time-to-solve at 1e-5 on the same problem (plane wave),
-the roofline of the pair kernel (HIP events on the library's stream) and the
-FP64 CPU oracle timed on a bounded sample of rows on this host.
+Also on the line: the GMRES time-to-solve of the stack's 256-piston field to a
+true (unpreconditioned, on-the-fly operator) relative residual of 1e-5, the
+roofline of the pair kernel (HIP events on the library's stream), the FP64 CPU
+oracle timed on a bounded sample of rows on this host, and, as a sub-object,
+the 10,242-vertex sphere (apply, solves with and without OSRC, assembled
+GEMV/GEMM paths).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-solve]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-solve] [--no-sphere]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,6 +36,8 @@ METRIC = "BEM apply G quad-pair interactions/s + GMRES time-to-solve at 1e-5; p5
 FLOP_PER_PAIR = 140.0          # fused V, K, K', W multitrace pair (per-pair count of the design notes)
 FLOP_PER_PAIR_V = 21.0         # single-layer pair alone: difference, r^2, r, phase, G, one complex multiply-add
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector peak
+ACHIEVED_KIND = ("algorithmic: 140 FLOP per quadrature-point pair (difference, r^2, rsq, phase, G, F and 15 "
+                 "complex channel multiply-adds) x pairs per launch / mean HIP-event duration of the kernel")
 
 
 def pairs_per_apply(prob):
@@ -36,8 +45,19 @@ def pairs_per_apply(prob):
     return float(m_all) ** 2 + sum(float(6 * d.n_triangles) ** 2 for d in prob.domains)
 
 
-def cpu_baseline(prob, seconds_target=15.0):
-    """FP64 oracle rows on this host; scaled to interactions/s of a full apply."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(prob, seconds_target=8.0, repeats=3):
+    """FP64 oracle rows on this host, scaled to interactions/s of a full apply;
+    the median of ``repeats`` timings of the same sample."""
     import oracle
     from bem_inputs import vectors
 
@@ -47,48 +67,152 @@ def cpu_baseline(prob, seconds_target=15.0):
         nthreads = int(env_threads)
     x = vectors.random_complex(prob.n_unknowns, seed=0)
     nv = sum(d.n_vertices for d in prob.domains)
-    # warm up (thread pool, rule tables), calibrate on 16 vertices, then run a
-    # sample sized for ~seconds_target
-    oracle.pmchwt_rows(prob, vectors.random_rows(nv, 2, seed=10))
-    n_v = 16
+    # warm up (thread pool, rule tables), calibrate on a few vertices, then time
+    # a sample sized for about seconds_target, three times
+    oracle.pmchwt_rows(prob, vectors.random_rows(nv, 1, seed=10))
+    n_v = 2
     t0 = time.perf_counter()
-    rows = vectors.random_rows(nv, n_v, seed=11)
-    R = oracle.pmchwt_rows(prob, rows)
-    _ = R @ x
+    R = oracle.pmchwt_rows(prob, vectors.random_rows(nv, n_v, seed=11))
     dt = time.perf_counter() - t0
     n_v2 = int(np.clip(n_v * seconds_target / max(dt, 1e-3), n_v, 4096))
     rows = vectors.random_rows(nv, n_v2, seed=12)
-    t0 = time.perf_counter()
-    R = oracle.pmchwt_rows(prob, rows)   # Dirichlet rows of the sampled vertices (all four operators computed)
-    _ = R @ x
-    dt = time.perf_counter() - t0
+    times = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        R = oracle.pmchwt_rows(prob, rows)   # Dirichlet rows of the sampled vertices (all four operators computed)
+        _ = R @ x
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
     frac = n_v2 / nv
     return {"value": frac * pairs_per_apply(prob) / dt, "unit": "quad-pair interactions/s", "cores": nthreads,
-            "kind": "oracle",
-            "sample": f"FP64 oracle rows of {n_v2} random test vertices of {nv} (V, K, K', W at k0 and k1, "
-                      f"6-point far rule + Sauter-Schwab order 6), {dt:.1f} s, scaled by {nv}/{n_v2}"}
+            "kind": "oracle", "cpu_model": cpu_model(), "repeats": repeats,
+            "times_s": [round(t, 3) for t in times],
+            "sample": f"{prob.name}: FP64 oracle rows of {n_v2} random test vertices of {nv} (V, K, K', W at k0 and "
+                      f"each domain's k, 6-point far rule + Sauter-Schwab order 6), median of {repeats} runs "
+                      f"{dt:.1f} s, scaled by {nv}/{n_v2}"}
+
+
+def profile_fields(name, source="k_farfield.hip"):
+    """Key-value lines of a committed profile summary, or None when the kernel
+    source changed since the counters were taken (SHA-256 recorded there)."""
+    path = os.path.join(ROOT, "profiles", name)
+    src = os.path.join(ROOT, "paper_1910_01011_amd", "csrc", source)
+    try:
+        fields = {}
+        for line in open(path):
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                fields[k.strip()] = v.strip().strip("`")
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if fields.get(f"{source} sha256") != digest:
+            return None
+        return fields
+    except OSError:
+        return None
+
+
+def recorded_traffic(name):
+    """HBM bytes per k_pairs launch from a committed counter summary, or None."""
+    f = profile_fields(name)
+    try:
+        return float(f["HBM bytes per launch"]) if f else None
+    except (KeyError, ValueError):
+        return None
+
+
+def recorded_executed_flop(name):
+    """Executed FP32 FLOP per k_pairs launch from a committed VALU-counter
+    summary (64 lanes x (ADD + MUL + TRANS + 2 FMA) F32 instructions), or None."""
+    f = profile_fields(name)
+    try:
+        return float(f["executed FP32 FLOP per launch"]) if f else None
+    except (KeyError, ValueError):
+        return None
+
+
+def time_applies(P, x, y, steps, warmup, torch):
+    """Warm-up applies, then `steps` timed applies: wall time of the whole
+    region, and per apply the HIP-event durations of the apply and of the pair
+    kernel (recorded on the library's stream)."""
+    for _ in range(warmup):
+        P.apply(x, out=y)
+    torch.cuda.synchronize()
+    pair_ms, step_ms = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        P.apply(x, out=y)
+        tm = P.timings()       # waits for this apply's events on the library stream
+        step_ms.append(tm[0])
+        pair_ms.append(tm[1])
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, step_ms, pair_ms
+
+
+def pair_roofline(pairs, pair_ms, traffic_profile, valu_profile):
+    k_ms = float(np.mean(pair_ms))
+    achieved = FLOP_PER_PAIR * pairs / (k_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_PEAK_TFLOPS, "traffic": recorded_traffic(traffic_profile),
+            "kernel": "k_pairs", "kernel_ms": k_ms, "flop_per_pair": FLOP_PER_PAIR, "achieved_kind": ACHIEVED_KIND}
+    ex = recorded_executed_flop(valu_profile)
+    if ex is not None:
+        t = ex / (k_ms * 1e-3) / 1e12
+        roof["executed"] = {"tflops": t, "frac": t / FP32_PEAK_TFLOPS, "flop_per_launch": ex,
+                            "flop_per_pair": ex / pairs, "source": f"profiles/{valu_profile}"}
+    else:
+        roof["executed"] = None
+    return roof
+
+
+def ribcage_time_to_solve(P, prob, bem, torch):
+    """Time-to-solve of the stack's 256-piston bowl (one field, all pistons at
+    unit amplitude) to a true relative residual of 1e-5 of the on-the-fly FP32
+    operator: flexible GMRES(10) whose Arnoldi vectors and residual use the
+    on-the-fly apply (FP64 accumulation), with inner OSRC-preconditioned
+    GMRES(200) to 1e-3 on the hierarchical matrix (ACA, eps 1e-4, leaves of 64,
+    eta 2; N_Pade = 8, R_eps = 1.5).  The hierarchical-matrix build is set-up
+    and reported beside the solve."""
+    from bem_inputs import pistons
+    c, n, a = pistons.bowl_array()
+    b = P.rhs(bem.Incident.pistons(c, n, a, 1.0, np.zeros(len(c), dtype=int)))
+    hinfo, t_build = _timed(torch, lambda: P.hmatrix_build(eps=1e-4, leaf_vertices=64, eta=2.0))
+    log(f"ribcage H-matrix: {hinfo['bytes'] / 1e9:.1f} GB, build {t_build:.1f} s")
+    opts = bem.solve_options(tol=1e-5, restart=10, max_iter=10, precond=bem.BEM_PRECOND_OSRC, n_pade=8, r_eps=1.5,
+                             theta=np.pi / 3, precision=bem.BEM_PREC_HMATRIX_FGMRES, inner_tol=1e-3,
+                             inner_restart=200, inner_max_iter=1000)
+    (u, info), t = _timed(torch, lambda: P.solve(b, opts))
+    log(f"ribcage time-to-solve {t:.1f} s, residual {info[0]['rel_residual']:.2e}")
+    return {"tol": 1e-5, "time_to_solve_s": t, "converged": info[0]["converged"],
+            "rel_residual": info[0]["rel_residual"], "outer_iterations": info[0]["iterations"],
+            "setup_hmatrix_build_s": t_build,
+            "hmatrix": {k: hinfo[k] for k in ("bytes", "dense_bytes", "n_lowrank", "n_dense", "max_rank")},
+            "method": "flexible GMRES(10), outer Arnoldi and residual on the on-the-fly FP32 operator; inner "
+                      "right-hand side: OSRC-preconditioned GMRES(200) to 1e-3 on the hierarchical matrix "
+                      "(ACA eps 1e-4); rel_residual is the true residual of the on-the-fly operator"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-sphere", action="store_true", help="skip the 10,242-vertex sphere sub-object")
     ap.add_argument("--no-assembled", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the heuristic launch shapes")
     ap.add_argument("--extra", default="",
-                    help="comma list of extra workloads appended to the JSON line: ribcage (53.5k-vertex stack, "
-                         "on the fly, pistons, OSRC), ribcage_assembled (26.9k vertices, 256 right-hand sides), "
+                    help="comma list of extra workloads appended to the JSON line: ribcage (OSRC GMRES on the "
+                         "fly on the 53.5k-vertex stack), ribcage_assembled (26.9k vertices, 256 right-hand sides), "
                          "serving (kidney request stream), paper_sphere (the paper's 1 cm sphere at 1 MHz, fat and "
                          "rib material, 4-10 elements per wavelength, OSRC GMRES), planning (full matrix capture "
                          "of 256 pistons on the 13.5k-vertex stack, then phase conjugation and rib sparing), hmatrix "
                          "(ACA-compressed operator on the sphere and the 53.5k-vertex stack)")
     ap.add_argument("--serving-requests", type=int, default=8, help="requests per arrival rate in --extra serving")
     ap.add_argument("--traffic-probe", action="store_true",
-                    help="run only a 1 GiB elementwise copy (the counter scale) and 3 applies, for HBM counters")
-    ap.add_argument("--level", type=int, default=5, help="icosphere level of the sphere workload (5: 10,242 v)")
+                    help="run only a 1 GiB elementwise copy (the counter scale) and 3 applies, for counter runs")
+    ap.add_argument("--probe-workload", default="ribcage", choices=("ribcage", "sphere"),
+                    help="workload of --traffic-probe")
     ap.add_argument("--assembled-kernels-only", action="store_true",
                     help="assembled section without its solves (GEMV and GEMM launches only, for counter runs)")
     args = ap.parse_args()
@@ -103,100 +227,55 @@ def main():
     from bem_inputs import configs, vectors
 
     torch.cuda.set_device(0)
-    prob = configs.config2() if args.level == 5 else configs.sphere_problem(args.level, 10.0, 10.5, 1.05)
-    t_setup = time.perf_counter()
-    P = bem.Problem.from_config(prob, device=True, autotune=not args.no_autotune)
-    torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t_setup
+    if args.traffic_probe:
+        prob = configs.ribcage(1.0) if args.probe_workload == "ribcage" else configs.config2()
+        P = bem.Problem.from_config(prob, device=True, autotune=not args.no_autotune)
+        x = torch.from_numpy(vectors.random_complex(prob.n_unknowns, seed=0)).cuda()
+        traffic_probe(P, x, torch.empty_like(x), torch)
+        return
+    prob = configs.ribcage(1.0)
+    log(f"rib-cage stack: {sum(d.n_vertices for d in prob.domains)} vertices, {prob.n_unknowns} unknowns")
+    P, t_setup = _timed(torch, lambda: bem.Problem.from_config(prob, device=True, autotune=not args.no_autotune))
+    log(f"set-up {t_setup:.1f} s, pair launch shape {P.pair_launch_shape()}")
     x = torch.from_numpy(vectors.random_complex(prob.n_unknowns, seed=0)).cuda()
     y = torch.empty_like(x)
-    if args.traffic_probe:
-        traffic_probe(P, x, y, torch)
-        return
-    for _ in range(args.warmup):
-        P.apply(x, out=y)
-    torch.cuda.synchronize()
-    pair_ms = []
-    step_ms = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        P.apply(x, out=y)
-        tm = P.timings()       # waits for this apply's events on the library stream
-        step_ms.append(tm[0])
-        pair_ms.append(tm[1])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall, step_ms, pair_ms = time_applies(P, x, y, args.steps, args.warmup, torch)
     pairs = pairs_per_apply(prob)
-    ms_per_step = 1e3 * wall / args.steps
-    value = pairs * args.steps / wall
-    pair_avg = float(np.mean(pair_ms))
-    achieved = FLOP_PER_PAIR * pairs / (pair_avg * 1e-3) / 1e12
-
+    log(f"ribcage apply {1e3 * wall / args.steps:.1f} ms per step")
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": pairs * args.steps / wall,
         "unit": "quad-pair interactions/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": 1e3 * wall / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{prob.name}: on-the-fly PMCHWT apply, icosphere {prob.domains[0].n_vertices} v / "
-                               f"{prob.domains[0].n_triangles} t, k0=10, k1=10.5, rho1/rho0=1.05, 6-pt far rule, "
-                               f"Sauter-Schwab order 6 singular pass",
+        "config": {"workload": f"{prob.name}: rib-cage stack (fat slab, five capsule ribs, liver box; 7 domains, "
+                               f"{sum(d.n_vertices for d in prob.domains)} v / {sum(d.n_triangles for d in prob.domains)} t "
+                               f"at lambda/6), on-the-fly PMCHWT apply, k0 = 2 pi, speed ratios 0.96 / 1.87 / 1.03, "
+                               f"density ratios 0.95 / 1.9 / 1.07, 6-pt far rule, Sauter-Schwab order 6 singular pass",
                    "pairs_per_apply": pairs, "unknowns": prob.n_unknowns, "setup_s": t_setup,
                    "autotune": not args.no_autotune, "pair_launch_shape": list(P.pair_launch_shape()),
                    "apply_ms_p50": float(np.percentile(step_ms, 50)),
                    "apply_ms_p99": float(np.percentile(step_ms, 99))},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": recorded_traffic(),
-                     "kernel": "k_pairs", "kernel_ms": pair_avg, "flop_per_pair": FLOP_PER_PAIR},
+        "roofline": pair_roofline(pairs, pair_ms, "k_pairs_ribcage53524_hbm_traffic.md",
+                                  "k_pairs_ribcage53524_valu.md"),
     }
-    out["single_layer"] = single_layer_section(P, prob, torch, args.steps, args.warmup)
     if not args.no_solve:
-        # GMRES(100) on the on-the-fly operator, plane wave along +z, without and
-        # with the OSRC preconditioner (N_Pade = 4, R_eps = 0.1 = radius / 10)
-        inc = bem.Incident.plane_waves([[0.0, 0.0, 1.0]])
-        b = P.rhs(inc)
-        g = {}
-        for pname, pc in (("plain", bem.BEM_PRECOND_NONE), ("osrc", bem.BEM_PRECOND_OSRC)):
-            for tol in (1e-5, 1e-6):
-                torch.cuda.synchronize()
-                ts = time.perf_counter()
-                u, info = P.solve(b, bem.solve_options(tol=tol, restart=100, max_iter=400, precond=pc, n_pade=4,
-                                                       r_eps=0.1, theta=np.pi / 3))
-                torch.cuda.synchronize()
-                ts = time.perf_counter() - ts
-                g[f"{pname}_tol{tol:g}"] = {"time_to_solve_s": ts, "iterations": info[0]["iterations"],
-                                            "rel_residual": info[0]["rel_residual"],
-                                            "converged": info[0]["converged"]}
-        # OSRC with tighter inner sparse solves than the default (one tenth of
-        # the GMRES tolerance): 1e-8 and 1e-10
-        for otol in (1e-8, 1e-10):
-            torch.cuda.synchronize()
-            ts = time.perf_counter()
-            u, info = P.solve(b, bem.solve_options(tol=1e-5, restart=100, max_iter=400, precond=bem.BEM_PRECOND_OSRC,
-                                                   n_pade=4, r_eps=0.1, theta=np.pi / 3, osrc_tol=otol))
-            torch.cuda.synchronize()
-            ts = time.perf_counter() - ts
-            g[f"osrc_cocg{otol:g}_tol1e-05"] = {"time_to_solve_s": ts, "iterations": info[0]["iterations"],
-                                                "rel_residual": info[0]["rel_residual"],
-                                                "converged": info[0]["converged"]}
-        out["gmres"] = g
-    if not args.no_assembled:
-        P = None
-        torch.cuda.empty_cache()
-        out["assembled"] = assembled_section(prob, bem, vectors, torch, autotune=not args.no_autotune,
-                                             solves=not args.assembled_kernels_only)
+        out["time_to_solve"] = ribcage_time_to_solve(P, prob, bem, torch)
+    P.close()
+    P = None
+    torch.cuda.empty_cache()
+    if not args.no_sphere:
+        out["sphere10242"] = sphere_section(args, bem, torch)
     extras = [e for e in args.extra.split(",") if e]
     if extras:
         os.environ.setdefault("BEM_PROGRESS", "50")   # solver progress lines on stderr
-        P = None
-        torch.cuda.empty_cache()
     for e in extras:
         log(f"extra workload {e}")
         if e == "ribcage":
@@ -214,11 +293,59 @@ def main():
         else:
             raise SystemExit(f"unknown extra workload {e}")
         torch.cuda.empty_cache()
-    if not args.no_solve:
+    if not args.no_solve and not args.no_sphere:
         out["config1"] = config1_section(bem, torch, oracle_leg=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
+        log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out))
+
+
+def sphere_section(args, bem, torch):
+    """The 10,242-vertex sphere (k0 = 10, k1 = 10.5, density ratio 1.05): the
+    on-the-fly apply with its pair-kernel roofline, the single-layer operator
+    alone, GMRES to 1e-5 and 1e-6 without and with OSRC (right- and
+    left-preconditioned), and the assembled paths."""
+    from bem_inputs import configs, vectors
+    prob = configs.config2()
+    P, t_setup = _timed(torch, lambda: bem.Problem.from_config(prob, device=True, autotune=not args.no_autotune))
+    x = torch.from_numpy(vectors.random_complex(prob.n_unknowns, seed=0)).cuda()
+    y = torch.empty_like(x)
+    wall, step_ms, pair_ms = time_applies(P, x, y, args.steps, args.warmup, torch)
+    pairs = pairs_per_apply(prob)
+    out = {"workload": f"{prob.name}: on-the-fly PMCHWT apply, icosphere {prob.domains[0].n_vertices} v / "
+                       f"{prob.domains[0].n_triangles} t, k0=10, k1=10.5, rho1/rho0=1.05",
+           "value": pairs * args.steps / wall, "unit": "quad-pair interactions/s",
+           "ms_per_step": 1e3 * wall / args.steps, "pairs_per_apply": pairs, "unknowns": prob.n_unknowns,
+           "setup_s": t_setup, "pair_launch_shape": list(P.pair_launch_shape()),
+           "apply_ms_p50": float(np.percentile(step_ms, 50)), "apply_ms_p99": float(np.percentile(step_ms, 99)),
+           "roofline": pair_roofline(pairs, pair_ms, "k_pairs_sphere10242_hbm_traffic.md", "k_pairs_sphere10242_valu.md")}
+    log(f"sphere apply {out['ms_per_step']:.2f} ms")
+    out["single_layer"] = single_layer_section(P, prob, torch, args.steps, args.warmup)
+    if not args.no_solve:
+        # GMRES(100) on the on-the-fly operator, plane wave along +z, without and
+        # with the OSRC preconditioner (N_Pade = 4, R_eps = 0.1 = radius / 10):
+        # right-preconditioned (stops on the true residual) and the paper's
+        # left form (stops on the preconditioned residual)
+        inc = bem.Incident.plane_waves([[0.0, 0.0, 1.0]])
+        b = P.rhs(inc)
+        g = {}
+        for pname, pc in (("plain", bem.BEM_PRECOND_NONE), ("osrc", bem.BEM_PRECOND_OSRC),
+                          ("osrc_left", bem.BEM_PRECOND_OSRC_LEFT)):
+            for tol in (1e-5, 1e-6):
+                (u, info), ts = _timed(torch, lambda: P.solve(b, bem.solve_options(
+                    tol=tol, restart=100, max_iter=400, precond=pc, n_pade=4, r_eps=0.1, theta=np.pi / 3)))
+                g[f"{pname}_tol{tol:g}"] = {"time_to_solve_s": ts, "iterations": info[0]["iterations"],
+                                            "rel_residual": info[0]["rel_residual"],
+                                            "converged": info[0]["converged"]}
+        out["gmres"] = g
+    P.close()
+    P = None
+    torch.cuda.empty_cache()
+    if not args.no_assembled:
+        out["assembled"] = assembled_section(prob, bem, vectors, torch, autotune=not args.no_autotune,
+                                             solves=not args.assembled_kernels_only)
+    return out
 
 
 def single_layer_section(P, prob, torch, steps, warmup):
@@ -538,26 +665,6 @@ def traffic_probe(P, x, y, torch):
         P.apply(x, out=y)
     torch.cuda.synchronize()
     print("traffic probe done", flush=True)
-
-
-def recorded_traffic():
-    """HBM bytes per k_pairs launch from the committed counter summary, or None
-    when the pair kernel's source changed since the counters were taken."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "k_pairs_sphere10242_hbm_traffic.md")
-    src = os.path.join(ROOT, "paper_1910_01011_amd", "csrc", "k_farfield.hip")
-    try:
-        fields = {}
-        for line in open(path):
-            if line.startswith("- ") and ": " in line:
-                k, v = line[2:].split(": ", 1)
-                fields[k.strip()] = v.strip().strip("`")
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if fields.get("k_farfield.hip sha256") != digest:
-            return None
-        return float(fields["HBM bytes per launch"])
-    except (OSError, KeyError, ValueError):
-        return None
 
 
 BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 MFMA

@@ -92,8 +92,21 @@ typedef struct {
     int64_t n_params;       /* rows of params (plane waves: n_fields) */
 } bem_incident;
 
+/* OSRC block-diagonal preconditioner P (paper eqs. OSRC_prec, OSRC_prec_blocks,
+ * OSRC_DtN_NtD_maps).  The paper solves the left-preconditioned system
+ * P A u = P b, whose GMRES stops on the preconditioned residual.
+ *   BEM_PRECOND_OSRC       plain forms: right preconditioning, GMRES on A P y = b,
+ *                          u = P y (the preconditioned vectors are stored, as in
+ *                          flexible GMRES); the Arnoldi residual, which stops it, is
+ *                          the unpreconditioned weak-form residual ||b - A u||/||b||
+ *   BEM_PRECOND_OSRC_LEFT  plain forms: the paper's left form, stopping on the
+ *                          preconditioned residual ||P(b - A u)||/||P b||
+ * The same P spectrum governs both (P A and A P are similar), so they take
+ * about as many iterations; only the first stops at the stated tolerance of
+ * the system itself. */
 #define BEM_PRECOND_NONE 0
 #define BEM_PRECOND_OSRC 1
+#define BEM_PRECOND_OSRC_LEFT 2
 /* Solver precision forms (compared at equal accuracy):
  *   BEM_PREC_FP32               plain GMRES on the FP32 operator (on-the-fly kernel, or the
  *                               dense FP32 matrix by GEMV with FP64 accumulation, one
@@ -111,10 +124,11 @@ typedef struct {
  *                               problem's mode (on-the-fly kernel or dense GEMV) with its
  *                               FP64 residual, inner GMRES on the hierarchical matrix to
  *                               inner_tol (any mode)
- * With BEM_PRECOND_OSRC, plain GMRES runs on the left-preconditioned system
- * (stopping on the preconditioned residual); the flexible forms precondition
- * their inner solves (inner GMRES on P A z = P v) and keep stopping on the
- * unpreconditioned FP64 residual.
+ * With BEM_PRECOND_OSRC, plain GMRES runs on the right-preconditioned system
+ * and stops on the unpreconditioned residual; with BEM_PRECOND_OSRC_LEFT on
+ * the left-preconditioned one (stopping on the preconditioned residual).  The
+ * flexible forms precondition their inner solves with either (inner GMRES on
+ * P A z = P v) and keep stopping on the unpreconditioned FP64 residual.
  * Progress: with the environment variable BEM_PROGRESS=k (k > 0) the solvers
  * print one line to stderr every k Arnoldi steps. */
 #define BEM_PREC_FP32 0
@@ -127,7 +141,7 @@ typedef struct {
     double tol;          /* relative residual target (paper: 1e-5) */
     int restart;         /* GMRES restart length (paper: 100) */
     int max_iter;        /* total iteration cap */
-    int precond;         /* BEM_PRECOND_NONE or BEM_PRECOND_OSRC */
+    int precond;         /* BEM_PRECOND_NONE, BEM_PRECOND_OSRC or BEM_PRECOND_OSRC_LEFT */
     int n_pade;          /* OSRC Pade terms */
     double r_eps;        /* OSRC damping length */
     double theta;        /* OSRC Pade branch-cut rotation */
@@ -146,7 +160,8 @@ typedef struct {
 
 typedef struct {
     int32_t iterations;    /* (outer) GMRES iterations */
-    int32_t converged;     /* the GMRES residual estimate reached tol */
+    int32_t converged;     /* the GMRES residual estimate reached tol: the unpreconditioned
+                              residual, except with BEM_PRECOND_OSRC_LEFT (preconditioned) */
     double rel_residual;   /* true ||b - A u|| / ||b|| of the returned u (weak form, FP32 operator) */
 } bem_solve_info;
 
@@ -215,7 +230,7 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
                          bem_complex *u, bem_solve_info *info);
 
 /* Out = P y for n_rhs residual vectors y [n_rhs][n_unknowns], P the OSRC
- * block-diagonal preconditioner of opts (precond = BEM_PRECOND_OSRC, n_pade,
+ * block-diagonal preconditioner of opts (precond = either OSRC form, n_pade,
  * r_eps, theta; paper eqs. OSRC_prec, OSRC_prec_blocks, OSRC_DtN_NtD_maps):
  * per domain, Lambda_DtN M^-1 applied to the Dirichlet-equation rows and
  * Lambda_NtD M^-1 to the Neumann-equation rows, k = k0, with the paper's

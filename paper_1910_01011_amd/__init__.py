@@ -39,7 +39,7 @@ BEM_APPLY_DEFAULT, BEM_APPLY_GEMV, BEM_APPLY_MFMA_FP32, BEM_APPLY_MFMA_SPLIT_BF1
 BEM_APPLY_MFMA_SPLIT_BF16_W4, BEM_APPLY_MFMA_SPLIT_BF16_W8 = 4, 5
 BEM_APPLY_HMATRIX = 6
 BEM_PLANE_WAVE, BEM_POINT_SOURCES, BEM_PISTON_ARRAY = 0, 1, 2
-BEM_PRECOND_NONE, BEM_PRECOND_OSRC = 0, 1
+BEM_PRECOND_NONE, BEM_PRECOND_OSRC, BEM_PRECOND_OSRC_LEFT = 0, 1, 2
 BEM_PREC_FP32, BEM_PREC_SPLIT_BF16_FGMRES, BEM_PREC_FP32_MFMA_FGMRES = 0, 1, 2
 BEM_PREC_HMATRIX, BEM_PREC_HMATRIX_FGMRES = 3, 4
 

@@ -685,9 +685,9 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
     if (!p || !b || !u || !info || n_rhs < 1) return fail(BEM_ERR_INVALID_ARG, "bem_solve: bad arguments");
     bem_solve_opts o = opts ? *opts : default_solve_opts();
     if (!(o.tol > 0) || o.restart < 1 || o.max_iter < 1) return fail(BEM_ERR_INVALID_ARG, "bem_solve: bad options");
-    if (o.precond != BEM_PRECOND_NONE && o.precond != BEM_PRECOND_OSRC)
+    if (o.precond != BEM_PRECOND_NONE && o.precond != BEM_PRECOND_OSRC && o.precond != BEM_PRECOND_OSRC_LEFT)
         return fail(BEM_ERR_INVALID_ARG, "bem_solve: unknown preconditioner");
-    if (o.precond == BEM_PRECOND_OSRC) {
+    if (o.precond != BEM_PRECOND_NONE) {
         if (!(o.r_eps > 0) || !std::isfinite(o.r_eps) || o.n_pade < 0 || o.n_pade > 64 || !std::isfinite(o.theta))
             return fail(BEM_ERR_INVALID_ARG, "bem_solve: OSRC needs r_eps > 0, 0 <= n_pade <= 64, finite theta");
     }
@@ -744,9 +744,18 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
             }
         };
         if (plain && o.precond == BEM_PRECOND_OSRC) {
-            // left preconditioning: GMRES on P A u = P b (stops on the
-            // preconditioned residual); the unpreconditioned weak-form residual
-            // is reported afterwards
+            // right preconditioning: GMRES on A P y = b, u = P y, with the
+            // preconditioned vectors kept (flexible form, so an inexact inner
+            // solve is harmless); the Arnoldi residual is that of the
+            // unpreconditioned weak-form system, which is what stops it
+            const bem::OsrcParams op{o.n_pade, o.r_eps, o.theta, osrc_inner_tol(o), 3000};
+            const bem::ApplyFn prec = [&P, op](const double2 *V, double2 *Z, int R) { bem::osrc_apply(P, op, V, Z, R); };
+            bem::gmres_batch(P, P.N, n_rhs, db, du, bem::KrylovOpts{o.tol, o.restart, o.max_iter, progress, "osrc gmres"},
+                             fp32_apply, &prec, info);
+        } else if (plain && o.precond == BEM_PRECOND_OSRC_LEFT) {
+            // left preconditioning (the paper's form): GMRES on P A u = P b,
+            // stopping on the preconditioned residual; the unpreconditioned
+            // weak-form residual is reported afterwards
             const bem::OsrcParams op{o.n_pade, o.r_eps, o.theta, osrc_inner_tol(o), 3000};
             double2 *PB = nullptr, *tmp = nullptr;
             dev_alloc(&PB, n);
@@ -793,7 +802,7 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
                 double2 *a = nullptr, *b = nullptr;
                 ~G2() { (void)hipFree(a); (void)hipFree(b); }
             } g2;
-            if (o.precond == BEM_PRECOND_OSRC) {
+            if (o.precond != BEM_PRECOND_NONE) {
                 // inner GMRES on the left-preconditioned system P A z = P v
                 const bem::OsrcParams op{o.n_pade, o.r_eps, o.theta, osrc_inner_tol(o), 3000};
                 dev_alloc(&PV, n);
@@ -836,7 +845,8 @@ bem_status bem_apply_preconditioner(bem_problem *p, const bem_solve_opts *opts, 
                                     bem_complex *out, int32_t n_rhs)
 {
     if (!p || !opts || !y || !out || n_rhs < 0) return fail(BEM_ERR_INVALID_ARG, "bem_apply_preconditioner: bad arguments");
-    if (opts->precond != BEM_PRECOND_OSRC) return fail(BEM_ERR_INVALID_ARG, "bem_apply_preconditioner: precond must be OSRC");
+    if (opts->precond != BEM_PRECOND_OSRC && opts->precond != BEM_PRECOND_OSRC_LEFT)
+        return fail(BEM_ERR_INVALID_ARG, "bem_apply_preconditioner: precond must be OSRC");
     if (!(opts->r_eps > 0) || opts->n_pade < 0 || opts->n_pade > 64 || !std::isfinite(opts->theta))
         return fail(BEM_ERR_INVALID_ARG, "bem_apply_preconditioner: need r_eps > 0, 0 <= n_pade <= 64");
     if (!(opts->osrc_tol >= 0 && opts->osrc_tol < 1))

@@ -43,6 +43,11 @@ def test_osrc_apply_matches_oracle(case):
 
 
 def test_osrc_preconditioned_solve():
+    """Both OSRC forms against the oracle's LU solution.  The right form stops on
+    the unpreconditioned residual, so its true residual meets the tolerance
+    (up to the FP32 operator's rounding in the recursive estimate); the left
+    form (the paper's P A u = P b) stops on the preconditioned residual, which
+    here sits below the true one."""
     prob = configs.config1()
     A = oracle.pmchwt_matrix(prob)
     b = oracle.rhs(prob, *oracle.plane_wave(prob.k0))
@@ -50,9 +55,16 @@ def test_osrc_preconditioned_solve():
     bem = _bem()
     P = bem.Problem.from_config(prob)
     u0, i0 = P.solve(b, bem.solve_options(tol=1e-8, restart=100, max_iter=400))
-    u1, i1 = P.solve(b, bem.solve_options(tol=1e-8, restart=100, max_iter=400, precond=bem.BEM_PRECOND_OSRC,
-                                          n_pade=4, r_eps=0.1, theta=np.pi / 3))
-    e1 = _relerr(u1, u_ref)
-    print(f"plain {i0}, OSRC {i1}, OSRC error vs LU {e1:.2e}")
-    assert i1[0]["converged"] and i1[0]["iterations"] < i0[0]["iterations"]
-    assert e1 <= 1e-5
+    for pc in (bem.BEM_PRECOND_OSRC, bem.BEM_PRECOND_OSRC_LEFT):
+        u1, i1 = P.solve(b, bem.solve_options(tol=1e-8, restart=100, max_iter=400, precond=pc,
+                                              n_pade=4, r_eps=0.1, theta=np.pi / 3))
+        e1 = _relerr(u1, u_ref)
+        print(f"plain {i0}, OSRC form {pc}: {i1}, error vs LU {e1:.2e}")
+        assert i1[0]["converged"] and i1[0]["iterations"] < i0[0]["iterations"]
+        assert e1 <= 1e-5
+    for tol in (1e-5, 1e-6):
+        u1, i1 = P.solve(b, bem.solve_options(tol=tol, restart=100, max_iter=400, precond=bem.BEM_PRECOND_OSRC,
+                                              n_pade=4, r_eps=0.1, theta=np.pi / 3))
+        res = _relerr(A @ np.ravel(u1), b)
+        print(f"right OSRC at tol {tol:g}: {i1[0]}, oracle residual {res:.2e}")
+        assert i1[0]["converged"] and i1[0]["rel_residual"] <= 1.1 * tol and res <= 2 * tol
