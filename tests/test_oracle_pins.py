@@ -567,3 +567,26 @@ def test_density_ratio_pin_rejects_an_inverted_scaling():
     assert np.linalg.norm(sl - dl - ref) / np.linalg.norm(ref) > 0.2
     p_ok, _ = oracle.field(prob, u, pts)
     assert np.linalg.norm(p_ok - ref) / np.linalg.norm(ref) < 0.02
+
+
+def test_config2_golden_lu_solution_matches_series():
+    """The stored FP64 LU solution of the 10,242-vertex sphere (k0 = 10, k1 =
+    10.5, density ratio 1.05; tests/golden/make_config2_lu.py, oracle only)
+    against the penetrable-sphere series: mass-norm trace errors below 1.5 %
+    (measured 0.66 % and 0.49 %), so the stored values the GPU solves are
+    compared with are pinned to the physics, not only to the oracle."""
+    import os
+    prob = configs.config2()
+    d = prob.domains[0]
+    nv = d.n_vertices
+    u = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config2_lu_planewave_z.npy"))
+    assert u.shape == (prob.n_unknowns,)
+    gD, gN = series.sphere_traces(d.vertices, 1.0, 10.0, 10.5, 1.0, 1.05)
+    M = oracle.mass_matrix(d.vertices, d.triangles)
+
+    def mnorm(x):
+        return np.sqrt(np.real(np.conj(x) @ M @ x))
+
+    eD = mnorm(u[:nv] - gD) / mnorm(gD)
+    eN = mnorm(u[nv:] - gN) / mnorm(gN)
+    assert eD < 0.015 and eN < 0.015, (eD, eN)
