@@ -625,13 +625,14 @@ def serving_section(bem, torch, n_requests):
 
 def paper_sphere_section(bem, torch):
     """The paper's single-sphere model problem: 1 cm sphere at 1 MHz in water,
-    fat or the table's rib material (attenuating media), plane wave, OSRC
+    fat, the table's rib material or the cortical-like bone of impedance ratio
+    5.2 (attenuating media), plane wave, OSRC
     (N_Pade = 4, R_eps = 5e-4 m) GMRES(100) to 1e-5; iterations and time per
     iteration against mesh density (the field error against the series
     solution is checked in the GPU tests)."""
     from bem_inputs import configs
     out = {}
-    for material in ("fat", "ribs"):
+    for material in ("fat", "ribs", "cortical"):
         for epw in (4, 6, 8, 10):
             prob = configs.paper_sphere(material, epw)
             (P, t_setup) = _timed(torch, lambda: bem.Problem.from_config(prob, device=True))

@@ -293,6 +293,33 @@ bem_status bem_hmatrix_build(bem_problem *p, double eps, int32_t leaf_vertices, 
 bem_status bem_hmatrix_plan(const bem_domain *domains, int32_t n_domains, int32_t leaf_vertices, double eta,
                             int64_t *out4);
 
+/* Continuous batching of solves (serving).  Requests are solved side by side,
+ * each by its own host thread on its own stream (right-hand sides, Krylov
+ * vectors, preconditioner and results stay on that stream).  A problem
+ * attached to a batch hands every operator apply of its solves (bem_solve,
+ * bem_solve_rhs) to the batch's dispatcher thread, which gathers the applies
+ * submitted by the requests in flight (until every attached problem inside a
+ * solve has submitted one, or for at most 0.3 ms) and launches them together
+ * on the batch's own stream: the pair kernels of all on-the-fly problems of
+ * one kernel variant as one grouped launch over their concatenated work lists
+ * (up to 16 problems), then each problem's gathers, reductions, projections,
+ * GEMVs, GEMMs or hierarchical-matrix products back to back.  Each problem's
+ * work items, launch shapes and summation orders are its own, so a result is
+ * bitwise the same whatever the mix.  Events order the batch's stream after
+ * the request's input and the request's stream after the result.
+ * bem_batch_create: a batch on `device` (its stream has the default priority).
+ * bem_batch_attach: route p's solves through b (NULL: launch them directly
+ * again); p and b on the same device; not while p is inside a solve.
+ * bem_batch_stats: out6 = {dispatches, applies, grouped pair launches, of
+ * them with several problems, most problems in one launch, pair work items}.
+ * bem_batch_destroy: stops the dispatcher; destroy or detach every attached
+ * problem first.  Errors: BEM_ERR_INVALID_ARG, BEM_ERR_DEVICE. */
+typedef struct bem_batch bem_batch;
+bem_status bem_batch_create(int device, bem_batch **out);
+bem_status bem_batch_attach(bem_problem *p, bem_batch *b);
+bem_status bem_batch_stats(bem_batch *b, int64_t *out6);
+void bem_batch_destroy(bem_batch *b);
+
 int64_t bem_num_unknowns(const bem_problem *p);
 
 /* Device bytes a problem would hold (admission control). */

@@ -27,7 +27,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "_bem_oracle.so")
+# BEM_ORACLE_LIB selects another build of bem_oracle.c (the sanitizer build)
+_LIB_PATH = os.path.join(_HERE, os.environ.get("BEM_ORACLE_LIB", "_bem_oracle.so"))
 _lib = None
 
 FAR, VERTEX, EDGE, COINCIDENT = 0, 1, 2, 3

@@ -7,11 +7,20 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def build(verbose: bool = False) -> str:
+SANITIZED = "_bem_oracle_san.so"
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """Compile the oracle; with ``sanitize`` a second library built with
+    AddressSanitizer and UndefinedBehaviorSanitizer (host code only), loaded
+    when BEM_ORACLE_LIB names it (run under gcc's libasan, see
+    tests/run_host_sanitizers.py)."""
     src = os.path.join(HERE, "bem_oracle.c")
-    out = os.path.join(HERE, "_bem_oracle.so")
+    out = os.path.join(HERE, SANITIZED if sanitize else "_bem_oracle.so")
     tmp = out + ".tmp"
-    cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+    opt = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined"] if sanitize else ["-O2"]
+    cmd = ["gcc", *opt, "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
            "-o", tmp, src, "-lm"]
     if verbose:
         print(" ".join(cmd))

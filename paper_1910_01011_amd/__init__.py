@@ -22,7 +22,9 @@ import numpy as np
 import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbem_mi355x.so")
+# BEM_LIBRARY selects another build of the same library in this directory (the
+# host-sanitizer build libbem_mi355x_san.so)
+LIB_PATH = os.path.join(_HERE, os.path.basename(os.environ.get("BEM_LIBRARY", "libbem_mi355x.so")))
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"paper_1910_01011_amd: HIP library not built ({LIB_PATH}); "
@@ -99,6 +101,11 @@ _L.bem_solve_rhs.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.POINTER(bem_solve_
                              ctypes.POINTER(bem_solve_info)]
 _L.bem_apply_preconditioner.argtypes = [_vp, ctypes.POINTER(bem_solve_opts), _vp, _vp, ctypes.c_int32]
 _L.bem_evaluate_field.argtypes = [_vp, _vp, ctypes.POINTER(bem_incident), _vp, ctypes.c_int64, _vp, _vp]
+_L.bem_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(_vp)]
+_L.bem_batch_attach.argtypes = [_vp, _vp]
+_L.bem_batch_stats.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
+_L.bem_batch_destroy.argtypes = [_vp]
+_L.bem_batch_destroy.restype = None
 _L.bem_num_unknowns.argtypes = [_vp]
 _L.bem_num_unknowns.restype = ctypes.c_int64
 _L.bem_footprint_bytes.argtypes = [ctypes.POINTER(bem_domain), ctypes.c_int32, ctypes.POINTER(bem_assemble_opts),
@@ -111,13 +118,15 @@ _L.bem_last_error.restype = ctypes.c_char_p
 for _f in ("bem_assemble", "bem_apply", "bem_apply_parts", "bem_apply_with", "bem_apply_single_layer",
            "bem_hmatrix_build", "bem_hmatrix_plan", "bem_rhs", "bem_solve", "bem_solve_rhs",
            "bem_apply_preconditioner", "bem_pair_launch_shape",
-           "bem_evaluate_field", "bem_footprint_bytes", "bem_last_timings"):
+           "bem_evaluate_field", "bem_footprint_bytes", "bem_last_timings", "bem_batch_create", "bem_batch_attach",
+           "bem_batch_stats"):
     getattr(_L, _f).restype = ctypes.c_int
 
 EXPORTED = ["bem_assemble", "bem_apply", "bem_apply_parts", "bem_apply_with", "bem_apply_single_layer",
             "bem_hmatrix_build", "bem_hmatrix_plan", "bem_rhs", "bem_solve", "bem_solve_rhs",
             "bem_apply_preconditioner", "bem_pair_launch_shape",
             "bem_evaluate_field", "bem_num_unknowns", "bem_footprint_bytes", "bem_last_timings",
+            "bem_batch_create", "bem_batch_attach", "bem_batch_stats", "bem_batch_destroy",
             "bem_destroy", "bem_last_error"]
 
 
@@ -213,6 +222,36 @@ def hmatrix_plan(domains, leaf_vertices=64, eta=1.0):
     _check(_L.bem_hmatrix_plan(arr, len(domains), int(leaf_vertices), float(eta), out))
     return {"n_blocks": int(out[0]), "n_admissible": int(out[1]), "n_touching": int(out[2]),
             "n_touching_admissible": int(out[3])}
+
+
+class Batch:
+    """Continuous batching of the operator applies of concurrent solves
+    (``bem_batch``): attach problems, then solve them from several threads."""
+
+    def __init__(self, gpu=0):
+        self._h = _vp()
+        _check(_L.bem_batch_create(int(gpu), ctypes.byref(self._h)))
+
+    def attach(self, problem):
+        _check(_L.bem_batch_attach(problem._h, self._h))
+
+    def stats(self):
+        out = (ctypes.c_int64 * 6)()
+        _check(_L.bem_batch_stats(self._h, out))
+        keys = ("dispatches", "applies", "pair_launches", "multi_problem_launches", "max_problems_per_launch",
+                "pair_work_items")
+        return dict(zip(keys, (int(v) for v in out)))
+
+    def close(self):
+        if self._h:
+            _L.bem_batch_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Problem:

@@ -36,7 +36,7 @@ bem_status guarded(F &&f)
 template <typename T>
 void dev_alloc(T **p, size_t n)
 {
-    BEM_HIP(hipMalloc(reinterpret_cast<void **>(p), std::max<size_t>(1, n) * sizeof(T)));
+    bem::dmalloc(reinterpret_cast<void **>(p), std::max<size_t>(1, n) * sizeof(T));
 }
 
 template <typename T>
@@ -51,16 +51,21 @@ T *dev_copy(const std::vector<T> &h, hipStream_t s)
 void free_problem(bem_problem *p)
 {
     if (!p) return;
+    (void)hipSetDevice(p->device);
+    bem::AllocScope alloc_scope(p->stream);
     void *ptrs[] = {p->d_verts, p->d_tris, p->d_rowD, p->d_rowN, p->d_area, p->d_normal, p->d_curl, p->d_pts,
                     p->d_tnrm, p->d_v2t_ptr, p->d_v2t, p->d_pass, p->d_work, p->d_trial, p->d_part, p->d_pot,
                     p->d_cptr, p->d_ccol, p->d_cval, p->d_x, p->d_y, p->d_A, p->d_Ahi, p->d_Alo,
                     p->d_gx, p->d_gc, p->d_aptr, p->d_acol, p->d_Mv, p->d_Sv, p->d_adiag, p->d_drange,
-                    p->d_sl_cptr, p->d_sl_ccol, p->d_sl_cval};
+                    p->d_sl_cptr, p->d_sl_ccol, p->d_sl_cval, p->d_cg_chunks};
     for (void *q : ptrs)
-        if (q) (void)hipFree(q);
+        if (q) bem::dfree(q);
     if (p->hm) bem::hmatrix_free(p->hm);
+    if (p->batch) bem::batch_detach(*p);
     for (auto &e : p->ev)
         if (e) (void)hipEventDestroy(e);
+    if (p->batch_ready) (void)hipEventDestroy(p->batch_ready);
+    if (p->batch_done) (void)hipEventDestroy(p->batch_done);
     delete p;
 }
 
@@ -162,7 +167,7 @@ void build_work(bem_problem &p)
 {
     if (p.d_work) {
         BEM_HIP(hipStreamSynchronize(p.stream));
-        (void)hipFree(p.d_work);
+        bem::dfree(p.d_work);
         p.d_work = nullptr;
     }
     // work items: consecutive workgroups take consecutive splits, so that the
@@ -182,8 +187,8 @@ void build_work(bem_problem &p)
 void ensure_scratch(bem_problem &p, int64_t n_rhs)
 {
     if (p.scratch_rhs >= n_rhs) return;
-    if (p.d_x) (void)hipFree(p.d_x);
-    if (p.d_y) (void)hipFree(p.d_y);
+    if (p.d_x) bem::dfree(p.d_x);
+    if (p.d_y) bem::dfree(p.d_y);
     p.d_x = p.d_y = nullptr;
     p.scratch_rhs = 0;
     dev_alloc(&p.d_x, size_t(n_rhs * p.N));
@@ -233,10 +238,10 @@ void apply_dense_one(bem_problem &p, const double2 *x, double2 *y, bool record)
 void grow(void **ptr, size_t &have, size_t need)
 {
     if (have >= need) return;
-    if (*ptr) (void)hipFree(*ptr);
+    if (*ptr) bem::dfree(*ptr);
     *ptr = nullptr;
     have = 0;
-    BEM_HIP(hipMalloc(ptr, need));
+    bem::dmalloc(ptr, need);
     have = need;
 }
 
@@ -268,17 +273,17 @@ void apply_dense_multi(bem_problem &p, const double2 *X, double2 *Y, int n_rhs, 
     }
     const bem::GemmPlan g = bem::gemm_plan(p, n_rhs, bf16, code % 100, code / 100);
     if (p.gx_bytes < g.bytes_x) {
-        if (p.d_gx) (void)hipFree(p.d_gx);
+        if (p.d_gx) bem::dfree(p.d_gx);
         p.d_gx = nullptr;
         p.gx_bytes = 0;
-        BEM_HIP(hipMalloc(&p.d_gx, g.bytes_x));
+        bem::dmalloc(&p.d_gx, g.bytes_x);
         p.gx_bytes = g.bytes_x;
     }
     if (p.gc_bytes < g.bytes_c) {
-        if (p.d_gc) (void)hipFree(p.d_gc);
+        if (p.d_gc) bem::dfree(p.d_gc);
         p.d_gc = nullptr;
         p.gc_bytes = 0;
-        BEM_HIP(hipMalloc(&p.d_gc, g.bytes_c));
+        bem::dmalloc(reinterpret_cast<void **>(&p.d_gc), g.bytes_c);
         p.gc_bytes = g.bytes_c;
     }
     BEM_HIP(hipEventRecord(p.ev[0], p.stream));
@@ -346,8 +351,8 @@ std::vector<double> residual_norms(bem_problem &p, const double2 *B, double2 *AX
     bem::bdot(p.stream, B, 0, 1, B, n, R, part, nblk, h);
     BEM_HIP(hipMemcpyAsync(bb.data(), h, R * sizeof(double2), hipMemcpyDeviceToHost, p.stream));
     BEM_HIP(hipStreamSynchronize(p.stream));
-    (void)hipFree(part);
-    (void)hipFree(h);
+    bem::dfree(part);
+    bem::dfree(h);
     std::vector<double> r(R);
     for (int i = 0; i < R; ++i) r[i] = bb[i].x > 0 ? std::sqrt(std::max(0.0, out[i].x) / bb[i].x) : 0.0;
     return r;
@@ -357,6 +362,28 @@ std::vector<double> residual_norms(bem_problem &p, const double2 *B, double2 *AX
 
 namespace bem {
 void set_error(const std::string &msg) { g_last_error = msg; }
+
+void apply_dense_multi_dispatch(bem_problem &p, const double2 *X, double2 *Y, int R, bool bf16)
+{
+    apply_dense_multi(p, X, Y, R, bf16, false);
+}
+
+hipStream_t &alloc_stream()
+{
+    thread_local hipStream_t s = nullptr;
+    return s;
+}
+
+void dmalloc(void **p, size_t bytes)
+{
+    *p = nullptr;
+    BEM_HIP(hipMallocAsync(p, std::max<size_t>(1, bytes), alloc_stream()));
+}
+
+void dfree(void *p)
+{
+    if (p) (void)hipFreeAsync(p, alloc_stream());
+}
 }  // namespace bem
 
 extern "C" {
@@ -410,6 +437,7 @@ bem_status bem_assemble(const bem_domain *domains, int32_t n_domains, bem_comple
                 p->h_rowN[d.v_off + i] = int32_t(2 * d.v_off + d.nv + i);
             }
         BEM_HIP(hipSetDevice(p->device));
+        bem::AllocScope alloc_scope(p->stream);
         for (auto &e : p->ev) BEM_HIP(hipEventCreate(&e));
         p->d_verts = dev_copy(p->h_verts, p->stream);
         p->d_tris = dev_copy(p->h_tris, p->stream);
@@ -447,7 +475,7 @@ bem_status bem_assemble(const bem_domain *domains, int32_t n_domains, bem_comple
             dev_alloc(&p->d_part, size_t(2) * max_split * 10 * p->M);
             bem::tune_pairs(*p, &build_work, max_split);
             BEM_HIP(hipStreamSynchronize(p->stream));
-            (void)hipFree(p->d_part);
+            bem::dfree(p->d_part);
             p->d_part = nullptr;
         }
         dev_alloc(&p->d_part, size_t(2) * p->n_split * 10 * p->M);
@@ -487,6 +515,7 @@ bem_status bem_apply_parts(bem_problem *p, const bem_complex *x, bem_complex *y,
     if (n_rhs == 0) return BEM_OK;
     return guarded([&]() -> bem_status {
         BEM_HIP(hipSetDevice(p->device));
+        bem::AllocScope alloc_scope(p->stream);
         const size_t bytes = size_t(n_rhs) * p->N * sizeof(double2);
         if (p->flags & BEM_DEVICE_PTRS) {
             apply_device(*p, reinterpret_cast<const double2 *>(x), reinterpret_cast<double2 *>(y), n_rhs, parts);
@@ -509,6 +538,7 @@ bem_status bem_apply_single_layer(bem_problem *p, const bem_complex *x, bem_comp
     if (n_rhs == 0) return BEM_OK;
     return guarded([&]() -> bem_status {
         BEM_HIP(hipSetDevice(p->device));
+        bem::AllocScope alloc_scope(p->stream);
         if (!p->sl_ready) {
             // V correction of the exterior pass: its touching pairs, V block only
             std::vector<bem::SingularItem> items, ext;
@@ -556,6 +586,7 @@ bem_status bem_apply_with(bem_problem *p, const bem_complex *x, bem_complex *y, 
         if (n_rhs == 0) return BEM_OK;
         return guarded([&]() -> bem_status {
             BEM_HIP(hipSetDevice(p->device));
+        bem::AllocScope alloc_scope(p->stream);
             const size_t bytes = size_t(n_rhs) * p->N * sizeof(double2);
             if (p->flags & BEM_DEVICE_PTRS) {
                 bem::hmatrix_apply(*p, reinterpret_cast<const double2 *>(x), reinterpret_cast<double2 *>(y), n_rhs, true);
@@ -576,6 +607,7 @@ bem_status bem_apply_with(bem_problem *p, const bem_complex *x, bem_complex *y, 
     if (n_rhs == 0) return BEM_OK;
     return guarded([&]() -> bem_status {
         BEM_HIP(hipSetDevice(p->device));
+        bem::AllocScope alloc_scope(p->stream);
         const size_t bytes = size_t(n_rhs) * p->N * sizeof(double2);
         const double2 *dx = reinterpret_cast<const double2 *>(x);
         double2 *dy = reinterpret_cast<double2 *>(y);
@@ -607,6 +639,7 @@ bem_status bem_hmatrix_build(bem_problem *p, double eps, int32_t leaf_vertices, 
         return fail(BEM_ERR_INVALID_ARG, "bem_hmatrix_build: need 0 < eps <= 0.1, 8 <= leaf_vertices <= 4096, eta > 0");
     return guarded([&]() -> bem_status {
         BEM_HIP(hipSetDevice(p->device));
+        bem::AllocScope alloc_scope(p->stream);
         if (p->hm) {
             bem::hmatrix_free(p->hm);
             p->hm = nullptr;
@@ -665,6 +698,7 @@ bem_status bem_rhs(bem_problem *p, const bem_incident *inc, bem_complex *b)
         return fail(BEM_ERR_INVALID_ARG, "bem_rhs: unknown incident kind");
     return guarded([&]() -> bem_status {
         BEM_HIP(hipSetDevice(p->device));
+        bem::AllocScope alloc_scope(p->stream);
         const size_t n = size_t(inc->n_fields) * p->N;
         if (p->flags & BEM_DEVICE_PTRS) {
             bem::launch_rhs(*p, *inc, reinterpret_cast<double2 *>(b));
@@ -673,7 +707,7 @@ bem_status bem_rhs(bem_problem *p, const bem_incident *inc, bem_complex *b)
             dev_alloc(&d_b, n);
             bem::launch_rhs(*p, *inc, d_b);
             BEM_HIP(hipMemcpy(b, d_b, n * sizeof(double2), hipMemcpyDeviceToHost));
-            (void)hipFree(d_b);
+            bem::dfree(d_b);
         }
         return BEM_OK;
     });
@@ -712,6 +746,7 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
         return fail(BEM_ERR_INVALID_ARG, "bem_solve: osrc_tol must be in [0, 1) (0: 1e-10)");
     return guarded([&]() -> bem_status {
         BEM_HIP(hipSetDevice(p->device));
+        bem::AllocScope alloc_scope(p->stream);
         const size_t n = size_t(n_rhs) * p->N;
         const double2 *db;
         double2 *du;
@@ -734,8 +769,18 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
         // FP32-accurate operator: on-the-fly kernel, or the FP32 dense matrix
         // (GEMV with FP64 accumulation for one vector, FP32 MFMA GEMM for a block)
         const bool hmat = o.precision == BEM_PREC_HMATRIX;
+        // a problem attached to a batch hands its operator applies to the
+        // batch (continuous batching across concurrent solves)
+        struct InSolve {
+            bem_batch *b;
+            explicit InSolve(bem_batch *x) : b(x) { if (b) bem::batch_enter(*b); }
+            ~InSolve() { if (b) bem::batch_leave(*b); }
+        } in_solve(P.batch);
         const bem::ApplyFn fp32_apply = [&P, hmat](const double2 *X, double2 *Y, int R) {
-            if (hmat) {
+            if (P.batch) {
+                bem::batch_apply(P, hmat ? bem::BATCH_HMATRIX : P.mode == BEM_OTF ? bem::BATCH_OTF : bem::BATCH_GEMV, X,
+                                 Y, R);
+            } else if (hmat) {
                 bem::hmatrix_apply(P, X, Y, R, false);
             } else if (P.mode == BEM_OTF) {
                 apply_device(P, X, Y, R, 3, false);
@@ -762,7 +807,7 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
             dev_alloc(&tmp, n);
             struct G2 {
                 double2 *a, *b;
-                ~G2() { (void)hipFree(a); (void)hipFree(b); }
+                ~G2() { bem::dfree(a); bem::dfree(b); }
             } g2{PB, tmp};
             bem::osrc_apply(P, op, db, PB, n_rhs);
             const bem::ApplyFn prec_apply = [&P, &fp32_apply, op, tmp](const double2 *X, double2 *Y, int R) {
@@ -788,11 +833,18 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
                     fp32_apply(X, Y, R);
                     return;
                 }
+                if (P.batch) {
+                    bem::batch_apply(P, bem::BATCH_GEMV, X, Y, R);
+                    return;
+                }
                 for (int r = 0; r < R; ++r) apply_dense_one(P, X + int64_t(r) * P.N, Y + int64_t(r) * P.N, true);
             };
             const bool bf16 = o.precision == BEM_PREC_SPLIT_BF16_FGMRES;
             const bem::ApplyFn inner_op = [&P, bf16, hinner](const double2 *X, double2 *Y, int R) {
-                if (hinner) bem::hmatrix_apply(P, X, Y, R, false);
+                if (P.batch)
+                    bem::batch_apply(P, hinner ? bem::BATCH_HMATRIX : bf16 ? bem::BATCH_GEMM_BF16 : bem::BATCH_GEMM_F32,
+                                     X, Y, R);
+                else if (hinner) bem::hmatrix_apply(P, X, Y, R, false);
                 else apply_dense_multi(P, X, Y, R, bf16, false);
             };
             const bem::KrylovOpts io{o.inner_tol, o.inner_restart, o.inner_max_iter, progress, "inner gmres"};
@@ -800,7 +852,7 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
             double2 *PV = nullptr, *tmp = nullptr;
             struct G2 {
                 double2 *a = nullptr, *b = nullptr;
-                ~G2() { (void)hipFree(a); (void)hipFree(b); }
+                ~G2() { bem::dfree(a); bem::dfree(b); }
             } g2;
             if (o.precond != BEM_PRECOND_NONE) {
                 // inner GMRES on the left-preconditioned system P A z = P v
@@ -833,8 +885,8 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
         if (!(p->flags & BEM_DEVICE_PTRS)) {
             BEM_HIP(hipMemcpyAsync(u, du, n * sizeof(double2), hipMemcpyDeviceToHost, p->stream));
             BEM_HIP(hipStreamSynchronize(p->stream));
-            (void)hipFree(tb);
-            (void)hipFree(tu);
+            bem::dfree(tb);
+            bem::dfree(tu);
         }
         if (!all) return fail(BEM_WARN_NOT_CONVERGED, "bem_solve: GMRES reached max_iter for some right-hand side");
         return BEM_OK;
@@ -854,6 +906,7 @@ bem_status bem_apply_preconditioner(bem_problem *p, const bem_solve_opts *opts, 
     if (n_rhs == 0) return BEM_OK;
     return guarded([&]() -> bem_status {
         BEM_HIP(hipSetDevice(p->device));
+        bem::AllocScope alloc_scope(p->stream);
         const bem::OsrcParams op{opts->n_pade, opts->r_eps, opts->theta, opts->osrc_tol > 0 ? opts->osrc_tol : 1e-10, 3000};
         const size_t n = size_t(n_rhs) * p->N;
         if (p->flags & BEM_DEVICE_PTRS) {
@@ -865,8 +918,8 @@ bem_status bem_apply_preconditioner(bem_problem *p, const bem_solve_opts *opts, 
             BEM_HIP(hipMemcpy(dy, y, n * sizeof(double2), hipMemcpyHostToDevice));
             bem::osrc_apply(*p, op, dy, dout, n_rhs);
             BEM_HIP(hipMemcpy(out, dout, n * sizeof(double2), hipMemcpyDeviceToHost));
-            (void)hipFree(dy);
-            (void)hipFree(dout);
+            bem::dfree(dy);
+            bem::dfree(dout);
         }
         return BEM_OK;
     });
@@ -878,6 +931,7 @@ bem_status bem_solve(bem_problem *p, const bem_incident *inc, const bem_solve_op
     if (!p || !inc || !u || !info || inc->n_fields < 1) return fail(BEM_ERR_INVALID_ARG, "bem_solve: bad arguments");
     return guarded([&]() -> bem_status {
         BEM_HIP(hipSetDevice(p->device));
+        bem::AllocScope alloc_scope(p->stream);
         const size_t n = size_t(inc->n_fields) * p->N;
         double2 *d_b = nullptr;
         dev_alloc(&d_b, n);
@@ -891,7 +945,7 @@ bem_status bem_solve(bem_problem *p, const bem_incident *inc, const bem_solve_op
             BEM_HIP(hipMemcpy(hb.data(), d_b, n * sizeof(double2), hipMemcpyDeviceToHost));
             st = bem_solve_rhs(p, hb.data(), inc->n_fields, opts, u, info);
         }
-        (void)hipFree(d_b);
+        bem::dfree(d_b);
         return st;
     });
 }
@@ -904,6 +958,7 @@ bem_status bem_evaluate_field(bem_problem *p, const bem_complex *u, const bem_in
     const int n_fields = inc ? inc->n_fields : 1;
     return guarded([&]() -> bem_status {
         BEM_HIP(hipSetDevice(p->device));
+        bem::AllocScope alloc_scope(p->stream);
         if (p->flags & BEM_DEVICE_PTRS) {
             bem::launch_field(*p, reinterpret_cast<const double2 *>(u), inc, n_fields, points, n_points,
                               reinterpret_cast<double2 *>(field), region);
@@ -920,7 +975,7 @@ bem_status bem_evaluate_field(bem_problem *p, const bem_complex *u, const bem_in
             bem::launch_field(*p, du, inc, n_fields, dp, n_points, df, dr);
             BEM_HIP(hipMemcpy(field, df, size_t(n_fields) * n_points * sizeof(double2), hipMemcpyDeviceToHost));
             BEM_HIP(hipMemcpy(region, dr, size_t(n_points) * sizeof(int32_t), hipMemcpyDeviceToHost));
-            (void)hipFree(du); (void)hipFree(df); (void)hipFree(dp); (void)hipFree(dr);
+            bem::dfree(du); bem::dfree(df); bem::dfree(dp); bem::dfree(dr);
         }
         return BEM_OK;
     });

@@ -25,6 +25,27 @@ struct Error {
 
 void set_error(const std::string &msg);
 
+// ---------------------------------------------------------------------------
+// device memory
+// ---------------------------------------------------------------------------
+
+// The library's device memory is stream-ordered (hipMallocAsync /
+// hipFreeAsync) on the stream of the work at hand, so that one problem's
+// allocations and frees never wait for the whole device, and requests served
+// side by side on their own streams do not stall each other.  Each entry
+// point sets the calling thread's allocation stream (AllocScope) to its
+// problem's stream.
+hipStream_t &alloc_stream();
+void dmalloc(void **p, size_t bytes);
+void dfree(void *p);
+struct AllocScope {
+    hipStream_t saved;
+    explicit AllocScope(hipStream_t s) : saved(alloc_stream()) { alloc_stream() = s; }
+    ~AllocScope() { alloc_stream() = saved; }
+    AllocScope(const AllocScope &) = delete;
+    AllocScope &operator=(const AllocScope &) = delete;
+};
+
 #define BEM_HIP(call)                                                                         \
     do {                                                                                      \
         hipError_t e_ = (call);                                                               \
@@ -79,6 +100,26 @@ struct GemmPlan {
     int64_t kslice;
     int n_wg;
     size_t bytes_x, bytes_c;
+};
+
+// One problem's share of a grouped pair-kernel launch (k_farfield.hip): its
+// work list and the arrays the kernel reads and writes.
+struct PairMember {
+    const int4 *work;
+    const PassDev *passes;
+    const float *pts, *tnrm;
+    const float4 *trial;
+    double *part;
+    int64_t M, nt;
+    int n_split, pad;
+};
+constexpr int PAIR_GROUP_MAX = 16;
+// Member table of a grouped launch, passed by value as the kernel argument:
+// workgroups [start[m], start[m + 1]) run member m's work items.
+struct PairGroup {
+    int n, pad;
+    int start[PAIR_GROUP_MAX + 1];
+    PairMember m[PAIR_GROUP_MAX];
 };
 
 // OSRC preconditioner parameters (k_osrc.hip).
@@ -183,9 +224,17 @@ struct bem_problem {
     int2 *d_drange = nullptr;       // vertex range [begin, end) of every domain
     double *d_Mv = nullptr, *d_Sv = nullptr;
     int64_t a_nnz = 0;
+    int *d_cg_chunks = nullptr;     // [chunks][8] row chunks of the batched COCG (domain, rows, first, count)
+    int cg_n_chunks = 0;
 
     // hierarchical matrix (bem_hmatrix_build)
     bem::HMatrix *hm = nullptr;
+
+    // continuous batching (serving.cpp): the batch that launches this problem's
+    // operator applies inside solves, and the events that order its stream and
+    // the batch's around each apply
+    bem_batch *batch = nullptr;
+    hipEvent_t batch_ready = nullptr, batch_done = nullptr;
 
     // scratch vectors
     double2 *d_x = nullptr, *d_y = nullptr;
@@ -226,6 +275,10 @@ std::vector<double> singular_rule(int cls, int n);
 void launch_geometry(bem_problem &p);
 void launch_gather(bem_problem &p, const double2 *x);
 void launch_pairs(bem_problem &p);
+// kernel variant of a problem's pair kernel (problems of one variant can share a
+// grouped launch) and the grouped launch of several problems' pair kernels
+int pair_variant(const bem_problem &p);
+void launch_pairs_group(hipStream_t s, const std::vector<bem_problem *> &ps);
 void launch_reduce(bem_problem &p);
 void launch_scatter(bem_problem &p, const double2 *x, double2 *y, int parts);
 void launch_assemble_dense(bem_problem &p);
@@ -322,6 +375,15 @@ struct KrylovOpts {
 };
 void gmres_batch(bem_problem &p, int64_t n, int R, const double2 *B, double2 *X, const KrylovOpts &o,
                  const ApplyFn &A, const ApplyFn *M, bem_solve_info *info);
+
+// continuous batching (serving.cpp): kinds of operator apply a problem hands
+// to its batch, the hand-over (returns once the apply is launched and the
+// problem's stream waits for it), and the count of problems inside a solve
+enum BatchKind : int { BATCH_OTF = 0, BATCH_GEMV = 1, BATCH_GEMM_BF16 = 2, BATCH_GEMM_F32 = 3, BATCH_HMATRIX = 4 };
+void batch_apply(bem_problem &p, int kind, const double2 *X, double2 *Y, int R);
+void batch_enter(bem_batch &b);
+void batch_leave(bem_batch &b);
+void batch_detach(bem_problem &p);
 
 // OSRC preconditioner (k_osrc.hip): Out = P Y for R residual vectors
 void osrc_setup(bem_problem &p);

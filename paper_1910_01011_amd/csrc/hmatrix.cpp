@@ -71,12 +71,12 @@ struct DevMem {
     DevMem &operator=(const DevMem &) = delete;
     ~DevMem()
     {
-        if (p) (void)hipFree(p);
+        if (p) dfree(p);
     }
     template <typename T>
     T *alloc(size_t n)
     {
-        BEM_HIP(hipMalloc(&p, std::max<size_t>(1, n) * sizeof(T)));
+        dmalloc(reinterpret_cast<void **>(&p), std::max<size_t>(1, n) * sizeof(T));
         return static_cast<T *>(p);
     }
 };
@@ -241,10 +241,10 @@ struct HMatrix {
     ~HMatrix()
     {
         for (void *q : pools)
-            if (q) (void)hipFree(q);
+            if (q) dfree(q);
         void *ptrs[] = {d_blocks, d_perm, d_rowptr, d_rowz, d_xp, d_z};
         for (void *q : ptrs)
-            if (q) (void)hipFree(q);
+            if (q) dfree(q);
     }
 };
 
@@ -297,14 +297,14 @@ static HMatrix *build(bem_problem &p, double eps, int leaf, double eta, int max_
     // device copies that live with the matrix (owned by H)
     const auto own = [&](auto &dst, const auto &h) {
         using T = typename std::decay_t<decltype(h)>::value_type;
-        BEM_HIP(hipMalloc(&dst, std::max<size_t>(1, h.size()) * sizeof(T)));
+        dmalloc(reinterpret_cast<void **>(&dst), std::max<size_t>(1, h.size()) * sizeof(T));
         if (!h.empty()) BEM_HIP(hipMemcpyAsync(dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
     };
     own(H->d_perm, perm);
     own(H->d_rowptr, rowptr);
     own(H->d_rowz, rowz);
-    BEM_HIP(hipMalloc(&H->d_xp, size_t(2 * NV) * sizeof(double2)));
-    BEM_HIP(hipMalloc(&H->d_z, size_t(std::max<int64_t>(1, zl)) * sizeof(double2)));
+    dmalloc(reinterpret_cast<void **>(&H->d_xp), size_t(2 * NV) * sizeof(double2));
+    dmalloc(reinterpret_cast<void **>(&H->d_z), size_t(std::max<int64_t>(1, zl)) * sizeof(double2));
     DevMem m_iperm;
     int32_t *d_iperm = upload(iperm, m_iperm, s);
 
@@ -326,7 +326,7 @@ static HMatrix *build(bem_problem &p, double eps, int leaf, double eta, int max_
         const auto a = mn(u), b = mn(v);
         return a.first * a.second > b.first * b.second || (a.first * a.second == b.first * b.second && u < v);
     });
-    BEM_HIP(hipMalloc(&H->d_blocks, std::max<size_t>(1, size_t(nb)) * sizeof(HBlock)));
+    dmalloc(reinterpret_cast<void **>(&H->d_blocks), std::max<size_t>(1, size_t(nb)) * sizeof(HBlock));
     const auto push_blocks = [&]() {
         BEM_HIP(hipMemcpyAsync(H->d_blocks, H->blocks.data(), size_t(nb) * sizeof(HBlock), hipMemcpyHostToDevice, s));
         BEM_HIP(hipStreamSynchronize(s));
@@ -357,7 +357,7 @@ static HMatrix *build(bem_problem &p, double eps, int leaf, double eta, int max_
                 keep += int64_t(rank[j]) * (m2 + n2);
             }
         float2 *pool = nullptr;
-        BEM_HIP(hipMalloc(&pool, size_t(std::max<int64_t>(1, keep)) * sizeof(float2)));
+        dmalloc(reinterpret_cast<void **>(&pool), size_t(std::max<int64_t>(1, keep)) * sizeof(float2));
         H->pools.push_back(pool);
         std::vector<const float2 *> src;
         std::vector<float2 *> dst;
@@ -445,7 +445,7 @@ static HMatrix *build(bem_problem &p, double eps, int leaf, double eta, int max_
         dense_len += m2 * n2;
     }
     float2 *dpool = nullptr;
-    BEM_HIP(hipMalloc(&dpool, size_t(std::max<int64_t>(1, dense_len)) * sizeof(float2)));
+    dmalloc(reinterpret_cast<void **>(&dpool), size_t(std::max<int64_t>(1, dense_len)) * sizeof(float2));
     H->pools.push_back(dpool);
     std::vector<float2 *> Dp(nb, nullptr);
     {

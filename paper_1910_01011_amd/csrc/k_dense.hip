@@ -265,16 +265,16 @@ struct EntrySetup {
     EntrySetup &operator=(const EntrySetup &) = delete;
     ~EntrySetup()
     {
-        if (rec) (void)hipFree(rec);
-        if (vdom) (void)hipFree(vdom);
-        if (doms) (void)hipFree(doms);
+        if (rec) dfree(rec);
+        if (vdom) dfree(vdom);
+        if (doms) dfree(doms);
     }
 };
 
 static void entry_setup(bem_problem &p, EntrySetup &E)
 {
     const int64_t n_corner = 3 * p.NT;
-    BEM_HIP(hipMalloc(&E.rec, size_t(18 * n_corner) * sizeof(float4)));
+    dmalloc(reinterpret_cast<void **>(&E.rec), size_t(18 * n_corner) * sizeof(float4));
     k_vertex_points<<<dim3(blocks_1d(6 * n_corner, 256)), dim3(256), 0, p.stream>>>(
         p.d_v2t, n_corner, p.d_area, p.d_normal, p.d_curl, p.d_pts, p.M, E.rec);
     BEM_HIP(hipGetLastError());
@@ -291,8 +291,8 @@ static void entry_setup(bem_problem &p, EntrySetup &E)
     }
     E.ext = DenseDom{float(p.k0re), float(p.k0re / (2.0 * M_PI)), float(p.k0im), 1.0f, 1.0f,
                      float(p.k0re * p.k0re - p.k0im * p.k0im), float(2.0 * p.k0re * p.k0im), 0.0f};
-    BEM_HIP(hipMalloc(&E.vdom, vdom.size() * sizeof(int32_t)));
-    BEM_HIP(hipMalloc(&E.doms, doms.size() * sizeof(DenseDom)));
+    dmalloc(reinterpret_cast<void **>(&E.vdom), vdom.size() * sizeof(int32_t));
+    dmalloc(reinterpret_cast<void **>(&E.doms), doms.size() * sizeof(DenseDom));
     BEM_HIP(hipMemcpyAsync(E.vdom, vdom.data(), vdom.size() * sizeof(int32_t), hipMemcpyHostToDevice, p.stream));
     BEM_HIP(hipMemcpyAsync(E.doms, doms.data(), doms.size() * sizeof(DenseDom), hipMemcpyHostToDevice, p.stream));
     // staged degree: the mesh's largest, at most STAGE_MAX_DEGREE (LDS per

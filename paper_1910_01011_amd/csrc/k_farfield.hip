@@ -231,14 +231,13 @@ __device__ __forceinline__ void triangle_step(const float nx, const float ny, co
 // hoists all twelve LDS reads of a triangle and needs 129 VGPRs (three
 // waves); bounded, it fits 93 without spills and runs 8 % faster.
 template <int TPL, bool ATT, bool WRAP>
-__global__ __launch_bounds__(PAIR_BLOCK) __attribute__((amdgpu_waves_per_eu(TPL == 1 ? 5 : 3))) void k_pairs(const int4 *__restrict__ work, const PassDev *__restrict__ passes,
-                                                      const float *__restrict__ pts, const float *__restrict__ tnrm,
-                                                      const float4 *__restrict__ trial, double *__restrict__ part,
-                                                      int64_t M, int64_t nt, int n_split)
+__device__ __forceinline__ void pairs_body(const int4 w, const PassDev *__restrict__ passes,
+                                           const float *__restrict__ pts, const float *__restrict__ tnrm,
+                                           const float4 *__restrict__ trial, double *__restrict__ part, int64_t M,
+                                           int64_t nt, int n_split)
 {
     __shared__ float4 lp[2][TILE_PTS];
     __shared__ float4 lt[3][TILE_TRI];
-    const int4 w = work[blockIdx.x];
     const PassDev P = passes[w.x];
     const int tid = threadIdx.x;
     const float kv = in_vgpr(P.k), k2piv = in_vgpr(P.k_over_2pi), kimv = in_vgpr(P.kim);
@@ -337,6 +336,29 @@ __global__ __launch_bounds__(PAIR_BLOCK) __attribute__((amdgpu_waves_per_eu(TPL 
             for (int c = 0; c < 10; ++c) out[size_t(c) * M + ti[u]] = acc[u][c];
 }
 
+template <int TPL, bool ATT, bool WRAP>
+__global__ __launch_bounds__(PAIR_BLOCK) __attribute__((amdgpu_waves_per_eu(TPL == 1 ? 5 : 3))) void k_pairs(
+    const int4 *__restrict__ work, const PassDev *__restrict__ passes, const float *__restrict__ pts,
+    const float *__restrict__ tnrm, const float4 *__restrict__ trial, double *__restrict__ part, int64_t M,
+    int64_t nt, int n_split)
+{
+    pairs_body<TPL, ATT, WRAP>(work[blockIdx.x], passes, pts, tnrm, trial, part, M, nt, n_split);
+}
+
+// Grouped launch: the work lists of several problems (their own records,
+// partials and launch shapes) in one grid; workgroup b runs item
+// b - start[m] of member m.  The member table travels in the kernel arguments.
+template <int TPL, bool ATT, bool WRAP>
+__global__ __launch_bounds__(PAIR_BLOCK) __attribute__((amdgpu_waves_per_eu(TPL == 1 ? 5 : 3))) void k_pairs_group(
+    const PairGroup g)
+{
+    int m = 0;
+    while (m + 1 < g.n && int(blockIdx.x) >= g.start[m + 1]) ++m;
+    const PairMember &q = g.m[m];
+    pairs_body<TPL, ATT, WRAP>(q.work[int(blockIdx.x) - g.start[m]], q.passes, q.pts, q.tnrm, q.trial, q.part, q.M,
+                               q.nt, q.n_split);
+}
+
 void launch_pairs(bem_problem &p)
 {
     bool att = false;
@@ -361,6 +383,49 @@ void launch_pairs(bem_problem &p)
         }
     }
 #undef PAIRS
+    BEM_HIP(hipGetLastError());
+}
+
+// The pair-kernel variant of a problem: test points per lane, complex
+// wavenumbers in some pass, explicit phase reduction.
+int pair_variant(const bem_problem &p)
+{
+    bool att = false;
+    for (int i = 0; i < p.n_pass; ++i)
+        if (p.passes[i].kim != 0.0) att = true;
+    return (p.tpl == 2 ? 4 : 0) + (att ? 2 : 0) + (p.wrap_phase ? 1 : 0);
+}
+
+void launch_pairs_group(hipStream_t s, const std::vector<bem_problem *> &ps)
+{
+    if (ps.empty()) return;
+    if (int(ps.size()) > PAIR_GROUP_MAX) throw Error{BEM_ERR_INVALID_ARG, "grouped pair launch: too many problems"};
+    const int v = pair_variant(*ps[0]);
+    PairGroup g{};
+    g.n = int(ps.size());
+    int64_t total = 0;
+    for (int i = 0; i < g.n; ++i) {
+        const bem_problem &p = *ps[i];
+        if (pair_variant(p) != v) throw Error{BEM_ERR_INVALID_ARG, "grouped pair launch: mixed kernel variants"};
+        g.start[i] = int(total);
+        g.m[i] = PairMember{p.d_work, p.d_pass, p.d_pts, p.d_tnrm, p.d_trial, p.d_part, p.M, p.NT, p.n_split, 0};
+        total += p.n_work;
+    }
+    if (total >= (int64_t(1) << 31) / PAIR_BLOCK) throw Error{BEM_ERR_UNSUPPORTED, "grouped pair launch too large"};
+    for (int i = g.n; i <= PAIR_GROUP_MAX; ++i) g.start[i] = int(total);
+    const dim3 grid{unsigned(total), 1u, 1u}, block{unsigned(PAIR_BLOCK), 1u, 1u};
+#define PAIRS_G(T, A, W) k_pairs_group<T, A, W><<<grid, block, 0, s>>>(g)
+    switch (v) {
+    case 0: PAIRS_G(1, false, false); break;
+    case 1: PAIRS_G(1, false, true); break;
+    case 2: PAIRS_G(1, true, false); break;
+    case 3: PAIRS_G(1, true, true); break;
+    case 4: PAIRS_G(2, false, false); break;
+    case 5: PAIRS_G(2, false, true); break;
+    case 6: PAIRS_G(2, true, false); break;
+    default: PAIRS_G(2, true, true); break;
+    }
+#undef PAIRS_G
     BEM_HIP(hipGetLastError());
 }
 

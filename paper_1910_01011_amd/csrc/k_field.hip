@@ -162,7 +162,7 @@ struct DevScratch {
     DevScratch &operator=(const DevScratch &) = delete;
     ~DevScratch()
     {
-        if (p) (void)hipFree(p);
+        if (p) dfree(p);
     }
 };
 
@@ -183,7 +183,7 @@ static IncDev upload_incident(bem_problem &p, const bem_incident &inc, double **
             const double l = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
             for (int c = 0; c < 3; ++c) d[c] /= l;
         }
-    BEM_HIP(hipMalloc(d_params, std::max<size_t>(1, h.size()) * sizeof(double)));
+    dmalloc(reinterpret_cast<void **>(d_params), std::max<size_t>(1, h.size()) * sizeof(double));
     BEM_HIP(hipMemcpyAsync(*d_params, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, p.stream));
     IncDev I;
     I.kind = inc.kind;
@@ -482,14 +482,14 @@ void launch_field(bem_problem &p, const double2 *u, const bem_incident *inc, int
         hd.push_back(DomDev{d.v_off, d.t_off, d.nt, d.nv, d.kre, d.kim, d.rho, sum / double(3 * d.nt)});
     }
     DomDev *d_doms = nullptr;
-    BEM_HIP(hipMalloc(&d_doms, hd.size() * sizeof(DomDev)));
+    dmalloc(reinterpret_cast<void **>(&d_doms), hd.size() * sizeof(DomDev));
     doms_mem.p = d_doms;
     BEM_HIP(hipMemcpyAsync(d_doms, hd.data(), hd.size() * sizeof(DomDev), hipMemcpyHostToDevice, p.stream));
     const int B = 128;
     int32_t *wreg = nullptr;
     double2 *R = nullptr;
     if (np > 0) {
-        BEM_HIP(hipMalloc(&wreg, size_t(np) * sizeof(int32_t)));
+        dmalloc(reinterpret_cast<void **>(&wreg), size_t(np) * sizeof(int32_t));
         wreg_mem.p = wreg;
         k_region<<<dim3(blocks_1d(np, B)), dim3(B), 0, p.stream>>>(d_doms, int(hd.size()), p.d_verts, p.d_tris, pts, np,
                                                                    wreg, region);
@@ -507,7 +507,7 @@ void launch_field(bem_problem &p, const double2 *u, const bem_incident *inc, int
                 const long long c = std::atoll(e);
                 if (c > 0) chunk = std::min<int64_t>(chunk, c);
             }
-            BEM_HIP(hipMalloc(&R, size_t(chunk) * p.N * sizeof(double2)));
+            dmalloc(reinterpret_cast<void **>(&R), size_t(chunk) * p.N * sizeof(double2));
             rows_mem.p = R;
             for (int64_t p0 = 0; p0 < np; p0 += chunk) {
                 const int64_t npc = std::min(chunk, np - p0);

@@ -484,8 +484,8 @@ static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 void split_matrix_bf16(bem_problem &p)
 {
     const int64_t Kp = round_up(2 * p.N, GKA), Mr = round_up(p.N, 16);
-    BEM_HIP(hipMalloc(&p.d_Ahi, size_t(Mr) * Kp * sizeof(uint16_t)));
-    BEM_HIP(hipMalloc(&p.d_Alo, size_t(Mr) * Kp * sizeof(uint16_t)));
+    dmalloc(reinterpret_cast<void **>(&p.d_Ahi), size_t(Mr) * Kp * sizeof(uint16_t));
+    dmalloc(reinterpret_cast<void **>(&p.d_Alo), size_t(Mr) * Kp * sizeof(uint16_t));
     const int64_t tot = Mr * Kp;
     k_split_matrix<<<dim3(blocks_1d(tot, 256, true)), dim3(256), 0, p.stream>>>(
         reinterpret_cast<const float *>(p.d_A), p.N, Mr, Kp, p.d_Ahi, p.d_Alo);

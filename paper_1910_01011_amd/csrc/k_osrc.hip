@@ -16,7 +16,8 @@
 // domain).  The sparse solves of one application (two batches: the mass solve,
 // then every Pade and w0 system) are done by a batched
 // Jacobi-preconditioned COCG (conjugate orthogonal CG for complex symmetric
-// matrices) in FP64, one workgroup per (system, domain) block.
+// matrices) in FP64, every (system, domain) block spread over workgroups of
+// 256 rows.
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -181,6 +182,8 @@ __global__ void k_osrc_out(const double2 *__restrict__ rootD, const double2 *__r
 
 static unsigned nb(int64_t n) { return blocks_1d(n, 256); }
 
+constexpr int CG_ROWS = 256;   // rows per chunk of the batched COCG (its workgroup size)
+
 // stream-ordered scratch on the stream of the current problem
 thread_local hipStream_t t_osrc_stream = nullptr;
 
@@ -216,52 +219,82 @@ void osrc_setup(bem_problem &p)
         dpos[g] = int32_t(std::lower_bound(col.begin() + ptr[g], col.begin() + ptr[g + 1], int32_t(g)) - col.begin());
     std::vector<int2> rng;
     for (const auto &d : p.doms) rng.push_back(make_int2(int(d.v_off), int(d.v_off + d.nv)));
-    BEM_HIP(hipMalloc(&p.d_adiag, dpos.size() * sizeof(int32_t)));
-    BEM_HIP(hipMalloc(&p.d_drange, rng.size() * sizeof(int2)));
+    dmalloc(reinterpret_cast<void **>(&p.d_adiag), dpos.size() * sizeof(int32_t));
+    dmalloc(reinterpret_cast<void **>(&p.d_drange), rng.size() * sizeof(int2));
     BEM_HIP(hipMemcpyAsync(p.d_adiag, dpos.data(), dpos.size() * sizeof(int32_t), hipMemcpyHostToDevice, p.stream));
     BEM_HIP(hipMemcpyAsync(p.d_drange, rng.data(), rng.size() * sizeof(int2), hipMemcpyHostToDevice, p.stream));
-    BEM_HIP(hipMalloc(&p.d_aptr, ptr.size() * sizeof(int32_t)));
-    BEM_HIP(hipMalloc(&p.d_acol, col.size() * sizeof(int32_t)));
-    BEM_HIP(hipMalloc(&p.d_Mv, col.size() * sizeof(double)));
-    BEM_HIP(hipMalloc(&p.d_Sv, col.size() * sizeof(double)));
+    dmalloc(reinterpret_cast<void **>(&p.d_aptr), ptr.size() * sizeof(int32_t));
+    dmalloc(reinterpret_cast<void **>(&p.d_acol), col.size() * sizeof(int32_t));
+    dmalloc(reinterpret_cast<void **>(&p.d_Mv), col.size() * sizeof(double));
+    dmalloc(reinterpret_cast<void **>(&p.d_Sv), col.size() * sizeof(double));
     BEM_HIP(hipMemcpyAsync(p.d_aptr, ptr.data(), ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice, p.stream));
     BEM_HIP(hipMemcpyAsync(p.d_acol, col.data(), col.size() * sizeof(int32_t), hipMemcpyHostToDevice, p.stream));
     k_mass_stiff<<<dim3(nb(p.NV)), dim3(256), 0, p.stream>>>(p.d_verts, p.d_tris, p.d_area, p.d_v2t_ptr, p.d_v2t,
                                                             p.d_aptr, p.d_acol, p.NV, p.d_Mv, p.d_Sv);
     BEM_HIP(hipGetLastError());
     BEM_HIP(hipStreamSynchronize(p.stream));
+    // row chunks of the batched COCG: every domain's rows cut into pieces of
+    // CG_ROWS (the kernels' workgroup size)
+    std::vector<int> ch;
+    for (size_t d = 0; d < p.doms.size(); ++d) {
+        const int b0 = int(p.doms[d].v_off), b1 = int(p.doms[d].v_off + p.doms[d].nv);
+        const int first = int(ch.size() / 8), nc = (b1 - b0 + CG_ROWS - 1) / CG_ROWS;
+        for (int c = 0; c < nc; ++c) {
+            const int lo = b0 + c * CG_ROWS;
+            const int v[8] = {int(d), lo, std::min(b1, lo + CG_ROWS), first, nc, 0, 0, 0};
+            ch.insert(ch.end(), v, v + 8);
+        }
+    }
+    p.cg_n_chunks = int(ch.size() / 8);
+    dmalloc(reinterpret_cast<void **>(&p.d_cg_chunks), ch.size() * sizeof(int));
+    BEM_HIP(hipMemcpyAsync(p.d_cg_chunks, ch.data(), ch.size() * sizeof(int), hipMemcpyHostToDevice, p.stream));
+    BEM_HIP(hipStreamSynchronize(p.stream));
 }
 
-// Persistent COCG: one 1024-lane workgroup per (system, domain) block of
-// (M - c_g S) x_g = b_g.  M and S couple only vertices of one boundary, so
-// the block of every domain is an independent system; each converges on its
-// own (||r_d|| <= tol ||b_d||) with a Jacobi preconditioner
-// (diag(M - c_g S)), zero initial guess, maxit iterations at most.  Every loop
-// decision uses block-reduced values, so all waves of a workgroup take the same
-// path and the loop ends for all of them.
-constexpr int CG_BLOCK = 1024;
+// Batched COCG for (M - c_g S) x_g = b_g, g = 0 .. G-1.  M and S couple only
+// vertices of one boundary, so the block of every domain is an independent
+// system: each (system, domain) block converges on its own
+// (||r|| <= tol ||b|| over the block) with a Jacobi preconditioner
+// (diag(M - c_g S)), zero initial guess, at most maxit iterations.
+//
+// The rows of every domain are cut into chunks of CG_ROWS; one workgroup per
+// (chunk, system) works on its rows, so a single system spreads over many CUs.
+// An iteration is three launches whose boundaries are the grid-wide waits of
+// the method (q = A p and p.q; x, r, z and r.z, |r|^2; the new direction):
+// the dot products of a block are per-chunk partial sums that every
+// workgroup of the block adds up again in the same fixed order, so each takes
+// the same decision and the result does not depend on scheduling.  A block's
+// flag `done` is written only by the last kernel of an iteration, which stops
+// on convergence before touching any vector, so workgroups that read the flag
+// early or late in that kernel act alike.  The host launches the iterations
+// and reads the flags every CG_CHECK iterations.
+constexpr int CG_CHECK = 8;
 
-__device__ __forceinline__ void block_sum3(double &a, double &b, double &c, double *red)
+// Fixed-order sum over the 256 threads of a workgroup: wave shuffles, then the
+// four wave sums in wave order.
+template <int K>
+__device__ __forceinline__ void wg_sum(double (&v)[K], double *red)
 {
-    for (int off = 32; off > 0; off >>= 1) {
-        a += __shfl_xor(a, off);
-        b += __shfl_xor(b, off);
-        c += __shfl_xor(c, off);
-    }
+    for (int k = 0; k < K; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     __syncthreads();
-    if (lane == 0) {
-        red[3 * w] = a;
-        red[3 * w + 1] = b;
-        red[3 * w + 2] = c;
-    }
+    if (lane == 0)
+        for (int k = 0; k < K; ++k) red[K * w + k] = v[k];
     __syncthreads();
-    a = b = c = 0.0;
-    for (int k = 0; k < CG_BLOCK / 64; ++k) {
-        a += red[3 * k];
-        b += red[3 * k + 1];
-        c += red[3 * k + 2];
-    }
+    for (int k = 0; k < K; ++k) v[k] = red[k] + red[K + k] + red[2 * K + k] + red[3 * K + k];
+}
+
+// Sum of the K-vectors part[first .. first + nc) (fixed assignment of chunks to
+// threads, then wg_sum).
+template <int K>
+__device__ __forceinline__ void block_partials(const double *__restrict__ part, int64_t first, int nc, double (&v)[K],
+                                               double *red)
+{
+    for (int k = 0; k < K; ++k) v[k] = 0.0;
+    for (int c = threadIdx.x; c < nc; c += CG_ROWS)
+        for (int k = 0; k < K; ++k) v[k] += part[K * (first + c) + k];
+    wg_sum<K>(v, red);
 }
 
 // z = r / d (complex)
@@ -271,87 +304,182 @@ __device__ __forceinline__ double2 cdiv(double2 r, double2 d)
     return make_double2((r.x * d.x + r.y * d.y) / den, (r.y * d.x - r.x * d.y) / den);
 }
 
-__global__ __launch_bounds__(CG_BLOCK) void k_cocg_persistent(const int32_t *__restrict__ aptr,
-                                                              const int32_t *__restrict__ acol,
-                                                              const int32_t *__restrict__ adiag,
-                                                              const double *__restrict__ Mv,
-                                                              const double *__restrict__ Sv,
-                                                              const int2 *__restrict__ drange, int n_dom,
-                                                              const double2 *__restrict__ c,
-                                                              const double2 *__restrict__ B, double2 *__restrict__ X,
-                                                              double2 *__restrict__ Rw, double2 *__restrict__ Pw,
-                                                              double2 *__restrict__ Qw, int64_t n, double tol,
-                                                              int maxit)
+struct CgChunk {
+    int dom, begin, end, first;   // domain, row range, index of the domain's first chunk
+    int nc, pad0, pad1, pad2;     // chunks of the domain
+};
+
+struct CgArgs {
+    const int32_t *aptr, *acol, *adiag;
+    const double *Mv, *Sv;
+    const CgChunk *chunks;
+    int n_chunks, n_dom;
+    int64_t n;                     // rows of one system (all vertices)
+    const double2 *c;              // [G] shifts
+    const double2 *B;              // [G][n]
+    double2 *X, *R, *P, *Q, *Z;    // [G][n]
+    double *part1, *part2;         // [G][n_chunks][2], [G][n_chunks][3]
+    double *bn2;                   // [G][n_dom]
+    double2 *rho;                  // [2][G][n_dom]
+    int32_t *done, *its;           // [G][n_dom]
+    double tol;
+    int maxit;
+};
+
+// The block's done flag as one value for the whole workgroup: read by one
+// thread and shared through LDS, so that every wave of the workgroup takes the
+// same branch even while another workgroup sets the flag.
+__device__ __forceinline__ bool cg_block_done(const int32_t *done, int64_t blk)
 {
-    __shared__ double red[3 * (CG_BLOCK / 64)];
-    const int64_t g = blockIdx.x / n_dom;
-    const int2 rng = drange[blockIdx.x - g * n_dom];
-    const int tid = threadIdx.x;
-    const double2 cg = c[g];
-    const double2 *b = B + g * n;
-    double2 *x = X + g * n, *r = Rw + g * n, *pv = Pw + g * n, *q = Qw + g * n;
-    auto diag = [&](int64_t i) {
-        const int32_t e = adiag[i];
-        return make_double2(Mv[e] - cg.x * Sv[e], -cg.y * Sv[e]);
-    };
-    double bn2 = 0, rr_ = 0, ri_ = 0;
-    for (int64_t i = rng.x + tid; i < rng.y; i += CG_BLOCK) {
-        const double2 v = b[i];
-        const double2 z = cdiv(v, diag(i));
-        x[i] = make_double2(0.0, 0.0);
-        r[i] = v;
-        pv[i] = z;
-        bn2 += v.x * v.x + v.y * v.y;
-        rr_ += v.x * z.x - v.y * z.y;   // rho = r^T z (unconjugated)
-        ri_ += v.x * z.y + v.y * z.x;
+    __shared__ int32_t flag;
+    if (threadIdx.x == 0) flag = done[blk];
+    __syncthreads();
+    return flag != 0;
+}
+
+__device__ __forceinline__ double2 cg_diag(const CgArgs &a, double2 cg, int64_t i)
+{
+    const int32_t e = a.adiag[i];
+    return make_double2(a.Mv[e] - cg.x * a.Sv[e], -cg.y * a.Sv[e]);
+}
+
+// x = 0, r = b, z = p = b / diag; partials (|b|^2, b.z)
+__global__ __launch_bounds__(CG_ROWS) void k_cg_init(CgArgs a)
+{
+    __shared__ double red[12];
+    const int64_t g = blockIdx.y;
+    const CgChunk ch = a.chunks[blockIdx.x];
+    const int64_t i = ch.begin + threadIdx.x;
+    const double2 cg = a.c[g];
+    double v[3] = {0.0, 0.0, 0.0};
+    if (i < ch.end) {
+        const int64_t k = g * a.n + i;
+        const double2 bv = a.B[k], z = cdiv(bv, cg_diag(a, cg, i));
+        a.X[k] = make_double2(0.0, 0.0);
+        a.R[k] = bv;
+        a.Z[k] = z;
+        a.P[k] = z;
+        v[0] = bv.x * bv.x + bv.y * bv.y;
+        v[1] = bv.x * z.x - bv.y * z.y;   // rho = r^T z (unconjugated)
+        v[2] = bv.x * z.y + bv.y * z.x;
     }
-    block_sum3(bn2, rr_, ri_, red);
-    if (bn2 == 0.0) return;
-    double rho_r = rr_, rho_i = ri_;
-    for (int it = 0; it < maxit; ++it) {
-        __syncthreads();   // p complete before the product
-        double pqr = 0, pqi = 0, dummy = 0;
-        for (int64_t i = rng.x + tid; i < rng.y; i += CG_BLOCK) {
-            double mr = 0, mi = 0, sr = 0, si = 0;
-            for (int32_t e = aptr[i]; e < aptr[i + 1]; ++e) {
-                const double2 v = pv[acol[e]];
-                mr += Mv[e] * v.x;
-                mi += Mv[e] * v.y;
-                sr += Sv[e] * v.x;
-                si += Sv[e] * v.y;
-            }
-            const double qr = mr - (cg.x * sr - cg.y * si), qi = mi - (cg.x * si + cg.y * sr);
-            q[i] = make_double2(qr, qi);
-            const double2 pp = pv[i];
-            pqr += pp.x * qr - pp.y * qi;
-            pqi += pp.x * qi + pp.y * qr;
+    wg_sum<3>(v, red);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) a.part2[3 * (g * a.n_chunks + blockIdx.x) + k] = v[k];
+}
+
+// per block: |b|^2 and rho_0; blocks with b = 0 are done (x = 0)
+__global__ __launch_bounds__(CG_ROWS) void k_cg_init_block(CgArgs a)
+{
+    __shared__ double red[12];
+    const int64_t g = blockIdx.y;
+    const CgChunk ch = a.chunks[blockIdx.x];
+    if (blockIdx.x != unsigned(ch.first)) return;   // one workgroup per block
+    double v[3];
+    block_partials<3>(a.part2, g * a.n_chunks + ch.first, ch.nc, v, red);
+    if (threadIdx.x == 0) {
+        const int64_t blk = g * a.n_dom + ch.dom;
+        a.bn2[blk] = v[0];
+        a.rho[blk] = make_double2(v[1], v[2]);
+        a.done[blk] = v[0] == 0.0 ? 1 : 0;
+        a.its[blk] = 0;
+    }
+}
+
+// q = (M - c S) p on the chunk's rows; partial p.q
+__global__ __launch_bounds__(CG_ROWS) void k_cg_spmv(CgArgs a)
+{
+    __shared__ double red[8];
+    const int64_t g = blockIdx.y;
+    const CgChunk ch = a.chunks[blockIdx.x];
+    if (cg_block_done(a.done, g * a.n_dom + ch.dom)) return;
+    const int64_t i = ch.begin + threadIdx.x;
+    const double2 cg = a.c[g];
+    const double2 *pv = a.P + g * a.n;
+    double v[2] = {0.0, 0.0};
+    if (i < ch.end) {
+        double mr = 0, mi = 0, sr = 0, si = 0;
+        for (int32_t e = a.aptr[i]; e < a.aptr[i + 1]; ++e) {
+            const double2 x = pv[a.acol[e]];
+            mr += a.Mv[e] * x.x;
+            mi += a.Mv[e] * x.y;
+            sr += a.Sv[e] * x.x;
+            si += a.Sv[e] * x.y;
         }
-        block_sum3(pqr, pqi, dummy, red);
-        const double den = pqr * pqr + pqi * pqi;
-        if (den == 0.0) break;
-        const double ar = (rho_r * pqr + rho_i * pqi) / den, ai = (rho_i * pqr - rho_r * pqi) / den;
-        double rn2 = 0, sr2 = 0, si2 = 0;
-        for (int64_t i = rng.x + tid; i < rng.y; i += CG_BLOCK) {
-            const double2 pp = pv[i], qq = q[i], xx = x[i], rv = r[i];
-            x[i] = make_double2(xx.x + ar * pp.x - ai * pp.y, xx.y + ar * pp.y + ai * pp.x);
-            const double2 nr = make_double2(rv.x - (ar * qq.x - ai * qq.y), rv.y - (ar * qq.y + ai * qq.x));
-            r[i] = nr;
-            const double2 z = cdiv(nr, diag(i));
-            rn2 += nr.x * nr.x + nr.y * nr.y;
-            sr2 += nr.x * z.x - nr.y * z.y;
-            si2 += nr.x * z.y + nr.y * z.x;
-        }
-        block_sum3(rn2, sr2, si2, red);
-        if (rn2 <= tol * tol * bn2) break;
-        const double d2 = rho_r * rho_r + rho_i * rho_i;
-        if (d2 == 0.0) break;
-        const double br = (sr2 * rho_r + si2 * rho_i) / d2, bi = (si2 * rho_r - sr2 * rho_i) / d2;
-        rho_r = sr2;
-        rho_i = si2;
-        for (int64_t i = rng.x + tid; i < rng.y; i += CG_BLOCK) {
-            const double2 pp = pv[i], z = cdiv(r[i], diag(i));
-            pv[i] = make_double2(z.x + br * pp.x - bi * pp.y, z.y + br * pp.y + bi * pp.x);
-        }
+        const double qr = mr - (cg.x * sr - cg.y * si), qi = mi - (cg.x * si + cg.y * sr);
+        a.Q[g * a.n + i] = make_double2(qr, qi);
+        const double2 pp = pv[i];
+        v[0] = pp.x * qr - pp.y * qi;
+        v[1] = pp.x * qi + pp.y * qr;
+    }
+    wg_sum<2>(v, red);
+    if (threadIdx.x == 0) {
+        a.part1[2 * (g * a.n_chunks + blockIdx.x)] = v[0];
+        a.part1[2 * (g * a.n_chunks + blockIdx.x) + 1] = v[1];
+    }
+}
+
+// alpha = rho / (p.q); x += alpha p, r -= alpha q, z = r / diag; partials
+// (|r|^2, r.z).  A breakdown (p.q = 0) leaves x and r and reports |r| = 0, which
+// ends the block in the next kernel.
+__global__ __launch_bounds__(CG_ROWS) void k_cg_update(CgArgs a, int parity)
+{
+    __shared__ double red[12];
+    const int64_t g = blockIdx.y;
+    const CgChunk ch = a.chunks[blockIdx.x];
+    const int64_t blk = g * a.n_dom + ch.dom;
+    if (cg_block_done(a.done, blk)) return;
+    double pq[2];
+    block_partials<2>(a.part1, g * a.n_chunks + ch.first, ch.nc, pq, red);
+    const double den = pq[0] * pq[0] + pq[1] * pq[1];
+    const double2 rho = a.rho[parity * a.n_dom * int64_t(gridDim.y) + blk];
+    const int64_t i = ch.begin + threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (den != 0.0 && i < ch.end) {
+        const double ar = (rho.x * pq[0] + rho.y * pq[1]) / den, ai = (rho.y * pq[0] - rho.x * pq[1]) / den;
+        const int64_t k = g * a.n + i;
+        const double2 pp = a.P[k], qq = a.Q[k], xx = a.X[k], rv = a.R[k];
+        a.X[k] = make_double2(xx.x + ar * pp.x - ai * pp.y, xx.y + ar * pp.y + ai * pp.x);
+        const double2 nr = make_double2(rv.x - (ar * qq.x - ai * qq.y), rv.y - (ar * qq.y + ai * qq.x));
+        a.R[k] = nr;
+        const double2 z = cdiv(nr, cg_diag(a, a.c[g], i));
+        a.Z[k] = z;
+        v[0] = nr.x * nr.x + nr.y * nr.y;
+        v[1] = nr.x * z.x - nr.y * z.y;
+        v[2] = nr.x * z.y + nr.y * z.x;
+    }
+    wg_sum<3>(v, red);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) a.part2[3 * (g * a.n_chunks + blockIdx.x) + k] = v[k];
+}
+
+// convergence test of the block, else beta = rho_new / rho and p = z + beta p;
+// rho_new goes to the other parity slot
+__global__ __launch_bounds__(CG_ROWS) void k_cg_direction(CgArgs a, int parity, int it)
+{
+    __shared__ double red[12];
+    const int64_t g = blockIdx.y;
+    const CgChunk ch = a.chunks[blockIdx.x];
+    const int64_t blk = g * a.n_dom + ch.dom;
+    if (cg_block_done(a.done, blk)) return;
+    double v[3];
+    block_partials<3>(a.part2, g * a.n_chunks + ch.first, ch.nc, v, red);
+    const int64_t nblk = a.n_dom * int64_t(gridDim.y);
+    const double2 rho = a.rho[parity * nblk + blk];
+    const double d2 = rho.x * rho.x + rho.y * rho.y;
+    const bool stop = v[0] <= a.tol * a.tol * a.bn2[blk] || d2 == 0.0 || it + 1 >= a.maxit;
+    if (threadIdx.x == 0 && blockIdx.x == unsigned(ch.first)) {
+        a.its[blk] = it + 1;
+        if (stop) a.done[blk] = 1;
+        else a.rho[(1 - parity) * nblk + blk] = make_double2(v[1], v[2]);
+    }
+    if (stop) return;
+    const double br = (v[1] * rho.x + v[2] * rho.y) / d2, bi = (v[2] * rho.x - v[1] * rho.y) / d2;
+    const int64_t i = ch.begin + threadIdx.x;
+    if (i < ch.end) {
+        const int64_t k = g * a.n + i;
+        const double2 pp = a.P[k], z = a.Z[k];
+        a.P[k] = make_double2(z.x + br * pp.x - bi * pp.y, z.y + br * pp.y + bi * pp.x);
     }
 }
 
@@ -361,19 +489,68 @@ static void cocg_batch(bem_problem &p, int G, const std::vector<cd> &c, const do
     t_osrc_stream = p.stream;
     const int64_t n = p.NV;
     hipStream_t s = p.stream;
+    const int n_dom = int(p.doms.size());
+    const int C = p.cg_n_chunks;
+    if (G < 1) return;
+    if (G > 65535) throw Error{BEM_ERR_UNSUPPORTED, "OSRC: too many systems in one batch"};
     const size_t tot = size_t(G) * n;
-    OsrcBuf R(tot), Pp(tot), Q(tot), cdev{size_t(G)};
+    OsrcBuf R(tot), Pp(tot), Q(tot), Z(tot), cdev{size_t(G)}, rho(size_t(2) * G * n_dom);
+    struct DBuf {
+        double *p = nullptr;
+        hipStream_t s;
+        DBuf(size_t k, hipStream_t st) : s(st)
+        {
+            BEM_HIP(hipMallocAsync(reinterpret_cast<void **>(&p), std::max<size_t>(1, k) * sizeof(double), s));
+        }
+        ~DBuf() { (void)hipFreeAsync(p, s); }
+    } part1(size_t(2) * G * C, s), part2(size_t(3) * G * C, s), bn2(size_t(G) * n_dom, s),
+        flags(size_t(G) * n_dom, s);   // done and its flags: two int32 per double
     std::vector<double2> t(G);
     for (int g = 0; g < G; ++g) t[g] = make_double2(c[g].real(), c[g].imag());
     BEM_HIP(hipMemcpyAsync(cdev.p, t.data(), G * sizeof(double2), hipMemcpyHostToDevice, s));
-    BEM_HIP(hipStreamSynchronize(s));
-    const int n_dom = int(p.doms.size());
-    const int64_t wgs = int64_t(G) * n_dom;
-    if (wgs >= (int64_t(1) << 31)) throw Error{BEM_ERR_UNSUPPORTED, "OSRC: too many systems in one batch"};
-    k_cocg_persistent<<<dim3(unsigned(wgs)), dim3(CG_BLOCK), 0, s>>>(p.d_aptr, p.d_acol, p.d_adiag, p.d_Mv, p.d_Sv,
-                                                                    p.d_drange, n_dom, cdev.p, B, X, R.p, Pp.p, Q.p,
-                                                                    n, tol, maxit);
+    CgArgs a{};
+    a.aptr = p.d_aptr;
+    a.acol = p.d_acol;
+    a.adiag = p.d_adiag;
+    a.Mv = p.d_Mv;
+    a.Sv = p.d_Sv;
+    a.chunks = reinterpret_cast<const CgChunk *>(p.d_cg_chunks);
+    a.n_chunks = C;
+    a.n_dom = n_dom;
+    a.n = n;
+    a.c = cdev.p;
+    a.B = B;
+    a.X = X;
+    a.R = R.p;
+    a.P = Pp.p;
+    a.Q = Q.p;
+    a.Z = Z.p;
+    a.part1 = part1.p;
+    a.part2 = part2.p;
+    a.bn2 = bn2.p;
+    a.rho = rho.p;
+    a.done = reinterpret_cast<int32_t *>(flags.p);
+    a.its = a.done + size_t(G) * n_dom;
+    a.tol = tol;
+    a.maxit = maxit;
+    const dim3 grid{unsigned(C), unsigned(G), 1u}, block{unsigned(CG_ROWS), 1u, 1u};
+    k_cg_init<<<grid, block, 0, s>>>(a);
     BEM_HIP(hipGetLastError());
+    k_cg_init_block<<<grid, block, 0, s>>>(a);
+    BEM_HIP(hipGetLastError());
+    std::vector<int32_t> done(size_t(G) * n_dom);
+    for (int it = 0; it < maxit; ++it) {
+        const int parity = it & 1;
+        k_cg_spmv<<<grid, block, 0, s>>>(a);
+        k_cg_update<<<grid, block, 0, s>>>(a, parity);
+        k_cg_direction<<<grid, block, 0, s>>>(a, parity, it);
+        BEM_HIP(hipGetLastError());
+        if ((it + 1) % CG_CHECK == 0 || it + 1 == maxit) {
+            BEM_HIP(hipMemcpyAsync(done.data(), a.done, done.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            BEM_HIP(hipStreamSynchronize(s));
+            if (std::all_of(done.begin(), done.end(), [](int32_t f) { return f != 0; })) break;
+        }
+    }
 }
 
 void osrc_apply(bem_problem &p, const OsrcParams &o, const double2 *Y, double2 *Out, int R)

@@ -177,7 +177,7 @@ template <typename T>
 static T *dev_upload(const std::vector<T> &h, hipStream_t s)
 {
     T *d = nullptr;
-    BEM_HIP(hipMalloc(&d, std::max<size_t>(1, h.size()) * sizeof(T)));
+    dmalloc(reinterpret_cast<void **>(&d), std::max<size_t>(1, h.size()) * sizeof(T));
     if (!h.empty()) BEM_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
     return d;
 }
@@ -191,7 +191,7 @@ void run_singular(bem_problem &p, const std::vector<SingularItem> &items, int32_
     *nnz_out = nnz;
     *d_cptr = dev_upload(cptr, p.stream);
     *d_ccol = dev_upload(ccol, p.stream);
-    BEM_HIP(hipMalloc(d_cval, std::max<int64_t>(1, 4 * nnz) * sizeof(double2)));
+    dmalloc(reinterpret_cast<void **>(d_cval), std::max<int64_t>(1, 4 * nnz) * sizeof(double2));
 
     const std::vector<double> rc = singular_rule(COINCIDENT, p.ss_order);
     const std::vector<double> re = singular_rule(EDGE, p.ss_order);
@@ -202,7 +202,7 @@ void run_singular(bem_problem &p, const std::vector<SingularItem> &items, int32_
     int32_t *d_cp = dev_upload(contrib_ptr, p.stream), *d_ci = dev_upload(contrib_idx, p.stream);
     double2 *d_elem = nullptr;
     const int64_t n_items = int64_t(items.size());
-    BEM_HIP(hipMalloc(&d_elem, std::max<int64_t>(1, 36 * n_items) * sizeof(double2)));
+    dmalloc(reinterpret_cast<void **>(&d_elem), std::max<int64_t>(1, 36 * n_items) * sizeof(double2));
     if (n_items > 0) {
         const int B = 64;
         k_singular<<<dim3(blocks_1d(n_items, B)), dim3(B), 0, p.stream>>>(
@@ -216,8 +216,8 @@ void run_singular(bem_problem &p, const std::vector<SingularItem> &items, int32_
         BEM_HIP(hipGetLastError());
     }
     BEM_HIP(hipStreamSynchronize(p.stream));
-    (void)hipFree(d_rc); (void)hipFree(d_re); (void)hipFree(d_rv); (void)hipFree(d_items); (void)hipFree(d_passes);
-    (void)hipFree(d_cp); (void)hipFree(d_ci); (void)hipFree(d_elem);
+    dfree(d_rc); dfree(d_re); dfree(d_rv); dfree(d_items); dfree(d_passes);
+    dfree(d_cp); dfree(d_ci); dfree(d_elem);
 }
 
 }  // namespace bem

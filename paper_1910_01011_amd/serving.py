@@ -1,19 +1,23 @@
-"""Serving loop: continuous admission of solve requests on one GPU.
+"""Serving loop: continuous batching of solve requests on one GPU.
 
 Requests (a transmission problem, an incident field with one or more right-
-hand sides, solver options) arrive over time.  The dispatcher admits a waiting
+hand sides, solver options) arrive over time.  The loop admits a waiting
 request as soon as a slot is free and its device footprint
 (``bem_footprint_bytes``: geometry, singular correction, dense matrix in the
 assembled modes, Krylov bases) fits in the HBM budget next to the requests
 already running.  Every admitted request runs on its own HIP stream in a
 worker thread: set-up, right-hand side and GMRES stay on the device (operators
-and Krylov state are device resident; the C calls release the Python lock),
-so the device work of concurrent requests overlaps.  Finished requests free
-their memory, which admits the next ones.
+and Krylov state are device resident; device memory is stream-ordered; the C
+calls release the Python lock).  Its problem is attached to the server's
+``bem_batch``: the operator applies of all requests inside a solve are
+gathered step by step and launched together (the on-the-fly pair kernels of
+all requests as one grouped launch over their ragged work lists).  Finished
+requests free their memory, which admits the next ones.
 
-Each request's computation is independent of the others (own problem handle,
-own stream, deterministic kernels, no reductions across requests), so its
-result is bitwise the same alone and in a mix.
+Each request's computation is its own (own problem handle and stream, the same
+per-request work items, launch shapes and summation orders whatever the mix,
+no reductions across requests), so its result is bitwise the same alone and in
+a mix.
 """
 from __future__ import annotations
 
@@ -25,7 +29,8 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-from . import (BEM_OTF, BEM_PREC_FP32, Incident, Problem, bem_assemble_opts, _L, _domains, _check, solve_options)
+from . import (BEM_OTF, BEM_PREC_FP32, Batch, Incident, Problem, bem_assemble_opts, _L, _domains, _check,
+               solve_options)
 import ctypes
 
 
@@ -106,12 +111,15 @@ def footprint(req: Request) -> int:
     return int(out.value)
 
 
-def run_request(req: Request, t0: float, admitted: float, fp: int) -> Result:
-    """Set up, build the right-hand sides and solve one request on its own stream."""
+def run_request(req: Request, t0: float, admitted: float, fp: int, batch: Batch | None = None) -> Result:
+    """Set up, build the right-hand sides and solve one request on its own
+    stream; with a batch, the solve's operator applies go through it."""
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         ta = time.perf_counter()
         P = Problem(req.domains, req.k0, req.rho0, device=True, mode=req.mode, stream=stream.cuda_stream)
+        if batch is not None:
+            batch.attach(P)
         b = P.rhs(req.incident)
         stream.synchronize()
         tb = time.perf_counter()
@@ -127,14 +135,18 @@ def run_request(req: Request, t0: float, admitted: float, fp: int) -> Result:
 
 
 class Server:
-    """Admission by HBM footprint, bounded concurrency, one stream per request."""
+    """Admission by HBM footprint, bounded concurrency, one stream per request,
+    operator applies batched across the requests in flight (``batching``)."""
 
-    def __init__(self, hbm_budget_bytes: int | None = None, max_inflight: int = 4, headroom_bytes: int = 16 << 30):
+    def __init__(self, hbm_budget_bytes: int | None = None, max_inflight: int = 4, headroom_bytes: int = 16 << 30,
+                 batching: bool = True):
         if hbm_budget_bytes is None:
             free, _total = torch.cuda.mem_get_info()
             hbm_budget_bytes = max(0, free - headroom_bytes)
         self.budget = int(hbm_budget_bytes)
         self.max_inflight = int(max_inflight)
+        self.batching = bool(batching)
+        self.last_batch_stats: dict = {}
 
     def run(self, requests: list[Request]) -> list[Result]:
         reqs = sorted(requests, key=lambda r: r.arrival)
@@ -160,6 +172,7 @@ class Server:
                     results.append(fut.result())
             done_evt.set()
 
+        batch = Batch(torch.cuda.current_device()) if self.batching else None
         t0 = time.perf_counter()
         pending: list[Request] = []
         nxt = 0
@@ -175,7 +188,7 @@ class Server:
                         r = pending.pop(0)
                         inflight[r.rid] = fps[r.rid]
                         used[0] += fps[r.rid]
-                        fut = pool.submit(run_request, r, t0, time.perf_counter() - t0, fps[r.rid])
+                        fut = pool.submit(run_request, r, t0, time.perf_counter() - t0, fps[r.rid], batch)
                         fut.add_done_callback(lambda f, rid=r.rid: finished(f, rid))
                 # sleep until the next arrival or a completion
                 wait = 0.05
@@ -185,6 +198,9 @@ class Server:
                 done_evt.clear()
                 if errors:
                     break
+        if batch is not None:
+            self.last_batch_stats = batch.stats()
+            batch.close()
         if errors:
             raise errors[0]
         return sorted(results, key=lambda r: r.rid)

@@ -23,7 +23,9 @@ def _requests(bem, serving):
     out = []
     specs = [(0.6, 1, bem.BEM_OTF, bem.BEM_PREC_FP32),
              (0.8, 5, bem.BEM_ASSEMBLED_SPLIT_BF16, bem.BEM_PREC_SPLIT_BF16_FGMRES),
-             (0.7, 3, bem.BEM_ASSEMBLED_FP32, bem.BEM_PREC_FP32_MFMA_FGMRES)]
+             (0.7, 3, bem.BEM_ASSEMBLED_FP32, bem.BEM_PREC_FP32_MFMA_FGMRES),
+             (0.9, 2, bem.BEM_OTF, bem.BEM_PREC_FP32),
+             (0.5, 1, bem.BEM_ASSEMBLED_FP32, bem.BEM_PREC_FP32)]
     for rid, (f, R, mode, prec) in enumerate(specs):
         k0 = 2 * np.pi * f
         doms = [configs.Domain(d.vertices, d.triangles, complex(k0 / s), d.rho) for d, s in zip(base.domains, (1.04, 0.941))]
@@ -35,20 +37,32 @@ def _requests(bem, serving):
 
 
 def test_result_is_the_same_alone_and_in_a_mix():
+    """Five requests (two on the fly, three assembled: split-BF16 and FP32-MFMA
+    flexible GMRES, FP32 GEMV GMRES) alone and all together.  In the mix their
+    operator applies are launched together: the two on-the-fly requests' pair
+    kernels share grouped launches.  Every result is bitwise the same."""
     bem = _bem()
     from paper_1910_01011_amd import serving
     reqs = _requests(bem, serving)
     alone = {}
     for r in reqs:
-        res = serving.Server(max_inflight=1).run([r])
+        srv = serving.Server(max_inflight=1)
+        res = srv.run([r])
         alone[r.rid] = res[0]
-    mix = serving.Server(max_inflight=3).run(reqs)
+        assert srv.last_batch_stats["multi_problem_launches"] == 0
+    srv = serving.Server(max_inflight=5)
+    mix = srv.run(reqs)
+    stats = srv.last_batch_stats
+    print(serving.summarize(mix))
+    print(f"batch: {stats}")
     for res in mix:
         assert all(i["converged"] for i in res.info), res.info
         assert np.array_equal(res.u, alone[res.rid].u), res.rid
-    # the three requests were admitted together and overlapped on the device
+    # the requests were admitted together, and the device work of the two
+    # on-the-fly requests ran in shared launches
     assert max(r.admitted for r in mix) < min(r.finished for r in mix)
-    print(serving.summarize(mix))
+    assert stats["multi_problem_launches"] > 0 and stats["max_problems_per_launch"] == 2
+    assert stats["applies"] > stats["dispatches"]
 
 
 def test_admission_waits_for_memory():
