@@ -190,6 +190,27 @@ bem_status bem_apply(bem_problem *p, const bem_complex *x, bem_complex *y, int32
  * Available in every mode (it runs on the far-field pair path). */
 bem_status bem_apply_single_layer(bem_problem *p, const bem_complex *x, bem_complex *y, int32_t n_rhs);
 
+/* bem_apply without any device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same operator, kernels and summation order as bem_apply, so the
+ * result is bitwise the same.  Only for on-the-fly problems assembled with
+ * BEM_DEVICE_PTRS: x and y are device arrays [n_rhs][n_unknowns] (not
+ * overlapping), work is ordered on the problem's stream and the call returns
+ * after enqueueing it.  The apply's scratch (trial records, pair-kernel partial
+ * sums, point potentials: 16 (2 M + 3 T) + 80 (2 S + 1) M bytes, M = 6 T
+ * quadrature points, T triangles, S the pair kernel's trial splits, each part
+ * rounded up to 256 bytes) lives in a file-scope device array of
+ * BEM_NOALLOC_SCRATCH_BYTES (256 MiB) that every GPU the library runs on holds
+ * until the process ends; a problem needing more is rejected with
+ * BEM_ERR_UNSUPPORTED (the 10,242-vertex sphere needs about 172 MB).  All
+ * calls on one GPU share that array and it keeps the last call's contents
+ * (the partial sums are cleared by a kernel on every call): calls that overlap
+ * in time on one GPU (other streams or threads) race; calls on one stream are
+ * ordered.  Errors: BEM_ERR_INVALID_ARG (null pointers, n_rhs < 0, assembled
+ * mode, host vectors), BEM_ERR_UNSUPPORTED, BEM_ERR_DEVICE. */
+#define BEM_NOALLOC_SCRATCH_BYTES (256ull << 20)
+bem_status bem_apply_noalloc(bem_problem *p, const bem_complex *x, bem_complex *y, int32_t n_rhs);
+
 /* bem_apply restricted to parts of the operator (parts: 1 = far field
  * (regular rule on every pair), 2 = singular correction; 3 = both). */
 bem_status bem_apply_parts(bem_problem *p, const bem_complex *x, bem_complex *y, int32_t n_rhs, int parts);

@@ -89,6 +89,7 @@ _L.bem_assemble.argtypes = [ctypes.POINTER(bem_domain), ctypes.c_int32, bem_comp
                             ctypes.POINTER(bem_assemble_opts), ctypes.POINTER(_vp)]
 _L.bem_apply.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
 _L.bem_apply_parts.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int]
+_L.bem_apply_noalloc.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
 _L.bem_apply_with.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int]
 _L.bem_apply_single_layer.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
 _L.bem_hmatrix_build.argtypes = [_vp, ctypes.c_double, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(bem_hmatrix_info)]
@@ -115,14 +116,14 @@ _L.bem_pair_launch_shape.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32)]
 _L.bem_destroy.argtypes = [_vp]
 _L.bem_destroy.restype = None
 _L.bem_last_error.restype = ctypes.c_char_p
-for _f in ("bem_assemble", "bem_apply", "bem_apply_parts", "bem_apply_with", "bem_apply_single_layer",
+for _f in ("bem_assemble", "bem_apply", "bem_apply_noalloc", "bem_apply_parts", "bem_apply_with", "bem_apply_single_layer",
            "bem_hmatrix_build", "bem_hmatrix_plan", "bem_rhs", "bem_solve", "bem_solve_rhs",
            "bem_apply_preconditioner", "bem_pair_launch_shape",
            "bem_evaluate_field", "bem_footprint_bytes", "bem_last_timings", "bem_batch_create", "bem_batch_attach",
            "bem_batch_stats"):
     getattr(_L, _f).restype = ctypes.c_int
 
-EXPORTED = ["bem_assemble", "bem_apply", "bem_apply_parts", "bem_apply_with", "bem_apply_single_layer",
+EXPORTED = ["bem_assemble", "bem_apply", "bem_apply_noalloc", "bem_apply_parts", "bem_apply_with", "bem_apply_single_layer",
             "bem_hmatrix_build", "bem_hmatrix_plan", "bem_rhs", "bem_solve", "bem_solve_rhs",
             "bem_apply_preconditioner", "bem_pair_launch_shape",
             "bem_evaluate_field", "bem_num_unknowns", "bem_footprint_bytes", "bem_last_timings",
@@ -325,6 +326,18 @@ class Problem:
             _check(_L.bem_apply_parts(self._h, xp, yp, n_rhs, parts))
         else:
             _check(_L.bem_apply_with(self._h, xp, yp, n_rhs, kernel))
+        return y
+
+    def apply_noalloc(self, x, out=None):
+        """y = A x through ``bem_apply_noalloc`` (device problems on the fly: the
+        apply's scratch is the library's file-scope device array, nothing is
+        allocated by the call)."""
+        if not self.device:
+            raise TypeError("bem_apply_noalloc takes device vectors: create the problem with device=True")
+        import torch
+        x, n_rhs = self._dev_in(x)
+        y = torch.empty_like(x) if out is None else out
+        _check(_L.bem_apply_noalloc(self._h, x.data_ptr(), y.data_ptr(), n_rhs))
         return y
 
     def apply_single_layer(self, x, out=None):

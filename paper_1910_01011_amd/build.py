@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbem_mi355x.so")
-SOURCES = ["bem_api.cpp", "mesh.cpp", "krylov.cpp", "autotune.cpp", "k_farfield.hip", "k_singular.hip", "k_linalg.hip", "k_field.hip", "k_dense.hip", "k_gemm.hip", "k_osrc.hip", "k_single_layer.hip", "hmatrix.cpp", "k_hmatrix.hip", "serving.cpp"]
+SOURCES = ["bem_api.cpp", "mesh.cpp", "krylov.cpp", "autotune.cpp", "k_farfield.hip", "k_singular.hip", "k_linalg.hip", "k_field.hip", "k_dense.hip", "k_gemm.hip", "k_osrc.hip", "k_single_layer.hip", "hmatrix.cpp", "k_hmatrix.hip", "noalloc.hip", "serving.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

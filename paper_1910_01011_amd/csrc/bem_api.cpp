@@ -575,6 +575,45 @@ bem_status bem_apply(bem_problem *p, const bem_complex *x, bem_complex *y, int32
     return bem_apply_parts(p, x, y, n_rhs, 3);
 }
 
+bem_status bem_apply_noalloc(bem_problem *p, const bem_complex *x, bem_complex *y, int32_t n_rhs)
+{
+    if (!p || !x || !y || n_rhs < 0) return fail(BEM_ERR_INVALID_ARG, "bem_apply_noalloc: bad arguments");
+    if (p->mode != BEM_OTF) return fail(BEM_ERR_INVALID_ARG, "bem_apply_noalloc: on-the-fly problems only");
+    if (!(p->flags & BEM_DEVICE_PTRS))
+        return fail(BEM_ERR_INVALID_ARG, "bem_apply_noalloc: needs device vectors (assemble with BEM_DEVICE_PTRS)");
+    // scratch layout: trial records, pair-kernel partial sums, point potentials
+    const auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t trial_b = up(sizeof(float4) * size_t(2 * p->M + 3 * p->NT));
+    const size_t part_b = up(sizeof(double) * size_t(2) * p->n_split * 10 * size_t(p->M));
+    const size_t pot_b = up(sizeof(double) * size_t(10) * p->M);
+    if (trial_b + part_b + pot_b > bem::NOALLOC_SCRATCH_BYTES)
+        return fail(BEM_ERR_UNSUPPORTED, "bem_apply_noalloc: the problem needs " + std::to_string(trial_b + part_b + pot_b) +
+                                             " bytes of scratch, more than the " +
+                                             std::to_string(bem::NOALLOC_SCRATCH_BYTES) + " available");
+    if (n_rhs == 0) return BEM_OK;
+    return guarded([&]() -> bem_status {
+        BEM_HIP(hipSetDevice(p->device));
+        bem::AllocScope alloc_scope(p->stream);
+        char *base = static_cast<char *>(bem::noalloc_scratch(p->device));
+        float4 *trial = reinterpret_cast<float4 *>(base);
+        double *part = reinterpret_cast<double *>(base + trial_b);
+        double *pot = reinterpret_cast<double *>(base + trial_b + part_b);
+        // the array keeps the previous call's contents: clear the partial sums
+        bem::launch_zero_f64(p->stream, part, int64_t(2) * p->n_split * 10 * p->M);
+        struct Swap {
+            bem_problem &q;
+            float4 *t;
+            double *a, *b;
+            ~Swap() { q.d_trial = t; q.d_part = a; q.d_pot = b; }
+        } restore{*p, p->d_trial, p->d_part, p->d_pot};
+        p->d_trial = trial;
+        p->d_part = part;
+        p->d_pot = pot;
+        apply_device(*p, reinterpret_cast<const double2 *>(x), reinterpret_cast<double2 *>(y), n_rhs, 3, false);
+        return BEM_OK;
+    });
+}
+
 bem_status bem_apply_with(bem_problem *p, const bem_complex *x, bem_complex *y, int32_t n_rhs, int kernel)
 {
     if (!p || !x || !y || n_rhs < 0) return fail(BEM_ERR_INVALID_ARG, "bem_apply_with: bad arguments");

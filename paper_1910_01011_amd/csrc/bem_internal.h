@@ -376,6 +376,13 @@ struct KrylovOpts {
 void gmres_batch(bem_problem &p, int64_t n, int R, const double2 *B, double2 *X, const KrylovOpts &o,
                  const ApplyFn &A, const ApplyFn *M, bem_solve_info *info);
 
+// allocation-free apply (noalloc.hip): the file-scope scratch array of this
+// many bytes; its device address on `device` (which must be current; looked up
+// on first use), and a fill kernel that clears FP64 words
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(256) << 20;
+void *noalloc_scratch(int device);
+void launch_zero_f64(hipStream_t s, double *p, int64_t n);
+
 // continuous batching (serving.cpp): kinds of operator apply a problem hands
 // to its batch, the hand-over (returns once the apply is launched and the
 // problem's stream waits for it), and the count of problems inside a solve
