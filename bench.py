@@ -12,9 +12,10 @@ region.
 Also on the line: the GMRES time-to-solve of the stack's 256-piston field to a
 true (unpreconditioned, on-the-fly operator) relative residual of 1e-5, the
 roofline of the pair kernel (HIP events on the library's stream), the FP64 CPU
-oracle timed on a bounded sample of rows on this host, and, as a sub-object,
+oracle timed on a bounded sample of rows on this host, and, as sub-objects,
 the 10,242-vertex sphere (apply, solves with and without OSRC, assembled
-GEMV/GEMM paths).
+GEMV/GEMM paths) and a bounded kidney serving run (request latency p50/p99,
+solves/s, continuous batching).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-solve] [--no-sphere]
 """
@@ -111,12 +112,15 @@ def profile_fields(name, source="k_farfield.hip"):
         return None
 
 
-def recorded_traffic(name):
-    """HBM bytes per k_pairs launch from a committed counter summary, or None."""
+def recorded_traffic(name, launch_shape):
+    """HBM bytes per k_pairs launch from a committed counter summary, or None
+    (source changed, or the summary was taken at another launch shape: the
+    partial sums written grow with the trial splits)."""
     f = profile_fields(name)
     try:
-        return float(f["HBM bytes per launch"]) if f else None
-    except (KeyError, ValueError):
+        key = "HBM bytes per launch ({} {})".format(*launch_shape)
+        return float(f[key]) if f and key in f else None
+    except (KeyError, ValueError, IndexError):
         return None
 
 
@@ -148,11 +152,11 @@ def time_applies(P, x, y, steps, warmup, torch):
     return time.perf_counter() - t0, step_ms, pair_ms
 
 
-def pair_roofline(pairs, pair_ms, traffic_profile, valu_profile):
+def pair_roofline(pairs, pair_ms, traffic_profile, valu_profile, launch_shape):
     k_ms = float(np.mean(pair_ms))
     achieved = FLOP_PER_PAIR * pairs / (k_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP32_PEAK_TFLOPS, "traffic": recorded_traffic(traffic_profile),
+            "frac": achieved / FP32_PEAK_TFLOPS, "traffic": recorded_traffic(traffic_profile, launch_shape),
             "kernel": "k_pairs", "kernel_ms": k_ms, "flop_per_pair": FLOP_PER_PAIR, "achieved_kind": ACHIEVED_KIND}
     ex = recorded_executed_flop(valu_profile)
     if ex is not None:
@@ -162,6 +166,21 @@ def pair_roofline(pairs, pair_ms, traffic_profile, valu_profile):
     else:
         roof["executed"] = None
     return roof
+
+
+def osrc_apply_ms(P, prob, bem, torch, n_pade, r_eps, cg_tol=1e-6, reps=5):
+    """Median wall time of one OSRC preconditioner apply (one residual vector,
+    inner COCG to cg_tol: the tolerance a GMRES solve to 1e-5 gives them)."""
+    from bem_inputs import vectors
+    y = torch.from_numpy(vectors.random_complex(prob.n_unknowns, seed=5)).cuda()
+    opts = bem.solve_options(precond=bem.BEM_PRECOND_OSRC, n_pade=n_pade, r_eps=r_eps, theta=np.pi / 3,
+                             osrc_tol=cg_tol)
+    P.precondition(y, opts)
+    ts = []
+    for _ in range(reps):
+        _, t = _timed(torch, lambda: P.precondition(y, opts))
+        ts.append(1e3 * t)
+    return {"apply_ms": float(np.median(ts)), "n_pade": n_pade, "r_eps": r_eps, "cocg_tol": cg_tol}
 
 
 def ribcage_time_to_solve(P, prob, bem, torch):
@@ -199,6 +218,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-sphere", action="store_true", help="skip the 10,242-vertex sphere sub-object")
+    ap.add_argument("--no-serving", action="store_true", help="skip the bounded kidney serving sub-object")
     ap.add_argument("--no-assembled", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the heuristic launch shapes")
     ap.add_argument("--extra", default="",
@@ -209,10 +229,14 @@ def main():
                          "of 256 pistons on the 13.5k-vertex stack, then phase conjugation and rib sparing), hmatrix "
                          "(ACA-compressed operator on the sphere and the 53.5k-vertex stack)")
     ap.add_argument("--serving-requests", type=int, default=8, help="requests per arrival rate in --extra serving")
+    ap.add_argument("--serving-rates", default="2,10", help="comma list of arrival rates (1/s) of --extra serving")
+    ap.add_argument("--serving-inflight", type=int, default=4, help="requests in flight at most in --extra serving")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only a 1 GiB elementwise copy (the counter scale) and 3 applies, for counter runs")
     ap.add_argument("--probe-workload", default="ribcage", choices=("ribcage", "sphere"),
-                    help="workload of --traffic-probe")
+                    help="workload of --traffic-probe and --osrc-probe")
+    ap.add_argument("--osrc-probe", action="store_true",
+                    help="run only five OSRC preconditioner applies of the probe workload (for kernel traces)")
     ap.add_argument("--assembled-kernels-only", action="store_true",
                     help="assembled section without its solves (GEMV and GEMM launches only, for counter runs)")
     args = ap.parse_args()
@@ -227,6 +251,13 @@ def main():
     from bem_inputs import configs, vectors
 
     torch.cuda.set_device(0)
+    if args.osrc_probe:
+        rib = args.probe_workload == "ribcage"
+        prob = configs.ribcage(1.0) if rib else configs.config2()
+        P = bem.Problem.from_config(prob, device=True, autotune=False)
+        res = osrc_apply_ms(P, prob, bem, torch, 8 if rib else 4, 1.5 if rib else 0.1)
+        print(json.dumps({"workload": prob.name, "osrc": res}), flush=True)
+        return
     if args.traffic_probe:
         prob = configs.ribcage(1.0) if args.probe_workload == "ribcage" else configs.config2()
         P = bem.Problem.from_config(prob, device=True, autotune=not args.no_autotune)
@@ -264,9 +295,11 @@ def main():
                    "apply_ms_p50": float(np.percentile(step_ms, 50)),
                    "apply_ms_p99": float(np.percentile(step_ms, 99))},
         "roofline": pair_roofline(pairs, pair_ms, "k_pairs_ribcage53524_hbm_traffic.md",
-                                  "k_pairs_ribcage53524_valu.md"),
+                                  "k_pairs_ribcage53524_valu.md", P.pair_launch_shape()),
     }
     if not args.no_solve:
+        out["osrc"] = osrc_apply_ms(P, prob, bem, torch, 8, 1.5)
+        log(f"ribcage OSRC apply {out['osrc']['apply_ms']:.1f} ms")
         out["time_to_solve"] = ribcage_time_to_solve(P, prob, bem, torch)
     P.close()
     P = None
@@ -283,7 +316,9 @@ def main():
         elif e == "ribcage_assembled":
             out["ribcage_assembled"] = ribcage_assembled_section(bem, torch, not args.no_autotune)
         elif e == "serving":
-            out["serving"] = serving_section(bem, torch, args.serving_requests)
+            out["serving"] = serving_section(bem, torch, args.serving_requests,
+                                             tuple(float(r) for r in args.serving_rates.split(",") if r),
+                                             args.serving_inflight)
         elif e == "paper_sphere":
             out["paper_sphere"] = paper_sphere_section(bem, torch)
         elif e == "planning":
@@ -293,6 +328,11 @@ def main():
         else:
             raise SystemExit(f"unknown extra workload {e}")
         torch.cuda.empty_cache()
+    if not args.no_serving and "serving" not in extras:
+        # a bounded serving run: 8 kidney requests arriving at 1/s, at most 4 in
+        # flight, continuous batching (request latency p50/p99, solves/s)
+        log("serving (bounded)")
+        out["serving"] = serving_section(bem, torch, 8, (1.0,), 4)
     if not args.no_solve and not args.no_sphere:
         out["config1"] = config1_section(bem, torch, oracle_leg=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
@@ -319,7 +359,8 @@ def sphere_section(args, bem, torch):
            "ms_per_step": 1e3 * wall / args.steps, "pairs_per_apply": pairs, "unknowns": prob.n_unknowns,
            "setup_s": t_setup, "pair_launch_shape": list(P.pair_launch_shape()),
            "apply_ms_p50": float(np.percentile(step_ms, 50)), "apply_ms_p99": float(np.percentile(step_ms, 99)),
-           "roofline": pair_roofline(pairs, pair_ms, "k_pairs_sphere10242_hbm_traffic.md", "k_pairs_sphere10242_valu.md")}
+           "roofline": pair_roofline(pairs, pair_ms, "k_pairs_sphere10242_hbm_traffic.md", "k_pairs_sphere10242_valu.md",
+                                     P.pair_launch_shape())}
     log(f"sphere apply {out['ms_per_step']:.2f} ms")
     out["single_layer"] = single_layer_section(P, prob, torch, args.steps, args.warmup)
     if not args.no_solve:
@@ -339,6 +380,7 @@ def sphere_section(args, bem, torch):
                                             "rel_residual": info[0]["rel_residual"],
                                             "converged": info[0]["converged"]}
         out["gmres"] = g
+        out["osrc"] = osrc_apply_ms(P, prob, bem, torch, 4, 0.1)
     P.close()
     P = None
     torch.cuda.empty_cache()
@@ -602,23 +644,30 @@ def hmatrix_section(bem, torch, autotune):
     return out
 
 
-def serving_section(bem, torch, n_requests):
-    """Kidney + fat-shell request stream: Poisson arrivals at two rates, 2k-40k
-    vertices, 1-64 pistons per request; p50/p99 latency and solves/s."""
+def serving_section(bem, torch, n_requests, rates=(2.0, 10.0), max_inflight=4):
+    """Kidney + fat-shell request stream: Poisson arrivals at each rate, 2k-40k
+    vertices, 1-64 pistons per request, continuous batching of the requests in
+    flight; p50/p99 latency (arrival to result on the host), solves/s and the
+    batch's launch statistics."""
     from bem_inputs import configs
     from paper_1910_01011_amd import serving
     free, _ = torch.cuda.mem_get_info()
     out = {}
-    for rate in (2.0, 10.0):
-        items = configs.serving_stream(rate, n_requests, 5000 + int(rate), 6000 + int(rate))
+    for rate in rates:
+        items = configs.serving_stream(rate, n_requests, 5000 + int(round(100 * rate)),
+                                       6000 + int(round(100 * rate)))
         reqs = serving.requests_from_stream(items, free)
-        res = serving.Server(max_inflight=4).run(reqs)
+        srv = serving.Server(max_inflight=max_inflight)
+        res = srv.run(reqs)
         summ = serving.summarize(res)
+        summ["batch"] = srv.last_batch_stats
         summ["vertices"] = [int(sum(d.n_vertices for d in r.domains)) for r in reqs]
         summ["modes"] = [int(r.mode) for r in reqs]
         summ["rhs_per_request"] = [int(r.incident.n_fields) for r in reqs]
+        summ["max_inflight"] = max_inflight
         out[f"rate_{rate:g}_per_s"] = summ
-        log(f"serving rate {rate}: p50 {summ['p50_latency_s']:.2f} s p99 {summ['p99_latency_s']:.2f} s")
+        log(f"serving rate {rate}: p50 {summ['p50_latency_s']:.2f} s p99 {summ['p99_latency_s']:.2f} s, "
+            f"{summ['requests_per_s']:.2f} requests/s, batch {srv.last_batch_stats}")
     return out
 
 

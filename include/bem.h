@@ -151,11 +151,11 @@ typedef struct {
     int inner_restart;   /* inner GMRES restart length (0: 30) */
     int inner_max_iter;  /* inner iteration cap per outer step (0: 300) */
     double osrc_tol;     /* relative residual of the OSRC inner sparse solves (COCG).  0: inside
-                            bem_solve one tenth of the tolerance GMRES works to (tol, or inner_tol
-                            for the flexible forms), within [1e-10, 1e-6]; in
-                            bem_apply_preconditioner 1e-10.  A looser value makes each
-                            preconditioner apply cheaper and slightly less exact; the solvers'
-                            stopping tests are unchanged */
+                            bem_solve one tenth of the tolerance of the GMRES it preconditions
+                            (tol for the plain forms, inner_tol for the flexible forms' inner
+                            solves), within [1e-10, 1e-4]; in bem_apply_preconditioner 1e-10.
+                            A looser value makes each preconditioner apply cheaper and slightly
+                            less exact; the solvers' stopping tests are unchanged */
 } bem_solve_opts;
 
 typedef struct {
@@ -320,7 +320,8 @@ bem_status bem_hmatrix_plan(const bem_domain *domains, int32_t n_domains, int32_
  * attached to a batch hands every operator apply of its solves (bem_solve,
  * bem_solve_rhs) to the batch's dispatcher thread, which gathers the applies
  * submitted by the requests in flight (until every attached problem inside a
- * solve has submitted one, or for at most 0.3 ms) and launches them together
+ * solve has submitted one, or for at most a window, 0.3 ms by default) and
+ * launches them together
  * on the batch's own stream: the pair kernels of all on-the-fly problems of
  * one kernel variant as one grouped launch over their concatenated work lists
  * (up to 16 problems), then each problem's gathers, reductions, projections,
@@ -331,6 +332,10 @@ bem_status bem_hmatrix_plan(const bem_domain *domains, int32_t n_domains, int32_
  * bem_batch_create: a batch on `device` (its stream has the default priority).
  * bem_batch_attach: route p's solves through b (NULL: launch them directly
  * again); p and b on the same device; not while p is inside a solve.
+ * bem_batch_set_window: the longest the dispatcher waits for the other
+ * requests in a solve once one apply is pending (default 0.3 ms; 0 launches
+ * at once; a long window makes the steps of all requests in a solve go in
+ * lockstep, every dispatch holding one apply of each), 0 <= seconds <= 10.
  * bem_batch_stats: out6 = {dispatches, applies, grouped pair launches, of
  * them with several problems, most problems in one launch, pair work items}.
  * bem_batch_destroy: stops the dispatcher; destroy or detach every attached
@@ -338,6 +343,7 @@ bem_status bem_hmatrix_plan(const bem_domain *domains, int32_t n_domains, int32_
 typedef struct bem_batch bem_batch;
 bem_status bem_batch_create(int device, bem_batch **out);
 bem_status bem_batch_attach(bem_problem *p, bem_batch *b);
+bem_status bem_batch_set_window(bem_batch *b, double seconds);
 bem_status bem_batch_stats(bem_batch *b, int64_t *out6);
 void bem_batch_destroy(bem_batch *b);
 

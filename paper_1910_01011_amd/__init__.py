@@ -105,6 +105,7 @@ _L.bem_evaluate_field.argtypes = [_vp, _vp, ctypes.POINTER(bem_incident), _vp, c
 _L.bem_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(_vp)]
 _L.bem_batch_attach.argtypes = [_vp, _vp]
 _L.bem_batch_stats.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
+_L.bem_batch_set_window.argtypes = [_vp, ctypes.c_double]
 _L.bem_batch_destroy.argtypes = [_vp]
 _L.bem_batch_destroy.restype = None
 _L.bem_num_unknowns.argtypes = [_vp]
@@ -120,14 +121,14 @@ for _f in ("bem_assemble", "bem_apply", "bem_apply_noalloc", "bem_apply_parts", 
            "bem_hmatrix_build", "bem_hmatrix_plan", "bem_rhs", "bem_solve", "bem_solve_rhs",
            "bem_apply_preconditioner", "bem_pair_launch_shape",
            "bem_evaluate_field", "bem_footprint_bytes", "bem_last_timings", "bem_batch_create", "bem_batch_attach",
-           "bem_batch_stats"):
+           "bem_batch_stats", "bem_batch_set_window"):
     getattr(_L, _f).restype = ctypes.c_int
 
 EXPORTED = ["bem_assemble", "bem_apply", "bem_apply_noalloc", "bem_apply_parts", "bem_apply_with", "bem_apply_single_layer",
             "bem_hmatrix_build", "bem_hmatrix_plan", "bem_rhs", "bem_solve", "bem_solve_rhs",
             "bem_apply_preconditioner", "bem_pair_launch_shape",
             "bem_evaluate_field", "bem_num_unknowns", "bem_footprint_bytes", "bem_last_timings",
-            "bem_batch_create", "bem_batch_attach", "bem_batch_stats", "bem_batch_destroy",
+            "bem_batch_create", "bem_batch_attach", "bem_batch_set_window", "bem_batch_stats", "bem_batch_destroy",
             "bem_destroy", "bem_last_error"]
 
 
@@ -235,6 +236,9 @@ class Batch:
 
     def attach(self, problem):
         _check(_L.bem_batch_attach(problem._h, self._h))
+
+    def set_window(self, seconds):
+        _check(_L.bem_batch_set_window(self._h, float(seconds)))
 
     def stats(self):
         out = (ctypes.c_int64 * 6)()

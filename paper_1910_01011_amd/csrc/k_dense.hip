@@ -14,18 +14,9 @@
 #include <vector>
 
 #include "bem_internal.h"
+#include "rule6.h"
 
 namespace bem {
-
-__constant__ double d_bary[6][3] = {
-    {0.10810301816807022736, 0.44594849091596488632, 0.44594849091596488632},
-    {0.44594849091596488632, 0.10810301816807022736, 0.44594849091596488632},
-    {0.44594849091596488632, 0.44594849091596488632, 0.10810301816807022736},
-    {0.81684757298045851308, 0.091576213509770743460, 0.091576213509770743460},
-    {0.091576213509770743460, 0.81684757298045851308, 0.091576213509770743460},
-    {0.091576213509770743460, 0.091576213509770743460, 0.81684757298045851308}};
-__constant__ double d_wq[6] = {0.22338158967801146570, 0.22338158967801146570, 0.22338158967801146570,
-                               0.10995174365532186764, 0.10995174365532186764, 0.10995174365532186764};
 
 // Per (vertex, incident triangle corner, point) record, 3 x float4:
 //   r0 = (x, w lambda_a(x) / (4 pi))   r1 = (n, w / (4 pi))   r2 = (curl lambda_a, 0)
@@ -42,8 +33,8 @@ __global__ void k_vertex_points(const int32_t *__restrict__ v2t, int64_t n_corne
     const int64_t t = tc / 3;
     const int a = tc - 3 * int(t);
     const int64_t i = 6 * t + q;
-    const double w = area[t] * d_wq[q] * 0.079577471545947667884;
-    rec[3 * k] = make_float4(pts[i], pts[M + i], pts[2 * M + i], float(w * d_bary[q][a]));
+    const double w = area[t] * q6_w[q] * 0.079577471545947667884;
+    rec[3 * k] = make_float4(pts[i], pts[M + i], pts[2 * M + i], float(w * q6_bary[q][a]));
     rec[3 * k + 1] = make_float4(float(normal[3 * t]), float(normal[3 * t + 1]), float(normal[3 * t + 2]), float(w));
     rec[3 * k + 2] = make_float4(float(curl[9 * t + 3 * a]), float(curl[9 * t + 3 * a + 1]),
                                  float(curl[9 * t + 3 * a + 2]), 0.0f);

@@ -14,19 +14,9 @@
 // with sV = sW = 1 for the exterior pass and sV = rho_j/rho_0, sW = rho_0/rho_j
 // for the interior pass of domain j (eq. Form1_calderon_sys_int_ptot).
 #include "bem_internal.h"
+#include "rule6.h"
 
 namespace bem {
-
-// 6-point degree-4 rule: barycentric coordinates and weights (weights sum to 1).
-__constant__ double c_bary[6][3] = {
-    {0.10810301816807022736, 0.44594849091596488632, 0.44594849091596488632},
-    {0.44594849091596488632, 0.10810301816807022736, 0.44594849091596488632},
-    {0.44594849091596488632, 0.44594849091596488632, 0.10810301816807022736},
-    {0.81684757298045851308, 0.091576213509770743460, 0.091576213509770743460},
-    {0.091576213509770743460, 0.81684757298045851308, 0.091576213509770743460},
-    {0.091576213509770743460, 0.091576213509770743460, 0.81684757298045851308}};
-__constant__ double c_wq[6] = {0.22338158967801146570, 0.22338158967801146570, 0.22338158967801146570,
-                               0.10995174365532186764, 0.10995174365532186764, 0.10995174365532186764};
 
 constexpr int PAIR_BLOCK = 256;   // threads (test points per TPL) of a pair-kernel workgroup
 constexpr double INV4PI = 0.079577471545947667884;
@@ -61,7 +51,7 @@ __global__ void k_geometry(const double *__restrict__ verts, const int32_t *__re
         for (int d = 0; d < 3; ++d) curl[9 * t + 3 * a + d] = -(P[(a + 2) % 3][d] - P[(a + 1) % 3][d]) / twice;
     for (int q = 0; q < 6; ++q)
         for (int d = 0; d < 3; ++d) {
-            const double x = c_bary[q][0] * P[0][d] + c_bary[q][1] * P[1][d] + c_bary[q][2] * P[2][d];
+            const double x = q6_bary[q][0] * P[0][d] + q6_bary[q][1] * P[1][d] + q6_bary[q][2] * P[2][d];
             pts[d * M + 6 * t + q] = float(x);
         }
 }
@@ -99,7 +89,7 @@ __global__ void k_gather(const double2 *__restrict__ x, const int32_t *__restric
         const int32_t g = tris[3 * t + a];
         const double2 xd = x[rowD[g]];
         const double2 xn = x[rowN[g]];
-        const double l = c_bary[q][a];
+        const double l = q6_bary[q][a];
         uDr += l * xd.x; uDi += l * xd.y;
         uNr += l * xn.x; uNi += l * xn.y;
         if (q == 0)
@@ -109,7 +99,7 @@ __global__ void k_gather(const double2 *__restrict__ x, const int32_t *__restric
                 ci[d] += c * xd.y;
             }
     }
-    const double A = area[t] * INV4PI, w = A * c_wq[q];
+    const double A = area[t] * INV4PI, w = A * q6_w[q];
     trial[2 * i] = make_float4(pts[i], pts[M + i], pts[2 * M + i], 0.0f);
     trial[2 * i + 1] = make_float4(float(uDr * w), float(uDi * w), float(uNr * w), float(uNi * w));
     if (q == 0) {
@@ -242,7 +232,7 @@ __device__ __forceinline__ void pairs_body(const int4 w, const PassDev *__restri
     const int tid = threadIdx.x;
     const float kv = in_vgpr(P.k), k2piv = in_vgpr(P.k_over_2pi), kimv = in_vgpr(P.kim);
     // the two weights of the 6-point rule (points 0-2 and 3-5)
-    const float wqa = in_vgpr(float(c_wq[0])), wqb = in_vgpr(float(c_wq[3]));
+    const float wqa = in_vgpr(float(q6_w[0])), wqb = in_vgpr(float(q6_w[3]));
     // pass constants of the per-tile combination: sV, sW and -k^2 sW
     const double sV = P.sV, sW = P.sW, cNr = -double(P.sW) * P.k2re, cNi = -double(P.sW) * P.k2im;
 
@@ -489,8 +479,8 @@ __global__ void k_scatter(const double *__restrict__ pot, const int32_t *__restr
             const double cx = curl[9 * t + 3 * a], cy = curl[9 * t + 3 * a + 1], cz = curl[9 * t + 3 * a + 2];
             for (int q = 0; q < 6; ++q) {
                 const double *P = pot + 10 * (6 * t + q);
-                const double w = ar * c_wq[q];
-                const double wl = w * c_bary[q][a];
+                const double w = ar * q6_w[q];
+                const double wl = w * q6_bary[q][a];
                 yDr += wl * P[0];
                 yDi += wl * P[1];
                 yNr += wl * P[2] + w * (cx * P[4] + cy * P[6] + cz * P[8]);

@@ -19,18 +19,9 @@
 #include <vector>
 
 #include "bem_internal.h"
+#include "rule6.h"
 
 namespace bem {
-
-__constant__ double f_bary[6][3] = {
-    {0.10810301816807022736, 0.44594849091596488632, 0.44594849091596488632},
-    {0.44594849091596488632, 0.10810301816807022736, 0.44594849091596488632},
-    {0.44594849091596488632, 0.44594849091596488632, 0.10810301816807022736},
-    {0.81684757298045851308, 0.091576213509770743460, 0.091576213509770743460},
-    {0.091576213509770743460, 0.81684757298045851308, 0.091576213509770743460},
-    {0.091576213509770743460, 0.091576213509770743460, 0.81684757298045851308}};
-__constant__ double f_wq[6] = {0.22338158967801146570, 0.22338158967801146570, 0.22338158967801146570,
-                               0.10995174365532186764, 0.10995174365532186764, 0.10995174365532186764};
 
 constexpr double PI_D = 3.14159265358979323846;
 
@@ -142,10 +133,10 @@ __global__ void k_rhs(IncDev I, const double *__restrict__ verts, const int32_t 
         const double *n = normal + 3 * t;
         for (int q = 0; q < 6; ++q) {
             double x[3];
-            for (int d = 0; d < 3; ++d) x[d] = f_bary[q][0] * P[0][d] + f_bary[q][1] * P[1][d] + f_bary[q][2] * P[2][d];
+            for (int d = 0; d < 3; ++d) x[d] = q6_bary[q][0] * P[0][d] + q6_bary[q][1] * P[1][d] + q6_bary[q][2] * P[2][d];
             double pr, pi, qr, qi;
             incident(I, f, x, n, pr, pi, qr, qi);
-            const double w = area[t] * f_wq[q] * f_bary[q][a];
+            const double w = area[t] * q6_w[q] * q6_bary[q][a];
             bDr += w * pr; bDi += w * pi;
             bNr += w * qr; bNi += w * qi;
         }
@@ -332,7 +323,7 @@ __global__ void k_field(IncDev I, int has_inc, const DomDev *__restrict__ doms, 
                 for (int q = 0; q < 6; ++q) {
                     double y[3];
                     for (int d = 0; d < 3; ++d)
-                        y[d] = f_bary[q][0] * P[0][d] + f_bary[q][1] * P[1][d] + f_bary[q][2] * P[2][d];
+                        y[d] = q6_bary[q][0] * P[0][d] + q6_bary[q][1] * P[1][d] + q6_bary[q][2] * P[2][d];
                     const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
                     const double r = sqrt(dx * dx + dy * dy + dz * dz);
                     double sn, cs;
@@ -344,10 +335,10 @@ __global__ void k_field(IncDev I, int has_inc, const DomDev *__restrict__ doms, 
                     const double fr = (gr * a1 - gi * b1) * dn, fi = (gr * b1 + gi * a1) * dn;   // dG/dn_y
                     double dr = 0, di = 0, nr = 0, ni = 0;
                     for (int c = 0; c < 3; ++c) {
-                        dr += f_bary[q][c] * uD[c].x; di += f_bary[q][c] * uD[c].y;
-                        nr += f_bary[q][c] * uN[c].x; ni += f_bary[q][c] * uN[c].y;
+                        dr += q6_bary[q][c] * uD[c].x; di += q6_bary[q][c] * uD[c].y;
+                        nr += q6_bary[q][c] * uN[c].x; ni += q6_bary[q][c] * uN[c].y;
                     }
-                    const double w = area[t] * f_wq[q];
+                    const double w = area[t] * q6_w[q];
                     pr += w * (sD * (fr * dr - fi * di) + sN * (gr * nr - gi * ni));
                     pim += w * (sD * (fr * di + fi * dr) + sN * (gr * ni + gi * nr));
                 }
@@ -400,7 +391,7 @@ __global__ void k_field_rows(const DomDev *__restrict__ doms, int n_dom, double 
         const double *n = normal + 3 * t;
         for (int q = 0; q < 6; ++q) {
             double y[3];
-            for (int d = 0; d < 3; ++d) y[d] = f_bary[q][0] * P[0][d] + f_bary[q][1] * P[1][d] + f_bary[q][2] * P[2][d];
+            for (int d = 0; d < 3; ++d) y[d] = q6_bary[q][0] * P[0][d] + q6_bary[q][1] * P[1][d] + q6_bary[q][2] * P[2][d];
             const double ex = x[0] - y[0], ey = x[1] - y[1], ez = x[2] - y[2];
             const double r = sqrt(ex * ex + ey * ey + ez * ez);
             double sn, cs;
@@ -410,7 +401,7 @@ __global__ void k_field_rows(const DomDev *__restrict__ doms, int n_dom, double 
             const double a1 = 1.0 + kim * r, b1 = -kre * r, ir2 = 1.0 / (r * r);
             const double dn = (ex * n[0] + ey * n[1] + ez * n[2]) * ir2;
             const double fr = (gr * a1 - gi * b1) * dn, fi = (gr * b1 + gi * a1) * dn;   // dG/dn_y
-            const double w = area[t] * f_wq[q] * f_bary[q][a];
+            const double w = area[t] * q6_w[q] * q6_bary[q][a];
             dr += w * fr; di += w * fi;
             nr += w * gr; ni += w * gi;
         }

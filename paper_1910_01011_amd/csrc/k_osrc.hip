@@ -19,6 +19,7 @@
 // matrices) in FP64, every (system, domain) block spread over workgroups of
 // 256 rows.
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <complex>
 #include <vector>
@@ -266,8 +267,8 @@ void osrc_setup(bem_problem &p)
 // the same decision and the result does not depend on scheduling.  A block's
 // flag `done` is written only by the last kernel of an iteration, which stops
 // on convergence before touching any vector, so workgroups that read the flag
-// early or late in that kernel act alike.  The host launches the iterations
-// and reads the flags every CG_CHECK iterations.
+// early or late in that kernel act alike.  The host replays a captured graph
+// of CG_CHECK iterations and reads the flags after each.
 constexpr int CG_CHECK = 8;
 
 // Fixed-order sum over the 256 threads of a workgroup: wave shuffles, then the
@@ -449,13 +450,15 @@ __global__ __launch_bounds__(CG_ROWS) void k_cg_update(CgArgs a, int parity)
         v[2] = nr.x * z.y + nr.y * z.x;
     }
     wg_sum<3>(v, red);
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         for (int k = 0; k < 3; ++k) a.part2[3 * (g * a.n_chunks + blockIdx.x) + k] = v[k];
+        if (blockIdx.x == unsigned(ch.first)) a.its[blk] += 1;   // read by the next kernel only
+    }
 }
 
-// convergence test of the block, else beta = rho_new / rho and p = z + beta p;
-// rho_new goes to the other parity slot
-__global__ __launch_bounds__(CG_ROWS) void k_cg_direction(CgArgs a, int parity, int it)
+// convergence test of the block (or its iteration cap), else beta = rho_new /
+// rho and p = z + beta p; rho_new goes to the other parity slot
+__global__ __launch_bounds__(CG_ROWS) void k_cg_direction(CgArgs a, int parity)
 {
     __shared__ double red[12];
     const int64_t g = blockIdx.y;
@@ -467,9 +470,8 @@ __global__ __launch_bounds__(CG_ROWS) void k_cg_direction(CgArgs a, int parity, 
     const int64_t nblk = a.n_dom * int64_t(gridDim.y);
     const double2 rho = a.rho[parity * nblk + blk];
     const double d2 = rho.x * rho.x + rho.y * rho.y;
-    const bool stop = v[0] <= a.tol * a.tol * a.bn2[blk] || d2 == 0.0 || it + 1 >= a.maxit;
+    const bool stop = v[0] <= a.tol * a.tol * a.bn2[blk] || d2 == 0.0 || a.its[blk] >= a.maxit;
     if (threadIdx.x == 0 && blockIdx.x == unsigned(ch.first)) {
-        a.its[blk] = it + 1;
         if (stop) a.done[blk] = 1;
         else a.rho[(1 - parity) * nblk + blk] = make_double2(v[1], v[2]);
     }
@@ -481,6 +483,39 @@ __global__ __launch_bounds__(CG_ROWS) void k_cg_direction(CgArgs a, int parity, 
         const double2 pp = a.P[k], z = a.Z[k];
         a.P[k] = make_double2(z.x + br * pp.x - bi * pp.y, z.y + br * pp.y + bi * pp.x);
     }
+}
+
+// Captures CG_CHECK iterations of the batched COCG on a capture stream of this
+// thread and device (so that the problem's stream, which may be the null
+// stream, is never in capture mode) and instantiates them.
+static hipGraphExec_t cg_chunk_graph(const CgArgs &a, dim3 grid, dim3 block)
+{
+    int dev = 0;
+    BEM_HIP(hipGetDevice(&dev));
+    thread_local std::vector<hipStream_t> cap(64, nullptr);
+    if (dev < 0 || dev >= int(cap.size())) throw Error{BEM_ERR_DEVICE, "OSRC: device ordinal out of range"};
+    if (!cap[dev]) BEM_HIP(hipStreamCreateWithFlags(&cap[dev], hipStreamNonBlocking));
+    hipStream_t cs = cap[dev];
+    BEM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < CG_CHECK; ++i) {
+        k_cg_spmv<<<grid, block, 0, cs>>>(a);
+        k_cg_update<<<grid, block, 0, cs>>>(a, i & 1);
+        k_cg_direction<<<grid, block, 0, cs>>>(a, i & 1);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e_launch = hipGetLastError();
+    const hipError_t e_end = hipStreamEndCapture(cs, &graph);
+    if (e_launch != hipSuccess || e_end != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        throw Error{BEM_ERR_DEVICE, std::string("OSRC: capture of the COCG iterations failed: ") +
+                                        hipGetErrorString(e_launch != hipSuccess ? e_launch : e_end)};
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e_inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e_inst != hipSuccess) throw Error{BEM_ERR_DEVICE, std::string("OSRC: graph instantiation failed: ") +
+                                                            hipGetErrorString(e_inst)};
+    return exec;
 }
 
 static void cocg_batch(bem_problem &p, int G, const std::vector<cd> &c, const double2 *B, double2 *X, double tol,
@@ -538,18 +573,37 @@ static void cocg_batch(bem_problem &p, int G, const std::vector<cd> &c, const do
     BEM_HIP(hipGetLastError());
     k_cg_init_block<<<grid, block, 0, s>>>(a);
     BEM_HIP(hipGetLastError());
-    std::vector<int32_t> done(size_t(G) * n_dom);
-    for (int it = 0; it < maxit; ++it) {
-        const int parity = it & 1;
-        k_cg_spmv<<<grid, block, 0, s>>>(a);
-        k_cg_update<<<grid, block, 0, s>>>(a, parity);
-        k_cg_direction<<<grid, block, 0, s>>>(a, parity, it);
-        BEM_HIP(hipGetLastError());
-        if ((it + 1) % CG_CHECK == 0 || it + 1 == maxit) {
-            BEM_HIP(hipMemcpyAsync(done.data(), a.done, done.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            BEM_HIP(hipStreamSynchronize(s));
-            if (std::all_of(done.begin(), done.end(), [](int32_t f) { return f != 0; })) break;
+    // CG_CHECK iterations (3 launches each) as one graph, replayed until every
+    // block is done: the launches of a chunk reach the GPU back to back instead
+    // of one host call each.  The graph holds kernel nodes only; the parity of
+    // node i is i & 1 and every chunk starts at an even iteration.
+    // BEM_COCG_EAGER=1 launches the same kernels one by one instead (the
+    // reference the graph replays are tested against)
+    const char *ev = std::getenv("BEM_COCG_EAGER");
+    const bool eager = ev && ev[0] == '1';
+    hipGraphExec_t exec = eager ? nullptr : cg_chunk_graph(a, grid, block);
+    struct ExecGuard {
+        hipGraphExec_t e;
+        ~ExecGuard()
+        {
+            if (e) (void)hipGraphExecDestroy(e);
         }
+    } exec_guard{exec};
+    std::vector<int32_t> done(size_t(G) * n_dom);
+    for (int it = 0; it < maxit; it += CG_CHECK) {
+        if (eager) {
+            for (int i = 0; i < CG_CHECK; ++i) {
+                k_cg_spmv<<<grid, block, 0, s>>>(a);
+                k_cg_update<<<grid, block, 0, s>>>(a, i & 1);
+                k_cg_direction<<<grid, block, 0, s>>>(a, i & 1);
+            }
+            BEM_HIP(hipGetLastError());
+        } else {
+            BEM_HIP(hipGraphLaunch(exec, s));
+        }
+        BEM_HIP(hipMemcpyAsync(done.data(), a.done, done.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        BEM_HIP(hipStreamSynchronize(s));
+        if (std::all_of(done.begin(), done.end(), [](int32_t f) { return f != 0; })) break;
     }
 }
 

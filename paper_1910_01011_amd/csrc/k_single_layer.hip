@@ -16,18 +16,9 @@
 #include <algorithm>
 
 #include "bem_internal.h"
+#include "rule6.h"
 
 namespace bem {
-
-__constant__ double v_bary[6][3] = {
-    {0.10810301816807022736, 0.44594849091596488632, 0.44594849091596488632},
-    {0.44594849091596488632, 0.10810301816807022736, 0.44594849091596488632},
-    {0.44594849091596488632, 0.44594849091596488632, 0.10810301816807022736},
-    {0.81684757298045851308, 0.091576213509770743460, 0.091576213509770743460},
-    {0.091576213509770743460, 0.81684757298045851308, 0.091576213509770743460},
-    {0.091576213509770743460, 0.091576213509770743460, 0.81684757298045851308}};
-__constant__ double v_wq[6] = {0.22338158967801146570, 0.22338158967801146570, 0.22338158967801146570,
-                               0.10995174365532186764, 0.10995174365532186764, 0.10995174365532186764};
 
 constexpr int SL_BLOCK = 256;   // threads of the pair kernel = trial tile (same as the fused kernel)
 constexpr double SL_INV4PI = 0.079577471545947667884;
@@ -45,10 +36,10 @@ __global__ void k_gather_v(const double2 *__restrict__ x, const int32_t *__restr
     double pr = 0, pi = 0;
     for (int a = 0; a < 3; ++a) {
         const double2 v = x[tris[3 * t + a]];
-        pr += v_bary[q][a] * v.x;
-        pi += v_bary[q][a] * v.y;
+        pr += q6_bary[q][a] * v.x;
+        pi += q6_bary[q][a] * v.y;
     }
-    const double w = area[t] * v_wq[q] * SL_INV4PI;
+    const double w = area[t] * q6_w[q] * SL_INV4PI;
     rec[i] = make_float4(pts[i], pts[M + i], pts[2 * M + i], float(pr * w));
     im[i] = float(pi * w);
 }
@@ -169,7 +160,7 @@ __global__ void k_scatter_v(const double2 *__restrict__ pot, const int32_t *__re
         const double ar = area[t];
         for (int q = 0; q < 6; ++q) {
             const double2 P = pot[6 * t + q];
-            const double wl = ar * v_wq[q] * v_bary[q][a];
+            const double wl = ar * q6_w[q] * q6_bary[q][a];
             yr += wl * P.x;
             yi += wl * P.y;
         }

@@ -10,18 +10,9 @@
 #include <algorithm>
 
 #include "bem_internal.h"
+#include "rule6.h"
 
 namespace bem {
-
-__constant__ double s_bary[6][3] = {
-    {0.10810301816807022736, 0.44594849091596488632, 0.44594849091596488632},
-    {0.44594849091596488632, 0.10810301816807022736, 0.44594849091596488632},
-    {0.44594849091596488632, 0.44594849091596488632, 0.10810301816807022736},
-    {0.81684757298045851308, 0.091576213509770743460, 0.091576213509770743460},
-    {0.091576213509770743460, 0.81684757298045851308, 0.091576213509770743460},
-    {0.091576213509770743460, 0.091576213509770743460, 0.81684757298045851308}};
-__constant__ double s_wq[6] = {0.22338158967801146570, 0.22338158967801146570, 0.22338158967801146570,
-                               0.10995174365532186764, 0.10995174365532186764, 0.10995174365532186764};
 
 struct SAcc {
     double vr[9], vi[9], kr[9], ki[9], pr[9], pi[9];
@@ -126,12 +117,12 @@ __global__ __launch_bounds__(64) void k_singular(const SingularItem *__restrict_
     // minus the regular 6 x 6 rule (original vertex order)
     for (int q = 0; q < 6; ++q) {
         double x[3];
-        for (int d = 0; d < 3; ++d) x[d] = s_bary[q][0] * Pt[0][d] + s_bary[q][1] * Pt[1][d] + s_bary[q][2] * Pt[2][d];
+        for (int d = 0; d < 3; ++d) x[d] = q6_bary[q][0] * Pt[0][d] + q6_bary[q][1] * Pt[1][d] + q6_bary[q][2] * Pt[2][d];
         for (int p = 0; p < 6; ++p) {
             if (it.cls == COINCIDENT && p == q) continue;
             double y[3];
-            for (int d = 0; d < 3; ++d) y[d] = s_bary[p][0] * Ps[0][d] + s_bary[p][1] * Ps[1][d] + s_bary[p][2] * Ps[2][d];
-            s_point(x, y, s_bary[q], s_bary[p], -(at * s_wq[q]) * (as * s_wq[p]), nt, ns, P.kre, P.kim, A);
+            for (int d = 0; d < 3; ++d) y[d] = q6_bary[p][0] * Ps[0][d] + q6_bary[p][1] * Ps[1][d] + q6_bary[p][2] * Ps[2][d];
+            s_point(x, y, q6_bary[q], q6_bary[p], -(at * q6_w[q]) * (as * q6_w[p]), nt, ns, P.kre, P.kim, A);
         }
     }
     // PMCHWT blocks; W = curl_a . curl_b sum(w G) - k^2 (n_t . n_s) V

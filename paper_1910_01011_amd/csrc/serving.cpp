@@ -237,6 +237,17 @@ bem_status bem_batch_attach(bem_problem *p, bem_batch *b)
     return BEM_OK;
 }
 
+bem_status bem_batch_set_window(bem_batch *b, double seconds)
+{
+    if (!b || !(seconds >= 0) || !(seconds <= 10)) {
+        bem::set_error("bem_batch_set_window: need a batch and 0 <= seconds <= 10");
+        return BEM_ERR_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> lk(b->mu);
+    b->window_s = seconds;
+    return BEM_OK;
+}
+
 bem_status bem_batch_stats(bem_batch *b, int64_t *out6)
 {
     if (!b || !out6) {

@@ -139,13 +139,14 @@ class Server:
     operator applies batched across the requests in flight (``batching``)."""
 
     def __init__(self, hbm_budget_bytes: int | None = None, max_inflight: int = 4, headroom_bytes: int = 16 << 30,
-                 batching: bool = True):
+                 batching: bool = True, batch_window_s: float | None = None):
         if hbm_budget_bytes is None:
             free, _total = torch.cuda.mem_get_info()
             hbm_budget_bytes = max(0, free - headroom_bytes)
         self.budget = int(hbm_budget_bytes)
         self.max_inflight = int(max_inflight)
         self.batching = bool(batching)
+        self.batch_window_s = batch_window_s
         self.last_batch_stats: dict = {}
 
     def run(self, requests: list[Request]) -> list[Result]:
@@ -173,6 +174,8 @@ class Server:
             done_evt.set()
 
         batch = Batch(torch.cuda.current_device()) if self.batching else None
+        if batch is not None and self.batch_window_s is not None:
+            batch.set_window(self.batch_window_s)
         t0 = time.perf_counter()
         pending: list[Request] = []
         nxt = 0

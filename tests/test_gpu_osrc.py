@@ -68,3 +68,26 @@ def test_osrc_preconditioned_solve():
         res = _relerr(A @ np.ravel(u1), b)
         print(f"right OSRC at tol {tol:g}: {i1[0]}, oracle residual {res:.2e}")
         assert i1[0]["converged"] and i1[0]["rel_residual"] <= 1.1 * tol and res <= 2 * tol
+
+
+def test_osrc_graph_replays_match_eager_launches(monkeypatch):
+    """The batched COCG replays a captured graph of eight iterations until every
+    block has converged.  The same kernels launched one by one (BEM_COCG_EAGER)
+    must give bitwise the same preconditioned vectors, on every one of several
+    applies with other work and synchronisations in between, on a single and a
+    two-domain problem."""
+    bem = _bem()
+    for prob in (configs.config1(), configs.two_spheres(level=2)):
+        P = bem.Problem.from_config(prob)
+        opts = bem.solve_options(precond=bem.BEM_PRECOND_OSRC, n_pade=4, r_eps=0.1, theta=np.pi / 3, osrc_tol=1e-8)
+        Y = vectors.random_complex(prob.n_unknowns, seed=24, n_rhs=3)
+        graph = []
+        for r in range(3):
+            graph.append(P.precondition(Y[r], opts))
+            P.apply(Y[r])                     # eager work between the replays
+        monkeypatch.setenv("BEM_COCG_EAGER", "1")
+        for r in range(3):
+            assert np.array_equal(P.precondition(Y[r], opts), graph[r]), (prob.name, r)
+        monkeypatch.delenv("BEM_COCG_EAGER")
+        assert np.array_equal(P.precondition(Y[0], opts), graph[0])
+        P.close()

@@ -50,7 +50,9 @@ def test_result_is_the_same_alone_and_in_a_mix():
         res = srv.run([r])
         alone[r.rid] = res[0]
         assert srv.last_batch_stats["multi_problem_launches"] == 0
-    srv = serving.Server(max_inflight=5)
+    # a long gather window: the requests in a solve step in lockstep, so the
+    # two on-the-fly requests' applies meet in the same dispatches
+    srv = serving.Server(max_inflight=5, batch_window_s=0.05)
     mix = srv.run(reqs)
     stats = srv.last_batch_stats
     print(serving.summarize(mix))

@@ -116,8 +116,11 @@ def test_config2_solves_match_oracle_lu():
     wave +z) solved on the GPU against the oracle's dense FP64 LU solution
     (written by tests/golden/make_config2_lu.py from the oracle alone): plain
     GMRES and right-preconditioned OSRC GMRES (stopping on the true residual),
-    both at tol 1e-6; the error is the larger of the relative l2 errors over the
-    u_D and the u_N blocks, at most 1e-5 (FP32 path)."""
+    both at tol 1e-7; the error is the larger of the relative l2 errors over the
+    u_D and the u_N blocks, at most 1e-5 (FP32 path).  The solution error is
+    about ten times the residual here (at tol 1e-6 the u_N block misses by
+    1e-5), so the residual must go one decade further than the error target,
+    down to the FP32 operator's own rounding floor (true residual ~2e-7)."""
     import paper_1910_01011_amd as bem
     prob = configs.config2()
     nv = prob.domains[0].n_vertices
@@ -127,13 +130,15 @@ def test_config2_solves_match_oracle_lu():
     P = bem.Problem.from_config(prob, autotune=True)
     b = P.rhs(bem.Incident.plane_waves([[0.0, 0.0, 1.0]]))
     assert _relerr(b[0], b_ref) <= 1e-10
-    for name, opts in (("plain", bem.solve_options(tol=1e-6, restart=100, max_iter=600)),
-                       ("osrc", bem.solve_options(tol=1e-6, restart=100, max_iter=600, precond=bem.BEM_PRECOND_OSRC,
+    for name, opts in (("plain", bem.solve_options(tol=1e-7, restart=100, max_iter=600)),
+                       ("osrc", bem.solve_options(tol=1e-7, restart=100, max_iter=600, precond=bem.BEM_PRECOND_OSRC,
                                                   n_pade=4, r_eps=0.1, theta=np.pi / 3))):
         u, info = P.solve(b, opts)
         u = np.ravel(u)
         eD, eN = _relerr(u[:nv], u_ref[:nv]), _relerr(u[nv:], u_ref[nv:])
         print(f"config2 {name}: {info[0]}, error vs LU: u_D {eD:.2e}, u_N {eN:.2e}", flush=True)
-        assert info[0]["converged"] and info[0]["rel_residual"] <= 1.1e-6
+        # the recursive residual reaches 1e-7; the true residual of the FP32
+        # operator stalls near 2e-7, the rounding of its apply
+        assert info[0]["converged"] and info[0]["rel_residual"] <= 5e-7
         assert max(eD, eN) <= 1e-5
     P.close()
