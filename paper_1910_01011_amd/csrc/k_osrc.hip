@@ -260,13 +260,15 @@ void osrc_setup(bem_problem &p)
 //
 // The rows of every domain are cut into chunks of CG_ROWS; one workgroup per
 // (chunk, system) works on its rows, so a single system spreads over many CUs.
-// An iteration is three launches whose boundaries are the grid-wide waits of
-// the method (q = A p and p.q; x, r, z and r.z, |r|^2; the new direction):
-// the dot products of a block are per-chunk partial sums that every
-// workgroup of the block adds up again in the same fixed order, so each takes
-// the same decision and the result does not depend on scheduling.  A block's
-// flag `done` is written only by the last kernel of an iteration, which stops
-// on convergence before touching any vector, so workgroups that read the flag
+// An iteration is two launches whose boundaries are the grid-wide waits of
+// the method: the convergence test, the new direction and q = A p with p.q;
+// then x, r, z with r.z and |r|^2.  The dot products of a block are per-chunk
+// partial sums that every workgroup of the block adds up again in the same
+// fixed order, so each takes the same decision and the result does not depend
+// on scheduling.  Directions and rho alternate between two slots by iteration
+// parity (read in one, written in the other).  A block's flag `done` is
+// written only by the first kernel of an iteration, which stops on
+// convergence before touching any vector, so workgroups that read the flag
 // early or late in that kernel act alike.  The host replays a captured graph
 // of CG_CHECK iterations and reads the flags after each.
 constexpr int CG_CHECK = 8;
@@ -318,7 +320,8 @@ struct CgArgs {
     int64_t n;                     // rows of one system (all vertices)
     const double2 *c;              // [G] shifts
     const double2 *B;              // [G][n]
-    double2 *X, *R, *P, *Q, *Z;    // [G][n]
+    double2 *X, *R, *Q, *Z;        // [G][n]
+    double2 *P;                    // [2][G][n]: directions of even and odd iterations
     double *part1, *part2;         // [G][n_chunks][2], [G][n_chunks][3]
     double *bn2;                   // [G][n_dom]
     double2 *rho;                  // [2][G][n_dom]
@@ -359,7 +362,6 @@ __global__ __launch_bounds__(CG_ROWS) void k_cg_init(CgArgs a)
         a.X[k] = make_double2(0.0, 0.0);
         a.R[k] = bv;
         a.Z[k] = z;
-        a.P[k] = z;
         v[0] = bv.x * bv.x + bv.y * bv.y;
         v[1] = bv.x * z.x - bv.y * z.y;   // rho = r^T z (unconjugated)
         v[2] = bv.x * z.y + bv.y * z.x;
@@ -387,21 +389,51 @@ __global__ __launch_bounds__(CG_ROWS) void k_cg_init_block(CgArgs a)
     }
 }
 
-// q = (M - c S) p on the chunk's rows; partial p.q
-__global__ __launch_bounds__(CG_ROWS) void k_cg_spmv(CgArgs a)
+// Iteration it, first kernel: the convergence test of the block (or its
+// iteration cap) on the residual the previous update left, else
+// beta = rho_it / rho_(it-1), the new direction p_it = z_it + beta p_(it-1) on
+// the chunk's rows (written to the direction slot of this parity), and
+// q = (M - c S) p_it with the direction at every neighbour formed from z and
+// p_(it-1) on the fly (that slot is not written in this launch); partial p.q.
+// rho_it goes to the rho slot of this parity.  The first iteration has p = z.
+__global__ __launch_bounds__(CG_ROWS) void k_cg_direction_spmv(CgArgs a, int parity, int first)
 {
-    __shared__ double red[8];
+    __shared__ double red[12];
     const int64_t g = blockIdx.y;
     const CgChunk ch = a.chunks[blockIdx.x];
-    if (cg_block_done(a.done, g * a.n_dom + ch.dom)) return;
+    const int64_t blk = g * a.n_dom + ch.dom;
+    if (cg_block_done(a.done, blk)) return;
+    const int64_t nblk = a.n_dom * int64_t(gridDim.y);
+    double br = 0.0, bi = 0.0;
+    if (!first) {
+        double v[3];
+        block_partials<3>(a.part2, g * a.n_chunks + ch.first, ch.nc, v, red);
+        const double2 rho = a.rho[(1 - parity) * nblk + blk];
+        const double d2 = rho.x * rho.x + rho.y * rho.y;
+        const bool stop = v[0] <= a.tol * a.tol * a.bn2[blk] || d2 == 0.0 || a.its[blk] >= a.maxit;
+        if (threadIdx.x == 0 && blockIdx.x == unsigned(ch.first)) {
+            if (stop) a.done[blk] = 1;
+            else a.rho[parity * nblk + blk] = make_double2(v[1], v[2]);
+        }
+        if (stop) return;
+        br = (v[1] * rho.x + v[2] * rho.y) / d2;
+        bi = (v[2] * rho.x - v[1] * rho.y) / d2;
+    }
     const int64_t i = ch.begin + threadIdx.x;
     const double2 cg = a.c[g];
-    const double2 *pv = a.P + g * a.n;
+    const double2 *zv = a.Z + g * a.n, *po = a.P + (1 - parity) * int64_t(gridDim.y) * a.n + g * a.n;
+    double2 *pn = a.P + parity * int64_t(gridDim.y) * a.n + g * a.n;
+    const auto dir = [&](int64_t j) {
+        const double2 z = zv[j];
+        if (first) return z;
+        const double2 pp = po[j];
+        return make_double2(z.x + br * pp.x - bi * pp.y, z.y + br * pp.y + bi * pp.x);
+    };
     double v[2] = {0.0, 0.0};
     if (i < ch.end) {
         double mr = 0, mi = 0, sr = 0, si = 0;
         for (int32_t e = a.aptr[i]; e < a.aptr[i + 1]; ++e) {
-            const double2 x = pv[a.acol[e]];
+            const double2 x = dir(a.acol[e]);
             mr += a.Mv[e] * x.x;
             mi += a.Mv[e] * x.y;
             sr += a.Sv[e] * x.x;
@@ -409,7 +441,8 @@ __global__ __launch_bounds__(CG_ROWS) void k_cg_spmv(CgArgs a)
         }
         const double qr = mr - (cg.x * sr - cg.y * si), qi = mi - (cg.x * si + cg.y * sr);
         a.Q[g * a.n + i] = make_double2(qr, qi);
-        const double2 pp = pv[i];
+        const double2 pp = dir(i);
+        pn[i] = pp;
         v[0] = pp.x * qr - pp.y * qi;
         v[1] = pp.x * qi + pp.y * qr;
     }
@@ -420,9 +453,9 @@ __global__ __launch_bounds__(CG_ROWS) void k_cg_spmv(CgArgs a)
     }
 }
 
-// alpha = rho / (p.q); x += alpha p, r -= alpha q, z = r / diag; partials
-// (|r|^2, r.z).  A breakdown (p.q = 0) leaves x and r and reports |r| = 0, which
-// ends the block in the next kernel.
+// Iteration it, second kernel: alpha = rho_it / (p.q); x += alpha p, r -= alpha q,
+// z = r / diag; partials (|r|^2, r.z) for the next test.  A breakdown (p.q = 0)
+// leaves x and r and reports |r| = 0, which ends the block in the next kernel.
 __global__ __launch_bounds__(CG_ROWS) void k_cg_update(CgArgs a, int parity)
 {
     __shared__ double red[12];
@@ -439,7 +472,7 @@ __global__ __launch_bounds__(CG_ROWS) void k_cg_update(CgArgs a, int parity)
     if (den != 0.0 && i < ch.end) {
         const double ar = (rho.x * pq[0] + rho.y * pq[1]) / den, ai = (rho.y * pq[0] - rho.x * pq[1]) / den;
         const int64_t k = g * a.n + i;
-        const double2 pp = a.P[k], qq = a.Q[k], xx = a.X[k], rv = a.R[k];
+        const double2 pp = a.P[parity * int64_t(gridDim.y) * a.n + k], qq = a.Q[k], xx = a.X[k], rv = a.R[k];
         a.X[k] = make_double2(xx.x + ar * pp.x - ai * pp.y, xx.y + ar * pp.y + ai * pp.x);
         const double2 nr = make_double2(rv.x - (ar * qq.x - ai * qq.y), rv.y - (ar * qq.y + ai * qq.x));
         a.R[k] = nr;
@@ -456,35 +489,6 @@ __global__ __launch_bounds__(CG_ROWS) void k_cg_update(CgArgs a, int parity)
     }
 }
 
-// convergence test of the block (or its iteration cap), else beta = rho_new /
-// rho and p = z + beta p; rho_new goes to the other parity slot
-__global__ __launch_bounds__(CG_ROWS) void k_cg_direction(CgArgs a, int parity)
-{
-    __shared__ double red[12];
-    const int64_t g = blockIdx.y;
-    const CgChunk ch = a.chunks[blockIdx.x];
-    const int64_t blk = g * a.n_dom + ch.dom;
-    if (cg_block_done(a.done, blk)) return;
-    double v[3];
-    block_partials<3>(a.part2, g * a.n_chunks + ch.first, ch.nc, v, red);
-    const int64_t nblk = a.n_dom * int64_t(gridDim.y);
-    const double2 rho = a.rho[parity * nblk + blk];
-    const double d2 = rho.x * rho.x + rho.y * rho.y;
-    const bool stop = v[0] <= a.tol * a.tol * a.bn2[blk] || d2 == 0.0 || a.its[blk] >= a.maxit;
-    if (threadIdx.x == 0 && blockIdx.x == unsigned(ch.first)) {
-        if (stop) a.done[blk] = 1;
-        else a.rho[(1 - parity) * nblk + blk] = make_double2(v[1], v[2]);
-    }
-    if (stop) return;
-    const double br = (v[1] * rho.x + v[2] * rho.y) / d2, bi = (v[2] * rho.x - v[1] * rho.y) / d2;
-    const int64_t i = ch.begin + threadIdx.x;
-    if (i < ch.end) {
-        const int64_t k = g * a.n + i;
-        const double2 pp = a.P[k], z = a.Z[k];
-        a.P[k] = make_double2(z.x + br * pp.x - bi * pp.y, z.y + br * pp.y + bi * pp.x);
-    }
-}
-
 // Captures CG_CHECK iterations of the batched COCG on a capture stream of this
 // thread and device (so that the problem's stream, which may be the null
 // stream, is never in capture mode) and instantiates them.
@@ -497,10 +501,11 @@ static hipGraphExec_t cg_chunk_graph(const CgArgs &a, dim3 grid, dim3 block)
     if (!cap[dev]) BEM_HIP(hipStreamCreateWithFlags(&cap[dev], hipStreamNonBlocking));
     hipStream_t cs = cap[dev];
     BEM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < CG_CHECK; ++i) {
-        k_cg_spmv<<<grid, block, 0, cs>>>(a);
+    // iterations 1 .. CG_CHECK of a chunk (the first iteration runs before the
+    // replays): iteration it has parity it & 1
+    for (int i = 1; i <= CG_CHECK; ++i) {
+        k_cg_direction_spmv<<<grid, block, 0, cs>>>(a, i & 1, 0);
         k_cg_update<<<grid, block, 0, cs>>>(a, i & 1);
-        k_cg_direction<<<grid, block, 0, cs>>>(a, i & 1);
     }
     hipGraph_t graph = nullptr;
     const hipError_t e_launch = hipGetLastError();
@@ -529,7 +534,7 @@ static void cocg_batch(bem_problem &p, int G, const std::vector<cd> &c, const do
     if (G < 1) return;
     if (G > 65535) throw Error{BEM_ERR_UNSUPPORTED, "OSRC: too many systems in one batch"};
     const size_t tot = size_t(G) * n;
-    OsrcBuf R(tot), Pp(tot), Q(tot), Z(tot), cdev{size_t(G)}, rho(size_t(2) * G * n_dom);
+    OsrcBuf R(tot), Pp(2 * tot), Q(tot), Z(tot), cdev{size_t(G)}, rho(size_t(2) * G * n_dom);
     struct DBuf {
         double *p = nullptr;
         hipStream_t s;
@@ -590,12 +595,14 @@ static void cocg_batch(bem_problem &p, int G, const std::vector<cd> &c, const do
         }
     } exec_guard{exec};
     std::vector<int32_t> done(size_t(G) * n_dom);
-    for (int it = 0; it < maxit; it += CG_CHECK) {
+    k_cg_direction_spmv<<<grid, block, 0, s>>>(a, 0, 1);   // iteration 0: p = z
+    k_cg_update<<<grid, block, 0, s>>>(a, 0);
+    BEM_HIP(hipGetLastError());
+    for (int it = 1; it < maxit; it += CG_CHECK) {
         if (eager) {
-            for (int i = 0; i < CG_CHECK; ++i) {
-                k_cg_spmv<<<grid, block, 0, s>>>(a);
+            for (int i = 1; i <= CG_CHECK; ++i) {
+                k_cg_direction_spmv<<<grid, block, 0, s>>>(a, i & 1, 0);
                 k_cg_update<<<grid, block, 0, s>>>(a, i & 1);
-                k_cg_direction<<<grid, block, 0, s>>>(a, i & 1);
             }
             BEM_HIP(hipGetLastError());
         } else {

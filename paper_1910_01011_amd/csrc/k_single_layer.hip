@@ -246,9 +246,14 @@ static void tune_single_layer(bem_problem &p, const float4 *rec, const float *ri
 void launch_single_layer(bem_problem &p, const double2 *x, double2 *y, bool record)
 {
     const int B = 256;
+    // the single-layer records reuse the fused apply's buffers: M float4 of
+    // records and M floats of imaginary parts (M + M/4 float4) in the trial
+    // buffer of 2 M + 3 NT float4; potentials (M complex) in the 10 M doubles
+    if (p.M + (p.M + 3) / 4 > 2 * p.M + 3 * p.NT)
+        throw Error{BEM_ERR_DEVICE, "single-layer records do not fit the trial buffer"};
     float4 *rec = p.d_trial;
-    float *rim = reinterpret_cast<float *>(p.d_trial + p.M);   // d_trial holds 4 M float4
-    double2 *pot = reinterpret_cast<double2 *>(p.d_pot);       // d_pot holds 10 M doubles
+    float *rim = reinterpret_cast<float *>(p.d_trial + p.M);
+    double2 *pot = reinterpret_cast<double2 *>(p.d_pot);
     if (record) BEM_HIP(hipEventRecord(p.ev[0], p.stream));
     k_gather_v<<<dim3(blocks_1d(p.M, B)), dim3(B), 0, p.stream>>>(x, p.d_tris, p.d_area, p.d_pts, p.M, rec, rim);
     BEM_HIP(hipGetLastError());
