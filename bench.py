@@ -657,7 +657,8 @@ def serving_section(bem, torch, n_requests, rates=(2.0, 10.0), max_inflight=4):
         items = configs.serving_stream(rate, n_requests, 5000 + int(round(100 * rate)),
                                        6000 + int(round(100 * rate)))
         reqs = serving.requests_from_stream(items, free)
-        srv = serving.Server(max_inflight=max_inflight)
+        srv = serving.Server(max_inflight=max_inflight, on_result=lambda r, rate=rate: log(
+            f"serving rate {rate:g}: request {r.rid} done, latency {r.latency:.2f} s"))
         res = srv.run(reqs)
         summ = serving.summarize(res)
         summ["batch"] = srv.last_batch_stats

@@ -281,11 +281,16 @@ bem_status bem_evaluate_field(bem_problem *p, const bem_complex *u, const bem_in
  * clustered by recursive median bisection down to leaf_vertices per cluster; a
  * pair of clusters with max(diam) <= eta dist (bounding boxes of the supports
  * of the clusters' basis functions; see bem_hmatrix_plan) becomes a
- * low-rank block, built by adaptive cross approximation with complete pivoting
- * to the relative tolerance eps of its largest entry (kept dense when the rank
- * would not halve its storage); pairs of leaves are dense blocks with the FP64
- * singular correction.  Entries are those of the assembled matrix (FP32 pairs,
- * complex64 storage).  Replaces any previous hierarchical matrix of p; it is
+ * low-rank block, built by adaptive cross approximation with partial pivoting
+ * to the relative tolerance eps of its Frobenius norm (the entries of each
+ * pivot row and column computed on demand, the stopping test confirmed on
+ * sampled rows; kept dense when the rank would not halve its storage); pairs
+ * of leaves are dense blocks with the FP64 singular correction.  Clusters
+ * never mix boundaries (the tree splits between boundaries first).  Entries
+ * are those of the assembled matrix (FP32 pairs, complex64 storage).  The
+ * environment variable BEM_HMATRIX_ACA=complete selects complete pivoting on
+ * fully computed blocks instead (to the tolerance eps of the largest entry),
+ * for comparisons.  Replaces any previous hierarchical matrix of p; it is
  * applied by bem_apply_with(BEM_APPLY_HMATRIX) and used by solves with
  * precision BEM_PREC_HMATRIX.  eps in (0, 0.1], leaf_vertices in [8, 4096],
  * eta > 0.  info may be NULL. */

@@ -335,6 +335,9 @@ EntryCtx *entry_ctx_create(bem_problem &p);
 void entry_ctx_free(EntryCtx *c);
 void launch_hblock_entries(bem_problem &p, EntryCtx *ctx, const int32_t *perm, const int4 *tiles, int64_t n_tiles,
                            const HBlock *blocks, float2 *const *out);
+void launch_aca_partial(bem_problem &p, EntryCtx *ctx, const int32_t *perm, const HBlock *blocks, const int32_t *ids,
+                        int n, float2 *const *U, float2 *const *V, const int32_t *kmax, float eps, int32_t *rank,
+                        int max_side);
 void launch_hblock_correction(bem_problem &p, const int2 *rows, int64_t n_rows, const HBlock *blocks,
                               float2 *const *out, const int32_t *perm, const int32_t *iperm);
 void hmatrix_free(HMatrix *h);

@@ -2,11 +2,10 @@
 // to go beyond dense storage, there with Bempp's H-matrices).
 //
 // Build:
-//  * cluster tree: the vertices of all boundaries are bisected recursively at
-//    the median of the longest axis of their bounding box, down to `leaf`
-//    vertices; the vertex order is permuted so that every cluster is a range
-//    (complete pivoting copes with blocks that mix boundaries; splitting by
-//    boundary first was measured no better);
+//  * cluster tree: clusters over several boundaries are split between
+//    boundaries; a cluster of one boundary is bisected recursively at the
+//    median of the longest axis of its bounding box, down to `leaf` vertices;
+//    the vertex order is permuted so that every cluster is a range;
 //  * block tree: a pair of clusters (s, t) is admissible when
 //    max(diam s, diam t) <= eta dist(s, t); admissible pairs become low-rank
 //    blocks, pairs of leaves dense blocks, others are split.  A cluster's box
@@ -14,13 +13,14 @@
 //    vertex), not the vertices alone: two vertices whose functions meet on
 //    touching triangles then lie in clusters at distance 0, which are never
 //    admissible;
-//  * entries: every block's vertex-pair entries (the far-field sums of the
-//    dense assembly) are computed on the GPU; dense blocks get the FP64 singular
-//    correction.  The build counts the entries of the singular pattern that fall
-//    in low-rank blocks and fails unless there are none;
-//  * low-rank blocks: adaptive cross approximation with complete pivoting to
-//    the relative tolerance eps, in batches; a block whose rank would not save
-//    storage is kept dense.
+//  * low-rank blocks: adaptive cross approximation with partial pivoting to
+//    the relative tolerance eps (Frobenius norm, confirmed on sampled rows),
+//    the entries of each pivot row and column computed on demand on the GPU
+//    (the far-field vertex-pair sums of the dense assembly), in batches; a
+//    block whose rank would not halve its storage is kept dense;
+//  * dense blocks: every vertex-pair entry, plus the FP64 singular correction.
+//    The build counts the entries of the singular pattern that fall in
+//    low-rank blocks and fails unless there are none.
 // Apply: reorder x, one workgroup per block writes its products, each row sums
 // its blocks' products in a fixed order (no atomics; deterministic).
 #include <algorithm>
@@ -29,6 +29,7 @@
 #include <cstdlib>
 #include <memory>
 #include <numeric>
+#include <string>
 #include <type_traits>
 #include <vector>
 
@@ -48,6 +49,10 @@ namespace {
 constexpr int HK_CAP = 128;                       // largest rank kept (LDS of the apply kernel)
 constexpr int HBLOCK_MAX_SIDE = 512;              // vertices on a side of a low-rank block
 constexpr int64_t ACA_BATCH_BYTES = int64_t(4) << 30;   // dense scratch of one batch of far blocks
+// U and V scratch of one batch of the partially pivoted build: large, so that
+// the long cross approximations of the largest blocks (one wave each) overlap
+// the many short ones in a single launch
+constexpr int64_t ACAP_BATCH_BYTES = int64_t(32) << 30;
 
 struct Cluster {
     int32_t b, e;          // range in the permuted order
@@ -154,20 +159,37 @@ HTree plan_tree(const bem_problem &p, int leaf, double eta, int max_side)
         cl.push_back(c);
         return int32_t(cl.size() - 1);
     };
+    // first vertex of every boundary but the first (the vertices of a boundary
+    // are a contiguous range of the original order)
+    std::vector<int32_t> starts;
+    for (size_t j = 1; j < p.doms.size(); ++j) starts.push_back(int32_t(p.doms[j].v_off));
     stack.push_back(make(0, int32_t(NV)));
     while (!stack.empty()) {
         const int32_t ci = stack.back();
         stack.pop_back();
         const Cluster c = cl[ci];
-        if (c.e - c.b <= leaf) continue;
-        int ax = 0;
-        for (int d = 1; d < 3; ++d)
-            if (c.hi[d] - c.lo[d] > c.hi[ax] - c.lo[ax]) ax = d;
-        const int32_t mid = c.b + (c.e - c.b) / 2;
-        std::nth_element(perm.begin() + c.b, perm.begin() + mid, perm.begin() + c.e, [&](int32_t u, int32_t v) {
-            const double xu = p.h_verts[3 * size_t(u) + ax], xv = p.h_verts[3 * size_t(v) + ax];
-            return xu < xv || (xu == xv && u < v);
-        });
+        // a cluster over several boundaries is split between two of them (the
+        // boundary start nearest its middle), at any size: every block then
+        // couples one boundary with one boundary, a single smooth kernel
+        // sum that the partially pivoted cross approximation samples
+        // uniformly.  Such clusters come from boundary splits alone, so the
+        // permutation is still the identity on them.
+        int32_t mid = -1;
+        for (int32_t st : starts)
+            if (st > c.b && st < c.e &&
+                (mid < 0 || std::abs(2 * int64_t(st) - c.b - c.e) < std::abs(2 * int64_t(mid) - c.b - c.e)))
+                mid = st;
+        if (mid < 0) {
+            if (c.e - c.b <= leaf) continue;
+            int ax = 0;
+            for (int d = 1; d < 3; ++d)
+                if (c.hi[d] - c.lo[d] > c.hi[ax] - c.lo[ax]) ax = d;
+            mid = c.b + (c.e - c.b) / 2;
+            std::nth_element(perm.begin() + c.b, perm.begin() + mid, perm.begin() + c.e, [&](int32_t u, int32_t v) {
+                const double xu = p.h_verts[3 * size_t(u) + ax], xv = p.h_verts[3 * size_t(v) + ax];
+                return xu < xv || (xu == xv && u < v);
+            });
+        }
         const int32_t c0 = make(c.b, mid), c1 = make(mid, c.e);
         cl[ci].child[0] = c0;
         cl[ci].child[1] = c1;
@@ -392,8 +414,52 @@ static HMatrix *build(bem_problem &p, double eps, int leaf, double eta, int max_
         launch_copy_list(s, d_src, d_dst, d_cnt, int(src.size()));
         BEM_HIP(hipStreamSynchronize(s));
     };
+    // low-rank blocks by cross approximation with partial pivoting (entries
+    // on demand); BEM_HMATRIX_ACA=complete selects complete pivoting on the
+    // computed blocks (for comparisons)
+    const char *aca_env = std::getenv("BEM_HMATRIX_ACA");
+    const bool complete = aca_env && std::string(aca_env) == "complete";
     size_t fi = 0;
-    while (fi < far_ids.size()) {
+    while (!complete && fi < far_ids.size()) {
+        std::vector<int> batch;
+        int64_t bytes = 0;
+        int side = 1;
+        while (fi < far_ids.size()) {
+            const auto [m2, n2] = mn(far_ids[fi]);
+            const int64_t need = int64_t(kcap(far_ids[fi])) * (m2 + n2) * int64_t(sizeof(float2));
+            if (!batch.empty() && bytes + need > ACAP_BATCH_BYTES) break;
+            batch.push_back(far_ids[fi++]);
+            bytes += need;
+            side = int(std::max<int64_t>(side, std::max(m2, n2) / 2));
+        }
+        DevMem m_scr;
+        float2 *scr = m_scr.alloc<float2>(size_t(bytes / int64_t(sizeof(float2))));
+        std::vector<float2 *> Ub, Vb;
+        std::vector<int32_t> kb, ids32;
+        int64_t off = 0;
+        for (int i : batch) {
+            const auto [m2, n2] = mn(i);
+            const int k = kcap(i);
+            Ub.push_back(scr + off);
+            off += int64_t(k) * m2;
+            Vb.push_back(scr + off);
+            off += int64_t(k) * n2;
+            kb.push_back(k);
+            ids32.push_back(i);
+        }
+        DevMem m_ids, m_U, m_V, m_k, m_rank;
+        int32_t *d_ids = upload(ids32, m_ids, s);
+        float2 **d_U = upload(Ub, m_U, s), **d_V = upload(Vb, m_V, s);
+        int32_t *d_k = upload(kb, m_k, s);
+        int32_t *d_rank = m_rank.alloc<int32_t>(batch.size());
+        launch_aca_partial(p, ectx, H->d_perm, H->d_blocks, d_ids, int(batch.size()), d_U, d_V, d_k, float(eps), d_rank,
+                           side);
+        std::vector<int32_t> rank(batch.size());
+        BEM_HIP(hipMemcpyAsync(rank.data(), d_rank, rank.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        BEM_HIP(hipStreamSynchronize(s));
+        compact(batch, rank, Ub, Vb);
+    }
+    while (complete && fi < far_ids.size()) {
         std::vector<int> batch;
         int64_t bytes = 0;
         while (fi < far_ids.size()) {

@@ -437,6 +437,359 @@ void launch_hblock_correction(bem_problem &p, const int2 *rows, int64_t n_rows, 
     BEM_HIP(hipStreamSynchronize(p.stream));
 }
 
+// ---------------------------------------------------------------------------
+// Low-rank blocks by adaptive cross approximation with partial pivoting
+// ---------------------------------------------------------------------------
+// The entries of a block are computed on demand, one residual row and one
+// residual column per term (the vertex-pair sums above), so a block of m x n
+// vertices and rank r costs r (m + n) vertex pairs instead of the m n of the
+// complete-pivoting build.  One wave (a workgroup of 64 lanes) per block; lane
+// l owns the vertices l, l + 64, ... of each side and the two interleaved rows
+// (or columns) of each.
+//
+// Term k: the residual of row i is computed, its largest entry in an unused
+// column j is the pivot, v_k = residual row / pivot and u_k = residual of
+// column j; the next row is the largest entry of u_k in an unused row.  The
+// Frobenius norm of S_k = sum u_l v_l is updated as
+//   |S_k|^2 = |S_{k-1}|^2 + 2 Re sum_{l<k} <u_l, u_k> <v_k, v_l> + |u_k|^2 |v_k|^2,
+// and the terms stop when |u_k| |v_k| <= eps |S_k|.  That test sees only the
+// rows and columns pivoted so far, so it is confirmed on ACAP_CHECK_ROWS unused
+// rows spread over the block (from a hash of the block and the rank), half of
+// them D rows and half N rows: their residual, scaled to all unused rows, must
+// be within eps |S_k|, else the worst of them is the next pivot row.  Both
+// kinds are sampled because on coplanar clusters (the faces of a slab or a
+// box) the double-layer entries vanish, the block splits into a D-row part
+// (V) and an N-row part (W) with no row or column in common, and pivots taken
+// from one part never reach the other.  Rank -1 when the cap comes first (the
+// block is then stored dense).  Every decision is taken on wave-uniform values
+// (shuffle reductions in a fixed order), so the result is deterministic.
+
+constexpr int ACAP_CHECK_ROWS = 4;   // even: half D rows, half N rows
+
+struct AcapIn {
+    const float4 *rec;
+    const int32_t *v2t_ptr, *vdom, *perm;
+    const DenseDom *doms;
+    DenseDom ext;
+};
+
+// entry (row 2 a + s, column 2 c + t) of a vertex pair, as k_hblock_entries
+// stores it
+__device__ __forceinline__ float2 acap_entry(const Acc4 &E, const Acc4 &I, const DenseDom &in, bool same, int s, int t)
+{
+    const float sV = same ? in.sV : 0.0f, sW = same ? in.sW : 0.0f, s1 = same ? 1.0f : 0.0f;
+    if (s == 0)
+        return t == 0 ? make_float2(-(E.kr + s1 * I.kr), -(E.ki + s1 * I.ki)) : make_float2(E.vr + sV * I.vr, E.vi + sV * I.vi);
+    return t == 0 ? make_float2(E.wr + sW * I.wr, E.wi + sW * I.wi) : make_float2(E.pr + s1 * I.pr, E.pi + s1 * I.pi);
+}
+
+template <bool ATT, bool WRAP>
+__device__ __forceinline__ void acap_pair(const AcapIn &a, int32_t g, int32_t h, Acc4 &E, Acc4 &I, DenseDom &in,
+                                          bool &same)
+{
+    const int dg = a.vdom[g];
+    same = dg == a.vdom[h];
+    in = a.doms[dg];
+    E = Acc4{0, 0, 0, 0, 0, 0, 0, 0};
+    I = Acc4{0, 0, 0, 0, 0, 0, 0, 0};
+    vertex_pair_sums<ATT, WRAP>(a.rec, 6 * a.v2t_ptr[g], 6 * a.v2t_ptr[g + 1], a.rec + 3 * int64_t(6 * a.v2t_ptr[h]),
+                                6 * (a.v2t_ptr[h + 1] - a.v2t_ptr[h]), a.ext, in, same, E, I);
+}
+
+// e - x y (complex)
+__device__ __forceinline__ float2 acap_msub(float2 e, float2 x, float2 y)
+{
+    return make_float2(e.x - fmaf(x.x, y.x, -x.y * y.y), e.y - fmaf(x.x, y.y, x.y * y.x));
+}
+
+__device__ __forceinline__ double acap_wsum(double x)
+{
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
+// largest v over the wave (ties: the smaller index), with its index and value
+__device__ __forceinline__ void acap_argmax(float &v, int &idx, float2 &z)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        const float ov = __shfl_xor(v, off);
+        const int oi = __shfl_xor(idx, off);
+        const float zx = __shfl_xor(z.x, off), zy = __shfl_xor(z.y, off);
+        if (ov > v || (ov == v && oi < idx)) {
+            v = ov;
+            idx = oi;
+            z = make_float2(zx, zy);
+        }
+    }
+}
+
+// out[0 .. 2 n) = residual of block row i after k terms
+template <bool ATT, bool WRAP>
+__device__ void acap_row(const AcapIn &a, const HBlock &B, const float2 *U, const float2 *V, int64_t m2, int64_t n2,
+                         int i, int k, float2 *out)
+{
+    const int32_t g = a.perm[B.r0 + (i >> 1)];
+    const int s = i & 1, n = B.c1 - B.c0;
+    for (int c = int(threadIdx.x); c < n; c += 64) {
+        Acc4 E, I;
+        DenseDom in;
+        bool same;
+        acap_pair<ATT, WRAP>(a, g, a.perm[B.c0 + c], E, I, in, same);
+        float2 e0 = acap_entry(E, I, in, same, s, 0), e1 = acap_entry(E, I, in, same, s, 1);
+#pragma unroll 8
+        for (int l = 0; l < k; ++l) {
+            const float2 ul = U[int64_t(l) * m2 + i];
+            e0 = acap_msub(e0, ul, V[int64_t(l) * n2 + 2 * c]);
+            e1 = acap_msub(e1, ul, V[int64_t(l) * n2 + 2 * c + 1]);
+        }
+        out[2 * c] = e0;
+        out[2 * c + 1] = e1;
+    }
+}
+
+// out[0 .. 2 m) = residual of block column j after k terms
+template <bool ATT, bool WRAP>
+__device__ void acap_col(const AcapIn &a, const HBlock &B, const float2 *U, const float2 *V, int64_t m2, int64_t n2,
+                         int j, int k, float2 *out)
+{
+    const int32_t h = a.perm[B.c0 + (j >> 1)];
+    const int t = j & 1, m = B.r1 - B.r0;
+    for (int r = int(threadIdx.x); r < m; r += 64) {
+        Acc4 E, I;
+        DenseDom in;
+        bool same;
+        acap_pair<ATT, WRAP>(a, a.perm[B.r0 + r], h, E, I, in, same);
+        float2 e0 = acap_entry(E, I, in, same, 0, t), e1 = acap_entry(E, I, in, same, 1, t);
+#pragma unroll 8
+        for (int l = 0; l < k; ++l) {
+            const float2 vl = V[int64_t(l) * n2 + j];
+            e0 = acap_msub(e0, U[int64_t(l) * m2 + 2 * r], vl);
+            e1 = acap_msub(e1, U[int64_t(l) * m2 + 2 * r + 1], vl);
+        }
+        out[2 * r] = e0;
+        out[2 * r + 1] = e1;
+    }
+}
+
+template <bool ATT, bool WRAP>
+__global__ __launch_bounds__(64) void k_aca_partial(const AcapIn a, const HBlock *__restrict__ blocks,
+                                                    const int32_t *__restrict__ ids, float2 *const *__restrict__ Uo,
+                                                    float2 *const *__restrict__ Vo, const int32_t *__restrict__ kmax,
+                                                    float eps, int32_t *__restrict__ rank_out)
+{
+    extern __shared__ unsigned char used[];   // [2 m] rows, then [2 n] columns
+    __shared__ int pick[ACAP_CHECK_ROWS];
+    const int lane = threadIdx.x;
+    const int32_t bid = ids[blockIdx.x];
+    const HBlock B = blocks[bid];
+    const int m = B.r1 - B.r0, n = B.c1 - B.c0, m2 = 2 * m, n2 = 2 * n;
+    unsigned char *usedr = used, *usedc = used + m2;
+    float2 *U = Uo[blockIdx.x], *V = Vo[blockIdx.x];
+    const int K = kmax[blockIdx.x];
+    for (int r = lane; r < m2 + n2; r += 64) used[r] = 0;
+    __syncthreads();
+    const double eps2 = double(eps) * double(eps);
+    double S2 = 0.0;
+    int k = 0, i = 0, skips = 0, rows_used = 0, result = -1;
+    for (;;) {
+        float2 *vk = V + int64_t(k) * n2;
+        acap_row<ATT, WRAP>(a, B, U, V, m2, n2, i, k, vk);
+        if (lane == 0) usedr[i] = 1;
+        ++rows_used;
+        __syncthreads();
+        // pivot: the largest entry of the residual row in an unused column
+        float best = -1.0f;
+        int j = 0x7fffffff;
+        float2 piv = make_float2(0.0f, 0.0f);
+        for (int c = lane; c < n; c += 64)
+            for (int t = 0; t < 2; ++t) {
+                const int cc = 2 * c + t;
+                if (usedc[cc]) continue;
+                const float2 z = vk[cc];
+                const float q = fmaf(z.x, z.x, z.y * z.y);
+                if (q > best) {
+                    best = q;
+                    j = cc;
+                    piv = z;
+                }
+            }
+        acap_argmax(best, j, piv);
+        if (!(best > 0.0f)) {
+            // no usable pivot in this row: the next unused row
+            if (lane == 0) {
+                int nxt = -1;
+                for (int q = 1; q <= m2 && nxt < 0; ++q)
+                    if (!usedr[(i + q) % m2]) nxt = (i + q) % m2;
+                pick[0] = nxt;
+            }
+            __syncthreads();
+            const int nxt = pick[0];
+            __syncthreads();
+            if (nxt < 0 || ++skips > 8) {
+                result = k;
+                break;
+            }
+            i = nxt;
+            continue;
+        }
+        const float pd = fmaf(piv.x, piv.x, piv.y * piv.y);
+        const float2 inv = make_float2(piv.x / pd, -piv.y / pd);
+        for (int c = lane; c < n; c += 64) {
+            const float2 z0 = vk[2 * c], z1 = vk[2 * c + 1];
+            vk[2 * c] = make_float2(fmaf(z0.x, inv.x, -z0.y * inv.y), fmaf(z0.x, inv.y, z0.y * inv.x));
+            vk[2 * c + 1] = make_float2(fmaf(z1.x, inv.x, -z1.y * inv.y), fmaf(z1.x, inv.y, z1.y * inv.x));
+        }
+        float2 *uk = U + int64_t(k) * m2;
+        acap_col<ATT, WRAP>(a, B, U, V, m2, n2, j, k, uk);
+        if (lane == 0) usedc[j] = 1;
+        // norms of the new term and its products with the earlier ones (own entries)
+        double nu = 0.0, nv = 0.0;
+        for (int r = lane; r < m2; r += 64) {
+            const float2 z = uk[r];
+            nu += double(z.x) * z.x + double(z.y) * z.y;
+        }
+        for (int c = lane; c < n2; c += 64) {
+            const float2 z = vk[c];
+            nv += double(z.x) * z.x + double(z.y) * z.y;
+        }
+        nu = acap_wsum(nu);
+        nv = acap_wsum(nv);
+        // four earlier terms at a time (independent loads and reductions)
+        double cross = 0.0;
+        for (int l0 = 0; l0 < k; l0 += 4) {
+            double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0}, br[4] = {0, 0, 0, 0}, bi[4] = {0, 0, 0, 0};
+            const int nl = min(4, k - l0);
+            for (int r = lane; r < m2; r += 64) {   // <u_l, u_k>
+                const float2 y = uk[r];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (q < nl) {
+                        const float2 x = U[int64_t(l0 + q) * m2 + r];
+                        ar[q] += double(x.x) * y.x + double(x.y) * y.y;
+                        ai[q] += double(x.x) * y.y - double(x.y) * y.x;
+                    }
+            }
+            for (int c = lane; c < n2; c += 64) {   // <v_k, v_l>
+                const float2 x = vk[c];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (q < nl) {
+                        const float2 y = V[int64_t(l0 + q) * n2 + c];
+                        br[q] += double(x.x) * y.x + double(x.y) * y.y;
+                        bi[q] += double(x.x) * y.y - double(x.y) * y.x;
+                    }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                ar[q] = acap_wsum(ar[q]);
+                ai[q] = acap_wsum(ai[q]);
+                br[q] = acap_wsum(br[q]);
+                bi[q] = acap_wsum(bi[q]);
+            }
+            for (int q = 0; q < nl; ++q) cross += ar[q] * br[q] - ai[q] * bi[q];
+        }
+        S2 += 2.0 * cross + nu * nv;
+        ++k;
+        __syncthreads();   // the new term and the column flag, for every lane
+        if (nu * nv <= eps2 * S2) {
+            if (k >= K) {
+                result = k;
+                break;
+            }
+            // confirm on unused rows; the slot of term k is scratch
+            if (lane == 0)
+                for (int q = 0; q < ACAP_CHECK_ROWS; ++q) {
+                    uint32_t h = uint32_t(bid) * 0x9E3779B1u ^ uint32_t(k) * 0x85EBCA77u ^ uint32_t(q + 1) * 0xC2B2AE3Du;
+                    h ^= h >> 15;
+                    h *= 0x2C1B3C6Du;
+                    h ^= h >> 12;
+                    int r = -1;
+                    for (int o = 0; o < m && r < 0; ++o) {   // rows of parity q & 1
+                        const int c = 2 * int((h + uint32_t(o)) % uint32_t(m)) + (q & 1);
+                        bool dup = usedr[c] != 0;
+                        for (int e = 0; e < q; ++e) dup = dup || pick[e] == c;
+                        if (!dup) r = c;
+                    }
+                    pick[q] = r;
+                }
+            __syncthreads();
+            int chk[ACAP_CHECK_ROWS];
+            for (int q = 0; q < ACAP_CHECK_ROWS; ++q) chk[q] = pick[q];
+            __syncthreads();
+            double sum = 0.0, worst = -1.0;
+            int wr = -1, nchk = 0;
+            float2 *tmp = V + int64_t(k) * n2;
+            for (int q = 0; q < ACAP_CHECK_ROWS; ++q) {
+                if (chk[q] < 0) continue;
+                acap_row<ATT, WRAP>(a, B, U, V, m2, n2, chk[q], k, tmp);
+                double e = 0.0;
+                for (int c = lane; c < n2; c += 64) {
+                    const float2 z = tmp[c];
+                    e += double(z.x) * z.x + double(z.y) * z.y;
+                }
+                e = acap_wsum(e);
+                sum += e;
+                ++nchk;
+                if (e > worst) {
+                    worst = e;
+                    wr = chk[q];
+                }
+            }
+            if (nchk == 0 || sum * double(m2 - rows_used) / double(nchk) <= eps2 * S2) {
+                result = k;
+                break;
+            }
+            i = wr;
+            continue;
+        }
+        if (k >= K) {
+            result = -1;
+            break;
+        }
+        // next row: the largest entry of u_{k-1} in an unused row
+        float bu = -1.0f;
+        int ni = 0x7fffffff;
+        float2 zu = make_float2(0.0f, 0.0f);
+        for (int r = lane; r < m; r += 64)
+            for (int s = 0; s < 2; ++s) {
+                const int rr = 2 * r + s;
+                if (usedr[rr]) continue;
+                const float2 z = uk[rr];
+                const float q = fmaf(z.x, z.x, z.y * z.y);
+                if (q > bu) {
+                    bu = q;
+                    ni = rr;
+                    zu = z;
+                }
+            }
+        acap_argmax(bu, ni, zu);
+        if (ni == 0x7fffffff) {   // every row used
+            result = k;
+            break;
+        }
+        i = ni;
+    }
+    if (lane == 0) rank_out[blockIdx.x] = result;
+}
+
+void launch_aca_partial(bem_problem &p, EntryCtx *ctx, const int32_t *perm, const HBlock *blocks, const int32_t *ids,
+                        int n, float2 *const *U, float2 *const *V, const int32_t *kmax, float eps, int32_t *rank,
+                        int max_side)
+{
+    if (n == 0) return;
+    const EntrySetup &E = *reinterpret_cast<EntrySetup *>(ctx);
+    const AcapIn a{E.rec, p.d_v2t_ptr, E.vdom, perm, E.doms, E.ext};
+    const size_t lds = size_t(4) * size_t(max_side);   // row and column flags of the largest block
+#define ACAP(A, W) k_aca_partial<A, W><<<dim3(unsigned(n)), dim3(64), lds, p.stream>>>(a, blocks, ids, U, V, kmax, eps, rank)
+    if (E.att) {
+        if (p.wrap_phase) ACAP(true, true); else ACAP(true, false);
+    } else {
+        if (p.wrap_phase) ACAP(false, true); else ACAP(false, false);
+    }
+#undef ACAP
+    BEM_HIP(hipGetLastError());
+}
+
 // y = A x, complex64 matrix, FP64 vectors and FP64 accumulation.  One wave per
 // GEMV_ROWS rows; lanes stride over the columns two entries at a time (16-byte
 // loads of A), GEMV_UNROLL column strides loaded before they are used (16

@@ -139,7 +139,7 @@ class Server:
     operator applies batched across the requests in flight (``batching``)."""
 
     def __init__(self, hbm_budget_bytes: int | None = None, max_inflight: int = 4, headroom_bytes: int = 16 << 30,
-                 batching: bool = True, batch_window_s: float | None = None):
+                 batching: bool = True, batch_window_s: float | None = None, on_result=None):
         if hbm_budget_bytes is None:
             free, _total = torch.cuda.mem_get_info()
             hbm_budget_bytes = max(0, free - headroom_bytes)
@@ -147,6 +147,7 @@ class Server:
         self.max_inflight = int(max_inflight)
         self.batching = bool(batching)
         self.batch_window_s = batch_window_s
+        self.on_result = on_result   # called with each Result as it completes (progress reporting)
         self.last_batch_stats: dict = {}
 
     def run(self, requests: list[Request]) -> list[Result]:
@@ -171,6 +172,8 @@ class Server:
                     errors.append(exc)
                 else:
                     results.append(fut.result())
+            if exc is None and self.on_result is not None:
+                self.on_result(fut.result())
             done_evt.set()
 
         batch = Batch(torch.cuda.current_device()) if self.batching else None

@@ -2,10 +2,12 @@
 
 * against the oracle's dense FP64 matrix: the compressed apply differs from
   the exact operator by the FP32 entries (~1e-7) plus the cross-approximation
-  truncation, at most eps of each block's largest entry: with eps = 1e-4 (the
+  truncation, about eps of each block's Frobenius norm: with eps = 1e-4 (the
   blocks of these small meshes are too small to compress at tighter
   tolerances) the relative error of a random apply stays below 1e-5, also on
   the fine trees of 8-vertex leaves;
+* on flat faces (two slabs) the partially pivoted build must find both the
+  D-row and the N-row part of blocks whose double-layer entries vanish;
 * against the library's dense complex64 matrix (same FP32 entries): the
   difference is the truncation alone, and it falls with eps (1e-2, then 1e-4);
 * GMRES on the compressed operator (eps = 1e-5) converges, and its solution
@@ -45,8 +47,8 @@ _CASES = [(configs.config1(), 16, False), (configs.config1(), 8, False), (config
 
 @pytest.mark.parametrize("prob,leaf,lowrank", _CASES, ids=[f"{p.name}-leaf{l}" for p, l, _ in _CASES])
 def test_hmatrix_apply_matches_oracle(prob, leaf, lowrank):
-    """The truncation at eps = 1e-4 of each block's largest entry leaves a few
-    1e-7 on a random apply; a touching pair placed in a low-rank block (its
+    """The truncation at eps = 1e-4 of each block's norm leaves a few 1e-7 on a
+    random apply; a touching pair placed in a low-rank block (its
     FP64 singular correction dropped) would cost far more than the 1e-5
     allowed, and the build refuses such a tree."""
     import paper_1910_01011_amd as bem
@@ -134,6 +136,44 @@ def test_hmatrix_large_blocks(monkeypatch, leaf, max_side):
     for r in range(2):
         err = _relerr(Yh[r], Yd[r])
         print(f"rhs {r}: rel diff to the dense matrix {err:.2e}", flush=True)
+        assert err <= 1e-4
+    assert np.array_equal(P.apply(X, kernel=bem.BEM_APPLY_HMATRIX), Yh)
+    P.close()
+
+
+def _slabs():
+    """Two thin boxes side by side (1,512 vertices each): their large faces are
+    coplanar within a box and across the two."""
+    from bem_inputs import meshes
+    v1, t1 = meshes.box((-3.0, -1.5, -0.25), (-0.5, 1.5, 0.25), 0.12)
+    v2, t2 = meshes.box((0.5, -1.5, -0.25), (3.0, 1.5, 0.25), 0.12)
+    return configs.Problem([configs.Domain(v1, t1, complex(2.3), 1.2, "slab_a"),
+                            configs.Domain(v2, t2, complex(1.9), 0.9, "slab_b")], complex(2.0), 1.0, "two_slabs")
+
+
+@pytest.mark.parametrize("aca", ["partial", "complete"])
+def test_hmatrix_flat_faces(monkeypatch, aca):
+    """Between coplanar clusters the double-layer entries vanish (n . (x - y) =
+    0), so a block is a D-row part (single layer, D rows against N columns) plus
+    an N-row part (hypersingular, N rows against D columns) with no row or column
+    in common: pivots taken in one part never reach the other, and the partially
+    pivoted build finds the second one through its check rows of both kinds.
+    Both builds against the library's dense matrix of the same FP32 entries at
+    eps = 1e-4; the default (partial pivoting) computes only the pivot rows and
+    columns of the low-rank blocks."""
+    import paper_1910_01011_amd as bem
+    monkeypatch.setenv("BEM_HMATRIX_ACA", aca)
+    prob = _slabs()
+    P = bem.Problem.from_config(prob, mode=bem.BEM_ASSEMBLED_FP32)
+    X = vectors.random_complex(prob.n_unknowns, seed=24, n_rhs=2)
+    Yd = P.apply(X, kernel=bem.BEM_APPLY_GEMV)
+    info = P.hmatrix_build(eps=1e-4, leaf_vertices=32, eta=2.0)
+    print(f"{aca}: {info}", flush=True)
+    assert info["n_lowrank"] > 0
+    Yh = P.apply(X, kernel=bem.BEM_APPLY_HMATRIX)
+    for r in range(2):
+        err = _relerr(Yh[r], Yd[r])
+        print(f"{aca} rhs {r}: rel diff to the dense matrix {err:.2e}", flush=True)
         assert err <= 1e-4
     assert np.array_equal(P.apply(X, kernel=bem.BEM_APPLY_HMATRIX), Yh)
     P.close()
