@@ -184,6 +184,7 @@ __global__ void k_osrc_out(const double2 *__restrict__ rootD, const double2 *__r
 static unsigned nb(int64_t n) { return blocks_1d(n, 256); }
 
 constexpr int CG_ROWS = 256;   // rows per chunk of the batched COCG (its workgroup size)
+constexpr int CG_NNZ_STEP = 8;   // row entries loaded together in the sparse product
 
 // stream-ordered scratch on the stream of the current problem
 thread_local hipStream_t t_osrc_stream = nullptr;
@@ -431,13 +432,32 @@ __global__ __launch_bounds__(CG_ROWS) void k_cg_direction_spmv(CgArgs a, int par
     };
     double v[2] = {0.0, 0.0};
     if (i < ch.end) {
+        // eight entries of the row at a time: their index, value and gathered
+        // direction loads are all in flight together (a P1 row has about 7);
+        // entries past the row end read row i with zero values, which adds
+        // exact zeros after the row's own terms in the same order
         double mr = 0, mi = 0, sr = 0, si = 0;
-        for (int32_t e = a.aptr[i]; e < a.aptr[i + 1]; ++e) {
-            const double2 x = dir(a.acol[e]);
-            mr += a.Mv[e] * x.x;
-            mi += a.Mv[e] * x.y;
-            sr += a.Sv[e] * x.x;
-            si += a.Sv[e] * x.y;
+        const int32_t e0 = a.aptr[i], e1 = a.aptr[i + 1];
+        for (int32_t e = e0; e < e1; e += CG_NNZ_STEP) {
+            int32_t col[CG_NNZ_STEP];
+            double mv[CG_NNZ_STEP], sv[CG_NNZ_STEP];
+#pragma unroll
+            for (int u = 0; u < CG_NNZ_STEP; ++u) {
+                const bool in = e + u < e1;
+                col[u] = in ? a.acol[e + u] : int32_t(i);
+                mv[u] = in ? a.Mv[e + u] : 0.0;
+                sv[u] = in ? a.Sv[e + u] : 0.0;
+            }
+            double2 x[CG_NNZ_STEP];
+#pragma unroll
+            for (int u = 0; u < CG_NNZ_STEP; ++u) x[u] = dir(col[u]);
+#pragma unroll
+            for (int u = 0; u < CG_NNZ_STEP; ++u) {
+                mr += mv[u] * x[u].x;
+                mi += mv[u] * x[u].y;
+                sr += sv[u] * x[u].x;
+                si += sv[u] * x[u].y;
+            }
         }
         const double qr = mr - (cg.x * sr - cg.y * si), qi = mi - (cg.x * si + cg.y * sr);
         a.Q[g * a.n + i] = make_double2(qr, qi);
