@@ -49,10 +49,12 @@ namespace {
 constexpr int HK_CAP = 128;                       // largest rank kept (LDS of the apply kernel)
 constexpr int HBLOCK_MAX_SIDE = 512;              // vertices on a side of a low-rank block
 constexpr int64_t ACA_BATCH_BYTES = int64_t(4) << 30;   // dense scratch of one batch of far blocks
-// U and V scratch of one batch of the partially pivoted build: large, so that
-// the long cross approximations of the largest blocks (one wave each) overlap
-// the many short ones in a single launch
-constexpr int64_t ACAP_BATCH_BYTES = int64_t(32) << 30;
+// U and V scratch of one batch of the partially pivoted build: large (up to
+// 64 GB, at most half the free device memory), so that the long cross
+// approximations of the largest blocks (one wave each) overlap the many short
+// ones in a single launch
+constexpr int64_t ACAP_BATCH_MAX = int64_t(64) << 30;
+constexpr int64_t ACAP_BATCH_MIN = int64_t(4) << 30;
 
 struct Cluster {
     int32_t b, e;          // range in the permuted order
@@ -419,6 +421,12 @@ static HMatrix *build(bem_problem &p, double eps, int leaf, double eta, int max_
     // computed blocks (for comparisons)
     const char *aca_env = std::getenv("BEM_HMATRIX_ACA");
     const bool complete = aca_env && std::string(aca_env) == "complete";
+    int64_t acap_batch = ACAP_BATCH_MIN;
+    {
+        size_t free_b = 0, total_b = 0;
+        BEM_HIP(hipMemGetInfo(&free_b, &total_b));
+        acap_batch = std::max(ACAP_BATCH_MIN, std::min(ACAP_BATCH_MAX, int64_t(free_b / 2)));
+    }
     size_t fi = 0;
     while (!complete && fi < far_ids.size()) {
         std::vector<int> batch;
@@ -427,7 +435,7 @@ static HMatrix *build(bem_problem &p, double eps, int leaf, double eta, int max_
         while (fi < far_ids.size()) {
             const auto [m2, n2] = mn(far_ids[fi]);
             const int64_t need = int64_t(kcap(far_ids[fi])) * (m2 + n2) * int64_t(sizeof(float2));
-            if (!batch.empty() && bytes + need > ACAP_BATCH_BYTES) break;
+            if (!batch.empty() && bytes + need > acap_batch) break;
             batch.push_back(far_ids[fi++]);
             bytes += need;
             side = int(std::max<int64_t>(side, std::max(m2, n2) / 2));
