@@ -234,9 +234,12 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only a 1 GiB elementwise copy (the counter scale) and 3 applies, for counter runs")
     ap.add_argument("--probe-workload", default="ribcage", choices=("ribcage", "sphere"),
-                    help="workload of --traffic-probe and --osrc-probe")
+                    help="workload of --traffic-probe, --osrc-probe and --hmatrix-probe")
     ap.add_argument("--osrc-probe", action="store_true",
                     help="run only five OSRC preconditioner applies of the probe workload (for kernel traces)")
+    ap.add_argument("--hmatrix-probe", action="store_true",
+                    help="run only the hierarchical-matrix build of the probe workload (eps 1e-4, leaves of 64, "
+                         "eta 2) and one compressed apply against the on-the-fly one (for kernel traces)")
     ap.add_argument("--assembled-kernels-only", action="store_true",
                     help="assembled section without its solves (GEMV and GEMM launches only, for counter runs)")
     args = ap.parse_args()
@@ -257,6 +260,17 @@ def main():
         P = bem.Problem.from_config(prob, device=True, autotune=False)
         res = osrc_apply_ms(P, prob, bem, torch, 8 if rib else 4, 1.5 if rib else 0.1)
         print(json.dumps({"workload": prob.name, "osrc": res}), flush=True)
+        return
+    if args.hmatrix_probe:
+        prob = configs.ribcage(1.0) if args.probe_workload == "ribcage" else configs.config2()
+        P = bem.Problem.from_config(prob, device=True, autotune=False)
+        x = torch.from_numpy(vectors.random_complex(prob.n_unknowns, seed=0)).cuda()
+        yo = P.apply(x)
+        info, t_build = _timed(torch, lambda: P.hmatrix_build(eps=1e-4, leaf_vertices=64, eta=2.0))
+        yh = P.apply(x, kernel=bem.BEM_APPLY_HMATRIX)
+        print(json.dumps({"workload": prob.name, "hmatrix": {"build_s": t_build, "info": info,
+                                                             "rel_diff_to_on_the_fly": float((yh - yo).norm() / yo.norm())}}),
+              flush=True)
         return
     if args.traffic_probe:
         prob = configs.ribcage(1.0) if args.probe_workload == "ribcage" else configs.config2()
