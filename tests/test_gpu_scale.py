@@ -101,7 +101,8 @@ def test_config3_full_size_solve_certificate(c3, bowl):
     """The full-size stack (53,524 vertices, 107,048 unknowns), 256 pistons as
     one field, solved to 1e-5 on the on-the-fly operator: flexible GMRES whose
     outer residual is the on-the-fly apply's, with inner OSRC-preconditioned
-    GMRES on the hierarchical matrix (eps 1e-4).  The oracle certifies the
+    GMRES on the hierarchical matrix (eps 1e-4; OSRC N_Pade = 4, R_eps =
+    lambda_0 / 3, the settings of the timed solve).  The oracle certifies the
     solution on the stratified rows to twice the tolerance."""
     import paper_1910_01011_amd as bem
     prob, rows, R = c3
@@ -112,7 +113,7 @@ def test_config3_full_size_solve_certificate(c3, bowl):
     inc = bem.Incident.pistons(centres, normals, radius, 1.0, np.zeros(len(centres), dtype=int))
     b = P.rhs(inc)
     u, info = P.solve(b, bem.solve_options(tol=1e-5, restart=10, max_iter=10, precond=bem.BEM_PRECOND_OSRC,
-                                           n_pade=8, r_eps=1.5, theta=np.pi / 3,
+                                           n_pade=4, r_eps=(2.0 * np.pi / prob.k0.real) / 3.0, theta=np.pi / 3,
                                            precision=bem.BEM_PREC_HMATRIX_FGMRES, inner_tol=1e-3,
                                            inner_restart=200, inner_max_iter=1000))
     P.close()
