@@ -244,6 +244,9 @@ def main():
     ap.add_argument("--hmatrix-probe", action="store_true",
                     help="run only the hierarchical-matrix build of the probe workload (eps 1e-4, leaves of 64, "
                          "eta 2) and one compressed apply against the on-the-fly one (for kernel traces)")
+    ap.add_argument("--gemm-reference", action="store_true",
+                    help="run only torch.matmul (the vendor GEMM library) on the real-GEMM shapes of the split-BF16 "
+                         "apply (BF16 and FP32) and on square shapes, as a reference for the library's kernels")
     ap.add_argument("--assembled-kernels-only", action="store_true",
                     help="assembled section without its solves (GEMV and GEMM launches only, for counter runs)")
     args = ap.parse_args()
@@ -264,6 +267,9 @@ def main():
         P = bem.Problem.from_config(prob, device=True, autotune=False)
         res = osrc_apply_ms(P, prob, bem, torch, 8 if rib else 4, 1.5 if rib else 0.1)
         print(json.dumps({"workload": prob.name, "osrc": res}), flush=True)
+        return
+    if args.gemm_reference:
+        print(json.dumps({"gemm_reference": gemm_reference(torch)}), flush=True)
         return
     if args.hmatrix_probe:
         prob = configs.ribcage(1.0) if args.probe_workload == "ribcage" else configs.config2()
@@ -509,6 +515,40 @@ def ribcage_section(bem, torch, autotune):
                           "s_per_iteration": t_solve / max(1, info[0]["iterations"])}}
     P.close()
     return res
+
+
+def gemm_reference(torch):
+    """torch.matmul (hipBLASLt / rocBLAS underneath) on the real GEMM of the
+    split-BF16 apply at R = 256 (n x 2n times 2n x 2R, one term of the three)
+    for the 53,848- and 20,484-unknown matrices, and on square shapes: the rate
+    the vendor library reaches on this chip, beside the library's kernels.
+    Random operands; median of 5 timed launches (HIP events)."""
+    out = {}
+    torch.backends.cuda.matmul.allow_tf32 = False
+    for (M, K, N) in ((53848, 107712, 512), (20484, 40968, 512), (16384, 16384, 16384), (8192, 8192, 8192)):
+        for dt, peak in ((torch.bfloat16, BF16_PEAK_TFLOPS), (torch.float32, FP32_MFMA_PEAK_TFLOPS)):
+            if dt == torch.float32 and M * K > 3e9:
+                continue
+            A = torch.randn(M, K, device="cuda").to(dt)
+            B = torch.randn(K, N, device="cuda").to(dt)
+            C = A @ B
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(5):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                C = A @ B
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            ms = float(np.median(ts))
+            tf = 2.0 * M * K * N / (ms * 1e-3) / 1e12
+            key = f"{str(dt).split('.')[-1]}_{M}x{K}x{N}"
+            out[key] = {"ms": ms, "TFLOPs": tf, "frac": tf / peak, "peak": peak}
+            log(f"torch.matmul {key}: {ms:.3f} ms, {tf:.0f} TFLOP/s, {tf / peak:.3f} of peak")
+            del A, B, C
+            torch.cuda.empty_cache()
+    return out
 
 
 def ribcage_assembled_section(bem, torch, autotune):
