@@ -195,7 +195,8 @@ def ribcage_time_to_solve(P, prob, bem, torch):
     solve."""
     from bem_inputs import pistons
     c, n, a = pistons.bowl_array()
-    b = P.rhs(bem.Incident.pistons(c, n, a, 1.0, np.zeros(len(c), dtype=int)))
+    b, t_rhs = _timed(torch, lambda: P.rhs(bem.Incident.pistons(c, n, a, 1.0, np.zeros(len(c), dtype=int))))
+    log(f"ribcage right-hand side (256 pistons, 24 monopoles each) {t_rhs:.2f} s")
     hinfo, t_build = _timed(torch, lambda: P.hmatrix_build(eps=1e-4, leaf_vertices=64, eta=2.0))
     log(f"ribcage H-matrix: {hinfo['bytes'] / 1e9:.1f} GB, build {t_build:.1f} s")
     r_eps = (2.0 * np.pi / prob.k0.real) / 3.0
@@ -206,7 +207,7 @@ def ribcage_time_to_solve(P, prob, bem, torch):
     log(f"ribcage time-to-solve {t:.1f} s, residual {info[0]['rel_residual']:.2e}")
     return {"tol": 1e-5, "time_to_solve_s": t, "converged": info[0]["converged"],
             "rel_residual": info[0]["rel_residual"], "outer_iterations": info[0]["iterations"],
-            "setup_hmatrix_build_s": t_build,
+            "setup_hmatrix_build_s": t_build, "setup_rhs_s": t_rhs,
             "hmatrix": {k: hinfo[k] for k in ("bytes", "dense_bytes", "n_lowrank", "n_dense", "max_rank")},
             "method": "flexible GMRES(10), outer Arnoldi and residual on the on-the-fly FP32 operator; inner "
                       "right-hand side: OSRC-preconditioned GMRES(200) to 1e-3 on the hierarchical matrix "

@@ -14,6 +14,7 @@
 // Points closer than 2 h_j to boundary j (h_j its mean edge length) are flagged
 // with region -1; their field is still computed, with the winding-number region.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdlib>
 #include <vector>
@@ -25,11 +26,16 @@ namespace bem {
 
 constexpr double PI_D = 3.14159265358979323846;
 
+// Device form of an incident field: plane waves keep their parameters
+// ([n_fields][5]: unit direction, amplitude); point sources and pistons become
+// one list of monopoles ([n][5]: position, complex amplitude) sorted by field,
+// fptr[f] .. fptr[f + 1] the monopoles of field f.
 struct IncDev {
     int kind;
     int n_fields;
-    int64_t n_params;
-    const double *params;   // device copy
+    const double *params;   // plane waves (device copy)
+    const double *src;      // monopoles (device copy)
+    const int32_t *fptr;
     double k0re, k0im;
 };
 
@@ -72,77 +78,59 @@ __device__ void incident(const IncDev &I, int f, const double *x, const double *
         const double kr = -I.k0im * dn, ki = I.k0re * dn;
         qr = kr * pr - ki * pi;
         qi = kr * pi + ki * pr;
-    } else if (I.kind == BEM_POINT_SOURCES) {
-        for (int64_t s = 0; s < I.n_params; ++s) {
-            const double *P = I.params + 6 * s;
-            if (int(P[5]) != f) continue;
-            monopole(x, nrm, P, P[3], P[4], I.k0re, I.k0im, pr, pi, qr, qi);
-        }
     } else {
-        // 3-point Gauss-Legendre radii on [0,1] and 8 equal angles
-        const double gx[3] = {0.11270166537925831148, 0.5, 0.88729833462074168852};
-        const double gw[3] = {0.27777777777777777778, 0.44444444444444444444, 0.27777777777777777778};
-        for (int64_t s = 0; s < I.n_params; ++s) {
-            const double *P = I.params + 10 * s;
-            if (int(P[9]) != f) continue;
-            const double *c = P, *nv = P + 3, a = P[6];
-            // orthonormal in-plane basis (e1, e2) of the disc
-            double ax[3] = {0, 0, 0};
-            const double anx = fabs(nv[0]), any = fabs(nv[1]), anz = fabs(nv[2]);
-            ax[(anx <= any && anx <= anz) ? 0 : (any <= anz ? 1 : 2)] = 1.0;
-            double e1[3] = {nv[1] * ax[2] - nv[2] * ax[1], nv[2] * ax[0] - nv[0] * ax[2], nv[0] * ax[1] - nv[1] * ax[0]};
-            const double l1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
-            for (int d = 0; d < 3; ++d) e1[d] /= l1;
-            const double e2[3] = {nv[1] * e1[2] - nv[2] * e1[1], nv[2] * e1[0] - nv[0] * e1[2], nv[0] * e1[1] - nv[1] * e1[0]};
-            // amplitude (-i k0 / 2 pi) * 4 pi * w_r * rho * dtheta * A  (G carries 1/(4 pi))
-            const double kr = I.k0re, ki = I.k0im;
-            const double br = 2.0 * ki, bi = -2.0 * kr;   // -2 i k0
-            for (int i = 0; i < 3; ++i) {
-                const double rho = a * gx[i];
-                const double wgt = a * gw[i] * rho * (2.0 * PI_D / 8.0);
-                for (int j = 0; j < 8; ++j) {
-                    const double th = 2.0 * PI_D * j / 8.0;
-                    const double ct = cos(th), st = sin(th);
-                    double src[3];
-                    for (int d = 0; d < 3; ++d) src[d] = c[d] + rho * (ct * e1[d] + st * e2[d]);
-                    const double amr = wgt * (br * P[7] - bi * P[8]), ami = wgt * (br * P[8] + bi * P[7]);
-                    monopole(x, nrm, src, amr, ami, I.k0re, I.k0im, pr, pi, qr, qi);
-                }
-            }
+        for (int32_t s = I.fptr[f]; s < I.fptr[f + 1]; ++s) {
+            const double *S = I.src + 5 * int64_t(s);
+            monopole(x, nrm, S, S[3], S[4], I.k0re, I.k0im, pr, pi, qr, qi);
         }
     }
 }
 
-// one thread per (vertex, field)
-__global__ void k_rhs(IncDev I, const double *__restrict__ verts, const int32_t *__restrict__ tris,
-                      const double *__restrict__ area, const double *__restrict__ normal,
-                      const int32_t *__restrict__ v2t_ptr, const int32_t *__restrict__ v2t,
-                      const int32_t *__restrict__ rowD, const int32_t *__restrict__ rowN, int64_t NV, int64_t N,
-                      double2 *__restrict__ b)
+// p_inc and dp_inc/dn of every field of [f0, f0 + gridDim.y) at every
+// quadrature point 6 t + q: PQ[(f - f0) M + i] = (p, dp/dn) as two double2
+__global__ void k_inc_points(IncDev I, const double *__restrict__ verts, const int32_t *__restrict__ tris,
+                             const double *__restrict__ normal, int64_t M, int f0, double2 *__restrict__ PQ)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const int64_t t = i / 6;
+    const int q = int(i - 6 * t);
+    const int f = f0 + int(blockIdx.y);
+    double x[3];
+    for (int d = 0; d < 3; ++d)
+        x[d] = q6_bary[q][0] * verts[3 * int64_t(tris[3 * t]) + d] + q6_bary[q][1] * verts[3 * int64_t(tris[3 * t + 1]) + d] +
+               q6_bary[q][2] * verts[3 * int64_t(tris[3 * t + 2]) + d];
+    double pr, pi, qr, qi;
+    incident(I, f, x, normal + 3 * t, pr, pi, qr, qi);
+    double2 *o = PQ + 2 * (int64_t(blockIdx.y) * M + i);
+    o[0] = make_double2(pr, pi);
+    o[1] = make_double2(qr, qi);
+}
+
+// b_D[g] = sum over the corners (t, a) at g and the points q of
+// w_t,q lambda_a(q) p_inc, b_N likewise with dp_inc/dn: one thread per
+// (vertex, field of the chunk), the point values from k_inc_points
+__global__ void k_rhs_scatter(const double2 *__restrict__ PQ, int64_t M, int f0, const double *__restrict__ area,
+                              const int32_t *__restrict__ v2t_ptr, const int32_t *__restrict__ v2t,
+                              const int32_t *__restrict__ rowD, const int32_t *__restrict__ rowN, int64_t NV, int64_t N,
+                              double2 *__restrict__ b)
 {
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int f = blockIdx.y;
     if (g >= NV) return;
+    const int64_t fl = blockIdx.y, f = f0 + fl;
     double bDr = 0, bDi = 0, bNr = 0, bNi = 0;
     for (int32_t k = v2t_ptr[g]; k < v2t_ptr[g + 1]; ++k) {
         const int64_t t = v2t[k] / 3;
         const int a = v2t[k] - 3 * int(t);
-        double P[3][3];
-        for (int c = 0; c < 3; ++c)
-            for (int d = 0; d < 3; ++d) P[c][d] = verts[3 * int64_t(tris[3 * t + c]) + d];
-        const double *n = normal + 3 * t;
         for (int q = 0; q < 6; ++q) {
-            double x[3];
-            for (int d = 0; d < 3; ++d) x[d] = q6_bary[q][0] * P[0][d] + q6_bary[q][1] * P[1][d] + q6_bary[q][2] * P[2][d];
-            double pr, pi, qr, qi;
-            incident(I, f, x, n, pr, pi, qr, qi);
+            const double2 *v = PQ + 2 * (fl * M + 6 * t + q);
             const double w = area[t] * q6_w[q] * q6_bary[q][a];
-            bDr += w * pr; bDi += w * pi;
-            bNr += w * qr; bNi += w * qi;
+            bDr += w * v[0].x; bDi += w * v[0].y;
+            bNr += w * v[1].x; bNi += w * v[1].y;
         }
     }
-    b[int64_t(f) * N + rowD[g]] = make_double2(bDr, bDi);
-    b[int64_t(f) * N + rowN[g]] = make_double2(bNr, bNi);
+    b[f * N + rowD[g]] = make_double2(bDr, bDi);
+    b[f * N + rowN[g]] = make_double2(bNr, bNi);
 }
 
 // device scratch of one call, freed on every exit path (hipFree waits for the device)
@@ -157,45 +145,110 @@ struct DevScratch {
     }
 };
 
+// Plane waves: directions normalised.  Point sources and pistons: one list of
+// monopoles sorted by field (stable: the order of the parameters within a
+// field); a piston is 3 Gauss-Legendre radii (weight r dr) times 8 equal
+// angles of its disc, amplitude (-i k0 / 2 pi) * 4 pi * w_r r dtheta * A (G
+// carries 1/(4 pi)).  Sources whose field index is outside [0, n_fields)
+// contribute to no field.  One device allocation (*d_params) holds it all.
 static IncDev upload_incident(bem_problem &p, const bem_incident &inc, double **d_params)
 {
-    int64_t cols = inc.kind == BEM_PLANE_WAVE ? 5 : (inc.kind == BEM_POINT_SOURCES ? 6 : 10);
-    int64_t rows = inc.kind == BEM_PLANE_WAVE ? inc.n_fields : inc.n_params;
-    std::vector<double> h(inc.params, inc.params + rows * cols);
-    if (inc.kind == BEM_PLANE_WAVE)
-        for (int64_t f = 0; f < rows; ++f) {
+    IncDev I{};
+    I.kind = inc.kind;
+    I.n_fields = inc.n_fields;
+    I.k0re = p.k0re;
+    I.k0im = p.k0im;
+    if (inc.kind == BEM_PLANE_WAVE) {
+        std::vector<double> h(inc.params, inc.params + int64_t(inc.n_fields) * 5);
+        for (int64_t f = 0; f < inc.n_fields; ++f) {
             double *d = &h[5 * f];
             const double l = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
             for (int c = 0; c < 3; ++c) d[c] /= l;
         }
-    if (inc.kind == BEM_PISTON_ARRAY)
-        for (int64_t s = 0; s < rows; ++s) {
-            double *d = &h[10 * s + 3];
-            const double l = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            for (int c = 0; c < 3; ++c) d[c] /= l;
+        dmalloc(reinterpret_cast<void **>(d_params), std::max<size_t>(1, h.size()) * sizeof(double));
+        BEM_HIP(hipMemcpyAsync(*d_params, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, p.stream));
+        I.params = *d_params;
+        return I;
+    }
+    const int64_t cols = inc.kind == BEM_POINT_SOURCES ? 6 : 10;
+    const int nf = inc.n_fields;
+    std::vector<std::vector<double>> per(size_t(std::max(1, nf)));
+    for (int64_t s = 0; s < inc.n_params; ++s) {
+        const double *P = inc.params + s * cols;
+        const double fd = P[cols - 1];
+        if (!(fd >= 0.0) || int64_t(fd) >= nf) continue;
+        std::vector<double> &o = per[size_t(int64_t(fd))];
+        if (inc.kind == BEM_POINT_SOURCES) {
+            o.insert(o.end(), {P[0], P[1], P[2], P[3], P[4]});
+            continue;
         }
-    dmalloc(reinterpret_cast<void **>(d_params), std::max<size_t>(1, h.size()) * sizeof(double));
-    BEM_HIP(hipMemcpyAsync(*d_params, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, p.stream));
-    IncDev I;
-    I.kind = inc.kind;
-    I.n_fields = inc.n_fields;
-    I.n_params = rows;
-    I.params = *d_params;
-    I.k0re = p.k0re;
-    I.k0im = p.k0im;
+        double nv[3] = {P[3], P[4], P[5]};
+        const double ln = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+        for (int d = 0; d < 3; ++d) nv[d] /= ln;
+        // orthonormal in-plane basis (e1, e2) of the disc
+        double ax[3] = {0, 0, 0};
+        const double anx = std::fabs(nv[0]), any = std::fabs(nv[1]), anz = std::fabs(nv[2]);
+        ax[(anx <= any && anx <= anz) ? 0 : (any <= anz ? 1 : 2)] = 1.0;
+        double e1[3] = {nv[1] * ax[2] - nv[2] * ax[1], nv[2] * ax[0] - nv[0] * ax[2], nv[0] * ax[1] - nv[1] * ax[0]};
+        const double l1 = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+        for (int d = 0; d < 3; ++d) e1[d] /= l1;
+        const double e2[3] = {nv[1] * e1[2] - nv[2] * e1[1], nv[2] * e1[0] - nv[0] * e1[2],
+                              nv[0] * e1[1] - nv[1] * e1[0]};
+        const double gx[3] = {0.11270166537925831148, 0.5, 0.88729833462074168852};
+        const double gw[3] = {0.27777777777777777778, 0.44444444444444444444, 0.27777777777777777778};
+        const double a = P[6], br = 2.0 * p.k0im, bi = -2.0 * p.k0re;   // -2 i k0
+        for (int i = 0; i < 3; ++i) {
+            const double rho = a * gx[i];
+            const double wgt = a * gw[i] * rho * (2.0 * PI_D / 8.0);
+            for (int j = 0; j < 8; ++j) {
+                const double th = 2.0 * PI_D * j / 8.0;
+                const double ct = std::cos(th), st = std::sin(th);
+                o.insert(o.end(), {P[0] + rho * (ct * e1[0] + st * e2[0]), P[1] + rho * (ct * e1[1] + st * e2[1]),
+                                   P[2] + rho * (ct * e1[2] + st * e2[2]), wgt * (br * P[7] - bi * P[8]),
+                                   wgt * (br * P[8] + bi * P[7])});
+            }
+        }
+    }
+    std::vector<double> src;
+    std::vector<int32_t> fptr(size_t(nf) + 1, 0);
+    for (int f = 0; f < nf; ++f) {
+        src.insert(src.end(), per[size_t(f)].begin(), per[size_t(f)].end());
+        if (src.size() / 5 > size_t(INT32_MAX)) throw Error{BEM_ERR_UNSUPPORTED, "incident field: too many sources"};
+        fptr[size_t(f) + 1] = int32_t(src.size() / 5);
+    }
+    const size_t nsrc = src.size();
+    const size_t ptr_doubles = (fptr.size() * sizeof(int32_t) + sizeof(double) - 1) / sizeof(double);
+    dmalloc(reinterpret_cast<void **>(d_params), std::max<size_t>(1, nsrc + ptr_doubles) * sizeof(double));
+    if (nsrc) BEM_HIP(hipMemcpyAsync(*d_params, src.data(), nsrc * sizeof(double), hipMemcpyHostToDevice, p.stream));
+    int32_t *dptr = reinterpret_cast<int32_t *>(*d_params + nsrc);
+    BEM_HIP(hipMemcpyAsync(dptr, fptr.data(), fptr.size() * sizeof(int32_t), hipMemcpyHostToDevice, p.stream));
+    // the host vectors go out of scope: the copies must be done first
+    BEM_HIP(hipStreamSynchronize(p.stream));
+    I.src = *d_params;
+    I.fptr = dptr;
     return I;
 }
 
 void launch_rhs(bem_problem &p, const bem_incident &inc, double2 *b)
 {
     double *d_params = nullptr;
-    DevScratch params_mem;
+    DevScratch params_mem, pq_mem;
     IncDev I = upload_incident(p, inc, &d_params);
     params_mem.p = d_params;
-    const int B = 128;
-    k_rhs<<<dim3(blocks_1d(p.NV, B), unsigned(inc.n_fields)), dim3(B), 0, p.stream>>>(
-        I, p.d_verts, p.d_tris, p.d_area, p.d_normal, p.d_v2t_ptr, p.d_v2t, p.d_rowD, p.d_rowN, p.NV, p.N, b);
-    BEM_HIP(hipGetLastError());
+    // point values of a chunk of fields (at most 1 GiB), then the scatter
+    const int64_t per_field = 2 * p.M * int64_t(sizeof(double2));
+    const int chunk = int(std::max<int64_t>(1, std::min<int64_t>(inc.n_fields, (int64_t(1) << 30) / per_field)));
+    dmalloc(&pq_mem.p, size_t(chunk) * size_t(per_field));
+    double2 *PQ = static_cast<double2 *>(pq_mem.p);
+    for (int f0 = 0; f0 < inc.n_fields; f0 += chunk) {
+        const int nf = std::min(chunk, inc.n_fields - f0);
+        k_inc_points<<<dim3(blocks_1d(p.M, 128), unsigned(nf)), dim3(128), 0, p.stream>>>(I, p.d_verts, p.d_tris,
+                                                                                         p.d_normal, p.M, f0, PQ);
+        BEM_HIP(hipGetLastError());
+        k_rhs_scatter<<<dim3(blocks_1d(p.NV, 128), unsigned(nf)), dim3(128), 0, p.stream>>>(
+            PQ, p.M, f0, p.d_area, p.d_v2t_ptr, p.d_v2t, p.d_rowD, p.d_rowN, p.NV, p.N, b);
+        BEM_HIP(hipGetLastError());
+    }
     BEM_HIP(hipStreamSynchronize(p.stream));
 }
 
