@@ -167,6 +167,7 @@ static IncDev upload_incident(bem_problem &p, const bem_incident &inc, double **
         }
         dmalloc(reinterpret_cast<void **>(d_params), std::max<size_t>(1, h.size()) * sizeof(double));
         BEM_HIP(hipMemcpyAsync(*d_params, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, p.stream));
+        BEM_HIP(hipStreamSynchronize(p.stream));   // h is pageable and goes out of scope
         I.params = *d_params;
         return I;
     }
