@@ -115,7 +115,7 @@ def test_config3_full_size_solve_certificate(c3, bowl):
     u, info = P.solve(b, bem.solve_options(tol=1e-5, restart=10, max_iter=10, precond=bem.BEM_PRECOND_OSRC,
                                            n_pade=4, r_eps=(2.0 * np.pi / prob.k0.real) / 3.0, theta=np.pi / 3,
                                            precision=bem.BEM_PREC_HMATRIX_FGMRES, inner_tol=1e-3,
-                                           inner_restart=200, inner_max_iter=1000))
+                                           inner_restart=300, inner_max_iter=1000))
     P.close()
     u = np.ravel(u)
     print(f"ribcage h=1 H-inner OSRC FGMRES: {info[0]}", flush=True)
