@@ -245,6 +245,9 @@ def main():
     ap.add_argument("--hmatrix-probe", action="store_true",
                     help="run only the hierarchical-matrix build of the probe workload (eps 1e-4, leaves of 64, "
                          "eta 2) and one compressed apply against the on-the-fly one (for kernel traces)")
+    ap.add_argument("--solve-probe", action="store_true",
+                    help="run only the rib-cage stack's time-to-solve with its set-up (right-hand side and "
+                         "hierarchical-matrix build), for kernel traces")
     ap.add_argument("--gemm-reference", action="store_true",
                     help="run only torch.matmul (the vendor GEMM library) on the real-GEMM shapes of the split-BF16 "
                          "apply (BF16 and FP32) and on square shapes, as a reference for the library's kernels")
@@ -271,6 +274,12 @@ def main():
         return
     if args.gemm_reference:
         print(json.dumps({"gemm_reference": gemm_reference(torch)}), flush=True)
+        return
+    if args.solve_probe:
+        prob = configs.ribcage(1.0)
+        P = bem.Problem.from_config(prob, device=True, autotune=not args.no_autotune)
+        print(json.dumps({"workload": prob.name, "time_to_solve": ribcage_time_to_solve(P, prob, bem, torch)}),
+              flush=True)
         return
     if args.hmatrix_probe:
         prob = configs.ribcage(1.0) if args.probe_workload == "ribcage" else configs.config2()

@@ -61,6 +61,7 @@ void free_problem(bem_problem *p)
     for (void *q : ptrs)
         if (q) bem::dfree(q);
     if (p->hm) bem::hmatrix_free(p->hm);
+    if (p->osrc) bem::osrc_free(p->osrc, p->stream);
     if (p->batch) bem::batch_detach(*p);
     for (auto &e : p->ev)
         if (e) (void)hipEventDestroy(e);
@@ -955,12 +956,14 @@ bem_status bem_apply_preconditioner(bem_problem *p, const bem_solve_opts *opts, 
         const size_t n = size_t(n_rhs) * p->N;
         if (p->flags & BEM_DEVICE_PTRS) {
             bem::osrc_apply(*p, op, reinterpret_cast<const double2 *>(y), reinterpret_cast<double2 *>(out), n_rhs);
+            BEM_HIP(hipStreamSynchronize(p->stream));
         } else {
             double2 *dy = nullptr, *dout = nullptr;
             dev_alloc(&dy, n);
             dev_alloc(&dout, n);
             BEM_HIP(hipMemcpy(dy, y, n * sizeof(double2), hipMemcpyHostToDevice));
             bem::osrc_apply(*p, op, dy, dout, n_rhs);
+            BEM_HIP(hipStreamSynchronize(p->stream));
             BEM_HIP(hipMemcpy(out, dout, n * sizeof(double2), hipMemcpyDeviceToHost));
             bem::dfree(dy);
             bem::dfree(dout);

@@ -144,6 +144,7 @@ struct HBlock {
     int64_t zoff;      // offset of the block's 2 m products in the product buffer
 };
 struct HMatrix;
+struct OsrcWork;   // per-problem OSRC workspace (k_osrc.hip)
 
 struct DomInfo {
     int64_t nv, nt;        // vertices / triangles of the domain
@@ -226,6 +227,7 @@ struct bem_problem {
     int64_t a_nnz = 0;
     int *d_cg_chunks = nullptr;     // [chunks][8] row chunks of the batched COCG (domain, rows, first, count)
     int cg_n_chunks = 0;
+    bem::OsrcWork *osrc = nullptr;  // buffers, coefficients and captured COCG iterations of the last OSRC form
 
     // hierarchical matrix (bem_hmatrix_build)
     bem::HMatrix *hm = nullptr;
@@ -397,7 +399,9 @@ void batch_detach(bem_problem &p);
 
 // OSRC preconditioner (k_osrc.hip): Out = P Y for R residual vectors
 void osrc_setup(bem_problem &p);
+// enqueued on the problem's stream (the host waits only for the COCG convergence tests)
 void osrc_apply(bem_problem &p, const OsrcParams &o, const double2 *Y, double2 *Out, int R);
+void osrc_free(OsrcWork *w, hipStream_t s);
 
 // incident fields and right-hand sides (k_field.hip)
 void launch_rhs(bem_problem &p, const bem_incident &inc, double2 *b);

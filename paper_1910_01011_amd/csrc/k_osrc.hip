@@ -186,19 +186,6 @@ static unsigned nb(int64_t n) { return blocks_1d(n, 256); }
 constexpr int CG_ROWS = 256;   // rows per chunk of the batched COCG (its workgroup size)
 constexpr int CG_NNZ_STEP = 8;   // row entries loaded together in the sparse product
 
-// stream-ordered scratch on the stream of the current problem
-thread_local hipStream_t t_osrc_stream = nullptr;
-
-struct OsrcBuf {
-    double2 *p = nullptr;
-    hipStream_t s;
-    explicit OsrcBuf(size_t n) : s(t_osrc_stream)
-    {
-        BEM_HIP(hipMallocAsync(reinterpret_cast<void **>(&p), std::max<size_t>(1, n) * sizeof(double2), s));
-    }
-    ~OsrcBuf() { (void)hipFreeAsync(p, s); }
-};
-
 void osrc_setup(bem_problem &p)
 {
     if (p.d_aptr) return;
@@ -543,31 +530,74 @@ static hipGraphExec_t cg_chunk_graph(const CgArgs &a, dim3 grid, dim3 block)
     return exec;
 }
 
-static void cocg_batch(bem_problem &p, int G, const std::vector<cd> &c, const double2 *B, double2 *X, double tol,
-                       int maxit)
+// Buffers of one batched COCG over G systems with fixed shifts, the captured
+// iterations on them (for one right-hand side array B, solution array X,
+// tolerance and iteration cap) and the iteration count of the batch's last
+// solve (its slowest block).
+struct CgWork {
+    int G = 0;
+    double2 *c = nullptr, *R = nullptr, *P = nullptr, *Q = nullptr, *Z = nullptr, *rho = nullptr;
+    double *part1 = nullptr, *part2 = nullptr, *bn2 = nullptr;
+    int32_t *flags = nullptr;   // done [G][n_dom], then its [G][n_dom]
+    hipGraphExec_t exec = nullptr;
+    const double2 *gB = nullptr;
+    double2 *gX = nullptr;
+    double gtol = 0.0;
+    int gmaxit = 0;
+    int hint = 0;
+};
+
+template <typename T>
+static void cg_dalloc(T **q, size_t n, hipStream_t s)
 {
-    t_osrc_stream = p.stream;
-    const int64_t n = p.NV;
-    hipStream_t s = p.stream;
-    const int n_dom = int(p.doms.size());
-    const int C = p.cg_n_chunks;
-    if (G < 1) return;
+    BEM_HIP(hipMallocAsync(reinterpret_cast<void **>(q), std::max<size_t>(1, n) * sizeof(T), s));
+}
+
+static void cg_release(CgWork &w, hipStream_t s)
+{
+    if (w.exec) (void)hipGraphExecDestroy(w.exec);
+    w.exec = nullptr;
+    void *ptrs[] = {w.c, w.R, w.P, w.Q, w.Z, w.rho, w.part1, w.part2, w.bn2, w.flags};
+    for (void *q : ptrs)
+        if (q) (void)hipFreeAsync(q, s);
+    w = CgWork{};
+}
+
+// Workspace for G systems with shifts c (uploaded here; the host waits for the
+// copy once).
+static void cg_prepare(bem_problem &p, CgWork &w, const std::vector<cd> &c, hipStream_t s)
+{
+    const int G = int(c.size());
     if (G > 65535) throw Error{BEM_ERR_UNSUPPORTED, "OSRC: too many systems in one batch"};
-    const size_t tot = size_t(G) * n;
-    OsrcBuf R(tot), Pp(2 * tot), Q(tot), Z(tot), cdev{size_t(G)}, rho(size_t(2) * G * n_dom);
-    struct DBuf {
-        double *p = nullptr;
-        hipStream_t s;
-        DBuf(size_t k, hipStream_t st) : s(st)
-        {
-            BEM_HIP(hipMallocAsync(reinterpret_cast<void **>(&p), std::max<size_t>(1, k) * sizeof(double), s));
-        }
-        ~DBuf() { (void)hipFreeAsync(p, s); }
-    } part1(size_t(2) * G * C, s), part2(size_t(3) * G * C, s), bn2(size_t(G) * n_dom, s),
-        flags(size_t(G) * n_dom, s);   // done and its flags: two int32 per double
+    const size_t tot = size_t(G) * p.NV, n_dom = p.doms.size(), C = size_t(p.cg_n_chunks);
+    w.G = G;
+    cg_dalloc(&w.c, G, s);
+    cg_dalloc(&w.R, tot, s);
+    cg_dalloc(&w.P, 2 * tot, s);
+    cg_dalloc(&w.Q, tot, s);
+    cg_dalloc(&w.Z, tot, s);
+    cg_dalloc(&w.rho, 2 * G * n_dom, s);
+    cg_dalloc(&w.part1, 2 * G * C, s);
+    cg_dalloc(&w.part2, 3 * G * C, s);
+    cg_dalloc(&w.bn2, G * n_dom, s);
+    cg_dalloc(&w.flags, 2 * G * n_dom, s);
     std::vector<double2> t(G);
     for (int g = 0; g < G; ++g) t[g] = make_double2(c[g].real(), c[g].imag());
-    BEM_HIP(hipMemcpyAsync(cdev.p, t.data(), G * sizeof(double2), hipMemcpyHostToDevice, s));
+    BEM_HIP(hipMemcpyAsync(w.c, t.data(), G * sizeof(double2), hipMemcpyHostToDevice, s));
+    BEM_HIP(hipStreamSynchronize(s));
+}
+
+// The batched COCG for B on the systems of w, into X.  Iteration 0 runs
+// eagerly, then replays of CG_CHECK iterations; the host reads the blocks'
+// flags only once as many iterations as the batch's last solve took have been
+// enqueued, then after every replay.  Replays after a block has stopped leave
+// it untouched, so the result does not depend on when the host looks.
+static void cocg_run(bem_problem &p, CgWork &w, const double2 *B, double2 *X, double tol, int maxit)
+{
+    hipStream_t s = p.stream;
+    const int n_dom = int(p.doms.size());
+    const int C = p.cg_n_chunks, G = w.G;
+    if (G < 1) return;
     CgArgs a{};
     a.aptr = p.d_aptr;
     a.acol = p.d_acol;
@@ -577,20 +607,20 @@ static void cocg_batch(bem_problem &p, int G, const std::vector<cd> &c, const do
     a.chunks = reinterpret_cast<const CgChunk *>(p.d_cg_chunks);
     a.n_chunks = C;
     a.n_dom = n_dom;
-    a.n = n;
-    a.c = cdev.p;
+    a.n = p.NV;
+    a.c = w.c;
     a.B = B;
     a.X = X;
-    a.R = R.p;
-    a.P = Pp.p;
-    a.Q = Q.p;
-    a.Z = Z.p;
-    a.part1 = part1.p;
-    a.part2 = part2.p;
-    a.bn2 = bn2.p;
-    a.rho = rho.p;
-    a.done = reinterpret_cast<int32_t *>(flags.p);
-    a.its = a.done + size_t(G) * n_dom;
+    a.R = w.R;
+    a.P = w.P;
+    a.Q = w.Q;
+    a.Z = w.Z;
+    a.part1 = w.part1;
+    a.part2 = w.part2;
+    a.bn2 = w.bn2;
+    a.rho = w.rho;
+    a.done = w.flags;
+    a.its = w.flags + size_t(G) * n_dom;
     a.tol = tol;
     a.maxit = maxit;
     const dim3 grid{unsigned(C), unsigned(G), 1u}, block{unsigned(CG_ROWS), 1u, 1u};
@@ -598,54 +628,103 @@ static void cocg_batch(bem_problem &p, int G, const std::vector<cd> &c, const do
     BEM_HIP(hipGetLastError());
     k_cg_init_block<<<grid, block, 0, s>>>(a);
     BEM_HIP(hipGetLastError());
-    // CG_CHECK iterations (3 launches each) as one graph, replayed until every
-    // block is done: the launches of a chunk reach the GPU back to back instead
-    // of one host call each.  The graph holds kernel nodes only; the parity of
-    // node i is i & 1 and every chunk starts at an even iteration.
-    // BEM_COCG_EAGER=1 launches the same kernels one by one instead (the
-    // reference the graph replays are tested against)
+    // CG_CHECK iterations (2 launches each) as one graph, captured once per
+    // (B, X, tol, maxit) of this workspace: the launches of a replay reach the
+    // GPU back to back instead of one host call each.  The graph holds kernel
+    // nodes only; the parity of node i is i & 1 and every replay starts at an
+    // even iteration.  BEM_COCG_EAGER=1 launches the same kernels one by one
+    // instead (the reference the graph replays are tested against)
     const char *ev = std::getenv("BEM_COCG_EAGER");
     const bool eager = ev && ev[0] == '1';
-    hipGraphExec_t exec = eager ? nullptr : cg_chunk_graph(a, grid, block);
-    struct ExecGuard {
-        hipGraphExec_t e;
-        ~ExecGuard()
-        {
-            if (e) (void)hipGraphExecDestroy(e);
-        }
-    } exec_guard{exec};
-    std::vector<int32_t> done(size_t(G) * n_dom);
+    if (!eager && (!w.exec || w.gB != B || w.gX != X || w.gtol != tol || w.gmaxit != maxit)) {
+        if (w.exec) (void)hipGraphExecDestroy(w.exec);
+        w.exec = nullptr;
+        w.exec = cg_chunk_graph(a, grid, block);
+        w.gB = B;
+        w.gX = X;
+        w.gtol = tol;
+        w.gmaxit = maxit;
+    }
     k_cg_direction_spmv<<<grid, block, 0, s>>>(a, 0, 1);   // iteration 0: p = z
     k_cg_update<<<grid, block, 0, s>>>(a, 0);
     BEM_HIP(hipGetLastError());
-    for (int it = 1; it < maxit; it += CG_CHECK) {
-        if (eager) {
-            for (int i = 1; i <= CG_CHECK; ++i) {
-                k_cg_direction_spmv<<<grid, block, 0, s>>>(a, i & 1, 0);
-                k_cg_update<<<grid, block, 0, s>>>(a, i & 1);
+    std::vector<int32_t> fl(size_t(2) * G * n_dom);
+    const auto done = fl.begin(), its = fl.begin() + ptrdiff_t(G) * n_dom;
+    for (int it = 1; it < maxit;) {
+        do {
+            if (eager) {
+                for (int i = 1; i <= CG_CHECK; ++i) {
+                    k_cg_direction_spmv<<<grid, block, 0, s>>>(a, i & 1, 0);
+                    k_cg_update<<<grid, block, 0, s>>>(a, i & 1);
+                }
+                BEM_HIP(hipGetLastError());
+            } else {
+                BEM_HIP(hipGraphLaunch(w.exec, s));
             }
-            BEM_HIP(hipGetLastError());
-        } else {
-            BEM_HIP(hipGraphLaunch(exec, s));
-        }
-        BEM_HIP(hipMemcpyAsync(done.data(), a.done, done.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            it += CG_CHECK;
+        } while (it < w.hint && it < maxit);
+        BEM_HIP(hipMemcpyAsync(fl.data(), w.flags, fl.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         BEM_HIP(hipStreamSynchronize(s));
-        if (std::all_of(done.begin(), done.end(), [](int32_t f) { return f != 0; })) break;
+        if (std::all_of(done, its, [](int32_t f) { return f != 0; })) break;
     }
+    w.hint = *std::max_element(its, fl.end());
 }
 
-void osrc_apply(bem_problem &p, const OsrcParams &o, const double2 *Y, double2 *Out, int R)
+// Per-problem OSRC workspace of one parameter set and number of vectors: the
+// vectors of the apply, the Pade coefficients on the device and the two COCG
+// batches (the mass solves and the shifted Pade systems).  Kept on the
+// problem while it takes at most OSRC_KEEP_BYTES, else built for the call.
+constexpr size_t OSRC_KEEP_BYTES = size_t(2) << 30;
+
+struct OsrcWork {
+    int R = 0, L = 0, cg_maxit = 0;
+    double r_eps = 0.0, theta = 0.0, cg_tol = 0.0;
+    double2 *U = nullptr, *Z = nullptr, *Bt = nullptr, *T = nullptr, *Al = nullptr, *coef = nullptr,
+            *rootD = nullptr, *WN = nullptr;
+    cd C0, ik, inv;
+    CgWork mass, pade;
+};
+
+static size_t osrc_bytes(const bem_problem &p, int R, int L)
 {
-    osrc_setup(p);
-    t_osrc_stream = p.stream;
-    const int64_t n = p.NV;
+    const size_t n = size_t(p.NV), G1 = size_t(2) * R, G2 = size_t(2) * R * L + R;
+    // apply vectors (U, Z, Bt, T, rootD, WN) and per batch R, P (2), Q, Z
+    return (2 * G1 + 2 * G2 + 2 * size_t(R)) * n * sizeof(double2) + 5 * (G1 + G2) * n * sizeof(double2);
+}
+
+void osrc_free(OsrcWork *w, hipStream_t s)
+{
+    if (!w) return;
+    cg_release(w->mass, s);
+    cg_release(w->pade, s);
+    void *ptrs[] = {w->U, w->Z, w->Bt, w->T, w->Al, w->coef, w->rootD, w->WN};
+    for (void *q : ptrs)
+        if (q) (void)hipFreeAsync(q, s);
+    delete w;
+}
+
+static OsrcWork *osrc_make(bem_problem &p, const OsrcParams &o, int R)
+{
     hipStream_t s = p.stream;
+    OsrcWork *raw = new OsrcWork;
+    struct Guard {
+        OsrcWork *w;
+        hipStream_t s;
+        ~Guard() { osrc_free(w, s); }
+    } guard{raw, s};
+    const int64_t n = p.NV;
     const int L = o.n_pade;
+    raw->R = R;
+    raw->L = L;
+    raw->cg_maxit = o.cg_maxit;
+    raw->r_eps = o.r_eps;
+    raw->theta = o.theta;
+    raw->cg_tol = o.cg_tol;
     // coefficients
     const cd k(p.k0re, p.k0im);
     const cd ke = k + cd(0.0, 0.4 * std::cbrt(p.k0re) * std::pow(o.r_eps, -2.0 / 3.0));
     const cd ke2 = ke * ke;
-    std::vector<cd> A(L), B(L);
+    std::vector<cd> A(L), Bc(L);
     const cd e = std::exp(cd(0.0, -o.theta)), c = e - 1.0;
     cd C0 = 1.0;
     for (int l = 1; l <= L; ++l) {
@@ -654,60 +733,92 @@ void osrc_apply(bem_problem &p, const OsrcParams &o, const double2 *Y, double2 *
         const cd D = 1.0 + b * c;
         C0 += a * c / D;
         A[l - 1] = std::exp(cd(0.0, -o.theta / 2.0)) * a / (D * D);
-        B[l - 1] = e * b / D;
+        Bc[l - 1] = e * b / D;
     }
-    C0 *= std::exp(cd(0.0, o.theta / 2.0));
-    const cd ik = cd(0.0, 1.0) * k;
-    // z = M^-1 (D rows, N rows)
-    OsrcBuf U(size_t(2 * R) * n), Z(size_t(2 * R) * n);
-    k_osrc_split<<<dim3(nb(n * R)), dim3(256), 0, s>>>(Y, p.d_rowD, p.d_rowN, n, p.N, R, U.p);
-    BEM_HIP(hipGetLastError());
-    cocg_batch(p, 2 * R, std::vector<cd>(2 * R, cd(0.0)), U.p, Z.p, o.cg_tol, o.cg_maxit);
-    // one batch: t_(v,l) = (M - B_l S')^-1 S' z_v for both rows of every vector,
-    // and w0_r = (M - S')^-1 M z_(N rows) (see k_osrc_ntd)
+    raw->C0 = C0 * std::exp(cd(0.0, o.theta / 2.0));
+    raw->ik = cd(0.0, 1.0) * k;
+    raw->inv = 1.0 / ke2;
     const int64_t nt = int64_t(2 * R) * L;   // Pade systems
-    OsrcBuf Bt(size_t(nt + R) * n), T(size_t(nt + R) * n);
-    const cd inv = 1.0 / ke2;
-    if (L > 0) {
-        k_osrc_sprime<<<dim3(nb(n * 2 * R)), dim3(256), 0, s>>>(p.d_aptr, p.d_acol, p.d_Sv, Z.p, n, 2 * R, L,
-                                                                make_double2(inv.real(), inv.imag()), Bt.p);
-        BEM_HIP(hipGetLastError());
-    }
-    k_mass_nrows<<<dim3(nb(n * R)), dim3(256), 0, s>>>(p.d_aptr, p.d_acol, p.d_Mv, Z.p, n, R, Bt.p + nt * n);
-    BEM_HIP(hipGetLastError());
-    std::vector<cd> shifts(size_t(nt + R));
-    for (int v = 0; v < 2 * R; ++v)
-        for (int l = 0; l < L; ++l) shifts[size_t(v) * L + l] = B[l] / ke2;
-    for (int r = 0; r < R; ++r) shifts[size_t(nt) + r] = inv;
-    cocg_batch(p, int(nt + R), shifts, Bt.p, T.p, o.cg_tol, o.cg_maxit);
-    // D rows: i k root; N rows: wN from w0 and the t_l
-    OsrcBuf Al(size_t(std::max(L, 1))), coef(size_t(2 * std::max(L, 1))), rootD(size_t(R) * n),
-        WN(size_t(R) * n);
+    cg_dalloc(&raw->U, size_t(2 * R) * n, s);
+    cg_dalloc(&raw->Z, size_t(2 * R) * n, s);
+    cg_dalloc(&raw->Bt, size_t(nt + R) * n, s);
+    cg_dalloc(&raw->T, size_t(nt + R) * n, s);
+    cg_dalloc(&raw->Al, size_t(std::max(L, 1)), s);
+    cg_dalloc(&raw->coef, size_t(2 * std::max(L, 1)), s);
+    cg_dalloc(&raw->rootD, size_t(R) * n, s);
+    cg_dalloc(&raw->WN, size_t(R) * n, s);
     {
         std::vector<double2> t(L), cf(2 * L);
         for (int l = 0; l < L; ++l) {
             t[l] = make_double2(A[l].real(), A[l].imag());
-            const cd q = A[l] / (1.0 - B[l]);
+            const cd q = A[l] / (1.0 - Bc[l]);
             cf[2 * l] = make_double2(q.real(), q.imag());
-            cf[2 * l + 1] = make_double2(B[l].real(), B[l].imag());
+            cf[2 * l + 1] = make_double2(Bc[l].real(), Bc[l].imag());
         }
         if (L > 0) {
-            BEM_HIP(hipMemcpyAsync(Al.p, t.data(), L * sizeof(double2), hipMemcpyHostToDevice, s));
-            BEM_HIP(hipMemcpyAsync(coef.p, cf.data(), 2 * L * sizeof(double2), hipMemcpyHostToDevice, s));
+            BEM_HIP(hipMemcpyAsync(raw->Al, t.data(), L * sizeof(double2), hipMemcpyHostToDevice, s));
+            BEM_HIP(hipMemcpyAsync(raw->coef, cf.data(), 2 * L * sizeof(double2), hipMemcpyHostToDevice, s));
         }
         BEM_HIP(hipStreamSynchronize(s));
     }
-    k_osrc_combine<<<dim3(nb(n * R)), dim3(256), 0, s>>>(Z.p, T.p, Al.p, L, make_double2(C0.real(), C0.imag()),
-                                                         make_double2(ik.real(), ik.imag()), n, R, rootD.p);
+    cg_prepare(p, raw->mass, std::vector<cd>(2 * R, cd(0.0)), s);
+    std::vector<cd> shifts(size_t(nt + R));
+    for (int v = 0; v < 2 * R; ++v)
+        for (int l = 0; l < L; ++l) shifts[size_t(v) * L + l] = Bc[l] / ke2;
+    for (int r = 0; r < R; ++r) shifts[size_t(nt) + r] = raw->inv;
+    cg_prepare(p, raw->pade, shifts, s);
+    guard.w = nullptr;
+    return raw;
+}
+
+void osrc_apply(bem_problem &p, const OsrcParams &o, const double2 *Y, double2 *Out, int R)
+{
+    osrc_setup(p);
+    const int64_t n = p.NV;
+    hipStream_t s = p.stream;
+    const int L = o.n_pade;
+    const bool keep = osrc_bytes(p, R, L) <= OSRC_KEEP_BYTES;
+    OsrcWork *w = p.osrc;
+    if (!keep || !w || w->R != R || w->L != L || w->r_eps != o.r_eps || w->theta != o.theta ||
+        w->cg_tol != o.cg_tol || w->cg_maxit != o.cg_maxit) {
+        if (keep && p.osrc) {
+            osrc_free(p.osrc, s);
+            p.osrc = nullptr;
+        }
+        w = osrc_make(p, o, R);
+        if (keep) p.osrc = w;
+    }
+    struct Once {
+        OsrcWork *w;
+        hipStream_t s;
+        ~Once() { osrc_free(w, s); }   // a workspace built for this call only
+    } once{keep ? nullptr : w, s};
+    // z = M^-1 (D rows, N rows)
+    k_osrc_split<<<dim3(nb(n * R)), dim3(256), 0, s>>>(Y, p.d_rowD, p.d_rowN, n, p.N, R, w->U);
     BEM_HIP(hipGetLastError());
-    k_osrc_ntd<<<dim3(nb(n * R)), dim3(256), 0, s>>>(Z.p, T.p, T.p + nt * n, coef.p, L,
-                                                     make_double2(C0.real(), C0.imag()), n, R, WN.p);
+    cocg_run(p, w->mass, w->U, w->Z, o.cg_tol, o.cg_maxit);
+    // one batch: t_(v,l) = (M - B_l S')^-1 S' z_v for both rows of every vector,
+    // and w0_r = (M - S')^-1 M z_(N rows) (see k_osrc_ntd)
+    const int64_t nt = int64_t(2 * R) * L;   // Pade systems
+    if (L > 0) {
+        k_osrc_sprime<<<dim3(nb(n * 2 * R)), dim3(256), 0, s>>>(p.d_aptr, p.d_acol, p.d_Sv, w->Z, n, 2 * R, L,
+                                                                make_double2(w->inv.real(), w->inv.imag()), w->Bt);
+        BEM_HIP(hipGetLastError());
+    }
+    k_mass_nrows<<<dim3(nb(n * R)), dim3(256), 0, s>>>(p.d_aptr, p.d_acol, p.d_Mv, w->Z, n, R, w->Bt + nt * n);
     BEM_HIP(hipGetLastError());
-    const cd sN = 1.0 / ik;
-    k_osrc_out<<<dim3(nb(n * R)), dim3(256), 0, s>>>(rootD.p, WN.p, make_double2(sN.real(), sN.imag()), p.d_rowD,
+    cocg_run(p, w->pade, w->Bt, w->T, o.cg_tol, o.cg_maxit);
+    // D rows: i k root; N rows: wN from w0 and the t_l
+    const double2 C0 = make_double2(w->C0.real(), w->C0.imag());
+    k_osrc_combine<<<dim3(nb(n * R)), dim3(256), 0, s>>>(w->Z, w->T, w->Al, L, C0,
+                                                         make_double2(w->ik.real(), w->ik.imag()), n, R, w->rootD);
+    BEM_HIP(hipGetLastError());
+    k_osrc_ntd<<<dim3(nb(n * R)), dim3(256), 0, s>>>(w->Z, w->T, w->T + nt * n, w->coef, L, C0, n, R, w->WN);
+    BEM_HIP(hipGetLastError());
+    const cd sN = 1.0 / w->ik;
+    k_osrc_out<<<dim3(nb(n * R)), dim3(256), 0, s>>>(w->rootD, w->WN, make_double2(sN.real(), sN.imag()), p.d_rowD,
                                                      p.d_rowN, n, p.N, R, Out);
     BEM_HIP(hipGetLastError());
-    BEM_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace bem
