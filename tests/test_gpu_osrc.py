@@ -91,3 +91,38 @@ def test_osrc_graph_replays_match_eager_launches(monkeypatch):
         monkeypatch.delenv("BEM_COCG_EAGER")
         assert np.array_equal(P.precondition(Y[0], opts), graph[0])
         P.close()
+
+
+def test_osrc_workspace_follows_parameters_and_vector_count():
+    """The OSRC apply keeps its vectors, coefficients and captured COCG graphs on
+    the problem and rebuilds them when the parameters or the number of vectors
+    change.  Applies that alternate between two parameter sets and between one
+    and two vectors give bitwise what a fresh problem gives for each, on both
+    the host-pointer and the device-pointer paths."""
+    import torch
+    bem = _bem()
+    prob = configs.two_spheres(level=2)
+    a = bem.solve_options(precond=bem.BEM_PRECOND_OSRC, n_pade=4, r_eps=0.1, theta=np.pi / 3, osrc_tol=1e-8)
+    b = bem.solve_options(precond=bem.BEM_PRECOND_OSRC, n_pade=2, r_eps=0.3, theta=np.pi / 4, osrc_tol=1e-6)
+    Y = vectors.random_complex(prob.n_unknowns, seed=31, n_rhs=2)
+
+    def fresh(opts, y):
+        F = bem.Problem.from_config(prob)
+        z = F.precondition(y, opts)
+        F.close()
+        return z
+
+    ref = {("a", 1): fresh(a, Y[0]), ("b", 1): fresh(b, Y[0]), ("a", 2): fresh(a, Y), ("b", 2): fresh(b, Y)}
+    P = bem.Problem.from_config(prob)
+    for key in (("a", 1), ("b", 1), ("a", 1), ("a", 2), ("b", 2), ("a", 1), ("b", 2)):
+        opts = a if key[0] == "a" else b
+        z = P.precondition(Y[0] if key[1] == 1 else Y, opts)
+        assert np.array_equal(z, ref[key]), key
+    P.close()
+    D = bem.Problem.from_config(prob, device=True)
+    for key in (("b", 2), ("a", 1), ("b", 2)):
+        opts = a if key[0] == "a" else b
+        y = torch.from_numpy(Y[0] if key[1] == 1 else Y).cuda()
+        z = D.precondition(y, opts).cpu().numpy()
+        assert np.array_equal(z, ref[key]), ("device", key)
+    D.close()
