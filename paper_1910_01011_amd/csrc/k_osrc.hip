@@ -184,7 +184,7 @@ __global__ void k_osrc_out(const double2 *__restrict__ rootD, const double2 *__r
 static unsigned nb(int64_t n) { return blocks_1d(n, 256); }
 
 constexpr int CG_ROWS = 256;   // rows per chunk of the batched COCG (its workgroup size)
-constexpr int CG_NNZ_STEP = 8;   // row entries loaded together in the sparse product
+constexpr int CG_NNZ_STEP = 9;   // row entries loaded together in the sparse product (P1 rows: mostly 5 to 9)
 
 void osrc_setup(bem_problem &p)
 {
@@ -250,7 +250,9 @@ void osrc_setup(bem_problem &p)
 // (chunk, system) works on its rows, so a single system spreads over many CUs.
 // An iteration is two launches whose boundaries are the grid-wide waits of
 // the method: the convergence test, the new direction and q = A p with p.q;
-// then x, r, z with r.z and |r|^2.  The dot products of a block are per-chunk
+// then x, r, z with r.z and |r|^2.  Each launch issues its rows' loads (the
+// sparse row, the gathered vector entries) before it adds up the block's
+// scalars, so that their latencies overlap.  The dot products of a block are per-chunk
 // partial sums that every workgroup of the block adds up again in the same
 // fixed order, so each takes the same decision and the result does not depend
 // on scheduling.  Directions and rho alternate between two slots by iteration
@@ -392,6 +394,33 @@ __global__ __launch_bounds__(CG_ROWS) void k_cg_direction_spmv(CgArgs a, int par
     const int64_t blk = g * a.n_dom + ch.dom;
     if (cg_block_done(a.done, blk)) return;
     const int64_t nblk = a.n_dom * int64_t(gridDim.y);
+    const int64_t i = ch.begin + threadIdx.x;
+    const bool own = i < ch.end;
+    const int64_t ir = own ? i : ch.begin;
+    const double2 *zv = a.Z + g * a.n, *po = a.P + (1 - parity) * int64_t(gridDim.y) * a.n + g * a.n;
+    double2 *pn = a.P + parity * int64_t(gridDim.y) * a.n + g * a.n;
+    // the row's first CG_NNZ_STEP entries with their z and old-direction
+    // values, loaded before the block's scalars are known (threads past the
+    // chunk load row ch.begin and discard it).  Entries past the row end read
+    // row i with zero values, which adds exact zeros after the row's own terms
+    // in the same order; longer rows continue CG_NNZ_STEP entries at a time.
+    const int32_t e0 = a.aptr[ir], e1 = a.aptr[ir + 1];
+    int32_t col[CG_NNZ_STEP];
+    double mv[CG_NNZ_STEP], sv[CG_NNZ_STEP];
+    double2 zcol[CG_NNZ_STEP], pcol[CG_NNZ_STEP];
+#pragma unroll
+    for (int u = 0; u < CG_NNZ_STEP; ++u) {
+        const bool in = e0 + u < e1;
+        col[u] = in ? a.acol[e0 + u] : int32_t(ir);
+        mv[u] = in ? a.Mv[e0 + u] : 0.0;
+        sv[u] = in ? a.Sv[e0 + u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < CG_NNZ_STEP; ++u) {
+        zcol[u] = zv[col[u]];
+        pcol[u] = first ? make_double2(0.0, 0.0) : po[col[u]];
+    }
+    const double2 zown = zv[ir], pown = first ? make_double2(0.0, 0.0) : po[ir];
     double br = 0.0, bi = 0.0;
     if (!first) {
         double v[3];
@@ -407,48 +436,47 @@ __global__ __launch_bounds__(CG_ROWS) void k_cg_direction_spmv(CgArgs a, int par
         br = (v[1] * rho.x + v[2] * rho.y) / d2;
         bi = (v[2] * rho.x - v[1] * rho.y) / d2;
     }
-    const int64_t i = ch.begin + threadIdx.x;
     const double2 cg = a.c[g];
-    const double2 *zv = a.Z + g * a.n, *po = a.P + (1 - parity) * int64_t(gridDim.y) * a.n + g * a.n;
-    double2 *pn = a.P + parity * int64_t(gridDim.y) * a.n + g * a.n;
-    const auto dir = [&](int64_t j) {
-        const double2 z = zv[j];
+    const auto comb = [&](double2 z, double2 pp) {
         if (first) return z;
-        const double2 pp = po[j];
         return make_double2(z.x + br * pp.x - bi * pp.y, z.y + br * pp.y + bi * pp.x);
     };
+    const auto dir = [&](int64_t j) { return comb(zv[j], first ? make_double2(0.0, 0.0) : po[j]); };
     double v[2] = {0.0, 0.0};
-    if (i < ch.end) {
-        // eight entries of the row at a time: their index, value and gathered
-        // direction loads are all in flight together (a P1 row has about 7);
-        // entries past the row end read row i with zero values, which adds
-        // exact zeros after the row's own terms in the same order
+    if (own) {
         double mr = 0, mi = 0, sr = 0, si = 0;
-        const int32_t e0 = a.aptr[i], e1 = a.aptr[i + 1];
-        for (int32_t e = e0; e < e1; e += CG_NNZ_STEP) {
-            int32_t col[CG_NNZ_STEP];
-            double mv[CG_NNZ_STEP], sv[CG_NNZ_STEP];
+#pragma unroll
+        for (int u = 0; u < CG_NNZ_STEP; ++u) {
+            const double2 x = comb(zcol[u], pcol[u]);
+            mr += mv[u] * x.x;
+            mi += mv[u] * x.y;
+            sr += sv[u] * x.x;
+            si += sv[u] * x.y;
+        }
+        for (int32_t e = e0 + CG_NNZ_STEP; e < e1; e += CG_NNZ_STEP) {
+            int32_t cl[CG_NNZ_STEP];
+            double m2[CG_NNZ_STEP], s2[CG_NNZ_STEP];
 #pragma unroll
             for (int u = 0; u < CG_NNZ_STEP; ++u) {
                 const bool in = e + u < e1;
-                col[u] = in ? a.acol[e + u] : int32_t(i);
-                mv[u] = in ? a.Mv[e + u] : 0.0;
-                sv[u] = in ? a.Sv[e + u] : 0.0;
+                cl[u] = in ? a.acol[e + u] : int32_t(i);
+                m2[u] = in ? a.Mv[e + u] : 0.0;
+                s2[u] = in ? a.Sv[e + u] : 0.0;
             }
             double2 x[CG_NNZ_STEP];
 #pragma unroll
-            for (int u = 0; u < CG_NNZ_STEP; ++u) x[u] = dir(col[u]);
+            for (int u = 0; u < CG_NNZ_STEP; ++u) x[u] = dir(cl[u]);
 #pragma unroll
             for (int u = 0; u < CG_NNZ_STEP; ++u) {
-                mr += mv[u] * x[u].x;
-                mi += mv[u] * x[u].y;
-                sr += sv[u] * x[u].x;
-                si += sv[u] * x[u].y;
+                mr += m2[u] * x[u].x;
+                mi += m2[u] * x[u].y;
+                sr += s2[u] * x[u].x;
+                si += s2[u] * x[u].y;
             }
         }
         const double qr = mr - (cg.x * sr - cg.y * si), qi = mi - (cg.x * si + cg.y * sr);
         a.Q[g * a.n + i] = make_double2(qr, qi);
-        const double2 pp = dir(i);
+        const double2 pp = comb(zown, pown);
         pn[i] = pp;
         v[0] = pp.x * qr - pp.y * qi;
         v[1] = pp.x * qi + pp.y * qr;
@@ -470,20 +498,23 @@ __global__ __launch_bounds__(CG_ROWS) void k_cg_update(CgArgs a, int parity)
     const CgChunk ch = a.chunks[blockIdx.x];
     const int64_t blk = g * a.n_dom + ch.dom;
     if (cg_block_done(a.done, blk)) return;
+    const int64_t i = ch.begin + threadIdx.x;
+    const bool own = i < ch.end;
+    const int64_t k = g * a.n + (own ? i : ch.begin);
+    // the row's vectors and diagonal, loaded before alpha is known
+    const double2 pp = a.P[parity * int64_t(gridDim.y) * a.n + k], qq = a.Q[k], xx = a.X[k], rv = a.R[k];
+    const double2 dg = cg_diag(a, a.c[g], own ? i : ch.begin);
     double pq[2];
     block_partials<2>(a.part1, g * a.n_chunks + ch.first, ch.nc, pq, red);
     const double den = pq[0] * pq[0] + pq[1] * pq[1];
     const double2 rho = a.rho[parity * a.n_dom * int64_t(gridDim.y) + blk];
-    const int64_t i = ch.begin + threadIdx.x;
     double v[3] = {0.0, 0.0, 0.0};
-    if (den != 0.0 && i < ch.end) {
+    if (den != 0.0 && own) {
         const double ar = (rho.x * pq[0] + rho.y * pq[1]) / den, ai = (rho.y * pq[0] - rho.x * pq[1]) / den;
-        const int64_t k = g * a.n + i;
-        const double2 pp = a.P[parity * int64_t(gridDim.y) * a.n + k], qq = a.Q[k], xx = a.X[k], rv = a.R[k];
         a.X[k] = make_double2(xx.x + ar * pp.x - ai * pp.y, xx.y + ar * pp.y + ai * pp.x);
         const double2 nr = make_double2(rv.x - (ar * qq.x - ai * qq.y), rv.y - (ar * qq.y + ai * qq.x));
         a.R[k] = nr;
-        const double2 z = cdiv(nr, cg_diag(a, a.c[g], i));
+        const double2 z = cdiv(nr, dg);
         a.Z[k] = z;
         v[0] = nr.x * nr.x + nr.y * nr.y;
         v[1] = nr.x * z.x - nr.y * z.y;
@@ -491,7 +522,7 @@ __global__ __launch_bounds__(CG_ROWS) void k_cg_update(CgArgs a, int parity)
     }
     wg_sum<3>(v, red);
     if (threadIdx.x == 0) {
-        for (int k = 0; k < 3; ++k) a.part2[3 * (g * a.n_chunks + blockIdx.x) + k] = v[k];
+        for (int kk = 0; kk < 3; ++kk) a.part2[3 * (g * a.n_chunks + blockIdx.x) + kk] = v[kk];
         if (blockIdx.x == unsigned(ch.first)) a.its[blk] += 1;   // read by the next kernel only
     }
 }
