@@ -255,7 +255,7 @@ def main():
                     help="assembled section without its solves (GEMV and GEMM launches only, for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+        print(f"bench.py: the library runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "sharding is a design note, not a code path.", file=sys.stderr)
         sys.exit(2)
 
