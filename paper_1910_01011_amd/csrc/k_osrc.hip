@@ -184,7 +184,26 @@ __global__ void k_osrc_out(const double2 *__restrict__ rootD, const double2 *__r
 static unsigned nb(int64_t n) { return blocks_1d(n, 256); }
 
 constexpr int CG_ROWS = 256;   // rows per chunk of the batched COCG (its workgroup size)
-constexpr int CG_NNZ_STEP = 9;   // row entries loaded together in the sparse product (P1 rows: mostly 5 to 9)
+constexpr int CG_NNZ_STEP = 9;   // row entries loaded together in the sparse product (P1 rows: mostly 5 to 9),
+                                 // also the width of the slot-major copy of the first entries
+
+// The first CG_NNZ_STEP entries of every row in slot-major order (slot u of
+// row i at u NV + i), entries past the row end as the row's own index with
+// zero values: the sparse product reads them without the row pointer.
+__global__ void k_cg_ell(const int32_t *__restrict__ aptr, const int32_t *__restrict__ acol,
+                         const double *__restrict__ Mv, const double *__restrict__ Sv, int64_t NV,
+                         int32_t *__restrict__ ecol, double *__restrict__ emv, double *__restrict__ esv)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= NV) return;
+    const int32_t e0 = aptr[i], e1 = aptr[i + 1];
+    for (int u = 0; u < CG_NNZ_STEP; ++u) {
+        const bool in = e0 + u < e1;
+        ecol[u * NV + i] = in ? acol[e0 + u] : int32_t(i);
+        emv[u * NV + i] = in ? Mv[e0 + u] : 0.0;
+        esv[u * NV + i] = in ? Sv[e0 + u] : 0.0;
+    }
+}
 
 void osrc_setup(bem_problem &p)
 {
@@ -220,6 +239,12 @@ void osrc_setup(bem_problem &p)
     BEM_HIP(hipMemcpyAsync(p.d_acol, col.data(), col.size() * sizeof(int32_t), hipMemcpyHostToDevice, p.stream));
     k_mass_stiff<<<dim3(nb(p.NV)), dim3(256), 0, p.stream>>>(p.d_verts, p.d_tris, p.d_area, p.d_v2t_ptr, p.d_v2t,
                                                             p.d_aptr, p.d_acol, p.NV, p.d_Mv, p.d_Sv);
+    BEM_HIP(hipGetLastError());
+    dmalloc(reinterpret_cast<void **>(&p.d_ell_col), size_t(CG_NNZ_STEP) * p.NV * sizeof(int32_t));
+    dmalloc(reinterpret_cast<void **>(&p.d_ell_mv), size_t(CG_NNZ_STEP) * p.NV * sizeof(double));
+    dmalloc(reinterpret_cast<void **>(&p.d_ell_sv), size_t(CG_NNZ_STEP) * p.NV * sizeof(double));
+    k_cg_ell<<<dim3(nb(p.NV)), dim3(256), 0, p.stream>>>(p.d_aptr, p.d_acol, p.d_Mv, p.d_Sv, p.NV, p.d_ell_col,
+                                                          p.d_ell_mv, p.d_ell_sv);
     BEM_HIP(hipGetLastError());
     BEM_HIP(hipStreamSynchronize(p.stream));
     // row chunks of the batched COCG: every domain's rows cut into pieces of
@@ -305,6 +330,8 @@ struct CgChunk {
 struct CgArgs {
     const int32_t *aptr, *acol, *adiag;
     const double *Mv, *Sv;
+    const int32_t *ell_col;        // [CG_NNZ_STEP][n] first entries of every row
+    const double *ell_mv, *ell_sv;
     const CgChunk *chunks;
     int n_chunks, n_dom;
     int64_t n;                     // rows of one system (all vertices)
@@ -399,21 +426,22 @@ __global__ __launch_bounds__(CG_ROWS) void k_cg_direction_spmv(CgArgs a, int par
     const int64_t ir = own ? i : ch.begin;
     const double2 *zv = a.Z + g * a.n, *po = a.P + (1 - parity) * int64_t(gridDim.y) * a.n + g * a.n;
     double2 *pn = a.P + parity * int64_t(gridDim.y) * a.n + g * a.n;
-    // the row's first CG_NNZ_STEP entries with their z and old-direction
+    // the row's first CG_NNZ_STEP entries (from the slot-major copy, so
+    // without waiting for the row pointer) with their z and old-direction
     // values, loaded before the block's scalars are known (threads past the
-    // chunk load row ch.begin and discard it).  Entries past the row end read
-    // row i with zero values, which adds exact zeros after the row's own terms
-    // in the same order; longer rows continue CG_NNZ_STEP entries at a time.
+    // chunk load row ch.begin and discard it).  Entries past the row end are
+    // the row's own index with zero values, which adds exact zeros after the
+    // row's own terms in the same order; longer rows continue from the CSR
+    // CG_NNZ_STEP entries at a time.
     const int32_t e0 = a.aptr[ir], e1 = a.aptr[ir + 1];
     int32_t col[CG_NNZ_STEP];
     double mv[CG_NNZ_STEP], sv[CG_NNZ_STEP];
     double2 zcol[CG_NNZ_STEP], pcol[CG_NNZ_STEP];
 #pragma unroll
     for (int u = 0; u < CG_NNZ_STEP; ++u) {
-        const bool in = e0 + u < e1;
-        col[u] = in ? a.acol[e0 + u] : int32_t(ir);
-        mv[u] = in ? a.Mv[e0 + u] : 0.0;
-        sv[u] = in ? a.Sv[e0 + u] : 0.0;
+        col[u] = a.ell_col[u * a.n + ir];
+        mv[u] = a.ell_mv[u * a.n + ir];
+        sv[u] = a.ell_sv[u * a.n + ir];
     }
 #pragma unroll
     for (int u = 0; u < CG_NNZ_STEP; ++u) {
@@ -635,6 +663,9 @@ static void cocg_run(bem_problem &p, CgWork &w, const double2 *B, double2 *X, do
     a.adiag = p.d_adiag;
     a.Mv = p.d_Mv;
     a.Sv = p.d_Sv;
+    a.ell_col = p.d_ell_col;
+    a.ell_mv = p.d_ell_mv;
+    a.ell_sv = p.d_ell_sv;
     a.chunks = reinterpret_cast<const CgChunk *>(p.d_cg_chunks);
     a.n_chunks = C;
     a.n_dom = n_dom;
