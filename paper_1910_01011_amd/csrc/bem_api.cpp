@@ -58,7 +58,7 @@ void free_problem(bem_problem *p)
                     p->d_cptr, p->d_ccol, p->d_cval, p->d_x, p->d_y, p->d_A, p->d_Ahi, p->d_Alo,
                     p->d_gx, p->d_gc, p->d_aptr, p->d_acol, p->d_Mv, p->d_Sv, p->d_adiag, p->d_drange,
                     p->d_sl_cptr, p->d_sl_ccol, p->d_sl_cval, p->d_cg_chunks, p->d_ell_col, p->d_ell_mv,
-                    p->d_ell_sv};
+                    p->d_ell_sv, p->d_mdiag};
     for (void *q : ptrs)
         if (q) bem::dfree(q);
     if (p->hm) bem::hmatrix_free(p->hm);

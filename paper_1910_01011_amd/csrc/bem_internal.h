@@ -228,6 +228,7 @@ struct bem_problem {
     int *d_cg_chunks = nullptr;     // [chunks][8] row chunks of the batched COCG (domain, rows, first, count)
     int32_t *d_ell_col = nullptr;   // [9][NV] first entries of every row of the CSR above, slot-major
     double *d_ell_mv = nullptr, *d_ell_sv = nullptr;   // (padded with the row's own index and zeros)
+    double2 *d_mdiag = nullptr;     // [NV] diagonal entries (M_ii, S_ii) of every row
     int cg_n_chunks = 0;
     bem::OsrcWork *osrc = nullptr;  // buffers, coefficients and captured COCG iterations of the last OSRC form
 

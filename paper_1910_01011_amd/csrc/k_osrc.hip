@@ -189,13 +189,17 @@ constexpr int CG_NNZ_STEP = 9;   // row entries loaded together in the sparse pr
 
 // The first CG_NNZ_STEP entries of every row in slot-major order (slot u of
 // row i at u NV + i), entries past the row end as the row's own index with
-// zero values: the sparse product reads them without the row pointer.
+// zero values: the sparse product reads them without the row pointer.  And
+// the diagonal entries (M_ii, S_ii) of every row, read by the updates without
+// the diagonal's position.
 __global__ void k_cg_ell(const int32_t *__restrict__ aptr, const int32_t *__restrict__ acol,
-                         const double *__restrict__ Mv, const double *__restrict__ Sv, int64_t NV,
-                         int32_t *__restrict__ ecol, double *__restrict__ emv, double *__restrict__ esv)
+                         const int32_t *__restrict__ adiag, const double *__restrict__ Mv,
+                         const double *__restrict__ Sv, int64_t NV, int32_t *__restrict__ ecol,
+                         double *__restrict__ emv, double *__restrict__ esv, double2 *__restrict__ mdiag)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= NV) return;
+    mdiag[i] = make_double2(Mv[adiag[i]], Sv[adiag[i]]);
     const int32_t e0 = aptr[i], e1 = aptr[i + 1];
     for (int u = 0; u < CG_NNZ_STEP; ++u) {
         const bool in = e0 + u < e1;
@@ -243,8 +247,9 @@ void osrc_setup(bem_problem &p)
     dmalloc(reinterpret_cast<void **>(&p.d_ell_col), size_t(CG_NNZ_STEP) * p.NV * sizeof(int32_t));
     dmalloc(reinterpret_cast<void **>(&p.d_ell_mv), size_t(CG_NNZ_STEP) * p.NV * sizeof(double));
     dmalloc(reinterpret_cast<void **>(&p.d_ell_sv), size_t(CG_NNZ_STEP) * p.NV * sizeof(double));
-    k_cg_ell<<<dim3(nb(p.NV)), dim3(256), 0, p.stream>>>(p.d_aptr, p.d_acol, p.d_Mv, p.d_Sv, p.NV, p.d_ell_col,
-                                                          p.d_ell_mv, p.d_ell_sv);
+    dmalloc(reinterpret_cast<void **>(&p.d_mdiag), size_t(p.NV) * sizeof(double2));
+    k_cg_ell<<<dim3(nb(p.NV)), dim3(256), 0, p.stream>>>(p.d_aptr, p.d_acol, p.d_adiag, p.d_Mv, p.d_Sv, p.NV,
+                                                          p.d_ell_col, p.d_ell_mv, p.d_ell_sv, p.d_mdiag);
     BEM_HIP(hipGetLastError());
     BEM_HIP(hipStreamSynchronize(p.stream));
     // row chunks of the batched COCG: every domain's rows cut into pieces of
@@ -332,6 +337,7 @@ struct CgArgs {
     const double *Mv, *Sv;
     const int32_t *ell_col;        // [CG_NNZ_STEP][n] first entries of every row
     const double *ell_mv, *ell_sv;
+    const double2 *mdiag;          // [n] (M_ii, S_ii)
     const CgChunk *chunks;
     int n_chunks, n_dom;
     int64_t n;                     // rows of one system (all vertices)
@@ -360,8 +366,8 @@ __device__ __forceinline__ bool cg_block_done(const int32_t *done, int64_t blk)
 
 __device__ __forceinline__ double2 cg_diag(const CgArgs &a, double2 cg, int64_t i)
 {
-    const int32_t e = a.adiag[i];
-    return make_double2(a.Mv[e] - cg.x * a.Sv[e], -cg.y * a.Sv[e]);
+    const double2 d = a.mdiag[i];
+    return make_double2(d.x - cg.x * d.y, -cg.y * d.y);
 }
 
 // x = 0, r = b, z = p = b / diag; partials (|b|^2, b.z)
@@ -666,6 +672,7 @@ static void cocg_run(bem_problem &p, CgWork &w, const double2 *B, double2 *X, do
     a.ell_col = p.d_ell_col;
     a.ell_mv = p.d_ell_mv;
     a.ell_sv = p.d_ell_sv;
+    a.mdiag = p.d_mdiag;
     a.chunks = reinterpret_cast<const CgChunk *>(p.d_cg_chunks);
     a.n_chunks = C;
     a.n_dom = n_dom;
