@@ -126,3 +126,35 @@ def test_osrc_workspace_follows_parameters_and_vector_count():
         z = D.precondition(y, opts).cpu().numpy()
         assert np.array_equal(z, ref[key]), ("device", key)
     D.close()
+
+
+def test_osrc_apply_rows_longer_than_one_load_step():
+    """The sparse product of the COCG loads nine entries of a row at a time
+    (from a slot-major copy of each row's first nine) and continues from the
+    CSR for longer rows.  A capsule (pole rows of 17 entries) beside a box
+    (rows of exactly nine) against the oracle's dense preconditioner."""
+    from bem_inputs import meshes
+    from bem_inputs.configs import Domain, Problem
+    vc, tc = meshes.capsule(radius=0.25, length=1.0, h=0.1, axis=1)
+    vb, tb = meshes.box((0.6, -0.5, -0.2), (1.2, 0.1, 0.2), 0.1)
+    prob = Problem(domains=[Domain(vc, tc, 3.3 + 0.05j, 1.2, "capsule"), Domain(vb, tb, 2.8, 0.9, "box")],
+                   k0=3.0, name="capsule_box")
+    lengths = []
+    for v, t in ((vc, tc), (vb, tb)):
+        adj = [set() for _ in range(len(v))]
+        for tri in t:
+            for a in tri:
+                adj[a].update(int(b) for b in tri)
+        lengths += [len(s) for s in adj]
+    assert max(lengths) > 9 and 9 in lengths
+    bem = _bem()
+    P = bem.Problem.from_config(prob)
+    opts = bem.solve_options(precond=bem.BEM_PRECOND_OSRC, n_pade=4, r_eps=0.1, theta=np.pi / 3)
+    Pm = osrc.preconditioner_matrix(prob, 0.1, 4, np.pi / 3)
+    Y = vectors.random_complex(prob.n_unknowns, seed=33, n_rhs=2)
+    Z = P.precondition(Y, opts)
+    for r in range(2):
+        err = _relerr(Z[r], Pm @ Y[r])
+        print(f"capsule and box OSRC apply rel err {err:.2e}")
+        assert err <= 1e-7
+    P.close()
