@@ -258,7 +258,11 @@ bem_status bem_solve_rhs(bem_problem *p, const bem_complex *b, int32_t n_rhs, co
  * permutation of the unknowns to [u_N; u_D] folded in: the Lambda_DtN result
  * is returned in the u_N positions and the Lambda_NtD result in the u_D
  * positions (GMRES on P A u = P b).  Inner sparse solves by COCG in FP64 to
- * the relative residual opts->osrc_tol, or 1e-10 when it is 0. */
+ * the relative residual opts->osrc_tol, or 1e-10 when it is 0.  The call
+ * returns once out is complete, with host or device pointers.  The problem
+ * keeps the preconditioner's sparse-solve workspace (up to 2 GB) for the next
+ * call with the same n_pade, r_eps, theta, osrc_tol and n_rhs; it is rebuilt
+ * when they change and freed by bem_destroy. */
 bem_status bem_apply_preconditioner(bem_problem *p, const bem_solve_opts *opts, const bem_complex *y,
                                     bem_complex *out, int32_t n_rhs);
 
