@@ -43,6 +43,40 @@ struct DevBuf {
     DevBuf &operator=(const DevBuf &) = delete;
 };
 
+// Pinned host staging for the values an Arnoldi step reads back: copies to
+// and from pageable memory would make the host wait for each of them.  One
+// buffer per thread and nesting depth (a flexible solve runs its inner solves
+// on the same thread while it holds its own), grown as needed and kept until
+// the process ends (a few kilobytes per thread and depth; freeing it at thread
+// exit could run after the HIP runtime has shut down).
+struct StageSlot {
+    double2 *p = nullptr;
+    size_t cap = 0;
+};
+thread_local std::vector<StageSlot> t_stage;
+thread_local int t_stage_depth = 0;
+
+struct StageLease {
+    double2 *p = nullptr;
+    explicit StageLease(size_t n)
+    {
+        if (int(t_stage.size()) <= t_stage_depth) t_stage.resize(size_t(t_stage_depth) + 1);
+        StageSlot &sl = t_stage[size_t(t_stage_depth)];
+        if (sl.cap < n) {
+            if (sl.p) (void)hipHostFree(sl.p);
+            sl.p = nullptr;
+            sl.cap = 0;
+            BEM_HIP(hipHostMalloc(reinterpret_cast<void **>(&sl.p), n * sizeof(double2), hipHostMallocPortable));
+            sl.cap = n;
+        }
+        p = sl.p;
+        ++t_stage_depth;
+    }
+    ~StageLease() { --t_stage_depth; }
+    StageLease(const StageLease &) = delete;
+    StageLease &operator=(const StageLease &) = delete;
+};
+
 }  // namespace
 
 void gmres_batch(bem_problem &p, int64_t n, int R, const double2 *B, double2 *X, const KrylovOpts &o,
@@ -54,6 +88,9 @@ void gmres_batch(bem_problem &p, int64_t n, int R, const double2 *B, double2 *X,
     DevBuf<double2> V(size_t(m + 1) * R * n, s), Z(M ? size_t(m) * R * n : 1, s), Xa(size_t(R) * n, s),
         Ba(size_t(R) * n, s);
     DevBuf<double2> hdev(size_t(R) * (m + 2), s), part(size_t(R) * (m + 2) * nblk, s);
+    // per step: the two Gram-Schmidt coefficient blocks, the norms, the scales
+    const StageLease lease(size_t(2) * R * (m + 2) + size_t(2) * R);
+    double2 *const stage = lease.p;
     const int64_t ld = int64_t(R) * n;   // stride between basis vectors (packed to the active count)
 
     auto host_dots = [&](const double2 *Vb, int64_t ldv, int nvec, const double2 *w, int Ra, std::vector<cd> &out) {
@@ -150,15 +187,24 @@ void gmres_batch(bem_problem &p, int64_t n, int R, const double2 *B, double2 *X,
                 zj = zz;
             }
             A(zj, vj1, Ra);
-            std::vector<cd> h1, h2;
+            // both Gram-Schmidt passes and the norm without waiting: each pass's
+            // coefficients are used on the device as computed and copied to the
+            // host for the Hessenberg matrix; the host waits once per step
+            const size_t nh = size_t(Ra) * (j + 1);
             for (int pass = 0; pass < 2; ++pass) {
-                std::vector<cd> &h = pass == 0 ? h1 : h2;
-                host_dots(V.p, ld, j + 1, vj1, Ra, h);
-                to_dev(h);
+                bdot(s, V.p, ld, j + 1, vj1, n, Ra, part.p, nblk, hdev.p);
+                BEM_HIP(hipMemcpyAsync(stage + pass * nh, hdev.p, nh * sizeof(double2), hipMemcpyDeviceToHost, s));
                 baxpy(s, V.p, ld, j + 1, hdev.p, vj1, n, Ra, -1.0);
             }
-            std::vector<cd> nn;
-            host_dots(vj1, 0, 1, vj1, Ra, nn);
+            bdot(s, vj1, 0, 1, vj1, n, Ra, part.p, nblk, hdev.p);
+            BEM_HIP(hipMemcpyAsync(stage + 2 * nh, hdev.p, Ra * sizeof(double2), hipMemcpyDeviceToHost, s));
+            BEM_HIP(hipStreamSynchronize(s));
+            std::vector<cd> h1(nh), h2(nh), nn(Ra);
+            for (size_t i = 0; i < nh; ++i) {
+                h1[i] = cd(stage[i].x, stage[i].y);
+                h2[i] = cd(stage[nh + i].x, stage[nh + i].y);
+            }
+            for (int a = 0; a < Ra; ++a) nn[a] = cd(stage[2 * nh + a].x, stage[2 * nh + a].y);
             std::vector<cd> sc(Ra);
             bool any = false;
             for (int a = 0; a < Ra; ++a) {
@@ -190,7 +236,11 @@ void gmres_batch(bem_problem &p, int64_t n, int R, const double2 *B, double2 *X,
                 }
                 any = any || live[a];
             }
-            to_dev(sc);
+            // the scales go up from the staging buffer without a wait: the host
+            // writes it again only after the next step's wait
+            double2 *up = stage + 2 * nh + Ra;
+            for (int a = 0; a < Ra; ++a) up[a] = make_double2(sc[a].real(), sc[a].imag());
+            BEM_HIP(hipMemcpyAsync(hdev.p, up, Ra * sizeof(double2), hipMemcpyHostToDevice, s));
             bscale(s, vj1, vj1, n, Ra, hdev.p);
             ++steps;
             if (o.progress > 0 && steps % o.progress == 0) {
