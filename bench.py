@@ -215,6 +215,31 @@ def ribcage_time_to_solve(P, prob, bem, torch):
                       "the on-the-fly operator", "n_pade": 4, "r_eps": r_eps}
 
 
+def field_probe(bem, torch):
+    """Field evaluation (representation formula off the surface, FP64, with the
+    winding-number regions) of the 10,242-vertex sphere's plane-wave solution
+    on 200 x 200 points over [-3 R, 3 R]^2 in the plane y = 0: median of three
+    evaluations, and the (point, source quadrature point) pairs per second."""
+    from bem_inputs import configs as cfg
+    prob = cfg.config2()
+    P = bem.Problem.from_config(prob)
+    inc = bem.Incident.plane_waves([[0.0, 0.0, 1.0]])
+    b = P.rhs(inc)
+    u, info = P.solve(b, bem.solve_options(tol=1e-5, restart=100, max_iter=500))
+    pts = cfg.grid_plane_y0(1.0, 200, 3.0)
+    ts = []
+    for _ in range(3):
+        (field, region), t = _timed(torch, lambda: P.evaluate_field(u, pts, inc))
+        ts.append(t)
+    P.close()
+    # one domain: every point's representation formula runs over all source points
+    pairs = float(len(pts)) * sum(6 * d.n_triangles for d in prob.domains)
+    t = float(np.median(ts))
+    log(f"field evaluation: {len(pts)} points, {t * 1e3:.1f} ms, {pairs / t:.3e} pairs/s")
+    return {"workload": prob.name, "points": len(pts), "pairs": pairs, "ms": t * 1e3, "pairs_per_s": pairs / t,
+            "near_boundary_points": int(np.count_nonzero(region == -1)), "solve_iterations": info[0]["iterations"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -248,6 +273,9 @@ def main():
     ap.add_argument("--solve-probe", action="store_true",
                     help="run only the rib-cage stack's time-to-solve with its set-up (right-hand side and "
                          "hierarchical-matrix build), for kernel traces")
+    ap.add_argument("--field-probe", action="store_true",
+                    help="run only the field evaluation of the 10,242-vertex sphere's plane-wave solution on a "
+                         "200 x 200 grid in the plane y = 0 (for kernel traces)")
     ap.add_argument("--gemm-reference", action="store_true",
                     help="run only torch.matmul (the vendor GEMM library) on the real-GEMM shapes of the split-BF16 "
                          "apply (BF16 and FP32) and on square shapes, as a reference for the library's kernels")
@@ -274,6 +302,9 @@ def main():
         return
     if args.gemm_reference:
         print(json.dumps({"gemm_reference": gemm_reference(torch)}), flush=True)
+        return
+    if args.field_probe:
+        print(json.dumps({"field": field_probe(bem, torch)}), flush=True)
         return
     if args.solve_probe:
         prob = configs.ribcage(1.0)

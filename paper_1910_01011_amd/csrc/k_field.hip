@@ -255,6 +255,8 @@ void launch_rhs(bem_problem &p, const bem_incident &inc, double2 *b)
 
 constexpr int FIELD_DIRECT_MAX = 4;                   // more fields: rows + dense product
 constexpr int64_t FIELD_ROWS_BYTES = int64_t(512) << 20;   // row buffer of one chunk of points
+constexpr int64_t FIELD_TARGET_THREADS = int64_t(256) * 4 * 8 * 64;   // eight waves per SIMD
+constexpr int FIELD_MAX_SPLIT = 64;
 
 struct DomDev {
     long long v_off, t_off, nt, nv;
@@ -295,19 +297,23 @@ __device__ double tri_dist2(const double *a, const double *b, const double *c)
 
 // one thread per point: region by winding numbers (wreg) and the reported
 // region code (-1 within 2 h of a boundary)
+// Split s of S of every domain's triangles for one point: the domain's partial
+// solid-angle sum (rpart[(s n_dom + j) np + ip]) and whether the point is within
+// 2 h of one of these triangles (npart[s np + ip]).
 __global__ void k_region(const DomDev *__restrict__ doms, int n_dom, const double *__restrict__ verts,
                          const int32_t *__restrict__ tris, const double *__restrict__ pts, int64_t np,
-                         int32_t *__restrict__ wreg, int32_t *__restrict__ region)
+                         double *__restrict__ rpart, int32_t *__restrict__ npart)
 {
     const int64_t ip = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (ip >= np) return;
+    const int sp = blockIdx.y, S = gridDim.y;
     const double x[3] = {pts[3 * ip], pts[3 * ip + 1], pts[3 * ip + 2]};
-    int reg = 0;
     bool near = false;
     for (int j = 0; j < n_dom; ++j) {
         double s = 0.0;
         const double h2 = 2.0 * doms[j].h;
-        for (long long t = doms[j].t_off; t < doms[j].t_off + doms[j].nt; ++t) {
+        const long long t0 = doms[j].t_off + doms[j].nt * sp / S, t1 = doms[j].t_off + doms[j].nt * (sp + 1) / S;
+        for (long long t = t0; t < t1; ++t) {
             double a[3], b[3], c[3];
             for (int d = 0; d < 3; ++d) {
                 a[d] = verts[3 * int64_t(tris[3 * t]) + d] - x[d];
@@ -333,70 +339,115 @@ __global__ void k_region(const DomDev *__restrict__ doms, int n_dom, const doubl
                     near = true;
             }
         }
+        rpart[(int64_t(sp) * n_dom + j) * np + ip] = s;
+    }
+    npart[int64_t(sp) * np + ip] = near ? 1 : 0;
+}
+
+// region code of every point from the S partial sums (added in split order):
+// the winding region (0 outside, j + 1 inside boundary j) and the reported
+// code (-1 within 2 h of a boundary)
+__global__ void k_region_reduce(const double *__restrict__ rpart, const int32_t *__restrict__ npart, int n_dom,
+                                int S, int64_t np, int32_t *__restrict__ wreg, int32_t *__restrict__ region)
+{
+    const int64_t ip = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (ip >= np) return;
+    int reg = 0;
+    bool near = false;
+    for (int j = 0; j < n_dom; ++j) {
+        double s = 0.0;
+        for (int sp = 0; sp < S; ++sp) s += rpart[(int64_t(sp) * n_dom + j) * np + ip];
         if (rint(s / (4.0 * PI_D)) == 1.0) reg = j + 1;
     }
+    for (int sp = 0; sp < S; ++sp) near = near || npart[int64_t(sp) * np + ip] != 0;
     wreg[ip] = reg;
     region[ip] = near ? -1 : reg;
 }
 
-// one thread per point: the potentials of all fields in the winding region
-__global__ void k_field(IncDev I, int has_inc, const DomDev *__restrict__ doms, int n_dom, double k0re, double k0im,
-                        double rho0, const double *__restrict__ verts, const int32_t *__restrict__ tris,
+// Split s of S of the source triangles of one point's winding region: the
+// potentials of all fields over those triangles (fpart[(s F + f) np + ip]).
+__global__ void k_field(const DomDev *__restrict__ doms, int n_dom, double k0re, double k0im, double rho0,
+                        const double *__restrict__ verts, const int32_t *__restrict__ tris,
                         const double *__restrict__ area, const double *__restrict__ normal,
                         const int32_t *__restrict__ rowD, const int32_t *__restrict__ rowN,
                         const double2 *__restrict__ u, int64_t N, int n_fields, const double *__restrict__ pts,
-                        int64_t np, const int32_t *__restrict__ wreg, double2 *__restrict__ field)
+                        int64_t np, const int32_t *__restrict__ wreg, double2 *__restrict__ fpart)
 {
     const int64_t ip = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (ip >= np) return;
+    const int sp = blockIdx.y, S = gridDim.y;
     const double x[3] = {pts[3 * ip], pts[3 * ip + 1], pts[3 * ip + 2]};
     const int reg = wreg[ip];
     const int j0 = reg == 0 ? 0 : reg - 1, j1 = reg == 0 ? n_dom : reg;
     const double kre = reg == 0 ? k0re : doms[reg - 1].kre, kim = reg == 0 ? k0im : doms[reg - 1].kim;
     const double sN = reg == 0 ? -1.0 : doms[reg - 1].rho / rho0;   // coefficient of SL u_N
     const double sD = reg == 0 ? 1.0 : -1.0;                         // coefficient of DL u_D
+    // the region's triangles are one contiguous range (domains are numbered in order)
+    const long long T0 = doms[j0].t_off, T1 = doms[j1 - 1].t_off + doms[j1 - 1].nt;
+    const long long t0 = T0 + (T1 - T0) * sp / S, t1 = T0 + (T1 - T0) * (sp + 1) / S;
     for (int f = 0; f < n_fields; ++f) {
         double pr = 0.0, pim = 0.0;
-        if (reg == 0 && has_inc) {
+        const double2 *uf = u + int64_t(f) * N;
+        for (long long t = t0; t < t1; ++t) {
+            double P[3][3];
+            double2 uD[3], uN[3];
+            for (int c = 0; c < 3; ++c) {
+                const int32_t g = tris[3 * t + c];
+                for (int d = 0; d < 3; ++d) P[c][d] = verts[3 * int64_t(g) + d];
+                uD[c] = uf[rowD[g]];
+                uN[c] = uf[rowN[g]];
+            }
+            const double *n = normal + 3 * t;
+            for (int q = 0; q < 6; ++q) {
+                double y[3];
+                for (int d = 0; d < 3; ++d)
+                    y[d] = q6_bary[q][0] * P[0][d] + q6_bary[q][1] * P[1][d] + q6_bary[q][2] * P[2][d];
+                const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+                const double r = sqrt(dx * dx + dy * dy + dz * dz);
+                double sn, cs;
+                sincos(kre * r, &sn, &cs);
+                // one reciprocal for 1/(4 pi r) and 1/r^2; the damping only
+                // for a complex wavenumber
+                const double rinv = 1.0 / r;
+                const double e = (kim != 0.0 ? exp(-kim * r) : 1.0) * (rinv * (0.25 / PI_D));
+                const double gr = e * cs, gi = e * sn;
+                const double a1 = 1.0 + kim * r, b1 = -kre * r, ir2 = rinv * rinv;
+                const double dn = (dx * n[0] + dy * n[1] + dz * n[2]) * ir2;
+                const double fr = (gr * a1 - gi * b1) * dn, fi = (gr * b1 + gi * a1) * dn;   // dG/dn_y
+                double dr = 0, di = 0, nr = 0, ni = 0;
+                for (int c = 0; c < 3; ++c) {
+                    dr += q6_bary[q][c] * uD[c].x; di += q6_bary[q][c] * uD[c].y;
+                    nr += q6_bary[q][c] * uN[c].x; ni += q6_bary[q][c] * uN[c].y;
+                }
+                const double w = area[t] * q6_w[q];
+                pr += w * (sD * (fr * dr - fi * di) + sN * (gr * nr - gi * ni));
+                pim += w * (sD * (fr * di + fi * dr) + sN * (gr * ni + gi * nr));
+            }
+        }
+        fpart[(int64_t(sp) * n_fields + f) * np + ip] = make_double2(pr, pim);
+    }
+}
+
+// field[f][ip] = incident (outside) + the S partial potentials in split order
+__global__ void k_field_reduce(IncDev I, int has_inc, const double2 *__restrict__ fpart, int S, int n_fields,
+                               const double *__restrict__ pts, int64_t np, const int32_t *__restrict__ wreg,
+                               double2 *__restrict__ field)
+{
+    const int64_t ip = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (ip >= np) return;
+    const double x[3] = {pts[3 * ip], pts[3 * ip + 1], pts[3 * ip + 2]};
+    for (int f = 0; f < n_fields; ++f) {
+        double pr = 0.0, pim = 0.0;
+        if (wreg[ip] == 0 && has_inc) {
             const double nz[3] = {0, 0, 1};
             double qr, qi;
             incident(I, f, x, nz, pr, pim, qr, qi);
         }
-        const double2 *uf = u + int64_t(f) * N;
-        for (int j = j0; j < j1; ++j)
-            for (long long t = doms[j].t_off; t < doms[j].t_off + doms[j].nt; ++t) {
-                double P[3][3];
-                double2 uD[3], uN[3];
-                for (int c = 0; c < 3; ++c) {
-                    const int32_t g = tris[3 * t + c];
-                    for (int d = 0; d < 3; ++d) P[c][d] = verts[3 * int64_t(g) + d];
-                    uD[c] = uf[rowD[g]];
-                    uN[c] = uf[rowN[g]];
-                }
-                const double *n = normal + 3 * t;
-                for (int q = 0; q < 6; ++q) {
-                    double y[3];
-                    for (int d = 0; d < 3; ++d)
-                        y[d] = q6_bary[q][0] * P[0][d] + q6_bary[q][1] * P[1][d] + q6_bary[q][2] * P[2][d];
-                    const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
-                    const double r = sqrt(dx * dx + dy * dy + dz * dz);
-                    double sn, cs;
-                    sincos(kre * r, &sn, &cs);
-                    const double e = exp(-kim * r) / (4.0 * PI_D * r);
-                    const double gr = e * cs, gi = e * sn;
-                    const double a1 = 1.0 + kim * r, b1 = -kre * r, ir2 = 1.0 / (r * r);
-                    const double dn = (dx * n[0] + dy * n[1] + dz * n[2]) * ir2;
-                    const double fr = (gr * a1 - gi * b1) * dn, fi = (gr * b1 + gi * a1) * dn;   // dG/dn_y
-                    double dr = 0, di = 0, nr = 0, ni = 0;
-                    for (int c = 0; c < 3; ++c) {
-                        dr += q6_bary[q][c] * uD[c].x; di += q6_bary[q][c] * uD[c].y;
-                        nr += q6_bary[q][c] * uN[c].x; ni += q6_bary[q][c] * uN[c].y;
-                    }
-                    const double w = area[t] * q6_w[q];
-                    pr += w * (sD * (fr * dr - fi * di) + sN * (gr * nr - gi * ni));
-                    pim += w * (sD * (fr * di + fi * dr) + sN * (gr * ni + gi * nr));
-                }
-            }
+        for (int sp = 0; sp < S; ++sp) {
+            const double2 v = fpart[(int64_t(sp) * n_fields + f) * np + ip];
+            pr += v.x;
+            pim += v.y;
+        }
         field[int64_t(f) * np + ip] = make_double2(pr, pim);
     }
 }
@@ -450,9 +501,10 @@ __global__ void k_field_rows(const DomDev *__restrict__ doms, int n_dom, double 
             const double r = sqrt(ex * ex + ey * ey + ez * ez);
             double sn, cs;
             sincos(kre * r, &sn, &cs);
-            const double e = exp(-kim * r) / (4.0 * PI_D * r);
+            const double rinv = 1.0 / r;
+            const double e = (kim != 0.0 ? exp(-kim * r) : 1.0) * (rinv * (0.25 / PI_D));
             const double gr = e * cs, gi = e * sn;
-            const double a1 = 1.0 + kim * r, b1 = -kre * r, ir2 = 1.0 / (r * r);
+            const double a1 = 1.0 + kim * r, b1 = -kre * r, ir2 = rinv * rinv;
             const double dn = (ex * n[0] + ey * n[1] + ez * n[2]) * ir2;
             const double fr = (gr * a1 - gi * b1) * dn, fi = (gr * b1 + gi * a1) * dn;   // dG/dn_y
             const double w = area[t] * q6_w[q] * q6_bary[q][a];
@@ -534,15 +586,38 @@ void launch_field(bem_problem &p, const double2 *u, const bem_incident *inc, int
     int32_t *wreg = nullptr;
     double2 *R = nullptr;
     if (np > 0) {
+        // every point's sums over the source triangles split S ways, so that a
+        // few ten thousand points still give about eight waves per SIMD; the
+        // partials (at most FIELD_ROWS_BYTES) are added in split order
+        const int n_dom = int(hd.size());
+        const int64_t per_split = 16 * std::max<int64_t>(n_fields <= FIELD_DIRECT_MAX ? n_fields : 0, 1) * np +
+                                  (8 * int64_t(n_dom) + 4) * np;
+        int S = int(std::clamp<int64_t>((FIELD_TARGET_THREADS + np - 1) / np, 1, FIELD_MAX_SPLIT));
+        while (S > 1 && S * per_split > FIELD_ROWS_BYTES) S /= 2;
+        DevScratch rpart_mem, npart_mem, fpart_mem;
+        double *rpart = nullptr;
+        int32_t *npart = nullptr;
         dmalloc(reinterpret_cast<void **>(&wreg), size_t(np) * sizeof(int32_t));
         wreg_mem.p = wreg;
-        k_region<<<dim3(blocks_1d(np, B)), dim3(B), 0, p.stream>>>(d_doms, int(hd.size()), p.d_verts, p.d_tris, pts, np,
-                                                                   wreg, region);
+        dmalloc(reinterpret_cast<void **>(&rpart), size_t(S) * n_dom * np * sizeof(double));
+        rpart_mem.p = rpart;
+        dmalloc(reinterpret_cast<void **>(&npart), size_t(S) * np * sizeof(int32_t));
+        npart_mem.p = npart;
+        k_region<<<dim3(blocks_1d(np, B), unsigned(S)), dim3(B), 0, p.stream>>>(d_doms, n_dom, p.d_verts, p.d_tris,
+                                                                                pts, np, rpart, npart);
+        BEM_HIP(hipGetLastError());
+        k_region_reduce<<<dim3(blocks_1d(np, 256)), dim3(256), 0, p.stream>>>(rpart, npart, n_dom, S, np, wreg, region);
         BEM_HIP(hipGetLastError());
         if (n_fields <= FIELD_DIRECT_MAX) {
-            k_field<<<dim3(blocks_1d(np, B)), dim3(B), 0, p.stream>>>(
-                I, inc ? 1 : 0, d_doms, int(hd.size()), p.k0re, p.k0im, p.rho0, p.d_verts, p.d_tris, p.d_area,
-                p.d_normal, p.d_rowD, p.d_rowN, u, p.N, n_fields, pts, np, wreg, field);
+            double2 *fpart = nullptr;
+            dmalloc(reinterpret_cast<void **>(&fpart), size_t(S) * n_fields * np * sizeof(double2));
+            fpart_mem.p = fpart;
+            k_field<<<dim3(blocks_1d(np, B), unsigned(S)), dim3(B), 0, p.stream>>>(
+                d_doms, n_dom, p.k0re, p.k0im, p.rho0, p.d_verts, p.d_tris, p.d_area, p.d_normal, p.d_rowD,
+                p.d_rowN, u, p.N, n_fields, pts, np, wreg, fpart);
+            BEM_HIP(hipGetLastError());
+            k_field_reduce<<<dim3(blocks_1d(np, 256)), dim3(256), 0, p.stream>>>(I, inc ? 1 : 0, fpart, S, n_fields,
+                                                                                 pts, np, wreg, field);
             BEM_HIP(hipGetLastError());
         } else {
             // points in chunks whose rows take at most FIELD_ROWS_BYTES
