@@ -112,3 +112,30 @@ def test_many_fields_in_point_chunks_and_empty_inputs(monkeypatch):
     y0 = P.apply_single_layer(np.zeros((0, prob.n_unknowns // 2), dtype=np.complex128))
     assert y0.shape == (0, prob.n_unknowns // 2)
     P.close()
+
+
+def test_field_direct_path_two_domains_matches_oracle():
+    """The per-point path (at most four fields: each point's source triangles
+    split over several threads, the partial sums added in split order) on two
+    domains, with points outside and inside each of them, against the oracle's
+    field and region codes."""
+    import paper_1910_01011_amd as bem
+    prob = configs.two_spheres()
+    rng = np.random.default_rng(12)
+
+    def ball(c, r, n):
+        d = rng.standard_normal((n, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        return np.asarray(c) + d * rng.uniform(0.0, r, n)[:, None]
+
+    pts = np.concatenate([ball((-1.0, 0.0, 0.0), 0.4, 10), ball((1.0, 0.3, 0.2), 0.25, 10),
+                          ball((0.0, 0.0, 0.0), 3.0, 40)])
+    U = rng.standard_normal((2, prob.n_unknowns)) + 1j * rng.standard_normal((2, prob.n_unknowns))
+    dirs = np.eye(3)[[2, 0]]
+    P = bem.Problem.from_config(prob)
+    f, r = P.evaluate_field(U, pts, bem.Incident.plane_waves(dirs))
+    P.close()
+    refs = [oracle.field(prob, U[i], pts, oracle.plane_wave(prob.k0, dirs[i])[0]) for i in range(2)]
+    assert np.array_equal(r, refs[0][1])
+    assert {0, 1, 2} <= set(r.tolist())   # outside, inside each domain (and near the boundaries: -1)
+    assert _relerr(f, np.array([ref[0] for ref in refs])) <= 1e-10
